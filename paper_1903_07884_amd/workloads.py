@@ -1,0 +1,147 @@
+"""Seeded synthetic inputs: geometries, permittivity contrasts and incident fields.
+
+This module holds no step of the solver's arithmetic.  It produces the inputs
+that both the GPU library and the CPU oracle consume:
+
+* the relative contrast chi = eps/eps_b - 1 per voxel ([nz, ny, nx], x fastest),
+* incident fields e_inc ([R, 3, nz, ny, nx]),
+* the background wavenumber k_b = 2 pi sqrt(eps_b) / lambda0,
+
+for the silicon-photonics geometries the paper studies (Sec. 3, Sec. 5):
+uniform Si waveguides in SiO2 cladding, Bragg gratings with an alternating
+core width and directional couplers made of two parallel cores.  Material
+values follow Table ref_ind (Si 12.1, SiO2 2.085); the operating wavelength is
+1550 nm (Sec. 3).  The paper's adiabatic absorbers and dipole-generated beam
+come from a cited work and are not reproduced; a Gaussian cross-section with a
+propagating phase along x and a seeded global phase stands in for the source.
+"""
+import numpy as np
+
+SEED = 190307884
+LAMBDA0 = 1.55e-6
+EPS_SI = 12.11
+EPS_SIO2 = 2.085
+
+
+def k_background(lambda0=LAMBDA0, eps_b=EPS_SIO2):
+    return 2.0 * np.pi * np.sqrt(eps_b) / lambda0
+
+
+def rng(tag):
+    return np.random.default_rng([SEED, int(tag)])
+
+
+def voxel_centres(grid, delta):
+    """Centres (x, y, z) in metres; y and z are centred on the box axis."""
+    nx, ny, nz = grid
+    x = (np.arange(nx) + 0.5) * delta
+    y = (np.arange(ny) + 0.5) * delta - 0.5 * ny * delta
+    z = (np.arange(nz) + 0.5) * delta - 0.5 * nz * delta
+    return x, y, z
+
+
+def chi_from_mask(mask, eps_core=EPS_SI, eps_b=EPS_SIO2):
+    chi = np.zeros(mask.shape, dtype=np.complex128)
+    chi[mask] = eps_core / eps_b - 1.0
+    return chi
+
+
+def waveguide(grid, delta=None):
+    """Uniform Si core filling the whole box (Sec. 5.1 without absorber)."""
+    nx, ny, nz = grid
+    return chi_from_mask(np.ones((nz, ny, nx), dtype=bool))
+
+
+def bragg(grid, delta, w_narrow=0.5e-6, w_wide=0.6e-6, period=0.32e-6):
+    """Bragg grating (Sec. 5.2): core width alternates narrow/wide each half period.
+
+    Si where |y| < w(x)/2, w = w_narrow if (x mod period) < period/2 else w_wide,
+    sampled at voxel centres, over all z layers.
+    """
+    nx, ny, nz = grid
+    x, y, _ = voxel_centres(grid, delta)
+    phase = np.mod(x + 1e-15, period)
+    w = np.where(phase < 0.5 * period, w_narrow, w_wide)
+    mask2 = np.abs(y)[:, None] < 0.5 * w[None, :]            # [ny, nx]
+    return chi_from_mask(np.broadcast_to(mask2, (nz, ny, nx)).copy())
+
+
+def coupler(grid, cores=((4, 20), (28, 44))):
+    """Directional coupler cross-section: Si in the given y-voxel ranges, all z, all x."""
+    nx, ny, nz = grid
+    mask = np.zeros((nz, ny, nx), dtype=bool)
+    for lo, hi in cores:
+        mask[:, lo:hi, :] = True
+    return chi_from_mask(mask)
+
+
+def gaussian_source(grid, delta, r, y0=0.0, z0=0.0, wy=0.2e-6, wz=0.1e-6, pol=1,
+                    phase=0.0, eps_core=EPS_SI, lambda0=LAMBDA0):
+    """e_inc = p_hat exp(-((y-y0)/wy)^2 - ((z-z0)/wz)^2) exp(-j beta x) exp(j phase).
+
+    beta = k0 sqrt(eps_core) (x-propagating under the exp(j w t) convention).
+    Returns [3, nz, ny, nx] complex128 with only component ``pol`` non-zero.
+    """
+    del r
+    nx, ny, nz = grid
+    x, y, z = voxel_centres(grid, delta)
+    beta = 2.0 * np.pi * np.sqrt(eps_core) / lambda0
+    prof = np.exp(-((y[None, :, None] - y0) / wy) ** 2 - ((z[:, None, None] - z0) / wz) ** 2)
+    wave = np.exp(-1j * beta * x)[None, None, :]
+    e = np.zeros((3, nz, ny, nx), dtype=np.complex128)
+    e[pol] = prof * wave * np.exp(1j * phase)
+    return e
+
+
+CONFIGS = {
+    1: dict(name='uniform Si waveguide 64x8x4 @ 50 nm', grid=(64, 8, 4), delta=50e-9,
+            geometry='waveguide', nrhs=1, wy=0.2e-6, wz=0.1e-6),
+    2: dict(name='long uniform Si waveguide 2048x16x8 @ 25 nm', grid=(2048, 16, 8), delta=25e-9,
+            geometry='waveguide', nrhs=1, wy=0.2e-6, wz=0.1e-6),
+    3: dict(name='Si Bragg grating 4096x24x8 @ 25 nm', grid=(4096, 24, 8), delta=25e-9,
+            geometry='bragg', nrhs=1, wy=0.25e-6, wz=0.1e-6),
+    4: dict(name='Si directional coupler 1024x48x8 @ 25 nm, 64 RHS', grid=(1024, 48, 8),
+            delta=25e-9, geometry='coupler', nrhs=64, wy=0.2e-6, wz=0.1e-6),
+}
+
+
+def make_chi(cfg):
+    grid, delta = cfg['grid'], cfg['delta']
+    geom = cfg['geometry']
+    if geom == 'waveguide':
+        return waveguide(grid, delta)
+    if geom == 'bragg':
+        return bragg(grid, delta)
+    if geom == 'coupler':
+        return coupler(grid)
+    raise ValueError(geom)
+
+
+def make_sources(cfg, tag):
+    """Seeded incident fields [R, 3, nz, ny, nx] for a configuration."""
+    g = rng(tag)
+    grid, delta = cfg['grid'], cfg['delta']
+    R = cfg['nrhs']
+    out = np.zeros((R, 3) + tuple(reversed(grid)), dtype=np.complex128)
+    if cfg['geometry'] == 'coupler':
+        ny = grid[1]
+        centres = [((lo + hi) / 2.0 - ny / 2.0) * delta for lo, hi in ((4, 20), (28, 44))]
+        for r in range(R):
+            core = int(g.integers(0, 2))
+            y0 = centres[core] + g.uniform(-0.1e-6, 0.1e-6)
+            z0 = g.uniform(-0.05e-6, 0.05e-6)
+            pol = 1 if g.integers(0, 2) == 0 else 2
+            ph = g.uniform(0.0, 2.0 * np.pi)
+            out[r] = gaussian_source(grid, delta, r, y0=y0, z0=z0, wy=cfg['wy'], wz=cfg['wz'],
+                                     pol=pol, phase=ph)
+    else:
+        for r in range(R):
+            ph = g.uniform(0.0, 2.0 * np.pi)
+            out[r] = gaussian_source(grid, delta, r, wy=cfg['wy'], wz=cfg['wz'], pol=1, phase=ph)
+    return out
+
+
+def random_field(shape, tag):
+    """Seeded complex normal test vector."""
+    g = rng(tag)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)

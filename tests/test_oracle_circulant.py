@@ -1,0 +1,200 @@
+"""Pins of the oracle's circulant preconditioners (Sec. 4, Sec. 5.1.1-5.3).
+
+* Chan's formula is the Frobenius-nearest circulant (Sec. 4, after eq. Chan):
+  checked against a brute-force least-squares fit over all circulants.
+* A circulant is its own Chan circulant; C = F^{-1} diag(F c) F (Sec. 4).
+* The 1-level block circulant built elementwise from Chan(T_ij) of the dense
+  operator's Toeplitz blocks (no FFT, no permutation), inverted densely,
+  equals the oracle's DFT + permuted block solves (eq. Di and its inverse).
+* If the operator is circulant along x, the preconditioner is exact and
+  preconditioned GMRES converges in one step.  Zero contrast gives P = I.
+* Memory reduction (Sec. 5.1.1): tol 0 keeps everything (identical result),
+  tol > 1 keeps only the central block, kept count monotone in tol.
+* Blocked preconditioner (Sec. 5.3): one box is the 1-level preconditioner;
+  several boxes equal a dense block-diagonal build.
+* Homogenisations (Sec. 5.2 list) on hand-made arrays.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import circulant as C
+from oracle import contrast as CT
+from oracle import generator as G
+from oracle import gmres as GM
+from oracle import matvec as MV
+
+KAPPA = 0.2926652804732217
+
+
+def test_chan_is_frobenius_optimal():
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 8):
+        t = rng.standard_normal(2 * n - 1) + 1j * rng.standard_normal(2 * n - 1)
+        T = np.array([[t[i - j + n - 1] for j in range(n)] for i in range(n)])
+        # design matrix: vec(circ(c)) = E c
+        E = np.zeros((n * n, n))
+        for i in range(n):
+            for j in range(n):
+                E[i * n + j, (i - j) % n] = 1.0
+        c_ls = np.linalg.lstsq(E, T.reshape(-1), rcond=None)[0]
+        assert np.allclose(C.chan(t), c_ls, rtol=1e-13, atol=1e-14)
+
+
+def test_circulant_fixed_point_and_diagonalisation():
+    rng = np.random.default_rng(1)
+    n = 7
+    c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    t = np.array([c[l % n] for l in range(-(n - 1), n)])
+    assert np.allclose(C.chan(t), c, rtol=1e-14)
+    Cm = np.array([[c[(i - j) % n] for j in range(n)] for i in range(n)])
+    F = C.dft_matrix(n)
+    assert np.allclose(np.linalg.inv(F) @ np.diag(F @ c) @ F, Cm, atol=1e-13)
+
+
+@pytest.fixture(scope="module")
+def box():
+    grid = (6, 3, 2)
+    K = G.generator_octant(grid, KAPPA)
+    rng = np.random.default_rng(7)
+    Mt = 0.8 + 0.1 * rng.standard_normal((2, 3)) + 0.05j * rng.standard_normal((2, 3))
+    return grid, K, Mt
+
+
+def _dense_block_circulant(K, Mt, grid):
+    """C_B elementwise: Chan of every x-level Toeplitz block of I - M~ N (no FFT)."""
+    nx, ny, nz = grid
+    M3 = np.broadcast_to(Mt[:, :, None], (nz, ny, nx))
+    A = MV.operator_matrix(K, M3, grid)     # rows/cols: (a, z, y, x), x fastest
+    m = 3 * ny * nz
+    A4 = A.reshape(m, nx, m, nx)
+    CB = np.zeros_like(A4)
+    for r in range(m):
+        for c in range(m):
+            T = A4[r, :, c, :]
+            t = np.array([T[l, 0] if l >= 0 else T[0, -l] for l in range(-(nx - 1), nx)])
+            cc = C.chan(t)
+            CB[r, :, c, :] = np.array([[cc[(i - j) % nx] for j in range(nx)] for i in range(nx)])
+    return CB.reshape(m * nx, m * nx), A
+
+
+def test_block_circulant_inverse_matches_dense(box):
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    CB, _ = _dense_block_circulant(K, Mt, grid)
+    inv = C.BlockCirculantInverse(K, Mt, nx, ny, nz)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(3 * nx * ny * nz) + 1j * rng.standard_normal(3 * nx * ny * nz)
+    z = inv.apply(r.reshape(3, nz, ny, nx)).reshape(-1)
+    assert np.allclose(z, np.linalg.solve(CB, r), rtol=1e-12, atol=1e-12)
+
+
+def test_blocks_are_the_permuted_fourier_diagonal(box):
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    m = 3 * ny * nz
+    CB, _ = _dense_block_circulant(K, Mt, grid)
+    F = C.dft_matrix(nx)
+    FF = np.kron(np.eye(m), F)
+    L = FF @ CB @ np.linalg.inv(FF)                      # [Lambda_ij], each diagonal
+    L4 = L.reshape(m, nx, m, nx)
+    D = C.chan_olkin_blocks(K, Mt, nx, ny, nz)
+    for k in range(nx):
+        assert np.allclose(L4[:, k, :, k], D[k], atol=1e-12)
+        for k2 in range(nx):
+            if k2 != k:
+                assert np.abs(L4[:, k, :, k2]).max() < 1e-12
+
+
+def test_x_circulant_operator_gives_exact_preconditioner():
+    grid = (5, 2, 2)
+    nx, ny, nz = grid
+    Kfull = G.generator_octant(grid, KAPPA)
+    K = np.zeros_like(Kfull)
+    K[:, :, :, 0] = Kfull[:, :, :, 0]         # no coupling along x: T blocks are diagonal
+    M = np.full((nz, ny, nx), 0.8 + 0.05j)
+    A = MV.operator_matrix(K, M, grid)
+    P = C.BlockedPreconditioner(K, M, grid, homog='none')
+    b = np.random.default_rng(4).standard_normal(3 * 20) + 0j
+    x, info = GM.gmres(lambda v: A @ v, b, M=P.apply, tol=1e-12)
+    assert info['iters'] == 1 and info['relres'] < 1e-12
+
+
+def test_zero_contrast_gives_identity(box):
+    grid, K, _ = box
+    nx, ny, nz = grid
+    inv = C.BlockCirculantInverse(K, np.zeros((nz, ny)), nx, ny, nz)
+    r = np.random.default_rng(5).standard_normal((3, nz, ny, nx)) + 0j
+    assert np.allclose(inv.apply(r), r, rtol=1e-14, atol=1e-14)
+
+
+def test_reduction_limits_and_monotone(box):
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    full = C.BlockCirculantInverse(K, Mt, nx, ny, nz)
+    r = np.random.default_rng(6).standard_normal((3, nz, ny, nx)) + 0j
+    red0 = C.BlockCirculantInverse(K, Mt, nx, ny, nz, reduce_tol=0.0)
+    assert red0.keep.all()
+    assert np.array_equal(red0.apply(r), full.apply(r))
+    red2 = C.BlockCirculantInverse(K, Mt, nx, ny, nz, reduce_tol=2.0)
+    assert red2.keep.sum() == 1 and red2.keep[int(np.ceil(nx / 2)) - 1]
+    v = C.proxy_values(K, nx, ny, nz)
+    counts = [C.reduction_keep(v, tol)[0].sum() for tol in (0.0, 1e-3, 1e-2, 0.1, 0.5, 2.0)]
+    assert all(a >= b for a, b in zip(counts, counts[1:]))
+
+
+def test_proxy_entry_location():
+    # ny=16, nz=8 -> column ceil(16/2)*ceil(8/2) = 32 (1-based) -> y'=15, z'=1
+    grid = (4, 16, 8)
+    K = np.zeros((6, 8, 16, 4), dtype=complex)
+    K[0, 1, 15, :] = np.array([1.0, 2.0, 3.0, 4.0])
+    v = C.proxy_values(K, 4, 16, 8)
+    # t_l = K^{xx}(l, -15, -1) = K(|l|, 15, 1); Chan + DFT by hand
+    t = np.array([4.0, 3.0, 2.0, 1.0, 2.0, 3.0, 4.0])
+    c = C.chan(t)
+    assert np.allclose(v, C.dft_matrix(4) @ c)
+
+
+def test_blocked_single_box_equals_one_level(box):
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    M = np.broadcast_to(Mt[:, :, None], (nz, ny, nx))
+    P = C.BlockedPreconditioner(K, M, grid)
+    inv = C.BlockCirculantInverse(K, Mt, nx, ny, nz)
+    r = np.random.default_rng(8).standard_normal(3 * nx * ny * nz) + 0j
+    assert np.array_equal(P.apply(r), inv.apply(r.reshape(3, nz, ny, nx)).reshape(-1))
+
+
+def test_blocked_boxes_equal_dense_block_diagonal():
+    grid = (8, 3, 2)
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    rng = np.random.default_rng(9)
+    M = 0.7 + 0.2 * rng.standard_normal((nz, ny, nx)) + 0.01j
+    boxes = [(0, 0, 0, 3, 3, 2), (3, 0, 0, 4, 2, 2)]       # last x column and one y row uncovered
+    P = C.BlockedPreconditioner(K, M, grid, boxes=boxes, homog='mean')
+    n = nx * ny * nz
+    Pd = np.eye(3 * n, dtype=complex)
+    idx = lambda a, x, y, z: a * n + x + nx * (y + ny * z)
+    for (x0, y0, z0, bx, by, bz) in boxes:
+        Mt = CT.homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], 'mean')
+        CB, _ = _dense_block_circulant(K, Mt, (bx, by, bz))
+        Cinv = np.linalg.inv(CB)
+        loc = [idx(a, x0 + x, y0 + y, z0 + z) for a in range(3) for z in range(bz)
+               for y in range(by) for x in range(bx)]
+        Pd[np.ix_(loc, loc)] = Cinv
+    r = rng.standard_normal(3 * n) + 1j * rng.standard_normal(3 * n)
+    assert np.allclose(P.apply(r), Pd @ r, rtol=1e-12, atol=1e-12)
+
+
+def test_homogenisations():
+    M = np.zeros((1, 2, 4), dtype=complex)
+    M[0, 0] = [1 + 1j, 2, 1 + 1j, 3]
+    M[0, 1] = [2, 2, 0.5j, 1 + 1j]
+    assert np.allclose(CT.homogenize(M, 'mode'), 1 + 1j)      # 3 x (1+1j) vs 3 x 2: earlier first
+    assert np.allclose(CT.homogenize(M, 'mean'), [[(7 + 2j) / 4, (5 + 1.5j) / 4]])
+    assert np.allclose(CT.homogenize(M, 'realmean'), [[7 / 4, 5 / 4]])
+    with pytest.raises(ValueError):
+        CT.homogenize(M, 'none')
+    U = np.ones((2, 2, 3)) * (0.5 + 0.1j)
+    assert np.allclose(CT.homogenize(U, 'none'), 0.5 + 0.1j)
