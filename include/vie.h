@@ -1,0 +1,183 @@
+/*
+ * vie.h -- C ABI of the MI355X voxel volume-integral-equation solver.
+ *
+ * Problem (Groth, Polimeridis, Tambova & White, arXiv:1903.07884, Sec. 2,
+ * eq. discrete_form): on a uniform grid of nx*ny*nz cubic voxels of edge
+ * Delta, solve
+ *
+ *        (I - M N) w = b,      b = M e_inc  (the factor j w eps0 is dropped),
+ *
+ * where M = (eps_r - 1)/eps_r is the diagonal contrast (eq. JVIE) and
+ * N^{ab}_{ij} = <N p_j^b, p_i^a> is the Galerkin matrix of the operator
+ * curl curl int exp(-j k R)/(4 pi R) on the orthonormal piecewise-constant
+ * voxel basis (eq. op_N).  Permittivities are relative to a homogeneous
+ * background of wavenumber k_background (Sec. 3, Table ref_ind).
+ *
+ * Vectors.  Every vector is interleaved complex (re, im) with layout
+ * [nrhs][3][nz][ny][nx] (component a = x, y, z slowest within one RHS, x
+ * fastest), i.e. the unknown ordering w = [w^x; w^y; w^z] of eq. sys_mat.
+ * VIE_C128 vectors are complex<double>, VIE_C64 vectors complex<float>.
+ * Vector arguments are DEVICE pointers owned by the caller; the library never
+ * frees or retains them beyond the call.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = legacy default
+ * stream).  vie_matvec, vie_rhs and precond_apply are asynchronous on it;
+ * vie_create, precond_setup and vie_solve synchronise it before returning.
+ * A handle owns per-handle scratch memory, so calls that use the same handle
+ * concurrently from different streams race: serialise them.
+ *
+ * Errors.  Every call returns a vie_status.  Negative values are failures;
+ * outputs are then unspecified and *out handles are set to NULL.
+ * vie_last_error() returns a thread-local message describing the last
+ * failure.  Argument errors are detected before any device work.  No C++
+ * exception crosses this interface.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vie_op_s *vie_op; /* owns M, the FP64 generator and the kernel transforms */
+typedef struct vie_pc_s *vie_pc; /* owns boxes, homogenised contrasts, block map, LU factors */
+
+typedef enum {
+    VIE_C128 = 0, /* complex<double> */
+    VIE_C64 = 1   /* complex<float>  */
+} vie_prec;
+
+typedef enum {
+    VIE_OK = 0,
+    VIE_NOT_CONVERGED = 1, /* vie_solve: best iterate returned, stats filled */
+    VIE_EARG = -1,         /* invalid argument (checked before device work)  */
+    VIE_EOOM = -2,         /* device allocation failed                        */
+    VIE_EDEVICE = -3,      /* HIP runtime error                               */
+    VIE_ESINGULAR = -4,    /* a preconditioner block has a zero pivot         */
+    VIE_ENONFINITE = -5    /* non-finite input or residual                    */
+} vie_status;
+
+/* ---- operator ------------------------------------------------------------ */
+
+typedef struct {
+    /* Also build the complex64 kernel transform so vie_matvec accepts VIE_C64. */
+    int32_t build_c64;
+    /* Debug / testing: host array of 12*nx*ny*nz doubles holding the generator
+     * K^{ab}(d) (N = I + K) on the octant d >= 0 as [6][nz][ny][nx] interleaved
+     * complex, components (xx, yy, zz, xy, xz, yz).  NULL = compute it by
+     * quadrature on the device (the normal path). */
+    const double *generator;
+} vie_create_opts;
+
+/* Build the operator of eq. discrete_form.
+ *   grid[3]       = {nx, ny, nz}, each >= 1 (x is the long, Toeplitz-innermost axis)
+ *   voxel_size    = Delta in metres (> 0)
+ *   k_background  = background wavenumber k_b = 2 pi sqrt(eps_b)/lambda0 in 1/m (>= 0)
+ *   chi           = HOST array of 2*nx*ny*nz doubles, interleaved complex relative
+ *                   contrast chi = eps/eps_b - 1 per voxel, [nz][ny][nx]; 1 + chi != 0
+ *   opts          = nullable
+ * The generator is computed in FP64 (Sec. 2, eq. op_N; six unique blocks, each
+ * defined by one octant through its per-axis parity), embedded in a circulant
+ * and transformed by FFT.  Synchronises `stream`. */
+vie_status vie_create(const int32_t grid[3], double voxel_size, double k_background,
+                      const double *chi, const vie_create_opts *opts, void *stream,
+                      vie_op *out);
+vie_status vie_destroy(vie_op op);
+
+/* Copy the FP64 octant generator (12*nx*ny*nz doubles, layout as in
+ * vie_create_opts.generator) to the HOST array `out`.  Synchronous. */
+vie_status vie_generator(vie_op op, double *out);
+
+/* b = M e_inc per voxel and component (right-hand side of eq. discrete_form
+ * without the factor j w eps0).  e_inc, b: device, c128, nrhs vectors. */
+vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrhs, void *stream);
+
+/* y = (I - M N) x  (eq. discrete_form) for nrhs vectors.  x, y: device, in
+ * precision `prec` (VIE_C64 needs build_c64).  x and y must not overlap.
+ * The product with the three-level Toeplitz N uses FFTs of the embedded
+ * circulant (Sec. 1: O(n log n) products). */
+vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec,
+                      void *stream);
+
+/* ---- preconditioner ------------------------------------------------------ */
+
+typedef enum {
+    VIE_HOMOG_NONE = 0,    /* use M itself; it must not vary along x inside a box */
+    VIE_HOMOG_MODE = 1,    /* Sec. 5.2, item 1: modal value of M over the box     */
+    VIE_HOMOG_MEAN = 2,    /* Sec. 5.2, item 2: mean of M along x                 */
+    VIE_HOMOG_REALMEAN = 3 /* Sec. 5.2, item 3: real part of the mean along x     */
+} vie_homog;
+
+typedef struct {
+    int32_t homog;       /* vie_homog */
+    int32_t nboxes;      /* 0 = one box covering the whole grid */
+    const int32_t *boxes;/* HOST, nboxes*6: {x0, y0, z0, bx, by, bz} per box; boxes must
+                            lie inside the grid, must not overlap and (this build) share
+                            one shape.  Voxels outside every box are left unchanged
+                            (Sec. 5.3: blocked-circulant preconditioner). */
+    int32_t reduce;      /* 1 = memory-reduced 1-level preconditioner (Sec. 5.1.1) */
+    double reduce_tol;   /* keep mode k iff |v_k|/||v||_inf > reduce_tol (paper: 1e-3) */
+    int32_t factor_prec; /* vie_prec of the stored LU factors */
+} vie_pc_opts;
+
+typedef struct {
+    int32_t nboxes, box_nx, block_m;  /* per-box length along x, block size m = 3*by*bz */
+    int32_t modes;                    /* nboxes * box_nx Fourier modes */
+    int32_t stored_blocks;            /* LU-factored blocks held on the device */
+    int64_t factor_bytes;             /* bytes of LU factors (+ pivots) */
+} vie_pc_info;
+
+/* Build the 1-level Chan-Olkin block-circulant preconditioner (Sec. 4): per box,
+ * T. Chan's optimal circulant (eq. Chan) of every x-level Toeplitz block of
+ * I - M~ N, a DFT along x, and the permuted diagonal blocks D_k (eq. Di), each
+ * LU-factorised with partial pivoting.  Synchronises `stream`. */
+vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *stream, vie_pc *out);
+vie_status precond_info(vie_pc pc, vie_pc_info *info);
+vie_status precond_destroy(vie_pc pc);
+
+/* z = P^{-1} r: per box, DFT along x, block solves with the LU factors of the
+ * D_k, inverse DFT (Sec. 4, inverse after eq. Di); identity outside the boxes.
+ * r, z: device, precision `prec`, nrhs vectors; must not overlap. */
+vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t nrhs, vie_prec prec,
+                         void *stream);
+
+/* ---- solver ---------------------------------------------------------------- */
+
+typedef enum {
+    VIE_MODE_FP64 = 0,  /* GMRES, everything in complex128 */
+    VIE_MODE_MIXED = 1  /* flexible GMRES: complex64 matvec and preconditioner,
+                           FP64 Arnoldi/Givens and FP64 true residual */
+} vie_mode;
+
+typedef struct {
+    double tol;        /* relative residual ||b - A x|| / ||b|| (default 1e-6) */
+    int32_t restart;   /* Krylov dimension per cycle (default 50, max 200) */
+    int32_t maxit;     /* total Arnoldi steps per right-hand side (default 5000) */
+    int32_t mode;      /* vie_mode */
+    int32_t x0_given;  /* 1 = x holds the initial guess, 0 = start from zero */
+} vie_solve_opts;
+
+typedef struct {
+    int32_t iters;     /* Arnoldi steps summed over cycles */
+    int32_t restarts;  /* completed cycles */
+    double relres;     /* true relative residual of the returned x (FP64) */
+    int32_t status;    /* VIE_OK or VIE_NOT_CONVERGED */
+} vie_solve_stats;
+
+/* Right-preconditioned restarted GMRES for (I - M N) x = b (Sec. 1; restart,
+ * side and tolerance are this library's choices, the paper reports 1e-4).
+ * b, x: device c128, nrhs vectors.  pc = NULL solves unpreconditioned.
+ * stats: HOST array of nrhs entries.  Synchronises `stream`. */
+vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
+                     const vie_solve_opts *opts, vie_solve_stats *stats, void *stream);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *vie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIE_H */

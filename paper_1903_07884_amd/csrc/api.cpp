@@ -1,0 +1,242 @@
+// C ABI entry points: argument validation, handle ownership, orchestration.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "vie_internal.h"
+
+static thread_local std::string g_err;
+void vie_set_error(const std::string &msg) { g_err = msg; }
+extern "C" const char *vie_last_error(void) { return g_err.c_str(); }
+
+static vie_status arg_error(const std::string &msg) {
+    g_err = msg;
+    return VIE_EARG;
+}
+
+static size_t max_lds() {
+    static size_t v = 0;
+    if (!v) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            v = p.sharedMemPerBlock;
+        else
+            v = 65536;
+    }
+    return v;
+}
+
+extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, double k_background, const double *chi,
+                                 const vie_create_opts *opts, void *stream, vie_op *out) {
+    if (!out) return arg_error("vie_create: out is NULL");
+    *out = nullptr;
+    if (!grid) return arg_error("vie_create: grid is NULL");
+    if (!chi) return arg_error("vie_create: chi is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 1) return arg_error("vie_create: every grid dimension must be >= 1");
+    if (!(voxel_size > 0) || !std::isfinite(voxel_size)) return arg_error("vie_create: voxel_size must be > 0");
+    if (!(k_background >= 0) || !std::isfinite(k_background))
+        return arg_error("vie_create: k_background must be finite and >= 0");
+    long long N = (long long)grid[0] * grid[1] * grid[2];
+    if (N > (1LL << 31)) return arg_error("vie_create: grid too large");
+    for (long long i = 0; i < N; ++i) {
+        double re = chi[2 * i], im = chi[2 * i + 1];
+        if (!std::isfinite(re) || !std::isfinite(im)) return arg_error("vie_create: non-finite contrast");
+        if (re == -1.0 && im == 0.0) return arg_error("vie_create: 1 + chi must be non-zero");
+    }
+    vie_create_opts o{};
+    if (opts) o = *opts;
+    vie_op op = new (std::nothrow) vie_op_s();
+    if (!op) return VIE_EOOM;
+    hipStream_t s = (hipStream_t)stream;
+    op->nx = grid[0];
+    op->ny = grid[1];
+    op->nz = grid[2];
+    op->N = N;
+    op->delta = voxel_size;
+    op->kb = k_background;
+    op->kappa = k_background * voxel_size;
+    op->Px = fft_good_length(2 * op->nx - 1);
+    op->Py = fft_good_length(2 * op->ny - 1);
+    op->Pz = fft_good_length(2 * op->nz - 1);
+    op->Hx = op->Px / 2 + 1;
+    op->Hy = op->Py / 2 + 1;
+    op->Hz = op->Pz / 2 + 1;
+    op->has_c64 = o.build_c64 != 0;
+    auto fail = [&](vie_status st) {
+        delete op;
+        return st;
+    };
+    if (2 * sizeof(c128) * op->Px > max_lds())
+        return fail(arg_error("vie_create: x extent too long for the LDS line transform (padded length " +
+                              std::to_string(op->Px) + ")"));
+    if (6 * sizeof(c128) * op->Py * op->Pz > max_lds())
+        return fail(arg_error("vie_create: cross-section too large for the LDS plane transform"));
+    vie_status st;
+    if ((st = op->fft.get(op->Px, &op->px)) < 0) return fail(st);
+    if ((st = op->fft.get(op->Py, &op->py)) < 0) return fail(st);
+    if ((st = op->fft.get(op->Pz, &op->pz)) < 0) return fail(st);
+    if ((st = op->M64.ensure(sizeof(c128) * N)) < 0) return fail(st);
+    if ((st = op->M32.ensure(sizeof(c64) * N)) < 0) return fail(st);
+    if ((st = op->gen.ensure(sizeof(c128) * 6 * N)) < 0) return fail(st);
+    {
+        DevBuf chid;
+        if ((st = chid.ensure(sizeof(c128) * N)) < 0) return fail(st);
+        if (hipMemcpyAsync(chid.p, chi, sizeof(c128) * N, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(VIE_EDEVICE);
+        if ((st = launch_contrast(op, chid.as<c128>(), s)) < 0) return fail(st);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(VIE_EDEVICE);
+    }
+    if (o.generator) {
+        if (hipMemcpyAsync(op->gen.p, o.generator, sizeof(c128) * 6 * N, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(VIE_EDEVICE);
+    } else if ((st = launch_generator(op, s)) < 0)
+        return fail(st);
+    if ((st = build_kernel_transform(op, s)) < 0) return fail(st);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        g_err = std::string("vie_create: ") + hipGetErrorString(e);
+        return fail(VIE_EDEVICE);
+    }
+    *out = op;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_destroy(vie_op op) {
+    if (!op) return VIE_OK;
+    delete op;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_generator(vie_op op, double *out) {
+    if (!op || !out) return arg_error("vie_generator: NULL argument");
+    VIE_HIP(hipDeviceSynchronize());
+    VIE_HIP(hipMemcpy(out, op->gen.p, sizeof(c128) * 6 * op->N, hipMemcpyDeviceToHost));
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrhs, void *stream) {
+    if (!op || !e_inc || !b) return arg_error("vie_rhs: NULL argument");
+    if (nrhs < 1) return arg_error("vie_rhs: nrhs must be >= 1");
+    return launch_rhs(op, (const c128 *)e_inc, (c128 *)b, nrhs, (hipStream_t)stream);
+}
+
+extern "C" vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec, void *stream) {
+    if (!op || !x || !y) return arg_error("vie_matvec: NULL argument");
+    if (nrhs < 1) return arg_error("vie_matvec: nrhs must be >= 1");
+    if (prec != VIE_C128 && prec != VIE_C64) return arg_error("vie_matvec: unknown precision");
+    if (prec == VIE_C64 && !op->has_c64) return arg_error("vie_matvec: operator built without complex64 transform");
+    if (x == y) return arg_error("vie_matvec: x and y must not overlap");
+    return launch_matvec(op, x, y, nrhs, prec, (hipStream_t)stream);
+}
+
+extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *stream, vie_pc *out) {
+    if (!out) return arg_error("precond_setup: out is NULL");
+    *out = nullptr;
+    if (!op || !opts) return arg_error("precond_setup: NULL argument");
+    const vie_pc_opts &o = *opts;
+    if (o.homog < VIE_HOMOG_NONE || o.homog > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown homog");
+    if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64)
+        return arg_error("precond_setup: unknown factor precision");
+    if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
+        return arg_error("precond_setup: reduce_tol must be finite and >= 0");
+    std::vector<int> boxes;
+    if (o.nboxes < 0) return arg_error("precond_setup: nboxes < 0");
+    if (o.nboxes == 0) {
+        boxes = {0, 0, 0, op->nx, op->ny, op->nz};
+    } else {
+        if (!o.boxes) return arg_error("precond_setup: boxes is NULL");
+        boxes.assign(o.boxes, o.boxes + 6 * o.nboxes);
+    }
+    int nb = (int)boxes.size() / 6;
+    const int dims[3] = {op->nx, op->ny, op->nz};
+    long long vol = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int *B = &boxes[6 * b];
+        for (int a = 0; a < 3; ++a)
+            if (B[a] < 0 || B[3 + a] < 1 || B[a] + B[3 + a] > dims[a])
+                return arg_error("precond_setup: box " + std::to_string(b) + " outside the grid");
+        for (int a = 3; a < 6; ++a)
+            if (B[a] != boxes[a]) return arg_error("precond_setup: all boxes must share one shape");
+        for (int c = 0; c < b; ++c) {
+            const int *C = &boxes[6 * c];
+            bool ov = true;
+            for (int a = 0; a < 3; ++a)
+                if (B[a] + B[3 + a] <= C[a] || C[a] + C[3 + a] <= B[a]) ov = false;
+            if (ov) return arg_error("precond_setup: boxes overlap");
+        }
+        vol += (long long)B[3] * B[4] * B[5];
+    }
+    int bx = boxes[3], by = boxes[4], bz = boxes[5], m = 3 * by * bz;
+    size_t esz = o.factor_prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+    if (!fft_supported_length(bx))
+        return arg_error("precond_setup: box length " + std::to_string(bx) + " has a prime factor above " +
+                         std::to_string(VIE_FFT_MAX_PRIME));
+    if (2 * sizeof(c128) * bx > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
+    if ((2 * (size_t)m + 32 * 32) * esz > max_lds())
+        return arg_error("precond_setup: cross-section block too large for the block solve");
+    vie_pc pc = new (std::nothrow) vie_pc_s();
+    if (!pc) return VIE_EOOM;
+    pc->op = op;
+    pc->nboxes = nb;
+    pc->bx = bx;
+    pc->by = by;
+    pc->bz = bz;
+    pc->m = m;
+    pc->boxes = boxes;
+    pc->covers_all = vol == op->N;
+    pc->prec = o.factor_prec;
+    vie_status st = pc_build(pc, &o, (hipStream_t)stream);
+    if (st < 0) {
+        delete pc;
+        return st;
+    }
+    *out = pc;
+    return VIE_OK;
+}
+
+extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
+    if (!pc || !info) return arg_error("precond_info: NULL argument");
+    info->nboxes = pc->nboxes;
+    info->box_nx = pc->bx;
+    info->block_m = pc->m;
+    info->modes = pc->nboxes * pc->bx;
+    info->stored_blocks = pc->nstored;
+    size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+    info->factor_bytes = (int64_t)pc->nstored * pc->m * ((int64_t)pc->m * esz + sizeof(int));
+    return VIE_OK;
+}
+
+extern "C" vie_status precond_destroy(vie_pc pc) {
+    if (pc) delete pc;
+    return VIE_OK;
+}
+
+extern "C" vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t nrhs, vie_prec prec, void *stream) {
+    if (!pc || !r || !z) return arg_error("precond_apply: NULL argument");
+    if (nrhs < 1) return arg_error("precond_apply: nrhs must be >= 1");
+    if (r == z) return arg_error("precond_apply: r and z must not overlap");
+    return pc_apply(pc, r, z, nrhs, prec, (hipStream_t)stream);
+}
+
+extern "C" vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
+                                const vie_solve_opts *opts, vie_solve_stats *stats, void *stream) {
+    if (!op || !b || !x || !stats) return arg_error("vie_solve: NULL argument");
+    if (nrhs < 1) return arg_error("vie_solve: nrhs must be >= 1");
+    if (pc && pc->op != op) return arg_error("vie_solve: preconditioner built for another operator");
+    vie_solve_opts o{1e-6, 50, 5000, VIE_MODE_FP64, 0};
+    if (opts) o = *opts;
+    if (!(o.tol > 0) || !std::isfinite(o.tol)) return arg_error("vie_solve: tol must be > 0");
+    if (o.restart < 1 || o.restart > 200) return arg_error("vie_solve: restart must be in [1, 200]");
+    if (o.maxit < 1) return arg_error("vie_solve: maxit must be >= 1");
+    if (o.mode != VIE_MODE_FP64) return arg_error("vie_solve: only VIE_MODE_FP64 is available in this build");
+    hipStream_t s = (hipStream_t)stream;
+    vie_status st = solve_gmres(op, pc, (const c128 *)b, (c128 *)x, nrhs, &o, stats, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (st >= 0 && e != hipSuccess) {
+        g_err = std::string("vie_solve: ") + hipGetErrorString(e);
+        return VIE_EDEVICE;
+    }
+    return st;
+}

@@ -1,0 +1,172 @@
+// LDS-resident Stockham FFT used by the matvec and preconditioner kernels.
+//
+// A transform of length L = p_1 p_2 ... p_s runs s stages.  Stage t (radix p,
+// Ns = p_1 ... p_{t-1}) reads butterfly j's inputs src[j + r L/p], multiplies
+// input r by W_L^{r k L/(Ns p)} with k = j mod Ns, applies a length-p DFT and
+// writes output r to dst[(j / Ns) Ns p + k + r Ns]; after the last stage the
+// result is in natural order (autosort), so no bit reversal is needed.
+// Forward uses W_L = exp(-2 pi i / L), inverse its conjugate; neither scales.
+#pragma once
+
+#include "vie_internal.h"
+
+template <class R>
+struct TwTable;
+template <>
+struct TwTable<double> {
+    static __device__ __forceinline__ const c128 *get(const FftPlan &p) { return p.tw64; }
+};
+template <>
+struct TwTable<float> {
+    static __device__ __forceinline__ const c64 *get(const FftPlan &p) { return p.tw32; }
+};
+
+// Lines addressed inside LDS: line l starts at (l % nl1) * s1 + (l / nl1) * s2,
+// element i of a line sits at start + i * es.
+struct LdsLines {
+    int nl1, s1, s2, es, nlines;
+};
+
+template <class R>
+__device__ __forceinline__ cpx<R> tw_at(const cpx<R> *tw, int q, bool inv) {
+    cpx<R> w = tw[q];
+    if (inv) w.im = -w.im;
+    return w;
+}
+
+template <class R>
+__device__ __forceinline__ void bfly2(cpx<R> *v) {
+    cpx<R> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <class R>
+__device__ __forceinline__ void bfly4(cpx<R> *v, bool inv) {
+    cpx<R> s02 = v[0] + v[2], d02 = v[0] - v[2];
+    cpx<R> s13 = v[1] + v[3], d13 = v[1] - v[3];
+    // forward: -i * d13 ; inverse: +i * d13
+    cpx<R> rot = inv ? mk(-d13.im, d13.re) : mk(d13.im, -d13.re);
+    v[0] = s02 + s13;
+    v[2] = s02 - s13;
+    v[1] = d02 + rot;
+    v[3] = d02 - rot;
+}
+
+template <class R>
+__device__ __forceinline__ void bfly3(cpx<R> *v, bool inv) {
+    const R h = R(0.8660254037844386467637231707529362);  // sqrt(3)/2
+    cpx<R> s = v[1] + v[2], d = v[1] - v[2];
+    cpx<R> t = mk(v[0].re - R(0.5) * s.re, v[0].im - R(0.5) * s.im);
+    // forward: y1 = t - i h d, y2 = t + i h d
+    R sg = inv ? R(-1) : R(1);
+    cpx<R> u = mk(sg * h * d.im, -sg * h * d.re);  // -i*sg*h*d
+    v[0] = v[0] + s;
+    v[1] = t + u;
+    v[2] = t - u;
+}
+
+template <class R>
+__device__ __forceinline__ void bfly5(cpx<R> *v, bool inv) {
+    const R c1 = R(0.3090169943749474241022934171828191);
+    const R c2 = R(-0.8090169943749474241022934171828191);
+    const R s1 = R(0.9510565162951535721164393333793821);
+    const R s2 = R(0.5877852522924731291687059546390728);
+    R sg = inv ? R(-1) : R(1);
+    cpx<R> b1 = v[1] + v[4], b2 = v[2] + v[3];
+    cpx<R> d1 = v[1] - v[4], d2 = v[2] - v[3];
+    cpx<R> a0 = v[0];
+    cpx<R> p1 = mk(a0.re + c1 * b1.re + c2 * b2.re, a0.im + c1 * b1.im + c2 * b2.im);
+    cpx<R> p2 = mk(a0.re + c2 * b1.re + c1 * b2.re, a0.im + c2 * b1.im + c1 * b2.im);
+    cpx<R> q1 = mk(s1 * d1.re + s2 * d2.re, s1 * d1.im + s2 * d2.im);
+    cpx<R> q2 = mk(s2 * d1.re - s1 * d2.re, s2 * d1.im - s1 * d2.im);
+    // -i*sg*q
+    cpx<R> m1 = mk(sg * q1.im, -sg * q1.re);
+    cpx<R> m2 = mk(sg * q2.im, -sg * q2.re);
+    v[0] = a0 + b1 + b2;
+    v[1] = p1 + m1;
+    v[4] = p1 - m1;
+    v[2] = p2 + m2;
+    v[3] = p2 - m2;
+}
+
+// One Stockham stage over all lines; src -> dst (both LDS).
+template <class R, int P>
+__device__ __forceinline__ void stage_fixed(const cpx<R> *src, cpx<R> *dst, const LdsLines &ln, int L,
+                                            int Ns, const cpx<R> *tw, bool inv) {
+    const int nb = L / P;
+    const int total = nb * ln.nlines;
+    const int twstep = L / (Ns * P);
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int l = t / nb, j = t - l * nb;
+        int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
+        int k = j % Ns;
+        cpx<R> v[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            cpx<R> a = src[base + (j + r * nb) * ln.es];
+            v[r] = (r == 0 || k == 0) ? a : a * tw_at(tw, r * k * twstep, inv);
+        }
+        if (P == 2) bfly2(v);
+        if (P == 3) bfly3(v, inv);
+        if (P == 4) bfly4(v, inv);
+        if (P == 5) bfly5(v, inv);
+        int d = (j / Ns) * Ns * P + k;
+#pragma unroll
+        for (int r = 0; r < P; ++r) dst[base + (d + r * Ns) * ln.es] = v[r];
+    }
+}
+
+// Generic prime radix: out[s] = sum_r src[j + r L/p] W_L^{r (k + s Ns) L/(Ns p)}.
+template <class R>
+__device__ void stage_generic(const cpx<R> *src, cpx<R> *dst, const LdsLines &ln, int L, int Ns, int P,
+                              const cpx<R> *tw, bool inv) {
+    const int nb = L / P;
+    const int total = nb * ln.nlines * P;
+    const int step = L / (Ns * P);
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int s = t % P;
+        int u = t / P;
+        int l = u / nb, j = u - l * nb;
+        int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
+        int k = j % Ns;
+        int e = (k + s * Ns) * step;  // < L
+        cpx<R> acc = czero<R>();
+        int q = 0;
+        for (int r = 0; r < P; ++r) {
+            acc = acc + src[base + (j + r * nb) * ln.es] * tw_at(tw, q, inv);
+            q += e;
+            if (q >= L) q -= L;
+        }
+        int d = (j / Ns) * Ns * P + k;
+        dst[base + (d + s * Ns) * ln.es] = acc;
+    }
+}
+
+// Transform all lines of `a`; `b` is a same-shaped scratch buffer.  Returns the
+// buffer holding the result.  Caller must __syncthreads() before (data ready).
+template <class R>
+__device__ cpx<R> *fft_lds(cpx<R> *a, cpx<R> *b, const LdsLines &ln, const FftPlan &plan, bool inv) {
+    const cpx<R> *tw = TwTable<R>::get(plan);
+    const int L = plan.L;
+    int Ns = 1;
+    cpx<R> *src = a, *dst = b;
+    for (int st = 0; st < plan.nrad; ++st) {
+        int P = plan.rad[st];
+        switch (P) {
+            case 2: stage_fixed<R, 2>(src, dst, ln, L, Ns, tw, inv); break;
+            case 3: stage_fixed<R, 3>(src, dst, ln, L, Ns, tw, inv); break;
+            case 4: stage_fixed<R, 4>(src, dst, ln, L, Ns, tw, inv); break;
+            case 5: stage_fixed<R, 5>(src, dst, ln, L, Ns, tw, inv); break;
+            default: stage_generic<R>(src, dst, ln, L, Ns, P, tw, inv); break;
+        }
+        __syncthreads();
+        Ns *= P;
+        cpx<R> *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+extern __shared__ __align__(16) unsigned char vie_smem[];

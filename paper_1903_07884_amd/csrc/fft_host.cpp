@@ -1,0 +1,120 @@
+// FFT plans: radix factorisation and device twiddle tables.
+#include <cmath>
+#include <mutex>
+
+#include "vie_internal.h"
+
+static int smallest_prime_factor(int n) {
+    for (int p = 2; p * p <= n; ++p)
+        if (n % p == 0) return p;
+    return n;
+}
+
+bool fft_supported_length(int L) {
+    if (L < 1) return false;
+    int n = L;
+    while (n > 1) {
+        int p = smallest_prime_factor(n);
+        if (p > VIE_FFT_MAX_PRIME) return false;
+        n /= p;
+    }
+    return true;
+}
+
+int fft_good_length(int minL) {
+    if (minL <= 1) return 1;
+    for (int L = minL;; ++L) {
+        int n = L;
+        for (int p : {2, 3, 5})
+            while (n % p == 0) n /= p;
+        if (n == 1) return L;
+    }
+}
+
+static void factor(int L, FftPlan *plan) {
+    int n = L;
+    plan->nrad = 0;
+    while (n % 4 == 0) {
+        plan->rad[plan->nrad++] = 4;
+        n /= 4;
+    }
+    while (n % 2 == 0) {
+        plan->rad[plan->nrad++] = 2;
+        n /= 2;
+    }
+    while (n > 1) {
+        int p = smallest_prime_factor(n);
+        plan->rad[plan->nrad++] = p;
+        n /= p;
+    }
+}
+
+vie_status FftCache::get(int L, FftPlan *plan) {
+    if (!fft_supported_length(L)) {
+        vie_set_error("FFT length " + std::to_string(L) + " has a prime factor above " +
+                      std::to_string(VIE_FFT_MAX_PRIME));
+        return VIE_EARG;
+    }
+    Entry *e = nullptr;
+    for (Entry *x : entries)
+        if (x->L == L) e = x;
+    if (!e) {
+        e = new Entry();
+        e->L = L;
+        entries.push_back(e);
+        std::vector<c128> h64(L);
+        std::vector<c64> h32(L);
+        const long double twopi = 6.283185307179586476925286766559005768L;
+        for (int q = 0; q < L; ++q) {
+            // exp(-2 pi i q / L), using the exactly representable reduction q/L in [0, 1)
+            long double a = twopi * (long double)q / (long double)L;
+            double c = (double)cosl(a), s = (double)(-sinl(a));
+            // exact values on the axes
+            if (4LL * q == 0) { c = 1.0; s = 0.0; }
+            if (4LL * q == (long long)L) { c = 0.0; s = -1.0; }
+            if (2LL * q == (long long)L) { c = -1.0; s = 0.0; }
+            if (4LL * q == 3LL * L) { c = 0.0; s = 1.0; }
+            h64[q] = mk(c, s);
+            h32[q] = mk((float)c, (float)s);
+        }
+        VIE_CHECK(e->t64.ensure(sizeof(c128) * L));
+        VIE_CHECK(e->t32.ensure(sizeof(c64) * L));
+        VIE_HIP(hipMemcpy(e->t64.p, h64.data(), sizeof(c128) * L, hipMemcpyHostToDevice));
+        VIE_HIP(hipMemcpy(e->t32.p, h32.data(), sizeof(c64) * L, hipMemcpyHostToDevice));
+    }
+    plan->L = L;
+    factor(L, plan);
+    plan->tw64 = e->t64.as<const c128>();
+    plan->tw32 = e->t32.as<const c64>();
+    return VIE_OK;
+}
+
+FftCache::~FftCache() {
+    for (Entry *e : entries) {
+        e->t64.release();
+        e->t32.release();
+        delete e;
+    }
+}
+
+vie_status DevBuf::ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return VIE_OK;
+    release();
+    if (nbytes == 0) return VIE_OK;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        p = nullptr;
+        bytes = 0;
+        vie_set_error("hipMalloc of " + std::to_string(nbytes) + " bytes failed: " +
+                      hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? VIE_EOOM : VIE_EDEVICE;
+    }
+    bytes = nbytes;
+    return VIE_OK;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}

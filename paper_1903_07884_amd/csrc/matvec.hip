@@ -1,0 +1,295 @@
+// Operator product y = (I - M N) x (Sec. 2, eq. discrete_form) by FFT.
+//
+// N = I + K with K three-level block Toeplitz (Sec. 2 after eq. sys_mat).
+// Each of the six unique generators is embedded in a circulant of period
+// (Px, Py, Pz) >= (2nx-1, 2ny-1, 2nz-1) (offset d placed at d, -d at P-d with
+// the block's parity, the rest zero) and transformed once at setup; the
+// product is then crop(IFFT(Khat . FFT(zero-pad(x)))) (Sec. 1: O(n log n)).
+//
+// Three passes per product, each a batch of LDS-resident transforms:
+//   1. forward x-FFT of every zero-padded x-line (coalesced line loads/stores),
+//   2. per x-frequency: 2-D (y,z) FFT of the three components, 3x3 multiply
+//      with the octant-stored, parity-signed Khat, inverse 2-D FFT, crop,
+//   3. inverse x-FFT of every line, crop, and y = x - M (x + K x).
+#include "fft_device.h"
+
+template <class R>
+__global__ void k_contrast(const c128 *chi, cpx<R> *M, long long N) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    c128 c = chi[i];
+    c128 m = cdiv(c, mk(1.0 + c.re, c.im));  // M = chi / (1 + chi)
+    M[i] = mk((R)m.re, (R)m.im);
+}
+
+vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s) {
+    long long N = op->N;
+    unsigned g = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_contrast<double>, dim3(g), dim3(256), 0, s, chi_dev, op->M64.as<c128>(), N);
+    hipLaunchKernelGGL(k_contrast<float>, dim3(g), dim3(256), 0, s, chi_dev, op->M32.as<c64>(), N);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
+__global__ void k_rhs(const c128 *e, c128 *b, const c128 *M, long long N, long long total) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    b[i] = M[i % N] * e[i];
+}
+
+vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s) {
+    long long total = 3LL * op->N * nrhs;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, e, b,
+                       op->M64.as<c128>(), op->N, total);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
+// ---------------------------------------------------------------- setup
+// Embedded periodic generator E[c][z][y][x] over (Pz, Py, Px).
+__global__ void k_embed(const c128 *gen, c128 *E, int nx, int ny, int nz, int Px, int Py, int Pz) {
+    long long P3 = (long long)Px * Py * Pz;
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= 6 * P3) return;
+    int c = (int)(i / P3);
+    long long r = i % P3;
+    int x = (int)(r % Px), y = (int)((r / Px) % Py), z = (int)(r / ((long long)Px * Py));
+    int ax = x < nx ? x : (Px - x < nx ? -(Px - x) : INT32_MAX);
+    int ay = y < ny ? y : (Py - y < ny ? -(Py - y) : INT32_MAX);
+    int az = z < nz ? z : (Pz - z < nz ? -(Pz - z) : INT32_MAX);
+    c128 v = czero<double>();
+    if (ax != INT32_MAX && ay != INT32_MAX && az != INT32_MAX) {
+        int d[3] = {ax, ay, az};
+        v = gen[(long long)c * nx * ny * nz + ((long long)abs(az) * ny + abs(ay)) * nx + abs(ax)];
+        // components (xx, yy, zz, xy, xz, yz): odd in the two axes of an off-diagonal block
+        const int oa[6] = {-1, -1, -1, 0, 0, 1}, ob[6] = {-1, -1, -1, 1, 2, 2};
+        if (c >= 3) {
+            double sg = 1.0;
+            if (d[oa[c]] < 0) sg = -sg;
+            if (d[ob[c]] < 0) sg = -sg;
+            if (d[oa[c]] == 0 || d[ob[c]] == 0) sg = 0.0;  // odd: zero at zero offset
+            v = mk(sg * v.re, sg * v.im);
+        }
+    }
+    E[i] = v;
+}
+
+// In-place FFT of lines in global memory: line l starts at (l % nl1)*s1 + (l / nl1)*s2,
+// element stride es.  One workgroup per line.
+template <class R>
+__global__ void k_fft_lines(cpx<R> *data, long long nl1, long long s1, long long s2, long long es,
+                            FftPlan plan, int inv) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    cpx<R> *b = a + plan.L;
+    long long l = blockIdx.x;
+    cpx<R> *base = data + (l % nl1) * s1 + (l / nl1) * s2;
+    for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = base[i * es];
+    __syncthreads();
+    LdsLines ln = {1, 0, 0, 1, 1};
+    cpx<R> *res = fft_lds<R>(a, b, ln, plan, inv != 0);
+    for (int i = threadIdx.x; i < plan.L; i += blockDim.x) base[i * es] = res[i];
+}
+
+// Octant extraction: khat[kx][kz][ky][c] = E[c][kz][ky][kx] / (Px Py Pz)
+__global__ void k_extract(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, int Pz, int Hx, int Hy,
+                          int Hz) {
+    long long total = (long long)Hx * Hy * Hz * 6;
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int c = (int)(i % 6);
+    long long r = i / 6;
+    int ky = (int)(r % Hy);
+    r /= Hy;
+    int kz = (int)(r % Hz);
+    int kx = (int)(r / Hz);
+    double sc = 1.0 / ((double)Px * Py * Pz);
+    c128 v = E[(long long)c * Px * Py * Pz + ((long long)kz * Py + ky) * Px + kx];
+    v = mk(v.re * sc, v.im * sc);
+    k64[i] = v;
+    if (k32) k32[i] = mk((float)v.re, (float)v.im);
+}
+
+static int block_for(int L) {
+    int t = 64;
+    while (t < 256 && t * 4 < L) t *= 2;
+    return t;
+}
+
+vie_status build_kernel_transform(vie_op op, hipStream_t s) {
+    const int Px = op->Px, Py = op->Py, Pz = op->Pz;
+    long long P3 = (long long)Px * Py * Pz;
+    DevBuf E;
+    VIE_CHECK(E.ensure(sizeof(c128) * 6 * P3));
+    long long tot = 6 * P3;
+    hipLaunchKernelGGL(k_embed, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, op->gen.as<c128>(),
+                       E.as<c128>(), op->nx, op->ny, op->nz, Px, Py, Pz);
+    VIE_HIP(hipGetLastError());
+    // x lines, y lines, z lines
+    struct {
+        const FftPlan *p;
+        long long nl1, s1, s2, es, nlines;
+    } passes[3] = {
+        {&op->px, 6LL * Py * Pz, Px, 0, 1, 6LL * Py * Pz},
+        {&op->py, Px, 1, (long long)Px * Py, Px, 6LL * Pz * Px},
+        {&op->pz, (long long)Px * Py, 1, P3, (long long)Px * Py, 6LL * Px * Py},
+    };
+    for (auto &ps : passes) {
+        if (ps.p->L == 1) continue;
+        size_t lds = 2 * sizeof(c128) * ps.p->L;
+        vie_lds_attr((const void *)k_fft_lines<double>, lds);
+        hipLaunchKernelGGL(k_fft_lines<double>, dim3((unsigned)ps.nlines), dim3(block_for(ps.p->L)), lds, s,
+                           E.as<c128>(), ps.nl1, ps.s1, ps.s2, ps.es, *ps.p, 0);
+        VIE_HIP(hipGetLastError());
+    }
+    long long H = (long long)op->Hx * op->Hy * op->Hz * 6;
+    VIE_CHECK(op->khat64.ensure(sizeof(c128) * H));
+    if (op->has_c64) VIE_CHECK(op->khat32.ensure(sizeof(c64) * H));
+    hipLaunchKernelGGL(k_extract, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
+                       op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
+                       op->Hx, op->Hy, op->Hz);
+    VIE_HIP(hipGetLastError());
+    VIE_HIP(hipStreamSynchronize(s));
+    E.release();
+    return VIE_OK;
+}
+
+// ---------------------------------------------------------------- product
+// pass 1: one workgroup per x-line (rhs, a, z, y): zero-pad to Px, forward FFT.
+template <class R>
+__global__ void k_xfwd(const cpx<R> *x, cpx<R> *work, int nx, FftPlan plan) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    cpx<R> *b = a + plan.L;
+    long long line = blockIdx.x;
+    const cpx<R> *src = x + line * nx;
+    for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = i < nx ? src[i] : czero<R>();
+    __syncthreads();
+    LdsLines ln = {1, 0, 0, 1, 1};
+    cpx<R> *res = fft_lds<R>(a, b, ln, plan, false);
+    cpx<R> *dst = work + line * plan.L;
+    for (int i = threadIdx.x; i < plan.L; i += blockDim.x) dst[i] = res[i];
+}
+
+// pass 2: one workgroup per (x-frequency, rhs).
+template <class R>
+__global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hx, int Hy, int Hz,
+                        FftPlan py, FftPlan pz) {
+    const int Py = py.L, Pz = pz.L;
+    const int plane = Py * Pz;
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    cpx<R> *b = a + 3 * plane;
+    const int kx = blockIdx.x;
+    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
+    for (int i = threadIdx.x; i < 6 * plane; i += blockDim.x) a[i] = czero<R>();
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * ny * nz; i += blockDim.x) {
+        int y = i % ny, z = (i / ny) % nz, c = i / (ny * nz);
+        a[c * plane + z * Py + y] = base[(long long)i * Px];
+    }
+    __syncthreads();
+    cpx<R> *buf = a, *oth = b;
+    // forward along y: rows z < nz of each component
+    if (Py > 1) {
+        LdsLines ly = {nz, Py, plane, 1, 3 * nz};
+        cpx<R> *r = fft_lds<R>(buf, oth, ly, py, false);
+        oth = (r == buf) ? oth : buf;
+        buf = r;
+    }
+    // forward along z: all Py columns
+    if (Pz > 1) {
+        LdsLines lz = {Py, 1, plane, Py, 3 * Py};
+        cpx<R> *r = fft_lds<R>(buf, oth, lz, pz, false);
+        oth = (r == buf) ? oth : buf;
+        buf = r;
+    }
+    // 3x3 multiply with the parity-signed octant transform
+    {
+        int kxo = kx <= Px - kx ? kx : Px - kx;
+        bool fx = kx > Px - kx;
+        const cpx<R> *kh = khat + (long long)kxo * Hz * Hy * 6;
+        for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+            int ky = i % Py, kz = i / Py;
+            int kyo = ky <= Py - ky ? ky : Py - ky;
+            int kzo = kz <= Pz - kz ? kz : Pz - kz;
+            bool fy = ky > Py - ky, fz = kz > Pz - kz;
+            const cpx<R> *k6 = kh + ((long long)kzo * Hy + kyo) * 6;
+            cpx<R> kxx = k6[0], kyy = k6[1], kzz = k6[2], kxy = k6[3], kxz = k6[4], kyz = k6[5];
+            if (fx != fy) kxy = mk(-kxy.re, -kxy.im);
+            if (fx != fz) kxz = mk(-kxz.re, -kxz.im);
+            if (fy != fz) kyz = mk(-kyz.re, -kyz.im);
+            cpx<R> u0 = buf[i], u1 = buf[plane + i], u2 = buf[2 * plane + i];
+            buf[i] = kxx * u0 + kxy * u1 + kxz * u2;
+            buf[plane + i] = kxy * u0 + kyy * u1 + kyz * u2;
+            buf[2 * plane + i] = kxz * u0 + kyz * u1 + kzz * u2;
+        }
+        __syncthreads();
+    }
+    if (Pz > 1) {
+        LdsLines lz = {Py, 1, plane, Py, 3 * Py};
+        cpx<R> *r = fft_lds<R>(buf, oth, lz, pz, true);
+        oth = (r == buf) ? oth : buf;
+        buf = r;
+    }
+    if (Py > 1) {
+        LdsLines ly = {nz, Py, plane, 1, 3 * nz};
+        cpx<R> *r = fft_lds<R>(buf, oth, ly, py, true);
+        oth = (r == buf) ? oth : buf;
+        buf = r;
+    }
+    for (int i = threadIdx.x; i < 3 * ny * nz; i += blockDim.x) {
+        int y = i % ny, z = (i / ny) % nz, c = i / (ny * nz);
+        base[(long long)i * Px] = buf[c * plane + z * Py + y];
+    }
+}
+
+// pass 3: one workgroup per x-line; inverse FFT, crop, y = x - M (x + K x).
+template <class R>
+__global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx<R> *y, int nx,
+                       long long lines_per_comp_rhs_N, int nyz, FftPlan plan) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    cpx<R> *b = a + plan.L;
+    long long line = blockIdx.x;
+    const cpx<R> *src = work + line * plan.L;
+    for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = src[i];
+    __syncthreads();
+    LdsLines ln = {1, 0, 0, 1, 1};
+    cpx<R> *res = fft_lds<R>(a, b, ln, plan, true);
+    long long yz = line % nyz;  // voxel row (z, y)
+    const cpx<R> *xl = x + line * nx;
+    const cpx<R> *ml = M + yz * nx;
+    cpx<R> *yl = y + line * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        cpx<R> xv = xl[i];
+        yl[i] = xv - ml[i] * (xv + res[i]);
+    }
+    (void)lines_per_comp_rhs_N;
+}
+
+template <class R>
+static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
+                           const cpx<R> *M, hipStream_t s) {
+    const int nx = op->nx, ny = op->ny, nz = op->nz, Px = op->Px;
+    long long lines = 3LL * ny * nz * nrhs;
+    VIE_CHECK(op->work.ensure(sizeof(cpx<R>) * lines * Px));
+    cpx<R> *work = op->work.as<cpx<R>>();
+    size_t ldsx = 2 * sizeof(cpx<R>) * Px;
+    vie_lds_attr((const void *)k_xfwd<R>, ldsx);
+    vie_lds_attr((const void *)k_xinv<R>, ldsx);
+    hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, x, work, nx, op->px);
+    VIE_HIP(hipGetLastError());
+    size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
+    vie_lds_attr((const void *)k_plane<R>, ldsp);
+    hipLaunchKernelGGL(k_plane<R>, dim3(Px, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
+                       op->Hz, op->py, op->pz);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, work, x, M, y, nx,
+                       0LL, ny * nz, op->px);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
+vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s) {
+    if (prec == VIE_C128)
+        return matvec_t<double>(op, (const c128 *)x, (c128 *)y, nrhs, op->khat64.as<c128>(),
+                                op->M64.as<c128>(), s);
+    return matvec_t<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(), s);
+}

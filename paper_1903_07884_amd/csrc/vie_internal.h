@@ -1,0 +1,169 @@
+// Internal declarations shared by the HIP translation units of libvie.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vie.h"
+
+// ---------------------------------------------------------------- complex
+template <class R>
+struct alignas(2 * sizeof(R)) cpx {
+    R re, im;
+};
+typedef cpx<double> c128;
+typedef cpx<float> c64;
+
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> mk(R a, R b) {
+    cpx<R> z;
+    z.re = a;
+    z.im = b;
+    return z;
+}
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return mk(s * a.re, s * a.im); }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> conjg(cpx<R> a) { return mk(a.re, -a.im); }
+// conj(a) * b
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+    return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class R>
+__host__ __device__ __forceinline__ R abs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+// a - b*c
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cfms(cpx<R> a, cpx<R> b, cpx<R> c) {
+    return mk(a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re);
+}
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cdiv(cpx<R> a, cpx<R> b) {
+    R d = b.re * b.re + b.im * b.im;
+    return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> czero() { return mk<R>(R(0), R(0)); }
+
+// ---------------------------------------------------------------- errors
+void vie_set_error(const std::string &msg);
+
+#define VIE_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            vie_set_error(std::string(#call) + ": " + hipGetErrorString(e_));           \
+            return (e_ == hipErrorOutOfMemory) ? VIE_EOOM : VIE_EDEVICE;               \
+        }                                                                               \
+    } while (0)
+
+#define VIE_CHECK(st)                      \
+    do {                                   \
+        vie_status s_ = (st);              \
+        if (s_ < 0) return s_;             \
+    } while (0)
+
+// device buffer owned by a handle
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    vie_status ensure(size_t nbytes);  // grow (contents not preserved)
+    void release();
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// Allow a kernel to request more than the default dynamic LDS.
+inline void vie_lds_attr(const void *kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ---------------------------------------------------------------- FFT plans
+// A length-L transform factored into radices (applied first to last).
+// Twiddles: table of W_L^q = exp(-2 pi i q / L), q in [0, L), complex double
+// (a complex float copy for single precision).
+#define VIE_MAX_RADICES 24
+struct FftPlan {
+    int L = 0;
+    int nrad = 0;
+    int rad[VIE_MAX_RADICES];
+    const c128 *tw64 = nullptr;  // device
+    const c64 *tw32 = nullptr;   // device
+};
+
+// Owns device twiddle tables, keyed by length.
+struct FftCache {
+    struct Entry {
+        int L;
+        DevBuf t64, t32;
+    };
+    std::vector<Entry *> entries;
+    vie_status get(int L, FftPlan *plan);
+    ~FftCache();
+};
+
+bool fft_supported_length(int L);  // every prime factor <= VIE_FFT_MAX_PRIME
+#define VIE_FFT_MAX_PRIME 61
+int fft_good_length(int minL);     // smallest 2^a 3^b 5^c >= minL
+
+// ---------------------------------------------------------------- handles
+struct vie_op_s {
+    int nx, ny, nz;
+    long long N;             // nx*ny*nz
+    double delta, kb, kappa;
+    int Px, Py, Pz;          // circulant embedding periods (>= 2n - 1, 2-3-5 smooth)
+    int Hx, Hy, Hz;          // octant extents Px/2+1 ...
+    DevBuf M64, M32;         // contrast per voxel (c128 / c64)
+    DevBuf gen;              // FP64 octant generator [6][nz][ny][nx]
+    DevBuf khat64, khat32;   // octant kernel transform [Hx][Hz][Hy][6], scaled by 1/(Px Py Pz)
+    bool has_c64 = false;
+    DevBuf work;             // matvec intermediate, nrhs*3*ny*nz*Px complex
+    FftCache fft;
+    FftPlan px, py, pz;      // plans for the three periods
+};
+
+struct vie_pc_s {
+    vie_op op;
+    int nboxes, bx, by, bz, m;
+    std::vector<int> boxes;  // nboxes*6
+    bool covers_all;
+    int prec;                // factor precision
+    int nstored;
+    std::vector<int> block_of_mode_host;  // [nboxes*bx]
+    DevBuf block_of_mode;    // int32 [nboxes*bx] -> stored block index
+    DevBuf factors;          // [nstored][m][m] column-major LU (complex, factor precision)
+    DevBuf perm;             // int32 [nstored][m] row permutation: (P r)[i] = r[perm[i]]
+    DevBuf info;             // int32 [nstored] 0 or first zero-pivot column + 1
+    DevBuf work;             // apply scratch: nrhs * nboxes * 3*by*bz * bx complex (factor prec)
+    FftPlan pxb;             // length bx
+};
+
+// ---------------------------------------------------------------- launchers
+// generator.hip
+vie_status launch_generator(vie_op op, hipStream_t s);
+// matvec.hip
+vie_status build_kernel_transform(vie_op op, hipStream_t s);
+vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s);
+vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s);
+vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
+// precond.hip
+vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
+vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s);
+// krylov.hip
+vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int nrhs,
+                       const vie_solve_opts *o, vie_solve_stats *stats, hipStream_t s);

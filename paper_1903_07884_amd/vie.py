@@ -1,0 +1,212 @@
+"""Thin ctypes binding of libvie.so (the C ABI declared in include/vie.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device vectors are torch tensors (complex128 or complex64, contiguous, on the
+GPU); the current torch stream is passed as the HIP stream.  Host inputs
+(contrast, generator, boxes) are numpy arrays.  If the library is missing,
+``load`` raises: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libvie.so')
+
+VIE_C128, VIE_C64 = 0, 1
+VIE_OK, VIE_NOT_CONVERGED = 0, 1
+STATUS = {0: 'VIE_OK', 1: 'VIE_NOT_CONVERGED', -1: 'VIE_EARG', -2: 'VIE_EOOM', -3: 'VIE_EDEVICE',
+          -4: 'VIE_ESINGULAR', -5: 'VIE_ENONFINITE'}
+HOMOG = {'none': 0, 'mode': 1, 'mean': 2, 'realmean': 3}
+MODE = {'fp64': 0, 'mixed': 1}
+
+EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
+           'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_last_error')
+
+
+class VieError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__('%s: %s' % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class CreateOpts(ctypes.Structure):
+    _fields_ = [('build_c64', ctypes.c_int32), ('generator', ctypes.c_void_p)]
+
+
+class PcOpts(ctypes.Structure):
+    _fields_ = [('homog', ctypes.c_int32), ('nboxes', ctypes.c_int32), ('boxes', ctypes.c_void_p),
+                ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32)]
+
+
+class PcInfo(ctypes.Structure):
+    _fields_ = [('nboxes', ctypes.c_int32), ('box_nx', ctypes.c_int32), ('block_m', ctypes.c_int32),
+                ('modes', ctypes.c_int32), ('stored_blocks', ctypes.c_int32), ('factor_bytes', ctypes.c_int64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [('tol', ctypes.c_double), ('restart', ctypes.c_int32), ('maxit', ctypes.c_int32),
+                ('mode', ctypes.c_int32), ('x0_given', ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [('iters', ctypes.c_int32), ('restarts', ctypes.c_int32), ('relres', ctypes.c_double),
+                ('status', ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load libvie.so (raises if it is missing or lacks a declared symbol)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError('libvie.so not built (%s); run paper_1903_07884_amd.build' % path)
+    lib = ctypes.CDLL(path)
+    for name in EXPORTS:
+        getattr(lib, name)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.vie_create.argtypes = [ctypes.POINTER(i32), dbl, dbl, vp, ctypes.POINTER(CreateOpts), vp,
+                               ctypes.POINTER(vp)]
+    lib.vie_destroy.argtypes = [vp]
+    lib.vie_generator.argtypes = [vp, vp]
+    lib.vie_rhs.argtypes = [vp, vp, vp, i32, vp]
+    lib.vie_matvec.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.precond_setup.argtypes = [vp, ctypes.POINTER(PcOpts), vp, ctypes.POINTER(vp)]
+    lib.precond_info.argtypes = [vp, ctypes.POINTER(PcInfo)]
+    lib.precond_destroy.argtypes = [vp]
+    lib.precond_apply.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.vie_solve.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+    lib.vie_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=(VIE_OK,)):
+    if status not in allow:
+        raise VieError(status, _lib.vie_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError('expected a contiguous CUDA tensor of %s' % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(t):
+    import torch
+    return VIE_C128 if t.dtype == torch.complex128 else VIE_C64
+
+
+class Operator:
+    """vie_op: I - M N on a voxel grid (see include/vie.h)."""
+
+    def __init__(self, grid, voxel_size, k_background, chi, build_c64=False, generator=None, stream=None):
+        lib = load()
+        nx, ny, nz = (int(v) for v in grid)
+        self.grid = (nx, ny, nz)
+        chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
+        g3 = (ctypes.c_int32 * 3)(nx, ny, nz)
+        opts = CreateOpts(1 if build_c64 else 0, None)
+        if generator is not None:
+            gen = np.ascontiguousarray(np.asarray(generator, dtype=np.complex128).reshape(6, nz, ny, nx))
+            opts.generator = gen.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib.vie_create(g3, float(voxel_size), float(k_background), chi.ctypes.data, ctypes.byref(opts),
+                              _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def n(self):
+        nx, ny, nz = self.grid
+        return 3 * nx * ny * nz
+
+    def generator(self):
+        nx, ny, nz = self.grid
+        out = np.empty((6, nz, ny, nx), dtype=np.complex128)
+        _check(_lib.vie_generator(self.h, out.ctypes.data))
+        return out
+
+    def rhs(self, e_inc, b, nrhs=1, stream=None):
+        import torch
+        _check(_lib.vie_rhs(self.h, _dev(e_inc, torch.complex128), _dev(b, torch.complex128), nrhs,
+                            _stream(stream)))
+
+    def matvec(self, x, y, nrhs=1, stream=None):
+        _check(_lib.vie_matvec(self.h, _dev(x, x.dtype), _dev(y, x.dtype), nrhs, _prec(x), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _lib.vie_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Preconditioner:
+    """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
+
+    def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, stream=None):
+        lib = load()
+        self.op = op
+        bx = None
+        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec)
+        if boxes is not None:
+            bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
+            o.nboxes = bx.shape[0]
+            o.boxes = bx.ctypes.data
+        if reduce_tol is not None:
+            o.reduce = 1
+            o.reduce_tol = float(reduce_tol)
+        h = ctypes.c_void_p()
+        _check(lib.precond_setup(op.h, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def info(self):
+        i = PcInfo()
+        _check(_lib.precond_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PcInfo._fields_}
+
+    def apply(self, r, z, nrhs=1, stream=None):
+        _check(_lib.precond_apply(self.h, _dev(r, r.dtype), _dev(z, r.dtype), nrhs, _prec(r), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _lib.precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(op, pc, b, x, nrhs=1, tol=1e-6, restart=50, maxit=5000, mode='fp64', x0_given=False, stream=None):
+    """vie_solve; returns a list of per-RHS stats dicts (status VIE_NOT_CONVERGED does not raise)."""
+    import torch
+    lib = load()
+    o = SolveOpts(float(tol), int(restart), int(maxit), MODE[mode], 1 if x0_given else 0)
+    st = (SolveStats * nrhs)()
+    _check(lib.vie_solve(op.h, pc.h if pc is not None else None, _dev(b, torch.complex128),
+                         _dev(x, torch.complex128), nrhs, ctypes.byref(o), st, _stream(stream)),
+           allow=(VIE_OK, VIE_NOT_CONVERGED))
+    return [{f: getattr(s, f) for f, _ in SolveStats._fields_} for s in st]
