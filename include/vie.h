@@ -75,8 +75,9 @@ typedef struct {
  *   grid[3]       = {nx, ny, nz}, each >= 1 (x is the long, Toeplitz-innermost axis)
  *   voxel_size    = Delta in metres (> 0)
  *   k_background  = background wavenumber k_b = 2 pi sqrt(eps_b)/lambda0 in 1/m (>= 0)
- *   chi           = HOST array of 2*nx*ny*nz doubles, interleaved complex relative
- *                   contrast chi = eps/eps_b - 1 per voxel, [nz][ny][nx]; 1 + chi != 0
+ *   chi           = host OR device array of 2*nx*ny*nz doubles, interleaved complex
+ *                   relative contrast chi = eps/eps_b - 1 per voxel, [nz][ny][nx];
+ *                   every entry finite with 1 + chi != 0 (checked; VIE_EARG otherwise)
  *   opts          = nullable
  * The generator is computed in FP64 (Sec. 2, eq. op_N; six unique blocks, each
  * defined by one octant through its per-axis parity), embedded in a circulant
@@ -172,6 +173,20 @@ typedef struct {
  * stats: HOST array of nrhs entries.  Synchronises `stream`. */
 vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
                      const vie_solve_opts *opts, vie_solve_stats *stats, void *stream);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Kernel timing with HIP events recorded on the stream each kernel is launched
+ * on.  vie_profile_begin() clears the record and starts recording;
+ * vie_profile_kernel() synchronises the recorded events and returns, for one
+ * kernel name, the summed duration in milliseconds and the number of
+ * launches; vie_profile_end() stops recording.  Names: "generator",
+ * "matvec_xfwd", "matvec_plane", "matvec_xinv", "precond_xfft", "block_solve",
+ * "precond_ixfft", "lu_panel", "lu_swap_trsm", "lu_update", "arnoldi_dots",
+ * "arnoldi_update".  Recording adds two event records per launch. */
+vie_status vie_profile_begin(void);
+vie_status vie_profile_kernel(const char *name, double *total_ms, int64_t *launches);
+vie_status vie_profile_end(void);
 
 /* Thread-local description of the last failure ("" if none). */
 const char *vie_last_error(void);

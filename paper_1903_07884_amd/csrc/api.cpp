@@ -40,11 +40,19 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
         return arg_error("vie_create: k_background must be finite and >= 0");
     long long N = (long long)grid[0] * grid[1] * grid[2];
     if (N > (1LL << 31)) return arg_error("vie_create: grid too large");
-    for (long long i = 0; i < N; ++i) {
-        double re = chi[2 * i], im = chi[2 * i + 1];
-        if (!std::isfinite(re) || !std::isfinite(im)) return arg_error("vie_create: non-finite contrast");
-        if (re == -1.0 && im == 0.0) return arg_error("vie_create: 1 + chi must be non-zero");
+    bool chi_on_device = false;
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, chi) == hipSuccess && attr.type == hipMemoryTypeDevice)
+            chi_on_device = true;
+        (void)hipGetLastError();
     }
+    if (!chi_on_device)
+        for (long long i = 0; i < N; ++i) {
+            double re = chi[2 * i], im = chi[2 * i + 1];
+            if (!std::isfinite(re) || !std::isfinite(im)) return arg_error("vie_create: non-finite contrast");
+            if (re == -1.0 && im == 0.0) return arg_error("vie_create: 1 + chi must be non-zero");
+        }
     vie_create_opts o{};
     if (opts) o = *opts;
     vie_op op = new (std::nothrow) vie_op_s();
@@ -83,8 +91,20 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
     {
         DevBuf chid;
         if ((st = chid.ensure(sizeof(c128) * N)) < 0) return fail(st);
-        if (hipMemcpyAsync(chid.p, chi, sizeof(c128) * N, hipMemcpyHostToDevice, s) != hipSuccess)
+        if (hipMemcpyAsync(chid.p, chi, sizeof(c128) * N,
+                           chi_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(VIE_EDEVICE);
+        if (chi_on_device) {
+            DevBuf bad;
+            int hbad = 0;
+            if ((st = bad.ensure(sizeof(int))) < 0) return fail(st);
+            if (hipMemsetAsync(bad.p, 0, sizeof(int), s) != hipSuccess) return fail(VIE_EDEVICE);
+            if ((st = launch_check_chi(chid.as<c128>(), N, bad.as<int>(), s)) < 0) return fail(st);
+            if (hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(VIE_EDEVICE);
+            if (hbad) return fail(arg_error("vie_create: non-finite contrast or 1 + chi == 0"));
+        }
         if ((st = launch_contrast(op, chid.as<c128>(), s)) < 0) return fail(st);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(VIE_EDEVICE);
     }

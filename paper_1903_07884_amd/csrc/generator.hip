@@ -312,6 +312,7 @@ vie_status launch_generator(vie_op op, hipStream_t s) {
         vie_set_error("grid too large for the generator launch");
         return VIE_EARG;
     }
+    ProfScope ps("generator", s);
     hipLaunchKernelGGL(k_generator, dim3((unsigned)N), dim3(GEN_THREADS), 0, s, op->gen.as<c128>(),
                        op->nx, op->ny, op->nz, op->kappa);
     VIE_HIP(hipGetLastError());

@@ -198,6 +198,7 @@ struct Ctx {
 };
 
 vie_status dots(Ctx &C, const c128 *V, long long ldv, int nv, const c128 *w, int self, c128 *out) {
+    ProfScope ps("arnoldi_dots", C.s);
     hipLaunchKernelGGL(k_dots, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, C.s, V, ldv, nv, w, C.n, self, C.partial);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(nv + self), dim3(KR_THREADS), 0, C.s, C.partial, KR_BLOCKS, nv + self, out);
@@ -316,12 +317,18 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b_all, c128 *x_all, int
                 VIE_CHECK(apply_P(C, vj, zj));
                 VIE_CHECK(apply_A(C, zj, w));
                 VIE_CHECK(dots(C, V, n, j + 1, w, 1, S.h1));
-                hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h1, w, n,
-                                   (c128 *)nullptr);
+                {
+                    ProfScope ps("arnoldi_update", s);
+                    hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h1, w, n,
+                                       (c128 *)nullptr);
+                }
                 VIE_HIP(hipGetLastError());
                 VIE_CHECK(dots(C, V, n, j + 1, w, 0, S.h2));
-                hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h2, w, n,
-                                   C.partial);
+                {
+                    ProfScope ps("arnoldi_update", s);
+                    hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h2, w, n,
+                                       C.partial);
+                }
                 VIE_HIP(hipGetLastError());
                 hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, C.partial, KR_BLOCKS, 1, S.nrm2);
                 VIE_HIP(hipGetLastError());

@@ -22,6 +22,19 @@ __global__ void k_contrast(const c128 *chi, cpx<R> *M, long long N) {
     M[i] = mk((R)m.re, (R)m.im);
 }
 
+__global__ void k_check_chi(const c128 *chi, long long N, int *bad) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    c128 c = chi[i];
+    if (!isfinite(c.re) || !isfinite(c.im) || (c.re == -1.0 && c.im == 0.0)) atomicOr(bad, 1);
+}
+
+vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_chi, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, chi, N, bad);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
 vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s) {
     long long N = op->N;
     unsigned g = (unsigned)((N + 255) / 256);
@@ -274,15 +287,24 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     size_t ldsx = 2 * sizeof(cpx<R>) * Px;
     vie_lds_attr((const void *)k_xfwd<R>, ldsx);
     vie_lds_attr((const void *)k_xinv<R>, ldsx);
-    hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, x, work, nx, op->px);
+    {
+        ProfScope ps("matvec_xfwd", s);
+        hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, x, work, nx, op->px);
+    }
     VIE_HIP(hipGetLastError());
     size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
     vie_lds_attr((const void *)k_plane<R>, ldsp);
-    hipLaunchKernelGGL(k_plane<R>, dim3(Px, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
-                       op->Hz, op->py, op->pz);
+    {
+        ProfScope ps("matvec_plane", s);
+        hipLaunchKernelGGL(k_plane<R>, dim3(Px, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
+                           op->Hz, op->py, op->pz);
+    }
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, work, x, M, y, nx,
-                       0LL, ny * nz, op->px);
+    {
+        ProfScope ps("matvec_xinv", s);
+        hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, work, x, M, y, nx,
+                           0LL, ny * nz, op->px);
+    }
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }

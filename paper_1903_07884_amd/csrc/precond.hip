@@ -293,15 +293,22 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
     for (int j0 = 0; j0 < m; j0 += LU_NB) {
         int w = std::min(LU_NB, m - j0);
-        hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(), m,
-                           j0, w);
+        {
+            ProfScope ps("lu_panel", s);
+            hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(), m,
+                               j0, w);
+        }
         VIE_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + 63) / 64, nb), dim3(64), 0, s, A, ipiv.as<int>(), m,
-                           j0, w);
+        {
+            ProfScope ps("lu_swap_trsm", s);
+            hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + 63) / 64, nb), dim3(64), 0, s, A, ipiv.as<int>(), m,
+                               j0, w);
+        }
         VIE_HIP(hipGetLastError());
         int rest = m - j0 - w;
         if (rest > 0) {
             int nt = (rest + LU_TILE - 1) / LU_TILE;
+            ProfScope ps("lu_update", s);
             hipLaunchKernelGGL(k_lu_update<R>, dim3(nt * nt, nb), dim3(256), 0, s, A, m, j0, w);
             VIE_HIP(hipGetLastError());
         }
@@ -456,17 +463,26 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     cpx<R> *work = pc->work.as<cpx<R>>();
     vie_lds_attr((const void *)k_box_fft<R>, lds);
     vie_lds_attr((const void *)k_box_ifft<R>, lds);
-    hipLaunchKernelGGL(k_box_fft<R>, dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, op->nx, op->ny,
-                       op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+    {
+        ProfScope ps("precond_xfft", s);
+        hipLaunchKernelGGL(k_box_fft<R>, dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, op->nx, op->ny,
+                           op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+    }
     VIE_HIP(hipGetLastError());
     size_t lds2 = (2 * (size_t)m + TS_B * TS_B) * sizeof(cpx<R>);
     vie_lds_attr((const void *)k_block_solve<R>, lds2);
-    hipLaunchKernelGGL(k_block_solve<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * n)), dim3(256), lds2, s,
-                       work, pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(), pc->block_of_mode.as<const int>(), m,
-                       n, pc->nboxes);
+    {
+        ProfScope ps("block_solve", s);
+        hipLaunchKernelGGL(k_block_solve<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * n)), dim3(256), lds2, s,
+                           work, pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(),
+                           pc->block_of_mode.as<const int>(), m, n, pc->nboxes);
+    }
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_box_ifft<R>, dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, op->ny,
-                       op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+    {
+        ProfScope ps("precond_ixfft", s);
+        hipLaunchKernelGGL(k_box_ifft<R>, dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, op->ny,
+                           op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+    }
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }

@@ -153,6 +153,15 @@ struct vie_pc_s {
     FftPlan pxb;             // length bx
 };
 
+// ---------------------------------------------------------------- profiling
+// Records a pair of HIP events around a launch on `s` while profiling is on.
+struct ProfScope {
+    int slot = -1;
+    hipStream_t s;
+    ProfScope(const char *name, hipStream_t stream);
+    ~ProfScope();
+};
+
 // ---------------------------------------------------------------- launchers
 // generator.hip
 vie_status launch_generator(vie_op op, hipStream_t s);
@@ -161,6 +170,7 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s);
 vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s);
 vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s);
 vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
+vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s);
 // precond.hip
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
 vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s);

@@ -22,7 +22,8 @@ HOMOG = {'none': 0, 'mode': 1, 'mean': 2, 'realmean': 3}
 MODE = {'fp64': 0, 'mixed': 1}
 
 EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
-           'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_last_error')
+           'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
+           'vie_profile_kernel', 'vie_profile_end', 'vie_last_error')
 
 
 class VieError(RuntimeError):
@@ -81,6 +82,9 @@ def load(path=None):
     lib.precond_destroy.argtypes = [vp]
     lib.precond_apply.argtypes = [vp, vp, vp, i32, i32, vp]
     lib.vie_solve.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+    lib.vie_profile_begin.argtypes = []
+    lib.vie_profile_kernel.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    lib.vie_profile_end.argtypes = []
     lib.vie_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = ctypes.c_int
@@ -116,17 +120,25 @@ class Operator:
     """vie_op: I - M N on a voxel grid (see include/vie.h)."""
 
     def __init__(self, grid, voxel_size, k_background, chi, build_c64=False, generator=None, stream=None):
+        """``chi``: numpy array (host) or contiguous complex128 CUDA tensor (device), [nz, ny, nx]."""
         lib = load()
         nx, ny, nz = (int(v) for v in grid)
         self.grid = (nx, ny, nz)
-        chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
+        if hasattr(chi, 'is_cuda') and chi.is_cuda:
+            import torch
+            if chi.numel() != nx * ny * nz:
+                raise ValueError('chi has the wrong size')
+            chi_ptr = _dev(chi, torch.complex128)
+        else:
+            chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
+            chi_ptr = chi.ctypes.data
         g3 = (ctypes.c_int32 * 3)(nx, ny, nz)
         opts = CreateOpts(1 if build_c64 else 0, None)
         if generator is not None:
             gen = np.ascontiguousarray(np.asarray(generator, dtype=np.complex128).reshape(6, nz, ny, nx))
             opts.generator = gen.ctypes.data
         h = ctypes.c_void_p()
-        _check(lib.vie_create(g3, float(voxel_size), float(k_background), chi.ctypes.data, ctypes.byref(opts),
+        _check(lib.vie_create(g3, float(voxel_size), float(k_background), chi_ptr, ctypes.byref(opts),
                               _stream(stream), ctypes.byref(h)))
         self.h = h
 
@@ -210,3 +222,19 @@ def solve(op, pc, b, x, nrhs=1, tol=1e-6, restart=50, maxit=5000, mode='fp64', x
                          _dev(x, torch.complex128), nrhs, ctypes.byref(o), st, _stream(stream)),
            allow=(VIE_OK, VIE_NOT_CONVERGED))
     return [{f: getattr(s, f) for f, _ in SolveStats._fields_} for s in st]
+
+
+def profile_begin():
+    _check(load().vie_profile_begin())
+
+
+def profile_kernel(name):
+    """(total_ms, launches) recorded for one kernel since profile_begin()."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().vie_profile_kernel(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def profile_end():
+    _check(load().vie_profile_end())
