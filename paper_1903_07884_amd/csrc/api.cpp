@@ -194,7 +194,7 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
         return arg_error("precond_setup: box length " + std::to_string(bx) + " has a prime factor above " +
                          std::to_string(VIE_FFT_MAX_PRIME));
     if (2 * sizeof(c128) * bx > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
-    if ((2 * (size_t)m + 32 * 32) * esz > max_lds())
+    if (((size_t)m + 4 * 64) * esz > max_lds())
         return arg_error("precond_setup: cross-section block too large for the block solve");
     vie_pc pc = new (std::nothrow) vie_pc_s();
     if (!pc) return VIE_EOOM;
@@ -250,7 +250,7 @@ extern "C" vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, in
     if (!(o.tol > 0) || !std::isfinite(o.tol)) return arg_error("vie_solve: tol must be > 0");
     if (o.restart < 1 || o.restart > 200) return arg_error("vie_solve: restart must be in [1, 200]");
     if (o.maxit < 1) return arg_error("vie_solve: maxit must be >= 1");
-    if (o.mode != VIE_MODE_FP64) return arg_error("vie_solve: only VIE_MODE_FP64 is available in this build");
+    if (o.mode != VIE_MODE_FP64 && o.mode != VIE_MODE_MIXED) return arg_error("vie_solve: unknown mode");
     hipStream_t s = (hipStream_t)stream;
     vie_status st = solve_gmres(op, pc, (const c128 *)b, (c128 *)x, nrhs, &o, stats, s);
     hipError_t e = hipStreamSynchronize(s);

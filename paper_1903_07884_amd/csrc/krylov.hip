@@ -1,20 +1,28 @@
-// Restarted right-preconditioned (flexible) GMRES on the device (Sec. 1: the
-// discrete JVIE is solved by GMRES; restart, side and orthogonalisation are
-// this library's choices).
+// Restarted right-preconditioned flexible GMRES on the device, batched over right-hand
+// sides in lockstep (Sec. 1: the discrete JVIE is solved by GMRES; restart, side and
+// orthogonalisation are this library's choices).
 //
-// Per Arnoldi step j: z_j = P^{-1} v_j (kept, so x += Z y at the end of a
-// cycle), w = A z_j, classical Gram-Schmidt applied twice with wavefront
-// reductions (two-stage: per-workgroup partials, then one reduction kernel),
-// a single-lane kernel applies the previous complex Givens rotations to the
-// new Hessenberg column, forms the next rotation and updates the residual
-// estimate |g_{j+1}|, which is the only value read back by the host each step.
-// Each cycle ends with the FP64 true residual r = b - A x.
+// Per Arnoldi step j, for every right-hand side r of the batch at once:
+//   z_j = P^{-1} v_j (kept, so x += Z y at the end of a cycle: flexible GMRES),
+//   w = A z_j (one batched operator product),
+//   classical Gram-Schmidt applied twice with wavefront reductions (per-workgroup
+//   partials, then one reduction kernel), FP64 throughout,
+//   a single-lane kernel per right-hand side applies the previous complex Givens rotations
+//   to the new Hessenberg column, forms the next rotation and updates |g_{j+1}|;
+//   these estimates (one per right-hand side) are the only values read back per step.
+// Each cycle ends with x += Z y and the FP64 true residual r = b - A x.
+//
+// FP64 mode: v, z, products and factors complex128.  Mixed mode: v_j is rounded to
+// complex64 for the preconditioner (complex64 factors) and the complex64 operator
+// product, whose result is widened back for the FP64 Arnoldi step; Z is kept in
+// complex64; the true residual of every cycle uses the complex128 product, so the
+// outer loop is an FP64 iterative refinement around the FP32 inner solve.
 #include <cmath>
 
 #include "vie_internal.h"
 
 #define KR_THREADS 256
-#define KR_BLOCKS 512
+#define KR_BLOCKS 256
 
 __device__ __forceinline__ c128 wave_sum(c128 v) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -36,332 +44,465 @@ __device__ __forceinline__ c128 block_sum_kr(c128 v, c128 *sh) {
     return r;  // valid in thread 0
 }
 
-// partial[blk * (nv + self) + i] = sum_e conj(V_i[e]) w[e]; with `self` an extra |w|^2 entry.
-__global__ void __launch_bounds__(KR_THREADS) k_dots(const c128 *V, long long ldv, int nv, const c128 *w, long long n,
+// Batched vectors: vector j of right-hand side r at base + j * ldj + r * n.
+// partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e]; `self` adds |w|^2.
+__global__ void __launch_bounds__(KR_THREADS) k_dots(const c128 *V, long long ldj, int nv, const c128 *w, long long n,
                                                      int self, c128 *partial) {
     __shared__ c128 sh[KR_THREADS / 64];
+    const int r = blockIdx.y;
+    const c128 *wr = w + r * n;
     long long chunk = (n + gridDim.x - 1) / gridDim.x;
     long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     int stride = nv + self;
+    c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
     for (int i = 0; i < nv; ++i) {
-        const c128 *v = V + i * ldv;
+        const c128 *v = V + i * ldj + r * n;
         c128 acc = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc = acc + cmulc(v[e], w[e]);
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc = acc + cmulc(v[e], wr[e]);
         c128 s = block_sum_kr(acc, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x * stride + i] = s;
+        if (threadIdx.x == 0) out[i] = s;
     }
     if (self) {
         c128 acc = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc.re += abs2(w[e]);
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc.re += abs2(wr[e]);
         c128 s = block_sum_kr(acc, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x * stride + nv] = s;
+        if (threadIdx.x == 0) out[nv] = s;
     }
 }
 
-// out[i] = sum_b partial[b * stride + i], i < cnt.  One workgroup per i.
-__global__ void __launch_bounds__(KR_THREADS) k_reduce(const c128 *partial, int nb, int stride, c128 *out) {
+// out[r * ostride + i] = sum_b partial[(r * nb + b) * stride + i]; grid (count, R)
+__global__ void __launch_bounds__(KR_THREADS) k_reduce(const c128 *partial, int nb, int stride, c128 *out,
+                                                       int ostride) {
     __shared__ c128 sh[KR_THREADS / 64];
-    int i = blockIdx.x;
+    int i = blockIdx.x, r = blockIdx.y;
     c128 acc = czero<double>();
-    for (int b = threadIdx.x; b < nb; b += KR_THREADS) acc = acc + partial[b * stride + i];
+    for (int b = threadIdx.x; b < nb; b += KR_THREADS) acc = acc + partial[((long long)r * nb + b) * stride + i];
     c128 s = block_sum_kr(acc, sh);
-    if (threadIdx.x == 0) out[i] = s;
+    if (threadIdx.x == 0) out[(long long)r * ostride + i] = s;
 }
 
-// w -= sum_i V_i h[i]; optional partial |w|^2 into partial[blk] (norm != 0).
-__global__ void __launch_bounds__(KR_THREADS) k_update(const c128 *V, long long ldv, int nv, const c128 *h, c128 *w,
-                                                       long long n, c128 *partial) {
+// w_r -= sum_i V_i,r h_r[i]; optional partial |w_r|^2 into partial[r * gridDim.x + blk].
+__global__ void __launch_bounds__(KR_THREADS) k_update(const c128 *V, long long ldj, int nv, const c128 *h, int hstride,
+                                                       c128 *w, long long n, c128 *partial) {
     __shared__ c128 hs[256];
     __shared__ c128 sh[KR_THREADS / 64];
-    for (int i = threadIdx.x; i < nv; i += KR_THREADS) hs[i] = h[i];
+    const int r = blockIdx.y;
+    for (int i = threadIdx.x; i < nv; i += KR_THREADS) hs[i] = h[(long long)r * hstride + i];
     __syncthreads();
+    c128 *wr = w + r * n;
     long long chunk = (n + gridDim.x - 1) / gridDim.x;
     long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     c128 nrm = czero<double>();
     for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
-        c128 acc = w[e];
-        for (int i = 0; i < nv; ++i) acc = cfms(acc, V[i * ldv + e], hs[i]);
-        w[e] = acc;
+        c128 acc = wr[e];
+        for (int i = 0; i < nv; ++i) acc = cfms(acc, V[i * ldj + r * n + e], hs[i]);
+        wr[e] = acc;
         nrm.re += abs2(acc);
     }
     if (partial) {
         c128 s = block_sum_kr(nrm, sh);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = s;
     }
 }
 
-// out = sum_i V_i y[i]  (x update direction)
-__global__ void __launch_bounds__(KR_THREADS) k_combine(const c128 *V, long long ldv, int nv, const c128 *y, c128 *out,
-                                                        long long n, int accumulate) {
+// x_r += sum_{i < jr[r]} Z_i,r y_r[i]   (Z in complex128 or complex64)
+template <class R>
+__global__ void __launch_bounds__(KR_THREADS) k_combine(const cpx<R> *Z, long long ldj, const int *jr, const c128 *y,
+                                                        int ystride, c128 *x, long long n) {
     __shared__ c128 ys[256];
-    for (int i = threadIdx.x; i < nv; i += KR_THREADS) ys[i] = y[i];
+    const int r = blockIdx.y;
+    const int nv = jr[r];
+    for (int i = threadIdx.x; i < nv; i += KR_THREADS) ys[i] = y[(long long)r * ystride + i];
     __syncthreads();
+    if (nv == 0) return;
     for (long long e = blockIdx.x * (long long)KR_THREADS + threadIdx.x; e < n; e += (long long)gridDim.x * KR_THREADS) {
-        c128 acc = accumulate ? out[e] : czero<double>();
-        for (int i = 0; i < nv; ++i) acc = acc + V[i * ldv + e] * ys[i];
-        out[e] = acc;
+        c128 acc = x[r * n + e];
+        for (int i = 0; i < nv; ++i) {
+            cpx<R> z = Z[i * ldj + r * n + e];
+            acc = acc + mk((double)z.re, (double)z.im) * ys[i];
+        }
+        x[r * n + e] = acc;
     }
 }
 
-// v = w * (1/s), s = scal[0].re
-__global__ void k_scale(const c128 *w, c128 *v, long long n, const double *scal) {
-    double f = 1.0 / scal[0];
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-        v[e] = mk(w[e].re * f, w[e].im * f);
+// v_r = w_r / scal[r * sstride]  (zero for an inactive right-hand side or a zero scale)
+__global__ void k_scale(const c128 *w, c128 *v, long long n, const double *scal, int sstride, const int *active) {
+    const int r = blockIdx.y;
+    double s = scal[(long long)r * sstride];
+    double f = (active[r] && s != 0.0) ? 1.0 / s : 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        c128 a = w[r * n + e];
+        v[r * n + e] = mk(a.re * f, a.im * f);
+    }
 }
 
-// r = b - r
 __global__ void k_residual(const c128 *b, c128 *r, long long n) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
         r[e] = b[e] - r[e];
 }
 
-// Arnoldi bookkeeping for step j (single lane).
-// st: [0] = |g_{j+1}|, [1] = h_{j+1,j} (the new basis scale), [2] = breakdown flag,
-// [3] = sqrt(|w_0|^2) before orthogonalisation.
+__global__ void k_narrow(const c128 *a, c64 *b, long long n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        b[e] = mk((float)a[e].re, (float)a[e].im);
+}
+
+__global__ void k_widen(const c64 *a, c128 *b, long long n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        b[e] = mk((double)a[e].re, (double)a[e].im);
+}
+
+// Per right-hand side Arnoldi bookkeeping arrays (device), each with R slices.
 struct GState {
-    c128 *h1, *h2;     // [nv] two CGS passes, h1[nv] = |w0|^2 (self entry)
-    c128 *nrm2;        // [1] |w|^2 after orthogonalisation
-    c128 *R;           // [restart][restart+1] column-major rotated Hessenberg
-    double *cs;        // [restart]
-    c128 *sn;          // [restart]
-    c128 *g;           // [restart+1]
-    double *st;        // [4]
+    c128 *h1, *h2;  // [R][m+2]: two CGS passes; h1[nv] = |w0|^2 (self entry)
+    c128 *nrm2;     // [R]: |w|^2 after orthogonalisation
+    c128 *Rm;       // [R][m][m+1] column-major rotated Hessenberg
+    double *cs;     // [R][m]
+    c128 *sn;       // [R][m]
+    c128 *g;        // [R][m+1]
+    c128 *y;        // [R][m]
+    double *st;     // [R][4]: |g_{j+1}|, h_{j+1,j}, breakdown, |w0|
+    int *active;    // [R]
+    int m;
 };
 
-__global__ void k_givens(GState S, int j, int ldr) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    c128 *col = S.R + (long long)j * ldr;
-    for (int i = 0; i <= j; ++i) col[i] = S.h1[i] + S.h2[i];
-    double hn = sqrt(S.nrm2[0].re);
-    double w0 = sqrt(S.h1[j + 1].re);
-    c128 hj1 = mk(hn, 0.0);
+// Step j for every active right-hand side: one lane per right-hand side.
+__global__ void k_givens(GState S, int j, int R) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int m = S.m;
+    double *st = S.st + 4 * r;
+    if (!S.active[r]) {
+        st[0] = 0.0;
+        st[1] = 0.0;
+        st[2] = 1.0;
+        st[3] = 0.0;
+        return;
+    }
+    const c128 *h1 = S.h1 + (long long)r * (m + 2), *h2 = S.h2 + (long long)r * (m + 2);
+    c128 *col = S.Rm + ((long long)r * m + j) * (m + 1);
+    double *cs = S.cs + (long long)r * m;
+    c128 *sn = S.sn + (long long)r * m;
+    c128 *g = S.g + (long long)r * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+    double hn = sqrt(S.nrm2[r].re);
+    double w0 = sqrt(h1[j + 1].re);
     for (int i = 0; i < j; ++i) {
         c128 a = col[i], b = col[i + 1];
-        col[i] = S.cs[i] * a + S.sn[i] * b;
-        col[i + 1] = S.cs[i] * b - conjg(S.sn[i]) * a;
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = cs[i] * b - conjg(sn[i]) * a;
     }
     c128 a = col[j];
     double c;
-    c128 s, r;
+    c128 s, rr;
     double aa = sqrt(abs2(a)), bb = hn;
     if (bb == 0.0) {
         c = 1.0;
         s = czero<double>();
-        r = a;
+        rr = a;
     } else if (aa == 0.0) {
         c = 0.0;
         s = mk(1.0, 0.0);
-        r = hj1;
+        rr = mk(hn, 0.0);
     } else {
         double rho = hypot(aa, bb);
         c128 ph = mk(a.re / aa, a.im / aa);
         c = aa / rho;
-        s = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b)/rho, b real
-        r = mk(ph.re * rho, ph.im * rho);
+        s = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b) / rho, b real
+        rr = mk(ph.re * rho, ph.im * rho);
     }
-    S.cs[j] = c;
-    S.sn[j] = s;
-    col[j] = r;
-    c128 gj = S.g[j];
-    S.g[j + 1] = mk(0.0, 0.0) - conjg(s) * gj;
-    S.g[j] = c * gj;
-    S.st[0] = sqrt(abs2(S.g[j + 1]));
-    S.st[1] = hn;
-    S.st[2] = (hn <= 1e-14 * w0) ? 1.0 : 0.0;
-    S.st[3] = w0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = rr;
+    c128 gj = g[j];
+    g[j + 1] = mk(0.0, 0.0) - conjg(s) * gj;
+    g[j] = c * gj;
+    st[0] = sqrt(abs2(g[j + 1]));
+    st[1] = hn;
+    st[2] = (hn <= 1e-14 * w0) ? 1.0 : 0.0;
+    st[3] = w0;
 }
 
-// y = R^{-1} g (k x k upper triangular), single lane
-__global__ void k_lsq(const c128 *R, int ldr, const c128 *g, c128 *y, int k) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// y_r = R_r^{-1} g_r over the first jr[r] columns; one lane per right-hand side.
+__global__ void k_lsq(GState S, const int *jr, int R) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int m = S.m, k = jr[r];
+    const c128 *Rm = S.Rm + (long long)r * m * (m + 1);
+    const c128 *g = S.g + (long long)r * (m + 1);
+    c128 *y = S.y + (long long)r * m;
     for (int i = k - 1; i >= 0; --i) {
         c128 acc = g[i];
-        for (int c = i + 1; c < k; ++c) acc = cfms(acc, R[(long long)c * ldr + i], y[c]);
-        y[i] = cdiv(acc, R[(long long)i * ldr + i]);
+        for (int c = i + 1; c < k; ++c) acc = cfms(acc, Rm[(long long)c * (m + 1) + i], y[c]);
+        y[i] = cdiv(acc, Rm[(long long)i * (m + 1) + i]);
     }
 }
 
-__global__ void k_setg(c128 *g, int n, double beta) {
+// g_r = (beta_r, 0, ...)
+__global__ void k_setg(c128 *g, int m1, const double *beta, int R) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) g[i] = mk(i == 0 ? beta : 0.0, 0.0);
+    if (i >= m1 * R) return;
+    int r = i / m1, k = i % m1;
+    g[i] = mk(k == 0 ? beta[r] : 0.0, 0.0);
 }
 
 namespace {
 struct Ctx {
     vie_op op;
-    vie_pc pc;
     hipStream_t s;
-    long long n;
+    long long n;  // 3N
+    int R;
     c128 *partial;
-    double *host;  // pinned
+    double *host;  // pinned scratch
 };
 
-vie_status dots(Ctx &C, const c128 *V, long long ldv, int nv, const c128 *w, int self, c128 *out) {
-    ProfScope ps("arnoldi_dots", C.s);
-    hipLaunchKernelGGL(k_dots, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, C.s, V, ldv, nv, w, C.n, self, C.partial);
+// batched norms: out[r].re = |w_r|^2
+vie_status norms(Ctx &C, const c128 *w, c128 *out) {
+    hipLaunchKernelGGL(k_dots, dim3(KR_BLOCKS, C.R), dim3(KR_THREADS), 0, C.s, (const c128 *)nullptr, 0LL, 0, w, C.n, 1,
+                       C.partial);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce, dim3(nv + self), dim3(KR_THREADS), 0, C.s, C.partial, KR_BLOCKS, nv + self, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1, C.R), dim3(KR_THREADS), 0, C.s, C.partial, KR_BLOCKS, 1, out, 1);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
 
-vie_status norm2(Ctx &C, const c128 *w, c128 *out) { return dots(C, nullptr, 0, 0, w, 1, out); }
-
-vie_status read_doubles(Ctx &C, const double *dev, int cnt) {
-    VIE_HIP(hipMemcpyAsync(C.host, dev, sizeof(double) * cnt, hipMemcpyDeviceToHost, C.s));
+vie_status read_host(Ctx &C, const void *dev, size_t bytes) {
+    VIE_HIP(hipMemcpyAsync(C.host, dev, bytes, hipMemcpyDeviceToHost, C.s));
     VIE_HIP(hipStreamSynchronize(C.s));
     return VIE_OK;
 }
-
-vie_status apply_A(Ctx &C, const c128 *x, c128 *y) { return launch_matvec(C.op, x, y, 1, VIE_C128, C.s); }
-vie_status apply_P(Ctx &C, const c128 *x, c128 *y) {
-    if (!C.pc) {
-        VIE_HIP(hipMemcpyAsync(y, x, sizeof(c128) * C.n, hipMemcpyDeviceToDevice, C.s));
-        return VIE_OK;
-    }
-    return pc_apply(C.pc, x, y, 1, VIE_C128, C.s);
-}
 }  // namespace
 
-vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b_all, c128 *x_all, int nrhs, const vie_solve_opts *o,
+vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, const vie_solve_opts *o,
                        vie_solve_stats *stats, hipStream_t s) {
-    if (pc && pc->prec != VIE_C128) {
-        vie_set_error("FP64 solve needs complex128 preconditioner factors");
+    const bool mixed = o->mode == VIE_MODE_MIXED;
+    if (mixed && !op->has_c64) {
+        vie_set_error("mixed-precision solve needs an operator built with build_c64");
+        return VIE_EARG;
+    }
+    if (pc && pc->prec != (mixed ? VIE_C64 : VIE_C128)) {
+        vie_set_error(mixed ? "mixed-precision solve needs complex64 preconditioner factors"
+                            : "FP64 solve needs complex128 preconditioner factors");
         return VIE_EARG;
     }
     const int m = o->restart;
     const long long n = 3LL * op->N;
-    Ctx C{op, pc, s, n, nullptr, nullptr};
-    DevBuf Vb, Zb, wb, rb, part, small;
-    VIE_CHECK(Vb.ensure(sizeof(c128) * n * (m + 1)));
-    VIE_CHECK(Zb.ensure(sizeof(c128) * n * m));
-    VIE_CHECK(wb.ensure(sizeof(c128) * n));
-    VIE_CHECK(rb.ensure(sizeof(c128) * n));
-    VIE_CHECK(part.ensure(sizeof(c128) * KR_BLOCKS * (m + 2)));
-    // small: h1[m+2], h2[m+2], nrm2[1], R[m*(m+1)], cs[m], sn[m], g[m+1], st[4], y[m]
-    size_t off_h1 = 0, off_h2 = off_h1 + (m + 2), off_n = off_h2 + (m + 2), off_R = off_n + 1,
-           off_sn = off_R + (size_t)m * (m + 1), off_g = off_sn + m, off_y = off_g + m + 1, off_end = off_y + m;
-    size_t bytes = sizeof(c128) * off_end + sizeof(double) * (m + 4);
-    VIE_CHECK(small.ensure(bytes));
-    c128 *sm = small.as<c128>();
-    double *cs = reinterpret_cast<double *>(sm + off_end);
-    double *st = cs + m;
-    GState S{sm + off_h1, sm + off_h2, sm + off_n, sm + off_R, cs, sm + off_sn, sm + off_g, st};
+    const long long Rn = (long long)R * n;
+    Ctx C{op, s, n, R, nullptr, nullptr};
+    const size_t zsz = mixed ? sizeof(c64) : sizeof(c128);
+    DevBuf Vb, Zb, wb, rb, part, small, t32, w32;
+    VIE_CHECK(Vb.ensure(sizeof(c128) * Rn * (m + 1)));
+    VIE_CHECK(Zb.ensure(zsz * Rn * m));
+    VIE_CHECK(wb.ensure(sizeof(c128) * Rn));
+    VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
+    VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * KR_BLOCKS * (m + 2)));
+    if (mixed) {
+        VIE_CHECK(t32.ensure(sizeof(c64) * Rn));
+        VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
+    }
+    size_t nc = (size_t)R * ((size_t)(m + 2) * 2 + 1 + (size_t)m * (m + 1) + m + (m + 1) + m);
+    size_t nd = (size_t)R * (m + 4 + 1);
+    VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * 2 * R));
+    c128 *cp = small.as<c128>();
+    GState S;
+    S.m = m;
+    S.h1 = cp;
+    cp += (size_t)R * (m + 2);
+    S.h2 = cp;
+    cp += (size_t)R * (m + 2);
+    S.nrm2 = cp;
+    cp += R;
+    S.Rm = cp;
+    cp += (size_t)R * m * (m + 1);
+    S.sn = cp;
+    cp += (size_t)R * m;
+    S.g = cp;
+    cp += (size_t)R * (m + 1);
+    S.y = cp;
+    cp += (size_t)R * m;
+    double *dp = reinterpret_cast<double *>(cp);
+    S.cs = dp;
+    dp += (size_t)R * m;
+    S.st = dp;
+    dp += (size_t)R * 4;
+    double *beta_dev = dp;
+    dp += R;
+    S.active = reinterpret_cast<int *>(dp);
+    int *jr_dev = S.active + R;
     C.partial = part.as<c128>();
     double *host = nullptr;
-    VIE_HIP(hipHostMalloc((void **)&host, sizeof(double) * 8, hipHostMallocDefault));
+    // pinned layout: doubles [0, 4R) | ints active [R] | ints jr [R]
+    VIE_HIP(hipHostMalloc((void **)&host, sizeof(double) * 4 * (size_t)R + sizeof(int) * 2 * R + 64,
+                          hipHostMallocDefault));
+    struct HostFree {
+        double *p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } hf{host};
     C.host = host;
-    c128 *V = Vb.as<c128>(), *Z = Zb.as<c128>(), *w = wb.as<c128>(), *r = rb.as<c128>();
-    vie_status result = VIE_OK;
-    for (int q = 0; q < nrhs; ++q) {
-        const c128 *b = b_all + q * n;
-        c128 *x = x_all + q * n;
-        vie_solve_stats &sq = stats[q];
-        sq.iters = 0;
-        sq.restarts = 0;
-        sq.relres = 0;
-        sq.status = VIE_OK;
-        // ||b||
-        VIE_CHECK(norm2(C, b, sm + off_n));
-        VIE_CHECK(read_doubles(C, reinterpret_cast<const double *>(sm + off_n), 1));
-        double nb = sqrt(host[0]);
-        if (!std::isfinite(nb)) {
-            vie_set_error("non-finite right-hand side");
-            (void)hipHostFree(host);
+    int *hact = reinterpret_cast<int *>(host + 4 * (size_t)R);
+    int *hjr = hact + R;
+    c128 *V = Vb.as<c128>(), *w = wb.as<c128>(), *r = rb.as<c128>();
+    const long long ldj = Rn;  // stride between Arnoldi vectors
+    dim3 grid_b(KR_BLOCKS, R), grid_e(1024, R);
+
+    std::vector<double> nb(R), beta(R);
+    std::vector<int> done(R, 0), act(R, 0), jr(R, 0);
+    for (int q = 0; q < R; ++q) stats[q] = vie_solve_stats{0, 0, 0.0, VIE_OK};
+    VIE_CHECK(norms(C, b, S.nrm2));
+    VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
+    for (int q = 0; q < R; ++q) nb[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+    for (int q = 0; q < R; ++q)
+        if (!std::isfinite(nb[q])) {
+            vie_set_error("non-finite right-hand side " + std::to_string(q));
             return VIE_ENONFINITE;
         }
-        if (nb == 0.0) {
-            VIE_HIP(hipMemsetAsync(x, 0, sizeof(c128) * n, s));
-            continue;
-        }
-        // r = b - A x0
-        if (o->x0_given) {
-            VIE_CHECK(apply_A(C, x, r));
-            hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, n);
-            VIE_HIP(hipGetLastError());
-        } else {
-            VIE_HIP(hipMemsetAsync(x, 0, sizeof(c128) * n, s));
-            VIE_HIP(hipMemcpyAsync(r, b, sizeof(c128) * n, hipMemcpyDeviceToDevice, s));
-        }
-        VIE_CHECK(norm2(C, r, sm + off_n));
-        VIE_CHECK(read_doubles(C, reinterpret_cast<const double *>(sm + off_n), 1));
-        double beta = sqrt(host[0]);
-        bool done = false;
-        while (!done) {
-            if (!std::isfinite(beta)) {
-                vie_set_error("non-finite residual");
-                (void)hipHostFree(host);
+    if (o->x0_given) {
+        VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
+        hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
+        VIE_HIP(hipGetLastError());
+    } else {
+        VIE_HIP(hipMemsetAsync(x, 0, sizeof(c128) * Rn, s));
+        VIE_HIP(hipMemcpyAsync(r, b, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
+    }
+    VIE_CHECK(norms(C, r, S.nrm2));
+    VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
+    for (int q = 0; q < R; ++q) beta[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+    vie_status result = VIE_OK;
+    for (;;) {
+        int nact = 0;
+        for (int q = 0; q < R; ++q) {
+            if (!std::isfinite(beta[q])) {
+                vie_set_error("non-finite residual for right-hand side " + std::to_string(q));
                 return VIE_ENONFINITE;
             }
-            if (beta / nb <= o->tol) {
-                sq.relres = beta / nb;
-                break;
-            }
-            if (sq.iters >= o->maxit) {
-                sq.relres = beta / nb;
-                sq.status = VIE_NOT_CONVERGED;
+            double rel = nb[q] > 0 ? beta[q] / nb[q] : 0.0;
+            stats[q].relres = rel;
+            if (!done[q] && (nb[q] == 0.0 || rel <= o->tol)) done[q] = 1;
+            if (!done[q] && stats[q].iters >= o->maxit) {
+                done[q] = 1;
+                stats[q].status = VIE_NOT_CONVERGED;
                 result = VIE_NOT_CONVERGED;
-                break;
             }
-            // v0 = r / beta
-            host[4] = beta;
-            VIE_HIP(hipMemcpyAsync(st + 1, host + 4, sizeof(double), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, s, r, V, n, st + 1);
+            act[q] = !done[q];
+            jr[q] = 0;
+            nact += act[q];
+        }
+        if (nact == 0) break;
+        // v0 = r / beta (zero for finished right-hand sides), g = (beta, 0, ...)
+        for (int q = 0; q < R; ++q) {
+            host[q] = beta[q];
+            hact[q] = act[q];
+        }
+        VIE_HIP(hipMemcpyAsync(beta_dev, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
+        VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_scale, grid_e, dim3(256), 0, s, (const c128 *)r, V, n, (const double *)beta_dev, 1,
+                           (const int *)S.active);
+        VIE_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_setg, dim3((unsigned)(((m + 1) * R + 63) / 64)), dim3(64), 0, s, S.g, m + 1,
+                           (const double *)beta_dev, R);
+        VIE_HIP(hipGetLastError());
+        int j = 0;
+        while (j < m && nact > 0) {
+            c128 *vj = V + j * ldj;
+            void *zj = (char *)Zb.p + zsz * Rn * j;
+            if (!mixed) {
+                if (pc)
+                    VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
+                else
+                    VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
+                VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
+            } else {
+                hipLaunchKernelGGL(k_narrow, dim3(1024), dim3(256), 0, s, (const c128 *)vj, t32.as<c64>(), Rn);
+                VIE_HIP(hipGetLastError());
+                if (pc)
+                    VIE_CHECK(pc_apply(pc, t32.p, zj, R, VIE_C64, s));
+                else
+                    VIE_HIP(hipMemcpyAsync(zj, t32.p, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
+                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
+                hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
+                VIE_HIP(hipGetLastError());
+            }
+            {
+                ProfScope ps("arnoldi_dots", s);
+                hipLaunchKernelGGL(k_dots, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1, (const c128 *)w, n,
+                                   1, C.partial);
+                VIE_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS,
+                               j + 2, S.h1, m + 2);
             VIE_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_setg, dim3((m + 1 + 63) / 64), dim3(64), 0, s, S.g, m + 1, beta);
+            {
+                ProfScope ps("arnoldi_update", s);
+                hipLaunchKernelGGL(k_update, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1,
+                                   (const c128 *)S.h1, m + 2, w, n, (c128 *)nullptr);
+                VIE_HIP(hipGetLastError());
+            }
+            {
+                ProfScope ps("arnoldi_dots", s);
+                hipLaunchKernelGGL(k_dots, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1, (const c128 *)w, n,
+                                   0, C.partial);
+                VIE_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS,
+                               j + 1, S.h2, m + 2);
             VIE_HIP(hipGetLastError());
-            int j = 0;
-            while (j < m && sq.iters < o->maxit) {
-                c128 *vj = V + j * n, *zj = Z + j * n;
-                VIE_CHECK(apply_P(C, vj, zj));
-                VIE_CHECK(apply_A(C, zj, w));
-                VIE_CHECK(dots(C, V, n, j + 1, w, 1, S.h1));
-                {
-                    ProfScope ps("arnoldi_update", s);
-                    hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h1, w, n,
-                                       (c128 *)nullptr);
-                }
+            {
+                ProfScope ps("arnoldi_update", s);
+                hipLaunchKernelGGL(k_update, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1,
+                                   (const c128 *)S.h2, m + 2, w, n, C.partial);
                 VIE_HIP(hipGetLastError());
-                VIE_CHECK(dots(C, V, n, j + 1, w, 0, S.h2));
-                {
-                    ProfScope ps("arnoldi_update", s);
-                    hipLaunchKernelGGL(k_update, dim3(KR_BLOCKS), dim3(KR_THREADS), 0, s, V, n, j + 1, S.h2, w, n,
-                                       C.partial);
-                }
-                VIE_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, C.partial, KR_BLOCKS, 1, S.nrm2);
-                VIE_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, S, j, m + 1);
-                VIE_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, s, w, V + (j + 1) * n, n, st + 1);
-                VIE_HIP(hipGetLastError());
-                VIE_CHECK(read_doubles(C, st, 3));
-                ++j;
-                ++sq.iters;
-                double est = host[0] / nb;
+            }
+            hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, 1,
+                               S.nrm2, 1);
+            VIE_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_givens, dim3((R + 63) / 64), dim3(64), 0, s, S, j, R);
+            VIE_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_scale, grid_e, dim3(256), 0, s, (const c128 *)w, V + (j + 1) * ldj, n,
+                               (const double *)(S.st + 1), 4, (const int *)S.active);
+            VIE_HIP(hipGetLastError());
+            VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
+            ++j;
+            bool changed = false;
+            for (int q = 0; q < R; ++q) {
+                if (!act[q]) continue;
+                double est = host[4 * q] / nb[q];
                 if (!std::isfinite(est)) {
-                    vie_set_error("non-finite Arnoldi step");
-                    (void)hipHostFree(host);
+                    vie_set_error("non-finite Arnoldi step for right-hand side " + std::to_string(q));
                     return VIE_ENONFINITE;
                 }
-                if (est <= o->tol || host[2] != 0.0) break;
+                ++stats[q].iters;
+                jr[q] = j;
+                if (est <= o->tol || host[4 * q + 2] != 0.0 || stats[q].iters >= o->maxit) {
+                    act[q] = 0;
+                    --nact;
+                    changed = true;
+                }
             }
-            // x += Z y
-            hipLaunchKernelGGL(k_lsq, dim3(1), dim3(64), 0, s, S.R, m + 1, S.g, sm + off_y, j);
-            VIE_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_combine, dim3(1024), dim3(KR_THREADS), 0, s, Z, n, j, sm + off_y, x, n, 1);
-            VIE_HIP(hipGetLastError());
-            ++sq.restarts;
-            // true residual
-            VIE_CHECK(apply_A(C, x, r));
-            hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, n);
-            VIE_HIP(hipGetLastError());
-            VIE_CHECK(norm2(C, r, sm + off_n));
-            VIE_CHECK(read_doubles(C, reinterpret_cast<const double *>(sm + off_n), 1));
-            beta = sqrt(host[0]);
+            if (changed && nact > 0 && j < m) {
+                for (int q = 0; q < R; ++q) hact[q] = act[q];
+                VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
+            }
         }
+        // x += Z y
+        for (int q = 0; q < R; ++q) hjr[q] = jr[q];
+        VIE_HIP(hipMemcpyAsync(jr_dev, hjr, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_lsq, dim3((R + 63) / 64), dim3(64), 0, s, S, (const int *)jr_dev, R);
+        VIE_HIP(hipGetLastError());
+        if (mixed)
+            hipLaunchKernelGGL(k_combine<float>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c64>(), ldj,
+                               (const int *)jr_dev, (const c128 *)S.y, m, x, n);
+        else
+            hipLaunchKernelGGL(k_combine<double>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c128>(), ldj,
+                               (const int *)jr_dev, (const c128 *)S.y, m, x, n);
+        VIE_HIP(hipGetLastError());
+        for (int q = 0; q < R; ++q)
+            if (jr[q] > 0) ++stats[q].restarts;
+        // FP64 true residual
+        VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
+        hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
+        VIE_HIP(hipGetLastError());
+        VIE_CHECK(norms(C, r, S.nrm2));
+        VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
+        for (int q = 0; q < R; ++q) beta[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
     }
-    (void)hipHostFree(host);
     return result;
 }

@@ -31,30 +31,38 @@
 #define LU_TILE 64
 
 // ---------------------------------------------------------------- homogenisation
-__global__ void k_homog(const c128 *M, c128 *Mt, const int *boxes, int nboxes, int nx, int ny, int by,
-                        int bz, int kind, int *violation) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per (box, z, y) row of a box: M~ = M(x0) (NONE, x-invariance checked),
+// mean or real part of the mean along x (Sec. 5.2, items 2 and 3).
+__global__ void __launch_bounds__(256) k_homog(const c128 *M, c128 *Mt, const int *boxes, int nx, int ny, int by,
+                                               int bz, int kind, int *violation) {
+    __shared__ c128 red[256];
+    int i = blockIdx.x;
     int per = by * bz;
-    if (i >= nboxes * per) return;
     int b = i / per, r = i % per;
     int y = r % by, z = r / by;
     const int *bx = boxes + 6 * b;
     const c128 *row = M + ((long long)(bx[2] + z) * ny + (bx[1] + y)) * nx + bx[0];
     int n = bx[3];
-    c128 out;
-    if (kind == VIE_HOMOG_NONE) {
-        out = row[0];
-        for (int x = 1; x < n; ++x)
-            if (row[x].re != out.re || row[x].im != out.im) atomicOr(violation, 1);
-    } else {
-        double sr = 0, si = 0;
-        for (int x = 0; x < n; ++x) {
-            sr += row[x].re;
-            si += row[x].im;
-        }
-        out = mk(sr / n, kind == VIE_HOMOG_REALMEAN ? 0.0 : si / n);
+    c128 first = row[0];
+    c128 acc = czero<double>();
+    int bad = 0;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        c128 v = row[x];
+        acc = acc + v;
+        if (v.re != first.re || v.im != first.im) bad = 1;
     }
-    Mt[i] = out;
+    if (kind == VIE_HOMOG_NONE) {
+        if (bad) atomicOr(violation, 1);
+        if (threadIdx.x == 0) Mt[i] = first;
+        return;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) Mt[i] = mk(red[0].re / n, kind == VIE_HOMOG_REALMEAN ? 0.0 : red[0].im / n);
 }
 
 // ---------------------------------------------------------------- Chan table
@@ -130,48 +138,77 @@ __global__ void k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode, 
 template <class R>
 __device__ __forceinline__ R cabs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
 
-// Factor the panel rows [j0, m), columns [j0, j0 + w) of every block (one workgroup per block).
+// argmax over the workgroup of (value, index); ties -> smaller index.  Result in (sv[0], si[0]).
+template <class R>
+__device__ __forceinline__ void block_argmax(R v, int idx, R *sv, int *si) {
+    for (int off = 32; off > 0; off >>= 1) {
+        R ov = __shfl_down(v, off);
+        int oi = __shfl_down(idx, off);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sv[1 + wid] = v;
+        si[1 + wid] = idx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        R bv = sv[1];
+        int bi = si[1];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+            if (sv[1 + k] > bv || (sv[1 + k] == bv && si[1 + k] < bi)) {
+                bv = sv[1 + k];
+                bi = si[1 + k];
+            }
+        sv[0] = bv;
+        si[0] = bi;
+    }
+    __syncthreads();
+}
+
+// Factor the panel rows [j0, m), columns [j0, j0 + w) of every block (one workgroup per block):
+// per column a wavefront-shuffle pivot search, the row interchange inside the panel, and the
+// scaled rank-1 update of the remaining panel columns, which also yields the next column's
+// pivot candidates.
 template <class R>
 __global__ void __launch_bounds__(256) k_lu_panel(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
-    __shared__ R vmax[256];
-    __shared__ int imax[256];
+    __shared__ R sv[1 + 256 / 64];
+    __shared__ int si[1 + 256 / 64];
     cpx<R> *a = A + (long long)blockIdx.x * m * m;
     int *piv = ipiv + (long long)blockIdx.x * m;
+    // candidates for the first column
+    R best = R(-1);
+    int bi = j0;
+    for (int i = j0 + threadIdx.x; i < m; i += blockDim.x) {
+        R v = cabs2(a[(long long)j0 * m + i]);
+        if (v > best) {
+            best = v;
+            bi = i;
+        }
+    }
     for (int j = j0; j < j0 + w; ++j) {
-        // pivot search in column j, rows j..m-1 (ties -> smallest row)
-        R best = R(-1);
-        int bi = j;
-        for (int i = j + threadIdx.x; i < m; i += blockDim.x) {
-            R v = cabs2(a[(long long)j * m + i]);
-            if (v > best) {
-                best = v;
-                bi = i;
-            }
-        }
-        vmax[threadIdx.x] = best;
-        imax[threadIdx.x] = bi;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                R o = vmax[threadIdx.x + s];
-                int oi = imax[threadIdx.x + s];
-                if (o > vmax[threadIdx.x] || (o == vmax[threadIdx.x] && oi < imax[threadIdx.x])) {
-                    vmax[threadIdx.x] = o;
-                    imax[threadIdx.x] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        int p = imax[0];
-        R pv = vmax[0];
-        __syncthreads();
+        block_argmax<R>(best, bi, sv, si);
+        int p = si[0];
+        R pv = sv[0];
         if (threadIdx.x == 0) piv[j] = p;
         if (pv == R(0)) {
             if (threadIdx.x == 0 && info[blockIdx.x] == 0) info[blockIdx.x] = j + 1;
-            __syncthreads();
+            // no elimination; next column's candidates
+            best = R(-1);
+            bi = j + 1;
+            if (j + 1 < j0 + w)
+                for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) {
+                    R v = cabs2(a[(long long)(j + 1) * m + i]);
+                    if (v > best) {
+                        best = v;
+                        bi = i;
+                    }
+                }
             continue;
         }
-        // swap rows j and p inside the panel
         if (p != j)
             for (int c = j0 + (int)threadIdx.x; c < j0 + w; c += blockDim.x) {
                 cpx<R> t = a[(long long)c * m + j];
@@ -182,37 +219,77 @@ __global__ void __launch_bounds__(256) k_lu_panel(cpx<R> *A, int *ipiv, int *inf
         cpx<R> piv_v = a[(long long)j * m + j];
         R d = cabs2(piv_v);
         cpx<R> inv = mk(piv_v.re / d, -piv_v.im / d);
+        best = R(-1);
+        bi = j + 1;
         for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) {
             cpx<R> l = a[(long long)j * m + i] * inv;
             a[(long long)j * m + i] = l;
-            for (int c = j + 1; c < j0 + w; ++c) a[(long long)c * m + i] = cfms(a[(long long)c * m + i], l, a[(long long)c * m + j]);
+            for (int c = j + 1; c < j0 + w; ++c) {
+                cpx<R> v = cfms(a[(long long)c * m + i], l, a[(long long)c * m + j]);
+                a[(long long)c * m + i] = v;
+                if (c == j + 1) {
+                    R q = cabs2(v);
+                    if (q > best) {
+                        best = q;
+                        bi = i;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-// Row swaps of the panel applied to all other columns; for columns right of the
-// panel also U12 = L11^{-1} A12.  One thread per column.
+// Row interchanges of the panel applied to the other columns, and for columns right of the
+// panel U12 = L11^{-1} A12.  One workgroup per (64-column tile, block): rows [j0, j0 + w) of
+// the tile are staged in LDS with coalesced loads; interchanges with rows below the panel are
+// exchanged with global memory.
 template <class R>
-__global__ void k_lu_swap_trsm(cpx<R> *A, const int *ipiv, int m, int j0, int w) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m || (c >= j0 && c < j0 + w)) return;
-    cpx<R> *col = A + (long long)blockIdx.y * m * m + (long long)c * m;
-    const int *piv = ipiv + (long long)blockIdx.y * m;
-    const cpx<R> *a = A + (long long)blockIdx.y * m * m;
-    for (int j = j0; j < j0 + w; ++j) {
-        int p = piv[j];
-        if (p != j) {
-            cpx<R> t = col[j];
-            col[j] = col[p];
-            col[p] = t;
-        }
+__global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *ipiv, int m, int j0, int w) {
+    __shared__ cpx<R> T[LU_NB][65];
+    __shared__ cpx<R> L11[LU_NB][LU_NB + 1];
+    __shared__ int pv[LU_NB];
+    const int c0 = blockIdx.x * 64;
+    cpx<R> *a = A + (long long)blockIdx.y * m * m;
+    if ((int)threadIdx.x < w) pv[threadIdx.x] = ipiv[(long long)blockIdx.y * m + j0 + threadIdx.x];
+    for (int e = threadIdx.x; e < w * 64; e += blockDim.x) {
+        int r = e % w, c = e / w, col = c0 + c;
+        bool live = col < m && !(col >= j0 && col < j0 + w);
+        T[r][c] = live ? a[(long long)col * m + j0 + r] : czero<R>();
     }
-    if (c >= j0 + w)
-        for (int j = j0; j < j0 + w; ++j) {
-            cpx<R> u = col[j];
-            for (int i = j + 1; i < j0 + w; ++i) col[i] = cfms(col[i], a[(long long)j * m + i], u);
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+        int r = e % w, c = e / w;
+        L11[r][c] = a[(long long)(j0 + c) * m + j0 + r];
+    }
+    __syncthreads();
+    const int c = threadIdx.x;
+    const int col = c0 + c;
+    const bool live = c < 64 && col < m && !(col >= j0 && col < j0 + w);
+    if (live) {
+        for (int j = 0; j < w; ++j) {
+            int p = pv[j];
+            if (p == j0 + j) continue;
+            if (p < j0 + w) {
+                cpx<R> t = T[j][c];
+                T[j][c] = T[p - j0][c];
+                T[p - j0][c] = t;
+            } else {
+                cpx<R> t = a[(long long)col * m + p];
+                a[(long long)col * m + p] = T[j][c];
+                T[j][c] = t;
+            }
         }
+        if (col >= j0 + w)
+            for (int j = 0; j < w; ++j) {
+                cpx<R> u = T[j][c];
+                for (int i = j + 1; i < w; ++i) T[i][c] = cfms(T[i][c], L11[i][j], u);
+            }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * 64; e += blockDim.x) {
+        int r = e % w, cc = e / w, cl = c0 + cc;
+        if (cl < m && !(cl >= j0 && cl < j0 + w)) a[(long long)cl * m + j0 + r] = T[r][cc];
+    }
 }
 
 // A22 -= L21 U12 on 64x64 tiles, 4x4 complex outputs per thread.
@@ -284,6 +361,51 @@ __global__ void k_lu_perm(const int *ipiv, int *perm, int m, int nblk) {
     }
 }
 
+#define TS 64
+// Setup: replace every 64x64 diagonal tile of the packed LU factors by the inverses of its
+// unit-lower part (strictly lower entries) and of its upper part (upper entries incl. the
+// diagonal).  The block solves then apply each diagonal tile as a parallel product.
+// One workgroup (128 threads) per (tile, block): thread j < 64 inverts column j of L,
+// thread 64 + j column j of U, both from an LDS copy of the tile.
+template <class R>
+__global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
+    cpx<R> *T = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][TS+1], column-major: T[c*(TS+1)+r]
+    cpx<R> *X = T + TS * (TS + 1);
+    const int t0 = blockIdx.x * TS;
+    const int w = min(TS, m - t0);
+    cpx<R> *a = F + (long long)blockIdx.y * m * m;
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+        int r = e % w, c = e / w;
+        T[c * (TS + 1) + r] = a[(long long)(t0 + c) * m + t0 + r];
+    }
+    __syncthreads();
+    int j = threadIdx.x & 63;
+    if (j < w) {
+        if (threadIdx.x < 64) {
+            // column j of L^{-1} (unit lower): x_j = 1 (implicit; the diagonal slot belongs to U^{-1}),
+            // x_i = -(l_ij + sum_{k=j+1}^{i-1} l_ik x_k)
+            for (int i = j + 1; i < w; ++i) {
+                cpx<R> acc = T[j * (TS + 1) + i];
+                for (int k = j + 1; k < i; ++k) acc = acc + T[k * (TS + 1) + i] * X[j * (TS + 1) + k];
+                X[j * (TS + 1) + i] = mk(-acc.re, -acc.im);
+            }
+        } else {
+            // column j of U^{-1}: x_j = 1/u_jj, x_i = -(sum_{k=i+1}^{j} u_ik x_k) / u_ii
+            X[j * (TS + 1) + j] = cdiv(mk(R(1), R(0)), T[j * (TS + 1) + j]);
+            for (int i = j - 1; i >= 0; --i) {
+                cpx<R> acc = czero<R>();
+                for (int k = i + 1; k <= j; ++k) acc = acc + T[k * (TS + 1) + i] * X[j * (TS + 1) + k];
+                X[j * (TS + 1) + i] = cdiv(mk(-acc.re, -acc.im), T[i * (TS + 1) + i]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+        int r = e % w, c = e / w;
+        a[(long long)(t0 + c) * m + t0 + r] = X[c * (TS + 1) + r];
+    }
+}
+
 template <class R>
 static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     const int m = pc->m, nb = pc->nstored;
@@ -301,7 +423,7 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
         VIE_HIP(hipGetLastError());
         {
             ProfScope ps("lu_swap_trsm", s);
-            hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + 63) / 64, nb), dim3(64), 0, s, A, ipiv.as<int>(), m,
+            hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + 63) / 64, nb), dim3(256), 0, s, A, ipiv.as<int>(), m,
                                j0, w);
         }
         VIE_HIP(hipGetLastError());
@@ -316,6 +438,13 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());
+    {
+        size_t lds = 2 * sizeof(cpx<R>) * TS * (TS + 1);
+        vie_lds_attr((const void *)k_invert_diag<R>, lds);
+        ProfScope ps("lu_invert_diag", s);
+        hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(128), lds, s, A, m);
+        VIE_HIP(hipGetLastError());
+    }
     VIE_HIP(hipStreamSynchronize(s));
     ipiv.release();
     return VIE_OK;
@@ -367,80 +496,70 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
 }
 
-#define TS_B 32
 // One workgroup per (rhs, box, mode): z_k = U^{-1} L^{-1} P rhat_k in place in `work`.
+// Forward and backward substitution by 64-row tiles: the (pre-inverted) diagonal tile is
+// applied by four wavefronts, each summing a quarter of the columns, then the panel below
+// (above) is applied to the remaining rows; factors stream from HBM once, column-coalesced.
 template <class R>
 __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm,
                                                      const int *block_of_mode, int m, int n, int nboxes) {
-    cpx<R> *yv = reinterpret_cast<cpx<R> *>(vie_smem);       // m
-    cpx<R> *tmp = yv + m;                                     // m
-    cpx<R> *dg = tmp + m;                                     // TS_B * TS_B
+    cpx<R> *yv = reinterpret_cast<cpx<R> *>(vie_smem);  // m
+    cpx<R> *part = yv + m;                              // 4 x TS
     long long bid = blockIdx.x;  // (rhs * nboxes + box) * n + k
     int k = (int)(bid % n);
-    long long rb = bid / n;      // rhs * nboxes + box
+    long long rb = bid / n;
     int box = (int)(rb % nboxes);
     int sblk = block_of_mode[box * n + k];
     const cpx<R> *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
-    cpx<R> *base = work + rb * (long long)m * n + k;  // element row i at base[i * n]
-    for (int i = threadIdx.x; i < m; i += blockDim.x) tmp[i] = base[(long long)i * n];
+    cpx<R> *base = work + rb * (long long)m * n + k;  // row i at base[i * n]
+    for (int i = threadIdx.x; i < m; i += blockDim.x) yv[i] = base[(long long)pm[i] * n];
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x) yv[i] = tmp[pm[i]];
-    __syncthreads();
+    const int g = threadIdx.x >> 6, r = threadIdx.x & 63;
     // forward: unit lower L
-    for (int j0 = 0; j0 < m; j0 += TS_B) {
-        int w = min(TS_B, m - j0);
-        for (int e = threadIdx.x; e < TS_B * TS_B; e += blockDim.x) {
-            int c = e / TS_B, i = e % TS_B;
-            dg[e] = (c < w && i < w) ? A[(long long)(j0 + c) * m + j0 + i] : czero<R>();
-        }
+    for (int t0 = 0; t0 < m; t0 += TS) {
+        int w = min(TS, m - t0);
+        cpx<R> acc = czero<R>();
+        if (r < w)
+            for (int c = g; c < r; c += 4) acc = acc + A[(long long)(t0 + c) * m + t0 + r] * yv[t0 + c];
+        part[g * TS + r] = acc;
         __syncthreads();
-        if (threadIdx.x < 64) {
+        if ((int)threadIdx.x < w) {
             int i = threadIdx.x;
-            cpx<R> yi = i < w ? yv[j0 + i] : czero<R>();
-            for (int c = 0; c < w; ++c) {
-                cpx<R> yc;
-                yc.re = __shfl(yi.re, c);
-                yc.im = __shfl(yi.im, c);
-                if (i > c && i < w) yi = cfms(yi, dg[c * TS_B + i], yc);
-            }
-            if (i < w) yv[j0 + i] = yi;
+            yv[t0 + i] = yv[t0 + i] + part[i] + part[TS + i] + part[2 * TS + i] + part[3 * TS + i];
         }
         __syncthreads();
-        for (int i = j0 + w + threadIdx.x; i < m; i += blockDim.x) {
-            cpx<R> acc = yv[i];
-            for (int c = 0; c < w; ++c) acc = cfms(acc, A[(long long)(j0 + c) * m + i], yv[j0 + c]);
-            yv[i] = acc;
+        for (int i = t0 + w + threadIdx.x; i < m; i += blockDim.x) {
+            cpx<R> s = yv[i];
+            const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 8
+            for (int c = 0; c < w; ++c) s = cfms(s, col[(long long)c * m], yv[t0 + c]);
+            yv[i] = s;
         }
         __syncthreads();
     }
     // backward: upper U
-    int nblk = (m + TS_B - 1) / TS_B;
-    for (int bb = nblk - 1; bb >= 0; --bb) {
-        int j0 = bb * TS_B;
-        int w = min(TS_B, m - j0);
-        for (int e = threadIdx.x; e < TS_B * TS_B; e += blockDim.x) {
-            int c = e / TS_B, i = e % TS_B;
-            dg[e] = (c < w && i < w) ? A[(long long)(j0 + c) * m + j0 + i] : czero<R>();
-        }
+    int ntile = (m + TS - 1) / TS;
+    for (int tt = ntile - 1; tt >= 0; --tt) {
+        int t0 = tt * TS;
+        int w = min(TS, m - t0);
+        cpx<R> acc = czero<R>();
+        if (r < w)
+            for (int c = g; c < w; c += 4)
+                if (c >= r) acc = acc + A[(long long)(t0 + c) * m + t0 + r] * yv[t0 + c];
+        part[g * TS + r] = acc;
         __syncthreads();
-        if (threadIdx.x < 64) {
+        if ((int)threadIdx.x < w) {
             int i = threadIdx.x;
-            cpx<R> yi = i < w ? yv[j0 + i] : czero<R>();
-            for (int c = w - 1; c >= 0; --c) {
-                if (i == c) yi = cdiv(yi, dg[c * TS_B + c]);
-                cpx<R> yc;
-                yc.re = __shfl(yi.re, c);
-                yc.im = __shfl(yi.im, c);
-                if (i < c) yi = cfms(yi, dg[c * TS_B + i], yc);
-            }
-            if (i < w) yv[j0 + i] = yi;
+            yv[t0 + i] = part[i] + part[TS + i] + part[2 * TS + i] + part[3 * TS + i];
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < j0; i += blockDim.x) {
-            cpx<R> acc = yv[i];
-            for (int c = 0; c < w; ++c) acc = cfms(acc, A[(long long)(j0 + c) * m + i], yv[j0 + c]);
-            yv[i] = acc;
+        for (int i = threadIdx.x; i < t0; i += blockDim.x) {
+            cpx<R> s = yv[i];
+            const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 8
+            for (int c = 0; c < w; ++c) s = cfms(s, col[(long long)c * m], yv[t0 + c]);
+            yv[i] = s;
         }
         __syncthreads();
     }
@@ -469,7 +588,7 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
                            op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
     }
     VIE_HIP(hipGetLastError());
-    size_t lds2 = (2 * (size_t)m + TS_B * TS_B) * sizeof(cpx<R>);
+    size_t lds2 = ((size_t)m + 4 * TS) * sizeof(cpx<R>);
     vie_lds_attr((const void *)k_block_solve<R>, lds2);
     {
         ProfScope ps("block_solve", s);
@@ -548,8 +667,8 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         VIE_HIP(hipMemcpyAsync(Mt.p, Mth.data(), sizeof(c128) * Mth.size(), hipMemcpyHostToDevice, s));
     } else {
         int tot = nbx * by * bz;
-        hipLaunchKernelGGL(k_homog, dim3((tot + 127) / 128), dim3(128), 0, s, op->M64.as<const c128>(), Mt.as<c128>(),
-                           dboxes.as<const int>(), nbx, op->nx, op->ny, by, bz, o->homog, flag.as<int>());
+        hipLaunchKernelGGL(k_homog, dim3(tot), dim3(256), 0, s, op->M64.as<const c128>(), Mt.as<c128>(),
+                           dboxes.as<const int>(), op->nx, op->ny, by, bz, o->homog, flag.as<int>());
         VIE_HIP(hipGetLastError());
         int hflag = 0;
         VIE_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));

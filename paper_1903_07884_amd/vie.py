@@ -177,6 +177,7 @@ class Preconditioner:
     """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
 
     def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, stream=None):
+        """``factor_prec``: VIE_C128 (FP64 solves) or VIE_C64 (mixed-precision solves)."""
         lib = load()
         self.op = op
         bx = None
