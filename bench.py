@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 METRIC = "time-to-1e-6 residual, mixed vs FP64 solve; matvec HBM GB/s; p50/p99"
 
 
@@ -38,26 +39,34 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def algorithmic_models(cfg, info, iters_total):
-    """Per-kernel algorithmic work per launch: (bound, amount, unit) with amount in bytes or flops."""
+def good_length(n):
+    """Smallest 2^a 3^b 5^c >= n (the circulant period the library uses)."""
+    L = max(1, n)
+    while True:
+        q = L
+        for p in (2, 3, 5):
+            while q % p == 0:
+                q //= p
+        if q == 1:
+            return L
+        L += 1
+
+
+def algorithmic_models(cfg, info, R, mode):
+    """Per-launch algorithmic bytes of the HBM-bound kernels (bound, bytes, unit)."""
     nx, ny, nz = cfg['grid']
     N = nx * ny * nz
-    c = 16  # bytes per complex128
+    v = 16 if mode == 'fp64' else 8      # vector / factor bytes per complex
     m = info['block_m']
     modes = info['modes']
     stored = info['stored_blocks']
-    Px = 1
-    while Px < 2 * nx - 1:
-        Px *= 2
-    Hx, Hy, Hz = Px // 2 + 1, ny + 1, nz + 1
-    khat = 6 * Hx * Hy * Hz * c
+    Hx, Hy, Hz = (good_length(2 * n - 1) // 2 + 1 for n in (nx, ny, nz))
+    khat = 6 * Hx * Hy * Hz * v
     return {
-        # every stored factor read once + r_hat in + z_hat out + permutation
-        'block_solve': ('hbm', stored * m * m * c + modes * (2 * m * c + 4 * m), 'bytes'),
-        # x in, y out, M, kernel transform (octant) -- split over the three passes by design bytes
-        'matvec': ('hbm', (3 * N + 3 * N + N) * c + khat, 'bytes'),
-        'precond_xfft': ('hbm', 2 * 3 * N * c, 'bytes'),
-        'precond_ixfft': ('hbm', 2 * 3 * N * c, 'bytes'),
+        # every stored factor read once + rhat in + zhat out + permutation, per right-hand side
+        'block_solve': ('hbm', stored * m * m * v + R * modes * (2 * m * v + 4 * m), 'bytes'),
+        # x in, y out and M per right-hand side, plus the octant kernel transform once
+        'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes'),
     }
 
 
@@ -69,6 +78,19 @@ def lu_flops(m, nblocks, nb=32):
         rest = m - j0 - w
         f += 8 * rest * rest * w
     return f * nblocks
+
+
+def workload_plan(cfg, tag):
+    """Solver settings per workload: precision mode, preconditioner boxes / homogenisation."""
+    nx, ny, nz = cfg['grid']
+    if tag == 3:   # Bragg: 16 equal x-segments, real part of the mean contrast, FP32 factors
+        seg = nx // 16
+        return dict(mode='mixed', homog='realmean', reduce_tol=None,
+                    boxes=[(i * seg, 0, 0, seg, ny, nz) for i in range(16)],
+                    label='16 x-boxes, real-mean contrast')
+    if tag == 4:   # coupler: one box over the full cross-section (contrast is x-invariant)
+        return dict(mode='mixed', homog='none', reduce_tol=None, boxes=None, label='full cross-section')
+    return dict(mode='fp64', homog='none', reduce_tol=None, boxes=None, label='full 1-level')
 
 
 def cpu_baseline(cfg, iters, restarts, seconds_budget=20.0):
@@ -178,29 +200,41 @@ def main():
     nx, ny, nz = grid
     kb = W.k_background()
     chi_d = torch.from_numpy(W.make_chi(cfg)).to(dev)
-    e_d = torch.from_numpy(W.make_sources(cfg, args.config).reshape(cfg['nrhs'], -1)[0].copy()).to(dev)
-    b_d = torch.empty_like(e_d)
-    x_d = torch.empty_like(e_d)
     stream = torch.cuda.current_stream()
 
-    def step(record):
+    R = cfg['nrhs']
+    e_d = torch.from_numpy(W.make_sources(cfg, args.config).reshape(R, -1).copy()).to(dev)
+    b_d = torch.empty_like(e_d)
+    x_d = torch.empty_like(e_d)
+    plan = workload_plan(cfg, args.config)
+
+    def step(record, mode=None, reduce_tol='default', boxes='default', proxy='product'):
+        mode = mode or plan['mode']
+        bxs = plan['boxes'] if boxes == 'default' else boxes
+        rt = plan['reduce_tol'] if reduce_tol == 'default' else reduce_tol
+        fp = vie.VIE_C64 if mode == 'mixed' else vie.VIE_C128
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
-        op = vie.Operator(grid, delta, kb, chi_d)
+        op = vie.Operator(grid, delta, kb, chi_d, build_c64=(mode == 'mixed'))
         ev[1].record(stream)
-        pc = vie.Preconditioner(op)
+        pc = vie.Preconditioner(op, homog=plan['homog'], boxes=bxs, reduce_tol=rt, factor_prec=fp, proxy=proxy)
         ev[2].record(stream)
-        op.rhs(e_d, b_d)
-        st = vie.solve(op, pc, b_d, x_d, tol=1e-6, restart=50)[0]
+        op.rhs(e_d, b_d, nrhs=R)
+        st = vie.solve(op, pc, b_d, x_d, nrhs=R, tol=1e-6, restart=50, mode=mode)
         ev[3].record(stream)
         info = pc.info()
         pc.close()
         op.close()
+        print('bench: %s solve done: %d iterations, relres %.3e' % (mode, max(q['iters'] for q in st),
+                                                                     max(q['relres'] for q in st)),
+              file=sys.stderr, flush=True)
         if record is not None:
             torch.cuda.synchronize()
             record.append(dict(create_ms=ev[0].elapsed_time(ev[1]), setup_ms=ev[1].elapsed_time(ev[2]),
-                               solve_ms=ev[2].elapsed_time(ev[3]), iters=st['iters'], restarts=st['restarts'],
-                               relres=st['relres'], status=st['status'], info=info))
+                               solve_ms=ev[2].elapsed_time(ev[3]),
+                               iters=max(q['iters'] for q in st), restarts=max(q['restarts'] for q in st),
+                               relres=max(q['relres'] for q in st),
+                               status=max(q['status'] for q in st), info=info, mode=mode))
         return st
 
     for _ in range(args.warmup):
@@ -224,8 +258,41 @@ def main():
     vie.profile_end()
     ms_per_step = 1000.0 * (t1 - t0) / args.steps
     last = recs[-1]
+    compare = {}
+    if plan['mode'] == 'fp64':
+        # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column
+        for label, kw in (('reduced_1e-3', dict(reduce_tol=1e-3)),
+                          ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre'))):
+            rr = []
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            step(rr, **kw)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            compare[label] = dict(ms=1000.0 * (tb - ta), iterations=rr[0]['iters'], relres=rr[0]['relres'],
+                                  breakdown_ms={k: rr[0][k] for k in ('create_ms', 'setup_ms', 'solve_ms')},
+                                  stored_blocks=rr[0]['info']['stored_blocks'])
+    if plan['mode'] == 'mixed':
+        # the same problem solved in plain FP64 (and, for the coupler, with the memory-reduced
+        # preconditioner), timed the same way, outside the main timed region
+        extra = ()
+        if args.config == 4:
+            extra = (('mixed_reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre')),)
+        if args.config == 3:
+            extra = (('mixed_single_box', dict(boxes=None)), ('fp64_single_box', dict(mode='fp64', boxes=None)))
+        for label, kw in (('fp64', dict(mode='fp64')),) + extra:
+            rr = []
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            step(rr, **kw)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            compare[label] = dict(ms=1000.0 * (tb - ta), iterations=rr[0]['iters'], relres=rr[0]['relres'],
+                                  breakdown_ms={k: rr[0][k] for k in ('create_ms', 'setup_ms', 'solve_ms')},
+                                  stored_blocks=rr[0]['info']['stored_blocks'])
+        compare['fp64_over_mixed_time'] = compare['fp64']['ms'] / ms_per_step
     info = last['info']
-    models = algorithmic_models(cfg, info, last['iters'])
+    models = algorithmic_models(cfg, info, R, plan['mode'])
 
     # dominant kernel and its roofline
     dom = max(names, key=lambda k: kern[k]['total_ms'])
@@ -234,8 +301,9 @@ def main():
         fl = lu_flops(info['block_m'], info['stored_blocks'])
         launches = max(1, kern[dom]['launches'])
         achieved = fl / (kern[dom]['total_ms'] * 1e-3) / 1e12
-        roof = dict(kernel=dom, bound='alu', achieved=achieved, peak=FP64_PEAK_TFLOPS, unit='TFLOP/s',
-                    frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
+        peak = FP64_PEAK_TFLOPS if plan['mode'] == 'fp64' else FP32_PEAK_TFLOPS
+        roof = dict(kernel=dom, bound='alu', achieved=achieved, peak=peak, unit='TFLOP/s',
+                    frac=achieved / peak, traffic=None,
                     per_launch_work='%.4g real flops summed over %d launches' % (fl, launches))
     elif dom in models:
         bound, amount, _ = models[dom]
@@ -261,11 +329,12 @@ def main():
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,
-        'dtype': 'c128',
+        'dtype': 'c128' if plan['mode'] == 'fp64' else 'c64+f64',
         'data': 'synthetic',
-        'config': {'workload': cfg['name'] + ', FP64, 1-level Chan-Olkin (%d blocks of %dx%d), GMRES(50) to 1e-6'
-                   % (info['stored_blocks'], info['block_m'], info['block_m']),
-                   'grid': list(grid), 'voxel_m': delta, 'nrhs': 1, 'precision': 'fp64'},
+        'config': {'workload': cfg['name'] + ', %s, 1-level Chan-Olkin %s (%d blocks of %dx%d), GMRES(50) to 1e-6'
+                   % (plan['mode'], plan['label'], info['stored_blocks'], info['block_m'], info['block_m']),
+                   'grid': list(grid), 'voxel_m': delta, 'nrhs': R, 'precision': plan['mode']},
+        'compare': compare or None,
         'time_to_solution_ms': ms_per_step,
         'breakdown_ms': {k: last[k] for k in ('create_ms', 'setup_ms', 'solve_ms')},
         'iterations': last['iters'], 'restarts': last['restarts'], 'relres': last['relres'],
@@ -277,7 +346,7 @@ def main():
         'roofline': roof,
         'kernel_sources': kernel_sources_digest(),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.config == 2:
         out['cpu_baseline'] = cpu_baseline(cfg, last['iters'], last['restarts'])
     print(json.dumps(out))
 

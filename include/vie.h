@@ -121,6 +121,10 @@ typedef struct {
     int32_t reduce;      /* 1 = memory-reduced 1-level preconditioner (Sec. 5.1.1) */
     double reduce_tol;   /* keep mode k iff |v_k|/||v||_inf > reduce_tol (paper: 1e-3) */
     int32_t factor_prec; /* vie_prec of the stored LU factors */
+    int32_t proxy;       /* column of the proxy entry of eq. proxy1, whose printed index
+                            "ceil(ny/2) ceil(nz/2)" is ambiguous: 0 = the 1-based linear
+                            cross-section index ceil(by/2)*ceil(bz/2) (y fastest); 1 = the
+                            cross-section centre voxel (ceil(by/2), ceil(bz/2)) */
 } vie_pc_opts;
 
 typedef struct {

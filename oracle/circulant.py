@@ -25,7 +25,9 @@ Readings (the paper is silent or ambiguous):
   (component slowest, then z, then y), so m = 3 ny nz.
 * Proxy entry "D_i(1, ceil(ny/2) ceil(nz/2))": row 1 is (x-component, y=0,
   z=0); the column is the 1-based linear cross-section index
-  ceil(ny/2)*ceil(nz/2) (y fastest) of the x-component.  It is read from the
+  ceil(ny/2)*ceil(nz/2) (y fastest) of the x-component (default reading), or,
+  as an alternative reading, the voxel (ceil(ny/2), ceil(nz/2)) at the
+  cross-section centre.  It is read from the
   Chan/DFT transform of the generator K alone (no M~, no identity), so it stays
   defined where M~ vanishes.  The keep test is strict (>), the central block is
   mode ceil(n/2) - 1 (0-based) and is always stored.
@@ -111,10 +113,21 @@ def chan_olkin_blocks(Koct, Mt, n, ny, nz):
     return D
 
 
-def proxy_values(Koct, n, ny, nz):
-    """v_k of eq. proxy1 (reading in the module header); returns v [n]."""
+def proxy_column(ny, nz, reading='product'):
+    """(y', z') of the proxy entry's column (x-component).
+
+    'product': the 1-based linear cross-section index ceil(ny/2)*ceil(nz/2), y fastest;
+    'centre' : the voxel (ceil(ny/2), ceil(nz/2)) (1-based), i.e. the cross-section centre.
+    """
+    if reading == 'centre':
+        return int(np.ceil(ny / 2.0)) - 1, int(np.ceil(nz / 2.0)) - 1
     col = int(np.ceil(ny / 2.0)) * int(np.ceil(nz / 2.0)) - 1   # 0-based linear index
-    yp, zp = col % ny, col // ny
+    return col % ny, col // ny
+
+
+def proxy_values(Koct, n, ny, nz, reading='product'):
+    """v_k of eq. proxy1 (reading in the module header); returns v [n]."""
+    yp, zp = proxy_column(ny, nz, reading)
     Ch = chan_transform(Koct, n, ny, nz, include_identity=False)
     return Ch[:, 0, 0, 0 - yp + ny - 1, 0 - zp + nz - 1]
 
@@ -132,11 +145,11 @@ def reduction_keep(v, tol):
 class BlockCirculantInverse:
     """z = C_B^{-1} r for one box (Sec. 4), optionally memory reduced (Sec. 5.1.1)."""
 
-    def __init__(self, Koct, Mt, n, ny, nz, reduce_tol=None):
+    def __init__(self, Koct, Mt, n, ny, nz, reduce_tol=None, proxy='product'):
         self.n, self.ny, self.nz = n, ny, nz
         D = chan_olkin_blocks(Koct, Mt, n, ny, nz)
         if reduce_tol is not None:
-            keep, centre = reduction_keep(proxy_values(Koct, n, ny, nz), reduce_tol)
+            keep, centre = reduction_keep(proxy_values(Koct, n, ny, nz, proxy), reduce_tol)
             self.keep, self.centre = keep, centre
             self.block_of_mode = np.where(keep, np.arange(n), centre)
         else:
@@ -169,7 +182,7 @@ class BlockedPreconditioner:
     'none', 'mode', 'mean', 'realmean' (Sec. 5.2), applied per box.
     """
 
-    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None):
+    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product'):
         from .contrast import homogenize
         nx, ny, nz = grid
         self.grid = grid
@@ -178,7 +191,7 @@ class BlockedPreconditioner:
         self.parts = []
         for (x0, y0, z0, bx, by, bz) in self.boxes:
             Mt = homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], homog)
-            self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol))
+            self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol, proxy))
 
     def apply(self, r):
         nx, ny, nz = self.grid

@@ -3,7 +3,7 @@
 #include <cstring>
 #include <new>
 
-#include "vie_internal.h"
+#include "fft_device.h"
 
 static thread_local std::string g_err;
 void vie_set_error(const std::string &msg) { g_err = msg; }
@@ -76,15 +76,20 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
         delete op;
         return st;
     };
-    if (2 * sizeof(c128) * op->Px > max_lds())
-        return fail(arg_error("vie_create: x extent too long for the LDS line transform (padded length " +
-                              std::to_string(op->Px) + ")"));
     if (6 * sizeof(c128) * op->Py * op->Pz > max_lds())
         return fail(arg_error("vie_create: cross-section too large for the LDS plane transform"));
     vie_status st;
     if ((st = op->fft.get(op->Px, &op->px)) < 0) return fail(st);
     if ((st = op->fft.get(op->Py, &op->py)) < 0) return fail(st);
     if ((st = op->fft.get(op->Pz, &op->pz)) < 0) return fail(st);
+    {
+        int thr;
+        size_t lds;
+        fft_line_shape(op->px, sizeof(c128), &thr, &lds);
+        if (lds > max_lds())
+            return fail(arg_error("vie_create: x extent too long for the LDS line transform (padded length " +
+                                  std::to_string(op->Px) + ")"));
+    }
     if ((st = op->M64.ensure(sizeof(c128) * N)) < 0) return fail(st);
     if ((st = op->M32.ensure(sizeof(c64) * N)) < 0) return fail(st);
     if ((st = op->gen.ensure(sizeof(c128) * 6 * N)) < 0) return fail(st);
@@ -159,6 +164,7 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     if (o.homog < VIE_HOMOG_NONE || o.homog > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown homog");
     if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64)
         return arg_error("precond_setup: unknown factor precision");
+    if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
     if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
         return arg_error("precond_setup: reduce_tol must be finite and >= 0");
     std::vector<int> boxes;
@@ -193,9 +199,15 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     if (!fft_supported_length(bx))
         return arg_error("precond_setup: box length " + std::to_string(bx) + " has a prime factor above " +
                          std::to_string(VIE_FFT_MAX_PRIME));
-    if (2 * sizeof(c128) * bx > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
-    if (((size_t)m + 4 * 64) * esz > max_lds())
-        return arg_error("precond_setup: cross-section block too large for the block solve");
+    {
+        FftPlan tmp;
+        if (op->fft.get(bx, &tmp) < 0) return VIE_EARG;
+        int thr;
+        size_t lds;
+        fft_line_shape(tmp, sizeof(c128), &thr, &lds);
+        if (lds > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
+    }
+    if (m > 1280) return arg_error("precond_setup: cross-section block (3*by*bz) above 1280 is not supported");
     vie_pc pc = new (std::nothrow) vie_pc_s();
     if (!pc) return VIE_EOOM;
     pc->op = op;

@@ -169,4 +169,94 @@ __device__ cpx<R> *fft_lds(cpx<R> *a, cpx<R> *b, const LdsLines &ln, const FftPl
     return src;
 }
 
+// In-place variant for radices 2..5: each thread keeps the inputs of up to FFT_BPT
+// butterflies in registers across a barrier, so one LDS buffer suffices (long lines).
+// Requires (L / smallest radix) * nlines <= FFT_BPT * blockDim.x.
+#define FFT_BPT 4
+template <class R, int P>
+__device__ __forceinline__ void stage_inplace(cpx<R> *buf, const LdsLines &ln, int L, int Ns, const cpx<R> *tw,
+                                              bool inv) {
+    const int nb = L / P;
+    const int total = nb * ln.nlines;
+    const int twstep = L / (Ns * P);
+    cpx<R> v[FFT_BPT][P];
+#pragma unroll
+    for (int q = 0; q < FFT_BPT; ++q) {
+        int t = threadIdx.x + q * blockDim.x;
+        if (t < total) {
+            int l = t / nb, j = t - l * nb;
+            int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
+            int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                cpx<R> a = buf[base + (j + r * nb) * ln.es];
+                v[q][r] = (r == 0 || k == 0) ? a : a * tw_at(tw, r * k * twstep, inv);
+            }
+            if (P == 2) bfly2(v[q]);
+            if (P == 3) bfly3(v[q], inv);
+            if (P == 4) bfly4(v[q], inv);
+            if (P == 5) bfly5(v[q], inv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < FFT_BPT; ++q) {
+        int t = threadIdx.x + q * blockDim.x;
+        if (t < total) {
+            int l = t / nb, j = t - l * nb;
+            int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
+            int k = j % Ns;
+            int d = (j / Ns) * Ns * P + k;
+#pragma unroll
+            for (int r = 0; r < P; ++r) buf[base + (d + r * Ns) * ln.es] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+__host__ __device__ inline bool fft_plan_inplace(const FftPlan &plan) {
+    if (plan.L > 2 * FFT_BPT * 1024) return false;  // radix-2 stage must fit 1024 threads
+    for (int i = 0; i < plan.nrad; ++i)
+        if (plan.rad[i] > 5) return false;
+    return true;
+}
+
+// Transform in place (plans with radices <= 5 only); caller syncs before.
+template <class R>
+__device__ void fft_lds_inplace(cpx<R> *buf, const LdsLines &ln, const FftPlan &plan, bool inv) {
+    const cpx<R> *tw = TwTable<R>::get(plan);
+    const int L = plan.L;
+    int Ns = 1;
+    for (int st = 0; st < plan.nrad; ++st) {
+        int P = plan.rad[st];
+        switch (P) {
+            case 2: stage_inplace<R, 2>(buf, ln, L, Ns, tw, inv); break;
+            case 3: stage_inplace<R, 3>(buf, ln, L, Ns, tw, inv); break;
+            case 4: stage_inplace<R, 4>(buf, ln, L, Ns, tw, inv); break;
+            default: stage_inplace<R, 5>(buf, ln, L, Ns, tw, inv); break;
+        }
+        Ns *= P;
+    }
+}
+
+// One line in LDS: in place when the plan allows (buffer of L), else ping-pong (2 L).
+template <class R>
+__device__ __forceinline__ cpx<R> *fft_line(cpx<R> *a, const FftPlan &plan, bool inv) {
+    LdsLines ln = {1, 0, 0, 1, 1};
+    if (fft_plan_inplace(plan)) {
+        fft_lds_inplace<R>(a, ln, plan, inv);
+        return a;
+    }
+    return fft_lds<R>(a, a + plan.L, ln, plan, inv);
+}
+
+// Launch shape of a one-line-per-workgroup transform: threads and LDS bytes.
+inline void fft_line_shape(const FftPlan &plan, size_t esz, int *threads, size_t *lds) {
+    int L = plan.L;
+    int t = 64;
+    while (t < 1024 && (long long)t * FFT_BPT * 2 < L) t *= 2;  // radix-2 worst case fits
+    *threads = t;
+    *lds = (fft_plan_inplace(plan) ? 1 : 2) * esz * (size_t)L;
+}
+
 extern __shared__ __align__(16) unsigned char vie_smem[];

@@ -93,13 +93,11 @@ template <class R>
 __global__ void k_fft_lines(cpx<R> *data, long long nl1, long long s1, long long s2, long long es,
                             FftPlan plan, int inv) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    cpx<R> *b = a + plan.L;
     long long l = blockIdx.x;
     cpx<R> *base = data + (l % nl1) * s1 + (l / nl1) * s2;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = base[i * es];
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    cpx<R> *res = fft_lds<R>(a, b, ln, plan, inv != 0);
+    cpx<R> *res = fft_line<R>(a, plan, inv != 0);
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) base[i * es] = res[i];
 }
 
@@ -148,9 +146,11 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
     };
     for (auto &ps : passes) {
         if (ps.p->L == 1) continue;
-        size_t lds = 2 * sizeof(c128) * ps.p->L;
+        size_t lds;
+        int thr;
+        fft_line_shape(*ps.p, sizeof(c128), &thr, &lds);
         vie_lds_attr((const void *)k_fft_lines<double>, lds);
-        hipLaunchKernelGGL(k_fft_lines<double>, dim3((unsigned)ps.nlines), dim3(block_for(ps.p->L)), lds, s,
+        hipLaunchKernelGGL(k_fft_lines<double>, dim3((unsigned)ps.nlines), dim3(thr), lds, s,
                            E.as<c128>(), ps.nl1, ps.s1, ps.s2, ps.es, *ps.p, 0);
         VIE_HIP(hipGetLastError());
     }
@@ -171,13 +171,11 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
 template <class R>
 __global__ void k_xfwd(const cpx<R> *x, cpx<R> *work, int nx, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    cpx<R> *b = a + plan.L;
     long long line = blockIdx.x;
     const cpx<R> *src = x + line * nx;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = i < nx ? src[i] : czero<R>();
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    cpx<R> *res = fft_lds<R>(a, b, ln, plan, false);
+    cpx<R> *res = fft_line<R>(a, plan, false);
     cpx<R> *dst = work + line * plan.L;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) dst[i] = res[i];
 }
@@ -259,13 +257,11 @@ template <class R>
 __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx<R> *y, int nx,
                        long long lines_per_comp_rhs_N, int nyz, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    cpx<R> *b = a + plan.L;
     long long line = blockIdx.x;
     const cpx<R> *src = work + line * plan.L;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    cpx<R> *res = fft_lds<R>(a, b, ln, plan, true);
+    cpx<R> *res = fft_line<R>(a, plan, true);
     long long yz = line % nyz;  // voxel row (z, y)
     const cpx<R> *xl = x + line * nx;
     const cpx<R> *ml = M + yz * nx;
@@ -284,12 +280,14 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     long long lines = 3LL * ny * nz * nrhs;
     VIE_CHECK(op->work.ensure(sizeof(cpx<R>) * lines * Px));
     cpx<R> *work = op->work.as<cpx<R>>();
-    size_t ldsx = 2 * sizeof(cpx<R>) * Px;
+    size_t ldsx;
+    int thx;
+    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx);
     vie_lds_attr((const void *)k_xfwd<R>, ldsx);
     vie_lds_attr((const void *)k_xinv<R>, ldsx);
     {
         ProfScope ps("matvec_xfwd", s);
-        hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, x, work, nx, op->px);
+        hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(thx), ldsx, s, x, work, nx, op->px);
     }
     VIE_HIP(hipGetLastError());
     size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
@@ -302,7 +300,7 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("matvec_xinv", s);
-        hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(block_for(Px)), ldsx, s, work, x, M, y, nx,
+        hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(thx), ldsx, s, work, x, M, y, nx,
                            0LL, ny * nz, op->px);
     }
     VIE_HIP(hipGetLastError());

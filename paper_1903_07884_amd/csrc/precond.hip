@@ -70,7 +70,6 @@ __global__ void __launch_bounds__(256) k_homog(const c128 *M, c128 *Mt, const in
 __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, int n, int by, int bz,
                              int identity, FftPlan plan) {
     c128 *a = reinterpret_cast<c128 *>(vie_smem);
-    c128 *b = a + n;
     const int ndy = 2 * by - 1, ndz = 2 * bz - 1;
     int seq = blockIdx.x;
     int c = seq / (ndy * ndz);
@@ -104,8 +103,7 @@ __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, 
         a[l] = v;
     }
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    c128 *res = fft_lds<double>(a, b, ln, plan, false);
+    c128 *res = fft_line<double>(a, plan, false);
     const long long stride_k = 6LL * ndz * ndy;
     for (int k = threadIdx.x; k < n; k += blockDim.x) Ch[k * stride_k + (long long)c * ndz * ndy + iz * ndy + iy] = res[k];
 }
@@ -456,7 +454,6 @@ template <class R>
 __global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int nx, int ny, int nz, int by,
                           int bz, int nboxes, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    cpx<R> *b = a + plan.L;
     const int n = plan.L, m = 3 * by * bz;
     long long line = blockIdx.x;  // ((rhs * nboxes + box) * m + row)
     int row = (int)(line % m);
@@ -467,8 +464,7 @@ __global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int n
     const cpx<R> *src = r + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    cpx<R> *res = fft_lds<R>(a, b, ln, plan, false);
+    cpx<R> *res = fft_line<R>(a, plan, false);
     cpx<R> *dst = work + line * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = res[i];
 }
@@ -478,7 +474,6 @@ template <class R>
 __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int nx, int ny, int nz, int by,
                            int bz, int nboxes, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    cpx<R> *b = a + plan.L;
     const int n = plan.L, m = 3 * by * bz;
     long long line = blockIdx.x;
     int row = (int)(line % m);
@@ -489,81 +484,202 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int
     const cpx<R> *src = work + line * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    LdsLines ln = {1, 0, 0, 1, 1};
-    cpx<R> *res = fft_lds<R>(a, b, ln, plan, true);
+    cpx<R> *res = fft_line<R>(a, plan, true);
     cpx<R> *dst = zv + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
     R sc = R(1) / R(n);
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
 }
 
-// One workgroup per (rhs, box, mode): z_k = U^{-1} L^{-1} P rhat_k in place in `work`.
-// Forward and backward substitution by 64-row tiles: the (pre-inverted) diagonal tile is
-// applied by four wavefronts, each summing a quarter of the columns, then the panel below
-// (above) is applied to the remaining rows; factors stream from HBM once, column-coalesced.
-template <class R>
+// One workgroup per (box, mode, chunk of RC right-hand sides):
+//   z_k = U^{-1} L^{-1} P rhat_k  in place in `work` for RC columns at once.
+// Thread t owns rows t, t + 256, ... (QR of them) and keeps their RC accumulators in
+// registers.  Forward and backward substitution run over 64-row tiles: the tile's owners
+// publish its rows to LDS, four wavefronts apply the pre-inverted diagonal tile (each a
+// quarter of its columns), and every thread then applies the tile's column panel to its
+// remaining rows.  Each factor entry is read once per chunk and used RC times; the factor
+// reads are coalesced along columns.  work element (rhs, box, row i, mode k) sits at
+// ((rhs * nboxes + box) * m + i) * n + k.
+template <class R, int QR, int RC>
 __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm,
-                                                     const int *block_of_mode, int m, int n, int nboxes) {
-    cpx<R> *yv = reinterpret_cast<cpx<R> *>(vie_smem);  // m
-    cpx<R> *part = yv + m;                              // 4 x TS
-    long long bid = blockIdx.x;  // (rhs * nboxes + box) * n + k
-    int k = (int)(bid % n);
-    long long rb = bid / n;
-    int box = (int)(rb % nboxes);
-    int sblk = block_of_mode[box * n + k];
+                                                     const int *block_of_mode, int m, int n, int nboxes, int nrhs) {
+    cpx<R> *yt = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][RC]
+    cpx<R> *part = yt + TS * RC;                        // [4][TS][RC]
+    const int k = blockIdx.x % n, box = blockIdx.x / n;
+    const int r0 = blockIdx.y * RC;
+    const int nr = min(RC, nrhs - r0);
+    const int sblk = block_of_mode[box * n + k];
     const cpx<R> *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
-    cpx<R> *base = work + rb * (long long)m * n + k;  // row i at base[i * n]
-    for (int i = threadIdx.x; i < m; i += blockDim.x) yv[i] = base[(long long)pm[i] * n];
-    __syncthreads();
-    const int g = threadIdx.x >> 6, r = threadIdx.x & 63;
-    // forward: unit lower L
+    const long long rstride = (long long)nboxes * m * n;
+    cpx<R> *base = work + (long long)box * m * n + k;
+    const int tid = threadIdx.x;
+    cpx<R> acc[QR][RC];
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+        int i = tid + 256 * q;
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+            acc[q][c] = (i < m && c < nr) ? base[(r0 + c) * rstride + (long long)pm[i] * n] : czero<R>();
+    }
+    const int g = tid >> 6, r = tid & 63;
+    // forward: unit lower L (diagonal tiles hold the strictly lower part of their inverse)
     for (int t0 = 0; t0 < m; t0 += TS) {
-        int w = min(TS, m - t0);
-        cpx<R> acc = czero<R>();
-        if (r < w)
-            for (int c = g; c < r; c += 4) acc = acc + A[(long long)(t0 + c) * m + t0 + r] * yv[t0 + c];
-        part[g * TS + r] = acc;
-        __syncthreads();
-        if ((int)threadIdx.x < w) {
-            int i = threadIdx.x;
-            yv[t0 + i] = yv[t0 + i] + part[i] + part[TS + i] + part[2 * TS + i] + part[3 * TS + i];
+        const int w = min(TS, m - t0);
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w)
+#pragma unroll
+                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
         }
         __syncthreads();
-        for (int i = t0 + w + threadIdx.x; i < m; i += blockDim.x) {
-            cpx<R> s = yv[i];
-            const cpx<R> *col = A + (long long)t0 * m + i;
-#pragma unroll 8
-            for (int c = 0; c < w; ++c) s = cfms(s, col[(long long)c * m], yv[t0 + c]);
-            yv[i] = s;
+        {
+            cpx<R> p[RC];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
+            if (r < w)
+                for (int cc = g; cc < r; cc += 4) {
+                    cpx<R> l = A[(long long)(t0 + cc) * m + t0 + r];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) p[c] = p[c] + l * yt[cc * RC + c];
+                }
+#pragma unroll
+            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
+        }
+        __syncthreads();
+        if (tid < w)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                yt[tid * RC + c] = yt[tid * RC + c] + part[tid * RC + c] + part[(TS + tid) * RC + c] +
+                                   part[(2 * TS + tid) * RC + c] + part[(3 * TS + tid) * RC + c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
+            } else if (i >= t0 + w && i < m) {
+                const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 4
+                for (int cc = 0; cc < w; ++cc) {
+                    cpx<R> l = col[(long long)cc * m];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], l, yt[cc * RC + c]);
+                }
+            }
         }
         __syncthreads();
     }
-    // backward: upper U
-    int ntile = (m + TS - 1) / TS;
+    // backward: upper U (diagonal tiles hold the upper part of their inverse)
+    const int ntile = (m + TS - 1) / TS;
     for (int tt = ntile - 1; tt >= 0; --tt) {
-        int t0 = tt * TS;
-        int w = min(TS, m - t0);
-        cpx<R> acc = czero<R>();
-        if (r < w)
-            for (int c = g; c < w; c += 4)
-                if (c >= r) acc = acc + A[(long long)(t0 + c) * m + t0 + r] * yv[t0 + c];
-        part[g * TS + r] = acc;
-        __syncthreads();
-        if ((int)threadIdx.x < w) {
-            int i = threadIdx.x;
-            yv[t0 + i] = part[i] + part[TS + i] + part[2 * TS + i] + part[3 * TS + i];
+        const int t0 = tt * TS;
+        const int w = min(TS, m - t0);
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w)
+#pragma unroll
+                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < t0; i += blockDim.x) {
-            cpx<R> s = yv[i];
-            const cpx<R> *col = A + (long long)t0 * m + i;
-#pragma unroll 8
-            for (int c = 0; c < w; ++c) s = cfms(s, col[(long long)c * m], yv[t0 + c]);
-            yv[i] = s;
+        {
+            cpx<R> p[RC];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
+            if (r < w)
+                for (int cc = g; cc < w; cc += 4)
+                    if (cc >= r) {
+                        cpx<R> u = A[(long long)(t0 + cc) * m + t0 + r];
+#pragma unroll
+                        for (int c = 0; c < RC; ++c) p[c] = p[c] + u * yt[cc * RC + c];
+                    }
+#pragma unroll
+            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
+        }
+        __syncthreads();
+        if (tid < w)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                yt[tid * RC + c] = part[tid * RC + c] + part[(TS + tid) * RC + c] + part[(2 * TS + tid) * RC + c] +
+                                   part[(3 * TS + tid) * RC + c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
+            } else if (i < t0) {
+                const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 4
+                for (int cc = 0; cc < w; ++cc) {
+                    cpx<R> u = col[(long long)cc * m];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], u, yt[cc * RC + c]);
+                }
+            }
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < m; i += blockDim.x) base[(long long)i * n] = yv[i];
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+        int i = tid + 256 * q;
+        if (i < m)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < nr) base[(r0 + c) * rstride + (long long)i * n] = acc[q][c];
+    }
+}
+
+#define VIE_MAX_QR 5
+// Columns per chunk: a power of two <= 8, bounded by the register budget of the accumulators.
+static int block_solve_rc(int m, int nrhs, size_t esz) {
+    int qr = (m + 255) / 256;
+    int budget = esz == sizeof(c128) ? 24 : 48;  // complex accumulators per thread
+    int rc = 1;
+    while (rc < 8 && rc < nrhs && qr * rc * 2 <= budget) rc *= 2;
+    return rc;
+}
+
+template <class R, int QR, int RC>
+static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F, const int *perm,
+                      const int *bom, int m, int n, int nboxes, int nrhs) {
+    hipLaunchKernelGGL((k_block_solve<R, QR, RC>), grid, dim3(256), lds, s, work, F, perm, bom, m, n, nboxes, nrhs);
+}
+
+template <class R, int QR>
+static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F,
+                         const int *perm, const int *bom, int m, int n, int nboxes, int nrhs) {
+    switch (rc) {
+        case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        case 2: launch_bs<R, QR, 2>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        case 4: launch_bs<R, QR, 4>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        default: launch_bs<R, QR, 8>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+    }
+}
+
+template <class R>
+static vie_status launch_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm, const int *bom, int m, int n,
+                                     int nboxes, int nrhs, hipStream_t s) {
+    const int qr = (m + 255) / 256;
+    if (qr > VIE_MAX_QR) {
+        vie_set_error("block size above 1280 is not supported by the block solve");
+        return VIE_EARG;
+    }
+    const int rc = block_solve_rc(m, nrhs, sizeof(cpx<R>));
+    dim3 grid((unsigned)(nboxes * n), (unsigned)((nrhs + rc - 1) / rc));
+    size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
+    switch (qr) {
+        case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        case 2: launch_bs_rc<R, 2>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        case 3: launch_bs_rc<R, 3>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        case 4: launch_bs_rc<R, 4>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+        default: launch_bs_rc<R, 5>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
+    }
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
 }
 
 // ---------------------------------------------------------------- host side
@@ -576,9 +692,9 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
     const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * n);
-    int thr = 64;
-    while (thr < 256 && thr * 4 < n) thr *= 2;
-    size_t lds = 2 * sizeof(cpx<R>) * n;
+    int thr;
+    size_t lds;
+    fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds);
     cpx<R> *work = pc->work.as<cpx<R>>();
     vie_lds_attr((const void *)k_box_fft<R>, lds);
     vie_lds_attr((const void *)k_box_ifft<R>, lds);
@@ -588,15 +704,11 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
                            op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
     }
     VIE_HIP(hipGetLastError());
-    size_t lds2 = ((size_t)m + 4 * TS) * sizeof(cpx<R>);
-    vie_lds_attr((const void *)k_block_solve<R>, lds2);
     {
         ProfScope ps("block_solve", s);
-        hipLaunchKernelGGL(k_block_solve<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * n)), dim3(256), lds2, s,
-                           work, pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(),
-                           pc->block_of_mode.as<const int>(), m, n, pc->nboxes);
+        VIE_CHECK(launch_block_solve<R>(work, pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(),
+                                        pc->block_of_mode.as<const int>(), m, n, pc->nboxes, nrhs, s));
     }
-    VIE_HIP(hipGetLastError());
     {
         ProfScope ps("precond_ixfft", s);
         hipLaunchKernelGGL(k_box_ifft<R>, dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, op->ny,
@@ -682,10 +794,11 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     DevBuf Ch;
     VIE_CHECK(Ch.ensure(sizeof(c128) * (size_t)n * 6 * ndy * ndz));
     {
-        int thr = 64;
-        while (thr < 256 && thr * 4 < n) thr *= 2;
-        vie_lds_attr((const void *)k_chan_table, 2 * sizeof(c128) * n);
-        hipLaunchKernelGGL(k_chan_table, dim3(6 * ndy * ndz), dim3(thr), 2 * sizeof(c128) * n, s, op->gen.as<const c128>(),
+        int thr;
+        size_t lds;
+        fft_line_shape(pc->pxb, sizeof(c128), &thr, &lds);
+        vie_lds_attr((const void *)k_chan_table, lds);
+        hipLaunchKernelGGL(k_chan_table, dim3(6 * ndy * ndz), dim3(thr), lds, s, op->gen.as<const c128>(),
                            Ch.as<c128>(), op->nx, op->ny, op->nz, n, by, bz, 1, pc->pxb);
         VIE_HIP(hipGetLastError());
     }
@@ -693,8 +806,15 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     std::vector<int> keep(n, 1);
     int centre = (n + 1) / 2 - 1;  // ceil(n/2) - 1
     if (o->reduce) {
-        int col = ((by + 1) / 2) * ((bz + 1) / 2) - 1;
-        int yp = col % by, zp = col / by;
+        int yp, zp;
+        if (o->proxy == 1) {
+            yp = (by + 1) / 2 - 1;
+            zp = (bz + 1) / 2 - 1;
+        } else {
+            int col = ((by + 1) / 2) * ((bz + 1) / 2) - 1;
+            yp = col % by;
+            zp = col / by;
+        }
         int iy = 0 - yp + by - 1, iz = 0 - zp + bz - 1;
         std::vector<c128> v(n);
         VIE_HIP(hipMemcpy2DAsync(v.data(), sizeof(c128), Ch.as<c128>() + (long long)iz * ndy + iy,

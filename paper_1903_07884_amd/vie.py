@@ -38,7 +38,8 @@ class CreateOpts(ctypes.Structure):
 
 class PcOpts(ctypes.Structure):
     _fields_ = [('homog', ctypes.c_int32), ('nboxes', ctypes.c_int32), ('boxes', ctypes.c_void_p),
-                ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32)]
+                ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32),
+                ('proxy', ctypes.c_int32)]
 
 
 class PcInfo(ctypes.Structure):
@@ -176,12 +177,14 @@ class Operator:
 class Preconditioner:
     """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
 
-    def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, stream=None):
-        """``factor_prec``: VIE_C128 (FP64 solves) or VIE_C64 (mixed-precision solves)."""
+    def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, proxy='product',
+                 stream=None):
+        """``factor_prec``: VIE_C128 (FP64 solves) or VIE_C64 (mixed-precision solves);
+        ``proxy``: 'product' or 'centre' reading of the memory-reduction proxy column."""
         lib = load()
         self.op = op
         bx = None
-        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec)
+        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, {'product': 0, 'centre': 1}[proxy])
         if boxes is not None:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
             o.nboxes = bx.shape[0]

@@ -133,6 +133,7 @@ PC_CASES = [
     # grid, chi kind, homog, boxes, reduce_tol
     ((64, 8, 4), 'uniform', 'none', None, None),
     ((64, 8, 4), 'uniform', 'none', None, 1e-3),
+    ((64, 8, 4), 'uniform', 'none', None, (1e-3, 'centre')),
     ((37, 5, 3), 'uniform', 'none', None, None),
     ((24, 6, 2), 'bragg', 'realmean', [(0, 0, 0, 12, 6, 2), (12, 0, 0, 12, 6, 2)], None),
     ((24, 6, 2), 'bragg', 'mean', [(0, 0, 0, 12, 6, 2), (12, 0, 0, 12, 6, 2)], 1e-2),
@@ -157,13 +158,16 @@ def _chi_kind(grid, kind):
 def test_precond_apply_matches_oracle(gpu_lib, case):
     import torch
     grid, kind, homog, boxes, tol = case
+    proxy = 'product'
+    if isinstance(tol, tuple):
+        tol, proxy = tol
     delta = 50e-9
     K = oracle_generator(grid, delta)
     chi = _chi_kind(grid, kind)
     M = OCT.contrast_from_chi(chi)
-    ref_pc = OC.BlockedPreconditioner(K, M, grid, boxes=boxes, homog=homog, reduce_tol=tol)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid, boxes=boxes, homog=homog, reduce_tol=tol, proxy=proxy)
     op = gpu_lib.Operator(grid, delta, KB, chi, generator=K)
-    pc = gpu_lib.Preconditioner(op, homog=homog, boxes=boxes, reduce_tol=tol)
+    pc = gpu_lib.Preconditioner(op, homog=homog, boxes=boxes, reduce_tol=tol, proxy=proxy)
     info = pc.info()
     n = 3 * int(np.prod(grid))
     r = W.random_field((2, n), 31)

@@ -198,3 +198,15 @@ def test_homogenisations():
         CT.homogenize(M, 'none')
     U = np.ones((2, 2, 3)) * (0.5 + 0.1j)
     assert np.allclose(CT.homogenize(U, 'none'), 0.5 + 0.1j)
+
+
+def test_proxy_centre_reading_location():
+    # centre reading: ny=16, nz=8 -> voxel (8, 4) 1-based -> y'=7, z'=3
+    assert C.proxy_column(16, 8, 'centre') == (7, 3)
+    assert C.proxy_column(16, 8, 'product') == (15, 1)
+    assert C.proxy_column(1, 1, 'product') == (0, 0) and C.proxy_column(1, 1, 'centre') == (0, 0)
+    K = np.zeros((6, 8, 16, 4), dtype=complex)
+    K[0, 3, 7, :] = np.array([1.0, -2.0, 0.5, 4.0])
+    v = C.proxy_values(K, 4, 16, 8, reading='centre')
+    t = np.array([4.0, 0.5, -2.0, 1.0, -2.0, 0.5, 4.0])
+    assert np.allclose(v, C.dft_matrix(4) @ C.chan(t))
