@@ -34,3 +34,24 @@ def test_binding_names_match_header():
     from paper_1903_07884_amd import vie
     assert sorted(vie.EXPORTS) == declared_functions()
     vie.load(LIB)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason='libvie.so not built')
+def test_argument_errors_before_device_work():
+    """Checks that return before any HIP call: usable without a GPU."""
+    from paper_1903_07884_amd import vie
+    lib = vie.load(LIB)
+    out = ctypes.c_void_p(123)
+    chi = (ctypes.c_double * 2)(0.0, 0.0)
+    for grid, dx, k in (((0, 1, 1), 1e-8, 1.0), ((2, -1, 1), 1e-8, 1.0), ((1, 1, 1), 0.0, 1.0),
+                        ((1, 1, 1), 1e-8, -1.0), ((1, 1, 1), float('nan'), 1.0)):
+        g = (ctypes.c_int32 * 3)(*grid)
+        st = lib.vie_create(g, dx, k, ctypes.cast(chi, ctypes.c_void_p), None, None, ctypes.byref(out))
+        assert st == -1 and out.value is None
+        assert lib.vie_last_error().decode().startswith('vie_create')
+    assert lib.vie_create(None, 1e-8, 1.0, None, None, None, ctypes.byref(out)) == -1
+    assert lib.vie_matvec(None, None, None, 1, 0, None) == -1
+    assert lib.precond_apply(None, None, None, 1, 0, None) == -1
+    assert lib.vie_solve(None, None, None, None, 1, None, None, None) == -1
+    assert lib.precond_setup(None, None, None, ctypes.byref(out)) == -1 and out.value is None
+    assert lib.vie_destroy(None) == 0 and lib.precond_destroy(None) == 0

@@ -1,0 +1,160 @@
+"""Error paths, invariants and the uniform-waveguide regression on the GPU, through the C ABI.
+
+Failure handling is forced from the host (invalid inputs, a generator injected
+to make a preconditioner block exactly singular, a small iteration cap); no
+kernel is made to fault.
+"""
+import numpy as np
+import pytest
+
+from paper_1903_07884_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KB = W.k_background()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_nonfinite_inputs(gpu_lib):
+    import torch
+    grid = (8, 2, 2)
+    chi = W.waveguide(grid)
+    bad = chi.copy()
+    bad[0, 0, 3] = np.nan
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Operator(grid, 50e-9, KB, bad)
+    assert e.value.status == -1 and 'non-finite' in str(e.value)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Operator(grid, 50e-9, KB, _dev(bad))          # device contrast: checked by a kernel
+    assert e.value.status == -1
+    minus_one = chi.copy()
+    minus_one[1, 1, 1] = -1.0
+    with pytest.raises(gpu_lib.VieError):
+        gpu_lib.Operator(grid, 50e-9, KB, minus_one)
+    op = gpu_lib.Operator(grid, 50e-9, KB, chi)
+    b = W.random_field((3 * 32,), 1)
+    b[5] = np.inf
+    bd = _dev(b)
+    xd = torch.zeros_like(bd)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.solve(op, None, bd, xd)
+    assert e.value.status == -5
+
+
+def test_singular_block_reported(gpu_lib):
+    """1x1 cross-section, K^{xx} = delta_{d0}, M~ = 1/2: D_k^{xx} = 1 - (1/2)(1 + 1) = 0 for every mode."""
+    grid = (4, 1, 1)
+    K = np.zeros((6, 1, 1, 4), dtype=complex)
+    K[0, 0, 0, 0] = 1.0
+    chi = np.ones((1, 1, 4), dtype=complex)        # M = chi / (1 + chi) = 1/2
+    op = gpu_lib.Operator(grid, 50e-9, KB, chi, generator=K)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Preconditioner(op)
+    assert e.value.status == -4 and 'zero pivot' in str(e.value)
+
+
+def test_iteration_cap_returns_not_converged(gpu_lib):
+    import torch
+    cfg = W.CONFIGS[1]
+    op = gpu_lib.Operator(cfg['grid'], cfg['delta'], KB, W.make_chi(cfg))
+    e = _dev(W.make_sources(cfg, 1)[0].reshape(-1))
+    b = torch.empty_like(e)
+    op.rhs(e, b)
+    x = torch.zeros_like(b)
+    st = gpu_lib.solve(op, None, b, x, tol=1e-6, maxit=7)[0]
+    assert st['status'] == 1 and st['iters'] == 7 and st['relres'] > 1e-6
+    # restart from the returned iterate: the solve continues and converges
+    st2 = gpu_lib.solve(op, None, b, x, tol=1e-6, x0_given=True)[0]
+    assert st2['status'] == 0 and st2['relres'] <= 1e-6
+
+
+def test_zero_rhs_and_exact_initial_guess(gpu_lib):
+    import torch
+    grid = (16, 4, 2)
+    op = gpu_lib.Operator(grid, 50e-9, KB, W.waveguide(grid))
+    pc = gpu_lib.Preconditioner(op)
+    z = torch.zeros(3 * 128, dtype=torch.complex128, device='cuda')
+    x = torch.ones_like(z)
+    st = gpu_lib.solve(op, pc, z, x)[0]
+    assert st['iters'] == 0 and st['status'] == 0 and float(x.abs().max()) == 0.0
+    b = _dev(W.random_field((3 * 128,), 2))
+    x = torch.zeros_like(b)
+    gpu_lib.solve(op, pc, b, x, tol=1e-12)
+    st = gpu_lib.solve(op, pc, b, x, tol=1e-10, x0_given=True)[0]
+    assert st['iters'] == 0 and st['relres'] <= 1e-10
+
+
+def test_argument_errors(gpu_lib):
+    import torch
+    grid = (8, 4, 2)
+    op = gpu_lib.Operator(grid, 50e-9, KB, W.waveguide(grid))
+    cases = [
+        lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 9, 4, 2)]),                     # outside
+        lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (2, 0, 0, 4, 4, 2)]),  # overlap
+        lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (4, 0, 0, 3, 4, 2)]),  # shapes
+        lambda: gpu_lib.Preconditioner(op, reduce_tol=-1.0),
+        lambda: gpu_lib.Preconditioner(op, homog='none', boxes=None, factor_prec=7),
+    ]
+    for f in cases:
+        with pytest.raises(gpu_lib.VieError) as e:
+            f()
+        assert e.value.status == -1
+    chi = W.waveguide((24, 6, 2))
+    chi[:, :, ::3] = 0.0                                # contrast varies along x
+    op2 = gpu_lib.Operator((24, 6, 2), 25e-9, KB, chi)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Preconditioner(op2, homog='none')      # contrast varies along x
+    assert e.value.status == -1 and 'x' in str(e.value)
+    b = torch.zeros(op.n, dtype=torch.complex128, device='cuda')
+    b[0] = 1
+    x = torch.zeros_like(b)
+    with pytest.raises(gpu_lib.VieError):
+        gpu_lib.solve(op, None, b, x, restart=500)
+    with pytest.raises(gpu_lib.VieError):
+        gpu_lib.solve(op, None, b, x, mode='mixed')       # operator built without complex64
+    pc = gpu_lib.Preconditioner(op)
+    op32 = gpu_lib.Operator(grid, 50e-9, KB, W.waveguide(grid), build_c64=True)
+    with pytest.raises(gpu_lib.VieError):
+        gpu_lib.solve(op, pc, b, x, mode='mixed')          # FP64 factors in a mixed solve
+    with pytest.raises(gpu_lib.VieError):
+        op.matvec(b, b)                                   # overlapping x and y
+    with pytest.raises(gpu_lib.VieError):
+        op.matvec(b.to(torch.complex64), torch.empty(op.n, dtype=torch.complex64, device='cuda'))
+    y32 = torch.empty(op.n, dtype=torch.complex64, device='cuda')
+    op32.matvec(b.to(torch.complex64), y32)
+
+
+def test_zero_contrast_matvec_is_identity(gpu_lib):
+    import torch
+    grid = (24, 6, 3)
+    op = gpu_lib.Operator(grid, 25e-9, KB, np.zeros((3, 6, 24), dtype=complex))
+    x = _dev(W.random_field((op.n,), 3))
+    y = torch.empty_like(x)
+    op.matvec(x, y)
+    assert torch.equal(x, y)
+
+
+def test_preconditioned_iterations_flat_in_length(gpu_lib):
+    """Sec. 5.1: with the 1-level preconditioner the count does not grow with the guide length."""
+    import torch
+    its, its_none = [], []
+    for nx in (128, 256, 512, 1024):
+        cfg = dict(grid=(nx, 16, 8), delta=25e-9, nrhs=1, geometry='waveguide', wy=0.2e-6, wz=0.1e-6)
+        op = gpu_lib.Operator(cfg['grid'], cfg['delta'], KB, W.make_chi(cfg))
+        pc = gpu_lib.Preconditioner(op)
+        e = _dev(W.make_sources(cfg, 2)[0].reshape(-1))
+        b = torch.empty_like(e)
+        op.rhs(e, b)
+        x = torch.zeros_like(b)
+        its.append(gpu_lib.solve(op, pc, b, x, tol=1e-6)[0]['iters'])
+        if nx <= 512:
+            x.zero_()
+            its_none.append(gpu_lib.solve(op, None, b, x, tol=1e-6, maxit=3000)[0]['iters'])
+    print('preconditioned iterations', its, 'unpreconditioned', its_none)
+    assert max(its) - min(its) <= 4
+    assert its_none[0] < its_none[1] < its_none[2]
+    assert min(its_none) > 2 * max(its)
