@@ -70,6 +70,24 @@ def algorithmic_models(cfg, info, R, mode):
     }
 
 
+def counter_traffic(kernel, workload_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the sources."""
+    path = os.path.join(ROOT, 'profiles', '%s_c%d_counters.txt' % (kernel, workload_tag))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if '=' in line and not line.startswith('#'):
+            k, v = line.split('=', 1)
+            vals[k.strip()] = v.strip()
+    if vals.get('kernel_sources') != kernel_sources_digest():
+        return None
+    try:
+        return float(vals['hbm_bytes_per_launch'])
+    except (KeyError, ValueError):
+        return None
+
+
 def lu_flops(m, nblocks, nb=32):
     """Real flops of the trailing updates of a right-looking LU (8 per complex multiply-add)."""
     f = 0
@@ -182,6 +200,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--config', type=int, default=2)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--copy-probe', type=int, default=0,
+                    help='also run one plain device copy of this many bytes (calibrates HBM counters)')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU sharding is '
@@ -237,6 +257,13 @@ def main():
                                status=max(q['status'] for q in st), info=info, mode=mode))
         return st
 
+    if args.copy_probe:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(None)
     torch.cuda.synchronize()
@@ -249,7 +276,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     names = ['generator', 'matvec_xfwd', 'matvec_plane', 'matvec_xinv', 'precond_xfft', 'block_solve',
-             'precond_ixfft', 'lu_panel', 'lu_swap_trsm', 'lu_update', 'arnoldi_dots', 'arnoldi_update']
+             'precond_ixfft', 'lu_panel', 'lu_swap_trsm', 'lu_update', 'lu_invert_diag', 'arnoldi_dots',
+             'arnoldi_update']
     kern = {}
     for nm in names:
         ms, cnt = vie.profile_kernel(nm)
@@ -310,7 +338,8 @@ def main():
         avg_s = kern[dom]['avg_us'] * 1e-6
         achieved = amount / avg_s / 1e9
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=HBM_PEAK_GBS, unit='GB/s',
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, per_launch_bytes=amount)
+                    frac=achieved / HBM_PEAK_GBS, traffic=counter_traffic(dom, args.config),
+                    per_launch_bytes=amount)
     else:
         roof = dict(kernel=dom, bound='alu', achieved=None, peak=FP64_PEAK_TFLOPS, unit='TFLOP/s', frac=None,
                     traffic=None)

@@ -186,8 +186,8 @@ vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
  * kernel name, the summed duration in milliseconds and the number of
  * launches; vie_profile_end() stops recording.  Names: "generator",
  * "matvec_xfwd", "matvec_plane", "matvec_xinv", "precond_xfft", "block_solve",
- * "precond_ixfft", "lu_panel", "lu_swap_trsm", "lu_update", "arnoldi_dots",
- * "arnoldi_update".  Recording adds two event records per launch. */
+ * "precond_ixfft", "lu_panel", "lu_swap_trsm", "lu_update", "lu_invert_diag",
+ * "arnoldi_dots", "arnoldi_update".  Recording adds two event records per launch. */
 vie_status vie_profile_begin(void);
 vie_status vie_profile_kernel(const char *name, double *total_ms, int64_t *launches);
 vie_status vie_profile_end(void);

@@ -97,13 +97,15 @@ __device__ __forceinline__ c128 block_sum(c128 v, c128 *red) {
 }
 
 // far field order by Chebyshev distance D >= 2
+// The integrand's nearest complex singularity sits about 2D unit cells away, so the
+// tensor rule error falls like (4D)^(-2p): p = 4 already reaches 1e-16 beyond D = 24.
 __device__ __forceinline__ int far_order(int D) {
     if (D <= 2) return 14;
     if (D <= 3) return 10;
-    if (D <= 5) return 9;
+    if (D <= 5) return 8;
     if (D <= 11) return 7;
-    if (D <= 23) return 6;
-    return 5;
+    if (D <= 23) return 5;
+    return 4;
 }
 
 // ---- near field: generic piecewise integrator -----------------------------------
@@ -216,56 +218,78 @@ __device__ c128 integrate(const Wt *w, int dim, double h2, bool singular, double
     return block_sum(acc, red);
 }
 
-__global__ void __launch_bounds__(GEN_THREADS)
-k_generator(c128 *gen, int nx, int ny, int nz, double kappa) {
-    __shared__ c128 red[GEN_THREADS];
+__device__ __forceinline__ c128 wave_sum64(c128 v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        v.re += __shfl_down(v.re, off);
+        v.im += __shfl_down(v.im, off);
+    }
+    return v;
+}
+
+// Far offsets (some |d_a| >= 2): one wavefront per offset, volume form, all six components.
+__global__ void __launch_bounds__(64) k_generator_far(c128 *gen, int nx, int ny, int nz, double kappa) {
     long long N = (long long)nx * ny * nz;
     long long o = blockIdx.x;
     int dx = (int)(o % nx), dy = (int)((o / nx) % ny), dz = (int)(o / ((long long)nx * ny));
     int d[3] = {dx, dy, dz};
     int D = max(dx, max(dy, dz));
-    c128 out[6];
-    if (D >= 2) {
-        int p = far_order(D);
-        const double *gx = gl_node + p * (p - 1) / 2, *gw = gl_wt + p * (p - 1) / 2;
-        int p3 = p * p * p;
-        c128 acc[6];
-        for (int c = 0; c < 6; ++c) acc[c] = czero<double>();
-        for (int t = threadIdx.x; t < 8 * p3; t += GEN_THREADS) {
-            int cell = t / p3, r = t % p3;
-            double x[3], wq = 1.0;
-            for (int a = 0; a < 3; ++a) {
-                int i = r % p;
-                r /= p;
-                double lo = d[a] - 1 + ((cell >> a) & 1);
-                x[a] = lo + gx[i];
-                wq *= gw[i] * (1.0 - fabs(x[a] - d[a]));
-            }
-            double R2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-            double R = sqrt(R2);
-            double s, c;
-            sincos(kappa * R, &s, &c);
-            double f = wq / (4.0 * M_PI * R2 * R);
-            c128 e = mk(c * f, -s * f);              // exp(-j kappa R)/(4 pi R^3) * weight
-            c128 A = mk(1.0, kappa * R);             // 1 + j kappa R
-            double k2R2 = kappa * kappa * R2;
-            double rh[3] = {x[0] / R, x[1] / R, x[2] / R};
-            // a == b: e [ (3 r_a^2 - 1) A - k2R2 r_a^2 + k2R2 ]
-            for (int a = 0; a < 3; ++a) {
-                double q = 3.0 * rh[a] * rh[a] - 1.0;
-                c128 br = mk(q * A.re - k2R2 * rh[a] * rh[a] + k2R2, q * A.im);
-                acc[a] = acc[a] + e * br;
-            }
-            // a != b: e r_a r_b (3 A - k2R2)
-            const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-            for (int k = 0; k < 3; ++k) {
-                double rr = rh[pa[k]] * rh[pb[k]];
-                c128 br = mk(rr * (3.0 * A.re - k2R2), rr * 3.0 * A.im);
-                acc[3 + k] = acc[3 + k] + e * br;
-            }
+    if (D < 2) return;  // near offsets: k_generator_near
+    int p = far_order(D);
+    const double *gx = gl_node + p * (p - 1) / 2, *gw = gl_wt + p * (p - 1) / 2;
+    int p3 = p * p * p;
+    c128 acc[6];
+    for (int c = 0; c < 6; ++c) acc[c] = czero<double>();
+    for (int t = threadIdx.x; t < 8 * p3; t += 64) {
+        int cell = t / p3, r = t % p3;
+        double x[3], wq = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            int i = r % p;
+            r /= p;
+            double lo = d[a] - 1 + ((cell >> a) & 1);
+            x[a] = lo + gx[i];
+            wq *= gw[i] * (1.0 - fabs(x[a] - d[a]));
         }
-        for (int c = 0; c < 6; ++c) out[c] = block_sum(acc[c], red);
-    } else {
+        double R2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        double R = sqrt(R2);
+        double sn, cs;
+        sincos(kappa * R, &sn, &cs);
+        double f = wq / (4.0 * M_PI * R2 * R);
+        c128 e = mk(cs * f, -sn * f);            // exp(-j kappa R)/(4 pi R^3) * weight
+        c128 A = mk(1.0, kappa * R);             // 1 + j kappa R
+        double k2R2 = kappa * kappa * R2;
+        double rh[3] = {x[0] / R, x[1] / R, x[2] / R};
+        for (int a = 0; a < 3; ++a) {            // a == b: e [(3 r_a^2 - 1) A - k2R2 r_a^2 + k2R2]
+            double q = 3.0 * rh[a] * rh[a] - 1.0;
+            c128 br = mk(q * A.re - k2R2 * rh[a] * rh[a] + k2R2, q * A.im);
+            acc[a] = acc[a] + e * br;
+        }
+        const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+        for (int k = 0; k < 3; ++k) {            // a != b: e r_a r_b (3 A - k2R2)
+            double rr = rh[pa[k]] * rh[pb[k]];
+            c128 br = mk(rr * (3.0 * A.re - k2R2), rr * 3.0 * A.im);
+            acc[3 + k] = acc[3 + k] + e * br;
+        }
+    }
+    for (int c = 0; c < 6; ++c) acc[c] = wave_sum64(acc[c]);
+    // off-diagonal blocks are odd in their two axes: exactly zero at zero offset there
+    if (dx == 0 || dy == 0) acc[3] = czero<double>();
+    if (dx == 0 || dz == 0) acc[4] = czero<double>();
+    if (dy == 0 || dz == 0) acc[5] = czero<double>();
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) gen[c * N + o] = acc[c];
+}
+
+// Touching offsets d in {0,1}^3 (the support of the overlap weights reaches the singular
+// point): face form.  One workgroup per such offset.
+__global__ void __launch_bounds__(GEN_THREADS) k_generator_near(c128 *gen, int nx, int ny, int nz, double kappa) {
+    __shared__ c128 red[GEN_THREADS];
+    long long N = (long long)nx * ny * nz;
+    int dx = blockIdx.x & 1, dy = (blockIdx.x >> 1) & 1, dz = (blockIdx.x >> 2) & 1;
+    if (dx >= nx || dy >= ny || dz >= nz) return;
+    long long o = ((long long)dz * ny + dy) * nx + dx;
+    int d[3] = {dx, dy, dz};
+    c128 out[6];
+    {
         const int p = 14, ps = 16;
         Wt w3[3] = {{0, (double)dx}, {0, (double)dy}, {0, (double)dz}};
         c128 I3 = integrate(w3, 3, 0.0, true, kappa, p, ps, red);
@@ -297,7 +321,6 @@ k_generator(c128 *gen, int nx, int ny, int nz, double kappa) {
             out[3 + k] = mk(-tot.re, -tot.im);
         }
     }
-    // off-diagonal blocks are odd in their two axes: exactly zero at zero offset there
     if (dx == 0 || dy == 0) out[3] = czero<double>();
     if (dx == 0 || dz == 0) out[4] = czero<double>();
     if (dy == 0 || dz == 0) out[5] = czero<double>();
@@ -313,8 +336,11 @@ vie_status launch_generator(vie_op op, hipStream_t s) {
         return VIE_EARG;
     }
     ProfScope ps("generator", s);
-    hipLaunchKernelGGL(k_generator, dim3((unsigned)N), dim3(GEN_THREADS), 0, s, op->gen.as<c128>(),
-                       op->nx, op->ny, op->nz, op->kappa);
+    hipLaunchKernelGGL(k_generator_far, dim3((unsigned)N), dim3(64), 0, s, op->gen.as<c128>(), op->nx, op->ny,
+                       op->nz, op->kappa);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_generator_near, dim3(8), dim3(GEN_THREADS), 0, s, op->gen.as<c128>(), op->nx, op->ny,
+                       op->nz, op->kappa);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }

@@ -180,7 +180,9 @@ __global__ void k_xfwd(const cpx<R> *x, cpx<R> *work, int nx, FftPlan plan) {
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) dst[i] = res[i];
 }
 
-// pass 2: one workgroup per (x-frequency, rhs).
+// pass 2: one workgroup per (PLANE_KB consecutive x-frequencies, rhs); the planes are
+// processed one after another so the cache lines of the strided gathers are reused.
+#define PLANE_KB 1
 template <class R>
 __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hx, int Hy, int Hz,
                         FftPlan py, FftPlan pz) {
@@ -188,8 +190,11 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
     const int plane = Py * Pz;
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
     cpx<R> *b = a + 3 * plane;
-    const int kx = blockIdx.x;
+    for (int kk = 0; kk < PLANE_KB; ++kk) {
+    const int kx = blockIdx.x * PLANE_KB + kk;
+    if (kx >= Px) break;
     cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
+    __syncthreads();
     for (int i = threadIdx.x; i < 6 * plane; i += blockDim.x) a[i] = czero<R>();
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * ny * nz; i += blockDim.x) {
@@ -250,6 +255,7 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
         int y = i % ny, z = (i / ny) % nz, c = i / (ny * nz);
         base[(long long)i * Px] = buf[c * plane + z * Py + y];
     }
+    }
 }
 
 // pass 3: one workgroup per x-line; inverse FFT, crop, y = x - M (x + K x).
@@ -294,7 +300,7 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     vie_lds_attr((const void *)k_plane<R>, ldsp);
     {
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane<R>, dim3(Px, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
+        hipLaunchKernelGGL(k_plane<R>, dim3((Px + PLANE_KB - 1) / PLANE_KB, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
                            op->Hz, op->py, op->pz);
     }
     VIE_HIP(hipGetLastError());

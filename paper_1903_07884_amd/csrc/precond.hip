@@ -238,107 +238,286 @@ __global__ void __launch_bounds__(256) k_lu_panel(cpx<R> *A, int *ipiv, int *inf
     }
 }
 
+// Register-resident panel (1024 threads): thread t holds column t >> 5 of the panel for the
+// local rows (t & 31) + 32 q, q < QS.  Per column: pivot search by the 32 lanes that hold it
+// (half-wavefront shuffles), row interchange through LDS, multipliers published to LDS, and
+// the rank-1 update of the remaining panel columns in registers.  No global traffic between
+// the panel load and the panel store.
+template <class R, int QS>
+__global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
+    cpx<R> *lcol = reinterpret_cast<cpx<R> *>(vie_smem);  // [m - j0] multipliers of the current column
+    __shared__ cpx<R> rj[LU_NB], rp[LU_NB];
+    __shared__ int sp;
+    __shared__ R spv;
+    const int t = threadIdx.x, c = t >> 5, g = t & 31;
+    const int mrem = m - j0;
+    cpx<R> *a = A + (long long)blockIdx.x * m * m;
+    int *piv = ipiv + (long long)blockIdx.x * m;
+    cpx<R> v[QS];
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+        int li = g + 32 * q;
+        v[q] = (c < w && li < mrem) ? a[(long long)(j0 + c) * m + j0 + li] : czero<R>();
+    }
+    for (int jj = 0; jj < w; ++jj) {
+        if (c == jj) {
+            R best = R(-1);
+            int bi = jj;
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                int li = g + 32 * q;
+                R val = cabs2(v[q]);
+                if (li >= jj && li < mrem && val > best) {
+                    best = val;
+                    bi = li;
+                }
+            }
+            for (int off = 16; off > 0; off >>= 1) {
+                R ov = __shfl_xor(best, off);
+                int oi = __shfl_xor(bi, off);
+                if (ov > best || (ov == best && oi < bi)) {
+                    best = ov;
+                    bi = oi;
+                }
+            }
+            if (g == 0) {
+                sp = bi;
+                spv = best;
+            }
+        }
+        __syncthreads();
+        const int p = sp;
+        const R pv = spv;
+        if (pv == R(0)) {
+            if (t == 0) {
+                piv[j0 + jj] = j0 + jj;
+                if (info[blockIdx.x] == 0) info[blockIdx.x] = j0 + jj + 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        // row interchange jj <-> p within the panel
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            int li = g + 32 * q;
+            if (c < w && li == jj) rj[c] = v[q];
+            if (c < w && li == p) rp[c] = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            int li = g + 32 * q;
+            if (c < w && li == jj) v[q] = rp[c];
+            else if (c < w && li == p) v[q] = rj[c];
+        }
+        // new row jj is rp[]; pivot rp[jj]
+        cpx<R> pivv = rp[jj];
+        R d = cabs2(pivv);
+        cpx<R> inv = mk(pivv.re / d, -pivv.im / d);
+        if (c == jj)
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                int li = g + 32 * q;
+                if (li > jj && li < mrem) {
+                    v[q] = v[q] * inv;
+                    lcol[li] = v[q];
+                }
+            }
+        __syncthreads();
+        if (c > jj && c < w) {
+            cpx<R> u = rp[c];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                int li = g + 32 * q;
+                if (li > jj && li < mrem) v[q] = cfms(v[q], lcol[li], u);
+            }
+        }
+        if (t == 0) piv[j0 + jj] = j0 + p;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+        int li = g + 32 * q;
+        if (c < w && li < mrem) a[(long long)(j0 + c) * m + j0 + li] = v[q];
+    }
+}
+
 // Row interchanges of the panel applied to the other columns, and for columns right of the
 // panel U12 = L11^{-1} A12.  One workgroup per (64-column tile, block): rows [j0, j0 + w) of
 // the tile are staged in LDS with coalesced loads; interchanges with rows below the panel are
 // exchanged with global memory.
+// L11^{-1} of the panel [j0, j0 + w) (unit lower, strictly lower part stored) into Linv[block],
+// one workgroup per block, lane jc forming column jc from an LDS copy of L11.
 template <class R>
-__global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *ipiv, int m, int j0, int w) {
-    __shared__ cpx<R> T[LU_NB][65];
-    __shared__ cpx<R> L11[LU_NB][LU_NB + 1];
-    __shared__ int pv[LU_NB];
-    const int c0 = blockIdx.x * 64;
-    cpx<R> *a = A + (long long)blockIdx.y * m * m;
-    if ((int)threadIdx.x < w) pv[threadIdx.x] = ipiv[(long long)blockIdx.y * m + j0 + threadIdx.x];
-    for (int e = threadIdx.x; e < w * 64; e += blockDim.x) {
-        int r = e % w, c = e / w, col = c0 + c;
-        bool live = col < m && !(col >= j0 && col < j0 + w);
-        T[r][c] = live ? a[(long long)col * m + j0 + r] : czero<R>();
-    }
+__global__ void __launch_bounds__(64) k_lu_linv(const cpx<R> *A, cpx<R> *Linv, int m, int j0, int w) {
+    __shared__ cpx<R> L[LU_NB][LU_NB + 1];
+    __shared__ cpx<R> X[LU_NB][LU_NB + 1];
+    const cpx<R> *a = A + (long long)blockIdx.x * m * m;
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
         int r = e % w, c = e / w;
-        L11[r][c] = a[(long long)(j0 + c) * m + j0 + r];
+        L[r][c] = a[(long long)(j0 + c) * m + j0 + r];
+        X[r][c] = czero<R>();
     }
     __syncthreads();
-    const int c = threadIdx.x;
-    const int col = c0 + c;
-    const bool live = c < 64 && col < m && !(col >= j0 && col < j0 + w);
-    if (live) {
-        for (int j = 0; j < w; ++j) {
-            int p = pv[j];
-            if (p == j0 + j) continue;
-            if (p < j0 + w) {
-                cpx<R> t = T[j][c];
-                T[j][c] = T[p - j0][c];
-                T[p - j0][c] = t;
-            } else {
-                cpx<R> t = a[(long long)col * m + p];
-                a[(long long)col * m + p] = T[j][c];
-                T[j][c] = t;
-            }
+    const int jc = threadIdx.x;
+    if (jc < w)
+        for (int i = jc + 1; i < w; ++i) {
+            cpx<R> acc = L[i][jc];
+            for (int k = jc + 1; k < i; ++k) acc = acc + L[i][k] * X[k][jc];
+            X[i][jc] = mk(-acc.re, -acc.im);
         }
-        if (col >= j0 + w)
+    __syncthreads();
+    cpx<R> *out = Linv + (long long)blockIdx.x * LU_NB * LU_NB;
+    for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) out[e] = X[e / LU_NB][e % LU_NB];
+}
+
+// Row interchanges of a panel [j0, j0 + w) applied to the columns outside it (do_swap), and
+// U12 = L11^{-1} A12 for the columns right of it (do_trsm, with L11^{-1} from k_lu_linv).
+// One workgroup per (64-column tile, block).  Rows [j0, j0 + w) of the tile and the distinct
+// pivot rows below the panel are staged in LDS with parallel loads, the interchanges are
+// replayed in LDS in order, and both sets are written back in parallel.
+#define SW_CT 32                       // columns per workgroup
+#define SW_OUT (LU_NB * SW_CT / 256)   // U12 outputs per thread
+template <class R>
+__global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *ipiv, const cpx<R> *Linv, int m, int j0,
+                                                      int w, int do_swap, int do_trsm) {
+    __shared__ cpx<R> T[2 * LU_NB][SW_CT + 1];     // slots < LU_NB: rows j0 + slot; slots >= LU_NB: staged rows
+    __shared__ cpx<R> Li[LU_NB][LU_NB + 1];
+    __shared__ int slot[LU_NB];
+    __shared__ int ext[LU_NB];
+    __shared__ int next;
+    const int c0 = blockIdx.x * SW_CT;
+    cpx<R> *a = A + (long long)blockIdx.y * m * m;
+    const int *piv = ipiv + (long long)blockIdx.y * m;
+    const bool right = do_trsm && c0 + SW_CT > j0 + w;
+    if (threadIdx.x == 0) {
+        int ne = 0;
+        if (do_swap)
             for (int j = 0; j < w; ++j) {
-                cpx<R> u = T[j][c];
-                for (int i = j + 1; i < w; ++i) T[i][c] = cfms(T[i][c], L11[i][j], u);
+                int p = piv[j0 + j];
+                if (p < j0 + w) {
+                    slot[j] = p - j0;
+                } else {
+                    int e = 0;
+                    while (e < ne && ext[e] != p) ++e;
+                    if (e == ne) ext[ne++] = p;
+                    slot[j] = LU_NB + e;
+                }
             }
+        next = ne;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < w * 64; e += blockDim.x) {
-        int r = e % w, cc = e / w, cl = c0 + cc;
-        if (cl < m && !(cl >= j0 && cl < j0 + w)) a[(long long)cl * m + j0 + r] = T[r][cc];
+    const int ne = next;
+    const int nrow = w + ne;
+    for (int e = threadIdx.x; e < nrow * SW_CT; e += blockDim.x) {
+        int r = e % nrow, c = e / nrow, col = c0 + c;
+        bool live = col < m && !(col >= j0 && col < j0 + w);
+        int row = r < w ? j0 + r : ext[r - w];
+        int sl = r < w ? r : LU_NB + (r - w);
+        T[sl][c] = live ? a[(long long)col * m + row] : czero<R>();
+    }
+    if (right) {
+        const cpx<R> *li = Linv + (long long)blockIdx.y * LU_NB * LU_NB;
+        for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) Li[e / LU_NB][e % LU_NB] = li[e];
+    }
+    __syncthreads();
+    if (do_swap && threadIdx.x < SW_CT) {
+        const int c = threadIdx.x;
+        for (int j = 0; j < w; ++j) {
+            int sl = slot[j];
+            if (sl == j) continue;
+            cpx<R> tt = T[j][c];
+            T[j][c] = T[sl][c];
+            T[sl][c] = tt;
+        }
+    }
+    __syncthreads();
+    if (right) {
+        cpx<R> outv[SW_OUT];
+        const int cc = threadIdx.x % SW_CT, rq = threadIdx.x / SW_CT;
+        const int cl = c0 + cc;
+#pragma unroll
+        for (int k = 0; k < SW_OUT; ++k) {
+            int r = rq + (256 / SW_CT) * k;
+            cpx<R> acc = czero<R>();
+            if (r < w) {
+                acc = T[r][cc];
+                for (int q = 0; q < r; ++q) acc = acc + Li[r][q] * T[q][cc];
+            }
+            outv[k] = acc;
+        }
+        __syncthreads();
+        if (cl >= j0 + w && cl < m)
+#pragma unroll
+            for (int k = 0; k < SW_OUT; ++k) {
+                int r = rq + (256 / SW_CT) * k;
+                if (r < w) T[r][cc] = outv[k];
+            }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nrow * SW_CT; e += blockDim.x) {
+        int r = e % nrow, cc = e / nrow, cl = c0 + cc;
+        if (cl < m && !(cl >= j0 && cl < j0 + w)) {
+            int row = r < w ? j0 + r : ext[r - w];
+            int sl = r < w ? r : LU_NB + (r - w);
+            a[(long long)cl * m + row] = T[sl][cc];
+        }
     }
 }
 
-// A22 -= L21 U12 on 64x64 tiles, 4x4 complex outputs per thread.
+// A[r, c] -= sum_{k in [k0, k0 + K)} A[r, k] A[k, c] for r in [r0, r1), c in [c0, c1):
+// 64x64 output tiles, K consumed in chunks of 32 staged in LDS, 4x4 complex outputs per thread.
 template <class R>
-__global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int j0, int w) {
+__global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int r0, int r1, int c0, int c1, int k0, int K) {
     __shared__ cpx<R> Ls[LU_NB][LU_TILE];
     __shared__ cpx<R> Us[LU_NB][LU_TILE];
-    const int t0 = j0 + w;
-    const int nt = (m - t0 + LU_TILE - 1) / LU_TILE;
-    int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
-    int r0 = t0 + ti * LU_TILE, c0 = t0 + tj * LU_TILE;
+    const int nt = (r1 - r0 + LU_TILE - 1) / LU_TILE;
+    const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
+    const int rr0 = r0 + ti * LU_TILE, cc0 = c0 + tj * LU_TILE;
     cpx<R> *a = A + (long long)blockIdx.y * m * m;
-    for (int e = threadIdx.x; e < LU_NB * LU_TILE; e += 256) {
-        int k = e / LU_TILE, i = e % LU_TILE;
-        cpx<R> lv = czero<R>(), uv = czero<R>();
-        if (k < w) {
-            if (r0 + i < m) lv = a[(long long)(j0 + k) * m + r0 + i];
-            if (c0 + i < m) uv = a[(long long)(c0 + i) * m + j0 + k];
-        }
-        Ls[k][i] = lv;
-        Us[k][i] = uv;
-    }
-    __syncthreads();
-    int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+    const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
     cpx<R> acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = czero<R>();
-    for (int k = 0; k < w; ++k) {
-        cpx<R> lv[4], uv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) lv[i] = Ls[k][tr + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) uv[j] = Us[k][tc + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[i][j].re += lv[i].re * uv[j].re - lv[i].im * uv[j].im;
-                acc[i][j].im += lv[i].re * uv[j].im + lv[i].im * uv[j].re;
+    for (int kc = 0; kc < K; kc += LU_NB) {
+        const int kw = min(LU_NB, K - kc);
+        __syncthreads();
+        for (int e = threadIdx.x; e < LU_NB * LU_TILE; e += 256) {
+            int k = e / LU_TILE, i = e % LU_TILE;
+            cpx<R> lv = czero<R>(), uv = czero<R>();
+            if (k < kw) {
+                if (rr0 + i < r1) lv = a[(long long)(k0 + kc + k) * m + rr0 + i];
+                if (cc0 + i < c1) uv = a[(long long)(cc0 + i) * m + k0 + kc + k];
             }
+            Ls[k][i] = lv;
+            Us[k][i] = uv;
+        }
+        __syncthreads();
+        for (int k = 0; k < kw; ++k) {
+            cpx<R> lv[4], uv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lv[i] = Ls[k][tr + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) uv[j] = Us[k][tc + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j].re += lv[i].re * uv[j].re - lv[i].im * uv[j].im;
+                    acc[i][j].im += lv[i].re * uv[j].im + lv[i].im * uv[j].re;
+                }
+        }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        int c = c0 + tc + 16 * j;
-        if (c >= m) continue;
+        int c = cc0 + tc + 16 * j;
+        if (c >= c1) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int r = r0 + tr + 16 * i;
-            if (r >= m) continue;
+            int r = rr0 + tr + 16 * i;
+            if (r >= r1) continue;
             cpx<R> &x = a[(long long)c * m + r];
             x = x - acc[i][j];
         }
@@ -363,12 +542,15 @@ __global__ void k_lu_perm(const int *ipiv, int *perm, int m, int nblk) {
 // Setup: replace every 64x64 diagonal tile of the packed LU factors by the inverses of its
 // unit-lower part (strictly lower entries) and of its upper part (upper entries incl. the
 // diagonal).  The block solves then apply each diagonal tile as a parallel product.
-// One workgroup (128 threads) per (tile, block): thread j < 64 inverts column j of L,
-// thread 64 + j column j of U, both from an LDS copy of the tile.
+// One workgroup (128 threads) per (tile, block), in place in one LDS copy of the tile:
+//   L: for j = w-1 .. 0, column j of L^{-1} below the diagonal is -L^{-1}_{>j,>j} l_{>j,j},
+//      with L^{-1}_{>j,>j} already in place in the columns right of j;
+//   U: for j = 0 .. w-1, column j of U^{-1} above the diagonal is -U^{-1}_{<j,<j} u_{<j,j} / u_jj,
+//      with U^{-1}_{<j,<j} already in place in the columns left of j, and 1/u_jj on the diagonal.
+// Lanes 0..63 own the rows of the L step, lanes 64..127 the rows of the U step.
 template <class R>
 __global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
-    cpx<R> *T = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][TS+1], column-major: T[c*(TS+1)+r]
-    cpx<R> *X = T + TS * (TS + 1);
+    cpx<R> *T = reinterpret_cast<cpx<R> *>(vie_smem);  // column-major [TS][TS+1]: T[c*(TS+1)+r]
     const int t0 = blockIdx.x * TS;
     const int w = min(TS, m - t0);
     cpx<R> *a = F + (long long)blockIdx.y * m * m;
@@ -377,30 +559,38 @@ __global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
         T[c * (TS + 1) + r] = a[(long long)(t0 + c) * m + t0 + r];
     }
     __syncthreads();
-    int j = threadIdx.x & 63;
-    if (j < w) {
-        if (threadIdx.x < 64) {
-            // column j of L^{-1} (unit lower): x_j = 1 (implicit; the diagonal slot belongs to U^{-1}),
-            // x_i = -(l_ij + sum_{k=j+1}^{i-1} l_ik x_k)
-            for (int i = j + 1; i < w; ++i) {
-                cpx<R> acc = T[j * (TS + 1) + i];
-                for (int k = j + 1; k < i; ++k) acc = acc + T[k * (TS + 1) + i] * X[j * (TS + 1) + k];
-                X[j * (TS + 1) + i] = mk(-acc.re, -acc.im);
+    const int i = threadIdx.x & 63;
+    const bool lower = threadIdx.x < 64;
+    for (int step = 0; step < w; ++step) {
+        cpx<R> x = czero<R>();
+        const int jl = w - 1 - step;  // L column of this step
+        const int ju = step;          // U column of this step
+        if (lower) {
+            if (i > jl && i < w) {
+                // x_i = -(l_ij + sum_{k=j+1}^{i-1} Linv_ik l_kj)
+                x = T[jl * (TS + 1) + i];
+                for (int k = jl + 1; k < i; ++k) x = x + T[k * (TS + 1) + i] * T[jl * (TS + 1) + k];
+                x = mk(-x.re, -x.im);
             }
         } else {
-            // column j of U^{-1}: x_j = 1/u_jj, x_i = -(sum_{k=i+1}^{j} u_ik x_k) / u_ii
-            X[j * (TS + 1) + j] = cdiv(mk(R(1), R(0)), T[j * (TS + 1) + j]);
-            for (int i = j - 1; i >= 0; --i) {
-                cpx<R> acc = czero<R>();
-                for (int k = i + 1; k <= j; ++k) acc = acc + T[k * (TS + 1) + i] * X[j * (TS + 1) + k];
-                X[j * (TS + 1) + i] = cdiv(mk(-acc.re, -acc.im), T[i * (TS + 1) + i]);
+            if (i < ju) {
+                // x_i = -(sum_{k=i}^{j-1} Uinv_ik u_kj) / u_jj
+                for (int k = i; k < ju; ++k) x = x + T[k * (TS + 1) + i] * T[ju * (TS + 1) + k];
+                x = cdiv(mk(-x.re, -x.im), T[ju * (TS + 1) + ju]);
             }
         }
+        __syncthreads();
+        if (lower) {
+            if (i > jl && i < w) T[jl * (TS + 1) + i] = x;
+        } else {
+            if (i < ju) T[ju * (TS + 1) + i] = x;
+            else if (i == ju) T[ju * (TS + 1) + ju] = cdiv(mk(R(1), R(0)), T[ju * (TS + 1) + ju]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
         int r = e % w, c = e / w;
-        a[(long long)(t0 + c) * m + t0 + r] = X[c * (TS + 1) + r];
+        a[(long long)(t0 + c) * m + t0 + r] = T[c * (TS + 1) + r];
     }
 }
 
@@ -408,36 +598,75 @@ template <class R>
 static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     const int m = pc->m, nb = pc->nstored;
     cpx<R> *A = pc->factors.as<cpx<R>>();
-    DevBuf ipiv;
+    DevBuf ipiv, linv;
     VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
+    VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
-    for (int j0 = 0; j0 < m; j0 += LU_NB) {
-        int w = std::min(LU_NB, m - j0);
-        {
-            ProfScope ps("lu_panel", s);
+    auto panel = [&](int j0, int w) -> vie_status {
+        ProfScope ps("lu_panel", s);
+        int qs = (m - j0 + 31) / 32;
+        size_t lds = sizeof(cpx<R>) * (size_t)(m - j0);
+        bool regs = qs * sizeof(cpx<R>) / 4 <= 96;  // accumulator VGPRs per thread
+#define PANEL_CASE(QV)                                                                                   \
+    if (qs <= QV) {                                                                                      \
+        hipLaunchKernelGGL((k_lu_panel_reg<R, QV>), dim3(nb), dim3(1024), lds, s, A, ipiv.as<int>(),     \
+                           pc->info.as<int>(), m, j0, w);                                               \
+    } else
+        if (regs) {
+            PANEL_CASE(2) PANEL_CASE(4) PANEL_CASE(8) PANEL_CASE(12) PANEL_CASE(16) PANEL_CASE(24)
+            PANEL_CASE(32) PANEL_CASE(40) {
+                hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(),
+                                   m, j0, w);
+            }
+        } else {
             hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(), m,
                                j0, w);
         }
+#undef PANEL_CASE
         VIE_HIP(hipGetLastError());
-        {
-            ProfScope ps("lu_swap_trsm", s);
-            hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + 63) / 64, nb), dim3(256), 0, s, A, ipiv.as<int>(), m,
-                               j0, w);
-        }
-        VIE_HIP(hipGetLastError());
-        int rest = m - j0 - w;
-        if (rest > 0) {
-            int nt = (rest + LU_TILE - 1) / LU_TILE;
-            ProfScope ps("lu_update", s);
-            hipLaunchKernelGGL(k_lu_update<R>, dim3(nt * nt, nb), dim3(256), 0, s, A, m, j0, w);
+        return VIE_OK;
+    };
+    auto swap_trsm = [&](int j0, int w, int do_swap, int do_trsm) -> vie_status {
+        ProfScope ps("lu_swap_trsm", s);
+        if (do_trsm) {
+            hipLaunchKernelGGL(k_lu_linv<R>, dim3(nb), dim3(64), 0, s, (const cpx<R> *)A, linv.as<cpx<R>>(), m, j0, w);
             VIE_HIP(hipGetLastError());
         }
+        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + SW_CT - 1) / SW_CT, nb), dim3(256), 0, s, A, ipiv.as<int>(),
+                           (const cpx<R> *)linv.as<cpx<R>>(), m, j0, w, do_swap, do_trsm);
+        VIE_HIP(hipGetLastError());
+        return VIE_OK;
+    };
+    auto update = [&](int r0, int r1, int c0, int c1, int k0, int K) -> vie_status {
+        if (r1 <= r0 || c1 <= c0 || K <= 0) return VIE_OK;
+        ProfScope ps("lu_update", s);
+        int ntr = (r1 - r0 + LU_TILE - 1) / LU_TILE, ntc = (c1 - c0 + LU_TILE - 1) / LU_TILE;
+        hipLaunchKernelGGL(k_lu_update<R>, dim3(ntr * ntc, nb), dim3(256), 0, s, A, m, r0, r1, c0, c1, k0, K);
+        VIE_HIP(hipGetLastError());
+        return VIE_OK;
+    };
+    // Two-level right-looking LU: macro panels of 2 x LU_NB columns.  The first sub-panel's
+    // update reaches only the second sub-panel (its columns, and its rows after the second
+    // sub-panel's interchanges); the trailing matrix is updated once with K = 2 LU_NB.
+    for (int j0 = 0; j0 < m; j0 += 2 * LU_NB) {
+        const int w1 = std::min(LU_NB, m - j0);
+        VIE_CHECK(panel(j0, w1));
+        VIE_CHECK(swap_trsm(j0, w1, 1, 1));
+        const int j1 = j0 + w1;
+        if (j1 >= m) break;
+        const int w2 = std::min(LU_NB, m - j1);
+        VIE_CHECK(update(j1, m, j1, j1 + w2, j0, w1));            // second sub-panel's columns
+        VIE_CHECK(panel(j1, w2));
+        VIE_CHECK(swap_trsm(j1, w2, 1, 0));                      // its interchanges everywhere
+        VIE_CHECK(update(j1, j1 + w2, j1 + w2, m, j0, w1));       // its rows, right of it
+        VIE_CHECK(swap_trsm(j1, w2, 0, 1));                      // U12 of the second sub-panel
+        VIE_CHECK(update(j1 + w2, m, j1 + w2, m, j0, w1 + w2));   // trailing matrix, K = w1 + w2
     }
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());
     {
-        size_t lds = 2 * sizeof(cpx<R>) * TS * (TS + 1);
+        size_t lds = sizeof(cpx<R>) * TS * (TS + 1);
         vie_lds_attr((const void *)k_invert_diag<R>, lds);
         ProfScope ps("lu_invert_diag", s);
         hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(128), lds, s, A, m);
