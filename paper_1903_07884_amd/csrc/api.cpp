@@ -72,20 +72,24 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
     op->Hy = op->Py / 2 + 1;
     op->Hz = op->Pz / 2 + 1;
     op->has_c64 = o.build_c64 != 0;
+    // few z layers: keep the z coupling as a direct Toeplitz sum (no z transform); the
+    // (y, z) plane working set must fit the LDS either way
+    op->direct_z = op->nz <= 16 && 3LL * op->nz * op->Py <= 2LL * FFT_BPT * 1024 &&
+                   sizeof(c128) * ((size_t)6 * op->nz * op->Py + (size_t)6 * op->Hy * op->nz) <= max_lds();
     auto fail = [&](vie_status st) {
         delete op;
         return st;
     };
-    if (6 * sizeof(c128) * op->Py * op->Pz > max_lds())
+    if (!op->direct_z && 6 * sizeof(c128) * op->Py * op->Pz > max_lds())
         return fail(arg_error("vie_create: cross-section too large for the LDS plane transform"));
     vie_status st;
     if ((st = op->fft.get(op->Px, &op->px)) < 0) return fail(st);
     if ((st = op->fft.get(op->Py, &op->py)) < 0) return fail(st);
     if ((st = op->fft.get(op->Pz, &op->pz)) < 0) return fail(st);
     {
-        int thr;
+        int thr, bpt;
         size_t lds;
-        fft_line_shape(op->px, sizeof(c128), &thr, &lds);
+        fft_line_shape(op->px, sizeof(c128), &thr, &lds, &bpt);
         if (lds > max_lds())
             return fail(arg_error("vie_create: x extent too long for the LDS line transform (padded length " +
                                   std::to_string(op->Px) + ")"));
@@ -202,9 +206,9 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     {
         FftPlan tmp;
         if (op->fft.get(bx, &tmp) < 0) return VIE_EARG;
-        int thr;
+        int thr, bpt;
         size_t lds;
-        fft_line_shape(tmp, sizeof(c128), &thr, &lds);
+        fft_line_shape(tmp, sizeof(c128), &thr, &lds, &bpt);
         if (lds > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
     }
     if (m > 1280) return arg_error("precond_setup: cross-section block (3*by*bz) above 1280 is not supported");

@@ -172,16 +172,16 @@ __device__ cpx<R> *fft_lds(cpx<R> *a, cpx<R> *b, const LdsLines &ln, const FftPl
 // In-place variant for radices 2..5: each thread keeps the inputs of up to FFT_BPT
 // butterflies in registers across a barrier, so one LDS buffer suffices (long lines).
 // Requires (L / smallest radix) * nlines <= FFT_BPT * blockDim.x.
-#define FFT_BPT 4
-template <class R, int P>
+#define FFT_BPT 4  // largest number of butterflies per thread an in-place transform may need
+template <class R, int P, int BPT>
 __device__ __forceinline__ void stage_inplace(cpx<R> *buf, const LdsLines &ln, int L, int Ns, const cpx<R> *tw,
                                               bool inv) {
     const int nb = L / P;
     const int total = nb * ln.nlines;
     const int twstep = L / (Ns * P);
-    cpx<R> v[FFT_BPT][P];
+    cpx<R> v[BPT][P];
 #pragma unroll
-    for (int q = 0; q < FFT_BPT; ++q) {
+    for (int q = 0; q < BPT; ++q) {
         int t = threadIdx.x + q * blockDim.x;
         if (t < total) {
             int l = t / nb, j = t - l * nb;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void stage_inplace(cpx<R> *buf, const LdsLines &ln, i
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < FFT_BPT; ++q) {
+    for (int q = 0; q < BPT; ++q) {
         int t = threadIdx.x + q * blockDim.x;
         if (t < total) {
             int l = t / nb, j = t - l * nb;
@@ -221,8 +221,9 @@ __host__ __device__ inline bool fft_plan_inplace(const FftPlan &plan) {
     return true;
 }
 
-// Transform in place (plans with radices <= 5 only); caller syncs before.
-template <class R>
+// Transform in place (plans with radices <= 5 only); caller syncs before.  BPT butterflies
+// per thread at most: (L / smallest radix) * nlines <= BPT * blockDim.x.
+template <class R, int BPT>
 __device__ void fft_lds_inplace(cpx<R> *buf, const LdsLines &ln, const FftPlan &plan, bool inv) {
     const cpx<R> *tw = TwTable<R>::get(plan);
     const int L = plan.L;
@@ -230,33 +231,62 @@ __device__ void fft_lds_inplace(cpx<R> *buf, const LdsLines &ln, const FftPlan &
     for (int st = 0; st < plan.nrad; ++st) {
         int P = plan.rad[st];
         switch (P) {
-            case 2: stage_inplace<R, 2>(buf, ln, L, Ns, tw, inv); break;
-            case 3: stage_inplace<R, 3>(buf, ln, L, Ns, tw, inv); break;
-            case 4: stage_inplace<R, 4>(buf, ln, L, Ns, tw, inv); break;
-            default: stage_inplace<R, 5>(buf, ln, L, Ns, tw, inv); break;
+            case 2: stage_inplace<R, 2, BPT>(buf, ln, L, Ns, tw, inv); break;
+            case 3: stage_inplace<R, 3, BPT>(buf, ln, L, Ns, tw, inv); break;
+            case 4: stage_inplace<R, 4, BPT>(buf, ln, L, Ns, tw, inv); break;
+            default: stage_inplace<R, 5, BPT>(buf, ln, L, Ns, tw, inv); break;
         }
         Ns *= P;
     }
 }
 
-// One line in LDS: in place when the plan allows (buffer of L), else ping-pong (2 L).
-template <class R>
+// One line per workgroup.  Ping-pong (2 L of LDS, no register staging) when both buffers fit
+// in FFT_PINGPONG_LDS bytes, otherwise in place (L of LDS; plans with radices <= 5).
+#define FFT_PINGPONG_LDS 65536
+__host__ __device__ inline bool fft_line_inplace(const FftPlan &plan, size_t esz) {
+    return 2 * esz * (size_t)plan.L > FFT_PINGPONG_LDS && fft_plan_inplace(plan);
+}
+
+template <class R, int BPT>
 __device__ __forceinline__ cpx<R> *fft_line(cpx<R> *a, const FftPlan &plan, bool inv) {
     LdsLines ln = {1, 0, 0, 1, 1};
-    if (fft_plan_inplace(plan)) {
-        fft_lds_inplace<R>(a, ln, plan, inv);
+    if (BPT > 0 && fft_line_inplace(plan, sizeof(cpx<R>))) {
+        fft_lds_inplace<R, (BPT > 0 ? BPT : 1)>(a, ln, plan, inv);
         return a;
     }
     return fft_lds<R>(a, a + plan.L, ln, plan, inv);
 }
 
-// Launch shape of a one-line-per-workgroup transform: threads and LDS bytes.
-inline void fft_line_shape(const FftPlan &plan, size_t esz, int *threads, size_t *lds) {
+// Host: expand X(B) for the butterflies-per-thread value fft_line_shape selected.
+#define VIE_BPT_SWITCH(bpt, X) \
+    do {                         \
+        if ((bpt) == 0) {        \
+            X(0);                \
+        } else if ((bpt) == 2) { \
+            X(2);                \
+        } else {                 \
+            X(4);                \
+        }                        \
+    } while (0)
+
+// Launch shape of a one-line-per-workgroup transform: threads, LDS bytes and the
+// butterflies-per-thread template argument (0 = ping-pong).
+inline void fft_line_shape(const FftPlan &plan, size_t esz, int *threads, size_t *lds, int *bpt) {
     int L = plan.L;
     int t = 64;
-    while (t < 1024 && (long long)t * FFT_BPT * 2 < L) t *= 2;  // radix-2 worst case fits
+    while (t < 256 && t * 4 < L) t *= 2;
+    if (fft_line_inplace(plan, esz)) {
+        t = 64;
+        while (t < 1024 && (long long)t * 2 * 2 < L) t *= 2;  // radix-2 stage with 2 per thread
+        int b = 2;
+        while ((long long)t * b * 2 < L) b *= 2;
+        *bpt = b;
+        *lds = esz * (size_t)L;
+    } else {
+        *bpt = 0;
+        *lds = 2 * esz * (size_t)L;
+    }
     *threads = t;
-    *lds = (fft_plan_inplace(plan) ? 1 : 2) * esz * (size_t)L;
 }
 
 extern __shared__ __align__(16) unsigned char vie_smem[];

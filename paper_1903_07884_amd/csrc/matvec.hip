@@ -89,7 +89,7 @@ __global__ void k_embed(const c128 *gen, c128 *E, int nx, int ny, int nz, int Px
 
 // In-place FFT of lines in global memory: line l starts at (l % nl1)*s1 + (l / nl1)*s2,
 // element stride es.  One workgroup per line.
-template <class R>
+template <class R, int BPT>
 __global__ void k_fft_lines(cpx<R> *data, long long nl1, long long s1, long long s2, long long es,
                             FftPlan plan, int inv) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
@@ -97,7 +97,7 @@ __global__ void k_fft_lines(cpx<R> *data, long long nl1, long long s1, long long
     cpx<R> *base = data + (l % nl1) * s1 + (l / nl1) * s2;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = base[i * es];
     __syncthreads();
-    cpx<R> *res = fft_line<R>(a, plan, inv != 0);
+    cpx<R> *res = fft_line<R, BPT>(a, plan, inv != 0);
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) base[i * es] = res[i];
 }
 
@@ -115,6 +115,25 @@ __global__ void k_extract(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, in
     int kx = (int)(r / Hz);
     double sc = 1.0 / ((double)Px * Py * Pz);
     c128 v = E[(long long)c * Px * Py * Pz + ((long long)kz * Py + ky) * Px + kx];
+    v = mk(v.re * sc, v.im * sc);
+    k64[i] = v;
+    if (k32) k32[i] = mk((float)v.re, (float)v.im);
+}
+
+// (x, y)-transformed generator for the direct z sum, octant in (kx, ky), real-space z offsets
+// dz in [0, nz): khat[kx][ky][dz][c] = E[c][dz][ky][kx] / (Px Py)
+__global__ void k_extract_xy(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, int Pz, int Hx, int Hy, int nz) {
+    long long total = (long long)Hx * Hy * nz * 6;
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int c = (int)(i % 6);
+    long long r = i / 6;
+    int dz = (int)(r % nz);
+    r /= nz;
+    int ky = (int)(r % Hy);
+    int kx = (int)(r / Hy);
+    double sc = 1.0 / ((double)Px * Py);
+    c128 v = E[(long long)c * Px * Py * Pz + ((long long)dz * Py + ky) * Px + kx];
     v = mk(v.re * sc, v.im * sc);
     k64[i] = v;
     if (k32) k32[i] = mk((float)v.re, (float)v.im);
@@ -144,22 +163,32 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
         {&op->py, Px, 1, (long long)Px * Py, Px, 6LL * Pz * Px},
         {&op->pz, (long long)Px * Py, 1, P3, (long long)Px * Py, 6LL * Px * Py},
     };
-    for (auto &ps : passes) {
+    for (int pi = 0; pi < 3; ++pi) {
+        auto &ps = passes[pi];
         if (ps.p->L == 1) continue;
+        if (pi == 2 && op->direct_z) continue;  // z offsets stay in real space
         size_t lds;
-        int thr;
-        fft_line_shape(*ps.p, sizeof(c128), &thr, &lds);
-        vie_lds_attr((const void *)k_fft_lines<double>, lds);
-        hipLaunchKernelGGL(k_fft_lines<double>, dim3((unsigned)ps.nlines), dim3(thr), lds, s,
-                           E.as<c128>(), ps.nl1, ps.s1, ps.s2, ps.es, *ps.p, 0);
+        int thr, bpt;
+        fft_line_shape(*ps.p, sizeof(c128), &thr, &lds, &bpt);
+#define LAUNCH_LINES(B)                                                                                   \
+    vie_lds_attr((const void *)k_fft_lines<double, B>, lds);                                              \
+    hipLaunchKernelGGL((k_fft_lines<double, B>), dim3((unsigned)ps.nlines), dim3(thr), lds, s, E.as<c128>(), \
+                       ps.nl1, ps.s1, ps.s2, ps.es, *ps.p, 0)
+        VIE_BPT_SWITCH(bpt, LAUNCH_LINES);
+#undef LAUNCH_LINES
         VIE_HIP(hipGetLastError());
     }
-    long long H = (long long)op->Hx * op->Hy * op->Hz * 6;
+    long long H = op->direct_z ? (long long)op->Hx * op->Hy * op->nz * 6 : (long long)op->Hx * op->Hy * op->Hz * 6;
     VIE_CHECK(op->khat64.ensure(sizeof(c128) * H));
     if (op->has_c64) VIE_CHECK(op->khat32.ensure(sizeof(c64) * H));
-    hipLaunchKernelGGL(k_extract, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
-                       op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
-                       op->Hx, op->Hy, op->Hz);
+    if (op->direct_z)
+        hipLaunchKernelGGL(k_extract_xy, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
+                           op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
+                           op->Hx, op->Hy, op->nz);
+    else
+        hipLaunchKernelGGL(k_extract, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
+                           op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
+                           op->Hx, op->Hy, op->Hz);
     VIE_HIP(hipGetLastError());
     VIE_HIP(hipStreamSynchronize(s));
     E.release();
@@ -168,14 +197,14 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
 
 // ---------------------------------------------------------------- product
 // pass 1: one workgroup per x-line (rhs, a, z, y): zero-pad to Px, forward FFT.
-template <class R>
+template <class R, int BPT>
 __global__ void k_xfwd(const cpx<R> *x, cpx<R> *work, int nx, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
     long long line = blockIdx.x;
     const cpx<R> *src = x + line * nx;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = i < nx ? src[i] : czero<R>();
     __syncthreads();
-    cpx<R> *res = fft_line<R>(a, plan, false);
+    cpx<R> *res = fft_line<R, BPT>(a, plan, false);
     cpx<R> *dst = work + line * plan.L;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) dst[i] = res[i];
 }
@@ -258,8 +287,75 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
     }
 }
 
-// pass 3: one workgroup per x-line; inverse FFT, crop, y = x - M (x + K x).
+// pass 2 for cross-sections with few z layers: one workgroup per (x-frequency, rhs).
+// Forward y-FFT of the 3 nz zero-padded rows, then for every y-frequency the z coupling as a
+// direct sum over the nz z-offsets of the (x, y)-transformed generator (its z-Toeplitz
+// structure kept in real space, parities applied per axis), inverse y-FFT, crop.
 template <class R>
+__global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hy, FftPlan py) {
+    const int Py = py.L;
+    const int rows = 3 * nz;
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);  // [3][nz][Py] lines
+    cpx<R> *b = a + rows * Py;                          // [3][nz][Py] second buffer
+    cpx<R> *G = b + rows * Py;                          // [nz][6][Hy] (y-frequency fastest)
+    const int kx = blockIdx.x;
+    const int kxo = kx <= Px - kx ? kx : Px - kx;
+    const bool fx = kx > Px - kx;
+    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
+    const cpx<R> *kh = khat + (long long)kxo * Hy * nz * 6;
+    for (int i = threadIdx.x; i < Hy * nz * 6; i += blockDim.x) {
+        int c = i % 6, dz = (i / 6) % nz, kyo = i / (6 * nz);  // source layout [Hy][nz][6]
+        G[(dz * 6 + c) * Hy + kyo] = kh[i];
+    }
+    for (int i = threadIdx.x; i < rows * Py; i += blockDim.x) {
+        int y = i % Py, rz = i / Py;  // rz = c * nz + z
+        a[i] = y < ny ? base[((long long)rz * ny + y) * Px] : czero<R>();
+    }
+    __syncthreads();
+    LdsLines ln = {rows, Py, 0, 1, rows};
+    cpx<R> *spec = a, *prod = b;  // spectra, then the coupled products in the other buffer
+    if (Py > 1) {
+        spec = fft_lds<R>(a, b, ln, py, false);
+        prod = spec == a ? b : a;
+    }
+    // parity: xy odd in x, y; xz odd in x, z; yz odd in y, z
+    const int cidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int o = threadIdx.x; o < rows * Py; o += blockDim.x) {
+        const int ky = o % Py, rz = o / Py;
+        const int al = rz / nz, z = rz % nz;
+        const int kyo = ky <= Py - ky ? ky : Py - ky;
+        const bool fy = ky > Py - ky;
+        const cpx<R> *g = G + kyo;
+        cpx<R> acc = czero<R>();
+        for (int be = 0; be < 3; ++be) {
+            const int c = cidx[al][be];
+            bool neg = false;
+            if ((c == 3 || c == 4) && fx) neg = !neg;
+            if ((c == 3 || c == 5) && fy) neg = !neg;
+            const bool oddz = (c == 4 || c == 5);
+            cpx<R> part = czero<R>();
+            for (int zp = 0; zp < nz; ++zp) {
+                int dz = z - zp;
+                cpx<R> gv = g[((dz < 0 ? -dz : dz) * 6 + c) * Hy];
+                cpx<R> xv = spec[(be * nz + zp) * Py + ky];
+                if (oddz && dz < 0) part = part - gv * xv;
+                else part = part + gv * xv;
+            }
+            acc = neg ? acc - part : acc + part;
+        }
+        prod[o] = acc;
+    }
+    __syncthreads();
+    cpx<R> *res = prod;
+    if (Py > 1) res = fft_lds<R>(prod, spec, ln, py, true);
+    for (int i = threadIdx.x; i < rows * ny; i += blockDim.x) {
+        int y = i % ny, rz = i / ny;
+        base[((long long)rz * ny + y) * Px] = res[rz * Py + y];
+    }
+}
+
+// pass 3: one workgroup per x-line; inverse FFT, crop, y = x - M (x + K x).
+template <class R, int BPT>
 __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx<R> *y, int nx,
                        long long lines_per_comp_rhs_N, int nyz, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
@@ -267,7 +363,7 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
     const cpx<R> *src = work + line * plan.L;
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    cpx<R> *res = fft_line<R>(a, plan, true);
+    cpx<R> *res = fft_line<R, BPT>(a, plan, true);
     long long yz = line % nyz;  // voxel row (z, y)
     const cpx<R> *xl = x + line * nx;
     const cpx<R> *ml = M + yz * nx;
@@ -287,27 +383,39 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     VIE_CHECK(op->work.ensure(sizeof(cpx<R>) * lines * Px));
     cpx<R> *work = op->work.as<cpx<R>>();
     size_t ldsx;
-    int thx;
-    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx);
-    vie_lds_attr((const void *)k_xfwd<R>, ldsx);
-    vie_lds_attr((const void *)k_xinv<R>, ldsx);
+    int thx, bpt;
+    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt);
     {
         ProfScope ps("matvec_xfwd", s);
-        hipLaunchKernelGGL(k_xfwd<R>, dim3((unsigned)lines), dim3(thx), ldsx, s, x, work, nx, op->px);
+#define LAUNCH_XFWD(B)                                      \
+    vie_lds_attr((const void *)k_xfwd<R, B>, ldsx);         \
+    hipLaunchKernelGGL((k_xfwd<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, x, work, nx, op->px)
+        VIE_BPT_SWITCH(bpt, LAUNCH_XFWD);
+#undef LAUNCH_XFWD
     }
     VIE_HIP(hipGetLastError());
-    size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
-    vie_lds_attr((const void *)k_plane<R>, ldsp);
-    {
+    if (op->direct_z) {
+        size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
+        int thr = 256;
+        vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane<R>, dim3((Px + PLANE_KB - 1) / PLANE_KB, nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px, op->Hx, op->Hy,
-                           op->Hz, op->py, op->pz);
+        hipLaunchKernelGGL(k_plane_dz<R>, dim3(Px, nrhs), dim3(thr), ldsp, s, work, khat, ny, nz, Px, op->Hy, op->py);
+    } else {
+        size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
+        vie_lds_attr((const void *)k_plane<R>, ldsp);
+        ProfScope ps("matvec_plane", s);
+        hipLaunchKernelGGL(k_plane<R>, dim3((Px + PLANE_KB - 1) / PLANE_KB, nrhs), dim3(256), ldsp, s, work, khat, ny,
+                           nz, Px, op->Hx, op->Hy, op->Hz, op->py, op->pz);
     }
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("matvec_xinv", s);
-        hipLaunchKernelGGL(k_xinv<R>, dim3((unsigned)lines), dim3(thx), ldsx, s, work, x, M, y, nx,
-                           0LL, ny * nz, op->px);
+#define LAUNCH_XINV(B)                                                                               \
+    vie_lds_attr((const void *)k_xinv<R, B>, ldsx);                                                  \
+    hipLaunchKernelGGL((k_xinv<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, work, x, M, y, nx, \
+                       0LL, ny * nz, op->px)
+        VIE_BPT_SWITCH(bpt, LAUNCH_XINV);
+#undef LAUNCH_XINV
     }
     VIE_HIP(hipGetLastError());
     return VIE_OK;

@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(256) k_homog(const c128 *M, c128 *Mt, const in
 
 // ---------------------------------------------------------------- Chan table
 // One workgroup per (component, dy, dz); output Ch[k][c][dz + bz - 1][dy + by - 1].
+template <int BPT>
 __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, int n, int by, int bz,
                              int identity, FftPlan plan) {
     c128 *a = reinterpret_cast<c128 *>(vie_smem);
@@ -103,7 +104,7 @@ __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, 
         a[l] = v;
     }
     __syncthreads();
-    c128 *res = fft_line<double>(a, plan, false);
+    c128 *res = fft_line<double, BPT>(a, plan, false);
     const long long stride_k = 6LL * ndz * ndy;
     for (int k = threadIdx.x; k < n; k += blockDim.x) Ch[k * stride_k + (long long)c * ndz * ndy + iz * ndy + iy] = res[k];
 }
@@ -679,7 +680,7 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
 
 // ---------------------------------------------------------------- apply
 // Forward x-DFT of every box line: work[rhs][box][row][k], row = a*by*bz + y + by*z.
-template <class R>
+template <class R, int BPT>
 __global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int nx, int ny, int nz, int by,
                           int bz, int nboxes, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
@@ -693,13 +694,13 @@ __global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int n
     const cpx<R> *src = r + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    cpx<R> *res = fft_line<R>(a, plan, false);
+    cpx<R> *res = fft_line<R, BPT>(a, plan, false);
     cpx<R> *dst = work + line * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = res[i];
 }
 
 // Inverse x-DFT (scaled 1/n) of every box line back into z.
-template <class R>
+template <class R, int BPT>
 __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int nx, int ny, int nz, int by,
                            int bz, int nboxes, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
@@ -713,7 +714,7 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int
     const cpx<R> *src = work + line * n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = src[i];
     __syncthreads();
-    cpx<R> *res = fft_line<R>(a, plan, true);
+    cpx<R> *res = fft_line<R, BPT>(a, plan, true);
     cpx<R> *dst = zv + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
     R sc = R(1) / R(n);
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
@@ -921,16 +922,18 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
     const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * n);
-    int thr;
+    int thr, bpt;
     size_t lds;
-    fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds);
+    fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds, &bpt);
     cpx<R> *work = pc->work.as<cpx<R>>();
-    vie_lds_attr((const void *)k_box_fft<R>, lds);
-    vie_lds_attr((const void *)k_box_ifft<R>, lds);
     {
         ProfScope ps("precond_xfft", s);
-        hipLaunchKernelGGL(k_box_fft<R>, dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, op->nx, op->ny,
-                           op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+#define LAUNCH_BOX_FFT(B)                                                                                 \
+    vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                     \
+    hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, op->nx, \
+                       op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
+        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
+#undef LAUNCH_BOX_FFT
     }
     VIE_HIP(hipGetLastError());
     {
@@ -940,8 +943,12 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     }
     {
         ProfScope ps("precond_ixfft", s);
-        hipLaunchKernelGGL(k_box_ifft<R>, dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, op->ny,
-                           op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb);
+#define LAUNCH_BOX_IFFT(B)                                                                                \
+    vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                    \
+    hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, \
+                       op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
+        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
+#undef LAUNCH_BOX_IFFT
     }
     VIE_HIP(hipGetLastError());
     return VIE_OK;
@@ -1023,12 +1030,15 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     DevBuf Ch;
     VIE_CHECK(Ch.ensure(sizeof(c128) * (size_t)n * 6 * ndy * ndz));
     {
-        int thr;
+        int thr, bpt;
         size_t lds;
-        fft_line_shape(pc->pxb, sizeof(c128), &thr, &lds);
-        vie_lds_attr((const void *)k_chan_table, lds);
-        hipLaunchKernelGGL(k_chan_table, dim3(6 * ndy * ndz), dim3(thr), lds, s, op->gen.as<const c128>(),
-                           Ch.as<c128>(), op->nx, op->ny, op->nz, n, by, bz, 1, pc->pxb);
+        fft_line_shape(pc->pxb, sizeof(c128), &thr, &lds, &bpt);
+#define LAUNCH_CHAN(B)                                                                                     \
+    vie_lds_attr((const void *)k_chan_table<B>, lds);                                                      \
+    hipLaunchKernelGGL(k_chan_table<B>, dim3(6 * ndy * ndz), dim3(thr), lds, s, op->gen.as<const c128>(),  \
+                       Ch.as<c128>(), op->nx, op->ny, op->nz, n, by, bz, 1, pc->pxb)
+        VIE_BPT_SWITCH(bpt, LAUNCH_CHAN);
+#undef LAUNCH_CHAN
         VIE_HIP(hipGetLastError());
     }
     // memory reduction: proxy v_k of eq. proxy1 read from the table of N (minus the identity)

@@ -130,8 +130,10 @@ struct vie_op_s {
     int Hx, Hy, Hz;          // octant extents Px/2+1 ...
     DevBuf M64, M32;         // contrast per voxel (c128 / c64)
     DevBuf gen;              // FP64 octant generator [6][nz][ny][nx]
-    DevBuf khat64, khat32;   // octant kernel transform [Hx][Hz][Hy][6], scaled by 1/(Px Py Pz)
+    DevBuf khat64, khat32;   // octant kernel transform [Hx][Hz][Hy][6] scaled by 1/(Px Py Pz), or with
+                             // direct_z the (x, y)-transform [Hx][Hy][nz][6] scaled by 1/(Px Py)
     bool has_c64 = false;
+    bool direct_z = false;   // kernel transform along x, y only; z handled as a direct Toeplitz sum
     DevBuf work;             // matvec intermediate, nrhs*3*ny*nz*Px complex
     FftCache fft;
     FftPlan px, py, pz;      // plans for the three periods
