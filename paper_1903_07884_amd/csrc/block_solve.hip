@@ -1,0 +1,519 @@
+// Block solves of the preconditioner apply: for every Fourier mode k of every box,
+//   z_k = U^{-1} L^{-1} P rhat_k
+// with the LU factors of D_k (the block-diagonal form of the one-level circulant, Sec. 4,
+// eq. Di and its inverse).  The packed factors are column-major [m][m] per stored block, every
+// 64x64 diagonal tile replaced by the inverses of its unit-lower part (strictly lower entries)
+// and of its upper part (upper entries incl. the diagonal), so each diagonal tile is applied
+// as a product.  work element (rhs, box, row i, mode k) sits at ((rhs*nboxes + box)*m + i)*n + k.
+//
+// Two kernels share the modes:
+//  * narrow: one workgroup per (box, mode, chunk of <= 8 right-hand sides), rows in registers;
+//    for blocks used by few columns (one mode at R = 1);
+//  * wide: one workgroup per (stored block, group of <= 64 columns), where a column is one
+//    (mode, right-hand side) pair whose mode uses the block -- the R right-hand sides of a
+//    mode, and, under the memory reduction, every mode that shares the central block.  The
+//    products run on the matrix cores.
+#include <algorithm>
+
+#include "fft_device.h"
+#include "vie_internal.h"
+
+#define TS 64
+
+// ---------------------------------------------------------------- narrow
+// Thread t owns rows t, t + 256, ... (QR of them) and keeps their RC accumulators in
+// registers.  Forward and backward substitution run over 64-row tiles: the tile's owners
+// publish its rows to LDS, four wavefronts apply the pre-inverted diagonal tile (each a
+// quarter of its columns), and every thread then applies the tile's column panel to its
+// remaining rows.  Each factor entry is read once per chunk and used RC times; the factor
+// reads are coalesced along columns.
+template <class R, int QR, int RC>
+__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm,
+                                                     const int *block_of_mode, const int *modes, int m, int n,
+                                                     int nboxes, int nrhs) {
+    cpx<R> *yt = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][RC]
+    cpx<R> *part = yt + TS * RC;                        // [4][TS][RC]
+    const int bm = modes[blockIdx.x];
+    const int k = bm % n, box = bm / n;
+    const int r0 = blockIdx.y * RC;
+    const int nr = min(RC, nrhs - r0);
+    const int sblk = block_of_mode[bm];
+    const cpx<R> *A = F + (long long)sblk * m * m;
+    const int *pm = perm + (long long)sblk * m;
+    const long long rstride = (long long)nboxes * m * n;
+    cpx<R> *base = work + (long long)box * m * n + k;
+    const int tid = threadIdx.x;
+    cpx<R> acc[QR][RC];
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+        int i = tid + 256 * q;
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+            acc[q][c] = (i < m && c < nr) ? base[(r0 + c) * rstride + (long long)pm[i] * n] : czero<R>();
+    }
+    const int g = tid >> 6, r = tid & 63;
+    // forward: unit lower L (diagonal tiles hold the strictly lower part of their inverse)
+    for (int t0 = 0; t0 < m; t0 += TS) {
+        const int w = min(TS, m - t0);
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w)
+#pragma unroll
+                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
+        }
+        __syncthreads();
+        {
+            cpx<R> p[RC];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
+            if (r < w)
+                for (int cc = g; cc < r; cc += 4) {
+                    cpx<R> l = A[(long long)(t0 + cc) * m + t0 + r];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) p[c] = p[c] + l * yt[cc * RC + c];
+                }
+#pragma unroll
+            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
+        }
+        __syncthreads();
+        if (tid < w)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                yt[tid * RC + c] = yt[tid * RC + c] + part[tid * RC + c] + part[(TS + tid) * RC + c] +
+                                   part[(2 * TS + tid) * RC + c] + part[(3 * TS + tid) * RC + c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
+            } else if (i >= t0 + w && i < m) {
+                const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 4
+                for (int cc = 0; cc < w; ++cc) {
+                    cpx<R> l = col[(long long)cc * m];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], l, yt[cc * RC + c]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // backward: upper U (diagonal tiles hold the upper part of their inverse)
+    const int ntile = (m + TS - 1) / TS;
+    for (int tt = ntile - 1; tt >= 0; --tt) {
+        const int t0 = tt * TS;
+        const int w = min(TS, m - t0);
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w)
+#pragma unroll
+                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
+        }
+        __syncthreads();
+        {
+            cpx<R> p[RC];
+#pragma unroll
+            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
+            if (r < w)
+                for (int cc = g; cc < w; cc += 4)
+                    if (cc >= r) {
+                        cpx<R> u = A[(long long)(t0 + cc) * m + t0 + r];
+#pragma unroll
+                        for (int c = 0; c < RC; ++c) p[c] = p[c] + u * yt[cc * RC + c];
+                    }
+#pragma unroll
+            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
+        }
+        __syncthreads();
+        if (tid < w)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                yt[tid * RC + c] = part[tid * RC + c] + part[(TS + tid) * RC + c] + part[(2 * TS + tid) * RC + c] +
+                                   part[(3 * TS + tid) * RC + c];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+            int i = tid + 256 * q;
+            if (i >= t0 && i < t0 + w) {
+#pragma unroll
+                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
+            } else if (i < t0) {
+                const cpx<R> *col = A + (long long)t0 * m + i;
+#pragma unroll 4
+                for (int cc = 0; cc < w; ++cc) {
+                    cpx<R> u = col[(long long)cc * m];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], u, yt[cc * RC + c]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+        int i = tid + 256 * q;
+        if (i < m)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < nr) base[(r0 + c) * rstride + (long long)i * n] = acc[q][c];
+    }
+}
+
+#define VIE_MAX_QR 5
+// Columns per chunk: a power of two <= 8, bounded by the register budget of the accumulators.
+static int block_solve_rc(int m, int nrhs, size_t esz) {
+    int qr = (m + 255) / 256;
+    int budget = esz == sizeof(c128) ? 24 : 48;  // complex accumulators per thread
+    int rc = 1;
+    while (rc < 8 && rc < nrhs && qr * rc * 2 <= budget) rc *= 2;
+    return rc;
+}
+
+template <class R, int QR, int RC>
+static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F, const int *perm,
+                      const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
+    hipLaunchKernelGGL((k_block_solve<R, QR, RC>), grid, dim3(256), lds, s, work, F, perm, bom, modes, m, n, nboxes,
+                       nrhs);
+}
+
+template <class R, int QR>
+static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F,
+                         const int *perm, const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
+    switch (rc) {
+        case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
+        case 2: launch_bs<R, QR, 2>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
+        case 4: launch_bs<R, QR, 4>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
+        default: launch_bs<R, QR, 8>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
+    }
+}
+
+// ---------------------------------------------------------------- wide
+// Complex products on the real 16x16x4 matrix-core instruction (FP32 or FP64).  A K-step
+// takes two complex columns c0, c0+1 of the left operand as four real ones: lane l supplies
+// row l%16 and real index q = l/16 (complex column c0 + q/2, part q%2).  With the right operand
+// fed as (Re b, Im b) interleaved, the real left operand (Re a, -Im a) accumulates Re(a b) and
+// (Im a, Re a) accumulates Im(a b).  The accumulator of a 16x16 tile holds, in lane l,
+// register v, the entry (row acc_row(l/16, v), column l%16): row 4*(l/16) + v for FP32 and
+// row 4*v + l/16 for FP64 (measured on gfx950; the operand layouts agree).
+template <class R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 fma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int acc_row(int q, int v) { return 4 * q + v; }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 fma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int acc_row(int q, int v) { return 4 * v + q; }
+};
+
+// acc (16 rows of this wavefront x CT*16 columns) -= A[rows, kb:ke] * Y[kb:ke, :], both
+// operands read from global memory (the factor strip from HBM, the solved rows Y from the
+// caches) with the next batch of K-steps in flight while the current one is multiplied.
+// A is column-major with leading dimension m (arow points at this wavefront's first row);
+// Y is row-major [m][CT*16].
+template <class R, int CT>
+__device__ __forceinline__ void wide_gemm_global(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci,
+                                                 const cpx<R> *arow, long long m, bool rv, const cpx<R> *Y, int kb,
+                                                 int ke) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    constexpr int WC = CT * 16;
+    constexpr int KC = sizeof(R) == 4 ? 4 : 2;
+    const R *yf = reinterpret_cast<const R *>(Y) + p;
+    cpx<R> ca[KC], na[KC];
+    R cb[KC][CT], nb[KC][CT];
+    auto load = [&](int ks0, cpx<R> *a, R (*bb)[CT]) {
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int kc = kb + 2 * (ks0 + u) + kh;
+            const bool in = kc < ke;
+            a[u] = (in && rv) ? arow[(long long)kc * m + r] : czero<R>();
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) bb[u][ct] = in ? yf[((long long)kc * WC + ct * 16 + r) * 2] : R(0);
+        }
+    };
+    const int nks = (ke - kb + 1) / 2;
+    load(0, ca, cb);
+    for (int ks0 = 0; ks0 < nks; ks0 += KC) {
+        if (ks0 + KC < nks) load(ks0 + KC, na, nb);
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const R ar = p ? ca[u].im : -ca[u].re;  // negated (Re a, -Im a)
+            const R ai = p ? -ca[u].re : -ca[u].im; // negated (Im a, Re a)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                cr[ct] = Mfma<R>::fma(ar, cb[u][ct], cr[ct]);
+                ci[ct] = Mfma<R>::fma(ai, cb[u][ct], ci[ct]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            ca[u] = na[u];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) cb[u][ct] = nb[u][ct];
+        }
+    }
+}
+
+// acc (16 rows x CT*16 columns) = T(16 x w) * Xs(w x CT*16) for a diagonal tile: T entries from
+// `t_at(row, kc)`, Xs the LDS tile (row-major [64][CT*16] complex), K-steps [kbeg, kend).
+template <class R, int CT, class TFn>
+__device__ __forceinline__ void wide_gemm_diag(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, const R *xs,
+                                               int kbeg, int kend, TFn t_at) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    constexpr int WC = CT * 16;
+    for (int ks = kbeg; ks < kend; ++ks) {
+        const int kc = 2 * ks + kh;
+        const cpx<R> a = t_at(r, kc);
+        const R ar = p ? -a.im : a.re;
+        const R ai = p ? a.re : a.im;
+        const R *xrow = xs + (size_t)kc * WC * 2 + p;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const R bv = xrow[(ct * 16 + r) * 2];
+            cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
+            ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
+        }
+    }
+}
+
+// Item = (stored block s, first column c0, column count, box).  Column g of block s is the
+// pair (mode modes[mode_ptr[s] + g / nrhs], right-hand side g % nrhs).  Y is a per-item
+// scratch, row-major [m][CT*16], holding y = L^{-1} P b and then x = U^{-1} y.  Left-looking
+// over 64-row tiles i:
+//   forward:  y_i = Linv_ii ((P b)_i - L[i, 0:i] y[0:i])
+//   backward: x_i = Uinv_ii (y_i - U[i, i+1:] x[i+1:])
+// Wavefront w owns rows 16w..16w+15 of the tile and all CT*16 columns; the off-diagonal
+// product is one continuous K loop over the block row; only the diagonal tile goes through LDS.
+// Workgroup b of the grid takes item (b % 8) * per + b / 8 so that the eight XCDs work on
+// contiguous item ranges (neighbouring modes share the cache lines of `work`).
+template <class R, int CT>
+__global__ void __launch_bounds__(256, 2) k_block_solve_wide(cpx<R> *work, const cpx<R> *F, const int *perm,
+                                                             const int4 *items, int nitems, const int *mode_ptr,
+                                                             const int *mode_list, cpx<R> *Y, int m, int n,
+                                                             int nboxes, int nrhs) {
+    typedef typename Mfma<R>::v4 v4;
+    constexpr int WC = CT * 16;
+    const int per = (nitems + 7) / 8;
+    const int it = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (it >= nitems) return;  // whole workgroup, before any barrier
+    const int4 item = items[it];
+    const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
+    cpx<R> *xs_c = reinterpret_cast<cpx<R> *>(vie_smem);  // [64][WC]
+    const R *xs = reinterpret_cast<const R *>(vie_smem);
+    const cpx<R> *A = F + (long long)sblk * m * m;
+    const int *pm = perm + (long long)sblk * m;
+    cpx<R> *Yi = Y + (long long)it * m * WC;
+    const long long rstride = (long long)nboxes * m * n;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int srow = 16 * wv;  // first tile row of this wavefront
+    long long off[CT];         // column base offsets in work (-1: no column)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + r;
+        off[ct] = -1;
+        if (col < ncols) {
+            const int g = c0 + col;
+            const int mode = mode_list[mode_ptr[sblk] + g / nrhs];
+            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode;
+        }
+    }
+    const int T = (m + TS - 1) / TS;
+    v4 cr[CT], ci[CT];
+    auto publish = [&]() {  // accumulators -> LDS tile
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                xs_c[(srow + Mfma<R>::acc_row(q, v)) * WC + ct * 16 + r] = mk(cr[ct][v], ci[ct][v]);
+    };
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            cr[ct] = v4{0, 0, 0, 0};
+            ci[ct] = v4{0, 0, 0, 0};
+        }
+    };
+    // ---- forward
+    for (int ti = 0; ti < T; ++ti) {
+        const int t0 = ti * TS, w = min(TS, m - t0);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = t0 + srow + Mfma<R>::acc_row(q, v);
+                cpx<R> b = (row < m && off[ct] >= 0) ? work[off[ct] + (long long)pm[row] * n] : czero<R>();
+                cr[ct][v] = b.re;
+                ci[ct][v] = b.im;
+            }
+        if (t0 > 0) wide_gemm_global<R, CT>(cr, ci, A + t0 + srow, m, t0 + srow + r < m, Yi, 0, t0);
+        publish();
+        __syncthreads();
+        zero_acc();
+        {
+            const cpx<R> *Aii = A + (long long)t0 * m + t0;
+            const int kend = min((w + 1) / 2, 8 * (wv + 1));  // unit-lower: columns <= row
+            wide_gemm_diag<R, CT>(cr, ci, xs, 0, kend, [&](int rr, int kc) -> cpx<R> {
+                const int row = srow + rr;
+                if (row >= w || kc >= w || kc > row) return czero<R>();
+                if (kc == row) return mk(R(1), R(0));
+                return Aii[(long long)kc * m + row];
+            });
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = srow + Mfma<R>::acc_row(q, v);
+                if (row < w) Yi[(long long)(t0 + row) * WC + ct * 16 + r] = mk(cr[ct][v], ci[ct][v]);
+            }
+        __syncthreads();  // y_i visible to every wavefront; LDS tile free
+    }
+    // ---- backward (x_i over y_i in Y)
+    for (int ti = T - 1; ti >= 0; --ti) {
+        const int t0 = ti * TS, w = min(TS, m - t0);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = srow + Mfma<R>::acc_row(q, v);
+                cpx<R> y = row < w ? Yi[(long long)(t0 + row) * WC + ct * 16 + r] : czero<R>();
+                cr[ct][v] = y.re;
+                ci[ct][v] = y.im;
+            }
+        if (t0 + w < m) wide_gemm_global<R, CT>(cr, ci, A + t0 + srow, m, srow + r < w, Yi, t0 + w, m);
+        publish();
+        __syncthreads();
+        zero_acc();
+        {
+            const cpx<R> *Aii = A + (long long)t0 * m + t0;
+            const int kbeg = 8 * wv;  // upper: columns >= row
+            wide_gemm_diag<R, CT>(cr, ci, xs, kbeg, (w + 1) / 2, [&](int rr, int kc) -> cpx<R> {
+                const int row = srow + rr;
+                if (row >= w || kc >= w || kc < row) return czero<R>();
+                return Aii[(long long)kc * m + row];
+            });
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = srow + Mfma<R>::acc_row(q, v);
+                if (row < w) {
+                    const cpx<R> x = mk(cr[ct][v], ci[ct][v]);
+                    Yi[(long long)(t0 + row) * WC + ct * 16 + r] = x;
+                    if (off[ct] >= 0) work[off[ct] + (long long)(t0 + row) * n] = x;
+                }
+            }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- schedule + launch
+#define WIDE_MIN_COLS 16
+#define WIDE_MAX_COLS 64
+
+// Split the stored blocks between the two kernels for `nrhs` right-hand sides and upload the
+// tables (only when nrhs changed since the last apply).
+static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
+    if (pc->sched_nrhs == nrhs) return VIE_OK;
+    const int n = pc->bx;
+    std::vector<int> wide;    // int4 items
+    std::vector<int> narrow;  // box * n + mode
+    int maxc = 0;
+    for (int sb = 0; sb < pc->nstored; ++sb) {
+        const int cnt = pc->mode_ptr[sb + 1] - pc->mode_ptr[sb];
+        const long long cols = (long long)cnt * nrhs;
+        if (cols >= WIDE_MIN_COLS) {
+            const long long ng = (cols + WIDE_MAX_COLS - 1) / WIDE_MAX_COLS;
+            const long long per = (cols + ng - 1) / ng;
+            for (long long c = 0; c < cols; c += per) {
+                const int nc = (int)std::min(per, cols - c);
+                wide.insert(wide.end(), {sb, (int)c, nc, pc->block_box[sb]});
+                maxc = std::max(maxc, nc);
+            }
+        } else {
+            for (int e = pc->mode_ptr[sb]; e < pc->mode_ptr[sb + 1]; ++e)
+                narrow.push_back(pc->block_box[sb] * n + pc->mode_list[e]);
+        }
+    }
+    pc->n_wide = (int)(wide.size() / 4);
+    pc->n_narrow = (int)narrow.size();
+    pc->wide_ct = maxc <= 16 ? 1 : maxc <= 32 ? 2 : 4;
+    std::vector<int> tab(wide);
+    tab.insert(tab.end(), narrow.begin(), narrow.end());
+    VIE_CHECK(pc->sched.ensure(sizeof(int) * std::max<size_t>(tab.size(), 4)));
+    VIE_HIP(hipMemcpyAsync(pc->sched.p, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s));
+    VIE_HIP(hipStreamSynchronize(s));  // the host table is freed on return
+    pc->sched_nrhs = nrhs;
+    return VIE_OK;
+}
+
+template <class R, int CT>
+static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, hipStream_t s) {
+    const int per = (pc->n_wide + 7) / 8;
+    const size_t lds = sizeof(cpx<R>) * TS * CT * 16;
+    vie_lds_attr((const void *)k_block_solve_wide<R, CT>, lds);
+    const int *mp = pc->modes_dev.as<const int>();
+    hipLaunchKernelGGL((k_block_solve_wide<R, CT>), dim3(8 * per), dim3(256), lds, s, work,
+                       pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(), pc->sched.as<const int4>(),
+                       pc->n_wide, mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs);
+}
+
+template <class R>
+static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
+    const int m = pc->m, n = pc->bx;
+    const int qr = (m + 255) / 256;
+    if (qr > VIE_MAX_QR) {
+        vie_set_error("block size above 1280 is not supported by the block solve");
+        return VIE_EARG;
+    }
+    VIE_CHECK(build_schedule(pc, nrhs, s));
+    if (pc->n_wide > 0) {
+        const int WC = 16 * pc->wide_ct;
+        VIE_CHECK(pc->wide_scratch.ensure(sizeof(cpx<R>) * (size_t)pc->n_wide * m * WC));
+        cpx<R> *Y = pc->wide_scratch.as<cpx<R>>();
+        switch (pc->wide_ct) {
+            case 1: launch_wide<R, 1>(pc, work, Y, nrhs, s); break;
+            case 2: launch_wide<R, 2>(pc, work, Y, nrhs, s); break;
+            default: launch_wide<R, 4>(pc, work, Y, nrhs, s); break;
+        }
+        VIE_HIP(hipGetLastError());
+    }
+    if (pc->n_narrow > 0) {
+        const int rc = block_solve_rc(m, nrhs, sizeof(cpx<R>));
+        dim3 grid((unsigned)pc->n_narrow, (unsigned)((nrhs + rc - 1) / rc));
+        size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
+        const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
+        const cpx<R> *F = pc->factors.as<const cpx<R>>();
+        const int *perm = pc->perm.as<const int>(), *bom = pc->block_of_mode.as<const int>();
+        switch (qr) {
+            case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+            case 2: launch_bs_rc<R, 2>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+            case 3: launch_bs_rc<R, 3>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+            case 4: launch_bs_rc<R, 4>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+            default: launch_bs_rc<R, 5>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+        }
+        VIE_HIP(hipGetLastError());
+    }
+    return VIE_OK;
+}
+
+vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s) {
+    if (pc->prec == VIE_C128) return block_solve_t<double>(pc, (c128 *)work, nrhs, s);
+    return block_solve_t<float>(pc, (c64 *)work, nrhs, s);
+}

@@ -209,6 +209,14 @@ __global__ void k_xfwd(const cpx<R> *x, cpx<R> *work, int nx, FftPlan plan) {
     for (int i = threadIdx.x; i < plan.L; i += blockDim.x) dst[i] = res[i];
 }
 
+// Block b of a grid of 8 * ceil(count / 8) works on index (b % 8) * ceil(count / 8) + b / 8
+// (>= count: nothing): workgroups are dealt to the eight XCDs round-robin, so each XCD gets
+// a contiguous range and neighbouring x-frequencies share the L2 lines of their strided rows.
+__device__ __forceinline__ int xcd_block(int b, int count) {
+    const int per = (count + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
 // pass 2: one workgroup per (PLANE_KB consecutive x-frequencies, rhs); the planes are
 // processed one after another so the cache lines of the strided gathers are reused.
 #define PLANE_KB 1
@@ -220,7 +228,7 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
     cpx<R> *b = a + 3 * plane;
     for (int kk = 0; kk < PLANE_KB; ++kk) {
-    const int kx = blockIdx.x * PLANE_KB + kk;
+    const int kx = xcd_block(blockIdx.x * PLANE_KB + kk, Px);
     if (kx >= Px) break;
     cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
     __syncthreads();
@@ -298,7 +306,8 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);  // [3][nz][Py] lines
     cpx<R> *b = a + rows * Py;                          // [3][nz][Py] second buffer
     cpx<R> *G = b + rows * Py;                          // [nz][6][Hy] (y-frequency fastest)
-    const int kx = blockIdx.x;
+    const int kx = xcd_block(blockIdx.x, Px);
+    if (kx >= Px) return;
     const int kxo = kx <= Px - kx ? kx : Px - kx;
     const bool fx = kx > Px - kx;
     cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
@@ -399,13 +408,14 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
         int thr = 256;
         vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane_dz<R>, dim3(Px, nrhs), dim3(thr), ldsp, s, work, khat, ny, nz, Px, op->Hy, op->py);
+        hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thr), ldsp, s, work, khat, ny, nz, Px,
+                           op->Hy, op->py);
     } else {
         size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
         vie_lds_attr((const void *)k_plane<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane<R>, dim3((Px + PLANE_KB - 1) / PLANE_KB, nrhs), dim3(256), ldsp, s, work, khat, ny,
-                           nz, Px, op->Hx, op->Hy, op->Hz, op->py, op->pz);
+        hipLaunchKernelGGL(k_plane<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px,
+                           op->Hx, op->Hy, op->Hz, op->py, op->pz);
     }
     VIE_HIP(hipGetLastError());
     {

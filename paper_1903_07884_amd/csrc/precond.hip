@@ -720,198 +720,6 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
 }
 
-// One workgroup per (box, mode, chunk of RC right-hand sides):
-//   z_k = U^{-1} L^{-1} P rhat_k  in place in `work` for RC columns at once.
-// Thread t owns rows t, t + 256, ... (QR of them) and keeps their RC accumulators in
-// registers.  Forward and backward substitution run over 64-row tiles: the tile's owners
-// publish its rows to LDS, four wavefronts apply the pre-inverted diagonal tile (each a
-// quarter of its columns), and every thread then applies the tile's column panel to its
-// remaining rows.  Each factor entry is read once per chunk and used RC times; the factor
-// reads are coalesced along columns.  work element (rhs, box, row i, mode k) sits at
-// ((rhs * nboxes + box) * m + i) * n + k.
-template <class R, int QR, int RC>
-__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm,
-                                                     const int *block_of_mode, int m, int n, int nboxes, int nrhs) {
-    cpx<R> *yt = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][RC]
-    cpx<R> *part = yt + TS * RC;                        // [4][TS][RC]
-    const int k = blockIdx.x % n, box = blockIdx.x / n;
-    const int r0 = blockIdx.y * RC;
-    const int nr = min(RC, nrhs - r0);
-    const int sblk = block_of_mode[box * n + k];
-    const cpx<R> *A = F + (long long)sblk * m * m;
-    const int *pm = perm + (long long)sblk * m;
-    const long long rstride = (long long)nboxes * m * n;
-    cpx<R> *base = work + (long long)box * m * n + k;
-    const int tid = threadIdx.x;
-    cpx<R> acc[QR][RC];
-#pragma unroll
-    for (int q = 0; q < QR; ++q) {
-        int i = tid + 256 * q;
-#pragma unroll
-        for (int c = 0; c < RC; ++c)
-            acc[q][c] = (i < m && c < nr) ? base[(r0 + c) * rstride + (long long)pm[i] * n] : czero<R>();
-    }
-    const int g = tid >> 6, r = tid & 63;
-    // forward: unit lower L (diagonal tiles hold the strictly lower part of their inverse)
-    for (int t0 = 0; t0 < m; t0 += TS) {
-        const int w = min(TS, m - t0);
-#pragma unroll
-        for (int q = 0; q < QR; ++q) {
-            int i = tid + 256 * q;
-            if (i >= t0 && i < t0 + w)
-#pragma unroll
-                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
-        }
-        __syncthreads();
-        {
-            cpx<R> p[RC];
-#pragma unroll
-            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
-            if (r < w)
-                for (int cc = g; cc < r; cc += 4) {
-                    cpx<R> l = A[(long long)(t0 + cc) * m + t0 + r];
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) p[c] = p[c] + l * yt[cc * RC + c];
-                }
-#pragma unroll
-            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
-        }
-        __syncthreads();
-        if (tid < w)
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-                yt[tid * RC + c] = yt[tid * RC + c] + part[tid * RC + c] + part[(TS + tid) * RC + c] +
-                                   part[(2 * TS + tid) * RC + c] + part[(3 * TS + tid) * RC + c];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QR; ++q) {
-            int i = tid + 256 * q;
-            if (i >= t0 && i < t0 + w) {
-#pragma unroll
-                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
-            } else if (i >= t0 + w && i < m) {
-                const cpx<R> *col = A + (long long)t0 * m + i;
-#pragma unroll 4
-                for (int cc = 0; cc < w; ++cc) {
-                    cpx<R> l = col[(long long)cc * m];
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], l, yt[cc * RC + c]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // backward: upper U (diagonal tiles hold the upper part of their inverse)
-    const int ntile = (m + TS - 1) / TS;
-    for (int tt = ntile - 1; tt >= 0; --tt) {
-        const int t0 = tt * TS;
-        const int w = min(TS, m - t0);
-#pragma unroll
-        for (int q = 0; q < QR; ++q) {
-            int i = tid + 256 * q;
-            if (i >= t0 && i < t0 + w)
-#pragma unroll
-                for (int c = 0; c < RC; ++c) yt[(i - t0) * RC + c] = acc[q][c];
-        }
-        __syncthreads();
-        {
-            cpx<R> p[RC];
-#pragma unroll
-            for (int c = 0; c < RC; ++c) p[c] = czero<R>();
-            if (r < w)
-                for (int cc = g; cc < w; cc += 4)
-                    if (cc >= r) {
-                        cpx<R> u = A[(long long)(t0 + cc) * m + t0 + r];
-#pragma unroll
-                        for (int c = 0; c < RC; ++c) p[c] = p[c] + u * yt[cc * RC + c];
-                    }
-#pragma unroll
-            for (int c = 0; c < RC; ++c) part[(g * TS + r) * RC + c] = p[c];
-        }
-        __syncthreads();
-        if (tid < w)
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-                yt[tid * RC + c] = part[tid * RC + c] + part[(TS + tid) * RC + c] + part[(2 * TS + tid) * RC + c] +
-                                   part[(3 * TS + tid) * RC + c];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QR; ++q) {
-            int i = tid + 256 * q;
-            if (i >= t0 && i < t0 + w) {
-#pragma unroll
-                for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
-            } else if (i < t0) {
-                const cpx<R> *col = A + (long long)t0 * m + i;
-#pragma unroll 4
-                for (int cc = 0; cc < w; ++cc) {
-                    cpx<R> u = col[(long long)cc * m];
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], u, yt[cc * RC + c]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < QR; ++q) {
-        int i = tid + 256 * q;
-        if (i < m)
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-                if (c < nr) base[(r0 + c) * rstride + (long long)i * n] = acc[q][c];
-    }
-}
-
-#define VIE_MAX_QR 5
-// Columns per chunk: a power of two <= 8, bounded by the register budget of the accumulators.
-static int block_solve_rc(int m, int nrhs, size_t esz) {
-    int qr = (m + 255) / 256;
-    int budget = esz == sizeof(c128) ? 24 : 48;  // complex accumulators per thread
-    int rc = 1;
-    while (rc < 8 && rc < nrhs && qr * rc * 2 <= budget) rc *= 2;
-    return rc;
-}
-
-template <class R, int QR, int RC>
-static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F, const int *perm,
-                      const int *bom, int m, int n, int nboxes, int nrhs) {
-    hipLaunchKernelGGL((k_block_solve<R, QR, RC>), grid, dim3(256), lds, s, work, F, perm, bom, m, n, nboxes, nrhs);
-}
-
-template <class R, int QR>
-static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F,
-                         const int *perm, const int *bom, int m, int n, int nboxes, int nrhs) {
-    switch (rc) {
-        case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        case 2: launch_bs<R, QR, 2>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        case 4: launch_bs<R, QR, 4>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        default: launch_bs<R, QR, 8>(grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-    }
-}
-
-template <class R>
-static vie_status launch_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm, const int *bom, int m, int n,
-                                     int nboxes, int nrhs, hipStream_t s) {
-    const int qr = (m + 255) / 256;
-    if (qr > VIE_MAX_QR) {
-        vie_set_error("block size above 1280 is not supported by the block solve");
-        return VIE_EARG;
-    }
-    const int rc = block_solve_rc(m, nrhs, sizeof(cpx<R>));
-    dim3 grid((unsigned)(nboxes * n), (unsigned)((nrhs + rc - 1) / rc));
-    size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
-    switch (qr) {
-        case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        case 2: launch_bs_rc<R, 2>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        case 3: launch_bs_rc<R, 3>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        case 4: launch_bs_rc<R, 4>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-        default: launch_bs_rc<R, 5>(rc, grid, lds, s, work, F, perm, bom, m, n, nboxes, nrhs); break;
-    }
-    VIE_HIP(hipGetLastError());
-    return VIE_OK;
-}
-
 // ---------------------------------------------------------------- host side
 template <class R>
 static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
@@ -938,8 +746,7 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("block_solve", s);
-        VIE_CHECK(launch_block_solve<R>(work, pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(),
-                                        pc->block_of_mode.as<const int>(), m, n, pc->nboxes, nrhs, s));
+        VIE_CHECK(launch_block_solve(pc, work, nrhs, s));
     }
     {
         ProfScope ps("precond_ixfft", s);
@@ -1085,6 +892,25 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             if (!keep[k]) pc->block_of_mode_host[(size_t)b * n + k] = cs;
     }
     pc->nstored = (int)smode.size();
+    // per stored block: the modes that use it (block-solve columns) and its box
+    pc->mode_ptr.assign(pc->nstored + 1, 0);
+    pc->mode_list.clear();
+    pc->block_box = sbox;
+    for (int b = 0; b < nbx; ++b)
+        for (int k = 0; k < n; ++k) pc->mode_ptr[pc->block_of_mode_host[(size_t)b * n + k] + 1]++;
+    for (int sb = 0; sb < pc->nstored; ++sb) pc->mode_ptr[sb + 1] += pc->mode_ptr[sb];
+    pc->mode_list.assign(pc->mode_ptr[pc->nstored], 0);
+    {
+        std::vector<int> fill(pc->mode_ptr.begin(), pc->mode_ptr.end() - 1);
+        for (int b = 0; b < nbx; ++b)
+            for (int k = 0; k < n; ++k) pc->mode_list[fill[pc->block_of_mode_host[(size_t)b * n + k]]++] = k;
+    }
+    pc->sched_nrhs = 0;
+    VIE_CHECK(pc->modes_dev.ensure(sizeof(int) * (pc->mode_ptr.size() + pc->mode_list.size())));
+    VIE_HIP(hipMemcpyAsync(pc->modes_dev.p, pc->mode_ptr.data(), sizeof(int) * pc->mode_ptr.size(),
+                           hipMemcpyHostToDevice, s));
+    VIE_HIP(hipMemcpyAsync(pc->modes_dev.as<int>() + pc->mode_ptr.size(), pc->mode_list.data(),
+                           sizeof(int) * pc->mode_list.size(), hipMemcpyHostToDevice, s));
     // device block map followed by the boxes (apply kernels read both)
     VIE_CHECK(pc->block_of_mode.ensure(sizeof(int) * ((size_t)nbx * n + 6 * nbx)));
     VIE_HIP(hipMemcpyAsync(pc->block_of_mode.p, pc->block_of_mode_host.data(), sizeof(int) * (size_t)nbx * n,

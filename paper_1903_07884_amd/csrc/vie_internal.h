@@ -153,6 +153,14 @@ struct vie_pc_s {
     DevBuf info;             // int32 [nstored] 0 or first zero-pivot column + 1
     DevBuf work;             // apply scratch: nrhs * nboxes * 3*by*bz * bx complex (factor prec)
     FftPlan pxb;             // length bx
+    // block-solve schedule
+    std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending)
+    std::vector<int> block_box;            // box of stored block s
+    DevBuf modes_dev;                      // int32 mode_ptr [nstored+1] then mode_list
+    int sched_nrhs = 0;                    // nrhs the tables below were built for
+    int n_wide = 0, n_narrow = 0, wide_ct = 1;
+    DevBuf sched;                          // int4 wide items [n_wide] then int32 box*bx+mode [n_narrow]
+    DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
 };
 
 // ---------------------------------------------------------------- profiling
@@ -176,6 +184,8 @@ vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t 
 // precond.hip
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
 vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s);
+// block_solve.hip: the per-mode block solves, in place in the apply work buffer
+vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s);
 // krylov.hip
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int nrhs,
                        const vie_solve_opts *o, vie_solve_stats *stats, hipStream_t s);

@@ -182,6 +182,44 @@ def test_precond_apply_matches_oracle(gpu_lib, case):
     assert err < 1e-10
 
 
+WIDE_CASES = [
+    # grid (m = 3 ny nz), nrhs, reduce_tol, factor precision
+    ((16, 4, 2), 16, None, 'c128'),      # m = 24: one ragged tile, 16 columns
+    ((24, 6, 4), 20, None, 'c128'),      # m = 72: full + ragged tile, 20 columns (32-wide groups)
+    ((32, 8, 6), 64, None, 'c128'),      # m = 144: three tiles, 64 columns
+    ((32, 8, 6), 70, None, 'c128'),      # two column groups per block
+    ((32, 8, 6), 1, 1e-2, 'c128'),       # R = 1: the shared central block goes wide
+    ((24, 6, 4), 33, None, 'c64'),
+    ((32, 8, 6), 64, 1e-2, 'c64'),
+]
+
+
+@pytest.mark.parametrize("case", WIDE_CASES)
+def test_precond_apply_many_rhs(gpu_lib, case):
+    """Blocks used by >= 16 (mode, rhs) columns take the matrix-core block solve."""
+    import torch
+    grid, nrhs, tol, prec = case
+    delta = 50e-9
+    K = oracle_generator(grid, delta)
+    chi = random_contrast(grid, 12)
+    chi = np.broadcast_to(chi[:, :, :1], chi.shape).copy()     # x-invariant: M~ = M
+    M = OCT.contrast_from_chi(chi)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid, reduce_tol=tol)
+    c64 = prec == 'c64'
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=c64)
+    pc = gpu_lib.Preconditioner(op, reduce_tol=tol, factor_prec=gpu_lib.VIE_C64 if c64 else gpu_lib.VIE_C128)
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((nrhs, n), 41)
+    z_ref = np.stack([ref_pc.apply(r[i]) for i in range(nrhs)])
+    rd = _to_dev(r.astype(np.complex64) if c64 else r)
+    zd = torch.empty_like(rd)
+    pc.apply(rd, zd, nrhs=nrhs)
+    z = zd.cpu().numpy().astype(np.complex128)
+    errs = [_rel(z[i], z_ref[i]) for i in range(nrhs)]
+    print('wide', grid, nrhs, tol, prec, 'max err', max(errs), 'stored', pc.info()['stored_blocks'])
+    assert max(errs) < (1e-5 if c64 else 1e-10)
+
+
 @pytest.mark.parametrize("precond", [False, True])
 def test_solve_matches_oracle_gmres(gpu_lib, precond):
     import torch
