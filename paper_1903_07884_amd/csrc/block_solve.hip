@@ -218,110 +218,167 @@ struct Mfma<double> {
     static __device__ __forceinline__ int acc_row(int q, int v) { return 4 * v + q; }
 };
 
+// The matrix-core products below keep one batch of K-steps in flight while the previous one
+// is multiplied: loads are issued unconditionally from addresses clamped into the buffers
+// (masks are applied to the loaded values), and two register sets alternate, so the waits
+// only cover the older batch.
+
 // acc (16 rows of this wavefront x CT*16 columns) -= A[rows, kb:ke] * Y[kb:ke, :], both
-// operands read from global memory (the factor strip from HBM, the solved rows Y from the
-// caches) with the next batch of K-steps in flight while the current one is multiplied.
-// A is column-major with leading dimension m (arow points at this wavefront's first row);
-// Y is row-major [m][CT*16].
+// operands from global memory (the factor strip from HBM, the solved rows Y from the caches).
+// A is column-major with leading dimension m: arow points at this wavefront's first row,
+// abase at row 0 of the block (used for rows past m, whose results are discarded).  Y is
+// row-major [m][CT*16].  The K-steps run in the rotated order rot, rot+1, ..., nks-1, 0, ...
+// so that workgroups sharing one factor (the memory-reduced central block) read different
+// parts of it at a time.
 template <class R, int CT>
 __device__ __forceinline__ void wide_gemm_global(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci,
-                                                 const cpx<R> *arow, long long m, bool rv, const cpx<R> *Y, int kb,
-                                                 int ke) {
+                                                 const cpx<R> *arow, const cpx<R> *abase, long long m, bool rv,
+                                                 const cpx<R> *Y, int kb, int ke, int rot) {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     constexpr int WC = CT * 16;
-    constexpr int KC = sizeof(R) == 4 ? 4 : 2;
+    constexpr int KC = 2;
     const R *yf = reinterpret_cast<const R *>(Y) + p;
-    cpx<R> ca[KC], na[KC];
-    R cb[KC][CT], nb[KC][CT];
-    auto load = [&](int ks0, cpx<R> *a, R (*bb)[CT]) {
+    const cpx<R> *ap = rv ? arow + r : abase;
+    const int nks = (ke - kb + 1) / 2;
+    rot = rot % nks;
+    cpx<R> a0[KC], a1[KC];
+    R b0[KC][CT], b1[KC][CT];
+    bool m0[KC], m1[KC];
+    auto load = [&](int ks0, cpx<R> *a, R (*bb)[CT], bool *msk) {
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
-            const int kc = kb + 2 * (ks0 + u) + kh;
-            const bool in = kc < ke;
-            a[u] = (in && rv) ? arow[(long long)kc * m + r] : czero<R>();
+            int ks = ks0 + u + rot;
+            if (ks >= nks) ks -= nks;
+            const int kc = kb + 2 * ks + kh;
+            const bool in = kc < ke && ks0 + u < nks;
+            const int kcl = in ? kc : kb;
+            msk[u] = in;
+            a[u] = ap[(long long)kcl * m];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) bb[u][ct] = in ? yf[((long long)kc * WC + ct * 16 + r) * 2] : R(0);
+            for (int ct = 0; ct < CT; ++ct) bb[u][ct] = yf[((long long)kcl * WC + ct * 16 + r) * 2];
         }
     };
-    const int nks = (ke - kb + 1) / 2;
-    load(0, ca, cb);
-    for (int ks0 = 0; ks0 < nks; ks0 += KC) {
-        if (ks0 + KC < nks) load(ks0 + KC, na, nb);
+    auto compute = [&](const cpx<R> *a, R (*bb)[CT], const bool *msk) {
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
-            const R ar = p ? ca[u].im : -ca[u].re;  // negated (Re a, -Im a)
-            const R ai = p ? -ca[u].re : -ca[u].im; // negated (Im a, Re a)
+            const R ar = p ? a[u].im : -a[u].re;   // negated (Re a, -Im a)
+            const R ai = p ? -a[u].re : -a[u].im;  // negated (Im a, Re a)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                cr[ct] = Mfma<R>::fma(ar, cb[u][ct], cr[ct]);
-                ci[ct] = Mfma<R>::fma(ai, cb[u][ct], ci[ct]);
+                const R bv = msk[u] ? bb[u][ct] : R(0);
+                cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
+                ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
             }
         }
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            ca[u] = na[u];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) cb[u][ct] = nb[u][ct];
-        }
+    };
+    // sched_barrier(0): the scheduler may not move instructions across it, which keeps each
+    // batch's loads one compute phase ahead of their use
+    load(0, a0, b0, m0);
+    for (int ks0 = 0; ks0 < nks; ks0 += 2 * KC) {
+        load(ks0 + KC, a1, b1, m1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a0, b0, m0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks0 + KC >= nks) break;
+        load(ks0 + 2 * KC, a0, b0, m0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a1, b1, m1);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// acc (16 rows x CT*16 columns) = T(16 x w) * Xs(w x CT*16) for a diagonal tile: T entries from
-// `t_at(row, kc)`, Xs the LDS tile (row-major [64][CT*16] complex), K-steps [kbeg, kend).
-template <class R, int CT, class TFn>
-__device__ __forceinline__ void wide_gemm_diag(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, const R *xs,
-                                               int kbeg, int kend, TFn t_at) {
+// acc (16 rows x CT*16 columns) += T(16 x w) * Xs(w x CT*16) over K-steps [kbeg, kend): T
+// entries loaded from `t_ptr(row, kc)` (always a valid address) and passed through
+// `t_val(row, kc, loaded)`; Xs is an LDS tile, row-major [64][CT*16] complex.
+template <class R, int CT, class TPtr, class TVal>
+__device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, const R *xs,
+                                              int kbeg, int kend, TPtr t_ptr, TVal t_val) {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     constexpr int WC = CT * 16;
-    for (int ks = kbeg; ks < kend; ++ks) {
-        const int kc = 2 * ks + kh;
-        const cpx<R> a = t_at(r, kc);
-        const R ar = p ? -a.im : a.re;
-        const R ai = p ? a.re : a.im;
-        const R *xrow = xs + (size_t)kc * WC * 2 + p;
+    constexpr int KC = 2;
+    cpx<R> a0[KC], a1[KC];
+    auto load = [&](int ks0, cpx<R> *a) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            const R bv = xrow[(ct * 16 + r) * 2];
-            cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
-            ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
+        for (int u = 0; u < KC; ++u) {
+            const int kc = 2 * (ks0 + u) + kh;
+            a[u] = *t_ptr(r, kc < 64 ? kc : 63);
         }
+    };
+    auto compute = [&](int ks0, const cpx<R> *a) {
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int ks = ks0 + u;
+            const int kc = 2 * ks + kh;
+            const cpx<R> t = (ks < kend) ? t_val(r, kc, a[u]) : czero<R>();
+            const R ar = p ? -t.im : t.re;
+            const R ai = p ? t.re : t.im;
+            const R *xrow = xs + (size_t)(kc < 64 ? kc : 63) * WC * 2 + p;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const R bv = xrow[(ct * 16 + r) * 2];
+                cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
+                ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
+            }
+        }
+    };
+    if (kbeg >= kend) return;
+    load(kbeg, a0);
+    for (int ks0 = kbeg; ks0 < kend; ks0 += 2 * KC) {
+        load(ks0 + KC, a1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ks0, a0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks0 + KC >= kend) break;
+        load(ks0 + 2 * KC, a0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ks0 + KC, a1);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 // Item = (stored block s, first column c0, column count, box).  Column g of block s is the
 // pair (mode modes[mode_ptr[s] + g / nrhs], right-hand side g % nrhs).  Y is a per-item
-// scratch, row-major [m][CT*16], holding y = L^{-1} P b and then x = U^{-1} y.  Left-looking
-// over 64-row tiles i:
-//   forward:  y_i = Linv_ii ((P b)_i - L[i, 0:i] y[0:i])
-//   backward: x_i = Uinv_ii (y_i - U[i, i+1:] x[i+1:])
-// Wavefront w owns rows 16w..16w+15 of the tile and all CT*16 columns; the off-diagonal
-// product is one continuous K loop over the block row; only the diagonal tile goes through LDS.
+// scratch, row-major [m][CT*16], holding y = L^{-1} P b and then x = U^{-1} y.
+//
+// NW wavefronts own 16 rows each of a super-tile of 16*NW rows (NW/4 tiles of 64 rows).
+// Forward, per super-tile S:
+//   acc = (P b)_S - L[S, 0:S] y[0:S]         one continuous K loop, every wavefront
+//   for each tile i of S in order:
+//     y_i = Linv_ii acc_i                     the tile's 4 wavefronts, through LDS
+//     acc_j -= L[j, i] y_i  for tiles j > i of S   (y_i read from LDS)
+// and backward the same with U from the last super-tile down.  The already solved rows are
+// re-read once per super-tile (not once per tile), and with one workgroup per CU the
+// per-item scratch of all resident workgroups stays in the last-level cache.
 // Workgroup b of the grid takes item (b % 8) * per + b / 8 so that the eight XCDs work on
 // contiguous item ranges (neighbouring modes share the cache lines of `work`).
-template <class R, int CT>
-__global__ void __launch_bounds__(256, 2) k_block_solve_wide(cpx<R> *work, const cpx<R> *F, const int *perm,
-                                                             const int4 *items, int nitems, const int *mode_ptr,
-                                                             const int *mode_list, cpx<R> *Y, int m, int n,
-                                                             int nboxes, int nrhs) {
+template <class R, int CT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, const cpx<R> *F, const int *perm,
+                                                               const int4 *items, int nitems, const int *mode_ptr,
+                                                               const int *mode_list, cpx<R> *Y, int m, int n,
+                                                               int nboxes, int nrhs) {
     typedef typename Mfma<R>::v4 v4;
     constexpr int WC = CT * 16;
+    constexpr int ST = 16 * NW;  // rows per super-tile
     const int per = (nitems + 7) / 8;
     const int it = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (it >= nitems) return;  // whole workgroup, before any barrier
     const int4 item = items[it];
     const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
-    cpx<R> *xs_c = reinterpret_cast<cpx<R> *>(vie_smem);  // [64][WC]
-    const R *xs = reinterpret_cast<const R *>(vie_smem);
+    cpx<R> *xs_c = reinterpret_cast<cpx<R> *>(vie_smem);  // [64][WC]: tile accumulators
+    cpx<R> *ys_c = xs_c + TS * WC;                         // [64][WC]: solved tile
+    const R *xs = reinterpret_cast<const R *>(xs_c);
+    const R *ys = reinterpret_cast<const R *>(ys_c);
     const cpx<R> *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     cpx<R> *Yi = Y + (long long)it * m * WC;
     const long long rstride = (long long)nboxes * m * n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
-    const int srow = 16 * wv;  // first tile row of this wavefront
-    long long off[CT];         // column base offsets in work (-1: no column)
+    const int sub = wv >> 2;             // tile of this wavefront within the super-tile
+    const int wrow = 16 * (wv & 3);      // first row of this wavefront within its tile
+    long long off[CT];                   // column base offsets in work (-1: no column)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
@@ -332,15 +389,8 @@ __global__ void __launch_bounds__(256, 2) k_block_solve_wide(cpx<R> *work, const
             off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode;
         }
     }
-    const int T = (m + TS - 1) / TS;
+    const int NS = (m + ST - 1) / ST;
     v4 cr[CT], ci[CT];
-    auto publish = [&]() {  // accumulators -> LDS tile
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                xs_c[(srow + Mfma<R>::acc_row(q, v)) * WC + ct * 16 + r] = mk(cr[ct][v], ci[ct][v]);
-    };
     auto zero_acc = [&]() {
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
@@ -348,77 +398,110 @@ __global__ void __launch_bounds__(256, 2) k_block_solve_wide(cpx<R> *work, const
             ci[ct] = v4{0, 0, 0, 0};
         }
     };
+    // tile step of tile `tt` (rows t0..t0+w) inside a super-tile: the owners solve it, the
+    // other wavefronts of the super-tile selected by `later` apply its column block.
+    auto tile_step = [&](int tt, int t0, int w, bool lower, int s0) {
+        const bool owner = sub == tt;
+        if (owner) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    xs_c[(wrow + Mfma<R>::acc_row(q, v)) * WC + ct * 16 + r] = mk(cr[ct][v], ci[ct][v]);
+        }
+        __syncthreads();
+        if (owner) {
+            zero_acc();
+            const cpx<R> *Aii = A + (long long)t0 * m + t0;
+            const int wl = wv & 3;
+            // addresses clamped into the tile (rows/columns >= w read entry (0, 0))
+            auto tptr = [&](int rr, int kc) -> const cpx<R> * {
+                const int row = wrow + rr;
+                return (row < w && kc < w) ? Aii + (long long)kc * m + row : Aii;
+            };
+            if (lower)
+                wide_gemm_lds<R, CT>(cr, ci, xs, 0, min((w + 1) / 2, 8 * (wl + 1)), tptr,
+                                     [&](int rr, int kc, cpx<R> v) -> cpx<R> {
+                                         const int row = wrow + rr;
+                                         if (row >= w || kc >= w || kc > row) return czero<R>();
+                                         return kc == row ? mk(R(1), R(0)) : v;
+                                     });
+            else
+                wide_gemm_lds<R, CT>(cr, ci, xs, 8 * wl, (w + 1) / 2, tptr, [&](int rr, int kc, cpx<R> v) -> cpx<R> {
+                    const int row = wrow + rr;
+                    return (row >= w || kc >= w || kc < row) ? czero<R>() : v;
+                });
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = wrow + Mfma<R>::acc_row(q, v);
+                    const cpx<R> x = mk(cr[ct][v], ci[ct][v]);
+                    ys_c[row * WC + ct * 16 + r] = x;
+                    if (row < w) {
+                        Yi[(long long)(t0 + row) * WC + ct * 16 + r] = x;
+                        if (!lower && off[ct] >= 0) work[off[ct] + (long long)(t0 + row) * n] = x;
+                    }
+                }
+        }
+        __syncthreads();
+        // the other tiles of the super-tile that still need this one
+        const bool later = lower ? sub > tt : sub < tt;
+        const int myt0 = s0 + TS * sub;
+        if (later && myt0 < m) {
+            const cpx<R> *Ab = A + (long long)t0 * m + myt0 + wrow;
+            const bool rv = myt0 + wrow + r < m;
+            wide_gemm_lds<R, CT>(
+                cr, ci, ys, 0, (w + 1) / 2,
+                [&](int rr, int kc) -> const cpx<R> * { return (rv && kc < w) ? Ab + (long long)kc * m + rr : A; },
+                [&](int rr, int kc, cpx<R> v) -> cpx<R> { return (!rv || kc >= w) ? czero<R>() : mk(-v.re, -v.im); });
+        }
+    };
     // ---- forward
-    for (int ti = 0; ti < T; ++ti) {
-        const int t0 = ti * TS, w = min(TS, m - t0);
+    for (int S = 0; S < NS; ++S) {
+        const int s0 = S * ST;
+        const int myt0 = s0 + TS * sub;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = t0 + srow + Mfma<R>::acc_row(q, v);
+                const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
                 cpx<R> b = (row < m && off[ct] >= 0) ? work[off[ct] + (long long)pm[row] * n] : czero<R>();
                 cr[ct][v] = b.re;
                 ci[ct][v] = b.im;
             }
-        if (t0 > 0) wide_gemm_global<R, CT>(cr, ci, A + t0 + srow, m, t0 + srow + r < m, Yi, 0, t0);
-        publish();
-        __syncthreads();
-        zero_acc();
-        {
-            const cpx<R> *Aii = A + (long long)t0 * m + t0;
-            const int kend = min((w + 1) / 2, 8 * (wv + 1));  // unit-lower: columns <= row
-            wide_gemm_diag<R, CT>(cr, ci, xs, 0, kend, [&](int rr, int kc) -> cpx<R> {
-                const int row = srow + rr;
-                if (row >= w || kc >= w || kc > row) return czero<R>();
-                if (kc == row) return mk(R(1), R(0));
-                return Aii[(long long)kc * m + row];
-            });
+        if (s0 > 0 && myt0 < m)
+            wide_gemm_global<R, CT>(cr, ci, A + myt0 + wrow, A, m, myt0 + wrow + r < m, Yi, 0, s0, 5 * it);
+        __syncthreads();  // y[0:s0] reads done before the tiles below overwrite LDS (not Y)
+        for (int tt = 0; tt < NW / 4; ++tt) {
+            const int t0 = s0 + TS * tt;
+            if (t0 >= m) break;
+            tile_step(tt, t0, min(TS, m - t0), true, s0);
         }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = srow + Mfma<R>::acc_row(q, v);
-                if (row < w) Yi[(long long)(t0 + row) * WC + ct * 16 + r] = mk(cr[ct][v], ci[ct][v]);
-            }
-        __syncthreads();  // y_i visible to every wavefront; LDS tile free
+        __syncthreads();
     }
     // ---- backward (x_i over y_i in Y)
-    for (int ti = T - 1; ti >= 0; --ti) {
-        const int t0 = ti * TS, w = min(TS, m - t0);
+    for (int S = NS - 1; S >= 0; --S) {
+        const int s0 = S * ST;
+        const int se = min(m, s0 + ST);
+        const int myt0 = s0 + TS * sub;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = srow + Mfma<R>::acc_row(q, v);
-                cpx<R> y = row < w ? Yi[(long long)(t0 + row) * WC + ct * 16 + r] : czero<R>();
+                const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
+                cpx<R> y = row < m ? Yi[(long long)row * WC + ct * 16 + r] : czero<R>();
                 cr[ct][v] = y.re;
                 ci[ct][v] = y.im;
             }
-        if (t0 + w < m) wide_gemm_global<R, CT>(cr, ci, A + t0 + srow, m, srow + r < w, Yi, t0 + w, m);
-        publish();
+        if (se < m && myt0 < m)
+            wide_gemm_global<R, CT>(cr, ci, A + myt0 + wrow, A, m, myt0 + wrow + r < m, Yi, se, m, 5 * it);
         __syncthreads();
-        zero_acc();
-        {
-            const cpx<R> *Aii = A + (long long)t0 * m + t0;
-            const int kbeg = 8 * wv;  // upper: columns >= row
-            wide_gemm_diag<R, CT>(cr, ci, xs, kbeg, (w + 1) / 2, [&](int rr, int kc) -> cpx<R> {
-                const int row = srow + rr;
-                if (row >= w || kc >= w || kc < row) return czero<R>();
-                return Aii[(long long)kc * m + row];
-            });
+        for (int tt = NW / 4 - 1; tt >= 0; --tt) {
+            const int t0 = s0 + TS * tt;
+            if (t0 >= m) continue;
+            tile_step(tt, t0, min(TS, m - t0), false, s0);
         }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = srow + Mfma<R>::acc_row(q, v);
-                if (row < w) {
-                    const cpx<R> x = mk(cr[ct][v], ci[ct][v]);
-                    Yi[(long long)(t0 + row) * WC + ct * 16 + r] = x;
-                    if (off[ct] >= 0) work[off[ct] + (long long)(t0 + row) * n] = x;
-                }
-            }
         __syncthreads();
     }
 }
@@ -426,6 +509,7 @@ __global__ void __launch_bounds__(256, 2) k_block_solve_wide(cpx<R> *work, const
 // ---------------------------------------------------------------- schedule + launch
 #define WIDE_MIN_COLS 16
 #define WIDE_MAX_COLS 64
+#define WIDE_MIN_RHS 8  // below this the per-mode narrow solve keeps every CU busy
 
 // Split the stored blocks between the two kernels for `nrhs` right-hand sides and upload the
 // tables (only when nrhs changed since the last apply).
@@ -435,11 +519,19 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     std::vector<int> wide;    // int4 items
     std::vector<int> narrow;  // box * n + mode
     int maxc = 0;
+    // group width: the widest of 64 / 32 / 16 columns that still gives >= 512 workgroups
+    long long wide_cols = 0;
+    for (int sb = 0; sb < pc->nstored; ++sb) {
+        const long long cols = (long long)(pc->mode_ptr[sb + 1] - pc->mode_ptr[sb]) * nrhs;
+        if (cols >= WIDE_MIN_COLS && nrhs >= WIDE_MIN_RHS) wide_cols += cols;
+    }
+    int gmax = WIDE_MAX_COLS;
+    while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
     for (int sb = 0; sb < pc->nstored; ++sb) {
         const int cnt = pc->mode_ptr[sb + 1] - pc->mode_ptr[sb];
         const long long cols = (long long)cnt * nrhs;
-        if (cols >= WIDE_MIN_COLS) {
-            const long long ng = (cols + WIDE_MAX_COLS - 1) / WIDE_MAX_COLS;
+        if (cols >= WIDE_MIN_COLS && nrhs >= WIDE_MIN_RHS) {
+            const long long ng = (cols + gmax - 1) / gmax;
             const long long per = (cols + ng - 1) / ng;
             for (long long c = 0; c < cols; c += per) {
                 const int nc = (int)std::min(per, cols - c);
@@ -465,11 +557,12 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
 
 template <class R, int CT>
 static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, hipStream_t s) {
+    constexpr int NW = sizeof(R) == 4 ? 16 : 8;  // wavefronts per workgroup (16 NW rows per super-tile)
     const int per = (pc->n_wide + 7) / 8;
-    const size_t lds = sizeof(cpx<R>) * TS * CT * 16;
-    vie_lds_attr((const void *)k_block_solve_wide<R, CT>, lds);
+    const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16;
+    vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW>, lds);
     const int *mp = pc->modes_dev.as<const int>();
-    hipLaunchKernelGGL((k_block_solve_wide<R, CT>), dim3(8 * per), dim3(256), lds, s, work,
+    hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(), pc->sched.as<const int4>(),
                        pc->n_wide, mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs);
 }

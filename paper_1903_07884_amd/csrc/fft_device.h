@@ -97,10 +97,12 @@ __device__ __forceinline__ void stage_fixed(const cpx<R> *src, cpx<R> *dst, cons
     const int nb = L / P;
     const int total = nb * ln.nlines;
     const int twstep = L / (Ns * P);
+    const FastDiv fnb(nb), fnl(ln.nl1), fns(Ns);
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int l = t / nb, j = t - l * nb;
-        int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
-        int k = j % Ns;
+        const int l = fnb.div(t), j = t - l * nb;
+        const int l2 = fnl.div(l);
+        const int base = (l - l2 * ln.nl1) * ln.s1 + l2 * ln.s2;
+        const int jn = fns.div(j), k = j - jn * Ns;
         cpx<R> v[P];
 #pragma unroll
         for (int r = 0; r < P; ++r) {
@@ -111,7 +113,7 @@ __device__ __forceinline__ void stage_fixed(const cpx<R> *src, cpx<R> *dst, cons
         if (P == 3) bfly3(v, inv);
         if (P == 4) bfly4(v, inv);
         if (P == 5) bfly5(v, inv);
-        int d = (j / Ns) * Ns * P + k;
+        const int d = jn * Ns * P + k;
 #pragma unroll
         for (int r = 0; r < P; ++r) dst[base + (d + r * Ns) * ln.es] = v[r];
     }
@@ -124,12 +126,13 @@ __device__ void stage_generic(const cpx<R> *src, cpx<R> *dst, const LdsLines &ln
     const int nb = L / P;
     const int total = nb * ln.nlines * P;
     const int step = L / (Ns * P);
+    const FastDiv fp(P), fnb(nb), fnl(ln.nl1), fns(Ns);
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int s = t % P;
-        int u = t / P;
-        int l = u / nb, j = u - l * nb;
-        int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
-        int k = j % Ns;
+        const int u = fp.div(t), s = t - u * P;
+        const int l = fnb.div(u), j = u - l * nb;
+        const int l2 = fnl.div(l);
+        const int base = (l - l2 * ln.nl1) * ln.s1 + l2 * ln.s2;
+        const int jn = fns.div(j), k = j - jn * Ns;
         int e = (k + s * Ns) * step;  // < L
         cpx<R> acc = czero<R>();
         int q = 0;
@@ -138,7 +141,7 @@ __device__ void stage_generic(const cpx<R> *src, cpx<R> *dst, const LdsLines &ln
             q += e;
             if (q >= L) q -= L;
         }
-        int d = (j / Ns) * Ns * P + k;
+        const int d = jn * Ns * P + k;
         dst[base + (d + s * Ns) * ln.es] = acc;
     }
 }
@@ -179,14 +182,16 @@ __device__ __forceinline__ void stage_inplace(cpx<R> *buf, const LdsLines &ln, i
     const int nb = L / P;
     const int total = nb * ln.nlines;
     const int twstep = L / (Ns * P);
+    const FastDiv fnb(nb), fnl(ln.nl1), fns(Ns);
     cpx<R> v[BPT][P];
 #pragma unroll
     for (int q = 0; q < BPT; ++q) {
         int t = threadIdx.x + q * blockDim.x;
         if (t < total) {
-            int l = t / nb, j = t - l * nb;
-            int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
-            int k = j % Ns;
+            const int l = fnb.div(t), j = t - l * nb;
+            const int l2 = fnl.div(l);
+            const int base = (l - l2 * ln.nl1) * ln.s1 + l2 * ln.s2;
+            const int k = j - fns.div(j) * Ns;
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 cpx<R> a = buf[base + (j + r * nb) * ln.es];
@@ -203,10 +208,11 @@ __device__ __forceinline__ void stage_inplace(cpx<R> *buf, const LdsLines &ln, i
     for (int q = 0; q < BPT; ++q) {
         int t = threadIdx.x + q * blockDim.x;
         if (t < total) {
-            int l = t / nb, j = t - l * nb;
-            int base = (l % ln.nl1) * ln.s1 + (l / ln.nl1) * ln.s2;
-            int k = j % Ns;
-            int d = (j / Ns) * Ns * P + k;
+            const int l = fnb.div(t), j = t - l * nb;
+            const int l2 = fnl.div(l);
+            const int base = (l - l2 * ln.nl1) * ln.s1 + l2 * ln.s2;
+            const int jn = fns.div(j), k = j - jn * Ns;
+            const int d = jn * Ns * P + k;
 #pragma unroll
             for (int r = 0; r < P; ++r) buf[base + (d + r * Ns) * ln.es] = v[q][r];
         }

@@ -312,12 +312,14 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
     const bool fx = kx > Px - kx;
     cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
     const cpx<R> *kh = khat + (long long)kxo * Hy * nz * 6;
+    const FastDiv f6nz(6 * nz), fpy(Py), fny(ny);
     for (int i = threadIdx.x; i < Hy * nz * 6; i += blockDim.x) {
-        int c = i % 6, dz = (i / 6) % nz, kyo = i / (6 * nz);  // source layout [Hy][nz][6]
+        const int kyo = f6nz.div(i), e = i - kyo * 6 * nz;  // source layout [Hy][nz][6]
+        const int dz = e / 6, c = e - dz * 6;
         G[(dz * 6 + c) * Hy + kyo] = kh[i];
     }
     for (int i = threadIdx.x; i < rows * Py; i += blockDim.x) {
-        int y = i % Py, rz = i / Py;  // rz = c * nz + z
+        const int rz = fpy.div(i), y = i - rz * Py;  // rz = c * nz + z
         a[i] = y < ny ? base[((long long)rz * ny + y) * Px] : czero<R>();
     }
     __syncthreads();
@@ -327,38 +329,38 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
         spec = fft_lds<R>(a, b, ln, py, false);
         prod = spec == a ? b : a;
     }
-    // parity: xy odd in x, y; xz odd in x, z; yz odd in y, z
-    const int cidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    for (int o = threadIdx.x; o < rows * Py; o += blockDim.x) {
-        const int ky = o % Py, rz = o / Py;
-        const int al = rz / nz, z = rz % nz;
+    // z coupling, one (z, ky) entry per thread with all three components: the 3x3 block of
+    // the transformed generator at offset z - z' with its parity signs (xy odd in x and y,
+    // xz in x and z, yz in y and z).
+    const R sx = fx ? R(-1) : R(1);
+    for (int o = threadIdx.x; o < nz * Py; o += blockDim.x) {
+        const int z = fpy.div(o), ky = o - z * Py;
         const int kyo = ky <= Py - ky ? ky : Py - ky;
-        const bool fy = ky > Py - ky;
+        const R sy = ky > Py - ky ? R(-1) : R(1);
+        const R sxy = sx * sy;
         const cpx<R> *g = G + kyo;
-        cpx<R> acc = czero<R>();
-        for (int be = 0; be < 3; ++be) {
-            const int c = cidx[al][be];
-            bool neg = false;
-            if ((c == 3 || c == 4) && fx) neg = !neg;
-            if ((c == 3 || c == 5) && fy) neg = !neg;
-            const bool oddz = (c == 4 || c == 5);
-            cpx<R> part = czero<R>();
-            for (int zp = 0; zp < nz; ++zp) {
-                int dz = z - zp;
-                cpx<R> gv = g[((dz < 0 ? -dz : dz) * 6 + c) * Hy];
-                cpx<R> xv = spec[(be * nz + zp) * Py + ky];
-                if (oddz && dz < 0) part = part - gv * xv;
-                else part = part + gv * xv;
-            }
-            acc = neg ? acc - part : acc + part;
+        const cpx<R> *u = spec + ky;
+        cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
+        for (int zp = 0; zp < nz; ++zp) {
+            const int dz = z - zp;
+            const R sz = dz < 0 ? R(-1) : R(1);
+            const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6 * Hy;
+            const cpx<R> gxx = gz[0], gyy = gz[Hy], gzz = gz[2 * Hy];
+            const cpx<R> gxy = sxy * gz[3 * Hy], gxz = (sx * sz) * gz[4 * Hy], gyz = (sy * sz) * gz[5 * Hy];
+            const cpx<R> u0 = u[zp * Py], u1 = u[(nz + zp) * Py], u2 = u[(2 * nz + zp) * Py];
+            a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
+            a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
+            a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
         }
-        prod[o] = acc;
+        prod[z * Py + ky] = a0;
+        prod[(nz + z) * Py + ky] = a1;
+        prod[(2 * nz + z) * Py + ky] = a2;
     }
     __syncthreads();
     cpx<R> *res = prod;
     if (Py > 1) res = fft_lds<R>(prod, spec, ln, py, true);
     for (int i = threadIdx.x; i < rows * ny; i += blockDim.x) {
-        int y = i % ny, rz = i / ny;
+        const int rz = fny.div(i), y = i - rz * ny;
         base[((long long)rz * ny + y) * Px] = res[rz * Py + y];
     }
 }

@@ -56,6 +56,21 @@ __host__ __device__ __forceinline__ cpx<R> cdiv(cpx<R> a, cpx<R> b) {
 template <class R>
 __host__ __device__ __forceinline__ cpx<R> czero() { return mk<R>(R(0), R(0)); }
 
+// Division of small non-negative ints (numerator < 2^20) by a runtime divisor: a float
+// reciprocal estimate and one correction step each way replace the integer division sequence.
+struct FastDiv {
+    int d;
+    float inv;
+    __device__ __forceinline__ explicit FastDiv(int dd) : d(dd), inv(__builtin_amdgcn_rcpf((float)dd)) {}
+    __device__ __forceinline__ int div(int a) const {
+        int q = (int)((float)a * inv);
+        const int r = a - q * d;
+        if (r >= d) ++q;
+        else if (r < 0) --q;
+        return q;
+    }
+};
+
 // ---------------------------------------------------------------- errors
 void vie_set_error(const std::string &msg);
 

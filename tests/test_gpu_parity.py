@@ -191,6 +191,8 @@ WIDE_CASES = [
     ((32, 8, 6), 1, 1e-2, 'c128'),       # R = 1: the shared central block goes wide
     ((24, 6, 4), 33, None, 'c64'),
     ((32, 8, 6), 64, 1e-2, 'c64'),
+    ((12, 12, 8), 16, None, 'c64'),      # m = 288: two super-tiles of the FP32 solve (256 + 32 rows)
+    ((12, 12, 8), 24, None, 'c128'),     # m = 288: three super-tiles of the FP64 solve (128 + 128 + 32)
 ]
 
 
