@@ -46,7 +46,10 @@ typedef struct vie_pc_s *vie_pc; /* owns boxes, homogenised contrasts, block map
 
 typedef enum {
     VIE_C128 = 0, /* complex<double> */
-    VIE_C64 = 1   /* complex<float>  */
+    VIE_C64 = 1,  /* complex<float>  */
+    VIE_BF16C = 2 /* preconditioner factors only: complex bfloat16 pairs (4 bytes); the
+                     factorisation runs in FP32 and the vectors of such a preconditioner
+                     are VIE_C64 */
 } vie_prec;
 
 typedef enum {
@@ -125,6 +128,10 @@ typedef struct {
                             "ceil(ny/2) ceil(nz/2)" is ambiguous: 0 = the 1-based linear
                             cross-section index ceil(by/2)*ceil(bz/2) (y fastest); 1 = the
                             cross-section centre voxel (ceil(by/2), ceil(bz/2)) */
+    int32_t refine_steps;/* VIE_BF16C factors only (else 0): 0 or 1 iterative-refinement
+                            steps of every block solve D_k z = r: the residual r - D_k z is
+                            formed in FP32 from D_k = I - diag(M~) C^_k itself (not from the
+                            rounded factors) and a second solve corrects z */
 } vie_pc_opts;
 
 typedef struct {
@@ -144,7 +151,9 @@ vie_status precond_destroy(vie_pc pc);
 
 /* z = P^{-1} r: per box, DFT along x, block solves with the LU factors of the
  * D_k, inverse DFT (Sec. 4, inverse after eq. Di); identity outside the boxes.
- * r, z: device, precision `prec`, nrhs vectors; must not overlap. */
+ * r, z: device, precision `prec` (VIE_C64 for VIE_BF16C factors), nrhs vectors; must
+ * not overlap.  With VIE_BF16C factors every block is solved on the matrix cores and, with
+ * refine_steps = 1, refined once against D_k in FP32. */
 vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t nrhs, vie_prec prec,
                          void *stream);
 

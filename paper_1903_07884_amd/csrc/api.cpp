@@ -166,8 +166,13 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     if (!op || !opts) return arg_error("precond_setup: NULL argument");
     const vie_pc_opts &o = *opts;
     if (o.homog < VIE_HOMOG_NONE || o.homog > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown homog");
-    if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64)
+    if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
         return arg_error("precond_setup: unknown factor precision");
+    if (o.refine_steps < 0 || o.refine_steps > 1) return arg_error("precond_setup: refine_steps must be 0 or 1");
+    if (o.refine_steps && o.factor_prec != VIE_BF16C)
+        return arg_error("precond_setup: refine_steps needs VIE_BF16C factors");
+    if (o.factor_prec == VIE_BF16C && !op->has_c64)
+        return arg_error("precond_setup: VIE_BF16C factors need an operator built with build_c64");
     if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
     if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
         return arg_error("precond_setup: reduce_tol must be finite and >= 0");
@@ -223,6 +228,7 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     pc->boxes = boxes;
     pc->covers_all = vol == op->N;
     pc->prec = o.factor_prec;
+    pc->refine = o.refine_steps;
     vie_status st = pc_build(pc, &o, (hipStream_t)stream);
     if (st < 0) {
         delete pc;
@@ -239,7 +245,7 @@ extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
     info->block_m = pc->m;
     info->modes = pc->nboxes * pc->bx;
     info->stored_blocks = pc->nstored;
-    size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+    size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : pc->prec == VIE_C64 ? sizeof(c64) : sizeof(bf16c);
     info->factor_bytes = (int64_t)pc->nstored * pc->m * ((int64_t)pc->m * esz + sizeof(int));
     return VIE_OK;
 }

@@ -27,8 +27,8 @@
 // quarter of its columns), and every thread then applies the tile's column panel to its
 // remaining rows.  Each factor entry is read once per chunk and used RC times; the factor
 // reads are coalesced along columns.
-template <class R, int QR, int RC>
-__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> *F, const int *perm,
+template <class R, int QR, int RC, class FT>
+__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, const int *perm,
                                                      const int *block_of_mode, const int *modes, int m, int n,
                                                      int nboxes, int nrhs) {
     cpx<R> *yt = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][RC]
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> 
     const int r0 = blockIdx.y * RC;
     const int nr = min(RC, nrhs - r0);
     const int sblk = block_of_mode[bm];
-    const cpx<R> *A = F + (long long)sblk * m * m;
+    const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     const long long rstride = (long long)nboxes * m * n;
     cpx<R> *base = work + (long long)box * m * n + k;
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> 
             for (int c = 0; c < RC; ++c) p[c] = czero<R>();
             if (r < w)
                 for (int cc = g; cc < r; cc += 4) {
-                    cpx<R> l = A[(long long)(t0 + cc) * m + t0 + r];
+                    cpx<R> l = ldf(A + (long long)(t0 + cc) * m + t0 + r);
 #pragma unroll
                     for (int c = 0; c < RC; ++c) p[c] = p[c] + l * yt[cc * RC + c];
                 }
@@ -90,10 +90,10 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> 
 #pragma unroll
                 for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
             } else if (i >= t0 + w && i < m) {
-                const cpx<R> *col = A + (long long)t0 * m + i;
+                const FT *col = A + (long long)t0 * m + i;
 #pragma unroll 4
                 for (int cc = 0; cc < w; ++cc) {
-                    cpx<R> l = col[(long long)cc * m];
+                    cpx<R> l = ldf(col + (long long)cc * m);
 #pragma unroll
                     for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], l, yt[cc * RC + c]);
                 }
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> 
             if (r < w)
                 for (int cc = g; cc < w; cc += 4)
                     if (cc >= r) {
-                        cpx<R> u = A[(long long)(t0 + cc) * m + t0 + r];
+                        cpx<R> u = ldf(A + (long long)(t0 + cc) * m + t0 + r);
 #pragma unroll
                         for (int c = 0; c < RC; ++c) p[c] = p[c] + u * yt[cc * RC + c];
                     }
@@ -142,10 +142,10 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const cpx<R> 
 #pragma unroll
                 for (int c = 0; c < RC; ++c) acc[q][c] = yt[(i - t0) * RC + c];
             } else if (i < t0) {
-                const cpx<R> *col = A + (long long)t0 * m + i;
+                const FT *col = A + (long long)t0 * m + i;
 #pragma unroll 4
                 for (int cc = 0; cc < w; ++cc) {
-                    cpx<R> u = col[(long long)cc * m];
+                    cpx<R> u = ldf(col + (long long)cc * m);
 #pragma unroll
                     for (int c = 0; c < RC; ++c) acc[q][c] = cfms(acc[q][c], u, yt[cc * RC + c]);
                 }
@@ -173,15 +173,15 @@ static int block_solve_rc(int m, int nrhs, size_t esz) {
     return rc;
 }
 
-template <class R, int QR, int RC>
-static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F, const int *perm,
+template <class R, int QR, int RC, class FT>
+static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const FT *F, const int *perm,
                       const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
-    hipLaunchKernelGGL((k_block_solve<R, QR, RC>), grid, dim3(256), lds, s, work, F, perm, bom, modes, m, n, nboxes,
-                       nrhs);
+    hipLaunchKernelGGL((k_block_solve<R, QR, RC, FT>), grid, dim3(256), lds, s, work, F, perm, bom, modes, m, n,
+                       nboxes, nrhs);
 }
 
-template <class R, int QR>
-static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const cpx<R> *F,
+template <class R, int QR, class FT>
+static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const FT *F,
                          const int *perm, const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
     switch (rc) {
         case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
@@ -230,16 +230,16 @@ struct Mfma<double> {
 // row-major [m][CT*16].  The K-steps run in the rotated order rot, rot+1, ..., nks-1, 0, ...
 // so that workgroups sharing one factor (the memory-reduced central block) read different
 // parts of it at a time.
-template <class R, int CT>
+template <class R, int CT, class FT>
 __device__ __forceinline__ void wide_gemm_global(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci,
-                                                 const cpx<R> *arow, const cpx<R> *abase, long long m, bool rv,
+                                                 const FT *arow, const FT *abase, long long m, bool rv,
                                                  const cpx<R> *Y, int kb, int ke, int rot) {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     constexpr int WC = CT * 16;
     constexpr int KC = 2;
     const R *yf = reinterpret_cast<const R *>(Y) + p;
-    const cpx<R> *ap = rv ? arow + r : abase;
+    const FT *ap = rv ? arow + r : abase;
     const int nks = (ke - kb + 1) / 2;
     rot = rot % nks;
     cpx<R> a0[KC], a1[KC];
@@ -254,7 +254,7 @@ __device__ __forceinline__ void wide_gemm_global(typename Mfma<R>::v4 *cr, typen
             const bool in = kc < ke && ks0 + u < nks;
             const int kcl = in ? kc : kb;
             msk[u] = in;
-            a[u] = ap[(long long)kcl * m];
+            a[u] = ldf(ap + (long long)kcl * m);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) bb[u][ct] = yf[((long long)kcl * WC + ct * 16 + r) * 2];
         }
@@ -303,7 +303,7 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
             const int kc = 2 * (ks0 + u) + kh;
-            a[u] = *t_ptr(r, kc < 64 ? kc : 63);
+            a[u] = ldf(t_ptr(r, kc < 64 ? kc : 63));
         }
     };
     auto compute = [&](int ks0, const cpx<R> *a) {
@@ -353,11 +353,14 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
 // per-item scratch of all resident workgroups stays in the last-level cache.
 // Workgroup b of the grid takes item (b % 8) * per + b / 8 so that the eight XCDs work on
 // contiguous item ranges (neighbouring modes share the cache lines of `work`).
-template <class R, int CT, int NW>
-__global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, const cpx<R> *F, const int *perm,
+// out_mode: 0 = write x to work; 1 = keep x in Y only; 2 = write x + Yadd to work (the
+// correction step of a refined solve, Yadd holding the first solution).
+template <class R, int CT, int NW, class FT>
+__global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, const FT *F, const int *perm,
                                                                const int4 *items, int nitems, const int *mode_ptr,
                                                                const int *mode_list, cpx<R> *Y, int m, int n,
-                                                               int nboxes, int nrhs) {
+                                                               int nboxes, int nrhs, int out_mode,
+                                                               const cpx<R> *Yadd) {
     typedef typename Mfma<R>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int ST = 16 * NW;  // rows per super-tile
@@ -370,9 +373,10 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     cpx<R> *ys_c = xs_c + TS * WC;                         // [64][WC]: solved tile
     const R *xs = reinterpret_cast<const R *>(xs_c);
     const R *ys = reinterpret_cast<const R *>(ys_c);
-    const cpx<R> *A = F + (long long)sblk * m * m;
+    const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     cpx<R> *Yi = Y + (long long)it * m * WC;
+    const cpx<R> *Ya = Yadd ? Yadd + (long long)it * m * WC : nullptr;
     const long long rstride = (long long)nboxes * m * n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
@@ -412,10 +416,10 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
         __syncthreads();
         if (owner) {
             zero_acc();
-            const cpx<R> *Aii = A + (long long)t0 * m + t0;
+            const FT *Aii = A + (long long)t0 * m + t0;
             const int wl = wv & 3;
             // addresses clamped into the tile (rows/columns >= w read entry (0, 0))
-            auto tptr = [&](int rr, int kc) -> const cpx<R> * {
+            auto tptr = [&](int rr, int kc) -> const FT * {
                 const int row = wrow + rr;
                 return (row < w && kc < w) ? Aii + (long long)kc * m + row : Aii;
             };
@@ -439,8 +443,10 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                     const cpx<R> x = mk(cr[ct][v], ci[ct][v]);
                     ys_c[row * WC + ct * 16 + r] = x;
                     if (row < w) {
-                        Yi[(long long)(t0 + row) * WC + ct * 16 + r] = x;
-                        if (!lower && off[ct] >= 0) work[off[ct] + (long long)(t0 + row) * n] = x;
+                        const long long yo = (long long)(t0 + row) * WC + ct * 16 + r;
+                        Yi[yo] = x;
+                        if (!lower && off[ct] >= 0 && out_mode != 1)
+                            work[off[ct] + (long long)(t0 + row) * n] = out_mode == 2 ? x + Ya[yo] : x;
                     }
                 }
         }
@@ -449,11 +455,11 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
         const bool later = lower ? sub > tt : sub < tt;
         const int myt0 = s0 + TS * sub;
         if (later && myt0 < m) {
-            const cpx<R> *Ab = A + (long long)t0 * m + myt0 + wrow;
+            const FT *Ab = A + (long long)t0 * m + myt0 + wrow;
             const bool rv = myt0 + wrow + r < m;
             wide_gemm_lds<R, CT>(
                 cr, ci, ys, 0, (w + 1) / 2,
-                [&](int rr, int kc) -> const cpx<R> * { return (rv && kc < w) ? Ab + (long long)kc * m + rr : A; },
+                [&](int rr, int kc) -> const FT * { return (rv && kc < w) ? Ab + (long long)kc * m + rr : A; },
                 [&](int rr, int kc, cpx<R> v) -> cpx<R> { return (!rv || kc >= w) ? czero<R>() : mk(-v.re, -v.im); });
         }
     };
@@ -506,6 +512,110 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     }
 }
 
+// ---------------------------------------------------------------- refinement residual
+// One refinement step of a solve with rounded (bfloat16) factors needs the residual of the
+// block system itself: for an item of stored block s (factorised from D_k, k = smode[s]),
+//   r^ <- r^ - D_k z0 = r^ - z0 + M~ (C^_k z0)          (over r^ in work)
+// with z0 the first solve's result (the item's scratch, row-major [m][CT*16]) and
+//   C^_k[(a,y,z), (b,y',z')] = C^_k^{c(a,b)}(y - y', z - z'),
+// the Chan/x-DFT table of the block (complex float, [6][2bz-1][2by-1] per mode, staged in
+// LDS), c(a,b) the index of the unique component (xx, yy, zz, xy, xz, yz).  The product is
+// a matrix-core GEMM whose left operand is generated from the table.  NW wavefronts take
+// 16-row strips in turn.
+template <int CT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c64 *chan, const c64 *mt,
+                                                              const int *smode, const int4 *items, int nitems,
+                                                              const int *mode_ptr, const int *mode_list,
+                                                              const c64 *Y, int m, int n, int nboxes, int nrhs,
+                                                              int by, int bz) {
+    typedef Mfma<float>::v4 v4;
+    constexpr int WC = CT * 16;
+    const int per = (nitems + 7) / 8;
+    const int it = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (it >= nitems) return;
+    const int4 item = items[it];
+    const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
+    const int ndy = 2 * by - 1, ndz = 2 * bz - 1, plane = by * bz;
+    const int tabn = 6 * ndz * ndy;
+    c64 *tab = reinterpret_cast<c64 *>(vie_smem);
+    const c64 *src = chan + (long long)smode[sblk] * tabn;
+    for (int i = threadIdx.x; i < tabn; i += blockDim.x) tab[i] = src[i];
+    const c64 *Yi = Y + (long long)it * m * WC;
+    const long long rstride = (long long)nboxes * m * n;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    long long off[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = ct * 16 + r;
+        off[ct] = -1;
+        if (col < ncols) {
+            const int g = c0 + col;
+            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode_list[mode_ptr[sblk] + g / nrhs];
+        }
+    }
+    __syncthreads();
+    const float *yf = reinterpret_cast<const float *>(Yi) + p;
+    const int nks = (m + 1) / 2;
+    for (int strip = wv; strip * 16 < m; strip += NW) {
+        const int row0 = strip * 16;
+        // this lane's operand row (a, y, z)
+        const int arow = min(row0 + r, m - 1);
+        const int a = arow / plane, yz = arow - a * plane, z = yz / by, y = yz - z * by;
+        v4 cr[CT], ci[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            cr[ct] = v4{0, 0, 0, 0};
+            ci[ct] = v4{0, 0, 0, 0};
+        }
+        // column (b, y', z') of K-step 0 for this lane (kc = kh), advanced by 2 per step
+        int b = 0, zp = 0, yp = kh;
+        while (yp >= by) {
+            yp -= by;
+            if (++zp == bz) {
+                zp = 0;
+                ++b;
+            }
+        }
+        for (int ks = 0; ks < nks; ++ks) {
+            const int kc = 2 * ks + kh;
+            const bool in = kc < m;
+            const int c = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
+            const c64 t = in ? tab[(c * ndz + (z - zp + bz - 1)) * ndy + (y - yp + by - 1)] : czero<float>();
+            const float ar = p ? -t.im : t.re;
+            const float ai = p ? t.re : t.im;
+            const int kcl = in ? kc : 0;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const float bv = yf[((long long)kcl * WC + ct * 16 + r) * 2];
+                cr[ct] = Mfma<float>::fma(ar, bv, cr[ct]);
+                ci[ct] = Mfma<float>::fma(ai, bv, ci[ct]);
+            }
+            yp += 2;
+            while (yp >= by) {
+                yp -= by;
+                if (++zp == bz) {
+                    zp = 0;
+                    ++b;
+                }
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + Mfma<float>::acc_row(q, v);
+                if (row < m && off[ct] >= 0) {
+                    const int ra = row / plane, ryz = row - ra * plane;  // M~ index (z, y)
+                    const c64 mv = mt[(long long)box * plane + ryz];
+                    const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
+                    const long long wo = off[ct] + (long long)row * n;
+                    work[wo] = work[wo] - z0 + mv * mk(cr[ct][v], ci[ct][v]);
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- schedule + launch
 #define WIDE_MIN_COLS 16
 #define WIDE_MAX_COLS 64
@@ -516,6 +626,9 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
 static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     if (pc->sched_nrhs == nrhs) return VIE_OK;
     const int n = pc->bx;
+    // bfloat16 factors are solved on the matrix cores only (every block goes wide)
+    const bool all_wide = pc->prec == VIE_BF16C;
+    const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : WIDE_MIN_RHS;
     std::vector<int> wide;    // int4 items
     std::vector<int> narrow;  // box * n + mode
     int maxc = 0;
@@ -523,14 +636,14 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     long long wide_cols = 0;
     for (int sb = 0; sb < pc->nstored; ++sb) {
         const long long cols = (long long)(pc->mode_ptr[sb + 1] - pc->mode_ptr[sb]) * nrhs;
-        if (cols >= WIDE_MIN_COLS && nrhs >= WIDE_MIN_RHS) wide_cols += cols;
+        if (cols >= min_cols && nrhs >= min_rhs) wide_cols += cols;
     }
     int gmax = WIDE_MAX_COLS;
     while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
     for (int sb = 0; sb < pc->nstored; ++sb) {
         const int cnt = pc->mode_ptr[sb + 1] - pc->mode_ptr[sb];
         const long long cols = (long long)cnt * nrhs;
-        if (cols >= WIDE_MIN_COLS && nrhs >= WIDE_MIN_RHS) {
+        if (cols >= min_cols && nrhs >= min_rhs) {
             const long long ng = (cols + gmax - 1) / gmax;
             const long long per = (cols + ng - 1) / ng;
             for (long long c = 0; c < cols; c += per) {
@@ -555,19 +668,33 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     return VIE_OK;
 }
 
-template <class R, int CT>
-static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, hipStream_t s) {
+template <class R, int CT, class FT>
+static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
+                        hipStream_t s) {
     constexpr int NW = sizeof(R) == 4 ? 16 : 8;  // wavefronts per workgroup (16 NW rows per super-tile)
     const int per = (pc->n_wide + 7) / 8;
     const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16;
-    vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW>, lds);
+    vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
     const int *mp = pc->modes_dev.as<const int>();
-    hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
-                       pc->factors.as<const cpx<R>>(), pc->perm.as<const int>(), pc->sched.as<const int4>(),
-                       pc->n_wide, mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs);
+    hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
+                       pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
+                       mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs, out_mode, Yadd);
 }
 
-template <class R>
+template <int CT>
+static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
+    constexpr int NW = 8;
+    const int per = (pc->n_wide + 7) / 8;
+    const size_t lds = sizeof(c64) * 6 * (2 * pc->bz - 1) * (2 * pc->by - 1);
+    vie_lds_attr((const void *)k_refine_residual<CT, NW>, lds);
+    const int *mp = pc->modes_dev.as<const int>();
+    hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
+                       pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
+                       pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y, pc->m, pc->bx,
+                       pc->nboxes, nrhs, pc->by, pc->bz);
+}
+
+template <class R, class FT>
 static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
     const int m = pc->m, n = pc->bx;
     const int qr = (m + 255) / 256;
@@ -578,13 +705,32 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
     VIE_CHECK(build_schedule(pc, nrhs, s));
     if (pc->n_wide > 0) {
         const int WC = 16 * pc->wide_ct;
-        VIE_CHECK(pc->wide_scratch.ensure(sizeof(cpx<R>) * (size_t)pc->n_wide * m * WC));
+        const size_t ybytes = sizeof(cpx<R>) * (size_t)pc->n_wide * m * WC;
+        VIE_CHECK(pc->wide_scratch.ensure(ybytes));
         cpx<R> *Y = pc->wide_scratch.as<cpx<R>>();
-        switch (pc->wide_ct) {
-            case 1: launch_wide<R, 1>(pc, work, Y, nrhs, s); break;
-            case 2: launch_wide<R, 2>(pc, work, Y, nrhs, s); break;
-            default: launch_wide<R, 4>(pc, work, Y, nrhs, s); break;
+        const bool refine = pc->refine && sizeof(R) == 4;
+        cpx<R> *Y2 = nullptr;
+        if (refine) {
+            VIE_CHECK(pc->wide_scratch2.ensure(ybytes));
+            Y2 = pc->wide_scratch2.as<cpx<R>>();
         }
+#define WIDE_CASES(CTV)                                                                                  \
+    if (!refine) {                                                                                       \
+        launch_wide<R, CTV, FT>(pc, work, Y, nrhs, 0, nullptr, s);                                       \
+    } else {                                                                                             \
+        launch_wide<R, CTV, FT>(pc, work, Y, nrhs, 1, nullptr, s);                                       \
+        VIE_HIP(hipGetLastError());                                                                      \
+        ProfScope pr("refine_residual", s);                                                              \
+        launch_residual<CTV>(pc, (c64 *)work, (const c64 *)Y, nrhs, s);                                  \
+        VIE_HIP(hipGetLastError());                                                                      \
+        launch_wide<R, CTV, FT>(pc, work, Y2, nrhs, 2, Y, s);                                            \
+    }
+        switch (pc->wide_ct) {
+            case 1: WIDE_CASES(1) break;
+            case 2: WIDE_CASES(2) break;
+            default: WIDE_CASES(4) break;
+        }
+#undef WIDE_CASES
         VIE_HIP(hipGetLastError());
     }
     if (pc->n_narrow > 0) {
@@ -592,7 +738,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
         dim3 grid((unsigned)pc->n_narrow, (unsigned)((nrhs + rc - 1) / rc));
         size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
         const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
-        const cpx<R> *F = pc->factors.as<const cpx<R>>();
+        const FT *F = pc->factors.as<const FT>();
         const int *perm = pc->perm.as<const int>(), *bom = pc->block_of_mode.as<const int>();
         switch (qr) {
             case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
@@ -607,6 +753,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
 }
 
 vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s) {
-    if (pc->prec == VIE_C128) return block_solve_t<double>(pc, (c128 *)work, nrhs, s);
-    return block_solve_t<float>(pc, (c64 *)work, nrhs, s);
+    if (pc->prec == VIE_C128) return block_solve_t<double, c128>(pc, (c128 *)work, nrhs, s);
+    if (pc->prec == VIE_BF16C) return block_solve_t<float, bf16c>(pc, (c64 *)work, nrhs, s);
+    return block_solve_t<float, c64>(pc, (c64 *)work, nrhs, s);
 }

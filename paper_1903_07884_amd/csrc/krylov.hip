@@ -279,8 +279,8 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         vie_set_error("mixed-precision solve needs an operator built with build_c64");
         return VIE_EARG;
     }
-    if (pc && pc->prec != (mixed ? VIE_C64 : VIE_C128)) {
-        vie_set_error(mixed ? "mixed-precision solve needs complex64 preconditioner factors"
+    if (pc && (mixed ? (pc->prec != VIE_C64 && pc->prec != VIE_BF16C) : pc->prec != VIE_C128)) {
+        vie_set_error(mixed ? "mixed-precision solve needs complex64 or bfloat16 preconditioner factors"
                             : "FP64 solve needs complex128 preconditioner factors");
         return VIE_EARG;
     }

@@ -133,6 +133,20 @@ __global__ void k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode, 
     D[(long long)s * m * m + e] = mk((R)v.re, (R)v.im);
 }
 
+// Round complex float factors to complex bfloat16.
+__global__ void k_to_bf16(const c64 *src, bf16c *dst, long long count) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const c64 v = src[i];
+    dst[i].v = bf16_bits(v.re) | (bf16_bits(v.im) << 16);
+}
+
+__global__ void k_narrow_c128(const c128 *src, c64 *dst, long long count) {
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    dst[i] = mk((float)src[i].re, (float)src[i].im);
+}
+
 // ---------------------------------------------------------------- batched LU
 template <class R>
 __device__ __forceinline__ R cabs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
@@ -762,8 +776,8 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
 }
 
 vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s) {
-    if (prec != pc->prec) {
-        vie_set_error("precond_apply: vector precision must equal the factor precision");
+    if (prec != (pc->prec == VIE_BF16C ? (int)VIE_C64 : pc->prec)) {
+        vie_set_error("precond_apply: vector precision must be the factor precision (complex64 for BF16 factors)");
         return VIE_EARG;
     }
     if (prec == VIE_C128) return apply_t<double>(pc, (const c128 *)r, (c128 *)z, nrhs, s);
@@ -922,6 +936,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     VIE_CHECK(dbox.ensure(sizeof(int) * pc->nstored));
     VIE_HIP(hipMemcpyAsync(dmode.p, smode.data(), sizeof(int) * pc->nstored, hipMemcpyHostToDevice, s));
     VIE_HIP(hipMemcpyAsync(dbox.p, sbox.data(), sizeof(int) * pc->nstored, hipMemcpyHostToDevice, s));
+    // BF16 factors: assembled and factorised in complex float, rounded afterwards
     size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
     VIE_CHECK(pc->factors.ensure(esz * (size_t)pc->nstored * m * m));
     VIE_CHECK(pc->perm.ensure(sizeof(int) * (size_t)pc->nstored * m));
@@ -935,9 +950,33 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
                            dmode.as<const int>(), dbox.as<const int>(), pc->factors.as<c64>(), by, bz);
     VIE_HIP(hipGetLastError());
     VIE_HIP(hipStreamSynchronize(s));
+    if (pc->refine) {  // FP32 copies of the C^_k tables and of M~ for the refinement residual
+        const long long nch = (long long)n * 6 * ndy * ndz, nmt = (long long)nbx * by * bz;
+        VIE_CHECK(pc->chan32.ensure(sizeof(c64) * nch));
+        VIE_CHECK(pc->mt32.ensure(sizeof(c64) * nmt));
+        hipLaunchKernelGGL(k_narrow_c128, dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, s, Ch.as<const c128>(),
+                           pc->chan32.as<c64>(), nch);
+        hipLaunchKernelGGL(k_narrow_c128, dim3((unsigned)((nmt + 255) / 256)), dim3(256), 0, s, Mt.as<const c128>(),
+                           pc->mt32.as<c64>(), nmt);
+        VIE_HIP(hipGetLastError());
+    }
+    VIE_CHECK(pc->smode_dev.ensure(sizeof(int) * pc->nstored));
+    VIE_HIP(hipMemcpyAsync(pc->smode_dev.p, smode.data(), sizeof(int) * pc->nstored, hipMemcpyHostToDevice, s));
+    VIE_HIP(hipStreamSynchronize(s));
     Ch.release();
     vie_status st = pc->prec == VIE_C128 ? lu_factor<double>(pc, s) : lu_factor<float>(pc, s);
     VIE_CHECK(st);
+    if (pc->prec == VIE_BF16C) {
+        const long long cnt = (long long)pc->nstored * m * m;
+        DevBuf b16;
+        VIE_CHECK(b16.ensure(sizeof(bf16c) * cnt));
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, pc->factors.as<const c64>(),
+                           b16.as<bf16c>(), cnt);
+        VIE_HIP(hipGetLastError());
+        VIE_HIP(hipStreamSynchronize(s));
+        std::swap(pc->factors.p, b16.p);
+        std::swap(pc->factors.bytes, b16.bytes);
+    }
     std::vector<int> info(pc->nstored);
     VIE_HIP(hipMemcpy(info.data(), pc->info.p, sizeof(int) * pc->nstored, hipMemcpyDeviceToHost));
     for (int i = 0; i < pc->nstored; ++i)

@@ -56,6 +56,26 @@ __host__ __device__ __forceinline__ cpx<R> cdiv(cpx<R> a, cpx<R> b) {
 template <class R>
 __host__ __device__ __forceinline__ cpx<R> czero() { return mk<R>(R(0), R(0)); }
 
+// Complex bfloat16 (stored preconditioner factors): real part in the low 16 bits, imaginary
+// part in the high 16 bits; bfloat16 = the upper half of an IEEE binary32.
+struct bf16c {
+    uint32_t v;
+};
+// Load a stored factor entry as working precision (identity for complex float/double).
+template <class R>
+__device__ __forceinline__ cpx<R> ldf(const cpx<R> *p) {
+    return *p;
+}
+__device__ __forceinline__ c64 ldf(const bf16c *p) {
+    const uint32_t v = p->v;
+    return mk(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+}
+// Round a float to bfloat16, to nearest with ties to even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
 // Division of small non-negative ints (numerator < 2^20) by a runtime divisor: a float
 // reciprocal estimate and one correction step each way replace the integer division sequence.
 struct FastDiv {
@@ -176,6 +196,12 @@ struct vie_pc_s {
     int n_wide = 0, n_narrow = 0, wide_ct = 1;
     DevBuf sched;                          // int4 wide items [n_wide] then int32 box*bx+mode [n_narrow]
     DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
+    DevBuf wide_scratch2;                  // second solve of a refined apply
+    // refinement of VIE_BF16C solves
+    int refine = 0;
+    DevBuf chan32;                         // complex float C^_k tables [n][6][2bz-1][2by-1] per box length
+    DevBuf mt32;                           // complex float M~ [nboxes][bz][by]
+    DevBuf smode_dev;                      // int32 [nstored] mode of each stored block
 };
 
 // ---------------------------------------------------------------- profiling

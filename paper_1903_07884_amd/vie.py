@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, 'libvie.so')
 
-VIE_C128, VIE_C64 = 0, 1
+VIE_C128, VIE_C64, VIE_BF16C = 0, 1, 2
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
 STATUS = {0: 'VIE_OK', 1: 'VIE_NOT_CONVERGED', -1: 'VIE_EARG', -2: 'VIE_EOOM', -3: 'VIE_EDEVICE',
           -4: 'VIE_ESINGULAR', -5: 'VIE_ENONFINITE'}
@@ -39,7 +39,7 @@ class CreateOpts(ctypes.Structure):
 class PcOpts(ctypes.Structure):
     _fields_ = [('homog', ctypes.c_int32), ('nboxes', ctypes.c_int32), ('boxes', ctypes.c_void_p),
                 ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32),
-                ('proxy', ctypes.c_int32)]
+                ('proxy', ctypes.c_int32), ('refine_steps', ctypes.c_int32)]
 
 
 class PcInfo(ctypes.Structure):
@@ -178,13 +178,17 @@ class Preconditioner:
     """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
 
     def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, proxy='product',
-                 stream=None):
-        """``factor_prec``: VIE_C128 (FP64 solves) or VIE_C64 (mixed-precision solves);
-        ``proxy``: 'product' or 'centre' reading of the memory-reduction proxy column."""
+                 refine=None, stream=None):
+        """``factor_prec``: VIE_C128 (FP64 solves), VIE_C64 or VIE_BF16C (mixed-precision
+        solves, complex64 vectors); ``proxy``: 'product' or 'centre' reading of the
+        memory-reduction proxy column; ``refine``: refinement steps of the bfloat16 block
+        solves (default 1 for VIE_BF16C, else 0)."""
         lib = load()
         self.op = op
         bx = None
-        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, {'product': 0, 'centre': 1}[proxy])
+        if refine is None:
+            refine = 1 if factor_prec == VIE_BF16C else 0
+        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, {'product': 0, 'centre': 1}[proxy], int(refine))
         if boxes is not None:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
             o.nboxes = bx.shape[0]

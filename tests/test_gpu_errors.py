@@ -126,6 +126,15 @@ def test_argument_errors(gpu_lib):
         op.matvec(b.to(torch.complex64), torch.empty(op.n, dtype=torch.complex64, device='cuda'))
     y32 = torch.empty(op.n, dtype=torch.complex64, device='cuda')
     op32.matvec(b.to(torch.complex64), y32)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Preconditioner(op32, factor_prec=gpu_lib.VIE_C64, refine=1)     # refinement needs bfloat16 factors
+    assert e.value.status == -1
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Preconditioner(op, factor_prec=gpu_lib.VIE_BF16C)              # operator without complex64
+    assert e.value.status == -1
+    pcb = gpu_lib.Preconditioner(op32, factor_prec=gpu_lib.VIE_BF16C)
+    with pytest.raises(gpu_lib.VieError):
+        pcb.apply(b, torch.empty_like(b))                                    # complex128 vectors, bfloat16 factors
 
 
 def test_zero_contrast_matvec_is_identity(gpu_lib):

@@ -222,6 +222,45 @@ def test_precond_apply_many_rhs(gpu_lib, case):
     assert max(errs) < (1e-5 if c64 else 1e-10)
 
 
+BF16_CASES = [
+    # grid, nrhs, reduce_tol
+    ((32, 8, 6), 16, None),
+    ((32, 8, 6), 1, None),
+    ((24, 6, 4), 20, 1e-2),
+    ((12, 12, 8), 8, None),
+]
+
+
+@pytest.mark.parametrize("case", BF16_CASES)
+def test_precond_apply_bf16_refined(gpu_lib, case):
+    """bfloat16 factors (FP32 factorisation, rounded): one refinement step against D_k in
+    FP32 cuts the error of the plain bfloat16 solve, both compared with the FP64 oracle."""
+    import torch
+    grid, nrhs, tol = case
+    delta = 50e-9
+    K = oracle_generator(grid, delta)
+    chi = random_contrast(grid, 13)
+    chi = np.broadcast_to(chi[:, :, :1], chi.shape).copy()
+    M = OCT.contrast_from_chi(chi)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid, reduce_tol=tol)
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=True)
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((nrhs, n), 43)
+    z_ref = np.stack([ref_pc.apply(r[i]) for i in range(nrhs)])
+    rd = _to_dev(r.astype(np.complex64))
+    errs = {}
+    for refine in (0, 1):
+        pc = gpu_lib.Preconditioner(op, reduce_tol=tol, factor_prec=gpu_lib.VIE_BF16C, refine=refine)
+        zd = torch.empty_like(rd)
+        pc.apply(rd, zd, nrhs=nrhs)
+        z = zd.cpu().numpy().astype(np.complex128)
+        errs[refine] = max(_rel(z[i], z_ref[i]) for i in range(nrhs))
+        assert pc.info()['factor_bytes'] == pc.info()['stored_blocks'] * pc.info()['block_m'] * (pc.info()['block_m'] * 4 + 4)
+    print('bf16', grid, nrhs, tol, 'plain err %.3e refined err %.3e' % (errs[0], errs[1]))
+    assert errs[0] < 5e-2
+    assert errs[1] < 1e-3 and errs[1] < errs[0] / 4
+
+
 @pytest.mark.parametrize("precond", [False, True])
 def test_solve_matches_oracle_gmres(gpu_lib, precond):
     import torch
@@ -357,6 +396,27 @@ def test_mixed_solve_reaches_fp64_residual(gpu_lib):
           % (st['iters'], st['restarts'], st['relres'], res, err, info_ref['iters']))
     assert st['status'] == 0 and res <= 1e-6
     assert err < 1e-4
+
+
+def test_mixed_solve_bf16_factors_reaches_fp64_residual(gpu_lib):
+    """Flexible GMRES with bfloat16 factors + one FP32 refinement step per block solve."""
+    import torch
+    grid, delta, K, chi, M, b = _bragg_problem()
+    boxes = [(0, 0, 0, 24, 8, 2), (24, 0, 0, 24, 8, 2)]
+    A = OM.operator_matrix(K, M, grid)
+    P = OC.BlockedPreconditioner(K, M, grid, boxes=boxes, homog='realmean')
+    x_ref, _ = OGM.gmres(lambda v: A @ v, b, M=P.apply, tol=1e-10)
+    op = gpu_lib.Operator(grid, delta, KB, chi, build_c64=True)
+    pcb = gpu_lib.Preconditioner(op, homog='realmean', boxes=boxes, factor_prec=gpu_lib.VIE_BF16C)
+    bd = _to_dev(b)
+    xd = torch.zeros_like(bd)
+    st = gpu_lib.solve(op, pcb, bd, xd, tol=1e-6, mode='mixed')[0]
+    x = xd.cpu().numpy()
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    print('bf16 mixed: iters %d relres %.3e oracle-evaluated %.3e error vs oracle %.3e'
+          % (st['iters'], st['relres'], res, _rel(x, x_ref)))
+    assert st['status'] == 0 and res <= 1e-6
+    assert _rel(x, x_ref) < 1e-4
 
 
 def test_batched_solve_equals_single(gpu_lib):
