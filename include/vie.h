@@ -201,6 +201,38 @@ vie_status vie_profile_begin(void);
 vie_status vie_profile_kernel(const char *name, double *total_ms, int64_t *launches);
 vie_status vie_profile_end(void);
 
+/* ---- footprint ------------------------------------------------------------------
+ * Upper bound, in bytes, of the device memory held by `op` (with the transient of its
+ * creation) plus, when `pc` is not NULL, a
+ * preconditioner built from those options (every mode stored, i.e. no memory reduction
+ * credited, factorisation temporaries and LU workspace included) plus, when `so` is not
+ * NULL, one vie_solve of `nrhs` right-hand sides with those options (Krylov basis, flexible
+ * basis, residual and reduction workspace, and the per-call matvec / apply scratch the solve
+ * grows), with autotuning off.  An admission controller compares it with the free HBM
+ * before it creates the preconditioner or starts the solve.  Argument errors as for
+ * precond_setup / vie_solve. */
+vie_status vie_footprint(vie_op op, const vie_pc_opts *pc, int32_t nrhs, const vie_solve_opts *so,
+                         uint64_t *bytes);
+
+/* Device bytes currently held by all handles and calls of this library (process-wide) and
+ * the high-water mark since the last reset (reset_peak != 0 first sets it to the current
+ * value).  Either output may be NULL. */
+vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_t reset_peak);
+
+/* ---- autotuning ----------------------------------------------------------------
+ * With autotuning on, the first precond_apply (and vie_solve) for a new problem shape and
+ * right-hand-side count times every candidate launch configuration of the block solves
+ * (column-group width and workgroup height of the matrix-core solve, right-hand sides per
+ * workgroup of the per-mode solve, and the right-hand-side count from which blocks use the
+ * matrix-core solve) on a copy of the data, and the first vie_matvec for a new shape times
+ * the thread counts of its FFT passes; the fastest is kept for the rest of the process,
+ * keyed by the shape.  Results never depend on the choice beyond rounding order.
+ * vie_autotune_report writes the cache as text ("key -> choice (ms, candidates)" lines)
+ * into buf (truncated to size - 1 characters, NUL-terminated); *needed receives the full
+ * length + 1.  Both calls are process-wide and thread-safe. */
+vie_status vie_autotune(int32_t enable);
+vie_status vie_autotune_report(char *buf, int64_t size, int64_t *needed);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *vie_last_error(void);
 

@@ -238,6 +238,54 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     return VIE_OK;
 }
 
+extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t nrhs, const vie_solve_opts *so,
+                                   uint64_t *bytes) {
+    if (!op || !bytes) return arg_error("vie_footprint: NULL argument");
+    if (nrhs < 1) return arg_error("vie_footprint: nrhs must be >= 1");
+    const uint64_t N = (uint64_t)op->N, R = (uint64_t)nrhs, n3 = 3 * N;
+    const uint64_t lines = 3ULL * op->ny * op->nz * R;
+    // operator: contrast, generator, kernel transforms (held) and the matvec scratch
+    uint64_t b = op->M64.bytes + op->M32.bytes + op->gen.bytes + op->khat64.bytes + op->khat32.bytes;
+    b += 6ULL * 16 * op->Px * op->Py * op->Pz;  // the circulant embedding transformed during vie_create
+    uint64_t mv_scratch = sizeof(c128) * lines * (uint64_t)op->Px;
+    uint64_t pc_bytes = 0, apply_scratch = 0;
+    bool mixed_pc = false;
+    if (pco) {
+        const vie_pc_opts &o = *pco;
+        if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
+            return arg_error("vie_footprint: unknown factor precision");
+        if (o.nboxes < 0 || (o.nboxes > 0 && !o.boxes)) return arg_error("vie_footprint: bad boxes");
+        const int *B = o.nboxes ? o.boxes : nullptr;
+        const uint64_t nb = o.nboxes ? o.nboxes : 1;
+        const uint64_t bx = B ? B[3] : op->nx, by = B ? B[4] : op->ny, bz = B ? B[5] : op->nz;
+        if (bx < 1 || by < 1 || bz < 1) return arg_error("vie_footprint: bad box shape");
+        const uint64_t m = 3 * by * bz, modes = nb * bx;
+        const uint64_t fesz = o.factor_prec == VIE_C128 ? 16 : o.factor_prec == VIE_BF16C ? 4 : 8;
+        const uint64_t vesz = o.factor_prec == VIE_C128 ? 16 : 8;  // vector / factorisation precision
+        mixed_pc = o.factor_prec != VIE_C128;
+        const uint64_t table = modes / nb * 6 * (2 * by - 1) * (2 * bz - 1);
+        pc_bytes = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
+        if (o.factor_prec == VIE_BF16C) pc_bytes += modes * m * m * 8;  // complex-float factorisation copy
+        pc_bytes += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;  // Chan table, LU workspace
+        if (o.refine_steps) pc_bytes += table * 8 + nb * by * bz * 8;
+        // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
+        const uint64_t cols = modes * R;
+        const uint64_t wide = (cols + 64 * modes) * m * vesz;
+        apply_scratch = R * nb * m * bx * vesz + wide * (o.refine_steps ? 2 : 1);
+    }
+    uint64_t solve_bytes = 0;
+    if (so) {
+        if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
+        const uint64_t rs = (uint64_t)so->restart;
+        const bool mixed = so->mode == VIE_MODE_MIXED;
+        solve_bytes = 16 * R * n3 * (rs + 1) + (mixed ? 8 : 16) * R * n3 * rs + 2 * 16 * R * n3 +
+                      16 * R * 256 * (rs + 2) + (mixed ? 2 * 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
+        (void)mixed_pc;
+    }
+    *bytes = b + mv_scratch + pc_bytes + apply_scratch + solve_bytes;
+    return VIE_OK;
+}
+
 extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
     if (!pc || !info) return arg_error("precond_info: NULL argument");
     info->nboxes = pc->nboxes;

@@ -14,6 +14,7 @@
 //    mode, and, under the memory reduction, every mode that shares the central block.  The
 //    products run on the matrix cores.
 #include <algorithm>
+#include <cstdio>
 
 #include "fft_device.h"
 #include "vie_internal.h"
@@ -628,18 +629,20 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     const int n = pc->bx;
     // bfloat16 factors are solved on the matrix cores only (every block goes wide)
     const bool all_wide = pc->prec == VIE_BF16C;
-    const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : WIDE_MIN_RHS;
+    const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : pc->cfg_min_rhs;
     std::vector<int> wide;    // int4 items
     std::vector<int> narrow;  // box * n + mode
     int maxc = 0;
-    // group width: the widest of 64 / 32 / 16 columns that still gives >= 512 workgroups
     long long wide_cols = 0;
     for (int sb = 0; sb < pc->nstored; ++sb) {
         const long long cols = (long long)(pc->mode_ptr[sb + 1] - pc->mode_ptr[sb]) * nrhs;
         if (cols >= min_cols && nrhs >= min_rhs) wide_cols += cols;
     }
-    int gmax = WIDE_MAX_COLS;
-    while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
+    int gmax = pc->cfg_gmax;
+    if (gmax == 0) {  // default: the widest group that still gives >= 512 workgroups
+        gmax = WIDE_MAX_COLS;
+        while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
+    }
     for (int sb = 0; sb < pc->nstored; ++sb) {
         const int cnt = pc->mode_ptr[sb + 1] - pc->mode_ptr[sb];
         const long long cols = (long long)cnt * nrhs;
@@ -668,10 +671,9 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     return VIE_OK;
 }
 
-template <class R, int CT, class FT>
-static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
-                        hipStream_t s) {
-    constexpr int NW = sizeof(R) == 4 ? 16 : 8;  // wavefronts per workgroup (16 NW rows per super-tile)
+template <class R, int CT, int NW, class FT>
+static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
+                           hipStream_t s) {
     const int per = (pc->n_wide + 7) / 8;
     const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16;
     vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
@@ -679,6 +681,25 @@ static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mo
     hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
                        mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs, out_mode, Yadd);
+}
+
+// wavefronts per workgroup (16 NW rows per super-tile): 8 or 16 for FP32, 4 or 8 for FP64
+static int wide_nw(vie_pc pc, bool fp32) {
+    if (pc->cfg_nw) return pc->cfg_nw;
+    return fp32 ? 16 : 8;
+}
+
+template <class R, int CT, class FT>
+static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
+                        hipStream_t s) {
+    const int nw = wide_nw(pc, sizeof(R) == 4);
+    if (sizeof(R) == 4) {
+        if (nw == 8) launch_wide_nw<R, CT, 8, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+        else launch_wide_nw<R, CT, 16, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+    } else {
+        if (nw == 4) launch_wide_nw<R, CT, 4, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+        else launch_wide_nw<R, CT, 8, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+    }
 }
 
 template <int CT>
@@ -695,13 +716,9 @@ static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStr
 }
 
 template <class R, class FT>
-static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
+static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
     const int m = pc->m, n = pc->bx;
     const int qr = (m + 255) / 256;
-    if (qr > VIE_MAX_QR) {
-        vie_set_error("block size above 1280 is not supported by the block solve");
-        return VIE_EARG;
-    }
     VIE_CHECK(build_schedule(pc, nrhs, s));
     if (pc->n_wide > 0) {
         const int WC = 16 * pc->wide_ct;
@@ -734,7 +751,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
         VIE_HIP(hipGetLastError());
     }
     if (pc->n_narrow > 0) {
-        const int rc = block_solve_rc(m, nrhs, sizeof(cpx<R>));
+        const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(m, nrhs, sizeof(cpx<R>));
         dim3 grid((unsigned)pc->n_narrow, (unsigned)((nrhs + rc - 1) / rc));
         size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
         const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
@@ -750,6 +767,62 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
         VIE_HIP(hipGetLastError());
     }
     return VIE_OK;
+}
+
+// Launch parameters of the block solves for `nrhs` right-hand sides: the defaults, or with
+// autotuning on the fastest candidate for this shape (timed on a copy of `work`, since the
+// solves run in place), looked up in or added to the process-wide cache.
+template <class R, class FT>
+static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
+    if ((pc->m + 255) / 256 > VIE_MAX_QR) {
+        vie_set_error("block size above 1280 is not supported by the block solve");
+        return VIE_EARG;
+    }
+    if (tune_enabled() && pc->tuned_nrhs != nrhs) {
+        const bool bf = pc->prec == VIE_BF16C, fp32 = sizeof(R) == 4;
+        char key[160];
+        snprintf(key, sizeof key, "block_solve prec=%d m=%d n=%d boxes=%d stored=%d nrhs=%d refine=%d", pc->prec,
+                 pc->m, pc->bx, pc->nboxes, pc->nstored, nrhs, pc->refine);
+        std::vector<int> choice;
+        if (!tune_lookup(key, &choice)) {
+            std::vector<std::vector<int>> cands;  // {gmax, nw, rc, min_rhs}
+            const int rcmax = block_solve_rc(pc->m, nrhs, sizeof(cpx<R>));
+            const int nws[2] = {fp32 ? 8 : 4, fp32 ? 16 : 8};
+            if (bf || nrhs >= WIDE_MIN_RHS)
+                for (int g = 16; g <= WIDE_MAX_COLS; g *= 2)
+                    for (int nw : nws) cands.push_back({g, nw, 0, bf ? 1 : WIDE_MIN_RHS});
+            if (!bf && nrhs < 32)
+                for (int rc = 1; rc <= rcmax; rc *= 2) cands.push_back({0, 0, rc, 1 << 30});
+            if (cands.size() > 1) {
+                const size_t bytes = sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->bx;
+                DevBuf copy;
+                VIE_CHECK(copy.ensure(bytes));
+                double best = 1e300;
+                for (auto &c : cands) {
+                    pc->cfg_gmax = c[0], pc->cfg_nw = c[1], pc->cfg_rc = c[2], pc->cfg_min_rhs = c[3];
+                    pc->sched_nrhs = 0;
+                    double ms = 0;
+                    VIE_CHECK(tune_time(s, 2, [&]() -> vie_status {
+                        VIE_HIP(hipMemcpyAsync(copy.p, work, bytes, hipMemcpyDeviceToDevice, s));
+                        return block_solve_run<R, FT>(pc, copy.as<cpx<R>>(), nrhs, s);
+                    }, &ms));
+                    if (ms < best) {
+                        best = ms;
+                        choice = c;
+                    }
+                }
+                tune_store(key, choice, best, (int)cands.size());
+            } else if (cands.size() == 1) {
+                choice = cands[0];
+            }
+        }
+        if (!choice.empty()) {
+            pc->cfg_gmax = choice[0], pc->cfg_nw = choice[1], pc->cfg_rc = choice[2], pc->cfg_min_rhs = choice[3];
+            pc->sched_nrhs = 0;
+        }
+        pc->tuned_nrhs = nrhs;
+    }
+    return block_solve_run<R, FT>(pc, work, nrhs, s);
 }
 
 vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s) {

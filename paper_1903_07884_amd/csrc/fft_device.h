@@ -276,23 +276,29 @@ __device__ __forceinline__ cpx<R> *fft_line(cpx<R> *a, const FftPlan &plan, bool
     } while (0)
 
 // Launch shape of a one-line-per-workgroup transform: threads, LDS bytes and the
-// butterflies-per-thread template argument (0 = ping-pong).
-inline void fft_line_shape(const FftPlan &plan, size_t esz, int *threads, size_t *lds, int *bpt) {
+// butterflies-per-thread template argument (0 = ping-pong).  t_req > 0 asks for that many
+// threads (a multiple of 64, <= 1024); returns false if an in-place transform would then
+// need more than 4 butterflies per thread.
+inline bool fft_line_shape(const FftPlan &plan, size_t esz, int *threads, size_t *lds, int *bpt, int t_req = 0) {
     int L = plan.L;
     int t = 64;
     while (t < 256 && t * 4 < L) t *= 2;
     if (fft_line_inplace(plan, esz)) {
         t = 64;
         while (t < 1024 && (long long)t * 2 * 2 < L) t *= 2;  // radix-2 stage with 2 per thread
+        if (t_req > 0) t = t_req;
         int b = 2;
         while ((long long)t * b * 2 < L) b *= 2;
         *bpt = b;
         *lds = esz * (size_t)L;
-    } else {
-        *bpt = 0;
-        *lds = 2 * esz * (size_t)L;
+        *threads = t;
+        return b <= 4;
     }
+    if (t_req > 0) t = t_req;
+    *bpt = 0;
+    *lds = 2 * esz * (size_t)L;
     *threads = t;
+    return true;
 }
 
 extern __shared__ __align__(16) unsigned char vie_smem[];

@@ -1,3 +1,4 @@
+#include <atomic>
 // FFT plans: radix factorisation and device twiddle tables.
 #include <cmath>
 #include <mutex>
@@ -97,6 +98,16 @@ FftCache::~FftCache() {
     }
 }
 
+// Device bytes held by the library's buffers, and their high-water mark.
+static std::atomic<uint64_t> g_dev_cur{0}, g_dev_peak{0};
+
+extern "C" vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_t reset_peak) {
+    if (reset_peak) g_dev_peak.store(g_dev_cur.load());
+    if (current) *current = g_dev_cur.load();
+    if (peak) *peak = g_dev_peak.load();
+    return VIE_OK;
+}
+
 vie_status DevBuf::ensure(size_t nbytes) {
     if (nbytes <= bytes && p) return VIE_OK;
     release();
@@ -110,11 +121,18 @@ vie_status DevBuf::ensure(size_t nbytes) {
         return e == hipErrorOutOfMemory ? VIE_EOOM : VIE_EDEVICE;
     }
     bytes = nbytes;
+    const uint64_t cur = g_dev_cur.fetch_add(nbytes) + nbytes;
+    uint64_t pk = g_dev_peak.load();
+    while (cur > pk && !g_dev_peak.compare_exchange_weak(pk, cur)) {
+    }
     return VIE_OK;
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+        (void)hipFree(p);
+        g_dev_cur.fetch_sub(bytes);
+    }
     p = nullptr;
     bytes = 0;
 }

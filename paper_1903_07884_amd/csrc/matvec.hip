@@ -11,6 +11,8 @@
 //   2. per x-frequency: 2-D (y,z) FFT of the three components, 3x3 multiply
 //      with the octant-stored, parity-signed Khat, inverse 2-D FFT, crop,
 //   3. inverse x-FFT of every line, crop, and y = x - M (x + K x).
+#include <cstdio>
+
 #include "fft_device.h"
 
 template <class R>
@@ -387,15 +389,17 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
 }
 
 template <class R>
-static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
-                           const cpx<R> *M, hipStream_t s) {
+static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
+                             const cpx<R> *M, hipStream_t s) {
     const int nx = op->nx, ny = op->ny, nz = op->nz, Px = op->Px;
+    const int pi = sizeof(R) == 8 ? 0 : 1;
     long long lines = 3LL * ny * nz * nrhs;
     VIE_CHECK(op->work.ensure(sizeof(cpx<R>) * lines * Px));
     cpx<R> *work = op->work.as<cpx<R>>();
     size_t ldsx;
     int thx, bpt;
-    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt);
+    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, op->cfg_x_thr[pi]);
+    const int thp = op->cfg_plane_thr[pi] ? op->cfg_plane_thr[pi] : 256;
     {
         ProfScope ps("matvec_xfwd", s);
 #define LAUNCH_XFWD(B)                                      \
@@ -407,16 +411,15 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     VIE_HIP(hipGetLastError());
     if (op->direct_z) {
         size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
-        int thr = 256;
         vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thr), ldsp, s, work, khat, ny, nz, Px,
+        hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz, Px,
                            op->Hy, op->py);
     } else {
         size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
         vie_lds_attr((const void *)k_plane<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(256), ldsp, s, work, khat, ny, nz, Px,
+        hipLaunchKernelGGL(k_plane<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz, Px,
                            op->Hx, op->Hy, op->Hz, op->py, op->pz);
     }
     VIE_HIP(hipGetLastError());
@@ -431,6 +434,47 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     }
     VIE_HIP(hipGetLastError());
     return VIE_OK;
+}
+
+// FFT launch parameters for `nrhs` right-hand sides: defaults, or with autotuning on the
+// fastest (plane-pass threads x x-line threads) for this shape, cached per process.
+template <class R>
+static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
+                           const cpx<R> *M, hipStream_t s) {
+    const int pi = sizeof(R) == 8 ? 0 : 1;
+    if (tune_enabled() && op->tuned_nrhs[pi] != nrhs) {
+        char key[160];
+        snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d", (int)sizeof(cpx<R>),
+                 op->Px, op->Py, op->Pz, op->nx, op->ny, op->nz, nrhs, (int)op->direct_z);
+        std::vector<int> choice;
+        if (!tune_lookup(key, &choice)) {
+            int t0, b0;
+            size_t l0;
+            fft_line_shape(op->px, sizeof(cpx<R>), &t0, &l0, &b0);
+            std::vector<std::vector<int>> cands;
+            for (int tp : {128, 256, 512})
+                for (int tx : {t0 / 2, t0, 2 * t0}) {
+                    int t, b;
+                    size_t l;
+                    if (tx < 64 || tx > 1024 || !fft_line_shape(op->px, sizeof(cpx<R>), &t, &l, &b, tx)) continue;
+                    cands.push_back({tp, tx});
+                }
+            double best = 1e300;
+            for (auto &c : cands) {
+                op->cfg_plane_thr[pi] = c[0], op->cfg_x_thr[pi] = c[1];
+                double ms = 0;
+                VIE_CHECK(tune_time(s, 2, [&]() { return matvec_run<R>(op, x, y, nrhs, khat, M, s); }, &ms));
+                if (ms < best) {
+                    best = ms;
+                    choice = c;
+                }
+            }
+            tune_store(key, choice, best, (int)cands.size());
+        }
+        op->cfg_plane_thr[pi] = choice[0], op->cfg_x_thr[pi] = choice[1];
+        op->tuned_nrhs[pi] = nrhs;
+    }
+    return matvec_run<R>(op, x, y, nrhs, khat, M, s);
 }
 
 vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s) {

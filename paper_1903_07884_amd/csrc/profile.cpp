@@ -16,6 +16,7 @@ std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
 }  // namespace
 
 ProfScope::ProfScope(const char *name, hipStream_t stream) : s(stream) {
+    if (tune_active()) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     hipEvent_t a, b;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -170,6 +171,8 @@ struct vie_op_s {
     bool has_c64 = false;
     bool direct_z = false;   // kernel transform along x, y only; z handled as a direct Toeplitz sum
     DevBuf work;             // matvec intermediate, nrhs*3*ny*nz*Px complex
+    // FFT launch parameters per vector precision (0 = default; autotuned for tuned_nrhs)
+    int cfg_plane_thr[2] = {0, 0}, cfg_x_thr[2] = {0, 0}, tuned_nrhs[2] = {-1, -1};
     FftCache fft;
     FftPlan px, py, pz;      // plans for the three periods
 };
@@ -202,6 +205,12 @@ struct vie_pc_s {
     DevBuf chan32;                         // complex float C^_k tables [n][6][2bz-1][2by-1] per box length
     DevBuf mt32;                           // complex float M~ [nboxes][bz][by]
     DevBuf smode_dev;                      // int32 [nstored] mode of each stored block
+    // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)
+    int cfg_gmax = 0;        // widest column group of the wide solve (0: widest giving >= 512 groups)
+    int cfg_nw = 0;          // wavefronts per wide workgroup (0: 16 for FP32, 8 for FP64)
+    int cfg_rc = 0;          // right-hand sides per narrow workgroup (0: register-budget rule)
+    int cfg_min_rhs = 8;     // blocks go wide from this many right-hand sides on
+    int tuned_nrhs = -1;
 };
 
 // ---------------------------------------------------------------- profiling
@@ -212,6 +221,14 @@ struct ProfScope {
     ProfScope(const char *name, hipStream_t stream);
     ~ProfScope();
 };
+
+// ---------------------------------------------------------------- autotuner (tune.cpp)
+bool tune_enabled();
+bool tune_active();  // candidates are running: profiling records nothing
+bool tune_lookup(const std::string &key, std::vector<int> *choice);
+void tune_store(const std::string &key, const std::vector<int> &choice, double ms, int candidates);
+// one warm-up run, then `reps` runs bracketed by events on `s`; *ms = time per run
+vie_status tune_time(hipStream_t s, int reps, const std::function<vie_status()> &run, double *ms);
 
 // ---------------------------------------------------------------- launchers
 // generator.hip

@@ -23,7 +23,8 @@ MODE = {'fp64': 0, 'mixed': 1}
 
 EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
            'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
-           'vie_profile_kernel', 'vie_profile_end', 'vie_last_error')
+           'vie_profile_kernel', 'vie_profile_end', 'vie_last_error', 'vie_footprint', 'vie_autotune',
+           'vie_autotune_report', 'vie_device_bytes')
 
 
 class VieError(RuntimeError):
@@ -86,9 +87,14 @@ def load(path=None):
     lib.vie_profile_begin.argtypes = []
     lib.vie_profile_kernel.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     lib.vie_profile_end.argtypes = []
-    lib.vie_last_error.restype = ctypes.c_char_p
-    for name in EXPORTS[:-1]:
+    lib.vie_autotune.argtypes = [i32]
+    lib.vie_device_bytes.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), i32]
+    lib.vie_footprint.argtypes = [vp, ctypes.POINTER(PcOpts), i32, ctypes.POINTER(SolveOpts),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    lib.vie_autotune_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_int
+    lib.vie_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -230,6 +236,52 @@ def solve(op, pc, b, x, nrhs=1, tol=1e-6, restart=50, maxit=5000, mode='fp64', x
                          _dev(x, torch.complex128), nrhs, ctypes.byref(o), st, _stream(stream)),
            allow=(VIE_OK, VIE_NOT_CONVERGED))
     return [{f: getattr(s, f) for f, _ in SolveStats._fields_} for s in st]
+
+
+def footprint(op, nrhs=1, homog='none', boxes=None, reduce_tol=None, factor_prec=None, refine=None,
+              restart=50, mode='fp64', solve=True):
+    """vie_footprint: upper bound of the device bytes of op + preconditioner (factor_prec not
+    None) + one solve of nrhs right-hand sides (solve=True)."""
+    lib = load()
+    po = None
+    bx = None
+    if factor_prec is not None:
+        if refine is None:
+            refine = 1 if factor_prec == VIE_BF16C else 0
+        po = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, 0, int(refine))
+        if boxes is not None:
+            bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
+            po.nboxes = bx.shape[0]
+            po.boxes = bx.ctypes.data
+        if reduce_tol is not None:
+            po.reduce, po.reduce_tol = 1, float(reduce_tol)
+    so = SolveOpts(1e-6, int(restart), 5000, MODE[mode], 0) if solve else None
+    out = ctypes.c_uint64()
+    _check(lib.vie_footprint(op.h, ctypes.byref(po) if po is not None else None, int(nrhs),
+                             ctypes.byref(so) if so is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+def device_bytes(reset_peak=False):
+    """(current, peak) device bytes held by the library (vie_device_bytes)."""
+    cur, pk = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().vie_device_bytes(ctypes.byref(cur), ctypes.byref(pk), 1 if reset_peak else 0))
+    return int(cur.value), int(pk.value)
+
+
+def autotune(enable=True):
+    """Process-wide switch of the launch-parameter autotuner (vie_autotune)."""
+    _check(load().vie_autotune(1 if enable else 0))
+
+
+def autotune_report():
+    """The autotuner cache as text, one 'key -> choice (ms, candidates)' line per shape."""
+    lib = load()
+    need = ctypes.c_int64()
+    _check(lib.vie_autotune_report(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(max(int(need.value), 1))
+    _check(lib.vie_autotune_report(buf, len(buf), ctypes.byref(need)))
+    return buf.value.decode()
 
 
 def profile_begin():

@@ -167,3 +167,28 @@ def test_preconditioned_iterations_flat_in_length(gpu_lib):
     assert max(its) - min(its) <= 4
     assert its_none[0] < its_none[1] < its_none[2]
     assert min(its_none) > 2 * max(its)
+
+
+def test_footprint_bounds_the_allocations(gpu_lib):
+    """vie_footprint bounds the library's device high-water mark over create + setup + solve
+    (a mixed, 8-RHS coupler at reduced length), and it is not loose by more than 3x."""
+    import torch
+    cfg = dict(grid=(128, 48, 8), delta=25e-9, nrhs=8, geometry='coupler', wy=0.2e-6, wz=0.1e-6)
+    for fprec, mode in ((gpu_lib.VIE_C64, 'mixed'), (gpu_lib.VIE_BF16C, 'mixed'), (gpu_lib.VIE_C128, 'fp64')):
+        torch.cuda.synchronize()
+        base, _ = gpu_lib.device_bytes(reset_peak=True)
+        op = gpu_lib.Operator(cfg['grid'], cfg['delta'], KB, W.make_chi(cfg), build_c64=True)
+        fp = gpu_lib.footprint(op, nrhs=8, factor_prec=fprec, mode=mode)
+        fp_op = gpu_lib.footprint(op, nrhs=8, solve=False)
+        assert 0 < fp_op < fp
+        pc = gpu_lib.Preconditioner(op, factor_prec=fprec)
+        e = _dev(W.make_sources(cfg, 3).reshape(8, -1))
+        b = torch.empty_like(e)
+        op.rhs(e, b, nrhs=8)
+        x = torch.zeros_like(b)
+        gpu_lib.solve(op, pc, b, x, nrhs=8, tol=1e-6, mode=mode, maxit=60)
+        _, peak = gpu_lib.device_bytes()
+        used = peak - base
+        print('prec %d: footprint %.1f MB, library high-water mark %.1f MB' % (fprec, fp / 1e6, used / 1e6))
+        assert used <= fp <= 3 * used
+        del pc, op

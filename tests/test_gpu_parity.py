@@ -261,6 +261,36 @@ def test_precond_apply_bf16_refined(gpu_lib, case):
     assert errs[1] < 1e-3 and errs[1] < errs[0] / 4
 
 
+def test_autotuned_launches_give_the_same_results(gpu_lib):
+    """Autotuning picks launch parameters only: results agree with the defaults to rounding,
+    and every tuned shape appears in the report."""
+    import torch
+    grid, delta, nrhs = (32, 8, 6), 50e-9, 24
+    K = oracle_generator(grid, delta)
+    chi = random_contrast(grid, 14)
+    chi = np.broadcast_to(chi[:, :, :1], chi.shape).copy()
+    n = 3 * int(np.prod(grid))
+    r = _to_dev(W.random_field((nrhs, n), 45).astype(np.complex64))
+    out = {}
+    try:
+        for tuned in (False, True):
+            gpu_lib.autotune(tuned)
+            op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=True)
+            pc = gpu_lib.Preconditioner(op, factor_prec=gpu_lib.VIE_C64)
+            z = torch.empty_like(r)
+            y = torch.empty_like(r)
+            pc.apply(r, z, nrhs=nrhs)
+            op.matvec(r, y, nrhs=nrhs)
+            out[tuned] = (z.cpu().numpy(), y.cpu().numpy())
+    finally:
+        gpu_lib.autotune(False)
+    rep = gpu_lib.autotune_report()
+    print(rep)
+    assert 'block_solve' in rep and 'matvec' in rep
+    assert _rel(out[True][0], out[False][0]) < 1e-5
+    assert _rel(out[True][1], out[False][1]) < 1e-5
+
+
 @pytest.mark.parametrize("precond", [False, True])
 def test_solve_matches_oracle_gmres(gpu_lib, precond):
     import torch
