@@ -52,22 +52,28 @@ def good_length(n):
         L += 1
 
 
-def algorithmic_models(cfg, info, R, mode):
-    """Per-launch algorithmic bytes of the HBM-bound kernels (bound, bytes, unit)."""
+def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0):
+    """Per-launch algorithmic work of the dominant kernels: (bound, amount, unit).
+
+    block_solve at few right-hand sides: every stored factor read once + rhat in + zhat out
+    + the permutation (HBM bytes); from 8 right-hand sides on the solves run on the matrix
+    cores and the bound is their FP32 (FP64) rate: 8 m^2 real flops per (mode, rhs) column
+    (L and U halves), three times that with one refinement step (two solves + the residual
+    product).  matvec: x in, y out and M per right-hand side, plus the octant transform once."""
     nx, ny, nz = cfg['grid']
     N = nx * ny * nz
-    v = 16 if mode == 'fp64' else 8      # vector / factor bytes per complex
+    v = 16 if mode == 'fp64' else 8      # vector bytes per complex
+    f = {'c128': 16, 'c64': 8, 'bf16': 4}[factor]
     m = info['block_m']
     modes = info['modes']
     stored = info['stored_blocks']
     Hx, Hy, Hz = (good_length(2 * n - 1) // 2 + 1 for n in (nx, ny, nz))
     khat = 6 * Hx * Hy * Hz * v
-    return {
-        # every stored factor read once + rhat in + zhat out + permutation, per right-hand side
-        'block_solve': ('hbm', stored * m * m * v + R * modes * (2 * m * v + 4 * m), 'bytes'),
-        # x in, y out and M per right-hand side, plus the octant kernel transform once
-        'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes'),
-    }
+    if R >= 8:
+        bs = ('mfma', 8.0 * m * m * modes * R * (3 if refine else 1), 'flops')
+    else:
+        bs = ('hbm', stored * m * m * f + R * modes * (2 * m * v + 4 * m), 'bytes')
+    return {'block_solve': bs, 'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes')}
 
 
 def counter_traffic(kernel, workload_tag):
@@ -103,11 +109,13 @@ def workload_plan(cfg, tag):
     nx, ny, nz = cfg['grid']
     if tag == 3:   # Bragg: 16 equal x-segments, real part of the mean contrast, FP32 factors
         seg = nx // 16
-        return dict(mode='mixed', homog='realmean', reduce_tol=None,
+        return dict(mode='mixed', homog='realmean', reduce_tol=None, factor='c64',
                     boxes=[(i * seg, 0, 0, seg, ny, nz) for i in range(16)],
                     label='16 x-boxes, real-mean contrast')
-    if tag == 4:   # coupler: one box over the full cross-section (contrast is x-invariant)
-        return dict(mode='mixed', homog='none', reduce_tol=None, boxes=None, label='full cross-section')
+    if tag == 4:   # coupler: one box over the full cross-section (contrast is x-invariant),
+        # bfloat16 factors with one FP32 refinement step of every block solve
+        return dict(mode='mixed', homog='none', reduce_tol=None, boxes=None, factor='bf16',
+                    label='full cross-section, BF16 factors + FP32 refinement')
     return dict(mode='fp64', homog='none', reduce_tol=None, boxes=None, label='full 1-level')
 
 
@@ -200,6 +208,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--config', type=int, default=2)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-autotune', action='store_true',
+                    help='default launch parameters (otherwise the warm-up step autotunes them)')
     ap.add_argument('--copy-probe', type=int, default=0,
                     help='also run one plain device copy of this many bytes (calibrates HBM counters)')
     args = ap.parse_args()
@@ -228,11 +238,12 @@ def main():
     x_d = torch.empty_like(e_d)
     plan = workload_plan(cfg, args.config)
 
-    def step(record, mode=None, reduce_tol='default', boxes='default', proxy='product'):
+    def step(record, mode=None, reduce_tol='default', boxes='default', proxy='product', factor=None):
         mode = mode or plan['mode']
         bxs = plan['boxes'] if boxes == 'default' else boxes
         rt = plan['reduce_tol'] if reduce_tol == 'default' else reduce_tol
-        fp = vie.VIE_C64 if mode == 'mixed' else vie.VIE_C128
+        factor = factor or (plan.get('factor', 'c64') if mode == 'mixed' else 'c128')
+        fp = {'c128': vie.VIE_C128, 'c64': vie.VIE_C64, 'bf16': vie.VIE_BF16C}[factor]
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         op = vie.Operator(grid, delta, kb, chi_d, build_c64=(mode == 'mixed'))
@@ -254,7 +265,7 @@ def main():
                                solve_ms=ev[2].elapsed_time(ev[3]),
                                iters=max(q['iters'] for q in st), restarts=max(q['restarts'] for q in st),
                                relres=max(q['relres'] for q in st),
-                               status=max(q['status'] for q in st), info=info, mode=mode))
+                               status=max(q['status'] for q in st), info=info, mode=mode, factor=factor))
         return st
 
     if args.copy_probe:
@@ -264,7 +275,8 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
+    vie.autotune(not args.no_autotune)
+    for _ in range(max(args.warmup, 0 if args.no_autotune else 1)):
         step(None)
     torch.cuda.synchronize()
     vie.profile_begin()
@@ -276,7 +288,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     names = ['generator', 'matvec_xfwd', 'matvec_plane', 'matvec_xinv', 'precond_xfft', 'block_solve',
-             'precond_ixfft', 'lu_panel', 'lu_swap_trsm', 'lu_update', 'lu_invert_diag', 'arnoldi_dots',
+             'refine_residual', 'precond_ixfft', 'lu_panel', 'lu_swap_trsm', 'lu_update', 'lu_invert_diag', 'arnoldi_dots',
              'arnoldi_update']
     kern = {}
     for nm in names:
@@ -286,6 +298,9 @@ def main():
     vie.profile_end()
     ms_per_step = 1000.0 * (t1 - t0) / args.steps
     last = recs[-1]
+    per_step = sorted(r['create_ms'] + r['setup_ms'] + r['solve_ms'] for r in recs)
+    latency = dict(p50=float(np.percentile(per_step, 50)), p99=float(np.percentile(per_step, 99)),
+                   samples=len(per_step), what='create + setup + solve per step, HIP events')
     compare = {}
     if plan['mode'] == 'fp64':
         # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column
@@ -305,7 +320,8 @@ def main():
         # preconditioner), timed the same way, outside the main timed region
         extra = ()
         if args.config == 4:
-            extra = (('mixed_reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre')),)
+            extra = (('mixed_c64_factors', dict(factor='c64')),
+                     ('mixed_reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre')))
         if args.config == 3:
             extra = (('mixed_single_box', dict(boxes=None)), ('fp64_single_box', dict(mode='fp64', boxes=None)))
         for label, kw in (('fp64', dict(mode='fp64')),) + extra:
@@ -320,7 +336,8 @@ def main():
                                   stored_blocks=rr[0]['info']['stored_blocks'])
         compare['fp64_over_mixed_time'] = compare['fp64']['ms'] / ms_per_step
     info = last['info']
-    models = algorithmic_models(cfg, info, R, plan['mode'])
+    factor = last['factor']
+    models = algorithmic_models(cfg, info, R, plan['mode'], factor, refine=1 if factor == 'bf16' else 0)
 
     # dominant kernel and its roofline
     dom = max(names, key=lambda k: kern[k]['total_ms'])
@@ -333,6 +350,12 @@ def main():
         roof = dict(kernel=dom, bound='alu', achieved=achieved, peak=peak, unit='TFLOP/s',
                     frac=achieved / peak, traffic=None,
                     per_launch_work='%.4g real flops summed over %d launches' % (fl, launches))
+    elif dom in models and models[dom][0] == 'mfma':
+        _, amount, _ = models[dom]
+        achieved = amount / (kern[dom]['avg_us'] * 1e-6) / 1e12
+        peak = FP64_PEAK_TFLOPS if plan['mode'] == 'fp64' else FP32_PEAK_TFLOPS
+        roof = dict(kernel=dom, bound='mfma', achieved=achieved, peak=peak, unit='TFLOP/s',
+                    frac=achieved / peak, traffic=counter_traffic(dom, args.config), per_launch_flops=amount)
     elif dom in models:
         bound, amount, _ = models[dom]
         avg_s = kern[dom]['avg_us'] * 1e-6
@@ -358,7 +381,7 @@ def main():
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,
-        'dtype': 'c128' if plan['mode'] == 'fp64' else 'c64+f64',
+        'dtype': 'c128' if plan['mode'] == 'fp64' else ('c64+bf16+f64' if factor == 'bf16' else 'c64+f64'),
         'data': 'synthetic',
         'config': {'workload': cfg['name'] + ', %s, 1-level Chan-Olkin %s (%d blocks of %dx%d), GMRES(50) to 1e-6'
                    % (plan['mode'], plan['label'], info['stored_blocks'], info['block_m'], info['block_m']),
@@ -369,8 +392,11 @@ def main():
         'iterations': last['iters'], 'restarts': last['restarts'], 'relres': last['relres'],
         'matvec_gbps_algorithmic': mv_bytes / (mv_us * 1e-6) / 1e9 if mv_us else None,
         'matvec_us': mv_us,
-        'block_solve_gbps_algorithmic': models['block_solve'][1] / (bs['avg_us'] * 1e-6) / 1e9
-        if bs['avg_us'] else None,
+        'block_solve_rate_algorithmic': (models['block_solve'][1] / (bs['avg_us'] * 1e-6) /
+                                         (1e9 if models['block_solve'][0] == 'hbm' else 1e12)) if bs['avg_us'] else None,
+        'block_solve_rate_unit': 'GB/s' if models['block_solve'][0] == 'hbm' else 'TFLOP/s',
+        'latency_ms': latency,
+        'autotune': None if args.no_autotune else vie.autotune_report(),
         'kernels': kern,
         'roofline': roof,
         'kernel_sources': kernel_sources_digest(),

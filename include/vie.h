@@ -194,7 +194,8 @@ vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
  * vie_profile_kernel() synchronises the recorded events and returns, for one
  * kernel name, the summed duration in milliseconds and the number of
  * launches; vie_profile_end() stops recording.  Names: "generator",
- * "matvec_xfwd", "matvec_plane", "matvec_xinv", "precond_xfft", "block_solve",
+ * "matvec_xfwd", "matvec_plane", "matvec_xinv", "precond_xfft", "block_solve" (all block
+ * solves of an apply), "refine_residual" (the refinement residual and correcting solve),
  * "precond_ixfft", "lu_panel", "lu_swap_trsm", "lu_update", "lu_invert_diag",
  * "arnoldi_dots", "arnoldi_update".  Recording adds two event records per launch. */
 vie_status vie_profile_begin(void);
@@ -218,6 +219,12 @@ vie_status vie_footprint(vie_op op, const vie_pc_opts *pc, int32_t nrhs, const v
  * the high-water mark since the last reset (reset_peak != 0 first sets it to the current
  * value).  Either output may be NULL. */
 vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_t reset_peak);
+
+/* Device memory released by handles and calls is kept by the library for reuse (freeing and
+ * re-allocating tens of GB costs the driver up to seconds); vie_trim returns that cache to
+ * the driver.  The cache is also returned, and the allocation retried, whenever the device
+ * runs out of memory.  vie_device_bytes counts only memory held by handles and calls. */
+vie_status vie_trim(void);
 
 /* ---- autotuning ----------------------------------------------------------------
  * With autotuning on, the first precond_apply (and vie_solve) for a new problem shape and

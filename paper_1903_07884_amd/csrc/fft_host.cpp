@@ -1,6 +1,8 @@
+// FFT plans: radix factorisation and device twiddle tables; the device buffer type and its
+// cache of released blocks.
 #include <atomic>
-// FFT plans: radix factorisation and device twiddle tables.
 #include <cmath>
+#include <map>
 #include <mutex>
 
 #include "vie_internal.h"
@@ -101,6 +103,22 @@ FftCache::~FftCache() {
 // Device bytes held by the library's buffers, and their high-water mark.
 static std::atomic<uint64_t> g_dev_cur{0}, g_dev_peak{0};
 
+// Released buffers are kept for reuse instead of being returned to the driver: freeing and
+// re-allocating tens of GB (the Krylov bases of a batched solve) costs seconds in the driver
+// at times.  A request takes the smallest cached block of at least its size and at most twice
+// it; when the driver is out of memory the cache is returned and the allocation retried.
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void *> g_pool;  // size -> block
+size_t g_pool_bytes = 0;
+
+void pool_trim_locked() {
+    for (auto &kv : g_pool) (void)hipFree(kv.second);
+    g_pool.clear();
+    g_pool_bytes = 0;
+}
+}  // namespace
+
 extern "C" vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_t reset_peak) {
     if (reset_peak) g_dev_peak.store(g_dev_cur.load());
     if (current) *current = g_dev_cur.load();
@@ -108,20 +126,43 @@ extern "C" vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_
     return VIE_OK;
 }
 
+extern "C" vie_status vie_trim(void) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    VIE_HIP(hipDeviceSynchronize());
+    pool_trim_locked();
+    return VIE_OK;
+}
+
 vie_status DevBuf::ensure(size_t nbytes) {
     if (nbytes <= bytes && p) return VIE_OK;
     release();
     if (nbytes == 0) return VIE_OK;
-    hipError_t e = hipMalloc(&p, nbytes);
-    if (e != hipSuccess) {
-        p = nullptr;
-        bytes = 0;
-        vie_set_error("hipMalloc of " + std::to_string(nbytes) + " bytes failed: " +
-                      hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? VIE_EOOM : VIE_EDEVICE;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pool.lower_bound(nbytes);
+        if (it != g_pool.end() && it->first <= 2 * nbytes) {
+            p = it->second;
+            bytes = it->first;
+            g_pool_bytes -= it->first;
+            g_pool.erase(it);
+        }
     }
-    bytes = nbytes;
-    const uint64_t cur = g_dev_cur.fetch_add(nbytes) + nbytes;
+    if (!p) {
+        hipError_t e = hipMalloc(&p, nbytes);
+        if (e == hipErrorOutOfMemory) {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            pool_trim_locked();
+            e = hipMalloc(&p, nbytes);
+        }
+        if (e != hipSuccess) {
+            p = nullptr;
+            bytes = 0;
+            vie_set_error("hipMalloc of " + std::to_string(nbytes) + " bytes failed: " + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? VIE_EOOM : VIE_EDEVICE;
+        }
+        bytes = nbytes;
+    }
+    const uint64_t cur = g_dev_cur.fetch_add(bytes) + bytes;
     uint64_t pk = g_dev_peak.load();
     while (cur > pk && !g_dev_peak.compare_exchange_weak(pk, cur)) {
     }
@@ -130,7 +171,12 @@ vie_status DevBuf::ensure(size_t nbytes) {
 
 void DevBuf::release() {
     if (p) {
-        (void)hipFree(p);
+        // hipFree would wait for the device; so does the cache, before another call may
+        // receive this block (on any stream)
+        (void)hipDeviceSynchronize();
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        g_pool.emplace(bytes, p);
+        g_pool_bytes += bytes;
         g_dev_cur.fetch_sub(bytes);
     }
     p = nullptr;

@@ -24,7 +24,7 @@ MODE = {'fp64': 0, 'mixed': 1}
 EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
            'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
            'vie_profile_kernel', 'vie_profile_end', 'vie_last_error', 'vie_footprint', 'vie_autotune',
-           'vie_autotune_report', 'vie_device_bytes')
+           'vie_autotune_report', 'vie_device_bytes', 'vie_trim')
 
 
 class VieError(RuntimeError):
@@ -88,6 +88,7 @@ def load(path=None):
     lib.vie_profile_kernel.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
     lib.vie_profile_end.argtypes = []
     lib.vie_autotune.argtypes = [i32]
+    lib.vie_trim.argtypes = []
     lib.vie_device_bytes.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), i32]
     lib.vie_footprint.argtypes = [vp, ctypes.POINTER(PcOpts), i32, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(ctypes.c_uint64)]
@@ -267,6 +268,11 @@ def device_bytes(reset_peak=False):
     cur, pk = ctypes.c_uint64(), ctypes.c_uint64()
     _check(load().vie_device_bytes(ctypes.byref(cur), ctypes.byref(pk), 1 if reset_peak else 0))
     return int(cur.value), int(pk.value)
+
+
+def trim():
+    """Return the library's cache of released device memory to the driver (vie_trim)."""
+    _check(load().vie_trim())
 
 
 def autotune(enable=True):
