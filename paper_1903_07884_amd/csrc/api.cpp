@@ -278,8 +278,9 @@ extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t n
         if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
         const uint64_t rs = (uint64_t)so->restart;
         const bool mixed = so->mode == VIE_MODE_MIXED;
-        solve_bytes = 16 * R * n3 * (rs + 1) + (mixed ? 8 : 16) * R * n3 * rs + 2 * 16 * R * n3 +
-                      16 * R * 256 * (rs + 2) + (mixed ? 2 * 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
+        const uint64_t vb = mixed ? 8 : 16;  // basis precision
+        solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * 256 * (rs + 2) +
+                      (mixed ? 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
         (void)mixed_pc;
     }
     *bytes = b + mv_scratch + pc_bytes + apply_scratch + solve_bytes;

@@ -44,9 +44,15 @@ __device__ __forceinline__ c128 block_sum_kr(c128 v, c128 *sh) {
     return r;  // valid in thread 0
 }
 
-// Batched vectors: vector j of right-hand side r at base + j * ldj + r * n.
+// Widen a stored basis entry (complex128, or complex64 in the mixed mode) to FP64.
+__device__ __forceinline__ c128 wide(c128 a) { return a; }
+__device__ __forceinline__ c128 wide(c64 a) { return mk((double)a.re, (double)a.im); }
+
+// Batched vectors: vector j of right-hand side r at base + j * ldj + r * n.  The basis V is
+// complex128, or complex64 in the mixed mode; sums are accumulated in FP64.
 // partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e]; `self` adds |w|^2.
-__global__ void __launch_bounds__(KR_THREADS) k_dots(const c128 *V, long long ldj, int nv, const c128 *w, long long n,
+template <class VT>
+__global__ void __launch_bounds__(KR_THREADS) k_dots(const VT *V, long long ldj, int nv, const c128 *w, long long n,
                                                      int self, c128 *partial) {
     __shared__ c128 sh[KR_THREADS / 64];
     const int r = blockIdx.y;
@@ -56,9 +62,9 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots(const c128 *V, long long ld
     int stride = nv + self;
     c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
     for (int i = 0; i < nv; ++i) {
-        const c128 *v = V + i * ldj + r * n;
+        const VT *v = V + i * ldj + r * n;
         c128 acc = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc = acc + cmulc(v[e], wr[e]);
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc = acc + cmulc(wide(v[e]), wr[e]);
         c128 s = block_sum_kr(acc, sh);
         if (threadIdx.x == 0) out[i] = s;
     }
@@ -82,7 +88,8 @@ __global__ void __launch_bounds__(KR_THREADS) k_reduce(const c128 *partial, int 
 }
 
 // w_r -= sum_i V_i,r h_r[i]; optional partial |w_r|^2 into partial[r * gridDim.x + blk].
-__global__ void __launch_bounds__(KR_THREADS) k_update(const c128 *V, long long ldj, int nv, const c128 *h, int hstride,
+template <class VT>
+__global__ void __launch_bounds__(KR_THREADS) k_update(const VT *V, long long ldj, int nv, const c128 *h, int hstride,
                                                        c128 *w, long long n, c128 *partial) {
     __shared__ c128 hs[256];
     __shared__ c128 sh[KR_THREADS / 64];
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_update(const c128 *V, long long 
     c128 nrm = czero<double>();
     for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
         c128 acc = wr[e];
-        for (int i = 0; i < nv; ++i) acc = cfms(acc, V[i * ldj + r * n + e], hs[i]);
+        for (int i = 0; i < nv; ++i) acc = cfms(acc, wide(V[i * ldj + r * n + e]), hs[i]);
         wr[e] = acc;
         nrm.re += abs2(acc);
     }
@@ -125,25 +132,23 @@ __global__ void __launch_bounds__(KR_THREADS) k_combine(const cpx<R> *Z, long lo
     }
 }
 
-// v_r = w_r / scal[r * sstride]  (zero for an inactive right-hand side or a zero scale)
-__global__ void k_scale(const c128 *w, c128 *v, long long n, const double *scal, int sstride, const int *active) {
+// v_r = w_r / scal[r * sstride]  (zero for an inactive right-hand side or a zero scale),
+// stored in the basis precision
+template <class VT>
+__global__ void k_scale(const c128 *w, VT *v, long long n, const double *scal, int sstride, const int *active) {
+    typedef decltype(v->re) T;
     const int r = blockIdx.y;
     double s = scal[(long long)r * sstride];
     double f = (active[r] && s != 0.0) ? 1.0 / s : 0.0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         c128 a = w[r * n + e];
-        v[r * n + e] = mk(a.re * f, a.im * f);
+        v[r * n + e] = mk((T)(a.re * f), (T)(a.im * f));
     }
 }
 
 __global__ void k_residual(const c128 *b, c128 *r, long long n) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
         r[e] = b[e] - r[e];
-}
-
-__global__ void k_narrow(const c128 *a, c64 *b, long long n) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-        b[e] = mk((float)a[e].re, (float)a[e].im);
 }
 
 __global__ void k_widen(const c64 *a, c128 *b, long long n) {
@@ -257,10 +262,56 @@ struct Ctx {
 
 // batched norms: out[r].re = |w_r|^2
 vie_status norms(Ctx &C, const c128 *w, c128 *out) {
-    hipLaunchKernelGGL(k_dots, dim3(KR_BLOCKS, C.R), dim3(KR_THREADS), 0, C.s, (const c128 *)nullptr, 0LL, 0, w, C.n, 1,
-                       C.partial);
+    hipLaunchKernelGGL(k_dots<c128>, dim3(KR_BLOCKS, C.R), dim3(KR_THREADS), 0, C.s, (const c128 *)nullptr, 0LL, 0, w,
+                       C.n, 1, C.partial);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(1, C.R), dim3(KR_THREADS), 0, C.s, C.partial, KR_BLOCKS, 1, out, 1);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
+// Classical Gram-Schmidt twice against v_0..v_j, the Givens update of column j and
+// v_{j+1} = w / h_{j+1,j} (Sec. 1: GMRES; the orthogonalisation is this build's choice).
+template <class VT>
+vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState &S, int m, dim3 grid_b, dim3 grid_e,
+                     VT *vnext) {
+    hipStream_t s = C.s;
+    const long long n = C.n;
+    const int R = C.R;
+    {
+        ProfScope ps("arnoldi_dots", s);
+        hipLaunchKernelGGL(k_dots<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 1, C.partial);
+        VIE_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, j + 2,
+                       S.h1, m + 2);
+    VIE_HIP(hipGetLastError());
+    {
+        ProfScope ps("arnoldi_update", s);
+        hipLaunchKernelGGL(k_update<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h1, m + 2, w, n,
+                           (c128 *)nullptr);
+        VIE_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps("arnoldi_dots", s);
+        hipLaunchKernelGGL(k_dots<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 0, C.partial);
+        VIE_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, j + 1,
+                       S.h2, m + 2);
+    VIE_HIP(hipGetLastError());
+    {
+        ProfScope ps("arnoldi_update", s);
+        hipLaunchKernelGGL(k_update<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h2, m + 2, w, n,
+                           C.partial);
+        VIE_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, 1, S.nrm2, 1);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_givens, dim3((R + 63) / 64), dim3(64), 0, s, S, j, R);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scale<VT>, grid_e, dim3(256), 0, s, (const c128 *)w, vnext, n, (const double *)(S.st + 1), 4,
+                       (const int *)S.active);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
@@ -288,17 +339,15 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     const long long n = 3LL * op->N;
     const long long Rn = (long long)R * n;
     Ctx C{op, s, n, R, nullptr, nullptr};
+    // mixed mode: basis V and flexible basis Z in complex64, FP64 sums and w
     const size_t zsz = mixed ? sizeof(c64) : sizeof(c128);
-    DevBuf Vb, Zb, wb, rb, part, small, t32, w32;
-    VIE_CHECK(Vb.ensure(sizeof(c128) * Rn * (m + 1)));
+    DevBuf Vb, Zb, wb, rb, part, small, w32;
+    VIE_CHECK(Vb.ensure(zsz * Rn * (m + 1)));
     VIE_CHECK(Zb.ensure(zsz * Rn * m));
     VIE_CHECK(wb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * KR_BLOCKS * (m + 2)));
-    if (mixed) {
-        VIE_CHECK(t32.ensure(sizeof(c64) * Rn));
-        VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
-    }
+    if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
     size_t nc = (size_t)R * ((size_t)(m + 2) * 2 + 1 + (size_t)m * (m + 1) + m + (m + 1) + m);
     size_t nd = (size_t)R * (m + 4 + 1);
     VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * 2 * R));
@@ -340,7 +389,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     C.host = host;
     int *hact = reinterpret_cast<int *>(host + 4 * (size_t)R);
     int *hjr = hact + R;
-    c128 *V = Vb.as<c128>(), *w = wb.as<c128>(), *r = rb.as<c128>();
+    c128 *w = wb.as<c128>(), *r = rb.as<c128>();
     const long long ldj = Rn;  // stride between Arnoldi vectors
     dim3 grid_b(KR_BLOCKS, R), grid_e(1024, R);
 
@@ -394,15 +443,19 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         }
         VIE_HIP(hipMemcpyAsync(beta_dev, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
         VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_scale, grid_e, dim3(256), 0, s, (const c128 *)r, V, n, (const double *)beta_dev, 1,
-                           (const int *)S.active);
+        if (mixed)
+            hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(), n,
+                               (const double *)beta_dev, 1, (const int *)S.active);
+        else
+            hipLaunchKernelGGL(k_scale<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(), n,
+                               (const double *)beta_dev, 1, (const int *)S.active);
         VIE_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_setg, dim3((unsigned)(((m + 1) * R + 63) / 64)), dim3(64), 0, s, S.g, m + 1,
                            (const double *)beta_dev, R);
         VIE_HIP(hipGetLastError());
         int j = 0;
         while (j < m && nact > 0) {
-            c128 *vj = V + j * ldj;
+            void *vj = (char *)Vb.p + zsz * Rn * j;
             void *zj = (char *)Zb.p + zsz * Rn * j;
             if (!mixed) {
                 if (pc)
@@ -411,54 +464,19 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                     VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
                 VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
             } else {
-                hipLaunchKernelGGL(k_narrow, dim3(1024), dim3(256), 0, s, (const c128 *)vj, t32.as<c64>(), Rn);
-                VIE_HIP(hipGetLastError());
                 if (pc)
-                    VIE_CHECK(pc_apply(pc, t32.p, zj, R, VIE_C64, s));
+                    VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C64, s));
                 else
-                    VIE_HIP(hipMemcpyAsync(zj, t32.p, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
+                    VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
                 VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
                 hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
                 VIE_HIP(hipGetLastError());
             }
-            {
-                ProfScope ps("arnoldi_dots", s);
-                hipLaunchKernelGGL(k_dots, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1, (const c128 *)w, n,
-                                   1, C.partial);
-                VIE_HIP(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS,
-                               j + 2, S.h1, m + 2);
-            VIE_HIP(hipGetLastError());
-            {
-                ProfScope ps("arnoldi_update", s);
-                hipLaunchKernelGGL(k_update, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1,
-                                   (const c128 *)S.h1, m + 2, w, n, (c128 *)nullptr);
-                VIE_HIP(hipGetLastError());
-            }
-            {
-                ProfScope ps("arnoldi_dots", s);
-                hipLaunchKernelGGL(k_dots, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1, (const c128 *)w, n,
-                                   0, C.partial);
-                VIE_HIP(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS,
-                               j + 1, S.h2, m + 2);
-            VIE_HIP(hipGetLastError());
-            {
-                ProfScope ps("arnoldi_update", s);
-                hipLaunchKernelGGL(k_update, grid_b, dim3(KR_THREADS), 0, s, (const c128 *)V, ldj, j + 1,
-                                   (const c128 *)S.h2, m + 2, w, n, C.partial);
-                VIE_HIP(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, 1,
-                               S.nrm2, 1);
-            VIE_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_givens, dim3((R + 63) / 64), dim3(64), 0, s, S, j, R);
-            VIE_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_scale, grid_e, dim3(256), 0, s, (const c128 *)w, V + (j + 1) * ldj, n,
-                               (const double *)(S.st + 1), 4, (const int *)S.active);
-            VIE_HIP(hipGetLastError());
+            if (mixed)
+                VIE_CHECK(cgs2_step<c64>(C, Vb.as<const c64>(), ldj, j, w, S, m, grid_b, grid_e, Vb.as<c64>() + (j + 1) * ldj));
+            else
+                VIE_CHECK(cgs2_step<c128>(C, Vb.as<const c128>(), ldj, j, w, S, m, grid_b, grid_e,
+                                          Vb.as<c128>() + (j + 1) * ldj));
             VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
             ++j;
             bool changed = false;
