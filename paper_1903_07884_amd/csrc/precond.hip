@@ -480,62 +480,95 @@ __global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *ipiv
     }
 }
 
-// A[r, c] -= sum_{k in [k0, k0 + K)} A[r, k] A[k, c] for r in [r0, r1), c in [c0, c1):
-// 64x64 output tiles, K consumed in chunks of 32 staged in LDS, 4x4 complex outputs per thread.
+// A[r, c] -= sum_{k in [k0, k0 + K)} A[r, k] A[k, c] for r in [r0, r1), c in [c0, c1): one
+// 64x64 output tile per workgroup, K staged in LDS in chunks of LU_NB, products on the matrix
+// cores.  Complex products as real ones: a K-step takes two complex columns of L as four
+// real ones (lane l: row l%16, real index l/16 = 2 x complex column + part); with U fed as
+// interleaved (Re, Im), the left operand (Re l, -Im l) accumulates Re(l u) and (Im l, Re l)
+// accumulates Im(l u).  Each of the 4 wavefronts owns a 32x32 quarter (2x2 tiles of 16x16).
+template <class R>
+struct LuMfma;
+template <>
+struct LuMfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 fma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator register v of lane l holds row 4 v + l/16 (FP64) / 4 (l/16) + v (FP32)
+    static __device__ __forceinline__ int acc_row(int q, int v) { return 4 * v + q; }
+};
+template <>
+struct LuMfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 fma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int acc_row(int q, int v) { return 4 * q + v; }
+};
+
 template <class R>
 __global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int r0, int r1, int c0, int c1, int k0, int K) {
-    __shared__ cpx<R> Ls[LU_NB][LU_TILE];
-    __shared__ cpx<R> Us[LU_NB][LU_TILE];
+    typedef typename LuMfma<R>::v4 v4;
+    __shared__ cpx<R> Ls[LU_NB][LU_TILE];  // [k][row]
+    __shared__ cpx<R> Us[LU_NB][LU_TILE];  // [k][col]
     const int nt = (r1 - r0 + LU_TILE - 1) / LU_TILE;
     const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
     const int rr0 = r0 + ti * LU_TILE, cc0 = c0 + tj * LU_TILE;
     cpx<R> *a = A + (long long)blockIdx.y * m * m;
-    const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
-    cpx<R> acc[4][4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    const int wrow = 32 * (wv & 1), wcol = 32 * (wv >> 1);
+    v4 cr[2][2], ci[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = czero<R>();
+        for (int j = 0; j < 2; ++j) {
+            cr[i][j] = v4{0, 0, 0, 0};
+            ci[i][j] = v4{0, 0, 0, 0};
+        }
     for (int kc = 0; kc < K; kc += LU_NB) {
         const int kw = min(LU_NB, K - kc);
         __syncthreads();
-        for (int e = threadIdx.x; e < LU_NB * LU_TILE; e += 256) {
-            int k = e / LU_TILE, i = e % LU_TILE;
-            cpx<R> lv = czero<R>(), uv = czero<R>();
-            if (k < kw) {
-                if (rr0 + i < r1) lv = a[(long long)(k0 + kc + k) * m + rr0 + i];
-                if (cc0 + i < c1) uv = a[(long long)(cc0 + i) * m + k0 + kc + k];
-            }
-            Ls[k][i] = lv;
-            Us[k][i] = uv;
+        for (int e = tid; e < LU_NB * LU_TILE; e += 256) {
+            const int kl = e / LU_TILE, i = e % LU_TILE;  // L: rows contiguous
+            Ls[kl][i] = (kl < kw && rr0 + i < r1) ? a[(long long)(k0 + kc + kl) * m + rr0 + i] : czero<R>();
+            const int ku = e % LU_NB, j = e / LU_NB;      // U: k contiguous within a column
+            Us[ku][j] = (ku < kw && cc0 + j < c1) ? a[(long long)(cc0 + j) * m + k0 + kc + ku] : czero<R>();
         }
         __syncthreads();
-        for (int k = 0; k < kw; ++k) {
-            cpx<R> lv[4], uv[4];
+        for (int ks = 0; ks < (kw + 1) / 2; ++ks) {
+            const int k = 2 * ks + kh;  // < LU_NB (zero-padded past kw)
+            R ar[2], ai[2], bv[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) lv[i] = Ls[k][tr + 16 * i];
+            for (int i = 0; i < 2; ++i) {
+                const cpx<R> l = Ls[k][wrow + 16 * i + r];
+                ar[i] = p ? -l.im : l.re;
+                ai[i] = p ? l.re : l.im;
+                const cpx<R> u = Us[k][wcol + 16 * i + r];
+                bv[i] = p ? u.im : u.re;
+            }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) uv[j] = Us[k][tc + 16 * j];
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].re += lv[i].re * uv[j].re - lv[i].im * uv[j].im;
-                    acc[i][j].im += lv[i].re * uv[j].im + lv[i].im * uv[j].re;
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = LuMfma<R>::fma(ar[i], bv[j], cr[i][j]);
+                    ci[i][j] = LuMfma<R>::fma(ai[i], bv[j], ci[i][j]);
                 }
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        int c = cc0 + tc + 16 * j;
+    for (int j = 0; j < 2; ++j) {
+        const int c = cc0 + wcol + 16 * j + r;
         if (c >= c1) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int r = rr0 + tr + 16 * i;
-            if (r >= r1) continue;
-            cpx<R> &x = a[(long long)c * m + r];
-            x = x - acc[i][j];
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rr0 + wrow + 16 * i + LuMfma<R>::acc_row(q, v);
+                if (row >= r1) continue;
+                cpx<R> &x = a[(long long)c * m + row];
+                x = x - mk(cr[i][j][v], ci[i][j][v]);
+            }
     }
 }
 
