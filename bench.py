@@ -208,6 +208,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--config', type=int, default=2)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-compare', action='store_true',
+                    help='skip the comparison solves (FP64 / reduced / other factor precisions)')
     ap.add_argument('--no-autotune', action='store_true',
                     help='default launch parameters (otherwise the warm-up step autotunes them)')
     ap.add_argument('--copy-probe', type=int, default=0,
@@ -248,8 +250,10 @@ def main():
         ev[0].record(stream)
         op = vie.Operator(grid, delta, kb, chi_d, build_c64=(mode == 'mixed'))
         ev[1].record(stream)
+        print('bench: operator built', file=sys.stderr, flush=True)
         pc = vie.Preconditioner(op, homog=plan['homog'], boxes=bxs, reduce_tol=rt, factor_prec=fp, proxy=proxy)
         ev[2].record(stream)
+        print('bench: preconditioner set up (%s factors)' % factor, file=sys.stderr, flush=True)
         op.rhs(e_d, b_d, nrhs=R)
         st = vie.solve(op, pc, b_d, x_d, nrhs=R, tol=1e-6, restart=50, mode=mode)
         ev[3].record(stream)
@@ -302,7 +306,9 @@ def main():
     latency = dict(p50=float(np.percentile(per_step, 50)), p99=float(np.percentile(per_step, 99)),
                    samples=len(per_step), what='create + setup + solve per step, HIP events')
     compare = {}
-    if plan['mode'] == 'fp64':
+    if args.no_compare:
+        pass
+    elif plan['mode'] == 'fp64':
         # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column
         for label, kw in (('reduced_1e-3', dict(reduce_tol=1e-3)),
                           ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre'))):
@@ -315,7 +321,7 @@ def main():
             compare[label] = dict(ms=1000.0 * (tb - ta), iterations=rr[0]['iters'], relres=rr[0]['relres'],
                                   breakdown_ms={k: rr[0][k] for k in ('create_ms', 'setup_ms', 'solve_ms')},
                                   stored_blocks=rr[0]['info']['stored_blocks'])
-    if plan['mode'] == 'mixed':
+    if plan['mode'] == 'mixed' and not args.no_compare:
         # the same problem solved in plain FP64 (and, for the coupler, with the memory-reduced
         # preconditioner), timed the same way, outside the main timed region
         extra = ()
