@@ -253,25 +253,26 @@ __global__ void __launch_bounds__(256) k_lu_panel(cpx<R> *A, int *ipiv, int *inf
     }
 }
 
-// Register-resident panel (1024 threads): thread t holds column t >> 5 of the panel for the
-// local rows (t & 31) + 32 q, q < QS.  Per column: pivot search by the 32 lanes that hold it
-// (half-wavefront shuffles), row interchange through LDS, multipliers published to LDS, and
-// the rank-1 update of the remaining panel columns in registers.  No global traffic between
-// the panel load and the panel store.
-template <class R, int QS>
-__global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
+// Register-resident panel (32 G threads, G = 32 or 16 row lanes per column): thread t holds
+// column t / G of the panel for the local rows (t % G) + G q, q < QS.  Per column: pivot
+// search by the G lanes that hold it (shuffles within the lane group), row interchange through
+// LDS, multipliers published to LDS, and the rank-1 update of the remaining panel columns in
+// registers.  No global traffic between the panel load and the panel store.  G = 16 halves
+// the workgroup so that two blocks share a CU.
+template <class R, int QS, int G>
+__global__ void __launch_bounds__(32 * G) k_lu_panel_reg(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
     cpx<R> *lcol = reinterpret_cast<cpx<R> *>(vie_smem);  // [m - j0] multipliers of the current column
     __shared__ cpx<R> rj[LU_NB], rp[LU_NB];
     __shared__ int sp;
     __shared__ R spv;
-    const int t = threadIdx.x, c = t >> 5, g = t & 31;
+    const int t = threadIdx.x, c = t / G, g = t % G;
     const int mrem = m - j0;
     cpx<R> *a = A + (long long)blockIdx.x * m * m;
     int *piv = ipiv + (long long)blockIdx.x * m;
     cpx<R> v[QS];
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-        int li = g + 32 * q;
+        int li = g + G * q;
         v[q] = (c < w && li < mrem) ? a[(long long)(j0 + c) * m + j0 + li] : czero<R>();
     }
     for (int jj = 0; jj < w; ++jj) {
@@ -280,14 +281,14 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int
             int bi = jj;
 #pragma unroll
             for (int q = 0; q < QS; ++q) {
-                int li = g + 32 * q;
+                int li = g + G * q;
                 R val = cabs2(v[q]);
                 if (li >= jj && li < mrem && val > best) {
                     best = val;
                     bi = li;
                 }
             }
-            for (int off = 16; off > 0; off >>= 1) {
+            for (int off = G / 2; off > 0; off >>= 1) {
                 R ov = __shfl_xor(best, off);
                 int oi = __shfl_xor(bi, off);
                 if (ov > best || (ov == best && oi < bi)) {
@@ -314,14 +315,14 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int
         // row interchange jj <-> p within the panel
 #pragma unroll
         for (int q = 0; q < QS; ++q) {
-            int li = g + 32 * q;
+            int li = g + G * q;
             if (c < w && li == jj) rj[c] = v[q];
             if (c < w && li == p) rp[c] = v[q];
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < QS; ++q) {
-            int li = g + 32 * q;
+            int li = g + G * q;
             if (c < w && li == jj) v[q] = rp[c];
             else if (c < w && li == p) v[q] = rj[c];
         }
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int
         if (c == jj)
 #pragma unroll
             for (int q = 0; q < QS; ++q) {
-                int li = g + 32 * q;
+                int li = g + G * q;
                 if (li > jj && li < mrem) {
                     v[q] = v[q] * inv;
                     lcol[li] = v[q];
@@ -343,7 +344,7 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int
             cpx<R> u = rp[c];
 #pragma unroll
             for (int q = 0; q < QS; ++q) {
-                int li = g + 32 * q;
+                int li = g + G * q;
                 if (li > jj && li < mrem) v[q] = cfms(v[q], lcol[li], u);
             }
         }
@@ -352,7 +353,7 @@ __global__ void __launch_bounds__(1024) k_lu_panel_reg(cpx<R> *A, int *ipiv, int
     }
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-        int li = g + 32 * q;
+        int li = g + G * q;
         if (c < w && li < mrem) a[(long long)(j0 + c) * m + j0 + li] = v[q];
     }
 }
@@ -509,8 +510,9 @@ struct LuMfma<float> {
 template <class R>
 __global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int r0, int r1, int c0, int c1, int k0, int K) {
     typedef typename LuMfma<R>::v4 v4;
-    __shared__ cpx<R> Ls[LU_NB][LU_TILE];  // [k][row]
-    __shared__ cpx<R> Us[LU_NB][LU_TILE];  // [k][col]
+    constexpr int KCH = sizeof(R) == 8 ? 16 : 32;  // K chunk: 32 KB of LDS either way (4 workgroups per CU)
+    __shared__ cpx<R> Ls[KCH][LU_TILE];  // [k][row]
+    __shared__ cpx<R> Us[KCH][LU_TILE];  // [k][col]
     const int nt = (r1 - r0 + LU_TILE - 1) / LU_TILE;
     const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
     const int rr0 = r0 + ti * LU_TILE, cc0 = c0 + tj * LU_TILE;
@@ -518,32 +520,39 @@ __global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int r0, int
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     const int wrow = 32 * (wv & 1), wcol = 32 * (wv >> 1);
+    // accumulators start from the output tile (loaded first, in flight during the staging)
     v4 cr[2][2], ci[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+        const int c = cc0 + wcol + 16 * j + r;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            cr[i][j] = v4{0, 0, 0, 0};
-            ci[i][j] = v4{0, 0, 0, 0};
-        }
-    for (int kc = 0; kc < K; kc += LU_NB) {
-        const int kw = min(LU_NB, K - kc);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rr0 + wrow + 16 * i + LuMfma<R>::acc_row(q, v);
+                const cpx<R> x = (row < r1 && c < c1) ? a[(long long)c * m + row] : czero<R>();
+                cr[i][j][v] = x.re;
+                ci[i][j][v] = x.im;
+            }
+    }
+    for (int kc = 0; kc < K; kc += KCH) {
+        const int kw = min(KCH, K - kc);
         __syncthreads();
-        for (int e = tid; e < LU_NB * LU_TILE; e += 256) {
+        for (int e = tid; e < KCH * LU_TILE; e += 256) {
             const int kl = e / LU_TILE, i = e % LU_TILE;  // L: rows contiguous
             Ls[kl][i] = (kl < kw && rr0 + i < r1) ? a[(long long)(k0 + kc + kl) * m + rr0 + i] : czero<R>();
-            const int ku = e % LU_NB, j = e / LU_NB;      // U: k contiguous within a column
+            const int ku = e % KCH, j = e / KCH;          // U: k contiguous within a column
             Us[ku][j] = (ku < kw && cc0 + j < c1) ? a[(long long)(cc0 + j) * m + k0 + kc + ku] : czero<R>();
         }
         __syncthreads();
         for (int ks = 0; ks < (kw + 1) / 2; ++ks) {
-            const int k = 2 * ks + kh;  // < LU_NB (zero-padded past kw)
+            const int k = 2 * ks + kh;  // < KCH (zero-padded past kw)
             R ar[2], ai[2], bv[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const cpx<R> l = Ls[k][wrow + 16 * i + r];
-                ar[i] = p ? -l.im : l.re;
-                ai[i] = p ? l.re : l.im;
+                ar[i] = p ? l.im : -l.re;   // negated: the accumulators subtract
+                ai[i] = p ? -l.re : -l.im;
                 const cpx<R> u = Us[k][wcol + 16 * i + r];
                 bv[i] = p ? u.im : u.re;
             }
@@ -565,9 +574,7 @@ __global__ void __launch_bounds__(256) k_lu_update(cpx<R> *A, int m, int r0, int
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = rr0 + wrow + 16 * i + LuMfma<R>::acc_row(q, v);
-                if (row >= r1) continue;
-                cpx<R> &x = a[(long long)c * m + row];
-                x = x - mk(cr[i][j][v], ci[i][j][v]);
+                if (row < r1) a[(long long)c * m + row] = mk(cr[i][j][v], ci[i][j][v]);
             }
     }
 }
@@ -652,13 +659,21 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
     auto panel = [&](int j0, int w) -> vie_status {
         ProfScope ps("lu_panel", s);
-        int qs = (m - j0 + 31) / 32;
+        // 16 row lanes (512 threads) when the panel takes <= 32 value VGPRs per thread that
+        // way (two blocks per CU), else 32 (1024 threads, one block per CU)
+        const int q16 = (m - j0 + 15) / 16;
+        const bool half = q16 * sizeof(cpx<R>) / 4 <= 32;
+        int qs = half ? q16 : (m - j0 + 31) / 32;
         size_t lds = sizeof(cpx<R>) * (size_t)(m - j0);
         bool regs = qs * sizeof(cpx<R>) / 4 <= 96;  // accumulator VGPRs per thread
-#define PANEL_CASE(QV)                                                                                   \
-    if (qs <= QV) {                                                                                      \
-        hipLaunchKernelGGL((k_lu_panel_reg<R, QV>), dim3(nb), dim3(1024), lds, s, A, ipiv.as<int>(),     \
-                           pc->info.as<int>(), m, j0, w);                                               \
+#define PANEL_CASE(QV)                                                                                     \
+    if (qs <= QV) {                                                                                        \
+        if (half)                                                                                          \
+            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 16>), dim3(nb), dim3(512), lds, s, A, ipiv.as<int>(), \
+                               pc->info.as<int>(), m, j0, w);                                             \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 32>), dim3(nb), dim3(1024), lds, s, A, ipiv.as<int>(),\
+                               pc->info.as<int>(), m, j0, w);                                             \
     } else
         if (regs) {
             PANEL_CASE(2) PANEL_CASE(4) PANEL_CASE(8) PANEL_CASE(12) PANEL_CASE(16) PANEL_CASE(24)
