@@ -224,68 +224,158 @@ struct Mfma<double> {
 // (masks are applied to the loaded values), and two register sets alternate, so the waits
 // only cover the older batch.
 
-// acc (16 rows of this wavefront x CT*16 columns) -= A[rows, kb:ke] * Y[kb:ke, :], both
-// operands from global memory (the factor strip from HBM, the solved rows Y from the caches).
-// A is column-major with leading dimension m: arow points at this wavefront's first row,
-// abase at row 0 of the block (used for rows past m, whose results are discarded).  Y is
-// row-major [m][CT*16].  The K-steps run in the rotated order rot, rot+1, ..., nks-1, 0, ...
-// so that workgroups sharing one factor (the memory-reduced central block) read different
-// parts of it at a time.
-template <class R, int CT, class FT>
-__device__ __forceinline__ void wide_gemm_global(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci,
-                                                 const FT *arow, const FT *abase, long long m, bool rv,
-                                                 const cpx<R> *Y, int kb, int ke, int rot) {
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// ---- shared right operand: the off-diagonal products of one super-tile multiply every
+// wavefront's own factor rows with the same solved rows Y[kb:ke], so those rows go through LDS
+// once per workgroup, in chunks, double-buffered: the next chunk's rows and factor entries are
+// loaded while the current chunk is multiplied, one barrier per chunk.  Every wavefront of the
+// workgroup must call these (active = false: it only helps stage).  Chunks run in rotated order
+// (rot) so that workgroups sharing one factor read different parts of it at a time.
+
+// FP32 / FP64 solved rows, row-major [m][CT*16] complex; YC rows per chunk.
+template <class R, int CT, int NTH, class FT>
+__device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, bool active,
+                                                  const FT *arow, const FT *abase, long long m, bool rv,
+                                                  const cpx<R> *Y, int kb, int ke, int rot, cpx<R> *buf) {
+    constexpr int WC = CT * 16;
+    constexpr int YC = sizeof(R) == 8 ? 8 : 16;       // rows per chunk
+    constexpr int SPT = (YC * WC + NTH - 1) / NTH;    // staged complex per thread
+    constexpr int KS = YC / 2;                        // K-steps per chunk
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
-    constexpr int WC = CT * 16;
-    constexpr int KC = 2;
-    const R *yf = reinterpret_cast<const R *>(Y) + p;
     const FT *ap = rv ? arow + r : abase;
-    const int nks = (ke - kb + 1) / 2;
-    rot = rot % nks;
-    cpx<R> a0[KC], a1[KC];
-    R b0[KC][CT], b1[KC][CT];
-    bool m0[KC], m1[KC];
-    auto load = [&](int ks0, cpx<R> *a, R (*bb)[CT], bool *msk) {
+    const int nch = (ke - kb + YC - 1) / YC;
+    rot = rot % nch;
+    cpx<R> st[SPT], a0[KS], a1[KS];
+    auto row0 = [&](int c) { int cc = c + rot; if (cc >= nch) cc -= nch; return kb + YC * cc; };
+    auto load = [&](int c, cpx<R> *a) {
+        const int k0 = row0(c);
 #pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            int ks = ks0 + u + rot;
-            if (ks >= nks) ks -= nks;
-            const int kc = kb + 2 * ks + kh;
-            const bool in = kc < ke && ks0 + u < nks;
-            const int kcl = in ? kc : kb;
-            msk[u] = in;
-            a[u] = ldf(ap + (long long)kcl * m);
+        for (int u = 0; u < SPT; ++u) {
+            const int e = threadIdx.x + u * NTH, row = k0 + e / WC;
+            st[u] = (e < YC * WC && row < ke) ? Y[(long long)row * WC + e % WC] : czero<R>();
+        }
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) bb[u][ct] = yf[((long long)kcl * WC + ct * 16 + r) * 2];
+        for (int u = 0; u < KS; ++u) {
+            const int kc = k0 + 2 * u + kh;
+            a[u] = ldf(ap + (long long)(kc < ke ? kc : kb) * m);  // past ke: multiplied by zero rows
         }
     };
-    auto compute = [&](const cpx<R> *a, R (*bb)[CT], const bool *msk) {
+    auto stage = [&](int slot) {
+        cpx<R> *b = buf + slot * YC * WC;
 #pragma unroll
-        for (int u = 0; u < KC; ++u) {
+        for (int u = 0; u < SPT; ++u) {
+            const int e = threadIdx.x + u * NTH;
+            if (e < YC * WC) b[e] = st[u];
+        }
+    };
+    auto compute = [&](int slot, const cpx<R> *a) {
+        const R *xs = reinterpret_cast<const R *>(buf + slot * YC * WC) + p;
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
             const R ar = p ? a[u].im : -a[u].re;   // negated (Re a, -Im a)
             const R ai = p ? -a[u].re : -a[u].im;  // negated (Im a, Re a)
+            const R *xr = xs + (2 * u + kh) * WC * 2;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const R bv = msk[u] ? bb[u][ct] : R(0);
+                const R bv = xr[(ct * 16 + r) * 2];
                 cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
                 ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
             }
         }
     };
-    // sched_barrier(0): the scheduler may not move instructions across it, which keeps each
-    // batch's loads one compute phase ahead of their use
-    load(0, a0, b0, m0);
-    for (int ks0 = 0; ks0 < nks; ks0 += 2 * KC) {
-        load(ks0 + KC, a1, b1, m1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(a0, b0, m0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (ks0 + KC >= nks) break;
-        load(ks0 + 2 * KC, a0, b0, m0);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(a1, b1, m1);
-        __builtin_amdgcn_sched_barrier(0);
+    load(0, a0);
+    stage(0);
+    for (int c = 0; c < nch; c += 2) {
+        if (c + 1 < nch) load(c + 1, a1);
+        __syncthreads();
+        if (active) compute(0, a0);
+        if (c + 1 >= nch) break;
+        stage(1);
+        if (c + 2 < nch) load(c + 2, a0);
+        __syncthreads();
+        if (active) compute(1, a1);
+        if (c + 2 < nch) stage(0);
+    }
+}
+
+// bfloat16 factors: solved rows split into bfloat16 hi + lo, [col][mp] per item (rows past m
+// zero); one chunk = one 16-complex K-step on v_mfma_f32_16x16x32_bf16, whose lane l supplies
+// row l%16 and reals 8 (l/16) .. +7: the four complex entries 4 (l/16) .. +3 as (re, im) pairs,
+// i.e. exactly four packed factor words.  -(Re a, -Im a) is the word with the low sign bit
+// flipped, -(Im a, Re a) the word with its halves swapped and both sign bits flipped.  The
+// accumulator layout is that of the FP32 16x16x4 instruction.  kb is a multiple of 16; columns
+// past ke meet zero rows of Y (ke < m is a multiple of 16; at ke = m the padding rows are zero).
+template <int CT, int NTH>
+__device__ __forceinline__ void wide_gemm_chunked_bf16(Mfma<float>::v4 *cr, Mfma<float>::v4 *ci, bool active,
+                                                       const bf16c *arow, const bf16c *abase, long long m, bool rv,
+                                                       const uint32_t *Yh, const uint32_t *Yl, int mp, int kb, int ke,
+                                                       int rot, uint32_t *buf) {
+    constexpr int WC = CT * 16;
+    constexpr int NV = 2 * WC * 4;                   // uint4 loads per chunk (hi and lo, 4 per column)
+    constexpr int SPT = (NV + NTH - 1) / NTH;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const uint32_t *ap = reinterpret_cast<const uint32_t *>(rv ? arow + r : abase);
+    const int nch = (ke - kb + 15) / 16;
+    rot = rot % nch;
+    u4v st[SPT], a0, a1;
+    auto row0 = [&](int c) { int cc = c + rot; if (cc >= nch) cc -= nch; return kb + 16 * cc; };
+    auto load = [&](int c, u4v &a) {
+        const int k0 = row0(c);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int e = threadIdx.x + u * NTH;      // e = (half * WC + col) * 4 + quad
+            if (e < NV) {
+                const int quad = e & 3, hc = e >> 2, half = hc / WC, col = hc % WC;
+                st[u] = *reinterpret_cast<const u4v *>((half ? Yl : Yh) + (long long)col * mp + k0 + 4 * quad);
+            }
+        }
+        const int kc0 = k0 + 4 * q;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = ap[(long long)min(kc0 + t, (int)m - 1) * m];
+    };
+    auto stage = [&](int slot) {
+        u4v *b = reinterpret_cast<u4v *>(buf) + slot * NV;
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int e = threadIdx.x + u * NTH;
+            if (e < NV) b[e] = st[u];
+        }
+    };
+    auto compute = [&](int slot, const u4v &a) {
+        const u4v *b = reinterpret_cast<const u4v *>(buf) + slot * NV;
+        u4v nre, nim;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            nre[t] = a[t] ^ 0x00008000u;                           // -(Re a, -Im a)
+            nim[t] = ((a[t] >> 16) | (a[t] << 16)) ^ 0x80008000u;  // -(Im a, Re a)
+        }
+        const v8bf vre = __builtin_bit_cast(v8bf, nre), vim = __builtin_bit_cast(v8bf, nim);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int col = ct * 16 + r;
+            const v8bf h = __builtin_bit_cast(v8bf, b[col * 4 + q]), l = __builtin_bit_cast(v8bf, b[(WC + col) * 4 + q]);
+            cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, h, cr[ct], 0, 0, 0);
+            ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, h, ci[ct], 0, 0, 0);
+            cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, l, cr[ct], 0, 0, 0);
+            ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, l, ci[ct], 0, 0, 0);
+        }
+    };
+    load(0, a0);
+    stage(0);
+    for (int c = 0; c < nch; c += 2) {
+        if (c + 1 < nch) load(c + 1, a1);
+        __syncthreads();
+        if (active) compute(0, a0);
+        if (c + 1 >= nch) break;
+        stage(1);
+        if (c + 2 < nch) load(c + 2, a0);
+        __syncthreads();
+        if (active) compute(1, a1);
+        if (c + 2 < nch) stage(0);
     }
 }
 
@@ -356,12 +446,14 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
 // contiguous item ranges (neighbouring modes share the cache lines of `work`).
 // out_mode: 0 = write x to work; 1 = keep x in Y only; 2 = write x + Yadd to work (the
 // correction step of a refined solve, Yadd holding the first solution).
+// With bfloat16 factors the off-diagonal products run on the bfloat16 matrix cores against the
+// solved rows split into bfloat16 hi + lo (Yb: [item][2][col][mp], mp = m rounded up to 16).
 template <class R, int CT, int NW, class FT>
 __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, const FT *F, const int *perm,
                                                                const int4 *items, int nitems, const int *mode_ptr,
                                                                const int *mode_list, cpx<R> *Y, int m, int n,
                                                                int nboxes, int nrhs, int out_mode,
-                                                               const cpx<R> *Yadd) {
+                                                               const cpx<R> *Yadd, uint32_t *Yb, int mp) {
     typedef typename Mfma<R>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int ST = 16 * NW;  // rows per super-tile
@@ -372,12 +464,21 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
     cpx<R> *xs_c = reinterpret_cast<cpx<R> *>(vie_smem);  // [64][WC]: tile accumulators
     cpx<R> *ys_c = xs_c + TS * WC;                         // [64][WC]: solved tile
+    cpx<R> *yb_c = ys_c + TS * WC;                         // staged chunks of solved rows (2 slots)
     const R *xs = reinterpret_cast<const R *>(xs_c);
     const R *ys = reinterpret_cast<const R *>(ys_c);
     const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     cpx<R> *Yi = Y + (long long)it * m * WC;
     const cpx<R> *Ya = Yadd ? Yadd + (long long)it * m * WC : nullptr;
+    constexpr bool kBf16 = sizeof(FT) == 4;
+    uint32_t *Yh = kBf16 ? Yb + (long long)it * 2 * WC * mp : nullptr;
+    uint32_t *Yl = kBf16 ? Yh + (long long)WC * mp : nullptr;
+    if (kBf16)  // zero padding rows m..mp-1 of the split copy (read by the last ragged K-step)
+        for (int e = threadIdx.x; e < 2 * WC * (mp - m); e += blockDim.x) {
+            const int col = e / (mp - m) % WC, row = m + e % (mp - m);
+            (e < WC * (mp - m) ? Yh : Yl)[(long long)col * mp + row] = 0u;
+        }
     const long long rstride = (long long)nboxes * m * n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
@@ -446,6 +547,14 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                     if (row < w) {
                         const long long yo = (long long)(t0 + row) * WC + ct * 16 + r;
                         Yi[yo] = x;
+                        if (kBf16) {  // hi + lo bfloat16 split of the solved row
+                            const uint32_t hr = bf16_bits((float)x.re), hi_ = bf16_bits((float)x.im);
+                            const float lr = (float)x.re - __uint_as_float(hr << 16);
+                            const float li = (float)x.im - __uint_as_float(hi_ << 16);
+                            const long long bo = (long long)(ct * 16 + r) * mp + t0 + row;
+                            Yh[bo] = hr | (hi_ << 16);
+                            Yl[bo] = bf16_bits(lr) | (bf16_bits(li) << 16);
+                        }
                         if (!lower && off[ct] >= 0 && out_mode != 1)
                             work[off[ct] + (long long)(t0 + row) * n] = out_mode == 2 ? x + Ya[yo] : x;
                     }
@@ -477,9 +586,16 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                 cr[ct][v] = b.re;
                 ci[ct][v] = b.im;
             }
-        if (s0 > 0 && myt0 < m)
-            wide_gemm_global<R, CT>(cr, ci, A + myt0 + wrow, A, m, myt0 + wrow + r < m, Yi, 0, s0, 5 * it);
-        __syncthreads();  // y[0:s0] reads done before the tiles below overwrite LDS (not Y)
+        if (s0 > 0) {  // every wavefront stages; those past m only help
+            const bool act = myt0 < m;
+            const FT *ar = A + min(myt0 + wrow, m - 1);
+            if constexpr (kBf16)
+                wide_gemm_chunked_bf16<CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yh, Yl, mp, 0, s0,
+                                                    5 * it, reinterpret_cast<uint32_t *>(yb_c));
+            else
+                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, 0, s0, 5 * it, yb_c);
+        }
+        __syncthreads();
         for (int tt = 0; tt < NW / 4; ++tt) {
             const int t0 = s0 + TS * tt;
             if (t0 >= m) break;
@@ -501,8 +617,15 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                 cr[ct][v] = y.re;
                 ci[ct][v] = y.im;
             }
-        if (se < m && myt0 < m)
-            wide_gemm_global<R, CT>(cr, ci, A + myt0 + wrow, A, m, myt0 + wrow + r < m, Yi, se, m, 5 * it);
+        if (se < m) {
+            const bool act = myt0 < m;
+            const FT *ar = A + min(myt0 + wrow, m - 1);
+            if constexpr (kBf16)
+                wide_gemm_chunked_bf16<CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yh, Yl, mp, se, m,
+                                                    5 * it, reinterpret_cast<uint32_t *>(yb_c));
+            else
+                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, se, m, 5 * it, yb_c);
+        }
         __syncthreads();
         for (int tt = NW / 4 - 1; tt >= 0; --tt) {
             const int t0 = s0 + TS * tt;
@@ -531,6 +654,9 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                                                               int by, int bz) {
     typedef Mfma<float>::v4 v4;
     constexpr int WC = CT * 16;
+    constexpr int NTH = NW * 64;
+    constexpr int YC = 16;                          // rows of z0 per staged chunk
+    constexpr int SPT = (YC * WC + NTH - 1) / NTH;
     const int per = (nitems + 7) / 8;
     const int it = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (it >= nitems) return;
@@ -539,6 +665,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     const int ndy = 2 * by - 1, ndz = 2 * bz - 1, plane = by * bz;
     const int tabn = 6 * ndz * ndy;
     c64 *tab = reinterpret_cast<c64 *>(vie_smem);
+    c64 *buf = tab + ((tabn + 1) & ~1);             // two chunk slots of z0 rows
     const c64 *src = chan + (long long)smode[sblk] * tabn;
     for (int i = threadIdx.x; i < tabn; i += blockDim.x) tab[i] = src[i];
     const c64 *Yi = Y + (long long)it * m * WC;
@@ -555,13 +682,27 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
             off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode_list[mode_ptr[sblk] + g / nrhs];
         }
     }
-    __syncthreads();
-    const float *yf = reinterpret_cast<const float *>(Yi) + p;
-    const int nks = (m + 1) / 2;
-    for (int strip = wv; strip * 16 < m; strip += NW) {
-        const int row0 = strip * 16;
-        // this lane's operand row (a, y, z)
-        const int arow = min(row0 + r, m - 1);
+    const int nch = (m + YC - 1) / YC;
+    c64 st[SPT];
+    auto load = [&](int c) {
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int e = tid + u * NTH, row = c * YC + e / WC;
+            st[u] = (e < YC * WC && row < m) ? Yi[(long long)row * WC + e % WC] : czero<float>();
+        }
+    };
+    auto stage = [&](int slot) {
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int e = tid + u * NTH;
+            if (e < YC * WC) buf[slot * YC * WC + e] = st[u];
+        }
+    };
+    // NW strips of 16 rows at a time; all wavefronts stage the shared z0 chunks
+    for (int g0 = 0; g0 * 16 * NW < m; ++g0) {
+        const int row0 = (g0 * NW + wv) * 16;
+        const bool active = row0 < m;
+        const int arow = min(row0 + r, m - 1);  // this lane's operand row (a, y, z)
         const int a = arow / plane, yz = arow - a * plane, z = yz / by, y = yz - z * by;
         v4 cr[CT], ci[CT];
 #pragma unroll
@@ -569,7 +710,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
             cr[ct] = v4{0, 0, 0, 0};
             ci[ct] = v4{0, 0, 0, 0};
         }
-        // column (b, y', z') of K-step 0 for this lane (kc = kh), advanced by 2 per step
+        // column (b, y', z') of K-step 0 for this lane (kc = kh), advanced by 2 per K-step
         int b = 0, zp = 0, yp = kh;
         while (yp >= by) {
             yp -= by;
@@ -578,42 +719,61 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                 ++b;
             }
         }
-        for (int ks = 0; ks < nks; ++ks) {
-            const int kc = 2 * ks + kh;
-            const bool in = kc < m;
-            const int c = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
-            const c64 t = in ? tab[(c * ndz + (z - zp + bz - 1)) * ndy + (y - yp + by - 1)] : czero<float>();
-            const float ar = p ? -t.im : t.re;
-            const float ai = p ? t.re : t.im;
-            const int kcl = in ? kc : 0;
+        auto compute = [&](int slot, int c) {
+            const float *xs = reinterpret_cast<const float *>(buf + slot * YC * WC) + p;
+#pragma unroll 2
+            for (int u = 0; u < YC / 2; ++u) {
+                const int kc = c * YC + 2 * u + kh;
+                const int cc = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
+                const c64 t = kc < m ? tab[(cc * ndz + (z - zp + bz - 1)) * ndy + (y - yp + by - 1)] : czero<float>();
+                const float ar = p ? -t.im : t.re;
+                const float ai = p ? t.re : t.im;
+                const float *xr = xs + (2 * u + kh) * WC * 2;
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const float bv = yf[((long long)kcl * WC + ct * 16 + r) * 2];
-                cr[ct] = Mfma<float>::fma(ar, bv, cr[ct]);
-                ci[ct] = Mfma<float>::fma(ai, bv, ci[ct]);
-            }
-            yp += 2;
-            while (yp >= by) {
-                yp -= by;
-                if (++zp == bz) {
-                    zp = 0;
-                    ++b;
+                for (int ct = 0; ct < CT; ++ct) {
+                    const float bv = xr[(ct * 16 + r) * 2];
+                    cr[ct] = Mfma<float>::fma(ar, bv, cr[ct]);
+                    ci[ct] = Mfma<float>::fma(ai, bv, ci[ct]);
+                }
+                yp += 2;
+                while (yp >= by) {
+                    yp -= by;
+                    if (++zp == bz) {
+                        zp = 0;
+                        ++b;
+                    }
                 }
             }
+        };
+        __syncthreads();  // previous group's chunk reads done (and the table staged)
+        load(0);
+        stage(0);
+        for (int c = 0; c < nch; c += 2) {
+            if (c + 1 < nch) load(c + 1);
+            __syncthreads();
+            if (active) compute(0, c);
+            if (c + 1 >= nch) break;
+            stage(1);
+            if (c + 2 < nch) load(c + 2);
+            __syncthreads();
+            if (active) compute(1, c + 1);
+            if (c + 2 < nch) stage(0);
         }
+        if (active) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+            for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = row0 + Mfma<float>::acc_row(q, v);
-                if (row < m && off[ct] >= 0) {
-                    const int ra = row / plane, ryz = row - ra * plane;  // M~ index (z, y)
-                    const c64 mv = mt[(long long)box * plane + ryz];
-                    const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
-                    const long long wo = off[ct] + (long long)row * n;
-                    work[wo] = work[wo] - z0 + mv * mk(cr[ct][v], ci[ct][v]);
+                for (int v = 0; v < 4; ++v) {
+                    const int row = row0 + Mfma<float>::acc_row(q, v);
+                    if (row < m && off[ct] >= 0) {
+                        const int ra = row / plane, ryz = row - ra * plane;  // M~ index (z, y)
+                        const c64 mv = mt[(long long)box * plane + ryz];
+                        const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
+                        const long long wo = off[ct] + (long long)row * n;
+                        work[wo] = work[wo] - z0 + mv * mk(cr[ct][v], ci[ct][v]);
+                    }
                 }
-            }
+        }
     }
 }
 
@@ -675,17 +835,22 @@ template <class R, int CT, int NW, class FT>
 static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
                            hipStream_t s) {
     const int per = (pc->n_wide + 7) / 8;
-    const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16;
+    // two 64-row tiles + two chunk slots of solved rows (FP: 16 / 8 rows; bfloat16: hi + lo, 16 rows)
+    const size_t chunk = sizeof(FT) == 4 ? 2 * 2 * (size_t)CT * 16 * 16 * sizeof(uint32_t)
+                                         : 2 * (size_t)(sizeof(R) == 8 ? 8 : 16) * CT * 16 * sizeof(cpx<R>);
+    const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16 + chunk;
     vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
-                       mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs, out_mode, Yadd);
+                       mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs, out_mode, Yadd,
+                       pc->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16);
 }
 
 // wavefronts per workgroup (16 NW rows per super-tile): 8 or 16 for FP32, 4 or 8 for FP64
 static int wide_nw(vie_pc pc, bool fp32) {
     if (pc->cfg_nw) return pc->cfg_nw;
+    if (pc->prec == VIE_BF16C) return 8;  // the bfloat16 double buffers need > 128 VGPRs
     return fp32 ? 16 : 8;
 }
 
@@ -706,7 +871,8 @@ template <int CT>
 static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
     constexpr int NW = 8;
     const int per = (pc->n_wide + 7) / 8;
-    const size_t lds = sizeof(c64) * 6 * (2 * pc->bz - 1) * (2 * pc->by - 1);
+    const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
+    const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16);
     vie_lds_attr((const void *)k_refine_residual<CT, NW>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
@@ -725,6 +891,8 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
         const size_t ybytes = sizeof(cpx<R>) * (size_t)pc->n_wide * m * WC;
         VIE_CHECK(pc->wide_scratch.ensure(ybytes));
         cpx<R> *Y = pc->wide_scratch.as<cpx<R>>();
+        if (pc->prec == VIE_BF16C)  // hi + lo bfloat16 copies of the solved rows
+            VIE_CHECK(pc->wide_bf16.ensure(sizeof(uint32_t) * 2 * (size_t)pc->n_wide * WC * ((m + 15) / 16 * 16)));
         const bool refine = pc->refine && sizeof(R) == 4;
         cpx<R> *Y2 = nullptr;
         if (refine) {

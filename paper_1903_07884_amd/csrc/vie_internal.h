@@ -200,6 +200,7 @@ struct vie_pc_s {
     DevBuf sched;                          // int4 wide items [n_wide] then int32 box*bx+mode [n_narrow]
     DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
     DevBuf wide_scratch2;                  // second solve of a refined apply
+    DevBuf wide_bf16;                      // bfloat16 hi + lo split of the solved rows (BF16 factors)
     // refinement of VIE_BF16C solves
     int refine = 0;
     DevBuf chan32;                         // complex float C^_k tables [n][6][2bz-1][2by-1] per box length
