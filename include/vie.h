@@ -132,6 +132,13 @@ typedef struct {
                             steps of every block solve D_k z = r: the residual r - D_k z is
                             formed in FP32 from D_k = I - diag(M~) C^_k itself (not from the
                             rounded factors) and a second solve corrects z */
+    int32_t keep_zero_rows; /* 0 (default): cross-section rows (a, y, z) whose homogenised
+                            contrast M~(y, z) is zero in every box are identity rows of every
+                            D_k (eq. Di with M~ = 0), so only the other rows are factorised and
+                            solved; input on the identity rows enters the solve through the
+                            exact coupling term M~ C^_k r^ (skipped on the device when that
+                            input is zero, as for every Krylov vector of a right-hand side
+                            that vanishes where M = 0).  1 = factorise the full cross-section. */
 } vie_pc_opts;
 
 typedef struct {
@@ -139,6 +146,8 @@ typedef struct {
     int32_t modes;                    /* nboxes * box_nx Fourier modes */
     int32_t stored_blocks;            /* LU-factored blocks held on the device */
     int64_t factor_bytes;             /* bytes of LU factors (+ pivots) */
+    int32_t active_m;                 /* order of the factorised blocks: block_m less the
+                                         identity rows (keep_zero_rows = 0) */
 } vie_pc_info;
 
 /* Build the 1-level Chan-Olkin block-circulant preconditioner (Sec. 4): per box,
@@ -196,7 +205,8 @@ vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
  * launches; vie_profile_end() stops recording.  Names: "generator",
  * "matvec_xfwd", "matvec_plane", "matvec_xinv", "precond_xfft", "block_solve" (all block
  * solves of an apply), "refine_residual" (the refinement residual and correcting solve),
- * "precond_ixfft", "lu_panel", "lu_swap_trsm", "lu_update", "lu_invert_diag",
+ * "precond_ixfft", "precond_identity_rows" (copy of the identity rows and, when they hold
+ * input, its coupling into the solved rows), "lu_panel", "lu_swap_trsm", "lu_update", "lu_invert_diag",
  * "arnoldi_dots", "arnoldi_update".  Recording adds two event records per launch. */
 vie_status vie_profile_begin(void);
 vie_status vie_profile_kernel(const char *name, double *total_ms, int64_t *launches);

@@ -171,6 +171,8 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     if (o.refine_steps < 0 || o.refine_steps > 1) return arg_error("precond_setup: refine_steps must be 0 or 1");
     if (o.refine_steps && o.factor_prec != VIE_BF16C)
         return arg_error("precond_setup: refine_steps needs VIE_BF16C factors");
+    if (o.keep_zero_rows != 0 && o.keep_zero_rows != 1)
+        return arg_error("precond_setup: keep_zero_rows must be 0 or 1");
     if (o.factor_prec == VIE_BF16C && !op->has_c64)
         return arg_error("precond_setup: VIE_BF16C factors need an operator built with build_c64");
     if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
@@ -225,6 +227,7 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     pc->by = by;
     pc->bz = bz;
     pc->m = m;
+    pc->m_full = m;
     pc->boxes = boxes;
     pc->covers_all = vol == op->N;
     pc->prec = o.factor_prec;
@@ -267,7 +270,9 @@ extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t n
         pc_bytes = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
         if (o.factor_prec == VIE_BF16C) pc_bytes += modes * m * m * 8;  // complex-float factorisation copy
         pc_bytes += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;  // Chan table, LU workspace
-        if (o.refine_steps) pc_bytes += table * 8 + nb * by * bz * 8;
+        if (o.refine_steps || !o.keep_zero_rows) pc_bytes += table * 8 + nb * by * bz * 8;
+        if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pc_bytes += table * 16 + nb * by * bz * 16;
+        pc_bytes += m * 4 + 64;  // row order, coupling flag
         // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
         const uint64_t cols = modes * R;
         const uint64_t wide = (cols + 64 * modes) * m * vesz;
@@ -291,7 +296,8 @@ extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
     if (!pc || !info) return arg_error("precond_info: NULL argument");
     info->nboxes = pc->nboxes;
     info->box_nx = pc->bx;
-    info->block_m = pc->m;
+    info->block_m = pc->m_full;
+    info->active_m = pc->m;
     info->modes = pc->nboxes * pc->bx;
     info->stored_blocks = pc->nstored;
     size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : pc->prec == VIE_C64 ? sizeof(c64) : sizeof(bf16c);

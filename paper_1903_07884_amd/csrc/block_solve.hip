@@ -642,6 +642,8 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
 //   r^ <- r^ - D_k z0 = r^ - z0 + M~ (C^_k z0)          (over r^ in work)
 // with z0 the first solve's result (the item's scratch, row-major [m][CT*16]) and
 //   C^_k[(a,y,z), (b,y',z')] = C^_k^{c(a,b)}(y - y', z - z'),
+// over the solve rows rows[0..m) (the cross-section rows with M~ != 0 when the identity rows
+// are left out; their input enters the right-hand side before the first solve),
 // the Chan/x-DFT table of the block (complex float, [6][2bz-1][2by-1] per mode, staged in
 // LDS), c(a,b) the index of the unique component (xx, yy, zz, xy, xz, yz).  The product is
 // a matrix-core GEMM whose left operand is generated from the table.  NW wavefronts take
@@ -650,8 +652,8 @@ template <int CT, int NW>
 __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c64 *chan, const c64 *mt,
                                                               const int *smode, const int4 *items, int nitems,
                                                               const int *mode_ptr, const int *mode_list,
-                                                              const c64 *Y, int m, int n, int nboxes, int nrhs,
-                                                              int by, int bz) {
+                                                              const c64 *Y, const int *rows, int m, int n,
+                                                              int nboxes, int nrhs, int by, int bz) {
     typedef Mfma<float>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int NTH = NW * 64;
@@ -666,8 +668,13 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     const int tabn = 6 * ndz * ndy;
     c64 *tab = reinterpret_cast<c64 *>(vie_smem);
     c64 *buf = tab + ((tabn + 1) & ~1);             // two chunk slots of z0 rows
+    int *pk = reinterpret_cast<int *>(buf + 2 * YC * WC);  // (b, z', y') of solve row j, packed
     const c64 *src = chan + (long long)smode[sblk] * tabn;
     for (int i = threadIdx.x; i < tabn; i += blockDim.x) tab[i] = src[i];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const int pr = rows[j], b = pr / plane, yz = pr - b * plane;
+        pk[j] = (b << 20) | ((yz / by) << 10) | (yz % by);
+    }
     const c64 *Yi = Y + (long long)it * m * WC;
     const long long rstride = (long long)nboxes * m * n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -702,7 +709,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     for (int g0 = 0; g0 * 16 * NW < m; ++g0) {
         const int row0 = (g0 * NW + wv) * 16;
         const bool active = row0 < m;
-        const int arow = min(row0 + r, m - 1);  // this lane's operand row (a, y, z)
+        const int arow = rows[min(row0 + r, m - 1)];  // this lane's operand row (a, y, z)
         const int a = arow / plane, yz = arow - a * plane, z = yz / by, y = yz - z * by;
         v4 cr[CT], ci[CT];
 #pragma unroll
@@ -710,20 +717,13 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
             cr[ct] = v4{0, 0, 0, 0};
             ci[ct] = v4{0, 0, 0, 0};
         }
-        // column (b, y', z') of K-step 0 for this lane (kc = kh), advanced by 2 per K-step
-        int b = 0, zp = 0, yp = kh;
-        while (yp >= by) {
-            yp -= by;
-            if (++zp == bz) {
-                zp = 0;
-                ++b;
-            }
-        }
         auto compute = [&](int slot, int c) {
             const float *xs = reinterpret_cast<const float *>(buf + slot * YC * WC) + p;
 #pragma unroll 2
             for (int u = 0; u < YC / 2; ++u) {
                 const int kc = c * YC + 2 * u + kh;
+                const int pc = pk[min(kc, m - 1)];  // column (b, y', z')
+                const int b = pc >> 20, zp = (pc >> 10) & 1023, yp = pc & 1023;
                 const int cc = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
                 const c64 t = kc < m ? tab[(cc * ndz + (z - zp + bz - 1)) * ndy + (y - yp + by - 1)] : czero<float>();
                 const float ar = p ? -t.im : t.re;
@@ -734,14 +734,6 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                     const float bv = xr[(ct * 16 + r) * 2];
                     cr[ct] = Mfma<float>::fma(ar, bv, cr[ct]);
                     ci[ct] = Mfma<float>::fma(ai, bv, ci[ct]);
-                }
-                yp += 2;
-                while (yp >= by) {
-                    yp -= by;
-                    if (++zp == bz) {
-                        zp = 0;
-                        ++b;
-                    }
                 }
             }
         };
@@ -766,7 +758,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                 for (int v = 0; v < 4; ++v) {
                     const int row = row0 + Mfma<float>::acc_row(q, v);
                     if (row < m && off[ct] >= 0) {
-                        const int ra = row / plane, ryz = row - ra * plane;  // M~ index (z, y)
+                        const int ryz = ((pk[row] >> 10) & 1023) * by + (pk[row] & 1023);  // M~ index (z, y)
                         const c64 mv = mt[(long long)box * plane + ryz];
                         const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
                         const long long wo = off[ct] + (long long)row * n;
@@ -872,13 +864,13 @@ static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStr
     constexpr int NW = 8;
     const int per = (pc->n_wide + 7) / 8;
     const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
-    const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16);
+    const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16) + sizeof(int) * pc->m;
     vie_lds_attr((const void *)k_refine_residual<CT, NW>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
-                       pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y, pc->m, pc->bx,
-                       pc->nboxes, nrhs, pc->by, pc->bz);
+                       pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y,
+                       pc->rows.as<const int>(), pc->m, pc->bx, pc->nboxes, nrhs, pc->by, pc->bz);
 }
 
 template <class R, class FT>

@@ -110,16 +110,16 @@ __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, 
 }
 
 // ---------------------------------------------------------------- assembly
-// D[s] column-major m x m, s-th stored block (mode ks, box bs)
+// D[s] column-major m x m, s-th stored block (mode ks, box bs), over the cross-section rows
+// rows[0..m) (entry a*by*bz + z*by + y)
 template <class R>
 __global__ void k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode, const int *blk_box,
-                           cpx<R> *D, int by, int bz) {
-    const int m = 3 * by * bz;
+                           const int *rows, cpx<R> *D, int m, int by, int bz) {
     const int ndy = 2 * by - 1, ndz = 2 * bz - 1;
     int s = blockIdx.y;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= (long long)m * m) return;
-    int r = (int)(e % m), col = (int)(e / m);
+    const int r = rows[(int)(e % m)], col = rows[(int)(e / m)];
     int ar = r / (by * bz), yr = r % by, zr = (r / by) % bz;
     int ac = col / (by * bz), yc = col % by, zc = (col / by) % bz;
     int k = blk_mode[s], b = blk_box[s];
@@ -741,16 +741,20 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- apply
-// Forward x-DFT of every box line: work[rhs][box][row][k], row = a*by*bz + y + by*z.
+// Forward x-DFT of the box lines of `mr` cross-section rows rows[0..mr):
+// work[rhs][box][i][k] holds line rows[i].  With a gate, the whole launch is skipped unless
+// *gate == epoch (the identity rows of this apply held input).
 template <class R, int BPT>
-__global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int nx, int ny, int nz, int by,
-                          int bz, int nboxes, FftPlan plan) {
+__global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, const int *rows, int mr, int nx,
+                          int ny, int nz, int by, int bz, int nboxes, FftPlan plan, const uint32_t *gate,
+                          uint32_t epoch) {
+    if (gate && *gate != epoch) return;
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    const int n = plan.L, m = 3 * by * bz;
-    long long line = blockIdx.x;  // ((rhs * nboxes + box) * m + row)
-    int row = (int)(line % m);
-    int box = (int)((line / m) % nboxes);
-    long long rhs = line / ((long long)m * nboxes);
+    const int n = plan.L;
+    long long line = blockIdx.x;  // ((rhs * nboxes + box) * mr + i)
+    int row = rows[(int)(line % mr)];
+    int box = (int)((line / mr) % nboxes);
+    long long rhs = line / ((long long)mr * nboxes);
     int comp = row / (by * bz), y = row % by, z = (row / by) % bz;
     const int *bx = boxes + 6 * box;
     const cpx<R> *src = r + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
@@ -761,16 +765,16 @@ __global__ void k_box_fft(const cpx<R> *r, cpx<R> *work, const int *boxes, int n
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = res[i];
 }
 
-// Inverse x-DFT (scaled 1/n) of every box line back into z.
+// Inverse x-DFT (scaled 1/n) of the solved lines back into z.
 template <class R, int BPT>
-__global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int nx, int ny, int nz, int by,
-                           int bz, int nboxes, FftPlan plan) {
+__global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, const int *rows, int mr, int nx,
+                           int ny, int nz, int by, int bz, int nboxes, FftPlan plan) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
-    const int n = plan.L, m = 3 * by * bz;
+    const int n = plan.L;
     long long line = blockIdx.x;
-    int row = (int)(line % m);
-    int box = (int)((line / m) % nboxes);
-    long long rhs = line / ((long long)m * nboxes);
+    int row = rows[(int)(line % mr)];
+    int box = (int)((line / mr) % nboxes);
+    long long rhs = line / ((long long)mr * nboxes);
     int comp = row / (by * bz), y = row % by, z = (row / by) % bz;
     const int *bx = boxes + 6 * box;
     const cpx<R> *src = work + line * n;
@@ -782,40 +786,133 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, int
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
 }
 
+// Identity rows of every D_k (M~ = 0 on the row): z = r on their box lines, and *flag = epoch
+// when any of that input is nonzero (it then couples into the solved rows).
+template <class R>
+__global__ void __launch_bounds__(256) k_identity_rows(const cpx<R> *r, cpx<R> *zv, const int *boxes,
+                                                       const int *rows, int mc, int nx, int ny, int nz, int by,
+                                                       int bz, int nboxes, uint32_t *flag, uint32_t epoch) {
+    const long long line = blockIdx.x;  // ((rhs * nboxes + box) * mc + j)
+    const int row = rows[(int)(line % mc)];
+    const int box = (int)((line / mc) % nboxes);
+    const long long rhs = line / ((long long)mc * nboxes);
+    const int comp = row / (by * bz), y = row % by, z = (row / by) % bz;
+    const int *bx = boxes + 6 * box;
+    const long long o = rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
+    bool nz_ = false;
+    for (int i = threadIdx.x; i < bx[3]; i += blockDim.x) {
+        const cpx<R> v = r[o + i];
+        zv[o + i] = v;
+        nz_ |= v.re != R(0) || v.im != R(0) || v.re != v.re || v.im != v.im;
+    }
+    if (nz_) *flag = epoch;
+}
+
+// Coupling of the identity rows C into the solved rows S of D_k = I - M~ C^_k:
+// with z^_C = r^_C, the solved rows satisfy D_SS z^_S = r^_S + M~_S (C^_k)_SC r^_C, so
+//   work[S] += M~(y, z) sum_j C^_k[(a,y,z), row_j] r^_C[j]
+// (one workgroup per (rhs, box, mode k); C^_k read from the Chan/x-DFT table).  Skipped
+// unless *gate == epoch.
+template <class R>
+__global__ void __launch_bounds__(256) k_couple(cpx<R> *work, const cpx<R> *workc, const cpx<R> *chan,
+                                                const cpx<R> *mt, const int *rows, int m, int mc, int n,
+                                                int nboxes, int by, int bz, const uint32_t *gate,
+                                                uint32_t epoch) {
+    if (*gate != epoch) return;
+    cpx<R> *rc = reinterpret_cast<cpx<R> *>(vie_smem);  // r^_C at mode k
+    int *pk = reinterpret_cast<int *>(rc + mc);          // (b, z', y') of row j, packed
+    const long long item = blockIdx.x;                   // (rhs * nboxes + box) * n + k
+    const int k = (int)(item % n);
+    const long long rb = item / n;
+    const int box = (int)(rb % nboxes);
+    const int plane = by * bz, ndy = 2 * by - 1, ndz = 2 * bz - 1;
+    for (int j = threadIdx.x; j < mc; j += blockDim.x) {
+        rc[j] = workc[(rb * mc + j) * n + k];
+        const int p = rows[m + j], b = p / plane, yz = p - b * plane;
+        pk[j] = (b << 20) | ((yz / by) << 10) | (yz % by);
+    }
+    __syncthreads();
+    const cpx<R> *tab = chan + (long long)k * 6 * ndz * ndy;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int p = rows[i], a = p / plane, yz = p - a * plane, z = yz / by, y = yz % by;
+        cpx<R> acc = czero<R>();
+        for (int j = 0; j < mc; ++j) {
+            const int b = pk[j] >> 20, zc = (pk[j] >> 10) & 1023, yc = pk[j] & 1023;
+            const int cc = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
+            acc = acc + tab[(cc * ndz + z - zc + bz - 1) * ndy + y - yc + by - 1] * rc[j];
+        }
+        cpx<R> *w = work + (rb * m + i) * n + k;
+        *w = *w + mt[(long long)box * plane + yz] * acc;
+    }
+}
+
 // ---------------------------------------------------------------- host side
 template <class R>
 static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
     vie_op op = pc->op;
-    const int m = pc->m, n = pc->bx;
+    const int m = pc->m, mc = pc->m_full - pc->m, n = pc->bx;
     long long lines = (long long)nrhs * pc->nboxes * m;
     VIE_CHECK(pc->work.ensure(sizeof(cpx<R>) * lines * n));
+    if (mc > 0) VIE_CHECK(pc->workc.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * mc * n));
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
     const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * n);
+    const int *rows = pc->rows.as<const int>();
     int thr, bpt;
     size_t lds;
     fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds, &bpt);
     cpx<R> *work = pc->work.as<cpx<R>>();
+    uint32_t *flag = pc->cflag.as<uint32_t>();
+    if (mc > 0) {
+        if (++pc->epoch == 0) {  // wrapped: no earlier apply may match the new epochs
+            VIE_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
+            pc->epoch = 1;
+        }
+        ProfScope ps("precond_identity_rows", s);
+        hipLaunchKernelGGL(k_identity_rows<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * mc)), dim3(256), 0, s,
+                           r, z, dboxes, rows + m, mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, flag,
+                           pc->epoch);
+        VIE_HIP(hipGetLastError());
+    }
     {
         ProfScope ps("precond_xfft", s);
-#define LAUNCH_BOX_FFT(B)                                                                                 \
-    vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                     \
-    hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, op->nx, \
-                       op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
+#define LAUNCH_BOX_FFT(B)                                                                                   \
+    vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                       \
+    hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, rows, m, \
+                       op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, nullptr, 0u)
         VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
 #undef LAUNCH_BOX_FFT
     }
     VIE_HIP(hipGetLastError());
+    if (mc > 0) {  // both launches return at once unless the identity rows held input
+        ProfScope ps("precond_identity_rows", s);
+        cpx<R> *workc = pc->workc.as<cpx<R>>();
+        const long long clines = (long long)nrhs * pc->nboxes * mc;
+#define LAUNCH_BOX_FFT_C(B)                                                                                       \
+    vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                             \
+    hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)clines), dim3(thr), lds, s, r, workc, dboxes, rows + m, \
+                       mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, flag, pc->epoch)
+        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT_C);
+#undef LAUNCH_BOX_FFT_C
+        VIE_HIP(hipGetLastError());
+        const cpx<R> *chan = sizeof(R) == 8 ? (const cpx<R> *)pc->chan64.p : (const cpx<R> *)pc->chan32.p;
+        const cpx<R> *mt = sizeof(R) == 8 ? (const cpx<R> *)pc->mt64.p : (const cpx<R> *)pc->mt32.p;
+        const size_t clds = (sizeof(cpx<R>) + sizeof(int)) * mc;
+        vie_lds_attr((const void *)k_couple<R>, clds);
+        hipLaunchKernelGGL(k_couple<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * n)), dim3(256), clds, s, work,
+                           workc, chan, mt, rows, m, mc, n, pc->nboxes, pc->by, pc->bz, flag, pc->epoch);
+        VIE_HIP(hipGetLastError());
+    }
     {
         ProfScope ps("block_solve", s);
         VIE_CHECK(launch_block_solve(pc, work, nrhs, s));
     }
     {
         ProfScope ps("precond_ixfft", s);
-#define LAUNCH_BOX_IFFT(B)                                                                                \
-    vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                    \
-    hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, op->nx, \
-                       op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
+#define LAUNCH_BOX_IFFT(B)                                                                                  \
+    vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                      \
+    hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, rows, m, \
+                       op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
         VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
 #undef LAUNCH_BOX_IFFT
     }
@@ -860,7 +957,7 @@ static c128 box_mode(const std::vector<c128> &M, int nx, int ny, const int *b) {
 
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     vie_op op = pc->op;
-    const int nbx = pc->nboxes, n = pc->bx, by = pc->by, bz = pc->bz, m = pc->m;
+    const int nbx = pc->nboxes, n = pc->bx, by = pc->by, bz = pc->bz;
     const int ndy = 2 * by - 1, ndz = 2 * bz - 1;
     VIE_CHECK(op->fft.get(n, &pc->pxb));
     // boxes on the device (kept after the block map)
@@ -895,6 +992,42 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             return VIE_EARG;
         }
     }
+    // Row order: cross-section positions (y, z) with M~ != 0 in some box first (all three
+    // components); the others are identity rows of every D_k and are not factorised.
+    {
+        const int plane = by * bz;
+        std::vector<char> act(plane, 1);
+        if (!o->keep_zero_rows) {
+            std::vector<c128> Mth((size_t)nbx * plane);
+            VIE_HIP(hipMemcpyAsync(Mth.data(), Mt.p, sizeof(c128) * Mth.size(), hipMemcpyDeviceToHost, s));
+            VIE_HIP(hipStreamSynchronize(s));
+            int cnt = 0;
+            for (int yz = 0; yz < plane; ++yz) {
+                bool any = false;
+                for (int b = 0; b < nbx; ++b) {
+                    const c128 v = Mth[(size_t)b * plane + yz];
+                    any |= v.re != 0.0 || v.im != 0.0;
+                }
+                act[yz] = any;
+                cnt += any;
+            }
+            if (cnt == 0) std::fill(act.begin(), act.end(), 1);  // M~ = 0: keep the (identity) blocks
+        }
+        pc->rows_host.clear();
+        for (int pass = 1; pass >= 0; --pass)
+            for (int a = 0; a < 3; ++a)
+                for (int yz = 0; yz < plane; ++yz)
+                    if (act[yz] == pass) pc->rows_host.push_back(a * plane + yz);
+        pc->m = 0;
+        for (int yz = 0; yz < plane; ++yz) pc->m += 3 * act[yz];
+        VIE_CHECK(pc->rows.ensure(sizeof(int) * pc->m_full));
+        VIE_HIP(hipMemcpyAsync(pc->rows.p, pc->rows_host.data(), sizeof(int) * pc->m_full, hipMemcpyHostToDevice, s));
+        VIE_CHECK(pc->cflag.ensure(sizeof(uint32_t)));
+        VIE_HIP(hipMemsetAsync(pc->cflag.p, 0, sizeof(uint32_t), s));
+        pc->epoch = 0;
+    }
+    const int m = pc->m;
+    const bool shortcut = pc->m < pc->m_full;
     // Chan + x-DFT table
     DevBuf Ch;
     VIE_CHECK(Ch.ensure(sizeof(c128) * (size_t)n * 6 * ndy * ndz));
@@ -992,13 +1125,16 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     dim3 ga((unsigned)(((long long)m * m + 255) / 256), pc->nstored);
     if (pc->prec == VIE_C128)
         hipLaunchKernelGGL(k_assemble<double>, ga, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
-                           dmode.as<const int>(), dbox.as<const int>(), pc->factors.as<c128>(), by, bz);
+                           dmode.as<const int>(), dbox.as<const int>(), pc->rows.as<const int>(),
+                           pc->factors.as<c128>(), m, by, bz);
     else
         hipLaunchKernelGGL(k_assemble<float>, ga, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
-                           dmode.as<const int>(), dbox.as<const int>(), pc->factors.as<c64>(), by, bz);
+                           dmode.as<const int>(), dbox.as<const int>(), pc->rows.as<const int>(),
+                           pc->factors.as<c64>(), m, by, bz);
     VIE_HIP(hipGetLastError());
     VIE_HIP(hipStreamSynchronize(s));
-    if (pc->refine) {  // FP32 copies of the C^_k tables and of M~ for the refinement residual
+    if (pc->refine || (shortcut && pc->prec != VIE_C128)) {
+        // FP32 copies of the C^_k tables and of M~ (refinement residual, identity-row coupling)
         const long long nch = (long long)n * 6 * ndy * ndz, nmt = (long long)nbx * by * bz;
         VIE_CHECK(pc->chan32.ensure(sizeof(c64) * nch));
         VIE_CHECK(pc->mt32.ensure(sizeof(c64) * nmt));
@@ -1011,6 +1147,12 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     VIE_CHECK(pc->smode_dev.ensure(sizeof(int) * pc->nstored));
     VIE_HIP(hipMemcpyAsync(pc->smode_dev.p, smode.data(), sizeof(int) * pc->nstored, hipMemcpyHostToDevice, s));
     VIE_HIP(hipStreamSynchronize(s));
+    if (shortcut && pc->prec == VIE_C128) {  // FP64 table and M~ kept for the identity-row coupling
+        std::swap(pc->chan64.p, Ch.p);
+        std::swap(pc->chan64.bytes, Ch.bytes);
+        std::swap(pc->mt64.p, Mt.p);
+        std::swap(pc->mt64.bytes, Mt.bytes);
+    }
     Ch.release();
     vie_status st = pc->prec == VIE_C128 ? lu_factor<double>(pc, s) : lu_factor<float>(pc, s);
     VIE_CHECK(st);

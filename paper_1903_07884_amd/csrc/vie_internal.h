@@ -179,7 +179,9 @@ struct vie_op_s {
 
 struct vie_pc_s {
     vie_op op;
-    int nboxes, bx, by, bz, m;
+    int nboxes, bx, by, bz;
+    int m;                   // order of the factorised blocks (active rows)
+    int m_full;              // 3*by*bz rows of a box cross-section
     std::vector<int> boxes;  // nboxes*6
     bool covers_all;
     int prec;                // factor precision
@@ -189,7 +191,15 @@ struct vie_pc_s {
     DevBuf factors;          // [nstored][m][m] column-major LU (complex, factor precision)
     DevBuf perm;             // int32 [nstored][m] row permutation: (P r)[i] = r[perm[i]]
     DevBuf info;             // int32 [nstored] 0 or first zero-pivot column + 1
-    DevBuf work;             // apply scratch: nrhs * nboxes * 3*by*bz * bx complex (factor prec)
+    DevBuf work;             // apply scratch: nrhs * nboxes * m * bx complex (vector prec)
+    // Cross-section rows in solve order: rows[0..m) have M~ != 0 in some box (factorised),
+    // rows[m..m_full) are identity rows of every D_k.  Entry = a*by*bz + z*by + y.
+    DevBuf rows;             // int32 [m_full]
+    std::vector<int> rows_host;
+    DevBuf workc;            // x-DFT of the identity rows, nrhs * nboxes * (m_full - m) * bx
+    DevBuf cflag;            // int32: epoch of the last apply whose identity rows held input
+    uint32_t epoch = 0;
+    DevBuf chan64, mt64;     // FP64 C^_k table / M~ for the coupling of an FP64 apply
     FftPlan pxb;             // length bx
     // block-solve schedule
     std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending)
@@ -204,6 +214,7 @@ struct vie_pc_s {
     // refinement of VIE_BF16C solves
     int refine = 0;
     DevBuf chan32;                         // complex float C^_k tables [n][6][2bz-1][2by-1] per box length
+                                           // (refinement, and the coupling of an FP32 apply)
     DevBuf mt32;                           // complex float M~ [nboxes][bz][by]
     DevBuf smode_dev;                      // int32 [nstored] mode of each stored block
     // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)

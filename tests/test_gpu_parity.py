@@ -255,10 +255,95 @@ def test_precond_apply_bf16_refined(gpu_lib, case):
         pc.apply(rd, zd, nrhs=nrhs)
         z = zd.cpu().numpy().astype(np.complex128)
         errs[refine] = max(_rel(z[i], z_ref[i]) for i in range(nrhs))
-        assert pc.info()['factor_bytes'] == pc.info()['stored_blocks'] * pc.info()['block_m'] * (pc.info()['block_m'] * 4 + 4)
+        am = pc.info()['active_m']
+        assert pc.info()['factor_bytes'] == pc.info()['stored_blocks'] * am * (am * 4 + 4)
     print('bf16', grid, nrhs, tol, 'plain err %.3e refined err %.3e' % (errs[0], errs[1]))
     assert errs[0] < 5e-2
     assert errs[1] < 1e-3 and errs[1] < errs[0] / 4
+
+
+SHORTCUT_CASES = [
+    # grid, nrhs, factor precision; two Si cores in SiO2 (coupler cross-section)
+    ((24, 10, 2), 1, 'c128'),    # narrow solves, m 60 -> 36
+    ((24, 10, 2), 16, 'c128'),   # matrix-core solves
+    ((16, 12, 4), 20, 'c128'),   # m 144 -> 96: full + ragged tile
+    ((24, 10, 2), 16, 'c64'),
+    ((16, 12, 4), 8, 'bf16'),    # bfloat16 factors, refined against D_k over the active rows
+]
+
+
+@pytest.mark.parametrize("case", SHORTCUT_CASES)
+def test_identity_rows_shortcut(gpu_lib, case):
+    """Cross-section rows with M~ = 0 are left out of the factorisation: the apply equals the
+    oracle's full-block preconditioner for input that is nonzero on those rows (coupling term)
+    and for input that vanishes there (zero output there), and equals the library's own
+    full-cross-section build."""
+    import torch
+    grid, nrhs, prec = case
+    nx, ny, nz = grid
+    delta = 50e-9
+    K = oracle_generator(grid, delta)
+    chi = W.coupler(grid, cores=((1, ny // 2 - 1), (ny // 2 + 1, ny - 1)))
+    M = OCT.contrast_from_chi(chi)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid)
+    fp = {'c128': gpu_lib.VIE_C128, 'c64': gpu_lib.VIE_C64, 'bf16': gpu_lib.VIE_BF16C}[prec]
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=prec != 'c128')
+    pc = gpu_lib.Preconditioner(op, factor_prec=fp)
+    full = gpu_lib.Preconditioner(op, factor_prec=fp, keep_zero_rows=True)
+    active = 3 * nz * (ny - 4)
+    assert pc.info()['active_m'] == active and pc.info()['block_m'] == 3 * ny * nz
+    assert full.info()['active_m'] == 3 * ny * nz
+    clad = np.tile((M == 0).reshape(-1), 3)
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((nrhs, n), 47)
+    r0 = r.copy()
+    r0[:, clad] = 0.0
+    tol = {'c128': 1e-10, 'c64': 1e-5, 'bf16': 1e-3}[prec]
+    for rr, label in ((r, 'input on cladding'), (r0, 'no input on cladding')):
+        z_ref = np.stack([ref_pc.apply(rr[i]) for i in range(nrhs)])
+        rd = _to_dev(rr if prec == 'c128' else rr.astype(np.complex64))
+        z, zf = torch.empty_like(rd), torch.empty_like(rd)
+        pc.apply(rd, z, nrhs=nrhs)
+        full.apply(rd, zf, nrhs=nrhs)
+        z = z.cpu().numpy().astype(np.complex128)
+        zf = zf.cpu().numpy().astype(np.complex128)
+        err = max(_rel(z[i], z_ref[i]) for i in range(nrhs))
+        err_f = max(_rel(zf[i], z_ref[i]) for i in range(nrhs))
+        diff = max(_rel(z[i], zf[i]) for i in range(nrhs))
+        print('shortcut', grid, nrhs, prec, label, 'err %.3e full-build err %.3e difference %.3e' % (err, err_f, diff))
+        assert err < tol and err_f < tol
+        assert diff < (1e-12 if prec == 'c128' else tol)
+        if rr is r0:
+            assert np.all(z[:, clad] == 0)
+
+
+def test_identity_rows_shortcut_solve(gpu_lib):
+    """The FP64 solve of a coupler with and without the identity rows factorised: same
+    iteration count, same solution (the Krylov vectors vanish on the cladding rows)."""
+    import torch
+    grid, delta = (48, 12, 4), 50e-9
+    nx, ny, nz = grid
+    K = oracle_generator(grid, delta)
+    chi = W.coupler(grid, cores=((1, 5), (7, 11)))
+    M = OCT.contrast_from_chi(chi)
+    e = W.random_field((1, 3 * nx * ny * nz), 53)[0]
+    b = np.tile(M.reshape(-1), 3) * e
+    A = OM.operator_matrix(K, M, grid)
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K)
+    out = {}
+    for keep in (False, True):
+        pc = gpu_lib.Preconditioner(op, keep_zero_rows=keep)
+        bd = _to_dev(b)
+        xd = torch.zeros_like(bd)
+        st = gpu_lib.solve(op, pc, bd, xd, tol=1e-10)[0]
+        x = xd.cpu().numpy()
+        out[keep] = (st, x)
+        res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        print('coupler solve keep_zero_rows=%s iters %d relres %.3e oracle residual %.3e m %d'
+              % (keep, st['iters'], st['relres'], res, pc.info()['active_m']))
+        assert st['status'] == 0 and res <= 1e-10
+    assert out[False][0]['iters'] == out[True][0]['iters']
+    assert _rel(out[False][1], out[True][1]) < 1e-9
 
 
 def test_autotuned_launches_give_the_same_results(gpu_lib):

@@ -13,6 +13,9 @@
 * Blocked preconditioner (Sec. 5.3): one box is the 1-level preconditioner;
   several boxes equal a dense block-diagonal build.
 * Homogenisations (Sec. 5.2 list) on hand-made arrays.
+* Cross-section rows with M~ = 0 are identity rows of every D_k (eq. Di), so the block
+  solve reduces exactly to the other rows S plus the coupling M~_S C^_SC r^_C, and to the
+  S x S solve alone when r^_C = 0 (the reduction the GPU path takes for cladding rows).
 """
 import numpy as np
 import pytest
@@ -126,6 +129,41 @@ def test_zero_contrast_gives_identity(box):
     inv = C.BlockCirculantInverse(K, np.zeros((nz, ny)), nx, ny, nz)
     r = np.random.default_rng(5).standard_normal((3, nz, ny, nx)) + 0j
     assert np.allclose(inv.apply(r), r, rtol=1e-14, atol=1e-14)
+
+
+def test_zero_contrast_rows_reduce_exactly(box):
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    Mt = Mt.copy()
+    Mt[0, 1] = 0.0
+    Mt[1, 2] = 0.0
+    D = C.chan_olkin_blocks(K, Mt, nx, ny, nz)
+    Ch = C.chan_transform(K, nx, ny, nz)
+    m = 3 * ny * nz
+    zero = np.array([Mt[(i % (ny * nz)) // ny, i % ny] == 0 for i in range(m)])
+    S, Cr = np.nonzero(~zero)[0], np.nonzero(zero)[0]
+    assert len(Cr) == 6
+    eye = np.eye(m)
+    for k in range(nx):
+        assert np.array_equal(D[k][Cr], eye[Cr])     # identity rows, exactly
+    rng = np.random.default_rng(12)
+    for k in range(nx):
+        rh = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        full = np.linalg.solve(D[k], rh)
+        # coupling from the Chan table itself: M~(y,z) C^_k[(a,y,z),(b,y',z')] r^_C
+        cpl = np.zeros(len(S), dtype=complex)
+        for ii, i in enumerate(S):
+            a, y, z = i // (ny * nz), i % ny, (i % (ny * nz)) // ny
+            for j in Cr:
+                b, yp, zp = j // (ny * nz), j % ny, (j % (ny * nz)) // ny
+                cpl[ii] += Mt[z, y] * Ch[k, a, b, y - yp + ny - 1, z - zp + nz - 1] * rh[j]
+        zs = np.linalg.solve(D[k][np.ix_(S, S)], rh[S] + cpl)
+        assert np.abs(zs - full[S]).max() < 1e-12 * np.abs(full).max()
+        assert np.array_equal(full[Cr], rh[Cr]) or np.abs(full[Cr] - rh[Cr]).max() < 1e-14
+        rh[Cr] = 0.0
+        full = np.linalg.solve(D[k], rh)
+        zs = np.linalg.solve(D[k][np.ix_(S, S)], rh[S])
+        assert np.abs(full[Cr]).max() < 1e-14 and np.abs(zs - full[S]).max() < 1e-12 * np.abs(full).max()
 
 
 def test_reduction_limits_and_monotone(box):
