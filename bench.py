@@ -315,6 +315,8 @@ def main():
         for label, kw in (('reduced_1e-3', dict(reduce_tol=1e-3)),
                           ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre'))):
             rr = []
+            if not args.no_autotune:   # tune this leg's new shapes outside its timing, like the main run
+                step(None, **kw)
             torch.cuda.synchronize()
             ta = time.perf_counter()
             step(rr, **kw)
@@ -335,6 +337,8 @@ def main():
             extra = (('mixed_single_box', dict(boxes=None)), ('fp64_single_box', dict(mode='fp64', boxes=None)))
         for label, kw in (('fp64', dict(mode='fp64')),) + extra:
             rr = []
+            if not args.no_autotune:   # tune this leg's new shapes outside its timing, like the main run
+                step(None, **kw)
             torch.cuda.synchronize()
             ta = time.perf_counter()
             step(rr, **kw)

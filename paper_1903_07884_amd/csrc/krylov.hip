@@ -50,29 +50,46 @@ __device__ __forceinline__ c128 wide(c64 a) { return mk((double)a.re, (double)a.
 
 // Batched vectors: vector j of right-hand side r at base + j * ldj + r * n.  The basis V is
 // complex128, or complex64 in the mixed mode; sums are accumulated in FP64.
-// partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e]; `self` adds |w|^2.
+// partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e]; `self` adds |w|^2 as
+// output nv.  The outputs are formed KR_DG at a time, so w is read once per group of KR_DG
+// basis vectors rather than once per vector.
+#define KR_DG 16
 template <class VT>
 __global__ void __launch_bounds__(KR_THREADS) k_dots(const VT *V, long long ldj, int nv, const c128 *w, long long n,
                                                      int self, c128 *partial) {
-    __shared__ c128 sh[KR_THREADS / 64];
+    __shared__ c128 sh[KR_DG][KR_THREADS / 64];
     const int r = blockIdx.y;
     const c128 *wr = w + r * n;
     long long chunk = (n + gridDim.x - 1) / gridDim.x;
     long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    int stride = nv + self;
+    const int stride = nv + self;
     c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
-    for (int i = 0; i < nv; ++i) {
-        const VT *v = V + i * ldj + r * n;
-        c128 acc = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc = acc + cmulc(wide(v[e]), wr[e]);
-        c128 s = block_sum_kr(acc, sh);
-        if (threadIdx.x == 0) out[i] = s;
-    }
-    if (self) {
-        c128 acc = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) acc.re += abs2(wr[e]);
-        c128 s = block_sum_kr(acc, sh);
-        if (threadIdx.x == 0) out[nv] = s;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i0 = 0; i0 < stride; i0 += KR_DG) {
+        c128 acc[KR_DG];
+#pragma unroll
+        for (int u = 0; u < KR_DG; ++u) acc[u] = czero<double>();
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+            const c128 we = wr[e];
+#pragma unroll
+            for (int u = 0; u < KR_DG; ++u) {
+                const int i = i0 + u;
+                if (i < nv) acc[u] = acc[u] + cmulc(wide(V[i * ldj + r * n + e]), we);
+                else if (i == nv && self) acc[u].re += abs2(we);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KR_DG; ++u) {
+            const c128 v = wave_sum(acc[u]);
+            if (lane == 0) sh[u][wid] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < KR_DG && i0 + (int)threadIdx.x < stride) {
+            c128 t = czero<double>();
+            for (int q = 0; q < KR_THREADS / 64; ++q) t = t + sh[threadIdx.x][q];
+            out[i0 + threadIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 

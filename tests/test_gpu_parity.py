@@ -228,6 +228,7 @@ BF16_CASES = [
     ((32, 8, 6), 1, None),
     ((24, 6, 4), 20, 1e-2),
     ((12, 12, 8), 8, None),
+    ((8, 2, 20), 8, None),       # 20 z layers, 2 y rows: m = 120
 ]
 
 
