@@ -861,7 +861,7 @@ static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mo
 
 template <int CT>
 static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
-    constexpr int NW = 8;
+    constexpr int NW = 16;  // one workgroup per CU (the table fills the LDS): 16 wavefronts hide the latency
     const int per = (pc->n_wide + 7) / 8;
     const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
     const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16) + sizeof(int) * pc->m;

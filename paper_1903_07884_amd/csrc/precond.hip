@@ -620,17 +620,30 @@ __global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
         cpx<R> x = czero<R>();
         const int jl = w - 1 - step;  // L column of this step
         const int ju = step;          // U column of this step
+        // each dot product in four independent partial sums (the LDS loads of four terms in flight)
+        auto dot = [&](int k0, int k1, int col) -> cpx<R> {
+            const cpx<R> *ti = T + i, *tc = T + col * (TS + 1);
+            cpx<R> p0 = czero<R>(), p1 = czero<R>(), p2 = czero<R>(), p3 = czero<R>();
+            int k = k0;
+            for (; k + 3 < k1; k += 4) {
+                p0 = p0 + ti[k * (TS + 1)] * tc[k];
+                p1 = p1 + ti[(k + 1) * (TS + 1)] * tc[k + 1];
+                p2 = p2 + ti[(k + 2) * (TS + 1)] * tc[k + 2];
+                p3 = p3 + ti[(k + 3) * (TS + 1)] * tc[k + 3];
+            }
+            for (; k < k1; ++k) p0 = p0 + ti[k * (TS + 1)] * tc[k];
+            return (p0 + p1) + (p2 + p3);
+        };
         if (lower) {
             if (i > jl && i < w) {
                 // x_i = -(l_ij + sum_{k=j+1}^{i-1} Linv_ik l_kj)
-                x = T[jl * (TS + 1) + i];
-                for (int k = jl + 1; k < i; ++k) x = x + T[k * (TS + 1) + i] * T[jl * (TS + 1) + k];
+                x = T[jl * (TS + 1) + i] + dot(jl + 1, i, jl);
                 x = mk(-x.re, -x.im);
             }
         } else {
             if (i < ju) {
                 // x_i = -(sum_{k=i}^{j-1} Uinv_ik u_kj) / u_jj
-                for (int k = i; k < ju; ++k) x = x + T[k * (TS + 1) + i] * T[ju * (TS + 1) + k];
+                x = dot(i, ju, ju);
                 x = cdiv(mk(-x.re, -x.im), T[ju * (TS + 1) + ju]);
             }
         }
@@ -649,14 +662,17 @@ __global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
     }
 }
 
+// LU of the batch [b0, b0 + nb) of stored blocks, all launches on stream `s`.
 template <class R>
-static vie_status lu_factor(vie_pc pc, hipStream_t s) {
-    const int m = pc->m, nb = pc->nstored;
-    cpx<R> *A = pc->factors.as<cpx<R>>();
-    DevBuf ipiv, linv;
-    VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
-    VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
-    VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
+static cpx<R> *A_of(vie_pc pc) { return pc->factors.as<cpx<R>>(); }
+
+template <class R>
+static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<R> *linv_all, hipStream_t s) {
+    const int m = pc->m;
+    cpx<R> *A = pc->factors.as<cpx<R>>() + (size_t)b0 * m * m;
+    int *ipiv = ipiv_all + (size_t)b0 * m;
+    int *info = pc->info.as<int>() + b0;
+    cpx<R> *linv = linv_all + (size_t)b0 * LU_NB * LU_NB;
     auto panel = [&](int j0, int w) -> vie_status {
         ProfScope ps("lu_panel", s);
         // 16 row lanes (512 threads) when the panel takes <= 32 value VGPRs per thread that
@@ -669,21 +685,19 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
 #define PANEL_CASE(QV)                                                                                     \
     if (qs <= QV) {                                                                                        \
         if (half)                                                                                          \
-            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 16>), dim3(nb), dim3(512), lds, s, A, ipiv.as<int>(), \
-                               pc->info.as<int>(), m, j0, w);                                             \
+            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 16>), dim3(nb), dim3(512), lds, s, A, ipiv, info, m, j0, \
+                               w);                                                                         \
         else                                                                                               \
-            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 32>), dim3(nb), dim3(1024), lds, s, A, ipiv.as<int>(),\
-                               pc->info.as<int>(), m, j0, w);                                             \
+            hipLaunchKernelGGL((k_lu_panel_reg<R, QV, 32>), dim3(nb), dim3(1024), lds, s, A, ipiv, info, m, j0, \
+                               w);                                                                         \
     } else
         if (regs) {
             PANEL_CASE(2) PANEL_CASE(4) PANEL_CASE(8) PANEL_CASE(12) PANEL_CASE(16) PANEL_CASE(24)
             PANEL_CASE(32) PANEL_CASE(40) {
-                hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(),
-                                   m, j0, w);
+                hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv, info, m, j0, w);
             }
         } else {
-            hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv.as<int>(), pc->info.as<int>(), m,
-                               j0, w);
+            hipLaunchKernelGGL(k_lu_panel<R>, dim3(nb), dim3(256), 0, s, A, ipiv, info, m, j0, w);
         }
 #undef PANEL_CASE
         VIE_HIP(hipGetLastError());
@@ -692,11 +706,11 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     auto swap_trsm = [&](int j0, int w, int do_swap, int do_trsm) -> vie_status {
         ProfScope ps("lu_swap_trsm", s);
         if (do_trsm) {
-            hipLaunchKernelGGL(k_lu_linv<R>, dim3(nb), dim3(64), 0, s, (const cpx<R> *)A, linv.as<cpx<R>>(), m, j0, w);
+            hipLaunchKernelGGL(k_lu_linv<R>, dim3(nb), dim3(64), 0, s, (const cpx<R> *)A, linv, m, j0, w);
             VIE_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + SW_CT - 1) / SW_CT, nb), dim3(256), 0, s, A, ipiv.as<int>(),
-                           (const cpx<R> *)linv.as<cpx<R>>(), m, j0, w, do_swap, do_trsm);
+        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + SW_CT - 1) / SW_CT, nb), dim3(256), 0, s, A, ipiv,
+                           (const cpx<R> *)linv, m, j0, w, do_swap, do_trsm);
         VIE_HIP(hipGetLastError());
         return VIE_OK;
     };
@@ -725,6 +739,18 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
         VIE_CHECK(swap_trsm(j1, w2, 0, 1));                      // U12 of the second sub-panel
         VIE_CHECK(update(j1 + w2, m, j1 + w2, m, j0, w1 + w2));   // trailing matrix, K = w1 + w2
     }
+    return VIE_OK;
+}
+
+// Batched LU of every stored block.
+template <class R>
+static vie_status lu_factor(vie_pc pc, hipStream_t s) {
+    const int m = pc->m, nb = pc->nstored;
+    DevBuf ipiv, linv;
+    VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
+    VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
+    VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
+    VIE_CHECK(lu_factor_range<R>(pc, 0, nb, ipiv.as<int>(), linv.as<cpx<R>>(), s));
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());
@@ -732,7 +758,7 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
         size_t lds = sizeof(cpx<R>) * TS * (TS + 1);
         vie_lds_attr((const void *)k_invert_diag<R>, lds);
         ProfScope ps("lu_invert_diag", s);
-        hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(128), lds, s, A, m);
+        hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(128), lds, s, A_of<R>(pc), m);
         VIE_HIP(hipGetLastError());
     }
     VIE_HIP(hipStreamSynchronize(s));
