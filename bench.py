@@ -31,10 +31,17 @@ FP32_PEAK_TFLOPS = 157.3
 METRIC = "time-to-1e-6 residual, mixed vs FP64 solve; matvec HBM GB/s; p50/p99"
 
 
-def kernel_sources_digest():
+# Sources that define each profiled kernel family (the kernel file and the headers it includes):
+# a counter summary applies while these are unchanged.
+KERNEL_SOURCES = {
+    'block_solve': ('block_solve.hip', 'fft_device.h', 'vie_internal.h'),
+}
+
+
+def kernel_sources_digest(kernel='block_solve'):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, 'paper_1903_07884_amd', 'csrc')
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(csrc, f), 'rb').read())
     return h.hexdigest()[:16]
 
@@ -86,7 +93,7 @@ def counter_traffic(kernel, workload_tag):
         if '=' in line and not line.startswith('#'):
             k, v = line.split('=', 1)
             vals[k.strip()] = v.strip()
-    if vals.get('kernel_sources') != kernel_sources_digest():
+    if kernel not in KERNEL_SOURCES or vals.get('kernel_sources') != kernel_sources_digest(kernel):
         return None
     try:
         return float(vals['hbm_bytes_per_launch'])
