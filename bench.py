@@ -101,6 +101,86 @@ def counter_traffic(kernel, workload_tag):
         return None
 
 
+def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, pool=4):
+    """The request scheduler on a seeded stream of catalogue devices (waveguides, Bragg gratings,
+    couplers; lengths 256-1024; cross-sections 16x8-32x8; 1-16 right-hand sides; mixed precision,
+    complex64 factors, 1-level preconditioner).  Each device is visited once to fill the resident
+    cache; a closed burst of n_burst requests measures the capacity; then open-loop Poisson streams
+    at the given fractions of it.  Latency = scheduled arrival -> result on the host."""
+    import queue as _queue
+    import threading
+
+    from paper_1903_07884_amd import workloads as W
+    devs = W.serving_devices()
+    kb = W.k_background()
+    chis = [W.device_chi(d) for d in devs]
+    srcs = [W.device_sources(d, pool, 1000 + i).reshape(pool, -1) for i, d in enumerate(devs)]
+
+    def submit(srv, i, nrhs, k):
+        d = devs[i]
+        e = srcs[i][[(k + j) % pool for j in range(nrhs)]]
+        return srv.submit(d['grid'], d['delta'], kb, chis[i], e, precond=True,
+                          homog='realmean' if d['geometry'] == 'bragg' else 'none', factor_prec=vie.VIE_C64,
+                          mode='mixed', tol=1e-6, restart=50)
+
+    def run(srv, stream):
+        q = _queue.Queue()
+        rec = [None] * len(stream)
+
+        def collect():
+            for _ in range(len(stream)):
+                k, rid, late_ms, nrhs = q.get()
+                _, st, tm = srv.wait(rid)
+                rec[k] = dict(lat=late_ms + tm['total_ms'], queue=tm['queue_ms'], hit=tm['cache_hit'],
+                              merged=tm['merged'], nrhs=nrhs, ok=all(x['status'] == 0 for x in st),
+                              done=time.perf_counter())
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for k, (t, i, nrhs) in enumerate(stream):
+            dt = t0 + t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            late = max(0.0, time.perf_counter() - (t0 + t)) * 1000.0
+            q.put((k, submit(srv, i, nrhs, k), late, nrhs))
+        th.join()
+        span = max(r['done'] for r in rec) - t0
+        lat = np.array([r['lat'] for r in rec])
+        return dict(requests=len(rec), seconds=span, requests_per_s=len(rec) / span,
+                    rhs_per_s=sum(r['nrhs'] for r in rec) / span,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_queue_ms=float(np.mean([r['queue'] for r in rec])),
+                    cache_hit_fraction=float(np.mean([r['hit'] for r in rec])),
+                    mean_merged=float(np.mean([r['merged'] for r in rec])),
+                    all_converged=all(r['ok'] for r in rec))
+
+    vie.autotune(False)
+    vie.trim()
+    srv = vie.Server(workers=workers, max_batch_rhs=64)
+    warm = run(srv, [(0.0, i, 1) for i in range(len(devs))])
+    print('bench: serving cache filled (%d devices, %.2f s)' % (len(devs), warm['seconds']), file=sys.stderr,
+          flush=True)
+    g = np.random.default_rng(seed)
+    burst = run(srv, [(0.0, int(g.integers(0, len(devs))), int(g.integers(1, 17))) for _ in range(n_burst)])
+    cap = burst['requests_per_s']
+    print('bench: serving capacity %.1f requests/s' % cap, file=sys.stderr, flush=True)
+    out = dict(workers=workers, devices=len(devs), capacity_requests_per_s=cap, burst=burst, streams=[])
+    for frac, n in streams:
+        st = run(srv, W.serving_stream(n, frac * cap, seed + int(100 * frac)))
+        st['offered_fraction_of_capacity'] = frac
+        st['offered_requests_per_s'] = frac * cap
+        out['streams'].append(st)
+        print('bench: serving stream at %.1fx capacity: p50 %.1f ms, p99 %.1f ms' % (frac, st['p50_ms'], st['p99_ms']),
+              file=sys.stderr, flush=True)
+    out['server'] = srv.info()
+    srv.close()
+    out['mix'] = ('catalogue of %d devices (waveguide / Bragg / coupler; n_x 256-1024; cross-sections 16x8-32x8; '
+                  '25 nm), 1-16 RHS per request, mixed precision with complex64 factors, GMRES(50) to 1e-6'
+                  % len(devs))
+    return out
+
+
 def lu_flops(m, nblocks, nb=32):
     """Real flops of the trailing updates of a right-looking LU (8 per complex multiply-add)."""
     f = 0
@@ -221,6 +301,10 @@ def main():
                     help='default launch parameters (otherwise the warm-up step autotunes them)')
     ap.add_argument('--copy-probe', type=int, default=0,
                     help='also run one plain device copy of this many bytes (calibrates HBM counters)')
+    ap.add_argument('--no-serving', action='store_true', help='skip the short serving-stream measurement')
+    ap.add_argument('--serve', action='store_true',
+                    help='only the serving stream: Poisson arrivals at 0.5, 0.8 and 1.0 of the measured '
+                         'capacity, 1000 requests each (one JSON line)')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU sharding is '
@@ -234,6 +318,19 @@ def main():
     vie.load()
     dev = torch.device('cuda:0')
     torch.cuda.set_device(dev)
+    if args.serve:
+        t0 = time.perf_counter()
+        sv = serving_bench(vie, n_burst=60, streams=((0.5, 1000), (0.8, 1000), (1.0, 1000)))
+        t1 = time.perf_counter()
+        s08 = [x for x in sv['streams'] if x['offered_fraction_of_capacity'] == 0.8][0]
+        print(json.dumps({
+            'metric': 'serving latency p50/p99 (arrival -> result) and throughput on a seeded request stream',
+            'value': s08['requests_per_s'], 'unit': 'requests/s', 'n_gpus': 1, 'steps': 1, 'warmup': 0,
+            'ms_per_step': 1000.0 * (t1 - t0), 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
+            'dtype': 'c64+f64', 'data': 'synthetic',
+            'config': {'workload': 'serving stream: ' + sv['mix'], 'workers': sv['workers']},
+            'p50_ms': s08['p50_ms'], 'p99_ms': s08['p99_ms'], 'serving': sv}))
+        return
     cfg = W.CONFIGS[args.config]
     grid, delta = cfg['grid'], cfg['delta']
     nx, ny, nz = grid
@@ -424,6 +521,8 @@ def main():
         'roofline': roof,
         'kernel_sources': kernel_sources_digest(),
     }
+    if not args.no_serving and not args.copy_probe:
+        out['serving'] = serving_bench(vie)
     if not args.no_cpu_baseline and args.config == 2:
         out['cpu_baseline'] = cpu_baseline(cfg, last['iters'], last['restarts'])
     print(json.dumps(out))

@@ -59,7 +59,8 @@ typedef enum {
     VIE_EOOM = -2,         /* device allocation failed                        */
     VIE_EDEVICE = -3,      /* HIP runtime error                               */
     VIE_ESINGULAR = -4,    /* a preconditioner block has a zero pivot         */
-    VIE_ENONFINITE = -5    /* non-finite input or residual                    */
+    VIE_ENONFINITE = -5,   /* non-finite input or residual                    */
+    VIE_EBUDGET = -6       /* request larger than the server's device-memory budget */
 } vie_status;
 
 /* ---- operator ------------------------------------------------------------ */
@@ -195,6 +196,69 @@ typedef struct {
  * stats: HOST array of nrhs entries.  Synchronises `stream`. */
 vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
                      const vie_solve_opts *opts, vie_solve_stats *stats, void *stream);
+
+/* ---- serving ------------------------------------------------------------------
+ * A request scheduler for many solves of different devices on one GPU (the solver of
+ * Sec. 1 applied to a stream of devices; the scheduling is this library's).  Requests are
+ * queued on submit and admitted while their device-memory footprint fits the budget;
+ * operators and preconditioners stay resident in a cache keyed by the device (grid, voxel
+ * size, wavenumber, a hash of the contrast) and the preconditioner options, evicted least
+ * recently used when memory is needed; each worker thread owns a HIP stream, so admitted
+ * solves run side by side on the device; requests waiting for the same device, options and
+ * solver settings are merged into one multi-RHS solve.  A result does not depend on what it
+ * was solved beside: columns of a merged solve equal the single solves (the batched GMRES
+ * runs every right-hand side on its own).  Thread-safe: any thread may submit and wait. */
+typedef struct vie_server_s *vie_server;
+
+typedef struct {
+    int32_t workers;        /* concurrent solves, one HIP stream each (0: 4; at most 16) */
+    int32_t max_batch_rhs;  /* merge queued requests of one device up to this many right-hand
+                               sides per solve (0: 64; 1: no merging) */
+    uint64_t hbm_budget;    /* device bytes the server may commit (0: 90% of the free memory at
+                               vie_server_create); admission uses the vie_footprint bounds */
+} vie_server_opts;
+
+typedef struct {
+    int32_t grid[3];
+    double voxel_size;
+    double k_background;
+    const double *chi;      /* HOST, 2*N doubles as in vie_create; copied by vie_server_submit */
+    const double *e_inc;    /* HOST, nrhs*6*N doubles: incident fields [nrhs][3][nz][ny][nx]
+                               interleaved complex (b = M e_inc is formed on the device); copied */
+    int32_t nrhs;
+    int32_t precond;        /* 0: unpreconditioned; 1: preconditioner built with `pc` */
+    vie_pc_opts pc;         /* boxes (if any) copied */
+    vie_solve_opts solve;   /* x0_given must be 0 */
+} vie_request;
+
+typedef struct {
+    double queue_ms;        /* submit -> start of its solve */
+    double run_ms;          /* start -> result on the host (build or cache lookup, solve, copy) */
+    double total_ms;        /* submit -> result */
+    int32_t cache_hit;      /* operator and preconditioner came from the resident cache */
+    int32_t merged;         /* requests solved in the same multi-RHS solve, itself included */
+} vie_request_times;
+
+typedef struct {
+    int64_t submitted, completed, solves, cache_hits, evictions;
+    int32_t cached_entries, queued, running;
+    uint64_t committed_bytes, peak_committed_bytes, budget_bytes;
+} vie_server_info;
+
+vie_status vie_server_create(const vie_server_opts *opts, vie_server *out);
+/* Queue a request; returns at once with its id.  x_out (HOST, nrhs*6*N doubles) and stats_out
+ * (HOST, nrhs entries) are written when it completes and must stay valid until
+ * vie_server_wait returns for it.  VIE_EARG for invalid arguments, VIE_EBUDGET when the
+ * request alone exceeds the budget. */
+vie_status vie_server_submit(vie_server srv, const vie_request *req, double *x_out,
+                             vie_solve_stats *stats_out, int64_t *id);
+/* Block until request `id` completes; returns its status (VIE_OK, VIE_NOT_CONVERGED or the
+ * error of its build or solve) and, if times != NULL, its timings.  Each id is waited once. */
+vie_status vie_server_wait(vie_server srv, int64_t id, vie_request_times *times);
+vie_status vie_server_query(vie_server srv, int64_t id, int32_t *done);
+vie_status vie_server_info_get(vie_server srv, vie_server_info *info);
+/* Finish queued and running requests, free the cache and the server. */
+vie_status vie_server_destroy(vie_server srv);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 

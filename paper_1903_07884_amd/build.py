@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libvie.so')
-SOURCES = ['api.cpp', 'fft_host.cpp', 'profile.cpp', 'tune.cpp', 'generator.hip', 'matvec.hip', 'precond.hip', 'block_solve.hip', 'krylov.hip']
+SOURCES = ['api.cpp', 'fft_host.cpp', 'profile.cpp', 'tune.cpp', 'generator.hip', 'matvec.hip', 'precond.hip', 'block_solve.hip', 'krylov.hip', 'serve.cpp']
 
 
 def hipcc():

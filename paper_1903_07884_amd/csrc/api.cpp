@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, handle ownership, orchestration.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -241,18 +242,29 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     return VIE_OK;
 }
 
-extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t nrhs, const vie_solve_opts *so,
-                                   uint64_t *bytes) {
-    if (!op || !bytes) return arg_error("vie_footprint: NULL argument");
-    if (nrhs < 1) return arg_error("vie_footprint: nrhs must be >= 1");
-    const uint64_t N = (uint64_t)op->N, R = (uint64_t)nrhs, n3 = 3 * N;
-    const uint64_t lines = 3ULL * op->ny * op->nz * R;
-    // operator: contrast, generator, kernel transforms (held) and the matvec scratch
-    uint64_t b = op->M64.bytes + op->M32.bytes + op->gen.bytes + op->khat64.bytes + op->khat32.bytes;
-    b += 6ULL * 16 * op->Px * op->Py * op->Pz;  // the circulant embedding transformed during vie_create
-    uint64_t mv_scratch = sizeof(c128) * lines * (uint64_t)op->Px;
-    uint64_t pc_bytes = 0, apply_scratch = 0;
-    bool mixed_pc = false;
+// Device bytes an operator of this grid holds (contrast, generator, kernel transforms) and the
+// transient of its creation (the transformed circulant embedding and the contrast upload),
+// computed from the grid alone (the sizes vie_create allocates).
+static void op_bytes_estimate(int nx, int ny, int nz, bool c64, uint64_t *held, uint64_t *transient, int *Px_out) {
+    const uint64_t N = (uint64_t)nx * ny * nz;
+    const int Px = fft_good_length(2 * nx - 1), Py = fft_good_length(2 * ny - 1), Pz = fft_good_length(2 * nz - 1);
+    const uint64_t Hx = Px / 2 + 1, Hy = Py / 2 + 1, Hz = Pz / 2 + 1;
+    // (x, y) transform with z offsets, or the full octant: the larger of the two
+    const uint64_t kh = Hx * Hy * std::max<uint64_t>((uint64_t)nz, Hz) * 6;
+    *held = 16 * N + 8 * N + 16 * 6 * N + kh * 16 + (c64 ? kh * 8 : 0);
+    *transient = 6ULL * 16 * Px * Py * Pz + 16 * N;
+    *Px_out = Px;
+}
+
+// Footprint of the preconditioner (held, with its setup temporaries), its apply scratch, the
+// matvec scratch and the solve workspace for nrhs right-hand sides.
+static vie_status footprint_parts(int nx, int ny, int nz, int Px, const vie_pc_opts *pco, int32_t nrhs,
+                                  const vie_solve_opts *so, uint64_t *mv_scratch, uint64_t *pc_held,
+                                  uint64_t *apply_scratch, uint64_t *solve_bytes) {
+    const uint64_t N = (uint64_t)nx * ny * nz, R = (uint64_t)nrhs, n3 = 3 * N;
+    const uint64_t lines = 3ULL * ny * nz * R;
+    *mv_scratch = sizeof(c128) * lines * (uint64_t)Px;
+    *pc_held = *apply_scratch = *solve_bytes = 0;
     if (pco) {
         const vie_pc_opts &o = *pco;
         if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
@@ -260,35 +272,56 @@ extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t n
         if (o.nboxes < 0 || (o.nboxes > 0 && !o.boxes)) return arg_error("vie_footprint: bad boxes");
         const int *B = o.nboxes ? o.boxes : nullptr;
         const uint64_t nb = o.nboxes ? o.nboxes : 1;
-        const uint64_t bx = B ? B[3] : op->nx, by = B ? B[4] : op->ny, bz = B ? B[5] : op->nz;
+        const uint64_t bx = B ? B[3] : nx, by = B ? B[4] : ny, bz = B ? B[5] : nz;
         if (bx < 1 || by < 1 || bz < 1) return arg_error("vie_footprint: bad box shape");
         const uint64_t m = 3 * by * bz, modes = nb * bx;
         const uint64_t fesz = o.factor_prec == VIE_C128 ? 16 : o.factor_prec == VIE_BF16C ? 4 : 8;
         const uint64_t vesz = o.factor_prec == VIE_C128 ? 16 : 8;  // vector / factorisation precision
-        mixed_pc = o.factor_prec != VIE_C128;
         const uint64_t table = modes / nb * 6 * (2 * by - 1) * (2 * bz - 1);
-        pc_bytes = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
-        if (o.factor_prec == VIE_BF16C) pc_bytes += modes * m * m * 8;  // complex-float factorisation copy
-        pc_bytes += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;  // Chan table, LU workspace
-        if (o.refine_steps || !o.keep_zero_rows) pc_bytes += table * 8 + nb * by * bz * 8;
-        if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pc_bytes += table * 16 + nb * by * bz * 16;
-        pc_bytes += m * 4 + 64;  // row order, coupling flag
+        uint64_t pcb = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
+        if (o.factor_prec == VIE_BF16C) pcb += modes * m * m * 8;        // complex-float factorisation copy
+        pcb += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;       // Chan table, LU workspace
+        if (o.refine_steps || !o.keep_zero_rows) pcb += table * 8 + nb * by * bz * 8;
+        if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pcb += table * 16 + nb * by * bz * 16;
+        pcb += m * 4 + 64;  // row order, coupling flag
+        *pc_held = pcb;
         // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
         const uint64_t cols = modes * R;
         const uint64_t wide = (cols + 64 * modes) * m * vesz;
-        apply_scratch = R * nb * m * bx * vesz + wide * (o.refine_steps ? 2 : 1);
+        *apply_scratch = R * nb * m * bx * vesz + wide * (o.refine_steps ? 2 : 1);
     }
-    uint64_t solve_bytes = 0;
     if (so) {
         if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
         const uint64_t rs = (uint64_t)so->restart;
         const bool mixed = so->mode == VIE_MODE_MIXED;
         const uint64_t vb = mixed ? 8 : 16;  // basis precision
-        solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * 256 * (rs + 2) +
-                      (mixed ? 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
-        (void)mixed_pc;
+        *solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * 256 * (rs + 2) +
+                       (mixed ? 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
     }
-    *bytes = b + mv_scratch + pc_bytes + apply_scratch + solve_bytes;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t nrhs, const vie_solve_opts *so,
+                                   uint64_t *bytes) {
+    if (!op || !bytes) return arg_error("vie_footprint: NULL argument");
+    if (nrhs < 1) return arg_error("vie_footprint: nrhs must be >= 1");
+    // operator: contrast, generator, kernel transforms (held) and the matvec scratch
+    uint64_t b = op->M64.bytes + op->M32.bytes + op->gen.bytes + op->khat64.bytes + op->khat32.bytes;
+    b += 6ULL * 16 * op->Px * op->Py * op->Pz;  // the circulant embedding transformed during vie_create
+    uint64_t mv, pcb, ap, sb;
+    VIE_CHECK(footprint_parts(op->nx, op->ny, op->nz, op->Px, pco, nrhs, so, &mv, &pcb, &ap, &sb));
+    *bytes = b + mv + pcb + ap + sb;
+    return VIE_OK;
+}
+
+vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts *pco, int32_t nrhs,
+                             const vie_solve_opts *so, uint64_t *resident, uint64_t *run) {
+    uint64_t held, transient, mv, pcb, ap, sb;
+    int Px;
+    op_bytes_estimate(grid[0], grid[1], grid[2], c64, &held, &transient, &Px);
+    VIE_CHECK(footprint_parts(grid[0], grid[1], grid[2], Px, pco, nrhs, so, &mv, &pcb, &ap, &sb));
+    *resident = held + mv + pcb + ap;           // kept by a cached operator + preconditioner
+    *run = sb + transient + 2 * 16 * 3ULL * grid[0] * grid[1] * grid[2] * nrhs;  // workspace, build, e/b
     return VIE_OK;
 }
 

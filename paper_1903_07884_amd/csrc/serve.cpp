@@ -1,0 +1,477 @@
+// Request scheduler for many solves on one GPU (the serving part of the C ABI).
+//
+// Submitted requests wait in a FIFO queue.  A worker thread (one HIP stream each) takes the
+// first queued request that can be admitted: its operator and preconditioner are found idle
+// in the resident cache, or the bytes to build them fit the budget after evicting idle cache
+// entries (least recently used first); the solve workspace must fit as well.  Later queued
+// requests with the same device, preconditioner options and solver settings join it in one
+// multi-RHS solve.  A request that has been passed over by later ones several times blocks
+// further overtaking until it is admitted.  After the solve the operator and preconditioner
+// return to the cache, the results are copied to the callers' host buffers and the waiters
+// are woken.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "vie_internal.h"
+
+namespace {
+using Clock = std::chrono::steady_clock;
+
+#define SERVE_MAX_OVERTAKE 8
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ULL) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+struct Req {
+    int64_t id = 0;
+    int32_t grid[3] = {0, 0, 0};
+    double delta = 0, kb = 0;
+    std::vector<double> chi, e;
+    int nrhs = 0;
+    int precond = 0;
+    vie_pc_opts pco{};
+    std::vector<int32_t> boxes;
+    vie_solve_opts so{};
+    double *x_out = nullptr;
+    vie_solve_stats *st_out = nullptr;
+    std::string key;        // device + preconditioner options: the cache key
+    std::string batch_key;  // key + solver settings: requests that may share one solve
+    Clock::time_point t_submit, t_start, t_end;
+    vie_status status = VIE_OK;
+    bool done = false;
+    int cache_hit = 0, merged = 1, overtaken = 0;
+    std::string err;  // message of a failed build or solve
+};
+
+struct Entry {
+    std::string key;
+    vie_op op = nullptr;
+    vie_pc pc = nullptr;
+    uint64_t bytes = 0;  // resident bytes accounted for this entry
+    bool in_use = false;
+    uint64_t last = 0;
+};
+
+// One admitted solve: the requests merged into it and its accounting.
+struct Batch {
+    std::vector<Req *> reqs;
+    Entry *entry = nullptr;  // cache entry in use (nullptr: build a new one)
+    int R = 0;
+    uint64_t resident = 0, run = 0;  // bytes committed for the entry (when new) and the run
+};
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+}  // namespace
+
+struct vie_server_s {
+    int workers_n = 4, max_rhs = 64;
+    uint64_t budget = 0;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> queue;
+    std::map<int64_t, Req *> reqs;
+    std::list<Entry *> cache;
+    uint64_t committed = 0, peak = 0, tick = 0;
+    int64_t next_id = 1;
+    bool stop = false;
+    int running = 0;
+    std::vector<std::thread> threads;
+    int64_t n_submitted = 0, n_completed = 0, n_solves = 0, n_hits = 0, n_evicted = 0;
+};
+
+namespace {
+void commit(vie_server srv, uint64_t b) {
+    srv->committed += b;
+    srv->peak = std::max(srv->peak, srv->committed);
+}
+
+void destroy_entry(Entry *e) {
+    if (e->pc) precond_destroy(e->pc);
+    if (e->op) vie_destroy(e->op);
+    delete e;
+}
+
+// Free idle cache entries (least recently used first, never `keep`) until `need` more bytes
+// fit; true if they do.  Called with the lock held.
+bool make_room(vie_server srv, uint64_t need, const Entry *keep) {
+    while (srv->committed + need > srv->budget) {
+        Entry *victim = nullptr;
+        for (Entry *e : srv->cache)
+            if (!e->in_use && e != keep && (!victim || e->last < victim->last)) victim = e;
+        if (!victim) return false;
+        srv->cache.remove(victim);
+        srv->committed -= victim->bytes;
+        destroy_entry(victim);
+        srv->n_evicted++;
+    }
+    return true;
+}
+
+// Admit the first admissible queued request (with the requests merged into it).  Lock held.
+bool pick(vie_server srv, Batch *b) {
+    for (size_t qi = 0; qi < srv->queue.size(); ++qi) {
+        Req *r = srv->queue[qi];
+        // merge later requests with the same batch key
+        std::vector<size_t> idx{qi};
+        int R = r->nrhs;
+        for (size_t qj = qi + 1; qj < srv->queue.size(); ++qj) {
+            Req *o = srv->queue[qj];
+            if (o->batch_key == r->batch_key && R + o->nrhs <= srv->max_rhs) {
+                idx.push_back(qj);
+                R += o->nrhs;
+            }
+        }
+        Entry *idle = nullptr;
+        for (Entry *e : srv->cache)
+            if (!e->in_use && e->key == r->key && (!idle || e->last > idle->last)) idle = e;
+        uint64_t resident = 0, run = 0;
+        const bool mixed = r->so.mode == VIE_MODE_MIXED;
+        if (request_footprint(r->grid, mixed, r->precond ? &r->pco : nullptr, R, &r->so, &resident, &run) != VIE_OK)
+            resident = run = 0;  // arguments were checked on submit
+        // a cached entry grows when it serves more right-hand sides than it was sized for
+        const uint64_t need = run + (idle ? (resident > idle->bytes ? resident - idle->bytes : 0) : resident);
+        if (make_room(srv, need, idle)) {
+            commit(srv, need);
+            b->reqs.clear();
+            for (size_t k : idx) b->reqs.push_back(srv->queue[k]);
+            for (size_t k = idx.size(); k-- > 0;) srv->queue.erase(srv->queue.begin() + (long)idx[k]);
+            for (size_t k = 0; k < qi; ++k) srv->queue[k]->overtaken++;
+            b->entry = idle;
+            if (idle) {
+                idle->in_use = true;
+                idle->bytes = std::max(idle->bytes, resident);
+            }
+            b->R = R;
+            b->resident = resident;
+            b->run = run;
+            return true;
+        }
+        if (r->overtaken >= SERVE_MAX_OVERTAKE) return false;  // the head waits for memory
+    }
+    return false;
+}
+
+// Build (or take from the cache) the operator and preconditioner, solve the merged right-hand
+// sides, copy each request's columns and statistics back.  Runs without the lock.
+vie_status run_batch(vie_server srv, Batch *b, hipStream_t s, vie_op *op_out, vie_pc *pc_out) {
+    (void)srv;
+    Req *r0 = b->reqs[0];
+    const long long N = (long long)r0->grid[0] * r0->grid[1] * r0->grid[2];
+    const long long n3 = 3 * N;
+    vie_op op = b->entry ? b->entry->op : nullptr;
+    vie_pc pc = b->entry ? b->entry->pc : nullptr;
+    if (!op) {
+        vie_create_opts co{};
+        co.build_c64 = r0->so.mode == VIE_MODE_MIXED;
+        VIE_CHECK(vie_create(r0->grid, r0->delta, r0->kb, r0->chi.data(), &co, s, &op));
+        *op_out = op;
+        if (r0->precond) VIE_CHECK(precond_setup(op, &r0->pco, s, &pc));
+        *pc_out = pc;
+    }
+    DevBuf e, bb, x;
+    VIE_CHECK(e.ensure(sizeof(c128) * n3 * b->R));
+    VIE_CHECK(bb.ensure(sizeof(c128) * n3 * b->R));
+    VIE_CHECK(x.ensure(sizeof(c128) * n3 * b->R));
+    long long off = 0;
+    for (Req *r : b->reqs) {
+        VIE_HIP(hipMemcpyAsync(e.as<c128>() + off, r->e.data(), sizeof(c128) * n3 * r->nrhs, hipMemcpyHostToDevice, s));
+        off += n3 * r->nrhs;
+    }
+    VIE_CHECK(vie_rhs(op, e.p, bb.p, b->R, s));
+    VIE_HIP(hipMemsetAsync(x.p, 0, sizeof(c128) * n3 * b->R, s));
+    std::vector<vie_solve_stats> st(b->R);
+    vie_solve_opts so = r0->so;
+    so.x0_given = 0;
+    const vie_status ss = vie_solve(op, pc, bb.p, x.p, b->R, &so, st.data(), s);
+    if (ss < 0) return ss;
+    off = 0;
+    int col = 0;
+    for (Req *r : b->reqs) {
+        VIE_HIP(hipMemcpyAsync(r->x_out, x.as<c128>() + off, sizeof(c128) * n3 * r->nrhs, hipMemcpyDeviceToHost, s));
+        off += n3 * r->nrhs;
+        r->status = VIE_OK;
+        for (int i = 0; i < r->nrhs; ++i) {
+            r->st_out[i] = st[col + i];
+            if (st[col + i].status != VIE_OK) r->status = VIE_NOT_CONVERGED;
+        }
+        col += r->nrhs;
+    }
+    VIE_HIP(hipStreamSynchronize(s));
+    return VIE_OK;
+}
+
+void worker(vie_server srv) {
+    (void)hipSetDevice(srv->device);
+    hipStream_t s = nullptr;
+    const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    for (;;) {
+        Batch b;
+        while (!pick(srv, &b)) {
+            if (srv->stop && srv->queue.empty()) break;
+            srv->cv_work.wait(lk);
+        }
+        if (b.reqs.empty()) break;
+        srv->running++;
+        lk.unlock();
+        const Clock::time_point t0 = Clock::now();
+        for (Req *r : b.reqs) r->t_start = t0;
+        vie_op op = nullptr;
+        vie_pc pc = nullptr;
+        vie_status st = have_stream ? run_batch(srv, &b, s, &op, &pc) : VIE_EDEVICE;
+        if (!have_stream) vie_set_error("vie_server: hipStreamCreate failed");
+        const std::string err = st < 0 ? std::string(vie_last_error()) : std::string();
+        const Clock::time_point t1 = Clock::now();
+        lk.lock();
+        srv->running--;
+        srv->committed -= b.run;
+        srv->n_solves++;
+        if (b.entry) {
+            b.entry->in_use = false;
+            b.entry->last = ++srv->tick;
+            srv->n_hits += (int64_t)b.reqs.size();
+        } else if (st >= 0) {
+            Entry *ne = new Entry();
+            ne->key = b.reqs[0]->key;
+            ne->op = op;
+            ne->pc = pc;
+            ne->bytes = b.resident;
+            ne->last = ++srv->tick;
+            srv->cache.push_back(ne);
+        } else {
+            srv->committed -= b.resident;
+            if (pc) precond_destroy(pc);
+            if (op) vie_destroy(op);
+        }
+        for (Req *r : b.reqs) {
+            r->t_end = t1;
+            r->cache_hit = b.entry != nullptr;
+            r->merged = (int)b.reqs.size();
+            if (st < 0) {
+                r->status = st;
+                r->err = err;
+            }
+            r->done = true;
+            srv->n_completed++;
+        }
+        srv->cv_done.notify_all();
+        srv->cv_work.notify_all();
+    }
+    lk.unlock();
+    if (have_stream) (void)hipStreamDestroy(s);
+}
+}  // namespace
+
+extern "C" vie_status vie_server_create(const vie_server_opts *opts, vie_server *out) {
+    if (!out) {
+        vie_set_error("vie_server_create: out is NULL");
+        return VIE_EARG;
+    }
+    *out = nullptr;
+    vie_server_opts o{};
+    if (opts) o = *opts;
+    if (o.workers < 0 || o.workers > 16 || o.max_batch_rhs < 0) {
+        vie_set_error("vie_server_create: workers must be in [0, 16] and max_batch_rhs >= 0");
+        return VIE_EARG;
+    }
+    vie_server srv = new (std::nothrow) vie_server_s();
+    if (!srv) return VIE_EOOM;
+    srv->workers_n = o.workers ? o.workers : 4;
+    srv->max_rhs = o.max_batch_rhs ? o.max_batch_rhs : 64;
+    if (hipGetDevice(&srv->device) != hipSuccess) {
+        delete srv;
+        vie_set_error("vie_server_create: no HIP device");
+        return VIE_EDEVICE;
+    }
+    srv->budget = o.hbm_budget;
+    if (!srv->budget) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete srv;
+            vie_set_error("vie_server_create: hipMemGetInfo failed");
+            return VIE_EDEVICE;
+        }
+        srv->budget = (uint64_t)(0.9 * (double)fr);
+    }
+    for (int i = 0; i < srv->workers_n; ++i) srv->threads.emplace_back(worker, srv);
+    *out = srv;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, double *x_out,
+                                        vie_solve_stats *stats_out, int64_t *id) {
+    if (!srv || !req || !x_out || !stats_out || !id) {
+        vie_set_error("vie_server_submit: NULL argument");
+        return VIE_EARG;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (req->grid[a] < 1) {
+            vie_set_error("vie_server_submit: every grid dimension must be >= 1");
+            return VIE_EARG;
+        }
+    if (!req->chi || !req->e_inc || req->nrhs < 1) {
+        vie_set_error("vie_server_submit: chi and e_inc are required and nrhs must be >= 1");
+        return VIE_EARG;
+    }
+    if (req->solve.x0_given) {
+        vie_set_error("vie_server_submit: requests start from x = 0 (x0_given must be 0)");
+        return VIE_EARG;
+    }
+    if (req->precond && req->pc.nboxes > 0 && !req->pc.boxes) {
+        vie_set_error("vie_server_submit: pc.boxes is NULL");
+        return VIE_EARG;
+    }
+    const long long N = (long long)req->grid[0] * req->grid[1] * req->grid[2];
+    Req *r = new (std::nothrow) Req();
+    if (!r) return VIE_EOOM;
+    std::copy(req->grid, req->grid + 3, r->grid);
+    r->delta = req->voxel_size;
+    r->kb = req->k_background;
+    r->chi.assign(req->chi, req->chi + 2 * N);
+    r->e.assign(req->e_inc, req->e_inc + 6 * N * req->nrhs);
+    r->nrhs = req->nrhs;
+    r->precond = req->precond != 0;
+    r->pco = req->pc;
+    if (r->precond && req->pc.nboxes > 0) {
+        r->boxes.assign(req->pc.boxes, req->pc.boxes + 6 * req->pc.nboxes);
+        r->pco.boxes = r->boxes.data();
+    }
+    r->so = req->solve;
+    r->x_out = x_out;
+    r->st_out = stats_out;
+    uint64_t resident = 0, run = 0;
+    const vie_status fs = request_footprint(r->grid, r->so.mode == VIE_MODE_MIXED, r->precond ? &r->pco : nullptr,
+                                            r->nrhs, &r->so, &resident, &run);
+    if (fs < 0) {
+        delete r;
+        return fs;
+    }
+    if (resident + run > srv->budget) {
+        delete r;
+        vie_set_error("vie_server_submit: the request needs " + std::to_string(resident + run) +
+                      " device bytes, above the budget of " + std::to_string(srv->budget));
+        return VIE_EBUDGET;
+    }
+    char buf[256];
+    const uint64_t hchi = fnv1a(r->chi.data(), sizeof(double) * r->chi.size());
+    snprintf(buf, sizeof buf, "%dx%dx%d|%a|%a|%016llx|%d|%d", r->grid[0], r->grid[1], r->grid[2], r->delta, r->kb,
+             (unsigned long long)hchi, r->precond, r->so.mode == VIE_MODE_MIXED);
+    r->key = buf;
+    if (r->precond) {
+        const vie_pc_opts &p = r->pco;
+        snprintf(buf, sizeof buf, "|pc %d %d %016llx %d %a %d %d %d %d", p.homog, p.nboxes,
+                 (unsigned long long)fnv1a(r->boxes.data(), sizeof(int32_t) * r->boxes.size()), p.reduce,
+                 p.reduce ? p.reduce_tol : 0.0, p.factor_prec, p.proxy, p.refine_steps, p.keep_zero_rows);
+        r->key += buf;
+    }
+    snprintf(buf, sizeof buf, "|so %a %d %d %d", r->so.tol, r->so.restart, r->so.maxit, r->so.mode);
+    r->batch_key = r->key + buf;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) {
+        delete r;
+        vie_set_error("vie_server_submit: the server is shutting down");
+        return VIE_EARG;
+    }
+    r->id = srv->next_id++;
+    r->t_submit = Clock::now();
+    srv->queue.push_back(r);
+    srv->reqs[r->id] = r;
+    srv->n_submitted++;
+    *id = r->id;
+    srv->cv_work.notify_one();
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_server_wait(vie_server srv, int64_t id, vie_request_times *times) {
+    if (!srv) {
+        vie_set_error("vie_server_wait: NULL server");
+        return VIE_EARG;
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) {
+        vie_set_error("vie_server_wait: unknown request id " + std::to_string(id));
+        return VIE_EARG;
+    }
+    Req *r = it->second;
+    srv->cv_done.wait(lk, [&] { return r->done; });
+    if (times) {
+        times->queue_ms = ms_between(r->t_submit, r->t_start);
+        times->run_ms = ms_between(r->t_start, r->t_end);
+        times->total_ms = ms_between(r->t_submit, r->t_end);
+        times->cache_hit = r->cache_hit;
+        times->merged = r->merged;
+    }
+    const vie_status st = r->status;
+    if (st < 0) vie_set_error("vie_server_wait: request " + std::to_string(id) + " failed: " + r->err);
+    srv->reqs.erase(it);
+    delete r;
+    return st;
+}
+
+extern "C" vie_status vie_server_query(vie_server srv, int64_t id, int32_t *done) {
+    if (!srv || !done) {
+        vie_set_error("vie_server_query: NULL argument");
+        return VIE_EARG;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) {
+        vie_set_error("vie_server_query: unknown request id " + std::to_string(id));
+        return VIE_EARG;
+    }
+    *done = it->second->done ? 1 : 0;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_server_info_get(vie_server srv, vie_server_info *info) {
+    if (!srv || !info) {
+        vie_set_error("vie_server_info_get: NULL argument");
+        return VIE_EARG;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    info->submitted = srv->n_submitted;
+    info->completed = srv->n_completed;
+    info->solves = srv->n_solves;
+    info->cache_hits = srv->n_hits;
+    info->evictions = srv->n_evicted;
+    info->cached_entries = (int32_t)srv->cache.size();
+    info->queued = (int32_t)srv->queue.size();
+    info->running = srv->running;
+    info->committed_bytes = srv->committed;
+    info->peak_committed_bytes = srv->peak;
+    info->budget_bytes = srv->budget;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_server_destroy(vie_server srv) {
+    if (!srv) return VIE_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    for (auto &t : srv->threads) t.join();
+    for (Entry *e : srv->cache) destroy_entry(e);
+    for (auto &kv : srv->reqs) delete kv.second;
+    delete srv;
+    return VIE_OK;
+}

@@ -253,6 +253,10 @@ vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
 vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s);
 // precond.hip
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
+// api.cpp: device bytes of a request before its operator exists: what a cached operator +
+// preconditioner keep (resident) and what one solve of nrhs right-hand sides adds (run)
+vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts *pco, int32_t nrhs,
+                             const vie_solve_opts *so, uint64_t *resident, uint64_t *run);
 vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s);
 // block_solve.hip: the per-mode block solves, in place in the apply work buffer
 vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s);

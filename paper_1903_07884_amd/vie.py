@@ -17,14 +17,15 @@ LIB_PATH = os.path.join(_HERE, 'libvie.so')
 VIE_C128, VIE_C64, VIE_BF16C = 0, 1, 2
 VIE_OK, VIE_NOT_CONVERGED = 0, 1
 STATUS = {0: 'VIE_OK', 1: 'VIE_NOT_CONVERGED', -1: 'VIE_EARG', -2: 'VIE_EOOM', -3: 'VIE_EDEVICE',
-          -4: 'VIE_ESINGULAR', -5: 'VIE_ENONFINITE'}
+          -4: 'VIE_ESINGULAR', -5: 'VIE_ENONFINITE', -6: 'VIE_EBUDGET'}
 HOMOG = {'none': 0, 'mode': 1, 'mean': 2, 'realmean': 3}
 MODE = {'fp64': 0, 'mixed': 1}
 
 EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
            'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
            'vie_profile_kernel', 'vie_profile_end', 'vie_last_error', 'vie_footprint', 'vie_autotune',
-           'vie_autotune_report', 'vie_device_bytes', 'vie_trim')
+           'vie_autotune_report', 'vie_device_bytes', 'vie_trim', 'vie_server_create', 'vie_server_submit',
+           'vie_server_wait', 'vie_server_query', 'vie_server_info_get', 'vie_server_destroy')
 
 
 class VieError(RuntimeError):
@@ -52,6 +53,28 @@ class PcInfo(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('restart', ctypes.c_int32), ('maxit', ctypes.c_int32),
                 ('mode', ctypes.c_int32), ('x0_given', ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [('workers', ctypes.c_int32), ('max_batch_rhs', ctypes.c_int32), ('hbm_budget', ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [('grid', ctypes.c_int32 * 3), ('voxel_size', ctypes.c_double), ('k_background', ctypes.c_double),
+                ('chi', ctypes.c_void_p), ('e_inc', ctypes.c_void_p), ('nrhs', ctypes.c_int32),
+                ('precond', ctypes.c_int32), ('pc', PcOpts), ('solve', SolveOpts)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [('queue_ms', ctypes.c_double), ('run_ms', ctypes.c_double), ('total_ms', ctypes.c_double),
+                ('cache_hit', ctypes.c_int32), ('merged', ctypes.c_int32)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [('submitted', ctypes.c_int64), ('completed', ctypes.c_int64), ('solves', ctypes.c_int64),
+                ('cache_hits', ctypes.c_int64), ('evictions', ctypes.c_int64), ('cached_entries', ctypes.c_int32),
+                ('queued', ctypes.c_int32), ('running', ctypes.c_int32), ('committed_bytes', ctypes.c_uint64),
+                ('peak_committed_bytes', ctypes.c_uint64), ('budget_bytes', ctypes.c_uint64)]
 
 
 class SolveStats(ctypes.Structure):
@@ -94,6 +117,13 @@ def load(path=None):
     lib.vie_footprint.argtypes = [vp, ctypes.POINTER(PcOpts), i32, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(ctypes.c_uint64)]
     lib.vie_autotune_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.vie_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.vie_server_submit.argtypes = [vp, ctypes.POINTER(Request), vp, ctypes.POINTER(SolveStats),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.vie_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(RequestTimes)]
+    lib.vie_server_query.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(i32)]
+    lib.vie_server_info_get.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+    lib.vie_server_destroy.argtypes = [vp]
     for name in EXPORTS:
         getattr(lib, name).restype = ctypes.c_int
     lib.vie_last_error.restype = ctypes.c_char_p
@@ -307,3 +337,74 @@ def profile_kernel(name):
 
 def profile_end():
     _check(load().vie_profile_end())
+
+
+class Server:
+    """vie_server: queue, admission by footprint, resident operator/preconditioner cache and
+    worker streams for a stream of solve requests (see include/vie.h)."""
+
+    def __init__(self, workers=4, max_batch_rhs=64, hbm_budget=0):
+        lib = load()
+        o = ServerOpts(int(workers), int(max_batch_rhs), int(hbm_budget))
+        h = ctypes.c_void_p()
+        _check(lib.vie_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._pending = {}
+
+    def submit(self, grid, voxel_size, k_background, chi, e_inc, precond=True, homog='none', boxes=None,
+               reduce_tol=None, factor_prec=VIE_C128, refine=None, keep_zero_rows=False, tol=1e-6, restart=50,
+               maxit=5000, mode='fp64'):
+        """Queue one request; ``chi`` [nz, ny, nx] and ``e_inc`` [nrhs, 3, nz, ny, nx] are host
+        arrays (copied).  Returns the request id; ``wait(id)`` returns (x, stats, times)."""
+        nx, ny, nz = (int(v) for v in grid)
+        chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
+        e = np.ascontiguousarray(np.asarray(e_inc, dtype=np.complex128).reshape(-1, 3 * nx * ny * nz))
+        nrhs = e.shape[0]
+        if refine is None:
+            refine = 1 if factor_prec == VIE_BF16C else 0
+        pc = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, 0, int(refine), 1 if keep_zero_rows else 0)
+        bx = None
+        if boxes is not None:
+            bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
+            pc.nboxes = bx.shape[0]
+            pc.boxes = bx.ctypes.data
+        if reduce_tol is not None:
+            pc.reduce, pc.reduce_tol = 1, float(reduce_tol)
+        req = Request((ctypes.c_int32 * 3)(nx, ny, nz), float(voxel_size), float(k_background), chi.ctypes.data,
+                      e.ctypes.data, nrhs, 1 if precond else 0, pc,
+                      SolveOpts(float(tol), int(restart), int(maxit), MODE[mode], 0))
+        x = np.empty((nrhs, 3 * nx * ny * nz), dtype=np.complex128)
+        st = (SolveStats * nrhs)()
+        rid = ctypes.c_int64()
+        _check(_lib.vie_server_submit(self.h, ctypes.byref(req), x.ctypes.data, st, ctypes.byref(rid)))
+        self._pending[rid.value] = (x, st)
+        return rid.value
+
+    def done(self, rid):
+        d = ctypes.c_int32()
+        _check(_lib.vie_server_query(self.h, int(rid), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid):
+        """(x [nrhs, 3N], per-RHS stats dicts, times dict); VIE_NOT_CONVERGED does not raise."""
+        t = RequestTimes()
+        _check(_lib.vie_server_wait(self.h, int(rid), ctypes.byref(t)), allow=(VIE_OK, VIE_NOT_CONVERGED))
+        x, st = self._pending.pop(rid)
+        return (x, [{f: getattr(s, f) for f, _ in SolveStats._fields_} for s in st],
+                {f: getattr(t, f) for f, _ in RequestTimes._fields_})
+
+    def info(self):
+        i = ServerInfo()
+        _check(_lib.vie_server_info_get(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self.h:
+            _lib.vie_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

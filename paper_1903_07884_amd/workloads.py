@@ -145,3 +145,66 @@ def random_field(shape, tag):
     """Seeded complex normal test vector."""
     g = rng(tag)
     return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- serving stream
+SERVE_TYPES = ('waveguide', 'bragg', 'coupler')
+SERVE_NX = (256, 512, 1024)
+SERVE_CROSS = ((16, 8), (24, 8), (32, 8))
+
+
+def serving_devices(delta=25e-9):
+    """Device catalogue of the serving stream: geometry x length x cross-section."""
+    return [dict(geometry=t, grid=(nx, ny, nz), delta=delta)
+            for t in SERVE_TYPES for nx in SERVE_NX for (ny, nz) in SERVE_CROSS]
+
+
+def coupler_cores(ny):
+    """Two cores of width ny/3 with a gap of ny/6 (at least one voxel each), centred in y."""
+    c, g = max(1, ny // 3), max(1, ny // 6)
+    lo = (ny - 2 * c - g) // 2
+    return ((lo, lo + c), (lo + c + g, lo + 2 * c + g))
+
+
+def device_chi(dev):
+    grid, delta = dev['grid'], dev['delta']
+    if dev['geometry'] == 'waveguide':
+        return waveguide(grid)
+    if dev['geometry'] == 'bragg':
+        return bragg(grid, delta)
+    return coupler(grid, cores=coupler_cores(grid[1]))
+
+
+def device_sources(dev, count, tag):
+    """`count` seeded incident fields [count, 3, nz, ny, nx] for a catalogue device: Gaussian
+    cross-section at a random offset (in a random core for couplers), random polarisation
+    (y or z) and phase."""
+    g = rng(tag)
+    grid, delta = dev['grid'], dev['delta']
+    ny = grid[1]
+    out = np.zeros((count, 3) + tuple(reversed(grid)), dtype=np.complex128)
+    for r in range(count):
+        if dev['geometry'] == 'coupler':
+            lo, hi = coupler_cores(ny)[int(g.integers(0, 2))]
+            y0 = ((lo + hi) / 2.0 - ny / 2.0) * delta
+        else:
+            y0 = 0.0
+        y0 += g.uniform(-0.05e-6, 0.05e-6)
+        z0 = g.uniform(-0.03e-6, 0.03e-6)
+        pol = 1 if g.integers(0, 2) == 0 else 2
+        out[r] = gaussian_source(grid, delta, r, y0=y0, z0=z0, wy=0.2e-6, wz=0.1e-6, pol=pol,
+                                 phase=g.uniform(0.0, 2.0 * np.pi))
+    return out
+
+
+def serving_stream(n, rate, tag, max_rhs=16):
+    """Seeded request stream: Poisson arrivals at `rate` per second, a uniform catalogue device
+    and U{1..max_rhs} right-hand sides per request.  Returns [(t_arrival_s, device_index, nrhs)]."""
+    g = rng(tag)
+    ndev = len(serving_devices())
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += g.exponential(1.0 / rate)
+        out.append((t, int(g.integers(0, ndev)), int(g.integers(1, max_rhs + 1))))
+    return out

@@ -55,3 +55,22 @@ def test_argument_errors_before_device_work():
     assert lib.vie_solve(None, None, None, None, 1, None, None, None) == -1
     assert lib.precond_setup(None, None, None, ctypes.byref(out)) == -1 and out.value is None
     assert lib.vie_destroy(None) == 0 and lib.precond_destroy(None) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason='libvie.so not built')
+def test_server_argument_errors_before_device_work():
+    """The serving calls reject NULL handles and bad options before touching the device."""
+    from paper_1903_07884_amd import vie
+    lib = vie.load(LIB)
+    out = ctypes.c_void_p(123)
+    bad = vie.ServerOpts(-1, 0, 0)
+    assert lib.vie_server_create(ctypes.byref(bad), ctypes.byref(out)) == -1 and out.value is None
+    assert lib.vie_last_error().decode().startswith('vie_server_create')
+    assert lib.vie_server_create(None, None) == -1
+    rid = ctypes.c_int64()
+    assert lib.vie_server_submit(None, None, None, None, ctypes.byref(rid)) == -1
+    assert lib.vie_server_wait(None, 1, None) == -1
+    done = ctypes.c_int32()
+    assert lib.vie_server_query(None, 1, ctypes.byref(done)) == -1
+    assert lib.vie_server_info_get(None, None) == -1
+    assert lib.vie_server_destroy(None) == 0

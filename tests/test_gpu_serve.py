@@ -1,0 +1,166 @@
+"""The request scheduler (vie_server_*): results alone and in a mix, merging, cache, budget.
+
+Each result must not depend on what it is solved beside: a request solved alone (one
+worker, no merging) and the same request solved while other devices run on other streams,
+possibly merged with another request of its own device, agree to 1e-12 (FP64) / 1e-6
+(mixed) relative, and every result meets its tolerance.  Merged requests equal the plain
+library solve of each request.
+"""
+import numpy as np
+import pytest
+
+from paper_1903_07884_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KB = W.k_background()
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def _devices():
+    """Three small devices: an FP64 guide with the 1-level preconditioner, a mixed-precision
+    coupler cross-section, an unpreconditioned random-contrast block."""
+    rng = np.random.default_rng(3)
+    g1 = (32, 8, 4)
+    g2 = (24, 12, 2)
+    g3 = (12, 6, 3)
+    chi3 = 2.0 + rng.standard_normal(g3[::-1]) + 0.3j * rng.standard_normal(g3[::-1])
+    return {
+        'guide': dict(grid=g1, voxel_size=50e-9, k_background=KB, chi=W.waveguide(g1), precond=True),
+        'coupler': dict(grid=g2, voxel_size=25e-9, k_background=KB,
+                        chi=W.coupler(g2, cores=((1, 5), (7, 11))), precond=True,
+                        factor_prec=1, mode='mixed'),
+        'block': dict(grid=g3, voxel_size=50e-9, k_background=KB, chi=chi3, precond=False),
+    }
+
+
+def _e(dev, nrhs, seed):
+    nx, ny, nz = dev['grid']
+    return W.random_field((nrhs, 3 * nx * ny * nz), seed)
+
+
+def _tol(dev):
+    return 1e-6 if dev.get('mode') == 'mixed' else 1e-12
+
+
+def test_result_is_the_same_alone_and_in_the_mix(gpu_lib):
+    devs = _devices()
+    # alone: one worker, no merging, one request at a time
+    srv = gpu_lib.Server(workers=1, max_batch_rhs=1)
+    alone = {}
+    for name, dev in devs.items():
+        rid = srv.submit(e_inc=_e(dev, 2, 11), tol=1e-10 if dev.get('mode') != 'mixed' else 1e-6, **dev)
+        alone[name] = srv.wait(rid)
+    srv.close()
+    # in the mix: four workers; every device submitted several times, the reference request
+    # between others of other devices and one more of its own device (it may be merged)
+    srv = gpu_lib.Server(workers=4, max_batch_rhs=64)
+    ids = {}
+    order = ['block', 'guide', 'coupler', 'guide', 'block', 'coupler', 'guide', 'coupler', 'block']
+    seen = {}
+    for k, name in enumerate(order):
+        dev = devs[name]
+        first = name not in seen
+        seen[name] = True
+        e = _e(dev, 2, 11) if first else _e(dev, 1, 100 + k)
+        rid = srv.submit(e_inc=e, tol=1e-10 if dev.get('mode') != 'mixed' else 1e-6, **dev)
+        if first:
+            ids[name] = rid
+        else:
+            ids.setdefault(name + '_others', []).append(rid)
+    results = {name: srv.wait(rid) for name, rid in ids.items() if not name.endswith('_others')}
+    others = [srv.wait(r) for name, rs in ids.items() if name.endswith('_others') for r in rs]
+    info = srv.info()
+    srv.close()
+    for name, dev in devs.items():
+        xa, sa, ta = alone[name]
+        xm, sm, tm = results[name]
+        d = _rel(xm, xa)
+        print('serve %s: alone %.1f ms, in the mix %.1f ms (queue %.1f, merged %d, cache hit %d); difference %.2e; '
+              'relres %s' % (name, ta['total_ms'], tm['total_ms'], tm['queue_ms'], tm['merged'], tm['cache_hit'], d,
+                             [s['relres'] for s in sm]))
+        assert d <= _tol(dev)
+        assert all(s['status'] == 0 for s in sa + sm)
+        assert all(s['relres'] <= (1e-10 if dev.get('mode') != 'mixed' else 1e-6) for s in sm)
+    assert all(all(s['status'] == 0 for s in st) for _, st, _ in others)
+    print('server info', info)
+    assert info['completed'] == len(order) and info['queued'] == 0 and info['running'] == 0
+    assert info['peak_committed_bytes'] <= info['budget_bytes']
+
+
+def test_queued_requests_of_one_device_are_merged_and_cached(gpu_lib):
+    """One worker busy with a long solve; three requests of another device queue behind it and
+    run as one 3-RHS solve, each column equal to the plain library solve of its request."""
+    import torch
+    devs = _devices()
+    slow = dict(devs['guide'])
+    slow['grid'] = (64, 8, 4)
+    slow['chi'] = W.waveguide((64, 8, 4))
+    slow['precond'] = False  # unpreconditioned: many iterations keep the worker busy
+    dev = devs['block']
+    srv = gpu_lib.Server(workers=1, max_batch_rhs=64)
+    r_slow = srv.submit(e_inc=_e(slow, 1, 5), tol=1e-8, **slow)
+    es = [_e(dev, 1, 20 + k) for k in range(3)]
+    rids = [srv.submit(e_inc=e, tol=1e-10, **dev) for e in es]
+    res = [srv.wait(r) for r in rids]
+    srv.wait(r_slow)
+    # the same device once more: operator from the cache
+    r4 = srv.submit(e_inc=es[0], tol=1e-10, **dev)
+    x4, _, t4 = srv.wait(r4)
+    srv.close()
+    merged = [t['merged'] for _, _, t in res]
+    print('merged counts', merged, 'second visit cache hit', t4['cache_hit'])
+    assert merged == [3, 3, 3]
+    assert t4['cache_hit'] == 1
+    # plain library solves of each request
+    op = gpu_lib.Operator(dev['grid'], dev['voxel_size'], dev['k_background'], dev['chi'])
+    for (x, st, _), e in zip(res, es):
+        ed = torch.from_numpy(e).cuda()
+        b = torch.empty_like(ed)
+        op.rhs(ed, b, nrhs=1)
+        xd = torch.zeros_like(b)
+        gpu_lib.solve(op, None, b, xd, tol=1e-10)
+        assert _rel(x, xd.cpu().numpy()) <= 1e-12
+        assert st[0]['status'] == 0
+    assert _rel(x4, res[0][0]) <= 1e-12
+
+
+def test_budget_admission_and_eviction(gpu_lib):
+    devs = _devices()
+    srv = gpu_lib.Server(workers=2, hbm_budget=1 << 20)
+    with pytest.raises(gpu_lib.VieError) as ei:
+        srv.submit(e_inc=_e(devs['guide'], 1, 1), **devs['guide'])
+    assert ei.value.status == -6
+    with pytest.raises(gpu_lib.VieError) as ei:
+        srv.submit(e_inc=_e(devs['guide'], 1, 1), factor_prec=7,
+                   **{k: v for k, v in devs['guide'].items() if k != 'factor_prec'})
+    assert ei.value.status == -1
+    srv.close()
+    # a budget that holds one guide request at a time: the others wait, idle entries are evicted
+    import ctypes
+    lib = gpu_lib.load()
+    g = devs['guide']
+    nx, ny, nz = g['grid']
+    pc = gpu_lib.PcOpts(0, 0, None, 0, 0.0, 0, 0, 0, 0)
+    so = gpu_lib.SolveOpts(1e-10, 50, 5000, 0, 0)
+    op = gpu_lib.Operator(g['grid'], g['voxel_size'], g['k_background'], g['chi'])
+    need = ctypes.c_uint64()
+    assert lib.vie_footprint(op.h, ctypes.byref(pc), 1, ctypes.byref(so), ctypes.byref(need)) == 0
+    op.close()
+    budget = int(1.3 * need.value)  # one request (resident + run) fits; a second needs an eviction
+    srv = gpu_lib.Server(workers=2, hbm_budget=budget)
+    rids = []
+    for k in range(3):  # three different devices (contrast scaled): no cache reuse
+        d = dict(g)
+        d['chi'] = g['chi'] * (1.0 + 0.1 * k)
+        rids.append(srv.submit(e_inc=_e(d, 1, 40 + k), tol=1e-10, **d))
+    out = [srv.wait(r) for r in rids]
+    info = srv.info()
+    srv.close()
+    print('budget %d bytes, one request %d; info %s' % (budget, need.value, info))
+    assert all(st[0]['status'] == 0 for _, st, _ in out)
+    assert info['evictions'] >= 1
+    assert info['peak_committed_bytes'] <= budget
