@@ -16,6 +16,11 @@
 * ``reduction_keep``      -- the memory reduction of Sec. 5.1.1 (eqs. proxy1,
                              proxy2): keep D_k where |v_k|/||v||_inf > tol, every
                              other mode uses the central block D_{ceil(n/2)}.
+* ``chan_transform_2level``, ``BlockCirculantInverse2`` -- the 2-level circulant
+                             C_B2 of Sec. 4: the Chan approximation applied again,
+                             along y, to the Toeplitz blocks of every D_k; one
+                             3nz x 3nz block per mode pair (kx, ky).  Needs a
+                             homogenised contrast that does not vary along x or y.
 * ``BlockedPreconditioner`` -- the blocked-circulant preconditioner of Sec. 5.3:
                              one circulant preconditioner per box, block
                              diagonal; voxels outside every box are left as is.
@@ -175,6 +180,62 @@ class BlockCirculantInverse:
         return z.reshape(3, nz, ny, n)
 
 
+def chan_transform_2level(Koct, nx, ny, nz):
+    """C^_{kx,ky}^{ab}(dz) of the 2-level circulant (Sec. 4): the x-level table of
+    chan_transform, then T. Chan's circulant of each of its Toeplitz sequences along y
+    (dy in (-ny, ny)) and a DFT along y.  Array [nx, ny, 3, 3, 2nz-1], modes in natural order.
+    """
+    Ch = chan_transform(Koct, nx, ny, nz)                # [nx, 3, 3, 2ny-1, 2nz-1]
+    seq = np.moveaxis(Ch, 3, 0)                          # [2ny-1, nx, 3, 3, 2nz-1]
+    c = chan(seq)                                        # [ny, nx, 3, 3, 2nz-1]
+    out = np.tensordot(dft_matrix(ny), c, axes=(1, 0))   # [ky, nx, 3, 3, 2nz-1]
+    return np.moveaxis(out, 0, 1)
+
+
+def chan_olkin_blocks_2level(Koct, Mz, nx, ny, nz):
+    """D_{kx,ky} = I - diag(M~) C^_{kx,ky}, each 3nz x 3nz with row (a, z) -> a*nz + z;
+    ``Mz`` is the homogenised contrast per z layer [nz]."""
+    Ch = chan_transform_2level(Koct, nx, ny, nz)
+    m = 3 * nz
+    Mz = np.asarray(Mz, dtype=np.complex128)
+    D = np.zeros((nx, ny, m, m), dtype=np.complex128)
+    for a in range(3):
+        for z in range(nz):
+            r = a * nz + z
+            for b in range(3):
+                for zp in range(nz):
+                    D[:, :, r, b * nz + zp] = -Mz[z] * Ch[:, :, a, b, z - zp + nz - 1]
+            D[:, :, r, r] += 1.0
+    return D
+
+
+class BlockCirculantInverse2:
+    """z = C_B2^{-1} r for one box (Sec. 4, 2-level): DFTs along x and y, one dense solve per
+    mode pair (kx, ky), inverse DFTs."""
+
+    def __init__(self, Koct, Mz, n, ny, nz):
+        self.n, self.ny, self.nz = n, ny, nz
+        D = chan_olkin_blocks_2level(Koct, Mz, n, ny, nz)
+        self.lu = [[scipy.linalg.lu_factor(D[kx, ky]) for ky in range(ny)] for kx in range(n)]
+        self.D = D
+        self.keep = np.ones(n * ny, dtype=bool)
+
+    def apply(self, r):
+        """r: [3, nz, ny, n] (box-local) -> z of the same shape."""
+        n, ny, nz = self.n, self.ny, self.nz
+        Fx, Fy = dft_matrix(n), dft_matrix(ny)
+        r = np.asarray(r, dtype=np.complex128).reshape(3, nz, ny, n)
+        rh = np.einsum('kx,azyx->azyk', Fx, r)
+        rh = np.einsum('jy,azyk->azjk', Fy, rh)                 # [3, nz, ky, kx]
+        zh = np.empty_like(rh)
+        for kx in range(n):
+            for ky in range(ny):
+                zh[:, :, ky, kx] = scipy.linalg.lu_solve(self.lu[kx][ky], rh[:, :, ky, kx].reshape(-1)).reshape(3, nz)
+        z = np.einsum('jy,azjk->azyk', np.conj(Fy), zh) / ny
+        z = np.einsum('kx,azyk->azyx', np.conj(Fx), z) / n
+        return z
+
+
 class BlockedPreconditioner:
     """Block-diagonal circulant preconditioner over boxes (Sec. 5.3).
 
@@ -182,7 +243,7 @@ class BlockedPreconditioner:
     'none', 'mode', 'mean', 'realmean' (Sec. 5.2), applied per box.
     """
 
-    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product'):
+    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product', levels=1):
         from .contrast import homogenize
         nx, ny, nz = grid
         self.grid = grid
@@ -191,7 +252,13 @@ class BlockedPreconditioner:
         self.parts = []
         for (x0, y0, z0, bx, by, bz) in self.boxes:
             Mt = homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], homog)
-            self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol, proxy))
+            if levels == 2:
+                Mt = np.broadcast_to(Mt, (bz, by))
+                if not np.all(Mt == Mt[:, :1]):
+                    raise ValueError('the 2-level circulant needs a contrast that does not vary along y')
+                self.parts.append(BlockCirculantInverse2(Koct, Mt[:, 0], bx, by, bz))
+            else:
+                self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol, proxy))
 
     def apply(self, r):
         nx, ny, nz = self.grid

@@ -13,6 +13,9 @@
 * Blocked preconditioner (Sec. 5.3): one box is the 1-level preconditioner;
   several boxes equal a dense block-diagonal build.
 * Homogenisations (Sec. 5.2 list) on hand-made arrays.
+* 2-level circulant (Sec. 4): equals the block-circulant-circulant matrix built elementwise
+  from T. Chan's weights in x and y (no DFT, no blocks) and inverted densely; with one y
+  layer it is the 1-level preconditioner; zero contrast gives the identity.
 * Cross-section rows with M~ = 0 are identity rows of every D_k (eq. Di), so the block
   solve reduces exactly to the other rows S plus the coupling M~_S C^_SC r^_C, and to the
   S x S solve alone when r^_C = 0 (the reduction the GPU path takes for cladding rows).
@@ -248,3 +251,60 @@ def test_proxy_centre_reading_location():
     v = C.proxy_values(K, 4, 16, 8, reading='centre')
     t = np.array([4.0, 0.5, -2.0, 1.0, -2.0, 0.5, 4.0])
     assert np.allclose(v, C.dft_matrix(4) @ C.chan(t))
+
+
+def _dense_two_level(K, Mz, grid):
+    """C_B2 elementwise: c(dx, dy) = sum over the four wrapped quadrants of T. Chan's weights in
+    x and y times T(dx - s nx, dy - t ny), T = I - M~ N (no DFT, no blocks)."""
+    nx, ny, nz = grid
+    n3 = 3 * nz * ny * nx
+
+    def T(a, b, dx, dy, z, zp):
+        v = -Mz[z] * G.generator_signed(K, a, b, np.array(dx), np.array(dy), np.array(z - zp))
+        if a == b and dx == 0 and dy == 0 and z == zp:
+            v = v + 1.0 - Mz[z]  # N = I + K
+        return complex(v)
+
+    A = np.zeros((n3, n3), dtype=complex)
+    idx = lambda a, z, y, x: ((a * nz + z) * ny + y) * nx + x
+    for a in range(3):
+        for b in range(3):
+            for z in range(nz):
+                for zp in range(nz):
+                    for lx in range(nx):
+                        for ly in range(ny):
+                            c = 0.0
+                            for s_, wx in ((0, (nx - lx) / nx), (1, lx / nx)):
+                                for t_, wy in ((0, (ny - ly) / ny), (1, ly / ny)):
+                                    if wx and wy:
+                                        c += wx * wy * T(a, b, lx - s_ * nx, ly - t_ * ny, z, zp)
+                            for x in range(nx):
+                                for y in range(ny):
+                                    A[idx(a, z, y, x), idx(b, zp, (y - ly) % ny, (x - lx) % nx)] = c
+    return A
+
+
+def test_two_level_matches_dense_twin():
+    grid = (5, 4, 2)
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    Mz = np.array([0.83 - 0.02j, 0.61 + 0.05j])
+    inv = C.BlockCirculantInverse2(K, Mz, nx, ny, nz)
+    A = _dense_two_level(K, Mz, grid)
+    r = np.random.default_rng(21).standard_normal(A.shape[0]) + 1j * np.random.default_rng(22).standard_normal(A.shape[0])
+    z = inv.apply(r.reshape(3, nz, ny, nx)).reshape(-1)
+    ref = np.linalg.solve(A, r)
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_two_level_with_one_y_layer_is_one_level():
+    grid = (6, 1, 3)
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    Mz = np.array([0.8, 0.7 + 0.1j, 0.5])
+    r = np.random.default_rng(23).standard_normal((3, nz, ny, nx)) + 0j
+    z2 = C.BlockCirculantInverse2(K, Mz, nx, ny, nz).apply(r)
+    z1 = C.BlockCirculantInverse(K, Mz[:, None], nx, ny, nz).apply(r)
+    assert np.abs(z2 - z1).max() < 1e-13 * np.abs(z1).max()
+    z0 = C.BlockCirculantInverse2(K, np.zeros(nz), nx, ny, nz).apply(r)
+    assert np.abs(z0 - r).max() < 1e-14
