@@ -140,6 +140,13 @@ typedef struct {
                             exact coupling term M~ C^_k r^ (skipped on the device when that
                             input is zero, as for every Krylov vector of a right-hand side
                             that vanishes where M = 0).  1 = factorise the full cross-section. */
+    int32_t levels;         /* 0 or 1: the 1-level circulant (one 3*by*bz block per x-mode);
+                            2: the 2-level circulant of Sec. 4 (the Chan approximation applied
+                            again along y: one 3*bz block per (x-mode, y-mode) pair), for boxes
+                            too wide in y for the 1-level blocks.  Needs a homogenised contrast
+                            that does not vary along y (e.g. homog = MODE, the modal average),
+                            factor_prec VIE_C128 or VIE_C64, no memory reduction; keep_zero_rows
+                            does not apply. */
 } vie_pc_opts;
 
 typedef struct {
@@ -149,6 +156,8 @@ typedef struct {
     int64_t factor_bytes;             /* bytes of LU factors (+ pivots) */
     int32_t active_m;                 /* order of the factorised blocks: block_m less the
                                          identity rows (keep_zero_rows = 0) */
+    int32_t levels;                   /* 1 or 2; with 2, block_m = 3*bz and modes counts the
+                                         (x-mode, y-mode) pairs */
 } vie_pc_info;
 
 /* Build the 1-level Chan-Olkin block-circulant preconditioner (Sec. 4): per box,

@@ -174,6 +174,9 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
         return arg_error("precond_setup: refine_steps needs VIE_BF16C factors");
     if (o.keep_zero_rows != 0 && o.keep_zero_rows != 1)
         return arg_error("precond_setup: keep_zero_rows must be 0 or 1");
+    if (o.levels < 0 || o.levels > 2) return arg_error("precond_setup: levels must be 0, 1 or 2");
+    if (o.levels == 2 && (o.reduce || o.factor_prec == VIE_BF16C))
+        return arg_error("precond_setup: the 2-level circulant takes VIE_C128 or VIE_C64 factors and no memory reduction");
     if (o.factor_prec == VIE_BF16C && !op->has_c64)
         return arg_error("precond_setup: VIE_BF16C factors need an operator built with build_c64");
     if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
@@ -219,6 +222,15 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
         fft_line_shape(tmp, sizeof(c128), &thr, &lds, &bpt);
         if (lds > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
     }
+    const int levels = o.levels == 2 ? 2 : 1;
+    if (levels == 2) {
+        if (!fft_supported_length(by))
+            return arg_error("precond_setup: box width " + std::to_string(by) + " has a prime factor above " +
+                             std::to_string(VIE_FFT_MAX_PRIME));
+        FftPlan tmp;
+        if (op->fft.get(by, &tmp) < 0) return VIE_EARG;
+        m = 3 * bz;
+    }
     if (m > 1280) return arg_error("precond_setup: cross-section block (3*by*bz) above 1280 is not supported");
     vie_pc pc = new (std::nothrow) vie_pc_s();
     if (!pc) return VIE_EOOM;
@@ -227,6 +239,8 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     pc->bx = bx;
     pc->by = by;
     pc->bz = bz;
+    pc->levels = levels;
+    pc->nm = levels == 2 ? bx * by : bx;
     pc->m = m;
     pc->m_full = m;
     pc->boxes = boxes;
@@ -274,10 +288,11 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, const vie_pc_o
         const uint64_t nb = o.nboxes ? o.nboxes : 1;
         const uint64_t bx = B ? B[3] : nx, by = B ? B[4] : ny, bz = B ? B[5] : nz;
         if (bx < 1 || by < 1 || bz < 1) return arg_error("vie_footprint: bad box shape");
-        const uint64_t m = 3 * by * bz, modes = nb * bx;
+        const bool two = o.levels == 2;
+        const uint64_t m = two ? 3 * bz : 3 * by * bz, modes = two ? nb * bx * by : nb * bx;
         const uint64_t fesz = o.factor_prec == VIE_C128 ? 16 : o.factor_prec == VIE_BF16C ? 4 : 8;
         const uint64_t vesz = o.factor_prec == VIE_C128 ? 16 : 8;  // vector / factorisation precision
-        const uint64_t table = modes / nb * 6 * (2 * by - 1) * (2 * bz - 1);
+        const uint64_t table = bx * 6 * (2 * by - 1) * (2 * bz - 1) + (two ? bx * by * 6 * (2 * bz - 1) : 0);
         uint64_t pcb = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
         if (o.factor_prec == VIE_BF16C) pcb += modes * m * m * 8;        // complex-float factorisation copy
         pcb += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;       // Chan table, LU workspace
@@ -288,7 +303,8 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, const vie_pc_o
         // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
         const uint64_t cols = modes * R;
         const uint64_t wide = (cols + 64 * modes) * m * vesz;
-        *apply_scratch = R * nb * m * bx * vesz + wide * (o.refine_steps ? 2 : 1);
+        *apply_scratch = R * nb * m * (modes / nb) * vesz + wide * (o.refine_steps ? 2 : 1);
+        if (two) *apply_scratch += R * nb * 3 * by * bz * bx * vesz + 4 * 3 * by * bz;  // x-stage lines
     }
     if (so) {
         if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
@@ -331,7 +347,8 @@ extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
     info->box_nx = pc->bx;
     info->block_m = pc->m_full;
     info->active_m = pc->m;
-    info->modes = pc->nboxes * pc->bx;
+    info->levels = pc->levels;
+    info->modes = pc->nboxes * pc->nm;
     info->stored_blocks = pc->nstored;
     size_t esz = pc->prec == VIE_C128 ? sizeof(c128) : pc->prec == VIE_C64 ? sizeof(c64) : sizeof(bf16c);
     info->factor_bytes = (int64_t)pc->nstored * pc->m * ((int64_t)pc->m * esz + sizeof(int));

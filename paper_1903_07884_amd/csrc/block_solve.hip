@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
 // tables (only when nrhs changed since the last apply).
 static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     if (pc->sched_nrhs == nrhs) return VIE_OK;
-    const int n = pc->bx;
+    const int n = pc->nm;
     // bfloat16 factors are solved on the matrix cores only (every block goes wide)
     const bool all_wide = pc->prec == VIE_BF16C;
     const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : pc->cfg_min_rhs;
@@ -835,7 +835,7 @@ static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
-                       mp, mp + pc->nstored + 1, Y, pc->m, pc->bx, pc->nboxes, nrhs, out_mode, Yadd,
+                       mp, mp + pc->nstored + 1, Y, pc->m, pc->nm, pc->nboxes, nrhs, out_mode, Yadd,
                        pc->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16);
 }
 
@@ -870,12 +870,12 @@ static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStr
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
                        pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y,
-                       pc->rows.as<const int>(), pc->m, pc->bx, pc->nboxes, nrhs, pc->by, pc->bz);
+                       pc->rows.as<const int>(), pc->m, pc->nm, pc->nboxes, nrhs, pc->by, pc->bz);
 }
 
 template <class R, class FT>
 static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
-    const int m = pc->m, n = pc->bx;
+    const int m = pc->m, n = pc->nm;
     const int qr = (m + 255) / 256;
     VIE_CHECK(build_schedule(pc, nrhs, s));
     if (pc->n_wide > 0) {
@@ -942,7 +942,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
         const bool bf = pc->prec == VIE_BF16C, fp32 = sizeof(R) == 4;
         char key[160];
         snprintf(key, sizeof key, "block_solve prec=%d m=%d n=%d boxes=%d stored=%d nrhs=%d refine=%d", pc->prec,
-                 pc->m, pc->bx, pc->nboxes, pc->nstored, nrhs, pc->refine);
+                 pc->m, pc->nm, pc->nboxes, pc->nstored, nrhs, pc->refine);
         std::vector<int> choice;
         if (!tune_lookup(key, &choice)) {
             std::vector<std::vector<int>> cands;  // {gmax, nw, rc, min_rhs}
@@ -954,7 +954,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
             if (!bf && nrhs < 32)
                 for (int rc = 1; rc <= rcmax; rc *= 2) cands.push_back({0, 0, rc, 1 << 30});
             if (cands.size() > 1) {
-                const size_t bytes = sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->bx;
+                const size_t bytes = sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->nm;
                 DevBuf copy;
                 VIE_CHECK(copy.ensure(bytes));
                 double best = 1e300;

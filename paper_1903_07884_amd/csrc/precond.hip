@@ -109,6 +109,29 @@ __global__ void k_chan_table(const c128 *gen, c128 *Ch, int nx, int ny, int nz, 
     for (int k = threadIdx.x; k < n; k += blockDim.x) Ch[k * stride_k + (long long)c * ndz * ndy + iz * ndy + iy] = res[k];
 }
 
+// 2-level table (Sec. 4, the Chan approximation applied again along y): one workgroup per
+// (x-mode k, component c, z offset dz) takes the y-sequence Ch[k][c][dz][dy], dy in (-by, by), of
+// the x-level table, T. Chan's circulant of it (length by) and its DFT along y:
+//   Ch2[ky*bx + k][c][dz + bz - 1].
+__global__ void k_chan_table2(const c128 *Ch, c128 *Ch2, int bx, int by, int bz, FftPlan py) {
+    c128 *a = reinterpret_cast<c128 *>(vie_smem), *b = a + py.L;
+    const int ndy = 2 * by - 1, ndz = 2 * bz - 1;
+    const int iz = blockIdx.x % ndz, c = (blockIdx.x / ndz) % 6, k = blockIdx.x / (6 * ndz);
+    const c128 *t = Ch + ((long long)k * 6 + c) * ndz * ndy + (long long)iz * ndy + (by - 1);  // t[dy]
+    for (int l = threadIdx.x; l < by; l += blockDim.x) {
+        const double w1 = (double)(by - l) / by, w2 = (double)l / by;
+        c128 v = t[l];
+        v = mk(w1 * v.re, w1 * v.im);
+        if (l > 0) v = v + mk(w2 * t[l - by].re, w2 * t[l - by].im);
+        a[l] = v;
+    }
+    __syncthreads();
+    LdsLines ln = {1, by, 0, 1, 1};
+    c128 *res = by > 1 ? fft_lds<double>(a, b, ln, py, false) : a;
+    for (int ky = threadIdx.x; ky < by; ky += blockDim.x)
+        Ch2[((long long)ky * bx + k) * 6 * ndz + (long long)c * ndz + iz] = res[ky];
+}
+
 // ---------------------------------------------------------------- assembly
 // D[s] column-major m x m, s-th stored block (mode ks, box bs), over the cross-section rows
 // rows[0..m) (entry a*by*bz + z*by + y)
@@ -127,6 +150,28 @@ __global__ void k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode, 
     int c = cidx[ar][ac];
     c128 ch = Ch[(long long)k * 6 * ndz * ndy + (long long)c * ndz * ndy + (zr - zc + bz - 1) * ndy + (yr - yc + by - 1)];
     c128 mt = Mt[(long long)b * by * bz + zr * by + yr];
+    c128 v = mt * ch;
+    v = mk(-v.re, -v.im);
+    if (r == col) v.re += 1.0;
+    D[(long long)s * m * m + e] = mk((R)v.re, (R)v.im);
+}
+
+// 2-level blocks: D[s] column-major (3 bz)^2 for the stored block s of mode pair blk_mode[s]
+// (= ky*bx + kx) and box blk_box[s]; row (a, z) = a*bz + z;
+//   D[(a,z),(b,z')] = delta - M~(z) Ch2[k2][c(a,b)][z - z' + bz - 1],
+// M~ of the box taken at y = 0 (it does not vary along y).
+template <class R>
+__global__ void k_assemble2(const c128 *Ch2, const c128 *Mt, const int *blk_mode, const int *blk_box, cpx<R> *D,
+                            int by, int bz) {
+    const int m = 3 * bz, ndz = 2 * bz - 1;
+    const int s = blockIdx.y;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)m * m) return;
+    const int r = (int)(e % m), col = (int)(e / m);
+    const int ar = r / bz, zr = r % bz, ac = col / bz, zc = col % bz;
+    const int c = ar == ac ? ar : ar + ac + 2;  // xy -> 3, xz -> 4, yz -> 5
+    const c128 ch = Ch2[(long long)blk_mode[s] * 6 * ndz + c * ndz + (zr - zc + bz - 1)];
+    const c128 mt = Mt[((long long)blk_box[s] * bz + zr) * by];
     c128 v = mt * ch;
     v = mk(-v.re, -v.im);
     if (r == col) v.re += 1.0;
@@ -812,6 +857,47 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, con
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
 }
 
+// 2-level apply, y stage.  Forward: from the x-DFT lines x1[rb][(a, y, z)][kx] (rb = rhs*nboxes
+// + box, cross-section row a*by*bz + z*by + y) to x2[rb][(a, z)][ky*bx + kx], transforming along
+// y; inverse: back, scaled by 1/by.  One workgroup per (rb, (a, z), group of YC x-modes); the
+// YC lines of length by are staged in LDS with coalesced loads and stores along kx.
+#define YC 8
+template <class R>
+__global__ void k_box_yfft(cpx<R> *x1, cpx<R> *x2, int bx, int by, int bz, FftPlan py, int inverse) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem), *b = a + YC * by;
+    const int ngx = (bx + YC - 1) / YC;
+    const int kg = blockIdx.x % ngx;
+    const long long row2 = blockIdx.x / ngx;  // rb * 3 bz + (a*bz + z)
+    const int r2 = (int)(row2 % (3 * bz));
+    const long long rb = row2 / (3 * bz);
+    const int comp = r2 / bz, z = r2 % bz;
+    const int kx0 = kg * YC;
+    const long long m1 = 3LL * by * bz, nm = (long long)bx * by;
+    cpx<R> *l1 = x1 + (rb * m1 + (long long)comp * by * bz + (long long)z * by) * bx;  // + y*bx + kx
+    cpx<R> *l2 = x2 + row2 * nm;                                                       // + ky*bx + kx
+    for (int e = threadIdx.x; e < YC * by; e += blockDim.x) {
+        const int y = e / YC, j = e % YC;
+        const int kx = kx0 + j;
+        cpx<R> v = czero<R>();
+        if (kx < bx) v = inverse ? l2[(long long)y * bx + kx] : l1[(long long)y * bx + kx];
+        a[j * by + y] = v;
+    }
+    __syncthreads();
+    LdsLines ln = {YC, by, 0, 1, YC};
+    cpx<R> *res = by > 1 ? fft_lds<R>(a, b, ln, py, inverse != 0) : a;
+    const R sc = inverse ? R(1) / R(by) : R(1);
+    for (int e = threadIdx.x; e < YC * by; e += blockDim.x) {
+        const int y = e / YC, j = e % YC;
+        const int kx = kx0 + j;
+        if (kx >= bx) continue;
+        const cpx<R> v = sc * res[j * by + y];
+        if (inverse)
+            l1[(long long)y * bx + kx] = v;
+        else
+            l2[(long long)y * bx + kx] = v;
+    }
+}
+
 // Identity rows of every D_k (M~ = 0 on the row): z = r on their box lines, and *flag = epoch
 // when any of that input is nonzero (it then couples into the solved rows).
 template <class R>
@@ -873,16 +959,68 @@ __global__ void __launch_bounds__(256) k_couple(cpx<R> *work, const cpx<R> *work
 }
 
 // ---------------------------------------------------------------- host side
+// 2-level apply: x-DFT of every box line, y-DFT to the (x-mode, y-mode) spectra, one block solve
+// per mode pair, inverse y-DFT, inverse x-DFT (Sec. 4: C_B2^{-1}).
+template <class R>
+static vie_status apply2_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
+    vie_op op = pc->op;
+    const int bx = pc->bx, by = pc->by, bz = pc->bz, m1 = 3 * by * bz;
+    const long long lines1 = (long long)nrhs * pc->nboxes * m1;
+    VIE_CHECK(pc->work1.ensure(sizeof(cpx<R>) * lines1 * bx));
+    VIE_CHECK(pc->work.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->nm));
+    if (!pc->covers_all)
+        VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
+    const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * pc->nm);
+    const int *rows1 = pc->rows1.as<const int>();
+    int thr, bpt;
+    size_t lds;
+    fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds, &bpt);
+    cpx<R> *w1 = pc->work1.as<cpx<R>>(), *w2 = pc->work.as<cpx<R>>();
+    const unsigned ygrid = (unsigned)((long long)nrhs * pc->nboxes * pc->m * ((bx + YC - 1) / YC));
+    const size_t ylds = 2 * sizeof(cpx<R>) * YC * by;
+    vie_lds_attr((const void *)k_box_yfft<R>, ylds);
+    {
+        ProfScope ps("precond_xfft", s);
+#define LAUNCH_BOX_FFT(B)                                                                                        \
+    vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                            \
+    hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines1), dim3(thr), lds, s, r, w1, dboxes, rows1, m1, op->nx, \
+                       op->ny, op->nz, by, bz, pc->nboxes, pc->pxb, nullptr, 0u)
+        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
+#undef LAUNCH_BOX_FFT
+        VIE_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_box_yfft<R>, dim3(ygrid), dim3(256), ylds, s, w1, w2, bx, by, bz, pc->pyb2, 0);
+        VIE_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps("block_solve", s);
+        VIE_CHECK(launch_block_solve(pc, w2, nrhs, s));
+    }
+    {
+        ProfScope ps("precond_ixfft", s);
+        hipLaunchKernelGGL(k_box_yfft<R>, dim3(ygrid), dim3(256), ylds, s, w1, w2, bx, by, bz, pc->pyb2, 1);
+        VIE_HIP(hipGetLastError());
+#define LAUNCH_BOX_IFFT(B)                                                                                       \
+    vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                           \
+    hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines1), dim3(thr), lds, s, w1, z, dboxes, rows1, m1,     \
+                       op->nx, op->ny, op->nz, by, bz, pc->nboxes, pc->pxb)
+        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
+#undef LAUNCH_BOX_IFFT
+    }
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
 template <class R>
 static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
     vie_op op = pc->op;
+    if (pc->levels == 2) return apply2_t<R>(pc, r, z, nrhs, s);
     const int m = pc->m, mc = pc->m_full - pc->m, n = pc->bx;
     long long lines = (long long)nrhs * pc->nboxes * m;
     VIE_CHECK(pc->work.ensure(sizeof(cpx<R>) * lines * n));
     if (mc > 0) VIE_CHECK(pc->workc.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * mc * n));
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
-    const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * n);
+    const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * pc->nm);
     const int *rows = pc->rows.as<const int>();
     int thr, bpt;
     size_t lds;
@@ -1018,9 +1156,33 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             return VIE_EARG;
         }
     }
+    if (pc->levels == 2) {
+        // the 2-level blocks need M~ independent of y; rows (a, z) in natural order, and the
+        // identity map of the full cross-section lines for the x stage of the apply
+        std::vector<c128> Mth((size_t)nbx * by * bz);
+        VIE_HIP(hipMemcpyAsync(Mth.data(), Mt.p, sizeof(c128) * Mth.size(), hipMemcpyDeviceToHost, s));
+        VIE_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < Mth.size(); ++i) {
+            const c128 &v = Mth[i], &v0 = Mth[i - i % by];
+            if (v.re != v0.re || v.im != v0.im) {
+                vie_set_error("the 2-level circulant needs a homogenised contrast that does not vary along y "
+                              "(homog MODE, or a contrast uniform in x and y per z layer)");
+                return VIE_EARG;
+            }
+        }
+        pc->rows_host.resize(pc->m_full);
+        for (int i = 0; i < pc->m_full; ++i) pc->rows_host[i] = i;
+        VIE_CHECK(pc->rows.ensure(sizeof(int) * pc->m_full));
+        VIE_HIP(hipMemcpyAsync(pc->rows.p, pc->rows_host.data(), sizeof(int) * pc->m_full, hipMemcpyHostToDevice, s));
+        std::vector<int> id1(3 * by * bz);
+        for (int i = 0; i < 3 * by * bz; ++i) id1[i] = i;
+        VIE_CHECK(pc->rows1.ensure(sizeof(int) * id1.size()));
+        VIE_HIP(hipMemcpyAsync(pc->rows1.p, id1.data(), sizeof(int) * id1.size(), hipMemcpyHostToDevice, s));
+        VIE_HIP(hipStreamSynchronize(s));
+        VIE_CHECK(op->fft.get(by, &pc->pyb2));
+    } else {
     // Row order: cross-section positions (y, z) with M~ != 0 in some box first (all three
     // components); the others are identity rows of every D_k and are not factorised.
-    {
         const int plane = by * bz;
         std::vector<char> act(plane, 1);
         if (!o->keep_zero_rows) {
@@ -1052,7 +1214,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         VIE_HIP(hipMemsetAsync(pc->cflag.p, 0, sizeof(uint32_t), s));
         pc->epoch = 0;
     }
-    const int m = pc->m;
+    const int m = pc->m, nm = pc->nm;
     const bool shortcut = pc->m < pc->m_full;
     // Chan + x-DFT table
     DevBuf Ch;
@@ -1070,8 +1232,8 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         VIE_HIP(hipGetLastError());
     }
     // memory reduction: proxy v_k of eq. proxy1 read from the table of N (minus the identity)
-    std::vector<int> keep(n, 1);
-    int centre = (n + 1) / 2 - 1;  // ceil(n/2) - 1
+    std::vector<int> keep(nm, 1);
+    int centre = (n + 1) / 2 - 1;  // ceil(n/2) - 1 (the 1-level memory reduction only)
     if (o->reduce) {
         int yp, zp;
         if (o->proxy == 1) {
@@ -1098,19 +1260,19 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         keep[centre] = 1;
     }
     // block map: stored blocks ordered (box, mode)
-    pc->block_of_mode_host.assign((size_t)nbx * n, -1);
+    pc->block_of_mode_host.assign((size_t)nbx * nm, -1);
     std::vector<int> smode, sbox;
     for (int b = 0; b < nbx; ++b) {
         int cs = -1;
-        for (int k = 0; k < n; ++k)
+        for (int k = 0; k < nm; ++k)
             if (keep[k]) {
                 if (k == centre) cs = (int)smode.size();
-                pc->block_of_mode_host[(size_t)b * n + k] = (int)smode.size();
+                pc->block_of_mode_host[(size_t)b * nm + k] = (int)smode.size();
                 smode.push_back(k);
                 sbox.push_back(b);
             }
-        for (int k = 0; k < n; ++k)
-            if (!keep[k]) pc->block_of_mode_host[(size_t)b * n + k] = cs;
+        for (int k = 0; k < nm; ++k)
+            if (!keep[k]) pc->block_of_mode_host[(size_t)b * nm + k] = cs;
     }
     pc->nstored = (int)smode.size();
     // per stored block: the modes that use it (block-solve columns) and its box
@@ -1118,13 +1280,13 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     pc->mode_list.clear();
     pc->block_box = sbox;
     for (int b = 0; b < nbx; ++b)
-        for (int k = 0; k < n; ++k) pc->mode_ptr[pc->block_of_mode_host[(size_t)b * n + k] + 1]++;
+        for (int k = 0; k < nm; ++k) pc->mode_ptr[pc->block_of_mode_host[(size_t)b * nm + k] + 1]++;
     for (int sb = 0; sb < pc->nstored; ++sb) pc->mode_ptr[sb + 1] += pc->mode_ptr[sb];
     pc->mode_list.assign(pc->mode_ptr[pc->nstored], 0);
     {
         std::vector<int> fill(pc->mode_ptr.begin(), pc->mode_ptr.end() - 1);
         for (int b = 0; b < nbx; ++b)
-            for (int k = 0; k < n; ++k) pc->mode_list[fill[pc->block_of_mode_host[(size_t)b * n + k]]++] = k;
+            for (int k = 0; k < nm; ++k) pc->mode_list[fill[pc->block_of_mode_host[(size_t)b * nm + k]]++] = k;
     }
     pc->sched_nrhs = 0;
     VIE_CHECK(pc->modes_dev.ensure(sizeof(int) * (pc->mode_ptr.size() + pc->mode_list.size())));
@@ -1133,10 +1295,10 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     VIE_HIP(hipMemcpyAsync(pc->modes_dev.as<int>() + pc->mode_ptr.size(), pc->mode_list.data(),
                            sizeof(int) * pc->mode_list.size(), hipMemcpyHostToDevice, s));
     // device block map followed by the boxes (apply kernels read both)
-    VIE_CHECK(pc->block_of_mode.ensure(sizeof(int) * ((size_t)nbx * n + 6 * nbx)));
-    VIE_HIP(hipMemcpyAsync(pc->block_of_mode.p, pc->block_of_mode_host.data(), sizeof(int) * (size_t)nbx * n,
+    VIE_CHECK(pc->block_of_mode.ensure(sizeof(int) * ((size_t)nbx * nm + 6 * nbx)));
+    VIE_HIP(hipMemcpyAsync(pc->block_of_mode.p, pc->block_of_mode_host.data(), sizeof(int) * (size_t)nbx * nm,
                            hipMemcpyHostToDevice, s));
-    VIE_HIP(hipMemcpyAsync(pc->block_of_mode.as<int>() + (size_t)nbx * n, pc->boxes.data(), sizeof(int) * 6 * nbx,
+    VIE_HIP(hipMemcpyAsync(pc->block_of_mode.as<int>() + (size_t)nbx * nm, pc->boxes.data(), sizeof(int) * 6 * nbx,
                            hipMemcpyHostToDevice, s));
     DevBuf dmode, dbox;
     VIE_CHECK(dmode.ensure(sizeof(int) * pc->nstored));
@@ -1149,7 +1311,23 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     VIE_CHECK(pc->perm.ensure(sizeof(int) * (size_t)pc->nstored * m));
     VIE_CHECK(pc->info.ensure(sizeof(int) * (size_t)pc->nstored));
     dim3 ga((unsigned)(((long long)m * m + 255) / 256), pc->nstored);
-    if (pc->prec == VIE_C128)
+    if (pc->levels == 2) {  // second level: Chan along y + y-DFT of the x-level table, then the blocks
+        DevBuf Ch2;
+        VIE_CHECK(Ch2.ensure(sizeof(c128) * (size_t)nm * 6 * ndz));
+        const size_t lds = 2 * sizeof(c128) * by;
+        vie_lds_attr((const void *)k_chan_table2, lds);
+        hipLaunchKernelGGL(k_chan_table2, dim3((unsigned)(n * 6 * ndz)), dim3(64), lds, s, Ch.as<const c128>(),
+                           Ch2.as<c128>(), n, by, bz, pc->pyb2);
+        VIE_HIP(hipGetLastError());
+        if (pc->prec == VIE_C128)
+            hipLaunchKernelGGL(k_assemble2<double>, ga, dim3(256), 0, s, Ch2.as<const c128>(), Mt.as<const c128>(),
+                               dmode.as<const int>(), dbox.as<const int>(), pc->factors.as<c128>(), by, bz);
+        else
+            hipLaunchKernelGGL(k_assemble2<float>, ga, dim3(256), 0, s, Ch2.as<const c128>(), Mt.as<const c128>(),
+                               dmode.as<const int>(), dbox.as<const int>(), pc->factors.as<c64>(), by, bz);
+        VIE_HIP(hipGetLastError());
+        VIE_HIP(hipStreamSynchronize(s));
+    } else if (pc->prec == VIE_C128)
         hipLaunchKernelGGL(k_assemble<double>, ga, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
                            dmode.as<const int>(), dbox.as<const int>(), pc->rows.as<const int>(),
                            pc->factors.as<c128>(), m, by, bz);

@@ -180,6 +180,8 @@ struct vie_op_s {
 struct vie_pc_s {
     vie_op op;
     int nboxes, bx, by, bz;
+    int levels = 1;          // 1: blocks per x-mode; 2: blocks per (x-mode, y-mode) pair
+    int nm;                  // modes per box: bx (1-level) or bx*by (2-level, mode ky*bx + kx)
     int m;                   // order of the factorised blocks (active rows)
     int m_full;              // 3*by*bz rows of a box cross-section
     std::vector<int> boxes;  // nboxes*6
@@ -200,6 +202,10 @@ struct vie_pc_s {
     DevBuf cflag;            // int32: epoch of the last apply whose identity rows held input
     uint32_t epoch = 0;
     DevBuf chan64, mt64;     // FP64 C^_k table / M~ for the coupling of an FP64 apply
+    // 2-level: x-DFT lines of the full cross-section [R][box][3*by*bz][bx] before the y-DFT,
+    // and the identity map of those lines
+    DevBuf work1, rows1;
+    FftPlan pyb2;            // length by (the y-DFT of the 2-level circulant)
     FftPlan pxb;             // length bx
     // block-solve schedule
     std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending)

@@ -41,13 +41,14 @@ class CreateOpts(ctypes.Structure):
 class PcOpts(ctypes.Structure):
     _fields_ = [('homog', ctypes.c_int32), ('nboxes', ctypes.c_int32), ('boxes', ctypes.c_void_p),
                 ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32),
-                ('proxy', ctypes.c_int32), ('refine_steps', ctypes.c_int32), ('keep_zero_rows', ctypes.c_int32)]
+                ('proxy', ctypes.c_int32), ('refine_steps', ctypes.c_int32), ('keep_zero_rows', ctypes.c_int32),
+                ('levels', ctypes.c_int32)]
 
 
 class PcInfo(ctypes.Structure):
     _fields_ = [('nboxes', ctypes.c_int32), ('box_nx', ctypes.c_int32), ('block_m', ctypes.c_int32),
                 ('modes', ctypes.c_int32), ('stored_blocks', ctypes.c_int32), ('factor_bytes', ctypes.c_int64),
-                ('active_m', ctypes.c_int32)]
+                ('active_m', ctypes.c_int32), ('levels', ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -216,19 +217,20 @@ class Preconditioner:
     """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
 
     def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, proxy='product',
-                 refine=None, keep_zero_rows=False, stream=None):
+                 refine=None, keep_zero_rows=False, levels=1, stream=None):
         """``factor_prec``: VIE_C128 (FP64 solves), VIE_C64 or VIE_BF16C (mixed-precision
         solves, complex64 vectors); ``proxy``: 'product' or 'centre' reading of the
         memory-reduction proxy column; ``refine``: refinement steps of the bfloat16 block
         solves (default 1 for VIE_BF16C, else 0); ``keep_zero_rows``: factorise the full
-        cross-section even where the homogenised contrast is zero."""
+        cross-section even where the homogenised contrast is zero; ``levels``: 1 or 2 (the
+        2-level circulant, one 3*bz block per (x-mode, y-mode) pair)."""
         lib = load()
         self.op = op
         bx = None
         if refine is None:
             refine = 1 if factor_prec == VIE_BF16C else 0
         o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, {'product': 0, 'centre': 1}[proxy], int(refine),
-                   1 if keep_zero_rows else 0)
+                   1 if keep_zero_rows else 0, int(levels))
         if boxes is not None:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
             o.nboxes = bx.shape[0]

@@ -208,3 +208,13 @@ def serving_stream(n, rate, tag, max_rhs=16):
         t += g.exponential(1.0 / rate)
         out.append((t, int(g.integers(0, ndev)), int(g.integers(1, max_rhs + 1))))
     return out
+
+
+def disk(grid, delta, radius):
+    """Si disk of the given radius centred in the (x, y) box, through every z layer (the disk of
+    the resonator in Sec. 5.3, without its bus waveguide)."""
+    nx, ny, nz = grid
+    x = (np.arange(nx) + 0.5) * delta - 0.5 * nx * delta
+    y = (np.arange(ny) + 0.5) * delta - 0.5 * ny * delta
+    mask2 = (x[None, :] ** 2 + y[:, None] ** 2) < radius ** 2   # [ny, nx]
+    return chi_from_mask(np.broadcast_to(mask2, (nz, ny, nx)).copy())

@@ -98,6 +98,8 @@ def test_argument_errors(gpu_lib):
         lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (4, 0, 0, 3, 4, 2)]),  # shapes
         lambda: gpu_lib.Preconditioner(op, reduce_tol=-1.0),
         lambda: gpu_lib.Preconditioner(op, homog='none', boxes=None, factor_prec=7),
+        lambda: gpu_lib.Preconditioner(op, levels=3),
+        lambda: gpu_lib.Preconditioner(op, levels=2, reduce_tol=1e-3),                # 2-level: no reduction
     ]
     for f in cases:
         with pytest.raises(gpu_lib.VieError) as e:
@@ -109,6 +111,13 @@ def test_argument_errors(gpu_lib):
     with pytest.raises(gpu_lib.VieError) as e:
         gpu_lib.Preconditioner(op2, homog='none')      # contrast varies along x
     assert e.value.status == -1 and 'x' in str(e.value)
+    chi3 = W.waveguide((8, 6, 2))
+    chi3[:, 0, :] = 0.0                                 # x-invariant, varies along y
+    op3 = gpu_lib.Operator((8, 6, 2), 25e-9, KB, chi3)
+    with pytest.raises(gpu_lib.VieError) as e:
+        gpu_lib.Preconditioner(op3, homog='none', levels=2)
+    assert e.value.status == -1 and 'along y' in str(e.value)
+    gpu_lib.Preconditioner(op3, homog='mode', levels=2)  # the modal average is y-invariant
     b = torch.zeros(op.n, dtype=torch.complex128, device='cuda')
     b[0] = 1
     x = torch.zeros_like(b)
