@@ -59,7 +59,7 @@ def good_length(n):
         L += 1
 
 
-def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0):
+def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, restart=50):
     """Per-launch algorithmic work of the dominant kernels: (bound, amount, unit).
 
     block_solve at few right-hand sides: every stored factor read once + rhat in + zhat out
@@ -80,7 +80,16 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0):
         bs = ('mfma', 8.0 * m * m * modes * R * (3 if refine else 1), 'flops')
     else:
         bs = ('hbm', stored * m * m * f + R * modes * (2 * m * v + 4 * m), 'bytes')
-    return {'block_solve': bs, 'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes')}
+    models = {'block_solve': bs, 'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes')}
+    if iters:
+        # CGS2 per Arnoldi step j (index within its cycle): each of the two dot passes reads the
+        # j+1 basis vectors and w once; each update pass also writes w.  Average per launch.
+        pv = 16 if mode == 'fp64' else 8
+        js = [it % restart for it in range(iters)]
+        n3 = 3 * N
+        models['arnoldi_dots'] = ('hbm', sum(((j + 1) * pv + 16) * n3 * R for j in js) / len(js), 'bytes')
+        models['arnoldi_update'] = ('hbm', sum(((j + 1) * pv + 32) * n3 * R for j in js) / len(js), 'bytes')
+    return models
 
 
 def counter_traffic(kernel, workload_tag):
@@ -203,6 +212,9 @@ def workload_plan(cfg, tag):
         # bfloat16 factors with one FP32 refinement step of every block solve
         return dict(mode='mixed', homog='none', reduce_tol=None, boxes=None, factor='bf16',
                     label='full cross-section, BF16 factors + FP32 refinement')
+    if tag == 5:   # disk: 2-level circulant (blocks per (x-mode, y-mode) pair), modal-average contrast
+        return dict(mode='fp64', homog='mode', reduce_tol=None, boxes=None, levels=2,
+                    label='2-level, modal-average contrast')
     return dict(mode='fp64', homog='none', reduce_tol=None, boxes=None, label='full 1-level')
 
 
@@ -345,7 +357,7 @@ def main():
     plan = workload_plan(cfg, args.config)
 
     def step(record, mode=None, reduce_tol='default', boxes='default', proxy='product', factor=None,
-             keep_zero_rows=False):
+             keep_zero_rows=False, precond=True):
         mode = mode or plan['mode']
         bxs = plan['boxes'] if boxes == 'default' else boxes
         rt = plan['reduce_tol'] if reduce_tol == 'default' else reduce_tol
@@ -357,14 +369,15 @@ def main():
         ev[1].record(stream)
         print('bench: operator built', file=sys.stderr, flush=True)
         pc = vie.Preconditioner(op, homog=plan['homog'], boxes=bxs, reduce_tol=rt, factor_prec=fp, proxy=proxy,
-                                keep_zero_rows=keep_zero_rows)
+                                keep_zero_rows=keep_zero_rows, levels=plan.get('levels', 1)) if precond else None
         ev[2].record(stream)
         print('bench: preconditioner set up (%s factors)' % factor, file=sys.stderr, flush=True)
         op.rhs(e_d, b_d, nrhs=R)
         st = vie.solve(op, pc, b_d, x_d, nrhs=R, tol=1e-6, restart=50, mode=mode)
         ev[3].record(stream)
-        info = pc.info()
-        pc.close()
+        info = pc.info() if pc is not None else dict(stored_blocks=0, active_m=0, block_m=0, modes=0)
+        if pc is not None:
+            pc.close()
         op.close()
         print('bench: %s solve done: %d iterations, relres %.3e' % (mode, max(q['iters'] for q in st),
                                                                      max(q['relres'] for q in st)),
@@ -415,9 +428,13 @@ def main():
     if args.no_compare:
         pass
     elif plan['mode'] == 'fp64':
-        # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column
-        for label, kw in (('reduced_1e-3', dict(reduce_tol=1e-3)),
-                          ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre'))):
+        # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column;
+        # the 2-level disk against no preconditioner
+        legs = (('reduced_1e-3', dict(reduce_tol=1e-3)),
+                ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre')))
+        if plan.get('levels') == 2:
+            legs = (('unpreconditioned', dict(precond=False)),)
+        for label, kw in legs:
             rr = []
             if not args.no_autotune:   # tune this leg's new shapes outside its timing, like the main run
                 step(None, **kw)
@@ -455,7 +472,8 @@ def main():
         compare['fp64_over_mixed_time'] = compare['fp64']['ms'] / ms_per_step
     info = last['info']
     factor = last['factor']
-    models = algorithmic_models(cfg, info, R, plan['mode'], factor, refine=1 if factor == 'bf16' else 0)
+    models = algorithmic_models(cfg, info, R, plan['mode'], factor, refine=1 if factor == 'bf16' else 0,
+                                iters=last['iters'])
 
     # dominant kernel and its roofline
     dom = max(names, key=lambda k: kern[k]['total_ms'])
@@ -501,9 +519,10 @@ def main():
         'vs_baseline': None,
         'dtype': 'c128' if plan['mode'] == 'fp64' else ('c64+bf16+f64' if factor == 'bf16' else 'c64+f64'),
         'data': 'synthetic',
-        'config': {'workload': cfg['name'] + ', %s, 1-level Chan-Olkin %s (%d blocks of %dx%d: the %d rows of the '
-                   '%d-row cross-section with nonzero contrast), GMRES(50) to 1e-6'
-                   % (plan['mode'], plan['label'], info['stored_blocks'], info['active_m'], info['active_m'],
+        'config': {'workload': cfg['name'] + ', %s, %d-level Chan-Olkin %s (%d blocks of %dx%d: the %d rows of the '
+                   '%d-row block with nonzero contrast), GMRES(50) to 1e-6'
+                   % (plan['mode'], plan.get('levels', 1), plan['label'], info['stored_blocks'], info['active_m'],
+                      info['active_m'],
                       info['active_m'], info['block_m']),
                    'grid': list(grid), 'voxel_m': delta, 'nrhs': R, 'precision': plan['mode']},
         'compare': compare or None,

@@ -102,6 +102,8 @@ CONFIGS = {
             geometry='bragg', nrhs=1, wy=0.25e-6, wz=0.1e-6),
     4: dict(name='Si directional coupler 1024x48x8 @ 25 nm, 64 RHS', grid=(1024, 48, 8),
             delta=25e-9, geometry='coupler', nrhs=64, wy=0.2e-6, wz=0.1e-6),
+    5: dict(name='Si disk 64x64x8 @ 25 nm (0.8 um radius)', grid=(64, 64, 8), delta=25e-9,
+            geometry='disk', nrhs=1, wy=0.2e-6, wz=0.1e-6),
 }
 
 
@@ -114,6 +116,8 @@ def make_chi(cfg):
         return bragg(grid, delta)
     if geom == 'coupler':
         return coupler(grid)
+    if geom == 'disk':
+        return disk(grid, delta, 0.5 * min(grid[0], grid[1]) * delta)
     raise ValueError(geom)
 
 
