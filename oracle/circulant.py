@@ -244,15 +244,19 @@ class BlockedPreconditioner:
     """
 
     def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product', levels=1):
+        """``homog`` and ``levels`` apply to every box, or are lists with one entry per box."""
         from .contrast import homogenize
         nx, ny, nz = grid
         self.grid = grid
         self.boxes = boxes or [(0, 0, 0, nx, ny, nz)]
         M = np.asarray(M, dtype=np.complex128)
+        nb = len(self.boxes)
+        homogs = list(homog) if isinstance(homog, (list, tuple)) else [homog] * nb
+        levs = list(levels) if isinstance(levels, (list, tuple)) else [levels] * nb
         self.parts = []
-        for (x0, y0, z0, bx, by, bz) in self.boxes:
-            Mt = homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], homog)
-            if levels == 2:
+        for (x0, y0, z0, bx, by, bz), hk, lev in zip(self.boxes, homogs, levs):
+            Mt = homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], hk)
+            if lev == 2:
                 Mt = np.broadcast_to(Mt, (bz, by))
                 if not np.all(Mt == Mt[:, :1]):
                     raise ValueError('the 2-level circulant needs a contrast that does not vary along y')

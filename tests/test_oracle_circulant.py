@@ -308,3 +308,32 @@ def test_two_level_with_one_y_layer_is_one_level():
     assert np.abs(z2 - z1).max() < 1e-13 * np.abs(z1).max()
     z0 = C.BlockCirculantInverse2(K, np.zeros(nz), nx, ny, nz).apply(r)
     assert np.abs(z0 - r).max() < 1e-14
+
+
+def test_blocked_boxes_of_different_shapes_and_levels_equal_dense_block_diagonal():
+    """A 1-level box (mean contrast) beside a 2-level box of another shape (modal contrast), with
+    voxels outside both: the blocked apply equals the dense block-diagonal of the per-box dense
+    circulant inverses (the 1-level one built elementwise, the 2-level one from its twin)."""
+    grid = (7, 6, 2)
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    rng = np.random.default_rng(31)
+    M = 0.7 + 0.2 * rng.standard_normal((nz, ny, nx)) - 0.03j
+    M[:, 2:, 1:6] = 0.65 - 0.01j                       # the 2-level box: one dominant value (its mode)
+    boxes = [(0, 0, 0, 7, 2, 2), (1, 2, 0, 5, 4, 2)]   # x column 0 and 6 of rows 2.. uncovered
+    P = C.BlockedPreconditioner(K, M, grid, boxes=boxes, homog=['mean', 'mode'], levels=[1, 2])
+    n = nx * ny * nz
+    Pd = np.eye(3 * n, dtype=complex)
+    idx = lambda a, x, y, z: a * n + x + nx * (y + ny * z)
+    for (x0, y0, z0, bx, by, bz), hk, lev in zip(boxes, ['mean', 'mode'], [1, 2]):
+        Mt = CT.homogenize(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx], hk)
+        if lev == 1:
+            CB, _ = _dense_block_circulant(K, Mt, (bx, by, bz))
+        else:
+            CB = _dense_two_level(K, Mt[:, 0], (bx, by, bz))
+        Cinv = np.linalg.inv(CB)
+        loc = [idx(a, x0 + x, y0 + y, z0 + z) for a in range(3) for z in range(bz)
+               for y in range(by) for x in range(bx)]
+        Pd[np.ix_(loc, loc)] = Cinv
+    r = rng.standard_normal(3 * n) + 1j * rng.standard_normal(3 * n)
+    assert np.allclose(P.apply(r), Pd @ r, rtol=1e-12, atol=1e-12)
