@@ -119,8 +119,9 @@ typedef struct {
     int32_t homog;       /* vie_homog */
     int32_t nboxes;      /* 0 = one box covering the whole grid */
     const int32_t *boxes;/* HOST, nboxes*6: {x0, y0, z0, bx, by, bz} per box; boxes must
-                            lie inside the grid, must not overlap and (this build) share
-                            one shape.  Voxels outside every box are left unchanged
+                            lie inside the grid and must not overlap; they may differ in
+                            shape (boxes of one shape, level and homogenisation share one
+                            factor store).  Voxels outside every box are left unchanged
                             (Sec. 5.3: blocked-circulant preconditioner). */
     int32_t reduce;      /* 1 = memory-reduced 1-level preconditioner (Sec. 5.1.1) */
     double reduce_tol;   /* keep mode k iff |v_k|/||v||_inf > reduce_tol (paper: 1e-3) */
@@ -147,6 +148,11 @@ typedef struct {
                             that does not vary along y (e.g. homog = MODE, the modal average),
                             factor_prec VIE_C128 or VIE_C64, no memory reduction; keep_zero_rows
                             does not apply. */
+    const int32_t *box_levels; /* HOST, nboxes entries or NULL: the level of each box, in place
+                            of `levels` (Sec. 5.3: e.g. a 1-level box around a bus guide and a
+                            2-level box around a disk) */
+    const int32_t *box_homog;  /* HOST, nboxes entries or NULL: the vie_homog of each box, in
+                            place of `homog` */
 } vie_pc_opts;
 
 typedef struct {

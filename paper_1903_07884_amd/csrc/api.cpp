@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, handle ownership, orchestration.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -161,56 +162,14 @@ extern "C" vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs
     return launch_matvec(op, x, y, nrhs, prec, (hipStream_t)stream);
 }
 
-extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *stream, vie_pc *out) {
-    if (!out) return arg_error("precond_setup: out is NULL");
-    *out = nullptr;
-    if (!op || !opts) return arg_error("precond_setup: NULL argument");
-    const vie_pc_opts &o = *opts;
-    if (o.homog < VIE_HOMOG_NONE || o.homog > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown homog");
-    if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
-        return arg_error("precond_setup: unknown factor precision");
-    if (o.refine_steps < 0 || o.refine_steps > 1) return arg_error("precond_setup: refine_steps must be 0 or 1");
-    if (o.refine_steps && o.factor_prec != VIE_BF16C)
-        return arg_error("precond_setup: refine_steps needs VIE_BF16C factors");
-    if (o.keep_zero_rows != 0 && o.keep_zero_rows != 1)
-        return arg_error("precond_setup: keep_zero_rows must be 0 or 1");
-    if (o.levels < 0 || o.levels > 2) return arg_error("precond_setup: levels must be 0, 1 or 2");
-    if (o.levels == 2 && (o.reduce || o.factor_prec == VIE_BF16C))
-        return arg_error("precond_setup: the 2-level circulant takes VIE_C128 or VIE_C64 factors and no memory reduction");
-    if (o.factor_prec == VIE_BF16C && !op->has_c64)
-        return arg_error("precond_setup: VIE_BF16C factors need an operator built with build_c64");
-    if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
-    if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
-        return arg_error("precond_setup: reduce_tol must be finite and >= 0");
-    std::vector<int> boxes;
-    if (o.nboxes < 0) return arg_error("precond_setup: nboxes < 0");
-    if (o.nboxes == 0) {
-        boxes = {0, 0, 0, op->nx, op->ny, op->nz};
-    } else {
-        if (!o.boxes) return arg_error("precond_setup: boxes is NULL");
-        boxes.assign(o.boxes, o.boxes + 6 * o.nboxes);
-    }
-    int nb = (int)boxes.size() / 6;
-    const int dims[3] = {op->nx, op->ny, op->nz};
-    long long vol = 0;
-    for (int b = 0; b < nb; ++b) {
-        const int *B = &boxes[6 * b];
-        for (int a = 0; a < 3; ++a)
-            if (B[a] < 0 || B[3 + a] < 1 || B[a] + B[3 + a] > dims[a])
-                return arg_error("precond_setup: box " + std::to_string(b) + " outside the grid");
-        for (int a = 3; a < 6; ++a)
-            if (B[a] != boxes[a]) return arg_error("precond_setup: all boxes must share one shape");
-        for (int c = 0; c < b; ++c) {
-            const int *C = &boxes[6 * c];
-            bool ov = true;
-            for (int a = 0; a < 3; ++a)
-                if (B[a] + B[3 + a] <= C[a] || C[a] + C[3 + a] <= B[a]) ov = false;
-            if (ov) return arg_error("precond_setup: boxes overlap");
-        }
-        vol += (long long)B[3] * B[4] * B[5];
-    }
-    int bx = boxes[3], by = boxes[4], bz = boxes[5], m = 3 * by * bz;
-    size_t esz = o.factor_prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+// One preconditioner over boxes that share shape, level and homogenisation (the boxes were
+// validated by the caller).  covers_all: the boxes cover the grid (else the apply copies r to z
+// first); a group inside a composite is built with covers_all = true, the composite copies.
+static vie_status build_group(vie_op op, const vie_pc_opts &o, const std::vector<int> &boxes, int levels,
+                              bool covers_all, hipStream_t s, vie_pc *out) {
+    const int nb = (int)boxes.size() / 6;
+    const int bx = boxes[3], by = boxes[4], bz = boxes[5];
+    int m = 3 * by * bz;
     if (!fft_supported_length(bx))
         return arg_error("precond_setup: box length " + std::to_string(bx) + " has a prime factor above " +
                          std::to_string(VIE_FFT_MAX_PRIME));
@@ -222,8 +181,9 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
         fft_line_shape(tmp, sizeof(c128), &thr, &lds, &bpt);
         if (lds > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
     }
-    const int levels = o.levels == 2 ? 2 : 1;
     if (levels == 2) {
+        if (o.reduce || o.factor_prec == VIE_BF16C)
+            return arg_error("precond_setup: the 2-level circulant takes VIE_C128 or VIE_C64 factors and no memory reduction");
         if (!fft_supported_length(by))
             return arg_error("precond_setup: box width " + std::to_string(by) + " has a prime factor above " +
                              std::to_string(VIE_FFT_MAX_PRIME));
@@ -244,15 +204,121 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     pc->m = m;
     pc->m_full = m;
     pc->boxes = boxes;
-    pc->covers_all = vol == op->N;
+    pc->covers_all = covers_all;
     pc->prec = o.factor_prec;
     pc->refine = o.refine_steps;
-    vie_status st = pc_build(pc, &o, (hipStream_t)stream);
+    vie_status st = pc_build(pc, &o, s);
     if (st < 0) {
         delete pc;
         return st;
     }
     *out = pc;
+    return VIE_OK;
+}
+
+extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *stream, vie_pc *out) {
+    if (!out) return arg_error("precond_setup: out is NULL");
+    *out = nullptr;
+    if (!op || !opts) return arg_error("precond_setup: NULL argument");
+    const vie_pc_opts &o = *opts;
+    if (o.homog < VIE_HOMOG_NONE || o.homog > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown homog");
+    if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
+        return arg_error("precond_setup: unknown factor precision");
+    if (o.refine_steps < 0 || o.refine_steps > 1) return arg_error("precond_setup: refine_steps must be 0 or 1");
+    if (o.refine_steps && o.factor_prec != VIE_BF16C)
+        return arg_error("precond_setup: refine_steps needs VIE_BF16C factors");
+    if (o.keep_zero_rows != 0 && o.keep_zero_rows != 1)
+        return arg_error("precond_setup: keep_zero_rows must be 0 or 1");
+    if (o.levels < 0 || o.levels > 2) return arg_error("precond_setup: levels must be 0, 1 or 2");
+    if (o.factor_prec == VIE_BF16C && !op->has_c64)
+        return arg_error("precond_setup: VIE_BF16C factors need an operator built with build_c64");
+    if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
+    if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
+        return arg_error("precond_setup: reduce_tol must be finite and >= 0");
+    std::vector<int> boxes;
+    if (o.nboxes < 0) return arg_error("precond_setup: nboxes < 0");
+    if (o.nboxes == 0) {
+        boxes = {0, 0, 0, op->nx, op->ny, op->nz};
+    } else {
+        if (!o.boxes) return arg_error("precond_setup: boxes is NULL");
+        boxes.assign(o.boxes, o.boxes + 6 * o.nboxes);
+    }
+    int nb = (int)boxes.size() / 6;
+    const int dims[3] = {op->nx, op->ny, op->nz};
+    long long vol = 0;
+    std::vector<int> lev(nb), hom(nb);
+    for (int b = 0; b < nb; ++b) {
+        const int *B = &boxes[6 * b];
+        for (int a = 0; a < 3; ++a)
+            if (B[a] < 0 || B[3 + a] < 1 || B[a] + B[3 + a] > dims[a])
+                return arg_error("precond_setup: box " + std::to_string(b) + " outside the grid");
+        for (int c = 0; c < b; ++c) {
+            const int *C = &boxes[6 * c];
+            bool ov = true;
+            for (int a = 0; a < 3; ++a)
+                if (B[a] + B[3 + a] <= C[a] || C[a] + C[3 + a] <= B[a]) ov = false;
+            if (ov) return arg_error("precond_setup: boxes overlap");
+        }
+        vol += (long long)B[3] * B[4] * B[5];
+        const int lv = o.nboxes > 0 && o.box_levels ? o.box_levels[b] : o.levels;
+        const int hm = o.nboxes > 0 && o.box_homog ? o.box_homog[b] : o.homog;
+        if (lv < 0 || lv > 2) return arg_error("precond_setup: box_levels entries must be 0, 1 or 2");
+        if (hm < VIE_HOMOG_NONE || hm > VIE_HOMOG_REALMEAN) return arg_error("precond_setup: unknown box_homog entry");
+        lev[b] = lv == 2 ? 2 : 1;
+        hom[b] = hm;
+    }
+    // group the boxes by (shape, level, homogenisation): one factor store per group
+    std::vector<std::vector<int>> groups;  // box indices
+    for (int b = 0; b < nb; ++b) {
+        bool placed = false;
+        for (auto &g : groups) {
+            const int f = g[0];
+            bool same = lev[f] == lev[b] && hom[f] == hom[b];
+            for (int a = 3; a < 6; ++a) same = same && boxes[6 * f + a] == boxes[6 * b + a];
+            if (same) {
+                g.push_back(b);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) groups.push_back({b});
+    }
+    const bool covers_all = vol == op->N;
+    hipStream_t s = (hipStream_t)stream;
+    auto group_boxes = [&](const std::vector<int> &g) {
+        std::vector<int> gb;
+        for (int b : g) gb.insert(gb.end(), boxes.begin() + 6 * b, boxes.begin() + 6 * b + 6);
+        return gb;
+    };
+    if (groups.size() == 1) {
+        vie_pc_opts go = o;
+        go.homog = hom[0];
+        return build_group(op, go, group_boxes(groups[0]), lev[0], covers_all, s, out);
+    }
+    vie_pc parent = new (std::nothrow) vie_pc_s();
+    if (!parent) return VIE_EOOM;
+    parent->op = op;
+    parent->nboxes = nb;
+    parent->boxes = boxes;
+    parent->covers_all = covers_all;
+    parent->prec = o.factor_prec;
+    parent->refine = o.refine_steps;
+    for (auto &g : groups) {
+        vie_pc_opts go = o;
+        go.homog = hom[g[0]];
+        vie_pc child = nullptr;
+        const vie_status st = build_group(op, go, group_boxes(g), lev[g[0]], true, s, &child);
+        if (st < 0) {
+            delete parent;
+            return st;
+        }
+        parent->children.push_back(child);
+        parent->nstored += child->nstored;
+        parent->levels = std::max(parent->levels, child->levels);
+        parent->m = std::max(parent->m, child->m);
+        parent->m_full = std::max(parent->m_full, child->m_full);
+    }
+    *out = parent;
     return VIE_OK;
 }
 
@@ -284,27 +350,42 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, const vie_pc_o
         if (o.factor_prec != VIE_C128 && o.factor_prec != VIE_C64 && o.factor_prec != VIE_BF16C)
             return arg_error("vie_footprint: unknown factor precision");
         if (o.nboxes < 0 || (o.nboxes > 0 && !o.boxes)) return arg_error("vie_footprint: bad boxes");
-        const int *B = o.nboxes ? o.boxes : nullptr;
-        const uint64_t nb = o.nboxes ? o.nboxes : 1;
-        const uint64_t bx = B ? B[3] : nx, by = B ? B[4] : ny, bz = B ? B[5] : nz;
-        if (bx < 1 || by < 1 || bz < 1) return arg_error("vie_footprint: bad box shape");
-        const bool two = o.levels == 2;
-        const uint64_t m = two ? 3 * bz : 3 * by * bz, modes = two ? nb * bx * by : nb * bx;
+        const int nbox = o.nboxes ? o.nboxes : 1;
+        // group the boxes by shape and level (one factor store each) and sum the groups
+        std::vector<std::array<int, 5>> groups;  // bx, by, bz, level, count
+        for (int b = 0; b < nbox; ++b) {
+            const int *B = o.nboxes ? o.boxes + 6 * b : nullptr;
+            const int gbx = B ? B[3] : nx, gby = B ? B[4] : ny, gbz = B ? B[5] : nz;
+            if (gbx < 1 || gby < 1 || gbz < 1) return arg_error("vie_footprint: bad box shape");
+            const int lv = (o.nboxes && o.box_levels ? o.box_levels[b] : o.levels) == 2 ? 2 : 1;
+            bool found = false;
+            for (auto &g : groups)
+                if (g[0] == gbx && g[1] == gby && g[2] == gbz && g[3] == lv) {
+                    g[4]++;
+                    found = true;
+                }
+            if (!found) groups.push_back({gbx, gby, gbz, lv, 1});
+        }
         const uint64_t fesz = o.factor_prec == VIE_C128 ? 16 : o.factor_prec == VIE_BF16C ? 4 : 8;
         const uint64_t vesz = o.factor_prec == VIE_C128 ? 16 : 8;  // vector / factorisation precision
-        const uint64_t table = bx * 6 * (2 * by - 1) * (2 * bz - 1) + (two ? bx * by * 6 * (2 * bz - 1) : 0);
-        uint64_t pcb = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
-        if (o.factor_prec == VIE_BF16C) pcb += modes * m * m * 8;        // complex-float factorisation copy
-        pcb += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;       // Chan table, LU workspace
-        if (o.refine_steps || !o.keep_zero_rows) pcb += table * 8 + nb * by * bz * 8;
-        if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pcb += table * 16 + nb * by * bz * 16;
-        pcb += m * 4 + 64;  // row order, coupling flag
-        *pc_held = pcb;
-        // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
-        const uint64_t cols = modes * R;
-        const uint64_t wide = (cols + 64 * modes) * m * vesz;
-        *apply_scratch = R * nb * m * (modes / nb) * vesz + wide * (o.refine_steps ? 2 : 1);
-        if (two) *apply_scratch += R * nb * 3 * by * bz * bx * vesz + 4 * 3 * by * bz;  // x-stage lines
+        for (const auto &g : groups) {
+            const uint64_t bx = g[0], by = g[1], bz = g[2], nb = g[4];
+            const bool two = g[3] == 2;
+            const uint64_t m = two ? 3 * bz : 3 * by * bz, modes = two ? nb * bx * by : nb * bx;
+            const uint64_t table = bx * 6 * (2 * by - 1) * (2 * bz - 1) + (two ? bx * by * 6 * (2 * bz - 1) : 0);
+            uint64_t pcb = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
+            if (o.factor_prec == VIE_BF16C) pcb += modes * m * m * 8;        // complex-float factorisation copy
+            pcb += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;       // Chan table, LU workspace
+            if (o.refine_steps || !o.keep_zero_rows) pcb += table * 8 + nb * by * bz * 8;
+            if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pcb += table * 16 + nb * by * bz * 16;
+            pcb += 3 * by * bz * 4 + 64;  // row orders, coupling flag
+            *pc_held += pcb;
+            // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
+            const uint64_t cols = modes * R;
+            const uint64_t wide = (cols + 64 * modes) * m * vesz;
+            *apply_scratch += R * nb * m * (modes / nb) * vesz + wide * (o.refine_steps ? 2 : 1);
+            if (two) *apply_scratch += R * nb * 3 * by * bz * bx * vesz;  // x-stage lines
+        }
     }
     if (so) {
         if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
@@ -343,6 +424,22 @@ vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts 
 
 extern "C" vie_status precond_info(vie_pc pc, vie_pc_info *info) {
     if (!pc || !info) return arg_error("precond_info: NULL argument");
+    if (!pc->children.empty()) {  // boxes of several shapes / levels: sums over the groups
+        vie_pc_info ci{};
+        *info = vie_pc_info{};
+        info->nboxes = pc->nboxes;
+        for (vie_pc c : pc->children) {
+            VIE_CHECK(precond_info(c, &ci));
+            info->box_nx = std::max(info->box_nx, ci.box_nx);
+            info->block_m = std::max(info->block_m, ci.block_m);
+            info->active_m = std::max(info->active_m, ci.active_m);
+            info->levels = std::max(info->levels, ci.levels);
+            info->modes += ci.modes;
+            info->stored_blocks += ci.stored_blocks;
+            info->factor_bytes += ci.factor_bytes;
+        }
+        return VIE_OK;
+    }
     info->nboxes = pc->nboxes;
     info->box_nx = pc->bx;
     info->block_m = pc->m_full;

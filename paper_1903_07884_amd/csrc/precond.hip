@@ -1089,6 +1089,14 @@ vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipSt
         vie_set_error("precond_apply: vector precision must be the factor precision (complex64 for BF16 factors)");
         return VIE_EARG;
     }
+    if (!pc->children.empty()) {  // groups of boxes: copy r to z once, then each group writes its boxes
+        if (!pc->covers_all) {
+            const size_t esz = prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+            VIE_HIP(hipMemcpyAsync(z, r, esz * 3 * pc->op->N * nrhs, hipMemcpyDeviceToDevice, s));
+        }
+        for (vie_pc c : pc->children) VIE_CHECK(pc_apply(c, r, z, nrhs, prec, s));
+        return VIE_OK;
+    }
     if (prec == VIE_C128) return apply_t<double>(pc, (const c128 *)r, (c128 *)z, nrhs, s);
     return apply_t<float>(pc, (const c64 *)r, (c64 *)z, nrhs, s);
 }

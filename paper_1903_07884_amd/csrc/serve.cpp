@@ -45,7 +45,7 @@ struct Req {
     int nrhs = 0;
     int precond = 0;
     vie_pc_opts pco{};
-    std::vector<int32_t> boxes;
+    std::vector<int32_t> boxes, box_levels, box_homog;
     vie_solve_opts so{};
     double *x_out = nullptr;
     vie_solve_stats *st_out = nullptr;
@@ -350,9 +350,20 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
     r->nrhs = req->nrhs;
     r->precond = req->precond != 0;
     r->pco = req->pc;
+    r->pco.boxes = nullptr;
+    r->pco.box_levels = r->pco.box_homog = nullptr;
     if (r->precond && req->pc.nboxes > 0) {
-        r->boxes.assign(req->pc.boxes, req->pc.boxes + 6 * req->pc.nboxes);
+        const int nb = req->pc.nboxes;
+        r->boxes.assign(req->pc.boxes, req->pc.boxes + 6 * nb);
         r->pco.boxes = r->boxes.data();
+        if (req->pc.box_levels) {
+            r->box_levels.assign(req->pc.box_levels, req->pc.box_levels + nb);
+            r->pco.box_levels = r->box_levels.data();
+        }
+        if (req->pc.box_homog) {
+            r->box_homog.assign(req->pc.box_homog, req->pc.box_homog + nb);
+            r->pco.box_homog = r->box_homog.data();
+        }
     }
     r->so = req->solve;
     r->x_out = x_out;
@@ -377,9 +388,12 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
     r->key = buf;
     if (r->precond) {
         const vie_pc_opts &p = r->pco;
-        snprintf(buf, sizeof buf, "|pc %d %d %016llx %d %a %d %d %d %d", p.homog, p.nboxes,
-                 (unsigned long long)fnv1a(r->boxes.data(), sizeof(int32_t) * r->boxes.size()), p.reduce,
-                 p.reduce ? p.reduce_tol : 0.0, p.factor_prec, p.proxy, p.refine_steps, p.keep_zero_rows);
+        uint64_t hb = fnv1a(r->boxes.data(), sizeof(int32_t) * r->boxes.size());
+        hb = fnv1a(r->box_levels.data(), sizeof(int32_t) * r->box_levels.size(), hb);
+        hb = fnv1a(r->box_homog.data(), sizeof(int32_t) * r->box_homog.size(), hb);
+        snprintf(buf, sizeof buf, "|pc %d %d %016llx %d %a %d %d %d %d %d", p.homog, p.nboxes, (unsigned long long)hb,
+                 p.reduce, p.reduce ? p.reduce_tol : 0.0, p.factor_prec, p.proxy, p.refine_steps, p.keep_zero_rows,
+                 p.levels);
         r->key += buf;
     }
     snprintf(buf, sizeof buf, "|so %a %d %d %d", r->so.tol, r->so.restart, r->so.maxit, r->so.mode);

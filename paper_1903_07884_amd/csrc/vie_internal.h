@@ -178,16 +178,22 @@ struct vie_op_s {
 };
 
 struct vie_pc_s {
-    vie_op op;
-    int nboxes, bx, by, bz;
+    vie_op op = nullptr;
+    int nboxes = 0, bx = 0, by = 0, bz = 0;
     int levels = 1;          // 1: blocks per x-mode; 2: blocks per (x-mode, y-mode) pair
-    int nm;                  // modes per box: bx (1-level) or bx*by (2-level, mode ky*bx + kx)
-    int m;                   // order of the factorised blocks (active rows)
-    int m_full;              // 3*by*bz rows of a box cross-section
+    int nm = 0;              // modes per box: bx (1-level) or bx*by (2-level, mode ky*bx + kx)
+    int m = 0;               // order of the factorised blocks (active rows)
+    int m_full = 0;          // 3*by*bz rows of a box cross-section
+    // boxes of several shapes / levels / homogenisations: one preconditioner per group, applied
+    // in turn (this handle then holds no factors of its own)
+    std::vector<vie_pc_s *> children;
+    ~vie_pc_s() {
+        for (vie_pc_s *c : children) delete c;
+    }
     std::vector<int> boxes;  // nboxes*6
-    bool covers_all;
-    int prec;                // factor precision
-    int nstored;
+    bool covers_all = true;
+    int prec = 0;            // factor precision
+    int nstored = 0;
     std::vector<int> block_of_mode_host;  // [nboxes*bx]
     DevBuf block_of_mode;    // int32 [nboxes*bx] -> stored block index
     DevBuf factors;          // [nstored][m][m] column-major LU (complex, factor precision)

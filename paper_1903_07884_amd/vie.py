@@ -42,7 +42,7 @@ class PcOpts(ctypes.Structure):
     _fields_ = [('homog', ctypes.c_int32), ('nboxes', ctypes.c_int32), ('boxes', ctypes.c_void_p),
                 ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32),
                 ('proxy', ctypes.c_int32), ('refine_steps', ctypes.c_int32), ('keep_zero_rows', ctypes.c_int32),
-                ('levels', ctypes.c_int32)]
+                ('levels', ctypes.c_int32), ('box_levels', ctypes.c_void_p), ('box_homog', ctypes.c_void_p)]
 
 
 class PcInfo(ctypes.Structure):
@@ -221,7 +221,8 @@ class Preconditioner:
         """``factor_prec``: VIE_C128 (FP64 solves), VIE_C64 or VIE_BF16C (mixed-precision
         solves, complex64 vectors); ``proxy``: 'product' or 'centre' reading of the
         memory-reduction proxy column; ``refine``: refinement steps of the bfloat16 block
-        solves (default 1 for VIE_BF16C, else 0); ``keep_zero_rows``: factorise the full
+        solves (default 1 for VIE_BF16C, else 0); ``homog`` and ``levels`` may be lists with
+        one entry per box; ``keep_zero_rows``: factorise the full
         cross-section even where the homogenised contrast is zero; ``levels``: 1 or 2 (the
         2-level circulant, one 3*bz block per (x-mode, y-mode) pair)."""
         lib = load()
@@ -229,12 +230,24 @@ class Preconditioner:
         bx = None
         if refine is None:
             refine = 1 if factor_prec == VIE_BF16C else 0
-        o = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, {'product': 0, 'centre': 1}[proxy], int(refine),
-                   1 if keep_zero_rows else 0, int(levels))
+        per_box_h = isinstance(homog, (list, tuple))
+        per_box_l = isinstance(levels, (list, tuple))
+        o = PcOpts(0 if per_box_h else HOMOG[homog], 0, None, 0, 0.0, factor_prec,
+                   {'product': 0, 'centre': 1}[proxy], int(refine), 1 if keep_zero_rows else 0,
+                   0 if per_box_l else int(levels))
         if boxes is not None:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
             o.nboxes = bx.shape[0]
             o.boxes = bx.ctypes.data
+        self._keep = []
+        if per_box_h:
+            hb = np.ascontiguousarray([HOMOG[h] for h in homog], dtype=np.int32)
+            o.box_homog = hb.ctypes.data
+            self._keep.append(hb)
+        if per_box_l:
+            lb = np.ascontiguousarray(levels, dtype=np.int32)
+            o.box_levels = lb.ctypes.data
+            self._keep.append(lb)
         if reduce_tol is not None:
             o.reduce = 1
             o.reduce_tol = float(reduce_tol)

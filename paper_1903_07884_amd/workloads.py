@@ -222,3 +222,18 @@ def disk(grid, delta, radius):
     y = (np.arange(ny) + 0.5) * delta - 0.5 * ny * delta
     mask2 = (x[None, :] ** 2 + y[:, None] ** 2) < radius ** 2   # [ny, nx]
     return chi_from_mask(np.broadcast_to(mask2, (nz, ny, nx)).copy())
+
+
+def guide_with_lossy_ends(grid, ramp, loss=0.3):
+    """Uniform Si guide whose first and last `ramp` x-voxels carry a growing imaginary part of
+    the contrast (a synthetic lossy termination: Im chi falls linearly to -loss at both ends).
+    It exercises the complex contrast (mean vs real-mean homogenisation); it is not the paper's
+    adiabatic absorber."""
+    nx, ny, nz = grid
+    chi = waveguide(grid).astype(np.complex128)
+    w = np.zeros(nx)
+    t = (np.arange(ramp) + 1) / ramp
+    w[:ramp] = t[::-1]
+    w[nx - ramp:] = t
+    chi = chi - 1j * loss * w[None, None, :]
+    return chi

@@ -95,7 +95,7 @@ def test_argument_errors(gpu_lib):
     cases = [
         lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 9, 4, 2)]),                     # outside
         lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (2, 0, 0, 4, 4, 2)]),  # overlap
-        lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (4, 0, 0, 3, 4, 2)]),  # shapes
+        lambda: gpu_lib.Preconditioner(op, boxes=[(0, 0, 0, 4, 4, 2), (4, 0, 0, 3, 4, 2)], levels=[1, 3]),
         lambda: gpu_lib.Preconditioner(op, reduce_tol=-1.0),
         lambda: gpu_lib.Preconditioner(op, homog='none', boxes=None, factor_prec=7),
         lambda: gpu_lib.Preconditioner(op, levels=3),

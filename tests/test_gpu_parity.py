@@ -421,6 +421,59 @@ def test_two_level_preconditioned_disk_solve(gpu_lib):
     assert its[2] < its[0]
 
 
+MIXED_BOX_CASES = [
+    # grid, geometry, boxes, homog per box, levels per box, nrhs, factor precision
+    ((14, 10, 2), 'bus+disk', [(0, 0, 0, 14, 3, 2), (2, 4, 0, 10, 6, 2)], ['none', 'mode'], [1, 2], 1, 'c128'),
+    ((14, 10, 2), 'bus+disk', [(0, 0, 0, 14, 3, 2), (2, 4, 0, 10, 6, 2)], ['none', 'mode'], [1, 2], 9, 'c128'),
+    ((16, 4, 2), 'lossy', [(0, 0, 0, 10, 4, 2), (10, 0, 0, 6, 4, 2)], ['mean', 'realmean'], [1, 1], 2, 'c128'),
+    ((16, 4, 2), 'lossy', [(0, 0, 0, 10, 4, 2), (10, 0, 0, 6, 4, 2)], ['mean', 'mean'], [1, 1], 2, 'c64'),
+]
+
+
+def _mixed_box_chi(grid, kind):
+    nx, ny, nz = grid
+    if kind == 'lossy':
+        return W.guide_with_lossy_ends(grid, 3)
+    chi = np.zeros((nz, ny, nx), dtype=complex)
+    chi[:, 0:3, :] = 12.11 / 2.085 - 1                      # bus guide
+    yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing='ij')
+    chi[:, (xx - 7.0) ** 2 + (yy - 7.0) ** 2 < 3.6 ** 2] = 12.11 / 2.085 - 1   # disk in the second box
+    return chi
+
+
+@pytest.mark.parametrize("case", MIXED_BOX_CASES)
+def test_boxes_of_different_shapes_levels_and_homogenisations(gpu_lib, case):
+    """Blocked-circulant preconditioner (Sec. 5.3) over boxes that differ in shape, circulant level
+    and homogenisation (a 1-level box around a bus guide beside a 2-level box around a disk; a
+    guide with lossy ends in two boxes of different lengths), against the oracle."""
+    import torch
+    grid, kind, boxes, homog, levels, nrhs, prec = case
+    delta = 25e-9
+    K = oracle_generator(grid, delta)
+    chi = _mixed_box_chi(grid, kind)
+    M = OCT.contrast_from_chi(chi)
+    if kind == 'bus+disk':
+        x0, y0, z0, bx, by, bz = boxes[1]
+        assert np.count_nonzero(M[z0:z0 + bz, y0:y0 + by, x0:x0 + bx]) > bx * by * bz // 2
+    ref_pc = OC.BlockedPreconditioner(K, M, grid, boxes=boxes, homog=homog, levels=levels)
+    c64 = prec == 'c64'
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=c64)
+    pc = gpu_lib.Preconditioner(op, homog=homog, boxes=boxes, levels=levels,
+                                factor_prec=gpu_lib.VIE_C64 if c64 else gpu_lib.VIE_C128)
+    info = pc.info()
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((nrhs, n), 71)
+    z_ref = np.stack([ref_pc.apply(r[i]) for i in range(nrhs)])
+    rd = _to_dev(r.astype(np.complex64) if c64 else r)
+    zd = torch.empty_like(rd)
+    pc.apply(rd, zd, nrhs=nrhs)
+    z = zd.cpu().numpy().astype(np.complex128)
+    err = max(_rel(z[i], z_ref[i]) for i in range(nrhs))
+    print('mixed boxes', kind, homog, levels, nrhs, prec, 'err %.3e' % err, info)
+    assert info['nboxes'] == len(boxes) and info['levels'] == max(levels)
+    assert err < (1e-5 if c64 else 1e-10)
+
+
 def test_autotuned_launches_give_the_same_results(gpu_lib):
     """Autotuning picks launch parameters only: results agree with the defaults to rounding,
     and every tuned shape appears in the report."""
