@@ -21,6 +21,8 @@
                              along y, to the Toeplitz blocks of every D_k; one
                              3nz x 3nz block per mode pair (kx, ky).  Needs a
                              homogenised contrast that does not vary along x or y.
+* ``share_runs``          -- a stronger compression read from the outlook of Sec. 6: runs
+                             of consecutive kept modes with close proxy values share one block.
 * ``BlockedPreconditioner`` -- the blocked-circulant preconditioner of Sec. 5.3:
                              one circulant preconditioner per box, block
                              diagonal; voxels outside every box are left as is.
@@ -147,10 +149,31 @@ def reduction_keep(v, tol):
     return keep, centre
 
 
-class BlockCirculantInverse:
-    """z = C_B^{-1} r for one box (Sec. 4), optionally memory reduced (Sec. 5.1.1)."""
+def share_runs(v, keep, share_tol):
+    """Stronger compression (a reading of the outlook of Sec. 6, not a method the paper gives):
+    walking the kept modes in ascending k, a mode joins the current run while its proxy value
+    is within share_tol (relative) of the run's first mode, |v_k - v_rep| <= share_tol |v_rep|,
+    else it starts a new run.  Returns rep [n]: the representative mode of every kept mode (-1
+    for discarded ones).  share_tol = 0 keeps every kept mode on its own block."""
+    v = np.asarray(v)
+    rep = np.full(len(v), -1)
+    cur = -1
+    for k in range(len(v)):
+        if not keep[k]:
+            continue
+        if cur >= 0 and share_tol > 0 and abs(v[k] - v[cur]) <= share_tol * abs(v[cur]):
+            rep[k] = cur
+        else:
+            cur = k
+            rep[k] = k
+    return rep
 
-    def __init__(self, Koct, Mt, n, ny, nz, reduce_tol=None, proxy='product'):
+
+class BlockCirculantInverse:
+    """z = C_B^{-1} r for one box (Sec. 4), optionally memory reduced (Sec. 5.1.1) and with
+    runs of similar kept modes sharing one block (share_runs)."""
+
+    def __init__(self, Koct, Mt, n, ny, nz, reduce_tol=None, proxy='product', share_tol=0.0):
         self.n, self.ny, self.nz = n, ny, nz
         D = chan_olkin_blocks(Koct, Mt, n, ny, nz)
         if reduce_tol is not None:
@@ -161,6 +184,9 @@ class BlockCirculantInverse:
             self.keep = np.ones(n, dtype=bool)
             self.centre = int(np.ceil(n / 2.0)) - 1
             self.block_of_mode = np.arange(n)
+        if share_tol > 0:
+            rep = share_runs(proxy_values(Koct, n, ny, nz, proxy), self.keep, share_tol)
+            self.block_of_mode = np.where(self.keep, rep, self.block_of_mode)
         self.lu = {}
         for k in np.unique(self.block_of_mode):
             self.lu[int(k)] = scipy.linalg.lu_factor(D[k])
@@ -243,7 +269,8 @@ class BlockedPreconditioner:
     'none', 'mode', 'mean', 'realmean' (Sec. 5.2), applied per box.
     """
 
-    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product', levels=1):
+    def __init__(self, Koct, M, grid, boxes=None, homog='none', reduce_tol=None, proxy='product', levels=1,
+                 share_tol=0.0):
         """``homog`` and ``levels`` apply to every box, or are lists with one entry per box."""
         from .contrast import homogenize
         nx, ny, nz = grid
@@ -262,7 +289,7 @@ class BlockedPreconditioner:
                     raise ValueError('the 2-level circulant needs a contrast that does not vary along y')
                 self.parts.append(BlockCirculantInverse2(Koct, Mt[:, 0], bx, by, bz))
             else:
-                self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol, proxy))
+                self.parts.append(BlockCirculantInverse(Koct, Mt, bx, by, bz, reduce_tol, proxy, share_tol))
 
     def apply(self, r):
         nx, ny, nz = self.grid

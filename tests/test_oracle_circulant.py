@@ -337,3 +337,33 @@ def test_blocked_boxes_of_different_shapes_and_levels_equal_dense_block_diagonal
         Pd[np.ix_(loc, loc)] = Cinv
     r = rng.standard_normal(3 * n) + 1j * rng.standard_normal(3 * n)
     assert np.allclose(P.apply(r), Pd @ r, rtol=1e-12, atol=1e-12)
+
+
+def test_share_runs_rule():
+    """Runs of kept modes: exact grouping on hand-made proxies, tolerance 0 = no sharing,
+    discarded modes untouched, stored count non-increasing in the tolerance."""
+    v = np.array([1.0, 1.004, 1.012, 2.0, 2.01, 0.001, 2.02, 5.0])
+    keep = np.array([True, True, True, True, True, False, True, True])
+    assert list(C.share_runs(v, keep, 0.0)) == [0, 1, 2, 3, 4, -1, 6, 7]
+    assert list(C.share_runs(v, keep, 0.005)) == [0, 0, 2, 3, 3, -1, 6, 7]
+    assert list(C.share_runs(v, keep, 0.02)) == [0, 0, 0, 3, 3, -1, 3, 7]
+    counts = [len(set(C.share_runs(v, keep, t)[keep])) for t in (0.0, 0.005, 0.02, 0.5, 2.0)]
+    assert counts == sorted(counts, reverse=True) and counts[-1] == 1
+
+
+def test_share_runs_apply_uses_the_representative_blocks(box):
+    """With sharing the apply equals the per-mode solve with each run's representative block."""
+    grid, K, Mt = box
+    nx, ny, nz = grid
+    inv = C.BlockCirculantInverse(K, Mt, nx, ny, nz, share_tol=0.3)
+    v = C.proxy_values(K, nx, ny, nz)
+    rep = C.share_runs(v, np.ones(nx, dtype=bool), 0.3)
+    assert list(inv.block_of_mode) == list(rep) and len(set(rep)) < nx
+    r = np.random.default_rng(41).standard_normal((3, nz, ny, nx)) + 0j
+    F = C.dft_matrix(nx)
+    rh = r.reshape(3 * ny * nz, nx) @ F.T
+    zh = np.stack([np.linalg.solve(inv.D[rep[k]], rh[:, k]) for k in range(nx)], axis=1)
+    z = (zh @ np.conj(F).T / nx).reshape(3, nz, ny, nx)
+    assert np.abs(inv.apply(r) - z).max() < 1e-12 * np.abs(z).max()
+    plain = C.BlockCirculantInverse(K, Mt, nx, ny, nz, share_tol=0.0)
+    assert list(plain.block_of_mode) == list(range(nx))
