@@ -347,7 +347,7 @@ def test_share_runs_rule():
     assert list(C.share_runs(v, keep, 0.0)) == [0, 1, 2, 3, 4, -1, 6, 7]
     assert list(C.share_runs(v, keep, 0.005)) == [0, 0, 2, 3, 3, -1, 6, 7]
     assert list(C.share_runs(v, keep, 0.02)) == [0, 0, 0, 3, 3, -1, 3, 7]
-    counts = [len(set(C.share_runs(v, keep, t)[keep])) for t in (0.0, 0.005, 0.02, 0.5, 2.0)]
+    counts = [len(set(C.share_runs(v, keep, t)[keep])) for t in (0.0, 0.005, 0.02, 0.5, 5.0)]
     assert counts == sorted(counts, reverse=True) and counts[-1] == 1
 
 
