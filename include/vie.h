@@ -153,6 +153,13 @@ typedef struct {
                             2-level box around a disk) */
     const int32_t *box_homog;  /* HOST, nboxes entries or NULL: the vie_homog of each box, in
                             place of `homog` */
+    double share_tol;       /* 1-level only; 0 = off.  Stronger compression (a reading of the
+                            outlook of Sec. 6): walking the kept modes in ascending order, a mode
+                            whose proxy value v_k (eq. proxy1) is within share_tol (relative) of
+                            the first mode of the current run uses that mode's block, else it
+                            starts a new run (the central mode of the memory reduction always
+                            starts one).  Fewer stored blocks, an approximate solve for the
+                            shared modes. */
 } vie_pc_opts;
 
 typedef struct {

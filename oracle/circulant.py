@@ -149,19 +149,21 @@ def reduction_keep(v, tol):
     return keep, centre
 
 
-def share_runs(v, keep, share_tol):
+def share_runs(v, keep, share_tol, centre=None):
     """Stronger compression (a reading of the outlook of Sec. 6, not a method the paper gives):
     walking the kept modes in ascending k, a mode joins the current run while its proxy value
     is within share_tol (relative) of the run's first mode, |v_k - v_rep| <= share_tol |v_rep|,
-    else it starts a new run.  Returns rep [n]: the representative mode of every kept mode (-1
-    for discarded ones).  share_tol = 0 keeps every kept mode on its own block."""
+    else it starts a new run.  Under the memory reduction the central mode (whose block the
+    discarded modes use) always starts a run of its own.  Returns rep [n]: the representative
+    mode of every kept mode (-1 for discarded ones).  share_tol = 0 keeps every kept mode on its
+    own block."""
     v = np.asarray(v)
     rep = np.full(len(v), -1)
     cur = -1
     for k in range(len(v)):
         if not keep[k]:
             continue
-        if cur >= 0 and share_tol > 0 and abs(v[k] - v[cur]) <= share_tol * abs(v[cur]):
+        if cur >= 0 and share_tol > 0 and k != centre and abs(v[k] - v[cur]) <= share_tol * abs(v[cur]):
             rep[k] = cur
         else:
             cur = k
@@ -185,7 +187,8 @@ class BlockCirculantInverse:
             self.centre = int(np.ceil(n / 2.0)) - 1
             self.block_of_mode = np.arange(n)
         if share_tol > 0:
-            rep = share_runs(proxy_values(Koct, n, ny, nz, proxy), self.keep, share_tol)
+            rep = share_runs(proxy_values(Koct, n, ny, nz, proxy), self.keep, share_tol,
+                             self.centre if reduce_tol is not None else None)
             self.block_of_mode = np.where(self.keep, rep, self.block_of_mode)
         self.lu = {}
         for k in np.unique(self.block_of_mode):

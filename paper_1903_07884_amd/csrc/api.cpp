@@ -182,7 +182,7 @@ static vie_status build_group(vie_op op, const vie_pc_opts &o, const std::vector
         if (lds > max_lds()) return arg_error("precond_setup: box too long for the LDS transform");
     }
     if (levels == 2) {
-        if (o.reduce || o.factor_prec == VIE_BF16C)
+        if (o.reduce || o.factor_prec == VIE_BF16C || o.share_tol > 0)
             return arg_error("precond_setup: the 2-level circulant takes VIE_C128 or VIE_C64 factors and no memory reduction");
         if (!fft_supported_length(by))
             return arg_error("precond_setup: box width " + std::to_string(by) + " has a prime factor above " +
@@ -235,6 +235,8 @@ extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *st
     if (o.proxy != 0 && o.proxy != 1) return arg_error("precond_setup: proxy must be 0 or 1");
     if (o.reduce && (!(o.reduce_tol >= 0) || !std::isfinite(o.reduce_tol)))
         return arg_error("precond_setup: reduce_tol must be finite and >= 0");
+    if (!(o.share_tol >= 0) || !std::isfinite(o.share_tol))
+        return arg_error("precond_setup: share_tol must be finite and >= 0");
     std::vector<int> boxes;
     if (o.nboxes < 0) return arg_error("precond_setup: nboxes < 0");
     if (o.nboxes == 0) {

@@ -1101,6 +1101,11 @@ vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipSt
     return apply_t<float>(pc, (const c64 *)r, (c64 *)z, nrhs, s);
 }
 
+// The central mode is always kept under the memory reduction (the discarded modes use its block).
+static bool levels_one_centre(const std::vector<int> &keep, int centre) {
+    return centre >= 0 && centre < (int)keep.size() && keep[centre];
+}
+
 // mode of complex values over one box (x fastest); ties -> earliest first occurrence
 static c128 box_mode(const std::vector<c128> &M, int nx, int ny, const int *b) {
     std::map<std::pair<double, double>, std::pair<long long, long long>> cnt;  // value -> (count, first)
@@ -1240,9 +1245,10 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         VIE_HIP(hipGetLastError());
     }
     // memory reduction: proxy v_k of eq. proxy1 read from the table of N (minus the identity)
-    std::vector<int> keep(nm, 1);
+    std::vector<int> keep(nm, 1), rep(nm);
+    for (int k = 0; k < nm; ++k) rep[k] = k;
     int centre = (n + 1) / 2 - 1;  // ceil(n/2) - 1 (the 1-level memory reduction only)
-    if (o->reduce) {
+    if (o->reduce || o->share_tol > 0) {
         int yp, zp;
         if (o->proxy == 1) {
             yp = (by + 1) / 2 - 1;
@@ -1261,26 +1267,45 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             for (auto &x : v) x.re -= 1.0;
         double vmax = 0;
         for (auto &x : v) vmax = std::max(vmax, std::sqrt(x.re * x.re + x.im * x.im));
-        for (int k = 0; k < n; ++k) {
-            double vh = vmax > 0 ? std::sqrt(v[k].re * v[k].re + v[k].im * v[k].im) / vmax : 0.0;
-            keep[k] = vh > o->reduce_tol;
+        if (o->reduce) {
+            for (int k = 0; k < n; ++k) {
+                double vh = vmax > 0 ? std::sqrt(v[k].re * v[k].re + v[k].im * v[k].im) / vmax : 0.0;
+                keep[k] = vh > o->reduce_tol;
+            }
+            keep[centre] = 1;
         }
-        keep[centre] = 1;
+        // runs of kept modes whose proxy stays within share_tol of the run's first mode share its block
+        if (o->share_tol > 0) {
+            int cur = -1;
+            for (int k = 0; k < n; ++k) {
+                if (!keep[k]) continue;
+                const double dre = v[k].re - (cur >= 0 ? v[cur].re : 0.0), dim = v[k].im - (cur >= 0 ? v[cur].im : 0.0);
+                const bool own = o->reduce && k == centre;  // the discarded modes' block stays its own
+                if (cur >= 0 && !own &&
+                    std::sqrt(dre * dre + dim * dim) <=
+                        o->share_tol * std::sqrt(v[cur].re * v[cur].re + v[cur].im * v[cur].im))
+                    rep[k] = cur;
+                else
+                    cur = k;
+            }
+        }
     }
     // block map: stored blocks ordered (box, mode)
     pc->block_of_mode_host.assign((size_t)nbx * nm, -1);
     std::vector<int> smode, sbox;
     for (int b = 0; b < nbx; ++b) {
-        int cs = -1;
+        int *bom = &pc->block_of_mode_host[(size_t)b * nm];
         for (int k = 0; k < nm; ++k)
-            if (keep[k]) {
-                if (k == centre) cs = (int)smode.size();
-                pc->block_of_mode_host[(size_t)b * nm + k] = (int)smode.size();
+            if (keep[k] && rep[k] == k) {  // a stored block
+                bom[k] = (int)smode.size();
                 smode.push_back(k);
                 sbox.push_back(b);
             }
         for (int k = 0; k < nm; ++k)
-            if (!keep[k]) pc->block_of_mode_host[(size_t)b * nm + k] = cs;
+            if (keep[k] && rep[k] != k) bom[k] = bom[rep[k]];  // shares its run's block
+        const int cs = levels_one_centre(keep, centre) ? bom[centre] : -1;
+        for (int k = 0; k < nm; ++k)
+            if (!keep[k]) bom[k] = cs;  // discarded: the central block
     }
     pc->nstored = (int)smode.size();
     // per stored block: the modes that use it (block-solve columns) and its box

@@ -474,6 +474,31 @@ def test_boxes_of_different_shapes_levels_and_homogenisations(gpu_lib, case):
     assert err < (1e-5 if c64 else 1e-10)
 
 
+@pytest.mark.parametrize("tol,share,nrhs", [(None, 0.05, 1), (1e-3, 0.02, 1), (1e-3, 0.2, 20)])
+def test_shared_runs_match_oracle(gpu_lib, tol, share, nrhs):
+    """Runs of kept modes sharing one block: same stored-block count and apply as the oracle."""
+    import torch
+    grid, delta = (64, 8, 4), 50e-9
+    K = oracle_generator(grid, delta)
+    chi = W.waveguide(grid)
+    M = OCT.contrast_from_chi(chi)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid, reduce_tol=tol, share_tol=share)
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K)
+    pc = gpu_lib.Preconditioner(op, reduce_tol=tol, share_tol=share)
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((nrhs, n), 73)
+    z_ref = np.stack([ref_pc.apply(r[i]) for i in range(nrhs)])
+    rd = _to_dev(r)
+    zd = torch.empty_like(rd)
+    pc.apply(rd, zd, nrhs=nrhs)
+    err = max(_rel(zd.cpu().numpy()[i], z_ref[i]) for i in range(nrhs))
+    stored = len(set(ref_pc.parts[0].block_of_mode))
+    print('shared runs tol', tol, 'share', share, 'stored gpu', pc.info()['stored_blocks'], 'oracle', stored,
+          'err %.2e' % err)
+    assert pc.info()['stored_blocks'] == stored < 64
+    assert err < 1e-10
+
+
 def test_autotuned_launches_give_the_same_results(gpu_lib):
     """Autotuning picks launch parameters only: results agree with the defaults to rounding,
     and every tuned shape appears in the report."""

@@ -349,6 +349,8 @@ def test_share_runs_rule():
     assert list(C.share_runs(v, keep, 0.02)) == [0, 0, 0, 3, 3, -1, 3, 7]
     counts = [len(set(C.share_runs(v, keep, t)[keep])) for t in (0.0, 0.005, 0.02, 0.5, 5.0)]
     assert counts == sorted(counts, reverse=True) and counts[-1] == 1
+    # the central mode of the memory reduction starts its own run
+    assert list(C.share_runs(v, keep, 0.02, centre=4)) == [0, 0, 0, 3, 4, -1, 4, 7]
 
 
 def test_share_runs_apply_uses_the_representative_blocks(box):
