@@ -31,6 +31,7 @@ static size_t max_lds() {
 
 extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, double k_background, const double *chi,
                                  const vie_create_opts *opts, void *stream, vie_op *out) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!out) return arg_error("vie_create: out is NULL");
     *out = nullptr;
     if (!grid) return arg_error("vie_create: grid is NULL");
@@ -148,12 +149,14 @@ extern "C" vie_status vie_generator(vie_op op, double *out) {
 }
 
 extern "C" vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrhs, void *stream) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!op || !e_inc || !b) return arg_error("vie_rhs: NULL argument");
     if (nrhs < 1) return arg_error("vie_rhs: nrhs must be >= 1");
     return launch_rhs(op, (const c128 *)e_inc, (c128 *)b, nrhs, (hipStream_t)stream);
 }
 
 extern "C" vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec, void *stream) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!op || !x || !y) return arg_error("vie_matvec: NULL argument");
     if (nrhs < 1) return arg_error("vie_matvec: nrhs must be >= 1");
     if (prec != VIE_C128 && prec != VIE_C64) return arg_error("vie_matvec: unknown precision");
@@ -217,6 +220,7 @@ static vie_status build_group(vie_op op, const vie_pc_opts &o, const std::vector
 }
 
 extern "C" vie_status precond_setup(vie_op op, const vie_pc_opts *opts, void *stream, vie_pc *out) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!out) return arg_error("precond_setup: out is NULL");
     *out = nullptr;
     if (!op || !opts) return arg_error("precond_setup: NULL argument");
@@ -460,6 +464,7 @@ extern "C" vie_status precond_destroy(vie_pc pc) {
 }
 
 extern "C" vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t nrhs, vie_prec prec, void *stream) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!pc || !r || !z) return arg_error("precond_apply: NULL argument");
     if (nrhs < 1) return arg_error("precond_apply: nrhs must be >= 1");
     if (r == z) return arg_error("precond_apply: r and z must not overlap");
@@ -468,6 +473,7 @@ extern "C" vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t n
 
 extern "C" vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
                                 const vie_solve_opts *opts, vie_solve_stats *stats, void *stream) {
+    StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
     if (!op || !b || !x || !stats) return arg_error("vie_solve: NULL argument");
     if (nrhs < 1) return arg_error("vie_solve: nrhs must be >= 1");
     if (pc && pc->op != op) return arg_error("vie_solve: preconditioner built for another operator");

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "vie_internal.h"
 
@@ -107,17 +108,43 @@ static std::atomic<uint64_t> g_dev_cur{0}, g_dev_peak{0};
 // re-allocating tens of GB (the Krylov bases of a batched solve) costs seconds in the driver
 // at times.  A request takes the smallest cached block of at least its size and at most twice
 // it; when the driver is out of memory the cache is returned and the allocation retried.
+// A block released inside a library call carries an event recorded on that call's stream (the
+// stream its last work was queued on): whoever takes it next waits for that event only.
+// Released outside a call (destroy, trim), the device is synchronised instead.
 namespace {
+struct Block {
+    void *p;
+    hipEvent_t ev;  // nullptr: idle already
+};
 std::mutex g_pool_mu;
-std::multimap<size_t, void *> g_pool;  // size -> block
+std::multimap<size_t, Block> g_pool;  // size -> block
 size_t g_pool_bytes = 0;
+std::vector<hipEvent_t> g_events;     // idle events (under g_pool_mu)
+thread_local hipStream_t t_stream = nullptr;
+thread_local int t_stream_depth = 0;
 
 void pool_trim_locked() {
-    for (auto &kv : g_pool) (void)hipFree(kv.second);
+    for (auto &kv : g_pool) {
+        if (kv.second.ev) {
+            (void)hipEventSynchronize(kv.second.ev);
+            g_events.push_back(kv.second.ev);
+        }
+        (void)hipFree(kv.second.p);
+    }
     g_pool.clear();
     g_pool_bytes = 0;
 }
 }  // namespace
+
+StreamScope::StreamScope(hipStream_t s) : prev(t_stream) {
+    t_stream = s;
+    ++t_stream_depth;
+}
+
+StreamScope::~StreamScope() {
+    t_stream = prev;
+    --t_stream_depth;
+}
 
 extern "C" vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_t reset_peak) {
     if (reset_peak) g_dev_peak.store(g_dev_cur.load());
@@ -138,13 +165,22 @@ vie_status DevBuf::ensure(size_t nbytes) {
     release();
     if (nbytes == 0) return VIE_OK;
     {
-        std::lock_guard<std::mutex> lk(g_pool_mu);
-        auto it = g_pool.lower_bound(nbytes);
-        if (it != g_pool.end() && it->first <= 2 * nbytes) {
-            p = it->second;
-            bytes = it->first;
-            g_pool_bytes -= it->first;
-            g_pool.erase(it);
+        hipEvent_t ev = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            auto it = g_pool.lower_bound(nbytes);
+            if (it != g_pool.end() && it->first <= 2 * nbytes) {
+                p = it->second.p;
+                ev = it->second.ev;
+                bytes = it->first;
+                g_pool_bytes -= it->first;
+                g_pool.erase(it);
+            }
+        }
+        if (ev) {  // the previous user's work on this block is done before it is handed out
+            (void)hipEventSynchronize(ev);
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            g_events.push_back(ev);
         }
     }
     if (!p) {
@@ -171,11 +207,24 @@ vie_status DevBuf::ensure(size_t nbytes) {
 
 void DevBuf::release() {
     if (p) {
-        // hipFree would wait for the device; so does the cache, before another call may
-        // receive this block (on any stream)
-        (void)hipDeviceSynchronize();
+        hipEvent_t ev = nullptr;
+        if (t_stream_depth > 0) {
+            {
+                std::lock_guard<std::mutex> lk(g_pool_mu);
+                if (!g_events.empty()) {
+                    ev = g_events.back();
+                    g_events.pop_back();
+                }
+            }
+            if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+            if (ev && hipEventRecord(ev, t_stream) != hipSuccess) {
+                (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
+        }
+        if (!ev) (void)hipDeviceSynchronize();  // no call stream known: wait for everything
         std::lock_guard<std::mutex> lk(g_pool_mu);
-        g_pool.emplace(bytes, p);
+        g_pool.emplace(bytes, Block{p, ev});
         g_pool_bytes += bytes;
         g_dev_cur.fetch_sub(bytes);
     }

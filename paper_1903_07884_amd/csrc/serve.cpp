@@ -173,6 +173,7 @@ bool pick(vie_server srv, Batch *b) {
 // sides, copy each request's columns and statistics back.  Runs without the lock.
 vie_status run_batch(vie_server srv, Batch *b, hipStream_t s, vie_op *op_out, vie_pc *pc_out) {
     (void)srv;
+    StreamScope scope(s);  // the batch's buffers are reused once this worker's stream is past them
     Req *r0 = b->reqs[0];
     const long long N = (long long)r0->grid[0] * r0->grid[1] * r0->grid[2];
     const long long n3 = 3 * N;

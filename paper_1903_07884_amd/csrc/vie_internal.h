@@ -124,6 +124,14 @@ struct DevBuf {
     T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// The stream of the library call in progress on this thread: buffers released during it are
+// handed out again only after the work queued on it so far has finished.
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+};
+
 // Allow a kernel to request more than the default dynamic LDS.
 inline void vie_lds_attr(const void *kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
