@@ -73,6 +73,10 @@ typedef struct {
      * complex, components (xx, yy, zz, xy, xz, yz).  NULL = compute it by
      * quadrature on the device (the normal path). */
     const double *generator;
+    /* Testing: 1 = run the product's (y, z) plane pass as three passes through device memory
+     * (y-FFT, z coupling, inverse y-FFT) even when the plane fits one workgroup's LDS; the
+     * split form is taken anyway for cross-sections too wide for the fused pass. */
+    int32_t split_plane;
 } vie_create_opts;
 
 /* Build the operator of eq. discrete_form.

@@ -16,7 +16,7 @@ static vie_status arg_error(const std::string &msg) {
     return VIE_EARG;
 }
 
-static size_t max_lds() {
+size_t max_lds() {
     static size_t v = 0;
     if (!v) {
         int dev = 0;
@@ -77,12 +77,16 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
     op->has_c64 = o.build_c64 != 0;
     // few z layers: keep the z coupling as a direct Toeplitz sum (no z transform); the
     // (y, z) plane working set must fit the LDS either way
-    op->direct_z = op->nz <= 16 && 3LL * op->nz * op->Py <= 2LL * FFT_BPT * 1024 &&
-                   sizeof(c128) * ((size_t)6 * op->nz * op->Py + (size_t)6 * op->Hy * op->nz) <= max_lds();
+    op->direct_z = op->nz <= 16;
+    const bool fused_plane = 3LL * op->nz * op->Py <= 2LL * FFT_BPT * 1024 &&
+                             sizeof(c128) * ((size_t)6 * op->nz * op->Py + (size_t)6 * op->Hy * op->nz) <= max_lds();
+    op->split_plane = op->direct_z && (!fused_plane || o.split_plane);
     auto fail = [&](vie_status st) {
         delete op;
         return st;
     };
+    if (op->split_plane && 2 * sizeof(c128) * op->Py > max_lds())
+        return fail(arg_error("vie_create: y extent too long for the LDS line transform"));
     if (!op->direct_z && 6 * sizeof(c128) * op->Py * op->Pz > max_lds())
         return fail(arg_error("vie_create: cross-section too large for the LDS plane transform"));
     vie_status st;
@@ -344,12 +348,13 @@ static void op_bytes_estimate(int nx, int ny, int nz, bool c64, uint64_t *held, 
 
 // Footprint of the preconditioner (held, with its setup temporaries), its apply scratch, the
 // matvec scratch and the solve workspace for nrhs right-hand sides.
-static vie_status footprint_parts(int nx, int ny, int nz, int Px, const vie_pc_opts *pco, int32_t nrhs,
-                                  const vie_solve_opts *so, uint64_t *mv_scratch, uint64_t *pc_held,
+static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool split, const vie_pc_opts *pco,
+                                  int32_t nrhs, const vie_solve_opts *so, uint64_t *mv_scratch, uint64_t *pc_held,
                                   uint64_t *apply_scratch, uint64_t *solve_bytes) {
     const uint64_t N = (uint64_t)nx * ny * nz, R = (uint64_t)nrhs, n3 = 3 * N;
     const uint64_t lines = 3ULL * ny * nz * R;
     *mv_scratch = sizeof(c128) * lines * (uint64_t)Px;
+    if (split) *mv_scratch += 2 * sizeof(c128) * R * (uint64_t)Px * 3 * nz * (uint64_t)Py;  // split plane pass
     *pc_held = *apply_scratch = *solve_bytes = 0;
     if (pco) {
         const vie_pc_opts &o = *pco;
@@ -412,7 +417,8 @@ extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t n
     uint64_t b = op->M64.bytes + op->M32.bytes + op->gen.bytes + op->khat64.bytes + op->khat32.bytes;
     b += 6ULL * 16 * op->Px * op->Py * op->Pz;  // the circulant embedding transformed during vie_create
     uint64_t mv, pcb, ap, sb;
-    VIE_CHECK(footprint_parts(op->nx, op->ny, op->nz, op->Px, pco, nrhs, so, &mv, &pcb, &ap, &sb));
+    VIE_CHECK(footprint_parts(op->nx, op->ny, op->nz, op->Px, op->Py, op->split_plane, pco, nrhs, so, &mv, &pcb, &ap,
+                              &sb));
     *bytes = b + mv + pcb + ap + sb;
     return VIE_OK;
 }
@@ -422,7 +428,11 @@ vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts 
     uint64_t held, transient, mv, pcb, ap, sb;
     int Px;
     op_bytes_estimate(grid[0], grid[1], grid[2], c64, &held, &transient, &Px);
-    VIE_CHECK(footprint_parts(grid[0], grid[1], grid[2], Px, pco, nrhs, so, &mv, &pcb, &ap, &sb));
+    const int Py = fft_good_length(2 * grid[1] - 1), Hy = Py / 2 + 1, nz = grid[2];
+    const bool fused = 3LL * nz * Py <= 2LL * FFT_BPT * 1024 &&
+                       sizeof(c128) * ((size_t)6 * nz * Py + (size_t)6 * Hy * nz) <= max_lds();
+    VIE_CHECK(footprint_parts(grid[0], grid[1], grid[2], Px, Py, nz <= 16 && !fused, pco, nrhs, so, &mv, &pcb, &ap,
+                              &sb));
     *resident = held + mv + pcb + ap;           // kept by a cached operator + preconditioner
     *run = sb + transient + 2 * 16 * 3ULL * grid[0] * grid[1] * grid[2] * nrhs;  // workspace, build, e/b
     return VIE_OK;

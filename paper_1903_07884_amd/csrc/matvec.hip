@@ -13,6 +13,8 @@
 //   3. inverse x-FFT of every line, crop, and y = x - M (x + K x).
 #include <cstdio>
 
+#include <algorithm>
+
 #include "fft_device.h"
 
 template <class R>
@@ -367,6 +369,90 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
     }
 }
 
+// pass 2 split in three, for cross-sections whose (y, z) plane does not fit one workgroup's LDS
+// (few z layers, direct z sum).  yb[rhs][kx][row][ky], row = c*nz + z, holds y-spectra.
+// (a) forward y-FFT of `lg` zero-padded rows per workgroup (rows of one (rhs, x-frequency)).
+template <class R>
+__global__ void k_ysplit_fwd(const cpx<R> *work, cpx<R> *yb, int ny, int nz, int Px, int lg, FftPlan py) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem), *b = a + lg * py.L;
+    const int Py = py.L, rows = 3 * nz, ngr = (rows + lg - 1) / lg;
+    const int g = blockIdx.x % ngr;
+    const int kx = xcd_block(blockIdx.x / ngr, Px);
+    if (kx >= Px) return;
+    const long long rhs = blockIdx.y;
+    const cpx<R> *base = work + rhs * 3LL * ny * nz * Px + kx;
+    const int r0 = g * lg, nr = min(lg, rows - r0);
+    for (int i = threadIdx.x; i < lg * Py; i += blockDim.x) {
+        const int l = i / Py, y = i - l * Py;
+        a[i] = (l < nr && y < ny) ? base[((long long)(r0 + l) * ny + y) * Px] : czero<R>();
+    }
+    __syncthreads();
+    const LdsLines ln = {lg, Py, 0, 1, lg};
+    cpx<R> *res = Py > 1 ? fft_lds<R>(a, b, ln, py, false) : a;
+    cpx<R> *dst = yb + ((rhs * Px + kx) * rows + r0) * (long long)Py;
+    for (int i = threadIdx.x; i < nr * Py; i += blockDim.x) dst[i] = res[i];
+}
+
+// (b) z coupling: one thread per (rhs, x-frequency, y-frequency), the 3x3 blocks of the
+// (x, y)-transformed generator summed directly over the z offsets (parity signs as in the fused
+// pass); yb -> yc.
+template <class R>
+__global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *yb, cpx<R> *yc, const cpx<R> *khat, int nz,
+                                                       int Px, int Py, int Hy) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long tot = (long long)gridDim.y * Px * Py;
+    const long long rk = t / Py;  // (rhs * Px + kx) within this rhs row of the grid
+    if (t >= (long long)Px * Py) return;
+    (void)tot;
+    const int ky = (int)(t - rk * Py), kx = (int)rk;
+    const long long rhs = blockIdx.y;
+    const int rows = 3 * nz;
+    const int kxo = kx <= Px - kx ? kx : Px - kx, kyo = ky <= Py - ky ? ky : Py - ky;
+    const R sx = kx > Px - kx ? R(-1) : R(1), sy = ky > Py - ky ? R(-1) : R(1), sxy = sx * sy;
+    const cpx<R> *u = yb + (rhs * Px + kx) * rows * (long long)Py + ky;
+    cpx<R> *o = yc + (rhs * Px + kx) * rows * (long long)Py + ky;
+    const cpx<R> *g = khat + ((long long)kxo * Hy + kyo) * nz * 6;  // [dz][c]
+    for (int z = 0; z < nz; ++z) {
+        cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
+        for (int zp = 0; zp < nz; ++zp) {
+            const int dz = z - zp;
+            const R sz = dz < 0 ? R(-1) : R(1);
+            const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6;
+            const cpx<R> gxx = gz[0], gyy = gz[1], gzz = gz[2];
+            const cpx<R> gxy = sxy * gz[3], gxz = (sx * sz) * gz[4], gyz = (sy * sz) * gz[5];
+            const cpx<R> u0 = u[(long long)zp * Py], u1 = u[(long long)(nz + zp) * Py], u2 = u[(long long)(2 * nz + zp) * Py];
+            a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
+            a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
+            a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
+        }
+        o[(long long)z * Py] = a0;
+        o[(long long)(nz + z) * Py] = a1;
+        o[(long long)(2 * nz + z) * Py] = a2;
+    }
+}
+
+// (c) inverse y-FFT of `lg` coupled rows per workgroup, cropped back into the x-spectra.
+template <class R>
+__global__ void k_ysplit_inv(cpx<R> *work, const cpx<R> *yc, int ny, int nz, int Px, int lg, FftPlan py) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem), *b = a + lg * py.L;
+    const int Py = py.L, rows = 3 * nz, ngr = (rows + lg - 1) / lg;
+    const int g = blockIdx.x % ngr;
+    const int kx = xcd_block(blockIdx.x / ngr, Px);
+    if (kx >= Px) return;
+    const long long rhs = blockIdx.y;
+    const int r0 = g * lg, nr = min(lg, rows - r0);
+    const cpx<R> *src = yc + ((rhs * Px + kx) * rows + r0) * (long long)Py;
+    for (int i = threadIdx.x; i < lg * Py; i += blockDim.x) a[i] = i < nr * Py ? src[i] : czero<R>();
+    __syncthreads();
+    const LdsLines ln = {lg, Py, 0, 1, lg};
+    cpx<R> *res = Py > 1 ? fft_lds<R>(a, b, ln, py, true) : a;
+    cpx<R> *base = work + rhs * 3LL * ny * nz * Px + kx;
+    for (int i = threadIdx.x; i < nr * ny; i += blockDim.x) {
+        const int l = i / ny, y = i - l * ny;
+        base[((long long)(r0 + l) * ny + y) * Px] = res[l * Py + y];
+    }
+}
+
 // pass 3: one workgroup per x-line; inverse FFT, crop, y = x - M (x + K x).
 template <class R, int BPT>
 __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx<R> *y, int nx,
@@ -409,7 +495,26 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
 #undef LAUNCH_XFWD
     }
     VIE_HIP(hipGetLastError());
-    if (op->direct_z) {
+    if (op->split_plane) {
+        const int Py = op->Py, rows = 3 * nz;
+        int lg = (int)std::min<size_t>(8, max_lds() / (2 * sizeof(cpx<R>) * Py));
+        lg = std::max(1, std::min(lg, rows));
+        const size_t ldsy = 2 * sizeof(cpx<R>) * lg * Py;
+        const size_t yb = sizeof(cpx<R>) * (size_t)nrhs * Px * rows * Py;
+        VIE_CHECK(op->ybuf.ensure(2 * yb));
+        cpx<R> *y1 = op->ybuf.as<cpx<R>>(), *y2 = y1 + (size_t)nrhs * Px * rows * Py;
+        const unsigned gx = (unsigned)(8 * ((Px + 7) / 8) * ((rows + lg - 1) / lg));
+        ProfScope ps("matvec_plane", s);
+        vie_lds_attr((const void *)k_ysplit_fwd<R>, ldsy);
+        hipLaunchKernelGGL(k_ysplit_fwd<R>, dim3(gx, nrhs), dim3(256), ldsy, s, (const cpx<R> *)work, y1, ny, nz, Px,
+                           lg, op->py);
+        const long long pts = (long long)Px * Py;
+        hipLaunchKernelGGL(k_ysplit_couple<R>, dim3((unsigned)((pts + 255) / 256), nrhs), dim3(256), 0, s,
+                           (const cpx<R> *)y1, y2, khat, nz, Px, Py, op->Hy);
+        vie_lds_attr((const void *)k_ysplit_inv<R>, ldsy);
+        hipLaunchKernelGGL(k_ysplit_inv<R>, dim3(gx, nrhs), dim3(256), ldsy, s, work, (const cpx<R> *)y2, ny, nz, Px,
+                           lg, op->py);
+    } else if (op->direct_z) {
         size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
         vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
         ProfScope ps("matvec_plane", s);
@@ -444,8 +549,9 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
     const int pi = sizeof(R) == 8 ? 0 : 1;
     if (tune_enabled() && op->tuned_nrhs[pi] != nrhs) {
         char key[160];
-        snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d", (int)sizeof(cpx<R>),
-                 op->Px, op->Py, op->Pz, op->nx, op->ny, op->nz, nrhs, (int)op->direct_z);
+        snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d split=%d",
+                 (int)sizeof(cpx<R>), op->Px, op->Py, op->Pz, op->nx, op->ny, op->nz, nrhs, (int)op->direct_z,
+                 (int)op->split_plane);
         std::vector<int> choice;
         if (!tune_lookup(key, &choice)) {
             int t0, b0;

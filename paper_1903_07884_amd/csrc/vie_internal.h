@@ -132,6 +132,9 @@ struct StreamScope {
     ~StreamScope();
 };
 
+// LDS bytes a workgroup may use on the current device (api.cpp).
+size_t max_lds();
+
 // Allow a kernel to request more than the default dynamic LDS.
 inline void vie_lds_attr(const void *kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -178,6 +181,9 @@ struct vie_op_s {
                              // direct_z the (x, y)-transform [Hx][Hy][nz][6] scaled by 1/(Px Py)
     bool has_c64 = false;
     bool direct_z = false;   // kernel transform along x, y only; z handled as a direct Toeplitz sum
+    bool split_plane = false; // direct z, but the (y, z) plane exceeds one workgroup's LDS: the plane
+                             // pass runs as y-FFT, z coupling and inverse y-FFT through ybuf
+    DevBuf ybuf;             // split plane pass: y-spectra and coupled y-spectra, 2 x nrhs*Px*3nz*Py
     DevBuf work;             // matvec intermediate, nrhs*3*ny*nz*Px complex
     // FFT launch parameters per vector precision (0 = default; autotuned for tuned_nrhs)
     int cfg_plane_thr[2] = {0, 0}, cfg_x_thr[2] = {0, 0}, tuned_nrhs[2] = {-1, -1};

@@ -35,7 +35,7 @@ class VieError(RuntimeError):
 
 
 class CreateOpts(ctypes.Structure):
-    _fields_ = [('build_c64', ctypes.c_int32), ('generator', ctypes.c_void_p)]
+    _fields_ = [('build_c64', ctypes.c_int32), ('generator', ctypes.c_void_p), ('split_plane', ctypes.c_int32)]
 
 
 class PcOpts(ctypes.Structure):
@@ -160,7 +160,8 @@ def _prec(t):
 class Operator:
     """vie_op: I - M N on a voxel grid (see include/vie.h)."""
 
-    def __init__(self, grid, voxel_size, k_background, chi, build_c64=False, generator=None, stream=None):
+    def __init__(self, grid, voxel_size, k_background, chi, build_c64=False, generator=None, split_plane=False,
+                 stream=None):
         """``chi``: numpy array (host) or contiguous complex128 CUDA tensor (device), [nz, ny, nx]."""
         lib = load()
         nx, ny, nz = (int(v) for v in grid)
@@ -174,7 +175,7 @@ class Operator:
             chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
             chi_ptr = chi.ctypes.data
         g3 = (ctypes.c_int32 * 3)(nx, ny, nz)
-        opts = CreateOpts(1 if build_c64 else 0, None)
+        opts = CreateOpts(1 if build_c64 else 0, None, 1 if split_plane else 0)
         if generator is not None:
             gen = np.ascontiguousarray(np.asarray(generator, dtype=np.complex128).reshape(6, nz, ny, nx))
             opts.generator = gen.ctypes.data

@@ -102,7 +102,7 @@ CONFIGS = {
             geometry='bragg', nrhs=1, wy=0.25e-6, wz=0.1e-6),
     4: dict(name='Si directional coupler 1024x48x8 @ 25 nm, 64 RHS', grid=(1024, 48, 8),
             delta=25e-9, geometry='coupler', nrhs=64, wy=0.2e-6, wz=0.1e-6),
-    5: dict(name='Si disk 64x64x8 @ 25 nm (0.8 um radius)', grid=(64, 64, 8), delta=25e-9,
+    5: dict(name='Si disk 160x160x8 @ 25 nm (2 um radius)', grid=(160, 160, 8), delta=25e-9,
             geometry='disk', nrhs=1, wy=0.2e-6, wz=0.1e-6),
 }
 
