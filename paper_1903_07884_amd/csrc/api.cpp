@@ -403,7 +403,7 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
         const uint64_t rs = (uint64_t)so->restart;
         const bool mixed = so->mode == VIE_MODE_MIXED;
         const uint64_t vb = mixed ? 8 : 16;  // basis precision
-        *solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * 256 * (rs + 2) +
+        *solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * (uint64_t)arnoldi_partials((long long)n3, (int)rs) +
                        (mixed ? 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
     }
     return VIE_OK;

@@ -22,7 +22,14 @@
 #include "vie_internal.h"
 
 #define KR_THREADS 256
-#define KR_BLOCKS 256
+// The Arnoldi kernels split every vector into parts, one workgroup each: about KR_EPT_DOTS
+// elements per thread for the dot products (their 16 loads in flight per element already
+// cover the latency; fewer parts mean fewer partial reductions), KR_EPT_UPD for the updates,
+// at most KR_PARTS_MAX parts.  The split depends on the vector length alone, so a right-hand
+// side is summed in the same order whatever it is batched with.
+#define KR_EPT_DOTS 12
+#define KR_EPT_UPD 2
+#define KR_PARTS_MAX 2048
 
 __device__ __forceinline__ c128 wave_sum(c128 v) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -50,44 +57,75 @@ __device__ __forceinline__ c128 wide(c64 a) { return mk((double)a.re, (double)a.
 
 // Batched vectors: vector j of right-hand side r at base + j * ldj + r * n.  The basis V is
 // complex128, or complex64 in the mixed mode; sums are accumulated in FP64.
-// partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e]; `self` adds |w|^2 as
-// output nv.  The outputs are formed KR_DG at a time, so w is read once per group of KR_DG
-// basis vectors rather than once per vector.
+// partial[(r * gridDim.x + blk) * stride + i] = sum_e conj(V_i[e]) w[e], stride = nv + self;
+// `self` adds |w|^2 as output nv.  The outputs are formed KR_DG at a time, so w is read once
+// per group of KR_DG basis vectors rather than once per vector; inside a group the KR_DG loads
+// of an element are unconditional (a short last group clamps its index and drops the extra
+// products), so they are all in flight together.
 #define KR_DG 16
 template <class VT>
 __global__ void __launch_bounds__(KR_THREADS) k_dots(const VT *V, long long ldj, int nv, const c128 *w, long long n,
                                                      int self, c128 *partial) {
-    __shared__ c128 sh[KR_DG][KR_THREADS / 64];
+    __shared__ c128 sh[KR_DG + 1][KR_THREADS / 64];
     const int r = blockIdx.y;
     const c128 *wr = w + r * n;
+    const VT *Vr = V + r * n;
     long long chunk = (n + gridDim.x - 1) / gridDim.x;
     long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     const int stride = nv + self;
     c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i0 = 0; i0 < stride; i0 += KR_DG) {
+    const int ngroups = nv > 0 ? (nv + KR_DG - 1) / KR_DG : 1;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const int i0 = gi * KR_DG, cnt = min(KR_DG, nv - i0);
+        const bool do_self = self && gi == 0;
         c128 acc[KR_DG];
+        double sacc = 0.0;
 #pragma unroll
         for (int u = 0; u < KR_DG; ++u) acc[u] = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
-            const c128 we = wr[e];
+        if (cnt == KR_DG) {
+            for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+                const c128 we = wr[e];
+                c128 v[KR_DG];
 #pragma unroll
-            for (int u = 0; u < KR_DG; ++u) {
-                const int i = i0 + u;
-                if (i < nv) acc[u] = acc[u] + cmulc(wide(V[i * ldj + r * n + e]), we);
-                else if (i == nv && self) acc[u].re += abs2(we);
+                for (int u = 0; u < KR_DG; ++u) v[u] = wide(Vr[(i0 + u) * ldj + e]);
+#pragma unroll
+                for (int u = 0; u < KR_DG; ++u) acc[u] = acc[u] + cmulc(v[u], we);
+                if (do_self) sacc += abs2(we);
             }
+        } else if (cnt > 0) {
+            for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+                const c128 we = wr[e];
+                c128 v[KR_DG];
+#pragma unroll
+                for (int u = 0; u < KR_DG; ++u) v[u] = wide(Vr[min(i0 + u, nv - 1) * ldj + e]);
+#pragma unroll
+                for (int u = 0; u < KR_DG; ++u)
+                    if (u < cnt) acc[u] = acc[u] + cmulc(v[u], we);
+                if (do_self) sacc += abs2(we);
+            }
+        } else {  // no basis vectors: the self entry alone
+            for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) sacc += abs2(wr[e]);
         }
 #pragma unroll
         for (int u = 0; u < KR_DG; ++u) {
             const c128 v = wave_sum(acc[u]);
             if (lane == 0) sh[u][wid] = v;
         }
+        if (do_self) {
+            const c128 v = wave_sum(mk(sacc, 0.0));
+            if (lane == 0) sh[KR_DG][wid] = v;
+        }
         __syncthreads();
-        if (threadIdx.x < KR_DG && i0 + (int)threadIdx.x < stride) {
+        if (threadIdx.x < KR_DG && (int)threadIdx.x < cnt) {
             c128 t = czero<double>();
             for (int q = 0; q < KR_THREADS / 64; ++q) t = t + sh[threadIdx.x][q];
             out[i0 + threadIdx.x] = t;
+        }
+        if (do_self && threadIdx.x == KR_DG) {
+            c128 t = czero<double>();
+            for (int q = 0; q < KR_THREADS / 64; ++q) t = t + sh[KR_DG][q];
+            out[nv] = t;
         }
         __syncthreads();
     }
@@ -117,9 +155,18 @@ __global__ void __launch_bounds__(KR_THREADS) k_update(const VT *V, long long ld
     long long chunk = (n + gridDim.x - 1) / gridDim.x;
     long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     c128 nrm = czero<double>();
+    const VT *Vr = V + r * n;
     for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
         c128 acc = wr[e];
-        for (int i = 0; i < nv; ++i) acc = cfms(acc, wide(V[i * ldj + r * n + e]), hs[i]);
+        int i = 0;
+        for (; i + 8 <= nv; i += 8) {  // eight loads in flight, products in order of i
+            c128 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = wide(Vr[(i + u) * ldj + e]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = cfms(acc, v[u], hs[i + u]);
+        }
+        for (; i < nv; ++i) acc = cfms(acc, wide(Vr[i * ldj + e]), hs[i]);
         wr[e] = acc;
         nrm.re += abs2(acc);
     }
@@ -273,16 +320,17 @@ struct Ctx {
     hipStream_t s;
     long long n;  // 3N
     int R;
+    int nbd, nbu;  // parts per vector of the dot products and of the updates
     c128 *partial;
     double *host;  // pinned scratch
 };
 
 // batched norms: out[r].re = |w_r|^2
 vie_status norms(Ctx &C, const c128 *w, c128 *out) {
-    hipLaunchKernelGGL(k_dots<c128>, dim3(KR_BLOCKS, C.R), dim3(KR_THREADS), 0, C.s, (const c128 *)nullptr, 0LL, 0, w,
+    hipLaunchKernelGGL(k_dots<c128>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, C.s, (const c128 *)nullptr, 0LL, 0, w,
                        C.n, 1, C.partial);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce, dim3(1, C.R), dim3(KR_THREADS), 0, C.s, C.partial, KR_BLOCKS, 1, out, 1);
+    hipLaunchKernelGGL(k_reduce, dim3(1, C.R), dim3(KR_THREADS), 0, C.s, C.partial, C.nbd, 1, out, 1);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
@@ -290,40 +338,41 @@ vie_status norms(Ctx &C, const c128 *w, c128 *out) {
 // Classical Gram-Schmidt twice against v_0..v_j, the Givens update of column j and
 // v_{j+1} = w / h_{j+1,j} (Sec. 1: GMRES; the orthogonalisation is this build's choice).
 template <class VT>
-vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState &S, int m, dim3 grid_b, dim3 grid_e,
+vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState &S, int m, dim3 grid_e,
                      VT *vnext) {
     hipStream_t s = C.s;
     const long long n = C.n;
     const int R = C.R;
+    const dim3 grid_d(C.nbd, R), grid_u(C.nbu, R);
     {
         ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 1, C.partial);
+        hipLaunchKernelGGL(k_dots<VT>, grid_d, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 1, C.partial);
         VIE_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, j + 2,
+    hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, j + 2,
                        S.h1, m + 2);
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h1, m + 2, w, n,
+        hipLaunchKernelGGL(k_update<VT>, grid_u, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h1, m + 2, w, n,
                            (c128 *)nullptr);
         VIE_HIP(hipGetLastError());
     }
     {
         ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 0, C.partial);
+        hipLaunchKernelGGL(k_dots<VT>, grid_d, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 0, C.partial);
         VIE_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, j + 1,
+    hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, j + 1,
                        S.h2, m + 2);
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update<VT>, grid_b, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h2, m + 2, w, n,
+        hipLaunchKernelGGL(k_update<VT>, grid_u, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h2, m + 2, w, n,
                            C.partial);
         VIE_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, KR_BLOCKS, 1, S.nrm2, 1);
+    hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbu, 1, S.nrm2, 1);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_givens, dim3((R + 63) / 64), dim3(64), 0, s, S, j, R);
     VIE_HIP(hipGetLastError());
@@ -340,6 +389,14 @@ vie_status read_host(Ctx &C, const void *dev, size_t bytes) {
 }
 }  // namespace
 
+static int kr_parts(long long n, int ept) {
+    return (int)std::max(1LL, std::min((long long)KR_PARTS_MAX, (n + ept * KR_THREADS - 1) / (ept * KR_THREADS)));
+}
+
+long long arnoldi_partials(long long n, int restart) {
+    return std::max((long long)kr_parts(n, KR_EPT_DOTS) * (restart + 2), (long long)kr_parts(n, KR_EPT_UPD));
+}
+
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, const vie_solve_opts *o,
                        vie_solve_stats *stats, hipStream_t s) {
     const bool mixed = o->mode == VIE_MODE_MIXED;
@@ -355,7 +412,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     const int m = o->restart;
     const long long n = 3LL * op->N;
     const long long Rn = (long long)R * n;
-    Ctx C{op, s, n, R, nullptr, nullptr};
+    Ctx C{op, s, n, R, kr_parts(n, KR_EPT_DOTS), kr_parts(n, KR_EPT_UPD), nullptr, nullptr};
     // mixed mode: basis V and flexible basis Z in complex64, FP64 sums and w
     const size_t zsz = mixed ? sizeof(c64) : sizeof(c128);
     DevBuf Vb, Zb, wb, rb, part, small, w32;
@@ -363,7 +420,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     VIE_CHECK(Zb.ensure(zsz * Rn * m));
     VIE_CHECK(wb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
-    VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * KR_BLOCKS * (m + 2)));
+    VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
     if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
     size_t nc = (size_t)R * ((size_t)(m + 2) * 2 + 1 + (size_t)m * (m + 1) + m + (m + 1) + m);
     size_t nd = (size_t)R * (m + 4 + 1);
@@ -408,7 +465,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     int *hjr = hact + R;
     c128 *w = wb.as<c128>(), *r = rb.as<c128>();
     const long long ldj = Rn;  // stride between Arnoldi vectors
-    dim3 grid_b(KR_BLOCKS, R), grid_e(1024, R);
+    dim3 grid_e(1024, R);
 
     std::vector<double> nb(R), beta(R);
     std::vector<int> done(R, 0), act(R, 0), jr(R, 0);
@@ -490,9 +547,9 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_HIP(hipGetLastError());
             }
             if (mixed)
-                VIE_CHECK(cgs2_step<c64>(C, Vb.as<const c64>(), ldj, j, w, S, m, grid_b, grid_e, Vb.as<c64>() + (j + 1) * ldj));
+                VIE_CHECK(cgs2_step<c64>(C, Vb.as<const c64>(), ldj, j, w, S, m, grid_e, Vb.as<c64>() + (j + 1) * ldj));
             else
-                VIE_CHECK(cgs2_step<c128>(C, Vb.as<const c128>(), ldj, j, w, S, m, grid_b, grid_e,
+                VIE_CHECK(cgs2_step<c128>(C, Vb.as<const c128>(), ldj, j, w, S, m, grid_e,
                                           Vb.as<c128>() + (j + 1) * ldj));
             VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
             ++j;

@@ -287,5 +287,7 @@ vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipSt
 // block_solve.hip: the per-mode block solves, in place in the apply work buffer
 vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s);
 // krylov.hip
+// complex partial sums per right-hand side kept by the Arnoldi reductions (vector length n)
+long long arnoldi_partials(long long n, int restart);
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int nrhs,
                        const vie_solve_opts *o, vie_solve_stats *stats, hipStream_t s);
