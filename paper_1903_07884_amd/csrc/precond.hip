@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <utility>
 
 #include "fft_device.h"
 
@@ -403,6 +404,127 @@ __global__ void __launch_bounds__(32 * G) k_lu_panel_reg(cpx<R> *A, int *ipiv, i
     }
 }
 
+// Row-resident panel: thread t holds the physical panel rows j0 + t + s T (s < RPT, T threads)
+// in registers, all LU_NB columns of each, and the logical position pos of each row; a row
+// interchange swaps two positions and moves no data.  Per column jj: every row at a position
+// >= jj offers |Re a| + |Im a|, a wavefront max-reduction and one LDS pass pick the pivot
+// (ties to the smaller position); the pivot row publishes its entries right of jj to LDS and
+// takes position jj; every row at a later position forms its multiplier and subtracts its
+// multiple of the pivot row (LDS broadcast reads).  Two barriers per column.  Rows are written
+// back to their final positions, which performs the panel's interchanges.
+
+// wavefront max-reduction of the ROCm device library (every lane receives the maximum)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
+template <class R, int RPT, int MAXT, int jj>
+__device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][LU_NB], int (&pos)[RPT], const int j0, const int w,
+                                                  const int mrem, const int t, const int T, const int lane,
+                                                  const int wid, const int nw, cpx<R> *rowp, unsigned long long *wkey,
+                                                  int *piv, int *info) {
+    // pivot key: magnitude |re| + |im| rounded to FP32 in the high word, the complement of the
+    // position in the low word, so the largest key is the largest magnitude at the smallest
+    // position; rows already pivoted offer 0
+    unsigned long long key = 0;
+#pragma unroll
+    for (int sidx = 0; sidx < RPT; ++sidx) {
+        const float mag = (float)(fabs(v[sidx][jj].re) + fabs(v[sidx][jj].im));
+        const unsigned long long k = ((unsigned long long)__float_as_uint(mag) << 32) | (0xffffffffu - (unsigned)pos[sidx]);
+        if (t + sidx * T < mrem && pos[sidx] >= jj && k > key) key = k;
+    }
+    key = __ockl_wfred_max_u64(key);
+    if (lane == 0) wkey[wid] = key;
+    __syncthreads();
+    key = wkey[0];
+    for (int k = 1; k < nw; ++k) key = max(key, wkey[k]);
+    const int pp = (int)(0xffffffffu - (unsigned)key);  // position of the pivot row
+    if ((key >> 32) == 0) {  // zero column at and below the diagonal: no interchange, no elimination
+        if (t == 0) {
+            piv[jj] = j0 + jj;
+            if (info[blockIdx.x] == 0) info[blockIdx.x] = j0 + jj + 1;
+        }
+        __syncthreads();
+        return;
+    }
+#pragma unroll
+    for (int sidx = 0; sidx < RPT; ++sidx) {
+        if (t + sidx * T >= mrem) continue;
+        if (pos[sidx] == pp) {
+            // slot jj carries the reciprocal of the pivot, formed once here
+            const cpx<R> pv = v[sidx][jj];
+            const R rd = R(1) / cabs2(pv);
+            rowp[jj] = mk(pv.re * rd, -pv.im * rd);
+#pragma unroll
+            for (int c = jj + 1; c < LU_NB; ++c) rowp[c] = v[sidx][c];
+            pos[sidx] = jj;
+        } else if (pos[sidx] == jj) {
+            pos[sidx] = pp;
+        }
+    }
+    __syncthreads();
+    const cpx<R> inv = rowp[jj];
+#pragma unroll
+    for (int sidx = 0; sidx < RPT; ++sidx) {
+        if (t + sidx * T < mrem && pos[sidx] > jj) {
+            const cpx<R> l = v[sidx][jj] * inv;
+            v[sidx][jj] = l;
+            // four pivot-row entries at a time, so that the LDS reads are not all hoisted
+            // into registers ahead of the products; columns >= w hold zeros and stay zero
+#pragma unroll
+            for (int c0 = jj + 1; c0 < LU_NB; c0 += 4) {
+#pragma unroll
+                for (int c = c0; c < c0 + 4 && c < LU_NB; ++c) v[sidx][c] = cfms(v[sidx][c], l, rowp[c]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    if (t == 0) piv[jj] = j0 + pp;
+}
+
+template <class R, int RPT, int MAXT, int... J>
+__device__ __forceinline__ void panel_rows_all(std::integer_sequence<int, J...>, cpx<R> (&v)[RPT][LU_NB],
+                                               int (&pos)[RPT], int j0, int w, int mrem, int t, int T, int lane,
+                                               int wid, int nw, cpx<R> *rowp, unsigned long long *wkey, int *piv,
+                                               int *info) {
+    ((J < w ? panel_rows_column<R, RPT, MAXT, J>(v, pos, j0, w, mrem, t, T, lane, wid, nw, rowp, wkey, piv, info)
+            : void()),
+     ...);
+}
+
+template <class R, int RPT, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
+    __shared__ cpx<R> rowp[LU_NB];
+    __shared__ unsigned long long wkey[MAXT / 64];
+    const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = T >> 6;
+    const int mrem = m - j0;
+    cpx<R> *a = A + (long long)blockIdx.x * m * m + (long long)j0 * m + j0;
+    int *piv = ipiv + (long long)blockIdx.x * m + j0;
+    cpx<R> v[RPT][LU_NB];
+    int pos[RPT];
+    // column bases are uniform, row offsets 32-bit: scalar-base addressing, no per-lane 64-bit
+    // addresses kept live
+#pragma unroll
+    for (int sidx = 0; sidx < RPT; ++sidx) {
+        const int row = t + sidx * T;
+        pos[sidx] = row;
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) {
+            const cpx<R> *col = a + c * m;
+            v[sidx][c] = (c < w && row < mrem) ? col[row] : czero<R>();
+        }
+    }
+    panel_rows_all<R, RPT, MAXT>(std::make_integer_sequence<int, LU_NB>{}, v, pos, j0, w, mrem, t, T, lane, wid, nw,
+                                 rowp, wkey, piv, info);
+#pragma unroll
+    for (int sidx = 0; sidx < RPT; ++sidx) {
+        if (t + sidx * T < mrem)
+#pragma unroll
+            for (int c = 0; c < LU_NB; ++c) {
+                cpx<R> *col = a + c * m;
+                if (c < w) col[pos[sidx]] = v[sidx][c];
+            }
+    }
+}
+
 // Row interchanges of the panel applied to the other columns, and for columns right of the
 // panel U12 = L11^{-1} A12.  One workgroup per (64-column tile, block): rows [j0, j0 + w) of
 // the tile are staged in LDS with coalesced loads; interchanges with rows below the panel are
@@ -750,6 +872,23 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
     cpx<R> *linv = linv_all + (size_t)b0 * LU_NB * LU_NB;
     auto panel = [&](int j0, int w) -> vie_status {
         ProfScope ps("lu_panel", s);
+        const int mrem = m - j0;
+        // row-resident panel while the rows fit the registers of one workgroup
+        if constexpr (sizeof(R) == 8) {
+            if (mrem <= 512) {
+                hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 512>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
+                                   info, m, j0, w);
+                VIE_HIP(hipGetLastError());
+                return VIE_OK;
+            }
+        } else {
+            if (mrem <= 1024) {
+                hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 1024>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
+                                   info, m, j0, w);
+                VIE_HIP(hipGetLastError());
+                return VIE_OK;
+            }
+        }
         // 16 row lanes (512 threads) when the panel takes <= 32 value VGPRs per thread that
         // way (two blocks per CU), else 32 (1024 threads, one block per CU)
         const int q16 = (m - j0 + 15) / 16;
