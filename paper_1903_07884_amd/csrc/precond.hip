@@ -30,6 +30,9 @@
 
 #define LU_NB 32
 #define LU_TILE 64
+#define LU_MOVES (1 + 4 * LU_NB)      // ints per block of a panel's row-move list
+#define SW_CT 32                      // columns per workgroup of the interchange kernel
+#define SW_OUT (LU_NB * SW_CT / 256)  // U12 outputs per thread
 
 // ---------------------------------------------------------------- homogenisation
 // One workgroup per (box, z, y) row of a box: M~ = M(x0) (NONE, x-invariance checked),
@@ -491,9 +494,11 @@ __device__ __forceinline__ void panel_rows_all(std::integer_sequence<int, J...>,
 }
 
 template <class R, int RPT, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w) {
+__global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w,
+                                                        int *moves) {
     __shared__ cpx<R> rowp[LU_NB];
     __shared__ unsigned long long wkey[MAXT / 64];
+    __shared__ int nmove;
     const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = T >> 6;
     const int mrem = m - j0;
     cpx<R> *a = A + (long long)blockIdx.x * m * m + (long long)j0 * m + j0;
@@ -512,23 +517,150 @@ __global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, in
             v[sidx][c] = (c < w && row < mrem) ? col[row] : czero<R>();
         }
     }
+    if (t == 0) nmove = 0;
     panel_rows_all<R, RPT, MAXT>(std::make_integer_sequence<int, LU_NB>{}, v, pos, j0, w, mrem, t, T, lane, wid, nw,
                                  rowp, wkey, piv, info);
+    // the panel's row moves for the other columns: (destination, source) of every row that
+    // changed position, at most 2 LU_NB of them
+    int *mv = moves + (long long)blockIdx.x * LU_MOVES;
 #pragma unroll
     for (int sidx = 0; sidx < RPT; ++sidx) {
-        if (t + sidx * T < mrem)
+        const int row = t + sidx * T;
+        if (row < mrem) {
 #pragma unroll
             for (int c = 0; c < LU_NB; ++c) {
                 cpx<R> *col = a + c * m;
                 if (c < w) col[pos[sidx]] = v[sidx][c];
             }
+            if (pos[sidx] != row) {
+                const int k = atomicAdd(&nmove, 1);
+                mv[1 + 2 * k] = j0 + pos[sidx];
+                mv[2 + 2 * k] = j0 + row;
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) mv[0] = nmove;
+}
+
+// Row moves of the panel [j0, j0 + w) from its interchanges, for the panel kernels that do not
+// emit them: one thread per block replays the interchanges on the rows they touch.
+// moves[block] = {count, (destination, source) x count}.
+__global__ void __launch_bounds__(64) k_lu_moves(const int *ipiv, int *moves, int m, int j0, int w, int nblk) {
+    __shared__ int2 ent[64][2 * LU_NB];  // (position, source row) of the touched positions
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= nblk) return;
+    const int *piv = ipiv + (long long)b * m;
+    int2 *e = ent[threadIdx.x];
+    int n = 0;
+    auto find = [&](int p) {
+        for (int i = 0; i < n; ++i)
+            if (e[i].x == p) return i;
+        e[n] = make_int2(p, p);
+        return n++;
+    };
+    for (int j = 0; j < w; ++j) {
+        const int p = piv[j0 + j];
+        if (p == j0 + j) continue;
+        const int ia = find(j0 + j), ib = find(p);
+        const int t = e[ia].y;
+        e[ia].y = e[ib].y;
+        e[ib].y = t;
+    }
+    int *mv = moves + (long long)b * LU_MOVES;
+    int k = 0;
+    for (int i = 0; i < n; ++i)
+        if (e[i].x != e[i].y) {
+            mv[1 + 2 * k] = e[i].x;
+            mv[2 + 2 * k] = e[i].y;
+            ++k;
+        }
+    mv[0] = k;
+}
+
+// The panel [j0, j0 + w)'s row moves applied to the columns [cfirst, m) outside the panel
+// (do_swap), and U12 = L11^{-1} A12 for the columns right of it (do_trsm, with L11^{-1} from
+// k_lu_linv).  One workgroup per (SW_CT-column tile, block): the old values of the moved rows
+// are gathered into registers, rows [j0, j0 + w) of the tile are staged in LDS with coalesced
+// loads; after a barrier the moved values land in LDS (panel rows) or in place (rows below),
+// the triangular product runs on the LDS rows, which are written back coalesced.
+template <class R>
+__global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *moves, const cpx<R> *Linv, int m, int j0,
+                                                      int w, int cfirst, int do_swap, int do_trsm) {
+    __shared__ cpx<R> Tp[LU_NB][SW_CT + 1];  // rows j0 + r of the tile
+    __shared__ cpx<R> Li[LU_NB][LU_NB + 1];
+    __shared__ int2 mvs[LU_MOVES / 2];
+    __shared__ int nmv;
+    const int c0 = cfirst + blockIdx.x * SW_CT;
+    cpx<R> *a = A + (long long)blockIdx.y * m * m;
+    if (do_swap) {
+        const int *mv = moves + (long long)blockIdx.y * LU_MOVES;
+        if (threadIdx.x == 0) nmv = mv[0];
+        for (int k = threadIdx.x; k < LU_MOVES / 2; k += blockDim.x) mvs[k] = make_int2(mv[1 + 2 * k], mv[2 + 2 * k]);
+    } else if (threadIdx.x == 0) {
+        nmv = 0;
+    }
+    const bool right = do_trsm && c0 + SW_CT > j0 + w;
+    for (int e = threadIdx.x; e < w * SW_CT; e += blockDim.x) {
+        const int r = e % w, c = e / w, col = c0 + c;
+        const bool live = col < m && !(col >= j0 && col < j0 + w);
+        Tp[r][c] = live ? a[(long long)col * m + j0 + r] : czero<R>();
+    }
+    if (right) {
+        const cpx<R> *li = Linv + (long long)blockIdx.y * LU_NB * LU_NB;
+        for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) Li[e / LU_NB][e % LU_NB] = li[e];
+    }
+    __syncthreads();
+    const int nm = nmv;
+    // gather: element (move k, column c) -> thread; at most LU_MOVES / 2 * SW_CT / 256 each
+    constexpr int GPT = (LU_MOVES / 2) * SW_CT / 256;
+    cpx<R> gv[GPT];
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+        const int e = threadIdx.x + 256 * u, k = e / SW_CT, c = e % SW_CT, col = c0 + c;
+        const bool live = k < nm && col < m && !(col >= j0 && col < j0 + w);
+        gv[u] = live ? a[(long long)col * m + mvs[k].y] : czero<R>();
+    }
+    __syncthreads();  // every old value is read before any is replaced
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) {
+        const int e = threadIdx.x + 256 * u, k = e / SW_CT, c = e % SW_CT, col = c0 + c;
+        if (k < nm && col < m && !(col >= j0 && col < j0 + w)) {
+            const int dst = mvs[k].x;
+            if (dst < j0 + w) Tp[dst - j0][c] = gv[u];
+            else a[(long long)col * m + dst] = gv[u];
+        }
+    }
+    __syncthreads();
+    if (right) {
+        cpx<R> outv[SW_OUT];
+        const int cc = threadIdx.x % SW_CT, rq = threadIdx.x / SW_CT;
+        const int cl = c0 + cc;
+#pragma unroll
+        for (int k = 0; k < SW_OUT; ++k) {
+            int r = rq + (256 / SW_CT) * k;
+            cpx<R> acc = czero<R>();
+            if (r < w) {
+                acc = Tp[r][cc];
+                for (int q = 0; q < r; ++q) acc = acc + Li[r][q] * Tp[q][cc];
+            }
+            outv[k] = acc;
+        }
+        __syncthreads();
+        if (cl >= j0 + w && cl < m)
+#pragma unroll
+            for (int k = 0; k < SW_OUT; ++k) {
+                int r = rq + (256 / SW_CT) * k;
+                if (r < w) Tp[r][cc] = outv[k];
+            }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < w * SW_CT; e += blockDim.x) {
+        const int r = e % w, c = e / w, col = c0 + c;
+        if (col < m && !(col >= j0 && col < j0 + w)) a[(long long)col * m + j0 + r] = Tp[r][c];
     }
 }
 
-// Row interchanges of the panel applied to the other columns, and for columns right of the
-// panel U12 = L11^{-1} A12.  One workgroup per (64-column tile, block): rows [j0, j0 + w) of
-// the tile are staged in LDS with coalesced loads; interchanges with rows below the panel are
-// exchanged with global memory.
 // L11^{-1} of the panel [j0, j0 + w) (unit lower, strictly lower part stored) into Linv[block],
 // one workgroup per block, lane jc forming column jc from an LDS copy of L11.
 template <class R>
@@ -554,99 +686,6 @@ __global__ void __launch_bounds__(64) k_lu_linv(const cpx<R> *A, cpx<R> *Linv, i
     for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) out[e] = X[e / LU_NB][e % LU_NB];
 }
 
-// Row interchanges of a panel [j0, j0 + w) applied to the columns outside it (do_swap), and
-// U12 = L11^{-1} A12 for the columns right of it (do_trsm, with L11^{-1} from k_lu_linv).
-// One workgroup per (64-column tile, block).  Rows [j0, j0 + w) of the tile and the distinct
-// pivot rows below the panel are staged in LDS with parallel loads, the interchanges are
-// replayed in LDS in order, and both sets are written back in parallel.
-#define SW_CT 32                       // columns per workgroup
-#define SW_OUT (LU_NB * SW_CT / 256)   // U12 outputs per thread
-template <class R>
-__global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *ipiv, const cpx<R> *Linv, int m, int j0,
-                                                      int w, int do_swap, int do_trsm) {
-    __shared__ cpx<R> T[2 * LU_NB][SW_CT + 1];     // slots < LU_NB: rows j0 + slot; slots >= LU_NB: staged rows
-    __shared__ cpx<R> Li[LU_NB][LU_NB + 1];
-    __shared__ int slot[LU_NB];
-    __shared__ int ext[LU_NB];
-    __shared__ int next;
-    const int c0 = blockIdx.x * SW_CT;
-    cpx<R> *a = A + (long long)blockIdx.y * m * m;
-    const int *piv = ipiv + (long long)blockIdx.y * m;
-    const bool right = do_trsm && c0 + SW_CT > j0 + w;
-    if (threadIdx.x == 0) {
-        int ne = 0;
-        if (do_swap)
-            for (int j = 0; j < w; ++j) {
-                int p = piv[j0 + j];
-                if (p < j0 + w) {
-                    slot[j] = p - j0;
-                } else {
-                    int e = 0;
-                    while (e < ne && ext[e] != p) ++e;
-                    if (e == ne) ext[ne++] = p;
-                    slot[j] = LU_NB + e;
-                }
-            }
-        next = ne;
-    }
-    __syncthreads();
-    const int ne = next;
-    const int nrow = w + ne;
-    for (int e = threadIdx.x; e < nrow * SW_CT; e += blockDim.x) {
-        int r = e % nrow, c = e / nrow, col = c0 + c;
-        bool live = col < m && !(col >= j0 && col < j0 + w);
-        int row = r < w ? j0 + r : ext[r - w];
-        int sl = r < w ? r : LU_NB + (r - w);
-        T[sl][c] = live ? a[(long long)col * m + row] : czero<R>();
-    }
-    if (right) {
-        const cpx<R> *li = Linv + (long long)blockIdx.y * LU_NB * LU_NB;
-        for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) Li[e / LU_NB][e % LU_NB] = li[e];
-    }
-    __syncthreads();
-    if (do_swap && threadIdx.x < SW_CT) {
-        const int c = threadIdx.x;
-        for (int j = 0; j < w; ++j) {
-            int sl = slot[j];
-            if (sl == j) continue;
-            cpx<R> tt = T[j][c];
-            T[j][c] = T[sl][c];
-            T[sl][c] = tt;
-        }
-    }
-    __syncthreads();
-    if (right) {
-        cpx<R> outv[SW_OUT];
-        const int cc = threadIdx.x % SW_CT, rq = threadIdx.x / SW_CT;
-        const int cl = c0 + cc;
-#pragma unroll
-        for (int k = 0; k < SW_OUT; ++k) {
-            int r = rq + (256 / SW_CT) * k;
-            cpx<R> acc = czero<R>();
-            if (r < w) {
-                acc = T[r][cc];
-                for (int q = 0; q < r; ++q) acc = acc + Li[r][q] * T[q][cc];
-            }
-            outv[k] = acc;
-        }
-        __syncthreads();
-        if (cl >= j0 + w && cl < m)
-#pragma unroll
-            for (int k = 0; k < SW_OUT; ++k) {
-                int r = rq + (256 / SW_CT) * k;
-                if (r < w) T[r][cc] = outv[k];
-            }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < nrow * SW_CT; e += blockDim.x) {
-        int r = e % nrow, cc = e / nrow, cl = c0 + cc;
-        if (cl < m && !(cl >= j0 && cl < j0 + w)) {
-            int row = r < w ? j0 + r : ext[r - w];
-            int sl = r < w ? r : LU_NB + (r - w);
-            a[(long long)cl * m + row] = T[sl][cc];
-        }
-    }
-}
 
 // A[r, c] -= sum_{k in [k0, k0 + K)} A[r, k] A[k, c] for r in [r0, r1), c in [c0, c1): one
 // 64x64 output tile per workgroup, K staged in LDS in chunks of LU_NB, products on the matrix
@@ -864,10 +903,12 @@ template <class R>
 static cpx<R> *A_of(vie_pc pc) { return pc->factors.as<cpx<R>>(); }
 
 template <class R>
-static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<R> *linv_all, hipStream_t s) {
+static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<R> *linv_all, int *moves_all,
+                                  hipStream_t s) {
     const int m = pc->m;
     cpx<R> *A = pc->factors.as<cpx<R>>() + (size_t)b0 * m * m;
     int *ipiv = ipiv_all + (size_t)b0 * m;
+    int *moves = moves_all + (size_t)b0 * LU_MOVES;
     int *info = pc->info.as<int>() + b0;
     cpx<R> *linv = linv_all + (size_t)b0 * LU_NB * LU_NB;
     auto panel = [&](int j0, int w) -> vie_status {
@@ -877,14 +918,14 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
         if constexpr (sizeof(R) == 8) {
             if (mrem <= 512) {
                 hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 512>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
-                                   info, m, j0, w);
+                                   info, m, j0, w, moves);
                 VIE_HIP(hipGetLastError());
                 return VIE_OK;
             }
         } else {
             if (mrem <= 1024) {
                 hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 1024>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
-                                   info, m, j0, w);
+                                   info, m, j0, w, moves);
                 VIE_HIP(hipGetLastError());
                 return VIE_OK;
             }
@@ -915,6 +956,9 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
         }
 #undef PANEL_CASE
         VIE_HIP(hipGetLastError());
+        // these panel kernels leave the row-move list to a replay of their interchanges
+        hipLaunchKernelGGL(k_lu_moves, dim3((nb + 63) / 64), dim3(64), 0, s, (const int *)ipiv, moves, m, j0, w, nb);
+        VIE_HIP(hipGetLastError());
         return VIE_OK;
     };
     auto swap_trsm = [&](int j0, int w, int do_swap, int do_trsm) -> vie_status {
@@ -923,8 +967,11 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
             hipLaunchKernelGGL(k_lu_linv<R>, dim3(nb), dim3(64), 0, s, (const cpx<R> *)A, linv, m, j0, w);
             VIE_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m + SW_CT - 1) / SW_CT, nb), dim3(256), 0, s, A, ipiv,
-                           (const cpx<R> *)linv, m, j0, w, do_swap, do_trsm);
+        // interchanges reach every column; the triangular product alone only those right of the panel
+        const int cfirst = do_swap ? 0 : j0 + w;
+        if (cfirst >= m) return VIE_OK;
+        hipLaunchKernelGGL(k_lu_swap_trsm<R>, dim3((m - cfirst + SW_CT - 1) / SW_CT, nb), dim3(256), 0, s, A,
+                           (const int *)moves, (const cpx<R> *)linv, m, j0, w, cfirst, do_swap, do_trsm);
         VIE_HIP(hipGetLastError());
         return VIE_OK;
     };
@@ -960,11 +1007,12 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
 template <class R>
 static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     const int m = pc->m, nb = pc->nstored;
-    DevBuf ipiv, linv;
+    DevBuf ipiv, linv, moves;
     VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
     VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
+    VIE_CHECK(moves.ensure(sizeof(int) * (size_t)nb * LU_MOVES));
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
-    VIE_CHECK(lu_factor_range<R>(pc, 0, nb, ipiv.as<int>(), linv.as<cpx<R>>(), s));
+    VIE_CHECK(lu_factor_range<R>(pc, 0, nb, ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(), s));
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());
