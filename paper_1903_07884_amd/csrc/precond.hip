@@ -830,68 +830,125 @@ __global__ void k_lu_perm(const int *ipiv, int *perm, int m, int nblk) {
 }
 
 #define TS 64
+// Marks the entries [q0, H) of a register column as computed here: the compiler then finishes
+// a substitution row before starting the next, instead of interleaving rows and holding the
+// factor entries of many rows in registers.  Emits no instruction.
+template <class R, int H>
+__device__ __forceinline__ void settle(cpx<R> (&x)[H], int q0) {
+#pragma unroll
+    for (int q = 0; q < H; ++q)
+        if (q >= q0) asm volatile("" : "+v"(x[q].re), "+v"(x[q].im));
+}
+
 // Setup: replace every 64x64 diagonal tile of the packed LU factors by the inverses of its
 // unit-lower part (strictly lower entries) and of its upper part (upper entries incl. the
 // diagonal).  The block solves then apply each diagonal tile as a parallel product.
-// One workgroup (128 threads) per (tile, block), in place in one LDS copy of the tile:
-//   L: for j = w-1 .. 0, column j of L^{-1} below the diagonal is -L^{-1}_{>j,>j} l_{>j,j},
-//      with L^{-1}_{>j,>j} already in place in the columns right of j;
-//   U: for j = 0 .. w-1, column j of U^{-1} above the diagonal is -U^{-1}_{<j,<j} u_{<j,j} / u_jj,
-//      with U^{-1}_{<j,<j} already in place in the columns left of j, and 1/u_jj on the diagonal.
-// Lanes 0..63 own the rows of the L step, lanes 64..127 the rows of the U step.
+// One workgroup (four wavefronts) per (tile, block), the tile in LDS (column-major, padded
+// to the identity past the block's order).  Lane j of a wavefront owns column j of one half
+// (rows 0..31 or 32..63) of an inverse in registers and forms it by substitution, one row at
+// a time, with the factor entries read as LDS broadcasts:
+//   phase 1: wave 0 the L^{-1} rows 0..31 (forward), wave 3 the U^{-1} rows 32..63 (backward);
+//   phase 2: wave 1 the L^{-1} rows 32..63 (the product with rows 0..31, then forward),
+//            wave 2 the U^{-1} rows 0..31 (the product with rows 32..63, then backward).
+// Each wavefront writes its results over the entries that it alone still reads, after its
+// reads (L^{-1} over the strictly lower part, U^{-1} over the upper part).
 template <class R>
-__global__ void __launch_bounds__(128) k_invert_diag(cpx<R> *F, int m) {
+__global__ void __launch_bounds__(256) k_invert_diag(cpx<R> *F, int m) {
     cpx<R> *T = reinterpret_cast<cpx<R> *>(vie_smem);  // column-major [TS][TS+1]: T[c*(TS+1)+r]
+    __shared__ cpx<R> dinv[TS];
+    constexpr int H = TS / 2;
     const int t0 = blockIdx.x * TS;
     const int w = min(TS, m - t0);
     cpx<R> *a = F + (long long)blockIdx.y * m * m;
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-        int r = e % w, c = e / w;
-        T[c * (TS + 1) + r] = a[(long long)(t0 + c) * m + t0 + r];
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+        const int r = e % TS, c = e / TS;
+        cpx<R> v = mk(r == c ? R(1) : R(0), R(0));
+        if (r < w && c < w) v = a[(long long)(t0 + c) * m + t0 + r];
+        T[c * (TS + 1) + r] = v;
     }
     __syncthreads();
-    const int i = threadIdx.x & 63;
-    const bool lower = threadIdx.x < 64;
-    for (int step = 0; step < w; ++step) {
-        cpx<R> x = czero<R>();
-        const int jl = w - 1 - step;  // L column of this step
-        const int ju = step;          // U column of this step
-        // each dot product in four independent partial sums (the LDS loads of four terms in flight)
-        auto dot = [&](int k0, int k1, int col) -> cpx<R> {
-            const cpx<R> *ti = T + i, *tc = T + col * (TS + 1);
-            cpx<R> p0 = czero<R>(), p1 = czero<R>(), p2 = czero<R>(), p3 = czero<R>();
-            int k = k0;
-            for (; k + 3 < k1; k += 4) {
-                p0 = p0 + ti[k * (TS + 1)] * tc[k];
-                p1 = p1 + ti[(k + 1) * (TS + 1)] * tc[k + 1];
-                p2 = p2 + ti[(k + 2) * (TS + 1)] * tc[k + 2];
-                p3 = p3 + ti[(k + 3) * (TS + 1)] * tc[k + 3];
-            }
-            for (; k < k1; ++k) p0 = p0 + ti[k * (TS + 1)] * tc[k];
-            return (p0 + p1) + (p2 + p3);
-        };
-        if (lower) {
-            if (i > jl && i < w) {
-                // x_i = -(l_ij + sum_{k=j+1}^{i-1} Linv_ik l_kj)
-                x = T[jl * (TS + 1) + i] + dot(jl + 1, i, jl);
-                x = mk(-x.re, -x.im);
-            }
-        } else {
-            if (i < ju) {
-                // x_i = -(sum_{k=i}^{j-1} Uinv_ik u_kj) / u_jj
-                x = dot(i, ju, ju);
-                x = cdiv(mk(-x.re, -x.im), T[ju * (TS + 1) + ju]);
-            }
+    if (threadIdx.x < TS) dinv[threadIdx.x] = cdiv(mk(R(1), R(0)), T[threadIdx.x * (TS + 1) + threadIdx.x]);
+    __syncthreads();
+    // the role of a wavefront as a uniform value: whole wavefronts branch
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), j = threadIdx.x & 63;
+    cpx<R> *Tj = T + j * (TS + 1);
+    cpx<R> x[H];
+    if (wv == 0) {  // L^{-1}, rows 0..31 of column j
+#pragma unroll
+        for (int q = 0; q < H; ++q) x[q] = mk(q == j ? R(1) : R(0), R(0));
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cpx<R> *Lk = T + k * (TS + 1);
+#pragma unroll
+            for (int q = k + 1; q < H; ++q) x[q] = cfms(x[q], Lk[q], x[k]);
+            settle(x, k + 1);
         }
-        __syncthreads();
-        if (lower) {
-            if (i > jl && i < w) T[jl * (TS + 1) + i] = x;
-        } else {
-            if (i < ju) T[ju * (TS + 1) + i] = x;
-            else if (i == ju) T[ju * (TS + 1) + ju] = cdiv(mk(R(1), R(0)), T[ju * (TS + 1) + ju]);
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+            if (q > j) Tj[q] = x[q];
+    } else if (wv == 3) {  // U^{-1}, rows 32..63 of column j
+#pragma unroll
+        for (int q = 0; q < H; ++q) x[q] = mk(H + q == j ? R(1) : R(0), R(0));
+#pragma unroll
+        for (int k = H - 1; k >= 0; --k) {
+            x[k] = x[k] * dinv[H + k];
+            const cpx<R> *Uk = T + (H + k) * (TS + 1) + H;
+#pragma unroll
+            for (int q = 0; q < k; ++q) x[q] = cfms(x[q], Uk[q], x[k]);
+            settle(x, 0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+            if (H + q <= j) Tj[H + q] = x[q];
     }
+    __syncthreads();
+    if (wv == 1) {  // L^{-1}, rows 32..63 of column j
+#pragma unroll
+        for (int q = 0; q < H; ++q) x[q] = mk(H + q == j ? R(1) : R(0), R(0));
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cpx<R> t = Tj[k];  // L^{-1}[k][j] from phase 1: unit diagonal, zero above
+            const cpx<R> xk = mk(k > j ? t.re : (k == j ? R(1) : R(0)), k > j ? t.im : R(0));
+            const cpx<R> *Lk = T + k * (TS + 1) + H;
+#pragma unroll
+            for (int q = 0; q < H; ++q) x[q] = cfms(x[q], Lk[q], xk);
+            settle(x, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cpx<R> *Lk = T + (H + k) * (TS + 1) + H;
+#pragma unroll
+            for (int q = k + 1; q < H; ++q) x[q] = cfms(x[q], Lk[q], x[k]);
+            settle(x, k + 1);
+        }
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+            if (H + q > j) Tj[H + q] = x[q];
+    } else if (wv == 2) {  // U^{-1}, rows 0..31 of column j
+#pragma unroll
+        for (int q = 0; q < H; ++q) x[q] = mk(q == j ? R(1) : R(0), R(0));
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const cpx<R> t = Tj[H + k];  // U^{-1}[32 + k][j] from phase 1: zero below the diagonal
+            const cpx<R> yk = mk(H + k <= j ? t.re : R(0), H + k <= j ? t.im : R(0));
+            const cpx<R> *Uk = T + (H + k) * (TS + 1);
+#pragma unroll
+            for (int q = 0; q < H; ++q) x[q] = cfms(x[q], Uk[q], yk);
+            settle(x, 0);
+        }
+#pragma unroll
+        for (int k = H - 1; k >= 0; --k) {
+            x[k] = x[k] * dinv[k];
+            const cpx<R> *Uk = T + k * (TS + 1);
+#pragma unroll
+            for (int q = 0; q < k; ++q) x[q] = cfms(x[q], Uk[q], x[k]);
+            settle(x, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+            if (q <= j) Tj[q] = x[q];
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
         int r = e % w, c = e / w;
         a[(long long)(t0 + c) * m + t0 + r] = T[c * (TS + 1) + r];
@@ -1020,7 +1077,7 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
         size_t lds = sizeof(cpx<R>) * TS * (TS + 1);
         vie_lds_attr((const void *)k_invert_diag<R>, lds);
         ProfScope ps("lu_invert_diag", s);
-        hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(128), lds, s, A_of<R>(pc), m);
+        hipLaunchKernelGGL(k_invert_diag<R>, dim3((m + TS - 1) / TS, nb), dim3(256), lds, s, A_of<R>(pc), m);
         VIE_HIP(hipGetLastError());
     }
     VIE_HIP(hipStreamSynchronize(s));
