@@ -114,12 +114,13 @@ static std::atomic<uint64_t> g_dev_cur{0}, g_dev_peak{0};
 namespace {
 struct Block {
     void *p;
-    hipEvent_t ev;  // nullptr: idle already
+    hipEvent_t ev;       // nullptr: idle already
+    hipStream_t stream;  // the stream ev was recorded on
 };
 std::mutex g_pool_mu;
 std::multimap<size_t, Block> g_pool;  // size -> block
 size_t g_pool_bytes = 0;
-std::vector<hipEvent_t> g_events;     // idle events (under g_pool_mu)
+std::vector<std::pair<hipEvent_t, hipStream_t>> g_events;  // idle events, last stream (under g_pool_mu)
 thread_local hipStream_t t_stream = nullptr;
 thread_local int t_stream_depth = 0;
 
@@ -127,7 +128,7 @@ void pool_trim_locked() {
     for (auto &kv : g_pool) {
         if (kv.second.ev) {
             (void)hipEventSynchronize(kv.second.ev);
-            g_events.push_back(kv.second.ev);
+            g_events.emplace_back(kv.second.ev, kv.second.stream);
         }
         (void)hipFree(kv.second.p);
     }
@@ -135,6 +136,26 @@ void pool_trim_locked() {
     g_pool_bytes = 0;
 }
 }  // namespace
+
+void pool_stream_retired(hipStream_t s) {
+    // an event must not outlive the stream it was last recorded on: wait for the blocks
+    // released on s and drop their events (fresh ones are created on demand)
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &kv : g_pool)
+        if (kv.second.ev && kv.second.stream == s) {
+            (void)hipEventSynchronize(kv.second.ev);
+            (void)hipEventDestroy(kv.second.ev);
+            kv.second.ev = nullptr;
+        }
+    for (size_t i = 0; i < g_events.size();)
+        if (g_events[i].second == s) {
+            (void)hipEventDestroy(g_events[i].first);
+            g_events[i] = g_events.back();
+            g_events.pop_back();
+        } else {
+            ++i;
+        }
+}
 
 StreamScope::StreamScope(hipStream_t s) : prev(t_stream) {
     t_stream = s;
@@ -166,12 +187,14 @@ vie_status DevBuf::ensure(size_t nbytes) {
     if (nbytes == 0) return VIE_OK;
     {
         hipEvent_t ev = nullptr;
+        hipStream_t evs = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_pool_mu);
             auto it = g_pool.lower_bound(nbytes);
             if (it != g_pool.end() && it->first <= 2 * nbytes) {
                 p = it->second.p;
                 ev = it->second.ev;
+                evs = it->second.stream;
                 bytes = it->first;
                 g_pool_bytes -= it->first;
                 g_pool.erase(it);
@@ -180,7 +203,7 @@ vie_status DevBuf::ensure(size_t nbytes) {
         if (ev) {  // the previous user's work on this block is done before it is handed out
             (void)hipEventSynchronize(ev);
             std::lock_guard<std::mutex> lk(g_pool_mu);
-            g_events.push_back(ev);
+            g_events.emplace_back(ev, evs);
         }
     }
     if (!p) {
@@ -212,7 +235,7 @@ void DevBuf::release() {
             {
                 std::lock_guard<std::mutex> lk(g_pool_mu);
                 if (!g_events.empty()) {
-                    ev = g_events.back();
+                    ev = g_events.back().first;
                     g_events.pop_back();
                 }
             }
@@ -224,7 +247,7 @@ void DevBuf::release() {
         }
         if (!ev) (void)hipDeviceSynchronize();  // no call stream known: wait for everything
         std::lock_guard<std::mutex> lk(g_pool_mu);
-        g_pool.emplace(bytes, Block{p, ev});
+        g_pool.emplace(bytes, Block{p, ev, t_stream});
         g_pool_bytes += bytes;
         g_dev_cur.fetch_sub(bytes);
     }

@@ -277,7 +277,11 @@ void worker(vie_server srv) {
         srv->cv_work.notify_all();
     }
     lk.unlock();
-    if (have_stream) (void)hipStreamDestroy(s);
+    if (have_stream) {
+        (void)hipStreamSynchronize(s);
+        pool_stream_retired(s);
+        (void)hipStreamDestroy(s);
+    }
 }
 }  // namespace
 

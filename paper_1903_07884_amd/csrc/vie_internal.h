@@ -126,6 +126,10 @@ struct DevBuf {
 
 // The stream of the library call in progress on this thread: buffers released during it are
 // handed out again only after the work queued on it so far has finished.
+// Before a stream created by the library is destroyed: the pool waits for the blocks released
+// on it and drops their events.
+void pool_stream_retired(hipStream_t s);
+
 struct StreamScope {
     hipStream_t prev;
     explicit StreamScope(hipStream_t s);
