@@ -231,9 +231,13 @@ vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
  * size, wavenumber, a hash of the contrast) and the preconditioner options, evicted least
  * recently used when memory is needed; each worker thread owns a HIP stream, so admitted
  * solves run side by side on the device; requests waiting for the same device, options and
- * solver settings are merged into one multi-RHS solve.  A result does not depend on what it
- * was solved beside: columns of a merged solve equal the single solves (the batched GMRES
- * runs every right-hand side on its own).  Thread-safe: any thread may submit and wait. */
+ * solver settings are merged into one multi-RHS solve.  The right-hand sides of a running
+ * solve are slots (continuous batching): at every GMRES restart boundary a request whose
+ * columns have all ended completes (its waiter returns while the others go on) and a queued
+ * request of the same device and settings that fits the freed slots joins the solve.  A
+ * result does not depend on what it was solved beside: columns of a merged solve equal the
+ * single solves (the batched GMRES runs every right-hand side on its own, with reductions
+ * whose order does not depend on the batch).  Thread-safe: any thread may submit and wait. */
 typedef struct vie_server_s *vie_server;
 
 typedef struct {
@@ -262,7 +266,10 @@ typedef struct {
     double run_ms;          /* start -> result on the host (build or cache lookup, solve, copy) */
     double total_ms;        /* submit -> result */
     int32_t cache_hit;      /* operator and preconditioner came from the resident cache */
-    int32_t merged;         /* requests solved in the same multi-RHS solve, itself included */
+    int32_t merged;         /* requests that took part in the same multi-RHS solve up to this
+                               one's completion, itself included */
+    int32_t joined;         /* 1: joined a running solve at a restart boundary (continuous
+                               batching), 0: admitted with the solve */
 } vie_request_times;
 
 typedef struct {

@@ -398,7 +398,7 @@ long long arnoldi_partials(long long n, int restart) {
 }
 
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, const vie_solve_opts *o,
-                       vie_solve_stats *stats, hipStream_t s) {
+                       vie_solve_stats *stats, hipStream_t s, SolveHook *hook) {
     const bool mixed = o->mode == VIE_MODE_MIXED;
     if (mixed && !op->has_c64) {
         vie_set_error("mixed-precision solve needs an operator built with build_c64");
@@ -468,7 +468,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     dim3 grid_e(1024, R);
 
     std::vector<double> nb(R), beta(R);
-    std::vector<int> done(R, 0), act(R, 0), jr(R, 0);
+    std::vector<int> done(R, 0), act(R, 0), jr(R, 0), told(R, 0);
     for (int q = 0; q < R; ++q) stats[q] = vie_solve_stats{0, 0, 0.0, VIE_OK};
     VIE_CHECK(norms(C, b, S.nrm2));
     VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
@@ -508,6 +508,36 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
             act[q] = !done[q];
             jr[q] = 0;
             nact += act[q];
+        }
+        if (hook) {  // hand out ended columns, take new right-hand sides into their slots
+            std::vector<int> ended, refill;
+            for (int q = 0; q < R; ++q)
+                if (done[q] && !told[q]) {
+                    told[q] = 1;
+                    ended.push_back(q);
+                }
+            VIE_CHECK(hook->boundary(ended, stats, x, const_cast<c128 *>(b), s, &refill));
+            if (!refill.empty()) {
+                for (int q : refill) {
+                    VIE_HIP(hipMemsetAsync(x + (long long)q * n, 0, sizeof(c128) * n, s));
+                    VIE_HIP(hipMemcpyAsync(r + (long long)q * n, b + (long long)q * n, sizeof(c128) * n,
+                                           hipMemcpyDeviceToDevice, s));
+                }
+                VIE_CHECK(norms(C, b, S.nrm2));
+                VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
+                for (int q : refill) {
+                    nb[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+                    if (!std::isfinite(nb[q])) {
+                        vie_set_error("non-finite right-hand side in slot " + std::to_string(q));
+                        return VIE_ENONFINITE;
+                    }
+                    beta[q] = nb[q];
+                    stats[q] = vie_solve_stats{0, 0, nb[q] > 0 ? 1.0 : 0.0, VIE_OK};
+                    done[q] = told[q] = 0;
+                    act[q] = 1;
+                    ++nact;
+                }
+            }
         }
         if (nact == 0) break;
         // v0 = r / beta (zero for finished right-hand sides), g = (beta, 0, ...)

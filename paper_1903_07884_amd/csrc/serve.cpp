@@ -6,9 +6,13 @@
 // entries (least recently used first); the solve workspace must fit as well.  Later queued
 // requests with the same device, preconditioner options and solver settings join it in one
 // multi-RHS solve.  A request that has been passed over by later ones several times blocks
-// further overtaking until it is admitted.  After the solve the operator and preconditioner
-// return to the cache, the results are copied to the callers' host buffers and the waiters
-// are woken.
+// further overtaking until it is admitted.
+// Continuous batching: the solve's right-hand sides are slots.  At every restart-cycle
+// boundary of the batched GMRES, a request whose columns have all ended is completed at once
+// (its columns copied to the caller's host buffer, its waiter woken) and its slots are freed;
+// a queued request for the same device and settings whose right-hand sides fit the free
+// slots joins the running solve there, without a new admission (its memory is the slots').
+// After the solve the operator and preconditioner return to the cache.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -54,7 +58,9 @@ struct Req {
     Clock::time_point t_submit, t_start, t_end;
     vie_status status = VIE_OK;
     bool done = false;
-    int cache_hit = 0, merged = 1, overtaken = 0;
+    int cache_hit = 0, merged = 1, overtaken = 0, joined = 0;
+    int cols_left = 0;      // columns of a running solve not yet ended
+    bool finished = false;  // all columns ended and copied out
     std::string err;  // message of a failed build or solve
 };
 
@@ -69,8 +75,10 @@ struct Entry {
 
 // One admitted solve: the requests merged into it and its accounting.
 struct Batch {
-    std::vector<Req *> reqs;
-    Entry *entry = nullptr;  // cache entry in use (nullptr: build a new one)
+    std::vector<Req *> reqs;  // requests of the solve not yet completed (a waiter may free the others)
+    std::string key, batch_key;
+    int n_total = 0;          // requests that took part, joiners included
+    Entry *entry = nullptr;   // cache entry in use (nullptr: build a new one)
     int R = 0;
     uint64_t resident = 0, run = 0;  // bytes committed for the entry (when new) and the run
 };
@@ -152,6 +160,9 @@ bool pick(vie_server srv, Batch *b) {
             commit(srv, need);
             b->reqs.clear();
             for (size_t k : idx) b->reqs.push_back(srv->queue[k]);
+            b->key = r->key;
+            b->batch_key = r->batch_key;
+            b->n_total = (int)idx.size();
             for (size_t k = idx.size(); k-- > 0;) srv->queue.erase(srv->queue.begin() + (long)idx[k]);
             for (size_t k = 0; k < qi; ++k) srv->queue[k]->overtaken++;
             b->entry = idle;
@@ -169,10 +180,106 @@ bool pick(vie_server srv, Batch *b) {
     return false;
 }
 
-// Build (or take from the cache) the operator and preconditioner, solve the merged right-hand
-// sides, copy each request's columns and statistics back.  Runs without the lock.
+// Mark request r complete (lock held): timings, status, waiter woken; r leaves the batch's
+// list, since its waiter may free it from now on.
+void complete_locked(vie_server srv, Req *r, Batch *b, vie_status st, const std::string &err) {
+    b->reqs.erase(std::remove(b->reqs.begin(), b->reqs.end(), r), b->reqs.end());
+    r->t_end = Clock::now();
+    r->cache_hit = (b->entry != nullptr) || r->joined;
+    r->merged = b->n_total;
+    if (st < 0) {
+        r->status = st;
+        r->err = err;
+    }
+    r->done = true;
+    srv->n_completed++;
+    srv->cv_done.notify_all();
+}
+
+// The slots of one running solve (see the header): completes requests whose columns have all
+// ended and lets queued requests of the same batch key join the freed slots.
+struct SlotHook : SolveHook {
+    vie_server srv;
+    Batch *batch;
+    vie_op op;
+    long long n3;
+    c128 *e;                    // device incident fields, one column per slot
+    std::vector<Req *> owner;   // slot -> request
+    std::vector<int> owner_col; // slot -> column of that request
+    std::vector<int> free_slots;
+
+    vie_status boundary(const std::vector<int> &ended, const vie_solve_stats *stats, const c128 *x, c128 *b,
+                        hipStream_t s, std::vector<int> *refill) override {
+        // requests whose last column ended: copy their columns out, then complete them
+        std::vector<Req *> fin;
+        for (int q : ended) {
+            Req *r = owner[q];
+            if (!r) continue;
+            r->st_out[owner_col[q]] = stats[q];
+            if (stats[q].status != VIE_OK) r->status = VIE_NOT_CONVERGED;
+            if (--r->cols_left == 0) fin.push_back(r);
+        }
+        for (Req *r : fin)
+            for (int q = 0; q < (int)owner.size(); ++q)
+                if (owner[q] == r) {
+                    VIE_HIP(hipMemcpyAsync(r->x_out + 2 * n3 * owner_col[q], x + n3 * q, sizeof(c128) * n3,
+                                           hipMemcpyDeviceToHost, s));
+                    owner[q] = nullptr;
+                    free_slots.push_back(q);
+                }
+        if (!fin.empty()) VIE_HIP(hipStreamSynchronize(s));
+        std::vector<Req *> join;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            // queued requests of this batch key that fit the free slots join, in queue order
+            if (!free_slots.empty() && !srv->stop) {
+                int nfree = (int)free_slots.size();
+                for (size_t qi = 0; qi < srv->queue.size() && nfree > 0;) {
+                    Req *r = srv->queue[qi];
+                    if (r->batch_key == batch->batch_key && r->nrhs <= nfree) {
+                        srv->queue.erase(srv->queue.begin() + (long)qi);
+                        nfree -= r->nrhs;
+                        r->joined = 1;
+                        r->t_start = Clock::now();
+                        batch->reqs.push_back(r);
+                        batch->n_total++;
+                        srv->n_hits++;
+                        join.push_back(r);
+                    } else {
+                        ++qi;
+                    }
+                }
+            }
+            // the requests of the solve's last boundary are completed by the worker, together
+            // with the end of the solve
+            const bool last = join.empty() && (int)free_slots.size() == (int)owner.size();
+            for (Req *r : fin) {
+                r->finished = true;
+                if (!last) complete_locked(srv, r, batch, VIE_OK, std::string());
+            }
+        }
+        for (Req *r : join) {
+            r->cols_left = r->nrhs;
+            r->status = VIE_OK;
+            for (int i = 0; i < r->nrhs; ++i) {
+                const int q = free_slots.back();
+                free_slots.pop_back();
+                owner[q] = r;
+                owner_col[q] = i;
+                VIE_HIP(hipMemcpyAsync(e + n3 * q, r->e.data() + 2 * n3 * i, sizeof(c128) * n3,
+                                       hipMemcpyHostToDevice, s));
+                VIE_CHECK(vie_rhs(op, e + n3 * q, b + n3 * q, 1, s));
+                refill->push_back(q);
+            }
+        }
+        return VIE_OK;
+    }
+};
+
+// Build (or take from the cache) the operator and preconditioner and solve the merged
+// right-hand sides as slots of one batched GMRES (SlotHook completes the requests and takes
+// joiners).  Runs without the lock.
 vie_status run_batch(vie_server srv, Batch *b, hipStream_t s, vie_op *op_out, vie_pc *pc_out) {
-    (void)srv;
     StreamScope scope(s);  // the batch's buffers are reused once this worker's stream is past them
     Req *r0 = b->reqs[0];
     const long long N = (long long)r0->grid[0] * r0->grid[1] * r0->grid[2];
@@ -191,30 +298,33 @@ vie_status run_batch(vie_server srv, Batch *b, hipStream_t s, vie_op *op_out, vi
     VIE_CHECK(e.ensure(sizeof(c128) * n3 * b->R));
     VIE_CHECK(bb.ensure(sizeof(c128) * n3 * b->R));
     VIE_CHECK(x.ensure(sizeof(c128) * n3 * b->R));
+    SlotHook hook;
+    hook.srv = srv;
+    hook.batch = b;
+    hook.op = op;
+    hook.n3 = n3;
+    hook.e = e.as<c128>();
+    hook.owner.assign(b->R, nullptr);
+    hook.owner_col.assign(b->R, 0);
     long long off = 0;
+    int slot = 0;
     for (Req *r : b->reqs) {
         VIE_HIP(hipMemcpyAsync(e.as<c128>() + off, r->e.data(), sizeof(c128) * n3 * r->nrhs, hipMemcpyHostToDevice, s));
         off += n3 * r->nrhs;
+        r->cols_left = r->nrhs;
+        r->status = VIE_OK;
+        for (int i = 0; i < r->nrhs; ++i, ++slot) {
+            hook.owner[slot] = r;
+            hook.owner_col[slot] = i;
+        }
     }
     VIE_CHECK(vie_rhs(op, e.p, bb.p, b->R, s));
     VIE_HIP(hipMemsetAsync(x.p, 0, sizeof(c128) * n3 * b->R, s));
     std::vector<vie_solve_stats> st(b->R);
     vie_solve_opts so = r0->so;
     so.x0_given = 0;
-    const vie_status ss = vie_solve(op, pc, bb.p, x.p, b->R, &so, st.data(), s);
+    const vie_status ss = solve_gmres(op, pc, bb.as<c128>(), x.as<c128>(), b->R, &so, st.data(), s, &hook);
     if (ss < 0) return ss;
-    off = 0;
-    int col = 0;
-    for (Req *r : b->reqs) {
-        VIE_HIP(hipMemcpyAsync(r->x_out, x.as<c128>() + off, sizeof(c128) * n3 * r->nrhs, hipMemcpyDeviceToHost, s));
-        off += n3 * r->nrhs;
-        r->status = VIE_OK;
-        for (int i = 0; i < r->nrhs; ++i) {
-            r->st_out[i] = st[col + i];
-            if (st[col + i].status != VIE_OK) r->status = VIE_NOT_CONVERGED;
-        }
-        col += r->nrhs;
-    }
     VIE_HIP(hipStreamSynchronize(s));
     return VIE_OK;
 }
@@ -235,12 +345,12 @@ void worker(vie_server srv) {
         lk.unlock();
         const Clock::time_point t0 = Clock::now();
         for (Req *r : b.reqs) r->t_start = t0;
+        const size_t n_admitted = b.reqs.size();  // later joiners are counted when they join
         vie_op op = nullptr;
         vie_pc pc = nullptr;
         vie_status st = have_stream ? run_batch(srv, &b, s, &op, &pc) : VIE_EDEVICE;
         if (!have_stream) vie_set_error("vie_server: hipStreamCreate failed");
         const std::string err = st < 0 ? std::string(vie_last_error()) : std::string();
-        const Clock::time_point t1 = Clock::now();
         lk.lock();
         srv->running--;
         srv->committed -= b.run;
@@ -248,10 +358,10 @@ void worker(vie_server srv) {
         if (b.entry) {
             b.entry->in_use = false;
             b.entry->last = ++srv->tick;
-            srv->n_hits += (int64_t)b.reqs.size();
+            srv->n_hits += (int64_t)n_admitted;
         } else if (st >= 0) {
             Entry *ne = new Entry();
-            ne->key = b.reqs[0]->key;
+            ne->key = b.key;
             ne->op = op;
             ne->pc = pc;
             ne->bytes = b.resident;
@@ -262,16 +372,10 @@ void worker(vie_server srv) {
             if (pc) precond_destroy(pc);
             if (op) vie_destroy(op);
         }
-        for (Req *r : b.reqs) {
-            r->t_end = t1;
-            r->cache_hit = b.entry != nullptr;
-            r->merged = (int)b.reqs.size();
-            if (st < 0) {
-                r->status = st;
-                r->err = err;
-            }
-            r->done = true;
-            srv->n_completed++;
+        const std::vector<Req *> left = b.reqs;  // finished at the last boundary, or the solve failed
+        for (Req *r : left) {
+            if (r->finished && st >= 0) complete_locked(srv, r, &b, VIE_OK, std::string());
+            else complete_locked(srv, r, &b, st < 0 ? st : VIE_EDEVICE, st < 0 ? err : "solve ended early");
         }
         srv->cv_done.notify_all();
         srv->cv_work.notify_all();
@@ -438,6 +542,7 @@ extern "C" vie_status vie_server_wait(vie_server srv, int64_t id, vie_request_ti
         times->total_ms = ms_between(r->t_submit, r->t_end);
         times->cache_hit = r->cache_hit;
         times->merged = r->merged;
+        times->joined = r->joined;
     }
     const vie_status st = r->status;
     if (st < 0) vie_set_error("vie_server_wait: request " + std::to_string(id) + " failed: " + r->err);

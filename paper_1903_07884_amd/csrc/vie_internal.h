@@ -293,5 +293,15 @@ vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s);
 // krylov.hip
 // complex partial sums per right-hand side kept by the Arnoldi reductions (vector length n)
 long long arnoldi_partials(long long n, int restart);
+// Called by the batched GMRES at every restart-cycle boundary, before the next cycle: `ended`
+// lists the columns (slots) whose solve ended since the previous call; their stats are final
+// and so is their column of x once the work queued on s is done.  The hook may put a new
+// right-hand side into ended slots (writing b on s) and returns those slots in `refill`: the
+// solver restarts them from x = 0 with fresh statistics.
+struct SolveHook {
+    virtual ~SolveHook() = default;
+    virtual vie_status boundary(const std::vector<int> &ended, const vie_solve_stats *stats, const c128 *x,
+                                c128 *b, hipStream_t s, std::vector<int> *refill) = 0;
+};
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int nrhs,
-                       const vie_solve_opts *o, vie_solve_stats *stats, hipStream_t s);
+                       const vie_solve_opts *o, vie_solve_stats *stats, hipStream_t s, SolveHook *hook = nullptr);

@@ -69,7 +69,7 @@ class Request(ctypes.Structure):
 
 class RequestTimes(ctypes.Structure):
     _fields_ = [('queue_ms', ctypes.c_double), ('run_ms', ctypes.c_double), ('total_ms', ctypes.c_double),
-                ('cache_hit', ctypes.c_int32), ('merged', ctypes.c_int32)]
+                ('cache_hit', ctypes.c_int32), ('merged', ctypes.c_int32), ('joined', ctypes.c_int32)]
 
 
 class ServerInfo(ctypes.Structure):

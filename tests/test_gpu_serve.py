@@ -164,3 +164,57 @@ def test_budget_admission_and_eviction(gpu_lib):
     assert all(st[0]['status'] == 0 for _, st, _ in out)
     assert info['evictions'] >= 1
     assert info['peak_committed_bytes'] <= budget
+
+
+def test_continuous_batching_completes_early_and_takes_joiners(gpu_lib):
+    """Continuous batching: a solve's right-hand sides are slots.  A request whose columns end
+    at the first restart boundary (a zero incident field) completes while its batch-mate goes
+    on; a request submitted after the batch was admitted joins the freed slot at a later
+    boundary.  Every result equals the plain library solve of its request."""
+    import time
+    import torch
+    devs = _devices()
+    busy = devs['block']
+    dev = dict(devs['guide'])
+    dev['grid'] = (128, 8, 4)
+    dev['chi'] = W.waveguide((128, 8, 4))
+    dev['precond'] = False  # unpreconditioned, GMRES(10): many restart cycles at 1e-10
+    kw = dict(tol=1e-10, restart=10)
+    srv = gpu_lib.Server(workers=1, max_batch_rhs=64)
+    r_busy = srv.submit(e_inc=_e(busy, 1, 3), tol=1e-10, **busy)
+    e_a = np.zeros_like(_e(dev, 1, 0))
+    e_b = _e(dev, 1, 51)
+    e_c = _e(dev, 1, 52)
+    r_a = srv.submit(e_inc=e_a, **kw, **dev)  # queued behind the busy solve with r_b: merged
+    r_b = srv.submit(e_inc=e_b, **kw, **dev)
+    t0 = time.time()
+    while True:  # until the (a, b) solve is admitted
+        info = srv.info()
+        if info['queued'] == 0 and info['running'] == 1 and srv.done(r_busy):
+            break
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    r_c = srv.submit(e_inc=e_c, **kw, **dev)
+    xa, sa, ta = srv.wait(r_a)
+    xb, sb, tb = srv.wait(r_b)
+    xc, sc, tc = srv.wait(r_c)
+    srv.wait(r_busy)
+    while srv.info()['running']:  # the worker's bookkeeping after the last result
+        time.sleep(0.001)
+    info = srv.info()
+    srv.close()
+    print('a: %s; b: %s (iters %d); c: %s (iters %d); server %s' % (ta, tb, sb[0]['iters'], tc, sc[0]['iters'], info))
+    assert ta['merged'] >= 2 and tb['merged'] >= 2
+    assert tc['joined'] == 1 and ta['joined'] == 0 and tb['joined'] == 0
+    assert ta['total_ms'] < tb['total_ms']  # a returned while b was still being solved
+    assert np.abs(xa).max() == 0.0 and sa[0]['iters'] == 0
+    op = gpu_lib.Operator(dev['grid'], dev['voxel_size'], dev['k_background'], dev['chi'])
+    for x, st, e in ((xb, sb, e_b), (xc, sc, e_c)):
+        ed = torch.from_numpy(e).cuda()
+        b = torch.empty_like(ed)
+        op.rhs(ed, b, nrhs=1)
+        xd = torch.zeros_like(b)
+        ref = gpu_lib.solve(op, None, b, xd, tol=1e-10, restart=10)
+        assert st[0]['status'] == 0 and st[0]['iters'] == ref[0]['iters']
+        assert _rel(x, xd.cpu().numpy()) <= 1e-12
+    assert info['solves'] == 2  # the busy solve and the (a, b) solve, which c joined
