@@ -141,7 +141,8 @@ def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, po
                 k, rid, late_ms, nrhs = q.get()
                 _, st, tm = srv.wait(rid)
                 rec[k] = dict(lat=late_ms + tm['total_ms'], queue=tm['queue_ms'], hit=tm['cache_hit'],
-                              merged=tm['merged'], nrhs=nrhs, ok=all(x['status'] == 0 for x in st),
+                              merged=tm['merged'], joined=tm['joined'], nrhs=nrhs,
+                              ok=all(x['status'] == 0 for x in st),
                               done=time.perf_counter())
 
         th = threading.Thread(target=collect)
@@ -162,6 +163,7 @@ def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, po
                     mean_queue_ms=float(np.mean([r['queue'] for r in rec])),
                     cache_hit_fraction=float(np.mean([r['hit'] for r in rec])),
                     mean_merged=float(np.mean([r['merged'] for r in rec])),
+                    joined_fraction=float(np.mean([r['joined'] for r in rec])),
                     all_converged=all(r['ok'] for r in rec))
 
     vie.autotune(False)
