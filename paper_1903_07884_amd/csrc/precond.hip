@@ -1040,22 +1040,31 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
         VIE_HIP(hipGetLastError());
         return VIE_OK;
     };
-    // Two-level right-looking LU: macro panels of 2 x LU_NB columns.  The first sub-panel's
-    // update reaches only the second sub-panel (its columns, and its rows after the second
-    // sub-panel's interchanges); the trailing matrix is updated once with K = 2 LU_NB.
-    for (int j0 = 0; j0 < m; j0 += 2 * LU_NB) {
-        const int w1 = std::min(LU_NB, m - j0);
-        VIE_CHECK(panel(j0, w1));
-        VIE_CHECK(swap_trsm(j0, w1, 1, 1));
-        const int j1 = j0 + w1;
-        if (j1 >= m) break;
-        const int w2 = std::min(LU_NB, m - j1);
-        VIE_CHECK(update(j1, m, j1, j1 + w2, j0, w1));            // second sub-panel's columns
-        VIE_CHECK(panel(j1, w2));
-        VIE_CHECK(swap_trsm(j1, w2, 1, 0));                      // its interchanges everywhere
-        VIE_CHECK(update(j1, j1 + w2, j1 + w2, m, j0, w1));       // its rows, right of it
-        VIE_CHECK(swap_trsm(j1, w2, 0, 1));                      // U12 of the second sub-panel
-        VIE_CHECK(update(j1 + w2, m, j1 + w2, m, j0, w1 + w2));   // trailing matrix, K = w1 + w2
+    // Two-level right-looking LU: macro panels of ns sub-panels of LU_NB columns.  Each
+    // sub-panel first takes the updates of the earlier sub-panels of its macro panel (its
+    // columns from row jr down), is factored, has its interchanges applied everywhere, and its
+    // rows right of it take the same updates before the U12 solve; the trailing matrix is
+    // updated once per macro panel, with K = the macro panel's width.  Measured: FP32 gains
+    // from wider macro panels (fewer passes over the trailing matrix; 4 sub-panels: -13% update
+    // time at 1024 blocks of 768), FP64 does not (2: the matrix-core time dominates).
+    const int ns = sizeof(R) == 8 ? 2 : 4;
+    for (int J0 = 0; J0 < m; J0 += ns * LU_NB) {
+        int jend = J0;
+        for (int i = 0; i < ns && J0 + i * LU_NB < m; ++i) {
+            const int jr = J0 + i * LU_NB, w = std::min(LU_NB, m - jr);
+            jend = jr + w;
+            if (i == 0) {
+                VIE_CHECK(panel(jr, w));
+                VIE_CHECK(swap_trsm(jr, w, 1, 1));
+            } else {
+                VIE_CHECK(update(jr, m, jr, jr + w, J0, jr - J0));       // its columns
+                VIE_CHECK(panel(jr, w));
+                VIE_CHECK(swap_trsm(jr, w, 1, 0));                      // its interchanges everywhere
+                VIE_CHECK(update(jr, jr + w, jr + w, m, J0, jr - J0));   // its rows, right of it
+                VIE_CHECK(swap_trsm(jr, w, 0, 1));                      // its U12
+            }
+        }
+        VIE_CHECK(update(jend, m, jend, m, J0, jend - J0));             // trailing matrix
     }
     return VIE_OK;
 }
