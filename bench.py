@@ -92,6 +92,27 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
     return models
 
 
+def copy_gbps(dev, nbytes=1 << 30, reps=5):
+    """Bytes moved per second by torch's elementwise negation over `nbytes` of float32 (reads
+    and writes nbytes each), timed with events on torch's stream; the best of `reps`."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.neg(src, out=dst)
+        b.record()
+        b.synchronize()
+        t = a.elapsed_time(b) * 1e-3
+        best = t if best is None else min(best, t)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def counter_traffic(kernel, workload_tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the sources."""
     path = os.path.join(ROOT, 'profiles', '%s_c%d_counters.txt' % (kernel, workload_tag))
@@ -505,6 +526,9 @@ def main():
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=HBM_PEAK_GBS, unit='GB/s',
                     frac=achieved / HBM_PEAK_GBS, traffic=counter_traffic(dom, args.config),
                     per_launch_bytes=amount)
+        if not args.copy_probe:  # context: what a plain device copy reaches on this HBM
+            cp = copy_gbps(dev)
+            roof.update(copy_gbps=cp, frac_of_copy=achieved / cp)
     else:
         roof = dict(kernel=dom, bound='alu', achieved=None, peak=FP64_PEAK_TFLOPS, unit='TFLOP/s', frac=None,
                     traffic=None)
