@@ -688,6 +688,39 @@ def test_precond_apply_c64_within_single_precision(gpu_lib):
     assert err < 1e-5
 
 
+LARGE_BLOCK_CASES = [
+    # grid (m = 3 ny nz, random x-invariant contrast: no identity rows), factor precision, bar
+    ((6, 24, 8), 'c128', 1e-10),  # m = 576 > 512: the first FP64 panels take the column-slice
+                                  # kernels and the row moves come from replaying the pivots
+    ((4, 44, 8), 'c64', 1e-4),    # m = 1056 > 1024: the same for FP32, 4-sub-panel macro panels
+]
+
+
+@pytest.mark.parametrize("case", LARGE_BLOCK_CASES)
+def test_precond_apply_large_blocks(gpu_lib, case):
+    import torch
+    grid, prec, bar = case
+    delta = 50e-9
+    K = oracle_generator(grid, delta)
+    chi = np.broadcast_to(random_contrast(grid, 12)[:, :, :1], grid[::-1]).copy()  # x-invariant
+    M = OCT.contrast_from_chi(chi)
+    ref_pc = OC.BlockedPreconditioner(K, M, grid)
+    c64 = prec == 'c64'
+    op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=c64)
+    pc = gpu_lib.Preconditioner(op, factor_prec=gpu_lib.VIE_C64 if c64 else gpu_lib.VIE_C128)
+    n = 3 * int(np.prod(grid))
+    r = W.random_field((2, n), 41)
+    z_ref = np.stack([ref_pc.apply(r[i]) for i in range(2)])
+    rd = _to_dev(r.astype(np.complex64) if c64 else r)
+    zd = torch.empty_like(rd)
+    pc.apply(rd, zd, nrhs=2)
+    err = _rel(zd.cpu().numpy().astype(np.complex128), z_ref)
+    info = pc.info()
+    print('large blocks', grid, prec, 'm', info['active_m'], 'err', err)
+    assert info['active_m'] == 3 * grid[1] * grid[2]
+    assert err < bar
+
+
 def _bragg_problem(grid=(48, 8, 2), delta=50e-9):
     nx, ny, nz = grid
     K = oracle_generator(grid, delta)
