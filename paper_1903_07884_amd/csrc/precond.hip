@@ -138,26 +138,35 @@ __global__ void k_chan_table2(const c128 *Ch, c128 *Ch2, int bx, int by, int bz,
 
 // ---------------------------------------------------------------- assembly
 // D[s] column-major m x m, s-th stored block (mode ks, box bs), over the cross-section rows
-// rows[0..m) (entry a*by*bz + z*by + y)
+// rows[0..m) (entry a*by*bz + z*by + y).  One workgroup per (AS_COLS columns, block): each
+// thread decodes its rows once; a column's decoding is uniform across the workgroup; every
+// column is written with coalesced stores.
+#define AS_COLS 16
 template <class R>
-__global__ void k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode, const int *blk_box,
-                           const int *rows, cpx<R> *D, int m, int by, int bz) {
-    const int ndy = 2 * by - 1, ndz = 2 * bz - 1;
-    int s = blockIdx.y;
-    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (e >= (long long)m * m) return;
-    const int r = rows[(int)(e % m)], col = rows[(int)(e / m)];
-    int ar = r / (by * bz), yr = r % by, zr = (r / by) % bz;
-    int ac = col / (by * bz), yc = col % by, zc = (col / by) % bz;
-    int k = blk_mode[s], b = blk_box[s];
+__global__ void __launch_bounds__(256) k_assemble(const c128 *Ch, const c128 *Mt, const int *blk_mode,
+                                                  const int *blk_box, const int *rows, cpx<R> *D, int m, int by,
+                                                  int bz) {
+    const int ndy = 2 * by - 1, ndz = 2 * bz - 1, byz = by * bz;
+    const int s = blockIdx.y, c0 = blockIdx.x * AS_COLS;
+    const c128 *chk = Ch + (long long)blk_mode[s] * 6 * ndz * ndy;
+    const c128 *mtb = Mt + (long long)blk_box[s] * byz;
+    cpx<R> *Ds = D + (long long)s * m * m;
     const int cidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    int c = cidx[ar][ac];
-    c128 ch = Ch[(long long)k * 6 * ndz * ndy + (long long)c * ndz * ndy + (zr - zc + bz - 1) * ndy + (yr - yc + by - 1)];
-    c128 mt = Mt[(long long)b * by * bz + zr * by + yr];
-    c128 v = mt * ch;
-    v = mk(-v.re, -v.im);
-    if (r == col) v.re += 1.0;
-    D[(long long)s * m * m + e] = mk((R)v.re, (R)v.im);
+    const int cend = min(m, c0 + AS_COLS);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int r = rows[i];
+        const int ar = r / byz, rz = r - ar * byz, zr = rz / by, yr = rz - zr * by;
+        const c128 mt = mtb[zr * by + yr];
+        for (int ci = c0; ci < cend; ++ci) {
+            const int col = rows[ci];
+            const int ac = col / byz, cz = col - ac * byz, zc = cz / by, yc = cz - zc * by;
+            const c128 ch = chk[cidx[ar][ac] * ndz * ndy + (zr - zc + bz - 1) * ndy + (yr - yc + by - 1)];
+            c128 v = mt * ch;
+            v = mk(-v.re, -v.im);
+            if (r == col) v.re += 1.0;
+            Ds[(long long)ci * m + i] = mk((R)v.re, (R)v.im);
+        }
+    }
 }
 
 // 2-level blocks: D[s] column-major (3 bz)^2 for the stored block s of mode pair blk_mode[s]
@@ -1627,6 +1636,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     VIE_CHECK(pc->perm.ensure(sizeof(int) * (size_t)pc->nstored * m));
     VIE_CHECK(pc->info.ensure(sizeof(int) * (size_t)pc->nstored));
     dim3 ga((unsigned)(((long long)m * m + 255) / 256), pc->nstored);
+    dim3 gc((unsigned)((m + AS_COLS - 1) / AS_COLS), pc->nstored);
     if (pc->levels == 2) {  // second level: Chan along y + y-DFT of the x-level table, then the blocks
         DevBuf Ch2;
         VIE_CHECK(Ch2.ensure(sizeof(c128) * (size_t)nm * 6 * ndz));
@@ -1644,11 +1654,11 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         VIE_HIP(hipGetLastError());
         VIE_HIP(hipStreamSynchronize(s));
     } else if (pc->prec == VIE_C128)
-        hipLaunchKernelGGL(k_assemble<double>, ga, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
+        hipLaunchKernelGGL(k_assemble<double>, gc, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
                            dmode.as<const int>(), dbox.as<const int>(), pc->rows.as<const int>(),
                            pc->factors.as<c128>(), m, by, bz);
     else
-        hipLaunchKernelGGL(k_assemble<float>, ga, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
+        hipLaunchKernelGGL(k_assemble<float>, gc, dim3(256), 0, s, Ch.as<const c128>(), Mt.as<const c128>(),
                            dmode.as<const int>(), dbox.as<const int>(), pc->rows.as<const int>(),
                            pc->factors.as<c64>(), m, by, bz);
     VIE_HIP(hipGetLastError());
