@@ -280,52 +280,74 @@ __global__ void __launch_bounds__(64) k_generator_far(c128 *gen, int nx, int ny,
 }
 
 // Touching offsets d in {0,1}^3 (the support of the overlap weights reaches the singular
-// point): face form.  One workgroup per such offset.
-__global__ void __launch_bounds__(GEN_THREADS) k_generator_near(c128 *gen, int nx, int ny, int nz, double kappa) {
+// point): face form.  Each offset needs 22 integrals: I3, J(h) for three normal distances per
+// axis, and P for four face pairs of each of the three off-diagonal components.  One
+// workgroup per (offset, integral) writes its value to parts[offset][22]; k_generator_near
+// combines them.
+#define NEAR_PARTS 22
+__global__ void __launch_bounds__(GEN_THREADS) k_generator_near_parts(c128 *parts, int nx, int ny, int nz,
+                                                                      double kappa) {
     __shared__ c128 red[GEN_THREADS];
-    long long N = (long long)nx * ny * nz;
-    int dx = blockIdx.x & 1, dy = (blockIdx.x >> 1) & 1, dz = (blockIdx.x >> 2) & 1;
+    const int off = blockIdx.x / NEAR_PARTS, idx = blockIdx.x % NEAR_PARTS;
+    const int dx = off & 1, dy = (off >> 1) & 1, dz = (off >> 2) & 1;
     if (dx >= nx || dy >= ny || dz >= nz) return;
-    long long o = ((long long)dz * ny + dy) * nx + dx;
-    int d[3] = {dx, dy, dz};
-    c128 out[6];
-    {
-        const int p = 14, ps = 16;
+    const int d[3] = {dx, dy, dz};
+    const int p = 14, ps = 16;
+    c128 v;
+    if (idx == 0) {  // I3
         Wt w3[3] = {{0, (double)dx}, {0, (double)dy}, {0, (double)dz}};
-        c128 I3 = integrate(w3, 3, 0.0, true, kappa, p, ps, red);
-        for (int a = 0; a < 3; ++a) {
-            int q0 = (a + 1) % 3, q1 = (a + 2) % 3;
-            Wt w2[2] = {{0, (double)d[q0 < q1 ? q0 : q1]}, {0, (double)d[q0 < q1 ? q1 : q0]}};
-            c128 J[3];
-            for (int k = 0; k < 3; ++k) {
-                int h = d[a] - 1 + k;
-                J[k] = integrate(w2, 2, (double)h * h, h == 0, kappa, p, ps, red);
-            }
-            c128 F = mk(-(2.0 * J[1].re - J[0].re - J[2].re), -(2.0 * J[1].im - J[0].im - J[2].im));
-            out[a] = F + mk(kappa * kappa * I3.re, kappa * kappa * I3.im);
-        }
+        v = integrate(w3, 3, 0.0, true, kappa, p, ps, red);
+    } else if (idx < 10) {  // J: axis a, normal distance d_a - 1 + k
+        const int a = (idx - 1) / 3, k = (idx - 1) % 3;
+        const int q0 = (a + 1) % 3, q1 = (a + 2) % 3;
+        Wt w2[2] = {{0, (double)d[q0 < q1 ? q0 : q1]}, {0, (double)d[q0 < q1 ? q1 : q0]}};
+        const int h = d[a] - 1 + k;
+        v = integrate(w2, 2, (double)h * h, h == 0, kappa, p, ps, red);
+    } else {  // P: component pair kk, face signs s, s'
         const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-        for (int k = 0; k < 3; ++k) {
-            int a = pa[k], b = pb[k], c = 3 - a - b;
-            c128 tot = czero<double>();
-            for (int s = 1; s >= -1; s -= 2)
-                for (int sp = 1; sp >= -1; sp -= 2) {
-                    Wt w[3];
-                    w[a] = {1, d[a] + 0.5 * s};
-                    w[b] = {1, d[b] - 0.5 * sp};
-                    w[c] = {0, (double)d[c]};
-                    c128 P = integrate(w, 3, 0.0, true, kappa, p, ps, red);
-                    double ss = (double)(s * sp);
-                    tot = tot + mk(ss * P.re, ss * P.im);
-                }
-            out[3 + k] = mk(-tot.re, -tot.im);
-        }
+        const int kk = (idx - 10) / 4, si = ((idx - 10) / 2) % 2, spi = (idx - 10) % 2;
+        const int a = pa[kk], b = pb[kk], c = 3 - a - b;
+        const int sg = si ? -1 : 1, sgp = spi ? -1 : 1;
+        Wt w[3];
+        w[a] = {1, d[a] + 0.5 * sg};
+        w[b] = {1, d[b] - 0.5 * sgp};
+        w[c] = {0, (double)d[c]};
+        v = integrate(w, 3, 0.0, true, kappa, p, ps, red);
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = v;
+}
+
+// K^{aa} = kappa^2 I3 - (2 J(d_a) - J(d_a - 1) - J(d_a + 1)); K^{ab} = -sum s s' P; the
+// components odd in an axis with d = 0 there vanish.  One lane per touching offset.
+__global__ void k_generator_near(c128 *gen, const c128 *parts, int nx, int ny, int nz, double kappa) {
+    const int off = threadIdx.x;
+    if (off >= 8) return;
+    const int dx = off & 1, dy = (off >> 1) & 1, dz = (off >> 2) & 1;
+    if (dx >= nx || dy >= ny || dz >= nz) return;
+    const long long N = (long long)nx * ny * nz;
+    const long long o = ((long long)dz * ny + dy) * nx + dx;
+    const c128 *pt = parts + off * NEAR_PARTS;
+    c128 out[6];
+    const c128 I3 = pt[0];
+    for (int a = 0; a < 3; ++a) {
+        const c128 *J = pt + 1 + 3 * a;
+        c128 F = mk(-(2.0 * J[1].re - J[0].re - J[2].re), -(2.0 * J[1].im - J[0].im - J[2].im));
+        out[a] = F + mk(kappa * kappa * I3.re, kappa * kappa * I3.im);
+    }
+    for (int k = 0; k < 3; ++k) {
+        c128 tot = czero<double>();
+        for (int si = 0; si < 2; ++si)
+            for (int spi = 0; spi < 2; ++spi) {
+                const c128 P = pt[10 + 4 * k + 2 * si + spi];
+                const double ss = (si == spi) ? 1.0 : -1.0;
+                tot = tot + mk(ss * P.re, ss * P.im);
+            }
+        out[3 + k] = mk(-tot.re, -tot.im);
     }
     if (dx == 0 || dy == 0) out[3] = czero<double>();
     if (dx == 0 || dz == 0) out[4] = czero<double>();
     if (dy == 0 || dz == 0) out[5] = czero<double>();
-    if (threadIdx.x == 0)
-        for (int c = 0; c < 6; ++c) gen[c * N + o] = out[c];
+    for (int c = 0; c < 6; ++c) gen[c * N + o] = out[c];
 }
 
 vie_status launch_generator(vie_op op, hipStream_t s) {
@@ -339,8 +361,13 @@ vie_status launch_generator(vie_op op, hipStream_t s) {
     hipLaunchKernelGGL(k_generator_far, dim3((unsigned)N), dim3(64), 0, s, op->gen.as<c128>(), op->nx, op->ny,
                        op->nz, op->kappa);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_generator_near, dim3(8), dim3(GEN_THREADS), 0, s, op->gen.as<c128>(), op->nx, op->ny,
-                       op->nz, op->kappa);
+    DevBuf parts;
+    VIE_CHECK(parts.ensure(sizeof(c128) * 8 * NEAR_PARTS));
+    hipLaunchKernelGGL(k_generator_near_parts, dim3(8 * NEAR_PARTS), dim3(GEN_THREADS), 0, s, parts.as<c128>(),
+                       op->nx, op->ny, op->nz, op->kappa);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_generator_near, dim3(1), dim3(64), 0, s, op->gen.as<c128>(), (const c128 *)parts.as<c128>(),
+                       op->nx, op->ny, op->nz, op->kappa);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
