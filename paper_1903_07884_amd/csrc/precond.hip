@@ -670,29 +670,43 @@ __global__ void __launch_bounds__(256) k_lu_swap_trsm(cpx<R> *A, const int *move
     }
 }
 
-// L11^{-1} of the panel [j0, j0 + w) (unit lower, strictly lower part stored) into Linv[block],
-// one workgroup per block, lane jc forming column jc from an LDS copy of L11.
+// Marks the entries [q0, H) of a register column as computed here: the compiler then finishes
+// a substitution row before starting the next, instead of interleaving rows and holding the
+// factor entries of many rows in registers.  Emits no instruction.
+template <class R, int H>
+__device__ __forceinline__ void settle(cpx<R> (&x)[H], int q0) {
+#pragma unroll
+    for (int q = 0; q < H; ++q)
+        if (q >= q0) asm volatile("" : "+v"(x[q].re), "+v"(x[q].im));
+}
+
+// L11^{-1} of the panel [j0, j0 + w) (unit lower, strictly lower part stored) into Linv[block]
+// (row-major LU_NB x LU_NB, strictly lower part; zero diagonal and above).  One workgroup per
+// block; lane jc forms column jc of the inverse in registers by forward substitution with L11
+// read as LDS broadcasts, one row at a time (settled).
 template <class R>
 __global__ void __launch_bounds__(64) k_lu_linv(const cpx<R> *A, cpx<R> *Linv, int m, int j0, int w) {
-    __shared__ cpx<R> L[LU_NB][LU_NB + 1];
-    __shared__ cpx<R> X[LU_NB][LU_NB + 1];
+    __shared__ cpx<R> L[LU_NB][LU_NB + 1];  // L[r][c], zero past w
     const cpx<R> *a = A + (long long)blockIdx.x * m * m;
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-        int r = e % w, c = e / w;
-        L[r][c] = a[(long long)(j0 + c) * m + j0 + r];
-        X[r][c] = czero<R>();
+    for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) {
+        const int r = e % LU_NB, c = e / LU_NB;
+        L[r][c] = (r < w && c < w) ? a[(long long)(j0 + c) * m + j0 + r] : czero<R>();
     }
     __syncthreads();
     const int jc = threadIdx.x;
-    if (jc < w)
-        for (int i = jc + 1; i < w; ++i) {
-            cpx<R> acc = L[i][jc];
-            for (int k = jc + 1; k < i; ++k) acc = acc + L[i][k] * X[k][jc];
-            X[i][jc] = mk(-acc.re, -acc.im);
-        }
-    __syncthreads();
+    if (jc >= LU_NB) return;
+    cpx<R> x[LU_NB];
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) x[q] = mk(q == jc ? R(1) : R(0), R(0));
+#pragma unroll
+    for (int k = 0; k < LU_NB; ++k) {
+#pragma unroll
+        for (int q = k + 1; q < LU_NB; ++q) x[q] = cfms(x[q], L[q][k], x[k]);
+        settle(x, k + 1);
+    }
     cpx<R> *out = Linv + (long long)blockIdx.x * LU_NB * LU_NB;
-    for (int e = threadIdx.x; e < LU_NB * LU_NB; e += blockDim.x) out[e] = X[e / LU_NB][e % LU_NB];
+#pragma unroll
+    for (int q = 0; q < LU_NB; ++q) out[q * LU_NB + jc] = q > jc ? x[q] : czero<R>();
 }
 
 
@@ -830,16 +844,6 @@ __global__ void k_lu_perm(const int *ipiv, int *perm, int m, int nblk) {
 }
 
 #define TS 64
-// Marks the entries [q0, H) of a register column as computed here: the compiler then finishes
-// a substitution row before starting the next, instead of interleaving rows and holding the
-// factor entries of many rows in registers.  Emits no instruction.
-template <class R, int H>
-__device__ __forceinline__ void settle(cpx<R> (&x)[H], int q0) {
-#pragma unroll
-    for (int q = 0; q < H; ++q)
-        if (q >= q0) asm volatile("" : "+v"(x[q].re), "+v"(x[q].im));
-}
-
 // Setup: replace every 64x64 diagonal tile of the packed LU factors by the inverses of its
 // unit-lower part (strictly lower entries) and of its upper part (upper entries incl. the
 // diagonal).  The block solves then apply each diagonal tile as a parallel product.
