@@ -342,7 +342,7 @@ def main():
                          'capacity, 1000 requests each (one JSON line)')
     args = ap.parse_args()
     if args.gpus != 1:
-        print('bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU sharding is '
+        print('bench.py runs on one GPU only (--gpus %d requested); sharding over several GPUs is '
               'a design note, not an implementation' % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -336,7 +336,7 @@ vie_status norms(Ctx &C, const c128 *w, c128 *out) {
 }
 
 // Classical Gram-Schmidt twice against v_0..v_j, the Givens update of column j and
-// v_{j+1} = w / h_{j+1,j} (Sec. 1: GMRES; the orthogonalisation is this build's choice).
+// v_{j+1} = w / h_{j+1,j} (Sec. 1: GMRES; the orthogonalisation is this library's choice).
 template <class VT>
 vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState &S, int m, dim3 grid_e,
                      VT *vnext) {
