@@ -393,18 +393,19 @@ __global__ void k_ysplit_fwd(const cpx<R> *work, cpx<R> *yb, int ny, int nz, int
     for (int i = threadIdx.x; i < nr * Py; i += blockDim.x) dst[i] = res[i];
 }
 
-// (b) z coupling: one thread per (rhs, x-frequency, y-frequency), the 3x3 blocks of the
-// (x, y)-transformed generator summed directly over the z offsets (parity signs as in the fused
-// pass); yb -> yc.
+// (b) z coupling: one thread per (rhs, x-frequency, y-frequency, z), its three components
+// summed directly over the z offsets with the 3x3 blocks of the (x, y)-transformed generator
+// (parity signs as in the fused pass); yb -> yc.  Threads run z fastest: a wavefront covers a
+// few y-frequencies, so its generator reads fall in a few [dz][c] blocks (y-frequency fastest
+// put every lane in a block of its own, 64 cache lines per load) and its yb reads are shared.
 template <class R>
-__global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *yb, cpx<R> *yc, const cpx<R> *khat, int nz,
-                                                       int Px, int Py, int Hy) {
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long tot = (long long)gridDim.y * Px * Py;
-    const long long rk = t / Py;  // (rhs * Px + kx) within this rhs row of the grid
-    if (t >= (long long)Px * Py) return;
-    (void)tot;
-    const int ky = (int)(t - rk * Py), kx = (int)rk;
+__global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *__restrict__ yb, cpx<R> *__restrict__ yc,
+                                                       const cpx<R> *__restrict__ khat, int nz, int Px, int Py,
+                                                       int Hy) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // within one right-hand side
+    if (t >= Px * nz * Py) return;
+    const int kx = t / (nz * Py), i = t - kx * (nz * Py);
+    const int ky = i / nz, z = i - ky * nz;
     const long long rhs = blockIdx.y;
     const int rows = 3 * nz;
     const int kxo = kx <= Px - kx ? kx : Px - kx, kyo = ky <= Py - ky ? ky : Py - ky;
@@ -412,23 +413,21 @@ __global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *yb, cpx<R> 
     const cpx<R> *u = yb + (rhs * Px + kx) * rows * (long long)Py + ky;
     cpx<R> *o = yc + (rhs * Px + kx) * rows * (long long)Py + ky;
     const cpx<R> *g = khat + ((long long)kxo * Hy + kyo) * nz * 6;  // [dz][c]
-    for (int z = 0; z < nz; ++z) {
-        cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
-        for (int zp = 0; zp < nz; ++zp) {
-            const int dz = z - zp;
-            const R sz = dz < 0 ? R(-1) : R(1);
-            const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6;
-            const cpx<R> gxx = gz[0], gyy = gz[1], gzz = gz[2];
-            const cpx<R> gxy = sxy * gz[3], gxz = (sx * sz) * gz[4], gyz = (sy * sz) * gz[5];
-            const cpx<R> u0 = u[(long long)zp * Py], u1 = u[(long long)(nz + zp) * Py], u2 = u[(long long)(2 * nz + zp) * Py];
-            a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
-            a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
-            a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
-        }
-        o[(long long)z * Py] = a0;
-        o[(long long)(nz + z) * Py] = a1;
-        o[(long long)(2 * nz + z) * Py] = a2;
+    cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
+    for (int zp = 0; zp < nz; ++zp) {
+        const int dz = z - zp;
+        const R sz = dz < 0 ? R(-1) : R(1);
+        const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6;
+        const cpx<R> gxx = gz[0], gyy = gz[1], gzz = gz[2];
+        const cpx<R> gxy = sxy * gz[3], gxz = (sx * sz) * gz[4], gyz = (sy * sz) * gz[5];
+        const cpx<R> u0 = u[zp * Py], u1 = u[(nz + zp) * Py], u2 = u[(2 * nz + zp) * Py];
+        a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
+        a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
+        a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
     }
+    o[z * Py] = a0;
+    o[(nz + z) * Py] = a1;
+    o[(2 * nz + z) * Py] = a2;
 }
 
 // (c) inverse y-FFT of `lg` coupled rows per workgroup, cropped back into the x-spectra.
@@ -508,7 +507,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
         vie_lds_attr((const void *)k_ysplit_fwd<R>, ldsy);
         hipLaunchKernelGGL(k_ysplit_fwd<R>, dim3(gx, nrhs), dim3(256), ldsy, s, (const cpx<R> *)work, y1, ny, nz, Px,
                            lg, op->py);
-        const long long pts = (long long)Px * Py;
+        const long long pts = (long long)Px * nz * Py;
         hipLaunchKernelGGL(k_ysplit_couple<R>, dim3((unsigned)((pts + 255) / 256), nrhs), dim3(256), 0, s,
                            (const cpx<R> *)y1, y2, khat, nz, Px, Py, op->Hy);
         vie_lds_attr((const void *)k_ysplit_inv<R>, ldsy);
