@@ -393,41 +393,66 @@ __global__ void k_ysplit_fwd(const cpx<R> *work, cpx<R> *yb, int ny, int nz, int
     for (int i = threadIdx.x; i < nr * Py; i += blockDim.x) dst[i] = res[i];
 }
 
-// (b) z coupling: one thread per (rhs, x-frequency, y-frequency, z), its three components
-// summed directly over the z offsets with the 3x3 blocks of the (x, y)-transformed generator
-// (parity signs as in the fused pass); yb -> yc.  Threads run z fastest: a wavefront covers a
-// few y-frequencies, so its generator reads fall in a few [dz][c] blocks (y-frequency fastest
-// put every lane in a block of its own, 64 cache lines per load) and its yb reads are shared.
+// (b) z coupling: one workgroup per (rhs, x-frequency, tile of KB = 256 / nz y-frequencies),
+// one thread per (y-frequency, z) computing its three components as a direct sum over the z
+// offsets with the 3x3 blocks of the (x, y)-transformed generator (parity signs as in the
+// fused pass); yb -> yc.  The tile's y-spectra (3 nz rows) and generator blocks ([dz][c] per
+// y-frequency, padded against bank conflicts) are staged in LDS with coalesced loads, and the
+// results leave through LDS as coalesced rows.
 template <class R>
 __global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *__restrict__ yb, cpx<R> *__restrict__ yc,
                                                        const cpx<R> *__restrict__ khat, int nz, int Px, int Py,
                                                        int Hy) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;  // within one right-hand side
-    if (t >= Px * nz * Py) return;
-    const int kx = t / (nz * Py), i = t - kx * (nz * Py);
-    const int ky = i / nz, z = i - ky * nz;
+    cpx<R> *us = reinterpret_cast<cpx<R> *>(vie_smem);  // [3 nz][KB] y-spectra, then results
+    const int KB = 256 / nz, rows = 3 * nz, gst = 6 * nz + 1;
+    cpx<R> *gs = us + rows * KB;                        // [KB][gst] generator blocks
+    const int ntile = (Py + KB - 1) / KB;
+    const int kx = blockIdx.x / ntile, ky0 = (blockIdx.x - kx * ntile) * KB;
+    const int kb = min(KB, Py - ky0);
     const long long rhs = blockIdx.y;
-    const int rows = 3 * nz;
-    const int kxo = kx <= Px - kx ? kx : Px - kx, kyo = ky <= Py - ky ? ky : Py - ky;
-    const R sx = kx > Px - kx ? R(-1) : R(1), sy = ky > Py - ky ? R(-1) : R(1), sxy = sx * sy;
-    const cpx<R> *u = yb + (rhs * Px + kx) * rows * (long long)Py + ky;
-    cpx<R> *o = yc + (rhs * Px + kx) * rows * (long long)Py + ky;
-    const cpx<R> *g = khat + ((long long)kxo * Hy + kyo) * nz * 6;  // [dz][c]
-    cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
-    for (int zp = 0; zp < nz; ++zp) {
-        const int dz = z - zp;
-        const R sz = dz < 0 ? R(-1) : R(1);
-        const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6;
-        const cpx<R> gxx = gz[0], gyy = gz[1], gzz = gz[2];
-        const cpx<R> gxy = sxy * gz[3], gxz = (sx * sz) * gz[4], gyz = (sy * sz) * gz[5];
-        const cpx<R> u0 = u[zp * Py], u1 = u[(nz + zp) * Py], u2 = u[(2 * nz + zp) * Py];
-        a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
-        a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
-        a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
+    const int kxo = kx <= Px - kx ? kx : Px - kx;
+    const R sx = kx > Px - kx ? R(-1) : R(1);
+    const cpx<R> *u = yb + (rhs * Px + kx) * rows * (long long)Py + ky0;
+    cpx<R> *o = yc + (rhs * Px + kx) * rows * (long long)Py + ky0;
+    for (int e = threadIdx.x; e < rows * KB; e += blockDim.x) {
+        const int r = e / KB, j = e - r * KB;
+        us[e] = j < kb ? u[(long long)r * Py + j] : czero<R>();
     }
-    o[z * Py] = a0;
-    o[(nz + z) * Py] = a1;
-    o[(2 * nz + z) * Py] = a2;
+    for (int e = threadIdx.x; e < KB * 6 * nz; e += blockDim.x) {
+        const int j = e / (6 * nz), q = e - j * 6 * nz;
+        const int ky = ky0 + j, kyo = ky <= Py - ky ? ky : Py - ky;
+        gs[j * gst + q] = j < kb ? khat[((long long)kxo * Hy + kyo) * nz * 6 + q] : czero<R>();
+    }
+    __syncthreads();
+    const int j = threadIdx.x / nz, z = threadIdx.x - j * nz;
+    cpx<R> a0 = czero<R>(), a1 = czero<R>(), a2 = czero<R>();
+    if (j < kb) {
+        const int ky = ky0 + j;
+        const R sy = ky > Py - ky ? R(-1) : R(1), sxy = sx * sy;
+        const cpx<R> *g = gs + j * gst;
+        for (int zp = 0; zp < nz; ++zp) {
+            const int dz = z - zp;
+            const R sz = dz < 0 ? R(-1) : R(1);
+            const cpx<R> *gz = g + (dz < 0 ? -dz : dz) * 6;
+            const cpx<R> gxx = gz[0], gyy = gz[1], gzz = gz[2];
+            const cpx<R> gxy = sxy * gz[3], gxz = (sx * sz) * gz[4], gyz = (sy * sz) * gz[5];
+            const cpx<R> u0 = us[zp * KB + j], u1 = us[(nz + zp) * KB + j], u2 = us[(2 * nz + zp) * KB + j];
+            a0 = a0 + gxx * u0 + gxy * u1 + gxz * u2;
+            a1 = a1 + gxy * u0 + gyy * u1 + gyz * u2;
+            a2 = a2 + gxz * u0 + gyz * u1 + gzz * u2;
+        }
+    }
+    __syncthreads();  // every thread is done with the staged y-spectra
+    if (j < kb) {
+        us[z * KB + j] = a0;
+        us[(nz + z) * KB + j] = a1;
+        us[(2 * nz + z) * KB + j] = a2;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * KB; e += blockDim.x) {
+        const int r = e / KB, jj = e - r * KB;
+        if (jj < kb) o[(long long)r * Py + jj] = us[e];
+    }
 }
 
 // (c) inverse y-FFT of `lg` coupled rows per workgroup, cropped back into the x-spectra.
@@ -507,8 +532,10 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
         vie_lds_attr((const void *)k_ysplit_fwd<R>, ldsy);
         hipLaunchKernelGGL(k_ysplit_fwd<R>, dim3(gx, nrhs), dim3(256), ldsy, s, (const cpx<R> *)work, y1, ny, nz, Px,
                            lg, op->py);
-        const long long pts = (long long)Px * nz * Py;
-        hipLaunchKernelGGL(k_ysplit_couple<R>, dim3((unsigned)((pts + 255) / 256), nrhs), dim3(256), 0, s,
+        const int kb = 256 / nz;
+        const size_t ldsc = sizeof(cpx<R>) * ((size_t)3 * nz * kb + (size_t)kb * (6 * nz + 1));
+        vie_lds_attr((const void *)k_ysplit_couple<R>, ldsc);
+        hipLaunchKernelGGL(k_ysplit_couple<R>, dim3((unsigned)(Px * ((Py + kb - 1) / kb)), nrhs), dim3(256), ldsc, s,
                            (const cpx<R> *)y1, y2, khat, nz, Px, Py, op->Hy);
         vie_lds_attr((const void *)k_ysplit_inv<R>, ldsy);
         hipLaunchKernelGGL(k_ysplit_inv<R>, dim3(gx, nrhs), dim3(256), ldsy, s, work, (const cpx<R> *)y2, ny, nz, Px,
