@@ -66,7 +66,8 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
     + the permutation (HBM bytes); from 8 right-hand sides on the solves run on the matrix
     cores and the bound is their FP32 (FP64) rate: 8 m^2 real flops per (mode, rhs) column
     (L and U halves), three times that with one refinement step (two solves + the residual
-    product).  matvec: x in, y out and M per right-hand side, plus the octant transform once."""
+    product).  matvec: x in, y out and M per right-hand side, plus the octant transform once;
+    its plane pass alone: the x-spectra of the cross-section rows in and out, and the transform."""
     nx, ny, nz = cfg['grid']
     N = nx * ny * nz
     v = 16 if mode == 'fp64' else 8      # vector bytes per complex
@@ -81,6 +82,11 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
     else:
         bs = ('hbm', stored * m * m * f + R * modes * (2 * m * v + 4 * m), 'bytes')
     models = {'block_solve': bs, 'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes')}
+    # plane pass of one product: the 3 ny nz rows of every x-frequency's spectra read and
+    # written once, and the kernel transform ((x, y) octant with nz real offsets when nz <= 16)
+    Px = good_length(2 * nx - 1)
+    kplane = 6 * Hx * Hy * nz * v if nz <= 16 else khat
+    models['matvec_plane'] = ('hbm', R * 2 * 3 * ny * nz * Px * v + kplane, 'bytes')
     if iters:
         # CGS2 per Arnoldi step j (index within its cycle): each of the two dot passes reads the
         # j+1 basis vectors and w once; each update pass also writes w.  Average per launch.
