@@ -164,6 +164,44 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
     }
 }
 
+// Blocks of one tile (m <= 64, e.g. the 3 nz blocks of the 2-level preconditioner): one
+// wavefront per (mode, right-hand side), lane i owning row i.  With the single diagonal tile
+// holding strict(L^{-1}) below and U^{-1} on and above the diagonal,
+//   y_i = (P r)_i + sum_{c < i} L^{-1}_{ic} (P r)_c,    x_i = sum_{c >= i} U^{-1}_{ic} y_c,
+// each factor entry is read once (columns coalesced across the lanes), the vector goes through
+// the wavefront's LDS row.  The sums of the per-mode kernel, accumulated in column order.
+template <class R, class FT>
+__global__ void __launch_bounds__(256) k_block_solve_tiny(cpx<R> *work, const FT *F, const int *perm,
+                                                          const int *block_of_mode, const int *modes, int m, int n,
+                                                          int nboxes, int nrhs, int nitems) {
+    __shared__ cpx<R> vs[4][TS];
+    const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wv;
+    if (item >= nitems) return;  // whole wavefront; no workgroup barrier below
+    const int mi = item / nrhs, rhs = item - mi * nrhs;
+    const int bm = modes[mi];
+    const int k = bm % n, box = bm / n;
+    const int sblk = block_of_mode[bm];
+    const FT *A = F + (long long)sblk * m * m;
+    const int *pm = perm + (long long)sblk * m;
+    cpx<R> *base = work + ((long long)rhs * nboxes + box) * m * n + k;
+    cpx<R> *v = vs[wv];
+    const bool row = i < m;
+    const cpx<R> r0 = row ? base[(long long)pm[i] * n] : czero<R>();
+    v[i] = r0;
+    __builtin_amdgcn_wave_barrier();
+    cpx<R> y = r0;
+    for (int c = 0; c < m; ++c)
+        if (c < i && row) y = y + ldf(A + (long long)c * m + i) * v[c];
+    __builtin_amdgcn_wave_barrier();
+    v[i] = y;
+    __builtin_amdgcn_wave_barrier();
+    cpx<R> x = czero<R>();
+    for (int c = 0; c < m; ++c)
+        if (c >= i && row) x = x + ldf(A + (long long)c * m + i) * v[c];
+    if (row) base[(long long)i * n] = x;
+}
+
 #define VIE_MAX_QR 5
 // Columns per chunk: a power of two <= 8, bounded by the register budget of the accumulators.
 static int block_solve_rc(int m, int nrhs, size_t esz) {
@@ -910,7 +948,14 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
 #undef WIDE_CASES
         VIE_HIP(hipGetLastError());
     }
-    if (pc->n_narrow > 0) {
+    if (pc->n_narrow > 0 && m <= TS) {
+        const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
+        const int nitems = pc->n_narrow * nrhs;
+        hipLaunchKernelGGL((k_block_solve_tiny<R, FT>), dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, work,
+                           pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->block_of_mode.as<const int>(),
+                           modes, m, n, pc->nboxes, nrhs, nitems);
+        VIE_HIP(hipGetLastError());
+    } else if (pc->n_narrow > 0) {
         const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(m, nrhs, sizeof(cpx<R>));
         dim3 grid((unsigned)pc->n_narrow, (unsigned)((nrhs + rc - 1) / rc));
         size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
