@@ -384,9 +384,12 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
             const bool two = g[3] == 2;
             const uint64_t m = two ? 3 * bz : 3 * by * bz, modes = two ? nb * bx * by : nb * bx;
             const uint64_t table = bx * 6 * (2 * by - 1) * (2 * bz - 1) + (two ? bx * by * 6 * (2 * bz - 1) : 0);
-            uint64_t pcb = modes * m * m * fesz + modes * m * 8 + modes * 16;  // factors, pivots, maps
-            if (o.factor_prec == VIE_BF16C) pcb += modes * m * m * 8;        // complex-float factorisation copy
-            pcb += table * 16 + modes * m * 4 + modes * 64 * 64 * vesz;       // Chan table, LU workspace
+            // stored blocks: every mode, or with the reflection pairing the modes 0..bx/2
+            const bool mirror = !two && !o.no_mirror && !o.reduce && !(o.share_tol > 0);
+            const uint64_t stored = mirror ? nb * (bx / 2 + 1) : modes;
+            uint64_t pcb = stored * m * m * fesz + stored * m * 8 + modes * 16;  // factors, pivots, maps
+            if (o.factor_prec == VIE_BF16C) pcb += stored * m * m * 8;         // complex-float factorisation copy
+            pcb += table * 16 + stored * m * 4 + stored * 64 * 64 * vesz;       // Chan table, LU workspace
             if (o.refine_steps || !o.keep_zero_rows) pcb += table * 8 + nb * by * bz * 8;
             if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pcb += table * 16 + nb * by * bz * 16;
             pcb += 3 * by * bz * 4 + 64;  // row orders, coupling flag

@@ -28,29 +28,46 @@
 // quarter of its columns), and every thread then applies the tile's column panel to its
 // remaining rows.  Each factor entry is read once per chunk and used RC times; the factor
 // reads are coalesced along columns.
+// Work item = (stored block s, first column c0, column count, box), column g of block s being the
+// pair (mode mode_list[mode_ptr[s] + g / nrhs], right-hand side g % nrhs): the two modes k and
+// n - k of a reflected pair share a workgroup and each factor read.  A reflected column (flag
+// VIE_MODE_MIRROR) is solved as S D_k^{-1} S: its x-component rows (the first mx block rows)
+// change sign on the way in and out.
 template <class R, int QR, int RC, class FT>
-__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, const int *perm,
-                                                     const int *block_of_mode, const int *modes, int m, int n,
-                                                     int nboxes, int nrhs) {
+__global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, const int *perm, const int4 *items,
+                                                     const int *mode_ptr, const int *mode_list, int m, int n,
+                                                     int nboxes, int nrhs, int mx) {
     cpx<R> *yt = reinterpret_cast<cpx<R> *>(vie_smem);  // [TS][RC]
     cpx<R> *part = yt + TS * RC;                        // [4][TS][RC]
-    const int bm = modes[blockIdx.x];
-    const int k = bm % n, box = bm / n;
-    const int r0 = blockIdx.y * RC;
-    const int nr = min(RC, nrhs - r0);
-    const int sblk = block_of_mode[bm];
+    const int4 item = items[blockIdx.x];
+    const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
     const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     const long long rstride = (long long)nboxes * m * n;
-    cpx<R> *base = work + (long long)box * m * n + k;
+    long long off[RC];
+    bool fl[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+        off[c] = -1;
+        fl[c] = false;
+        if (c < ncols) {
+            const int g = c0 + c, me = mode_list[mode_ptr[sblk] + g / nrhs];
+            off[c] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
+            fl[c] = (me & VIE_MODE_MIRROR) != 0;
+        }
+    }
     const int tid = threadIdx.x;
     cpx<R> acc[QR][RC];
 #pragma unroll
     for (int q = 0; q < QR; ++q) {
         int i = tid + 256 * q;
+        const int src = i < m ? pm[i] : 0;
 #pragma unroll
-        for (int c = 0; c < RC; ++c)
-            acc[q][c] = (i < m && c < nr) ? base[(r0 + c) * rstride + (long long)pm[i] * n] : czero<R>();
+        for (int c = 0; c < RC; ++c) {
+            cpx<R> v = (i < m && off[c] >= 0) ? work[off[c] + (long long)src * n] : czero<R>();
+            if (fl[c] && src < mx) v = mk(-v.re, -v.im);
+            acc[q][c] = v;
+        }
     }
     const int g = tid >> 6, r = tid & 63;
     // forward: unit lower L (diagonal tiles hold the strictly lower part of their inverse)
@@ -160,7 +177,10 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
         if (i < m)
 #pragma unroll
             for (int c = 0; c < RC; ++c)
-                if (c < nr) base[(r0 + c) * rstride + (long long)i * n] = acc[q][c];
+                if (off[c] >= 0) {
+                    const cpx<R> v = acc[q][c];
+                    work[off[c] + (long long)i * n] = (fl[c] && i < mx) ? mk(-v.re, -v.im) : v;
+                }
     }
 }
 
@@ -173,7 +193,7 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
 template <class R, class FT>
 __global__ void __launch_bounds__(256) k_block_solve_tiny(cpx<R> *work, const FT *F, const int *perm,
                                                           const int *block_of_mode, const int *modes, int m, int n,
-                                                          int nboxes, int nrhs, int nitems) {
+                                                          int nboxes, int nrhs, int nitems, int mx) {
     __shared__ cpx<R> vs[4][TS];
     const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
     const int item = blockIdx.x * 4 + wv;
@@ -181,13 +201,16 @@ __global__ void __launch_bounds__(256) k_block_solve_tiny(cpx<R> *work, const FT
     const int mi = item / nrhs, rhs = item - mi * nrhs;
     const int bm = modes[mi];
     const int k = bm % n, box = bm / n;
-    const int sblk = block_of_mode[bm];
+    const int sraw = block_of_mode[bm], sblk = sraw & ~VIE_MODE_MIRROR;
+    const bool fl = (sraw & VIE_MODE_MIRROR) != 0;  // reflected mode: S D_k^{-1} S
     const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     cpx<R> *base = work + ((long long)rhs * nboxes + box) * m * n + k;
     cpx<R> *v = vs[wv];
     const bool row = i < m;
-    const cpx<R> r0 = row ? base[(long long)pm[i] * n] : czero<R>();
+    const int src = row ? pm[i] : 0;
+    cpx<R> r0 = row ? base[(long long)src * n] : czero<R>();
+    if (fl && src < mx) r0 = mk(-r0.re, -r0.im);
     v[i] = r0;
     __builtin_amdgcn_wave_barrier();
     cpx<R> y = r0;
@@ -199,34 +222,48 @@ __global__ void __launch_bounds__(256) k_block_solve_tiny(cpx<R> *work, const FT
     cpx<R> x = czero<R>();
     for (int c = 0; c < m; ++c)
         if (c >= i && row) x = x + ldf(A + (long long)c * m + i) * v[c];
-    if (row) base[(long long)i * n] = x;
+    if (row) base[(long long)i * n] = (fl && i < mx) ? mk(-x.re, -x.im) : x;
 }
 
 #define VIE_MAX_QR 5
-// Columns per chunk: a power of two <= 8, bounded by the register budget of the accumulators.
-static int block_solve_rc(int m, int nrhs, size_t esz) {
+// Columns per chunk: a power of two <= 8, at most the columns of a block (`cols`: right-hand
+// sides times the modes sharing it), bounded by the register budget of the accumulators.
+static int block_solve_rc(int m, int cols, size_t esz) {
     int qr = (m + 255) / 256;
     int budget = esz == sizeof(c128) ? 24 : 48;  // complex accumulators per thread
     int rc = 1;
-    while (rc < 8 && rc < nrhs && qr * rc * 2 <= budget) rc *= 2;
+    while (rc < 8 && rc < cols && qr * rc * 2 <= budget) rc *= 2;
     return rc;
 }
 
+// Most columns one stored block has for `nrhs` right-hand sides.
+static int block_cols_max(vie_pc pc, int nrhs) {
+    int c = 1;
+    for (int sb = 0; sb < pc->nstored; ++sb) c = std::max(c, (pc->mode_ptr[sb + 1] - pc->mode_ptr[sb]) * nrhs);
+    return c;
+}
+
+struct NarrowArgs {
+    const int4 *items;
+    const int *mode_ptr, *mode_list;
+    int m, n, nboxes, nrhs, mx;
+};
+
 template <class R, int QR, int RC, class FT>
 static void launch_bs(dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const FT *F, const int *perm,
-                      const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
-    hipLaunchKernelGGL((k_block_solve<R, QR, RC, FT>), grid, dim3(256), lds, s, work, F, perm, bom, modes, m, n,
-                       nboxes, nrhs);
+                      const NarrowArgs &a) {
+    hipLaunchKernelGGL((k_block_solve<R, QR, RC, FT>), grid, dim3(256), lds, s, work, F, perm, a.items, a.mode_ptr,
+                       a.mode_list, a.m, a.n, a.nboxes, a.nrhs, a.mx);
 }
 
 template <class R, int QR, class FT>
 static void launch_bs_rc(int rc, dim3 grid, size_t lds, hipStream_t s, cpx<R> *work, const FT *F,
-                         const int *perm, const int *bom, const int *modes, int m, int n, int nboxes, int nrhs) {
+                         const int *perm, const NarrowArgs &a) {
     switch (rc) {
-        case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
-        case 2: launch_bs<R, QR, 2>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
-        case 4: launch_bs<R, QR, 4>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
-        default: launch_bs<R, QR, 8>(grid, lds, s, work, F, perm, bom, modes, m, n, nboxes, nrhs); break;
+        case 1: launch_bs<R, QR, 1>(grid, lds, s, work, F, perm, a); break;
+        case 2: launch_bs<R, QR, 2>(grid, lds, s, work, F, perm, a); break;
+        case 4: launch_bs<R, QR, 4>(grid, lds, s, work, F, perm, a); break;
+        default: launch_bs<R, QR, 8>(grid, lds, s, work, F, perm, a); break;
     }
 }
 
@@ -491,7 +528,7 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                                                                const int4 *items, int nitems, const int *mode_ptr,
                                                                const int *mode_list, cpx<R> *Y, int m, int n,
                                                                int nboxes, int nrhs, int out_mode,
-                                                               const cpx<R> *Yadd, uint32_t *Yb, int mp) {
+                                                               const cpx<R> *Yadd, uint32_t *Yb, int mp, int mx) {
     typedef typename Mfma<R>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int ST = 16 * NW;  // rows per super-tile
@@ -523,14 +560,17 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     const int sub = wv >> 2;             // tile of this wavefront within the super-tile
     const int wrow = 16 * (wv & 3);      // first row of this wavefront within its tile
     long long off[CT];                   // column base offsets in work (-1: no column)
+    bool fl[CT];                         // reflected mode: x-component rows change sign in and out
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
         off[ct] = -1;
+        fl[ct] = false;
         if (col < ncols) {
             const int g = c0 + col;
-            const int mode = mode_list[mode_ptr[sblk] + g / nrhs];
-            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode;
+            const int me = mode_list[mode_ptr[sblk] + g / nrhs];
+            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
+            fl[ct] = (me & VIE_MODE_MIRROR) != 0;
         }
     }
     const int NS = (m + ST - 1) / ST;
@@ -593,8 +633,10 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                             Yh[bo] = hr | (hi_ << 16);
                             Yl[bo] = bf16_bits(lr) | (bf16_bits(li) << 16);
                         }
-                        if (!lower && off[ct] >= 0 && out_mode != 1)
-                            work[off[ct] + (long long)(t0 + row) * n] = out_mode == 2 ? x + Ya[yo] : x;
+                        if (!lower && off[ct] >= 0 && out_mode != 1) {
+                            const cpx<R> o = out_mode == 2 ? x + Ya[yo] : x;
+                            work[off[ct] + (long long)(t0 + row) * n] = (fl[ct] && t0 + row < mx) ? mk(-o.re, -o.im) : o;
+                        }
                     }
                 }
         }
@@ -620,7 +662,9 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
-                cpx<R> b = (row < m && off[ct] >= 0) ? work[off[ct] + (long long)pm[row] * n] : czero<R>();
+                const int src = row < m ? pm[row] : 0;
+                cpx<R> b = (row < m && off[ct] >= 0) ? work[off[ct] + (long long)src * n] : czero<R>();
+                if (fl[ct] && src < mx) b = mk(-b.re, -b.im);
                 cr[ct][v] = b.re;
                 ci[ct][v] = b.im;
             }
@@ -691,7 +735,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                                                               const int *smode, const int4 *items, int nitems,
                                                               const int *mode_ptr, const int *mode_list,
                                                               const c64 *Y, const int *rows, int m, int n,
-                                                              int nboxes, int nrhs, int by, int bz) {
+                                                              int nboxes, int nrhs, int by, int bz, int mx) {
     typedef Mfma<float>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int NTH = NW * 64;
@@ -718,13 +762,17 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     long long off[CT];
+    bool fl[CT];  // reflected mode: the residual of S D_k S, i.e. the x rows of r - D_k z0 change sign
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
         off[ct] = -1;
+        fl[ct] = false;
         if (col < ncols) {
             const int g = c0 + col;
-            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + mode_list[mode_ptr[sblk] + g / nrhs];
+            const int me = mode_list[mode_ptr[sblk] + g / nrhs];
+            off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
+            fl[ct] = (me & VIE_MODE_MIRROR) != 0;
         }
     }
     const int nch = (m + YC - 1) / YC;
@@ -800,7 +848,8 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                         const c64 mv = mt[(long long)box * plane + ryz];
                         const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
                         const long long wo = off[ct] + (long long)row * n;
-                        work[wo] = work[wo] - z0 + mv * mk(cr[ct][v], ci[ct][v]);
+                        const c64 t = mv * mk(cr[ct][v], ci[ct][v]);
+                        work[wo] = (fl[ct] && row < mx) ? work[wo] + z0 - t : work[wo] - z0 + t;
                     }
                 }
         }
@@ -821,7 +870,10 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     const bool all_wide = pc->prec == VIE_BF16C;
     const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : pc->cfg_min_rhs;
     std::vector<int> wide;    // int4 items
-    std::vector<int> narrow;  // box * n + mode
+    std::vector<int> narrow;  // int4 items of narrow_rc columns, or box * n + mode (tiny blocks)
+    const bool tiny = pc->m <= TS;
+    const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(pc->m, block_cols_max(pc, nrhs),
+                                                            pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64));
     int maxc = 0;
     long long wide_cols = 0;
     for (int sb = 0; sb < pc->nstored; ++sb) {
@@ -844,13 +896,17 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
                 wide.insert(wide.end(), {sb, (int)c, nc, pc->block_box[sb]});
                 maxc = std::max(maxc, nc);
             }
-        } else {
+        } else if (tiny) {
             for (int e = pc->mode_ptr[sb]; e < pc->mode_ptr[sb + 1]; ++e)
-                narrow.push_back(pc->block_box[sb] * n + pc->mode_list[e]);
+                narrow.push_back(pc->block_box[sb] * n + (pc->mode_list[e] & ~VIE_MODE_MIRROR));
+        } else {
+            for (long long c = 0; c < cols; c += rc)
+                narrow.insert(narrow.end(), {sb, (int)c, (int)std::min<long long>(rc, cols - c), pc->block_box[sb]});
         }
     }
     pc->n_wide = (int)(wide.size() / 4);
-    pc->n_narrow = (int)narrow.size();
+    pc->n_narrow = (int)(tiny ? narrow.size() : narrow.size() / 4);
+    pc->narrow_rc = rc;
     pc->wide_ct = maxc <= 16 ? 1 : maxc <= 32 ? 2 : 4;
     std::vector<int> tab(wide);
     tab.insert(tab.end(), narrow.begin(), narrow.end());
@@ -874,7 +930,7 @@ static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out
     hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
                        mp, mp + pc->nstored + 1, Y, pc->m, pc->nm, pc->nboxes, nrhs, out_mode, Yadd,
-                       pc->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16);
+                       pc->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16, pc->mirror_rows);
 }
 
 // wavefronts per workgroup (16 NW rows per super-tile): 8 or 16 for FP32, 4 or 8 for FP64
@@ -908,7 +964,7 @@ static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStr
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
                        pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y,
-                       pc->rows.as<const int>(), pc->m, pc->nm, pc->nboxes, nrhs, pc->by, pc->bz);
+                       pc->rows.as<const int>(), pc->m, pc->nm, pc->nboxes, nrhs, pc->by, pc->bz, pc->mirror_rows);
 }
 
 template <class R, class FT>
@@ -953,21 +1009,23 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
         const int nitems = pc->n_narrow * nrhs;
         hipLaunchKernelGGL((k_block_solve_tiny<R, FT>), dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, work,
                            pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->block_of_mode.as<const int>(),
-                           modes, m, n, pc->nboxes, nrhs, nitems);
+                           modes, m, n, pc->nboxes, nrhs, nitems, pc->mirror_rows);
         VIE_HIP(hipGetLastError());
     } else if (pc->n_narrow > 0) {
-        const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(m, nrhs, sizeof(cpx<R>));
-        dim3 grid((unsigned)pc->n_narrow, (unsigned)((nrhs + rc - 1) / rc));
+        const int rc = pc->narrow_rc;
+        dim3 grid((unsigned)pc->n_narrow);
         size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
-        const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
+        const int *mp = pc->modes_dev.as<const int>();
+        const NarrowArgs a{reinterpret_cast<const int4 *>(pc->sched.as<const int>() + 4 * pc->n_wide), mp,
+                           mp + pc->nstored + 1, m, n, pc->nboxes, nrhs, pc->mirror_rows};
         const FT *F = pc->factors.as<const FT>();
-        const int *perm = pc->perm.as<const int>(), *bom = pc->block_of_mode.as<const int>();
+        const int *perm = pc->perm.as<const int>();
         switch (qr) {
-            case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
-            case 2: launch_bs_rc<R, 2>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
-            case 3: launch_bs_rc<R, 3>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
-            case 4: launch_bs_rc<R, 4>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
-            default: launch_bs_rc<R, 5>(rc, grid, lds, s, work, F, perm, bom, modes, m, n, pc->nboxes, nrhs); break;
+            case 1: launch_bs_rc<R, 1>(rc, grid, lds, s, work, F, perm, a); break;
+            case 2: launch_bs_rc<R, 2>(rc, grid, lds, s, work, F, perm, a); break;
+            case 3: launch_bs_rc<R, 3>(rc, grid, lds, s, work, F, perm, a); break;
+            case 4: launch_bs_rc<R, 4>(rc, grid, lds, s, work, F, perm, a); break;
+            default: launch_bs_rc<R, 5>(rc, grid, lds, s, work, F, perm, a); break;
         }
         VIE_HIP(hipGetLastError());
     }
@@ -991,7 +1049,7 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
         std::vector<int> choice;
         if (!tune_lookup(key, &choice)) {
             std::vector<std::vector<int>> cands;  // {gmax, nw, rc, min_rhs}
-            const int rcmax = block_solve_rc(pc->m, nrhs, sizeof(cpx<R>));
+            const int rcmax = block_solve_rc(pc->m, block_cols_max(pc, nrhs), sizeof(cpx<R>));
             const int nws[2] = {fp32 ? 8 : 4, fp32 ? 16 : 8};
             if (bf || nrhs >= WIDE_MIN_RHS)
                 for (int g = 16; g <= WIDE_MAX_COLS; g *= 2)

@@ -1577,17 +1577,26 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             }
         }
     }
+    // reflection along x: C^_{n-k} = S C^_k S (the parities of the Chan sequences, exact before
+    // the x-DFT), so D_{n-k} = S D_k S and modes k > n/2 take the factors of mode n - k
+    const bool mirror = pc->levels == 1 && !o->no_mirror && !o->reduce && !(o->share_tol > 0);
+    pc->mirror_rows = m / 3;
+    std::vector<char> mir(nm, 0);
+    if (mirror)
+        for (int k = 1; k < nm; ++k) mir[k] = nm - k < k;
     // block map: stored blocks ordered (box, mode)
     pc->block_of_mode_host.assign((size_t)nbx * nm, -1);
     std::vector<int> smode, sbox;
     for (int b = 0; b < nbx; ++b) {
         int *bom = &pc->block_of_mode_host[(size_t)b * nm];
         for (int k = 0; k < nm; ++k)
-            if (keep[k] && rep[k] == k) {  // a stored block
+            if (keep[k] && rep[k] == k && !mir[k]) {  // a stored block
                 bom[k] = (int)smode.size();
                 smode.push_back(k);
                 sbox.push_back(b);
             }
+        for (int k = 0; k < nm; ++k)
+            if (mir[k]) bom[k] = bom[nm - k] | VIE_MODE_MIRROR;
         for (int k = 0; k < nm; ++k)
             if (keep[k] && rep[k] != k) bom[k] = bom[rep[k]];  // shares its run's block
         const int cs = levels_one_centre(keep, centre) ? bom[centre] : -1;
@@ -1600,13 +1609,16 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     pc->mode_list.clear();
     pc->block_box = sbox;
     for (int b = 0; b < nbx; ++b)
-        for (int k = 0; k < nm; ++k) pc->mode_ptr[pc->block_of_mode_host[(size_t)b * nm + k] + 1]++;
+        for (int k = 0; k < nm; ++k) pc->mode_ptr[(pc->block_of_mode_host[(size_t)b * nm + k] & ~VIE_MODE_MIRROR) + 1]++;
     for (int sb = 0; sb < pc->nstored; ++sb) pc->mode_ptr[sb + 1] += pc->mode_ptr[sb];
     pc->mode_list.assign(pc->mode_ptr[pc->nstored], 0);
     {
         std::vector<int> fill(pc->mode_ptr.begin(), pc->mode_ptr.end() - 1);
         for (int b = 0; b < nbx; ++b)
-            for (int k = 0; k < nm; ++k) pc->mode_list[fill[pc->block_of_mode_host[(size_t)b * nm + k]]++] = k;
+            for (int k = 0; k < nm; ++k) {
+                const int e = pc->block_of_mode_host[(size_t)b * nm + k];
+                pc->mode_list[fill[e & ~VIE_MODE_MIRROR]++] = k | (e & VIE_MODE_MIRROR);
+            }
     }
     pc->sched_nrhs = 0;
     VIE_CHECK(pc->modes_dev.ensure(sizeof(int) * (pc->mode_ptr.size() + pc->mode_list.size())));

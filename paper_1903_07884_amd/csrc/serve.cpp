@@ -500,9 +500,9 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
         uint64_t hb = fnv1a(r->boxes.data(), sizeof(int32_t) * r->boxes.size());
         hb = fnv1a(r->box_levels.data(), sizeof(int32_t) * r->box_levels.size(), hb);
         hb = fnv1a(r->box_homog.data(), sizeof(int32_t) * r->box_homog.size(), hb);
-        snprintf(buf, sizeof buf, "|pc %d %d %016llx %d %a %d %d %d %d %d %a", p.homog, p.nboxes,
+        snprintf(buf, sizeof buf, "|pc %d %d %016llx %d %a %d %d %d %d %d %a %d", p.homog, p.nboxes,
                  (unsigned long long)hb, p.reduce, p.reduce ? p.reduce_tol : 0.0, p.factor_prec, p.proxy,
-                 p.refine_steps, p.keep_zero_rows, p.levels, p.share_tol);
+                 p.refine_steps, p.keep_zero_rows, p.levels, p.share_tol, p.no_mirror);
         r->key += buf;
     }
     snprintf(buf, sizeof buf, "|so %a %d %d %d", r->so.tol, r->so.restart, r->so.maxit, r->so.mode);

@@ -195,6 +195,11 @@ struct vie_op_s {
     FftPlan px, py, pz;      // plans for the three periods
 };
 
+// Flag on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is the
+// reflection n - k of the block's own mode k, solved as S D_k^{-1} S (S: sign -1 on the x-component
+// rows).
+#define VIE_MODE_MIRROR (1 << 30)
+
 struct vie_pc_s {
     vie_op op = nullptr;
     int nboxes = 0, bx = 0, by = 0, bz = 0;
@@ -213,7 +218,7 @@ struct vie_pc_s {
     int prec = 0;            // factor precision
     int nstored = 0;
     std::vector<int> block_of_mode_host;  // [nboxes*bx]
-    DevBuf block_of_mode;    // int32 [nboxes*bx] -> stored block index
+    DevBuf block_of_mode;    // int32 [nboxes*bx] -> stored block index (| VIE_MODE_MIRROR)
     DevBuf factors;          // [nstored][m][m] column-major LU (complex, factor precision)
     DevBuf perm;             // int32 [nstored][m] row permutation: (P r)[i] = r[perm[i]]
     DevBuf info;             // int32 [nstored] 0 or first zero-pivot column + 1
@@ -232,12 +237,14 @@ struct vie_pc_s {
     FftPlan pyb2;            // length by (the y-DFT of the 2-level circulant)
     FftPlan pxb;             // length bx
     // block-solve schedule
-    std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending)
+    std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending, | VIE_MODE_MIRROR)
+    int mirror_rows = 0;                   // leading block rows that are x components (m/3, 1-level)
     std::vector<int> block_box;            // box of stored block s
     DevBuf modes_dev;                      // int32 mode_ptr [nstored+1] then mode_list
     int sched_nrhs = 0;                    // nrhs the tables below were built for
-    int n_wide = 0, n_narrow = 0, wide_ct = 1;
-    DevBuf sched;                          // int4 wide items [n_wide] then int32 box*bx+mode [n_narrow]
+    int n_wide = 0, n_narrow = 0, wide_ct = 1, narrow_rc = 1;
+    DevBuf sched;                          // int4 wide items [n_wide], then the narrow work: int4 items
+                                           // of narrow_rc columns, or (m <= 64) int32 box*bx+mode
     DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
     DevBuf wide_scratch2;                  // second solve of a refined apply
     DevBuf wide_bf16;                      // bfloat16 hi + lo split of the solved rows (BF16 factors)
@@ -250,7 +257,7 @@ struct vie_pc_s {
     // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)
     int cfg_gmax = 0;        // widest column group of the wide solve (0: widest giving >= 512 groups)
     int cfg_nw = 0;          // wavefronts per wide workgroup (0: 16 for FP32, 8 for FP64)
-    int cfg_rc = 0;          // right-hand sides per narrow workgroup (0: register-budget rule)
+    int cfg_rc = 0;          // columns per narrow workgroup (0: register-budget rule)
     int cfg_min_rhs = 8;     // blocks go wide from this many right-hand sides on
     int tuned_nrhs = -1;
 };

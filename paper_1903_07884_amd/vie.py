@@ -43,7 +43,7 @@ class PcOpts(ctypes.Structure):
                 ('reduce', ctypes.c_int32), ('reduce_tol', ctypes.c_double), ('factor_prec', ctypes.c_int32),
                 ('proxy', ctypes.c_int32), ('refine_steps', ctypes.c_int32), ('keep_zero_rows', ctypes.c_int32),
                 ('levels', ctypes.c_int32), ('box_levels', ctypes.c_void_p), ('box_homog', ctypes.c_void_p),
-                ('share_tol', ctypes.c_double)]
+                ('share_tol', ctypes.c_double), ('no_mirror', ctypes.c_int32)]
 
 
 class PcInfo(ctypes.Structure):
@@ -219,7 +219,7 @@ class Preconditioner:
     """vie_pc: blocked Chan-Olkin circulant preconditioner (see include/vie.h)."""
 
     def __init__(self, op, homog='none', boxes=None, reduce_tol=None, factor_prec=VIE_C128, proxy='product',
-                 refine=None, keep_zero_rows=False, levels=1, share_tol=0.0, stream=None):
+                 refine=None, keep_zero_rows=False, levels=1, share_tol=0.0, mirror=True, stream=None):
         """``factor_prec``: VIE_C128 (FP64 solves), VIE_C64 or VIE_BF16C (mixed-precision
         solves, complex64 vectors); ``proxy``: 'product' or 'centre' reading of the
         memory-reduction proxy column; ``refine``: refinement steps of the bfloat16 block
@@ -227,7 +227,9 @@ class Preconditioner:
         one entry per box; ``share_tol``: runs of kept modes with close proxy values share one
         block (0 = off); ``keep_zero_rows``: factorise the full
         cross-section even where the homogenised contrast is zero; ``levels``: 1 or 2 (the
-        2-level circulant, one 3*bz block per (x-mode, y-mode) pair)."""
+        2-level circulant, one 3*bz block per (x-mode, y-mode) pair); ``mirror``: solve the modes
+        k > n/2 with the factors of mode n - k through the reflection symmetry along x (1-level,
+        no memory reduction or sharing; False factorises every mode)."""
         lib = load()
         self.op = op
         bx = None
@@ -243,6 +245,7 @@ class Preconditioner:
             o.nboxes = bx.shape[0]
             o.boxes = bx.ctypes.data
         o.share_tol = float(share_tol)
+        o.no_mirror = 0 if mirror else 1
         self._keep = []
         if per_box_h:
             hb = np.ascontiguousarray([HOMOG[h] for h in homog], dtype=np.int32)

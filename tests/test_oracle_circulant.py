@@ -16,6 +16,9 @@
 * 2-level circulant (Sec. 4): equals the block-circulant-circulant matrix built elementwise
   from T. Chan's weights in x and y (no DFT, no blocks) and inverted densely; with one y
   layer it is the 1-level preconditioner; zero contrast gives the identity.
+* Reflection along x: the xy and xz couplings are odd in the x offset and the others even, so
+  D_{n-k} = S D_k S with S = -1 on the x-component rows (the identity the GPU path uses to
+  solve modes k > n/2 with the factors of mode n - k), for odd and even n.
 * Cross-section rows with M~ = 0 are identity rows of every D_k (eq. Di), so the block
   solve reduces exactly to the other rows S plus the coupling M~_S C^_SC r^_C, and to the
   S x S solve alone when r^_C = 0 (the reduction the GPU path takes for cladding rows).
@@ -369,3 +372,19 @@ def test_share_runs_apply_uses_the_representative_blocks(box):
     assert np.abs(inv.apply(r) - z).max() < 1e-12 * np.abs(z).max()
     plain = C.BlockCirculantInverse(K, Mt, nx, ny, nz, share_tol=0.0)
     assert list(plain.block_of_mode) == list(range(nx))
+
+
+@pytest.mark.parametrize('grid', [(6, 3, 2), (7, 2, 3)])
+def test_reflected_modes_are_sign_conjugate(grid):
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    rng = np.random.default_rng(11)
+    Mt = 0.8 + 0.1 * rng.standard_normal((nz, ny)) + 0.05j * rng.standard_normal((nz, ny))
+    D = C.chan_olkin_blocks(K, Mt, nx, ny, nz)
+    m = 3 * ny * nz
+    S = np.diag(np.where(np.arange(m) < ny * nz, -1.0, 1.0))
+    scale = np.abs(D).max()
+    for k in range(1, nx):
+        assert np.abs(D[nx - k] - S @ D[k] @ S).max() < 1e-13 * scale, k
+    # not a tautology: the couplings that change sign are there
+    assert np.abs(D[1][:ny * nz, ny * nz:]).max() > 1e-3 * scale
