@@ -384,9 +384,10 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
             const bool two = g[3] == 2;
             const uint64_t m = two ? 3 * bz : 3 * by * bz, modes = two ? nb * bx * by : nb * bx;
             const uint64_t table = bx * 6 * (2 * by - 1) * (2 * bz - 1) + (two ? bx * by * 6 * (2 * bz - 1) : 0);
-            // stored blocks: every mode, or with the reflection pairing the modes 0..bx/2
-            const bool mirror = !two && !o.no_mirror && !o.reduce && !(o.share_tol > 0);
-            const uint64_t stored = mirror ? nb * (bx / 2 + 1) : modes;
+            // stored blocks: every mode, or with the reflection pairing the x-modes 0..bx/2
+            // (2-level: times the y-modes 0..by/2)
+            const bool mirror = !o.no_mirror && (two || (!o.reduce && !(o.share_tol > 0)));
+            const uint64_t stored = mirror ? nb * (bx / 2 + 1) * (two ? by / 2 + 1 : 1) : modes;
             uint64_t pcb = stored * m * m * fesz + stored * m * 8 + modes * 16;  // factors, pivots, maps
             if (o.factor_prec == VIE_BF16C) pcb += stored * m * m * 8;         // complex-float factorisation copy
             pcb += table * 16 + stored * m * 4 + stored * 64 * 64 * vesz;       // Chan table, LU workspace

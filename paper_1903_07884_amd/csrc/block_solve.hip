@@ -21,6 +21,12 @@
 
 #define TS 64
 
+// Sign of block row `row` in a reflected mode (flags of VIE_MODE_MIRROR, mx rows per component):
+// true where S = -1.
+__device__ __forceinline__ bool mirror_flip(int flags, int row, int mx) {
+    return ((flags & VIE_MODE_MIRROR_X) && row < mx) != ((flags & VIE_MODE_MIRROR_Y) && row >= mx && row < 2 * mx);
+}
+
 // ---------------------------------------------------------------- narrow
 // Thread t owns rows t, t + 256, ... (QR of them) and keeps their RC accumulators in
 // registers.  Forward and backward substitution run over 64-row tiles: the tile's owners
@@ -32,7 +38,7 @@
 // pair (mode mode_list[mode_ptr[s] + g / nrhs], right-hand side g % nrhs): the two modes k and
 // n - k of a reflected pair share a workgroup and each factor read.  A reflected column (flag
 // VIE_MODE_MIRROR) is solved as S D_k^{-1} S: its x-component rows (the first mx block rows)
-// change sign on the way in and out.
+// (and, for a reflected y-mode, its y-component rows) change sign on the way in and out.
 template <class R, int QR, int RC, class FT>
 __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, const int *perm, const int4 *items,
                                                      const int *mode_ptr, const int *mode_list, int m, int n,
@@ -45,15 +51,15 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
     const int *pm = perm + (long long)sblk * m;
     const long long rstride = (long long)nboxes * m * n;
     long long off[RC];
-    bool fl[RC];
+    int fl[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) {
         off[c] = -1;
-        fl[c] = false;
+        fl[c] = 0;
         if (c < ncols) {
             const int g = c0 + c, me = mode_list[mode_ptr[sblk] + g / nrhs];
             off[c] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
-            fl[c] = (me & VIE_MODE_MIRROR) != 0;
+            fl[c] = me & VIE_MODE_MIRROR;
         }
     }
     const int tid = threadIdx.x;
@@ -65,7 +71,7 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
             cpx<R> v = (i < m && off[c] >= 0) ? work[off[c] + (long long)src * n] : czero<R>();
-            if (fl[c] && src < mx) v = mk(-v.re, -v.im);
+            if (mirror_flip(fl[c], src, mx)) v = mk(-v.re, -v.im);
             acc[q][c] = v;
         }
     }
@@ -179,50 +185,58 @@ __global__ void __launch_bounds__(256) k_block_solve(cpx<R> *work, const FT *F, 
             for (int c = 0; c < RC; ++c)
                 if (off[c] >= 0) {
                     const cpx<R> v = acc[q][c];
-                    work[off[c] + (long long)i * n] = (fl[c] && i < mx) ? mk(-v.re, -v.im) : v;
+                    work[off[c] + (long long)i * n] = mirror_flip(fl[c], i, mx) ? mk(-v.re, -v.im) : v;
                 }
     }
 }
 
 // Blocks of one tile (m <= 64, e.g. the 3 nz blocks of the 2-level preconditioner): one
-// wavefront per (mode, right-hand side), lane i owning row i.  With the single diagonal tile
-// holding strict(L^{-1}) below and U^{-1} on and above the diagonal,
+// wavefront per item of up to 64/m columns of one stored block (items as in the per-block solve),
+// lane slot*m + i owning row i of column `slot`.  With the single diagonal tile holding
+// strict(L^{-1}) below and U^{-1} on and above the diagonal,
 //   y_i = (P r)_i + sum_{c < i} L^{-1}_{ic} (P r)_c,    x_i = sum_{c >= i} U^{-1}_{ic} y_c,
-// each factor entry is read once (columns coalesced across the lanes), the vector goes through
-// the wavefront's LDS row.  The sums of the per-mode kernel, accumulated in column order.
+// each factor entry is read once per wavefront (columns coalesced across the lanes, the column
+// slots reading the same addresses), the vectors go through the wavefront's LDS row.  The sums
+// of the per-block kernel, accumulated in column order.
 template <class R, class FT>
 __global__ void __launch_bounds__(256) k_block_solve_tiny(cpx<R> *work, const FT *F, const int *perm,
-                                                          const int *block_of_mode, const int *modes, int m, int n,
-                                                          int nboxes, int nrhs, int nitems, int mx) {
-    __shared__ cpx<R> vs[4][TS];
-    const int wv = threadIdx.x >> 6, i = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wv;
-    if (item >= nitems) return;  // whole wavefront; no workgroup barrier below
-    const int mi = item / nrhs, rhs = item - mi * nrhs;
-    const int bm = modes[mi];
-    const int k = bm % n, box = bm / n;
-    const int sraw = block_of_mode[bm], sblk = sraw & ~VIE_MODE_MIRROR;
-    const bool fl = (sraw & VIE_MODE_MIRROR) != 0;  // reflected mode: S D_k^{-1} S
+                                                          const int4 *items, const int *mode_ptr,
+                                                          const int *mode_list, int m, int n, int nboxes, int nrhs,
+                                                          int nitems, int mx) {
+    __shared__ cpx<R> vs[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int it = blockIdx.x * 4 + wv;
+    if (it >= nitems) return;  // whole wavefront; no workgroup barrier below
+    const int4 item = items[it];
+    const int sblk = item.x, c0 = item.y, ncols = item.z, box = item.w;
+    const int slot = lane / m, i = lane - slot * m;
+    const bool row = slot < ncols;
+    long long off = 0;
+    int fl = 0;
+    if (row) {
+        const int g = c0 + slot, me = mode_list[mode_ptr[sblk] + g / nrhs];
+        off = (long long)(g % nrhs) * nboxes * m * n + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
+        fl = me & VIE_MODE_MIRROR;
+    }
     const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
-    cpx<R> *base = work + ((long long)rhs * nboxes + box) * m * n + k;
     cpx<R> *v = vs[wv];
-    const bool row = i < m;
+    const cpx<R> *vc = v + (row ? slot * m : 0);  // this column's vector
     const int src = row ? pm[i] : 0;
-    cpx<R> r0 = row ? base[(long long)src * n] : czero<R>();
-    if (fl && src < mx) r0 = mk(-r0.re, -r0.im);
-    v[i] = r0;
+    cpx<R> r0 = row ? work[off + (long long)src * n] : czero<R>();
+    if (mirror_flip(fl, src, mx)) r0 = mk(-r0.re, -r0.im);
+    v[lane] = r0;
     __builtin_amdgcn_wave_barrier();
     cpx<R> y = r0;
     for (int c = 0; c < m; ++c)
-        if (c < i && row) y = y + ldf(A + (long long)c * m + i) * v[c];
+        if (c < i && row) y = y + ldf(A + (long long)c * m + i) * vc[c];
     __builtin_amdgcn_wave_barrier();
-    v[i] = y;
+    v[lane] = y;
     __builtin_amdgcn_wave_barrier();
     cpx<R> x = czero<R>();
     for (int c = 0; c < m; ++c)
-        if (c >= i && row) x = x + ldf(A + (long long)c * m + i) * v[c];
-    if (row) base[(long long)i * n] = (fl && i < mx) ? mk(-x.re, -x.im) : x;
+        if (c >= i && row) x = x + ldf(A + (long long)c * m + i) * vc[c];
+    if (row) work[off + (long long)i * n] = mirror_flip(fl, i, mx) ? mk(-x.re, -x.im) : x;
 }
 
 #define VIE_MAX_QR 5
@@ -560,17 +574,17 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     const int sub = wv >> 2;             // tile of this wavefront within the super-tile
     const int wrow = 16 * (wv & 3);      // first row of this wavefront within its tile
     long long off[CT];                   // column base offsets in work (-1: no column)
-    bool fl[CT];                         // reflected mode: x-component rows change sign in and out
+    int fl[CT];                          // reflected mode: rows where S = -1 change sign in and out
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
         off[ct] = -1;
-        fl[ct] = false;
+        fl[ct] = 0;
         if (col < ncols) {
             const int g = c0 + col;
             const int me = mode_list[mode_ptr[sblk] + g / nrhs];
             off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
-            fl[ct] = (me & VIE_MODE_MIRROR) != 0;
+            fl[ct] = me & VIE_MODE_MIRROR;
         }
     }
     const int NS = (m + ST - 1) / ST;
@@ -635,7 +649,8 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                         }
                         if (!lower && off[ct] >= 0 && out_mode != 1) {
                             const cpx<R> o = out_mode == 2 ? x + Ya[yo] : x;
-                            work[off[ct] + (long long)(t0 + row) * n] = (fl[ct] && t0 + row < mx) ? mk(-o.re, -o.im) : o;
+                            work[off[ct] + (long long)(t0 + row) * n] =
+                                mirror_flip(fl[ct], t0 + row, mx) ? mk(-o.re, -o.im) : o;
                         }
                     }
                 }
@@ -664,7 +679,7 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                 const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
                 const int src = row < m ? pm[row] : 0;
                 cpx<R> b = (row < m && off[ct] >= 0) ? work[off[ct] + (long long)src * n] : czero<R>();
-                if (fl[ct] && src < mx) b = mk(-b.re, -b.im);
+                if (mirror_flip(fl[ct], src, mx)) b = mk(-b.re, -b.im);
                 cr[ct][v] = b.re;
                 ci[ct][v] = b.im;
             }
@@ -762,17 +777,17 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
     long long off[CT];
-    bool fl[CT];  // reflected mode: the residual of S D_k S, i.e. the x rows of r - D_k z0 change sign
+    int fl[CT];  // reflected mode: the residual of S D_k S, i.e. rows of r - D_k z0 where S = -1 change sign
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
         off[ct] = -1;
-        fl[ct] = false;
+        fl[ct] = 0;
         if (col < ncols) {
             const int g = c0 + col;
             const int me = mode_list[mode_ptr[sblk] + g / nrhs];
             off[ct] = (long long)(g % nrhs) * rstride + (long long)box * m * n + (me & ~VIE_MODE_MIRROR);
-            fl[ct] = (me & VIE_MODE_MIRROR) != 0;
+            fl[ct] = me & VIE_MODE_MIRROR;
         }
     }
     const int nch = (m + YC - 1) / YC;
@@ -849,7 +864,7 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                         const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
                         const long long wo = off[ct] + (long long)row * n;
                         const c64 t = mv * mk(cr[ct][v], ci[ct][v]);
-                        work[wo] = (fl[ct] && row < mx) ? work[wo] + z0 - t : work[wo] - z0 + t;
+                        work[wo] = mirror_flip(fl[ct], row, mx) ? work[wo] + z0 - t : work[wo] - z0 + t;
                     }
                 }
         }
@@ -870,7 +885,7 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
     const bool all_wide = pc->prec == VIE_BF16C;
     const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : pc->cfg_min_rhs;
     std::vector<int> wide;    // int4 items
-    std::vector<int> narrow;  // int4 items of narrow_rc columns, or box * n + mode (tiny blocks)
+    std::vector<int> narrow;  // int4 items of narrow_rc columns (tiny blocks: 64/m columns)
     const bool tiny = pc->m <= TS;
     const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(pc->m, block_cols_max(pc, nrhs),
                                                             pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64));
@@ -896,16 +911,14 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
                 wide.insert(wide.end(), {sb, (int)c, nc, pc->block_box[sb]});
                 maxc = std::max(maxc, nc);
             }
-        } else if (tiny) {
-            for (int e = pc->mode_ptr[sb]; e < pc->mode_ptr[sb + 1]; ++e)
-                narrow.push_back(pc->block_box[sb] * n + (pc->mode_list[e] & ~VIE_MODE_MIRROR));
         } else {
-            for (long long c = 0; c < cols; c += rc)
-                narrow.insert(narrow.end(), {sb, (int)c, (int)std::min<long long>(rc, cols - c), pc->block_box[sb]});
+            const int per = tiny ? TS / pc->m : rc;  // columns per wavefront / per workgroup
+            for (long long c = 0; c < cols; c += per)
+                narrow.insert(narrow.end(), {sb, (int)c, (int)std::min<long long>(per, cols - c), pc->block_box[sb]});
         }
     }
     pc->n_wide = (int)(wide.size() / 4);
-    pc->n_narrow = (int)(tiny ? narrow.size() : narrow.size() / 4);
+    pc->n_narrow = (int)(narrow.size() / 4);
     pc->narrow_rc = rc;
     pc->wide_ct = maxc <= 16 ? 1 : maxc <= 32 ? 2 : 4;
     std::vector<int> tab(wide);
@@ -1005,11 +1018,12 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
         VIE_HIP(hipGetLastError());
     }
     if (pc->n_narrow > 0 && m <= TS) {
-        const int *modes = pc->sched.as<const int>() + 4 * pc->n_wide;
-        const int nitems = pc->n_narrow * nrhs;
+        const int4 *items = reinterpret_cast<const int4 *>(pc->sched.as<const int>() + 4 * pc->n_wide);
+        const int nitems = pc->n_narrow;
+        const int *mp = pc->modes_dev.as<const int>();
         hipLaunchKernelGGL((k_block_solve_tiny<R, FT>), dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, work,
-                           pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->block_of_mode.as<const int>(),
-                           modes, m, n, pc->nboxes, nrhs, nitems, pc->mirror_rows);
+                           pc->factors.as<const FT>(), pc->perm.as<const int>(), items, mp, mp + pc->nstored + 1, m,
+                           n, pc->nboxes, nrhs, nitems, pc->mirror_rows);
         VIE_HIP(hipGetLastError());
     } else if (pc->n_narrow > 0) {
         const int rc = pc->narrow_rc;

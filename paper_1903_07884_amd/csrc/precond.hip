@@ -1577,13 +1577,19 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
             }
         }
     }
-    // reflection along x: C^_{n-k} = S C^_k S (the parities of the Chan sequences, exact before
-    // the x-DFT), so D_{n-k} = S D_k S and modes k > n/2 take the factors of mode n - k
-    const bool mirror = pc->levels == 1 && !o->no_mirror && !o->reduce && !(o->share_tol > 0);
+    // reflections: C^_{n-kx} = S_x C^_kx S_x (the x parities of the Chan sequences, exact before
+    // the x-DFT), so D_{n-kx} = S_x D_kx S_x and modes kx > n/2 take the factors of mode n - kx;
+    // the 2-level table keeps the y parities through its Chan circulant along y, so y-modes
+    // ky > by/2 take those of by - ky (S_y on the y rows).
+    const bool mirror = !o->no_mirror && (pc->levels == 2 || (!o->reduce && !(o->share_tol > 0)));
     pc->mirror_rows = m / 3;
-    std::vector<char> mir(nm, 0);
-    if (mirror)
-        for (int k = 1; k < nm; ++k) mir[k] = nm - k < k;
+    std::vector<int> mir(nm, 0), canon(nm);
+    for (int k = 0; k < nm; ++k) {
+        const int kx = k % n, ky = k / n;
+        const bool fx = mirror && n - kx < kx, fy = mirror && pc->levels == 2 && by - ky < ky;
+        canon[k] = (fy ? by - ky : ky) * n + (fx ? n - kx : kx);
+        mir[k] = (fx ? VIE_MODE_MIRROR_X : 0) | (fy ? VIE_MODE_MIRROR_Y : 0);
+    }
     // block map: stored blocks ordered (box, mode)
     pc->block_of_mode_host.assign((size_t)nbx * nm, -1);
     std::vector<int> smode, sbox;
@@ -1596,7 +1602,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
                 sbox.push_back(b);
             }
         for (int k = 0; k < nm; ++k)
-            if (mir[k]) bom[k] = bom[nm - k] | VIE_MODE_MIRROR;
+            if (mir[k]) bom[k] = bom[canon[k]] | mir[k];
         for (int k = 0; k < nm; ++k)
             if (keep[k] && rep[k] != k) bom[k] = bom[rep[k]];  // shares its run's block
         const int cs = levels_one_centre(keep, centre) ? bom[centre] : -1;

@@ -195,10 +195,13 @@ struct vie_op_s {
     FftPlan px, py, pz;      // plans for the three periods
 };
 
-// Flag on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is the
-// reflection n - k of the block's own mode k, solved as S D_k^{-1} S (S: sign -1 on the x-component
-// rows).
-#define VIE_MODE_MIRROR (1 << 30)
+// Flags on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is a
+// reflection of the block's own mode, solved as S D_k^{-1} S.  X: x-mode n - kx, S = -1 on the
+// x-component rows (block rows [0, m/3)); Y (2-level): y-mode by - ky, S = -1 on the y-component
+// rows [m/3, 2m/3); both: the product.
+#define VIE_MODE_MIRROR_X (1 << 30)
+#define VIE_MODE_MIRROR_Y (1 << 29)
+#define VIE_MODE_MIRROR (VIE_MODE_MIRROR_X | VIE_MODE_MIRROR_Y)
 
 struct vie_pc_s {
     vie_op op = nullptr;
@@ -238,13 +241,13 @@ struct vie_pc_s {
     FftPlan pxb;             // length bx
     // block-solve schedule
     std::vector<int> mode_ptr, mode_list;  // CSR: modes using stored block s (ascending, | VIE_MODE_MIRROR)
-    int mirror_rows = 0;                   // leading block rows that are x components (m/3, 1-level)
+    int mirror_rows = 0;                   // block rows per component (m/3): x rows first, then y
     std::vector<int> block_box;            // box of stored block s
     DevBuf modes_dev;                      // int32 mode_ptr [nstored+1] then mode_list
     int sched_nrhs = 0;                    // nrhs the tables below were built for
     int n_wide = 0, n_narrow = 0, wide_ct = 1, narrow_rc = 1;
-    DevBuf sched;                          // int4 wide items [n_wide], then the narrow work: int4 items
-                                           // of narrow_rc columns, or (m <= 64) int32 box*bx+mode
+    DevBuf sched;                          // int4 wide items [n_wide], then int4 narrow items of
+                                           // narrow_rc columns (m <= 64: of 64/m columns)
     DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
     DevBuf wide_scratch2;                  // second solve of a refined apply
     DevBuf wide_bf16;                      // bfloat16 hi + lo split of the solved rows (BF16 factors)

@@ -290,6 +290,9 @@ MIRROR_CASES = [
     ((16, 8, 6), 16, 'c128'),    # m = 144: matrix-core solves
     ((16, 8, 6), 4, 'c64'),
     ((16, 8, 6), 2, 'bf16'),     # bfloat16 factors, refined against D_k of the reflected mode
+    ((12, 10, 3), 1, 'c128-2'),  # 2-level, m = 9: x, y and xy reflections, 7 columns per wavefront
+    ((13, 9, 8), 2, 'c128-2'),   # 2-level, m = 24, odd lengths
+    ((8, 6, 22), 1, 'c128-2'),   # 2-level, m = 66: per-block workgroups
 ]
 
 
@@ -299,10 +302,15 @@ def test_precond_mirror_equals_every_mode(gpu_lib, case):
     of the preconditioner that factorises every mode, with about half the stored blocks."""
     import torch
     grid, nrhs, prec = case
+    levels = 2 if prec.endswith('-2') else 1
+    prec = prec.split('-')[0]
     delta = 50e-9
     K = oracle_generator(grid, delta)
-    chi = random_contrast(grid, 17)
-    chi = np.broadcast_to(chi[:, :, :1], chi.shape).copy()
+    if levels == 2:
+        chi = W.disk(grid, delta, 0.5 * min(grid[:2]) * delta)
+    else:
+        chi = random_contrast(grid, 17)
+        chi = np.broadcast_to(chi[:, :, :1], chi.shape).copy()
     fp = dict(c128=gpu_lib.VIE_C128, c64=gpu_lib.VIE_C64, bf16=gpu_lib.VIE_BF16C)[prec]
     op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=prec != 'c128')
     n = 3 * int(np.prod(grid))
@@ -310,13 +318,17 @@ def test_precond_mirror_equals_every_mode(gpu_lib, case):
     rd = _to_dev(r if prec == 'c128' else r.astype(np.complex64))
     out, stored = {}, {}
     for mirror in (True, False):
-        pc = gpu_lib.Preconditioner(op, factor_prec=fp, mirror=mirror)
+        pc = gpu_lib.Preconditioner(op, factor_prec=fp, mirror=mirror, levels=levels,
+                                    homog='mode' if levels == 2 else 'none')
         zd = torch.empty_like(rd)
         pc.apply(rd, zd, nrhs=nrhs)
         out[mirror] = zd.cpu().numpy().astype(np.complex128)
         stored[mirror] = pc.info()['stored_blocks']
-    nx = grid[0]
-    assert stored[False] == nx and stored[True] == nx // 2 + 1
+    nx, ny = grid[:2]
+    if levels == 1:
+        assert stored[False] == nx and stored[True] == nx // 2 + 1
+    else:
+        assert stored[False] == nx * ny and stored[True] == (nx // 2 + 1) * (ny // 2 + 1)
     err = max(_rel(out[True][i], out[False][i]) for i in range(nrhs))
     print('mirror', grid, nrhs, prec, 'stored', stored, 'rel diff %.3e' % err)
     # the pair differs by the rounding of the x-DFT of the Chan sequences (and of the solves)
@@ -483,6 +495,8 @@ def test_two_level_apply_matches_oracle(gpu_lib, case):
     info = pc.info()
     bx, by, bz = (boxes[0][3:] if boxes else grid)
     assert info['levels'] == 2 and info['block_m'] == 3 * bz and info['modes'] == len(boxes or [0]) * bx * by
+    # reflections along x and y: the modes (kx, ky) with kx <= bx/2, ky <= by/2 hold factors
+    assert info['stored_blocks'] == len(boxes or [0]) * (bx // 2 + 1) * (by // 2 + 1)
     n = 3 * int(np.prod(grid))
     r = W.random_field((nrhs, n), 61)
     z_ref = np.stack([ref_pc.apply(r[i]) for i in range(nrhs)])

@@ -388,3 +388,22 @@ def test_reflected_modes_are_sign_conjugate(grid):
         assert np.abs(D[nx - k] - S @ D[k] @ S).max() < 1e-13 * scale, k
     # not a tautology: the couplings that change sign are there
     assert np.abs(D[1][:ny * nz, ny * nz:]).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize('grid', [(6, 5, 2), (5, 4, 3)])
+def test_two_level_reflected_modes_are_sign_conjugate(grid):
+    """2-level: the Chan circulant along y keeps the y parities, so D_{kx,ny-ky} = S_y D S_y as
+    well as D_{nx-kx,ky} = S_x D S_x (S_x, S_y: -1 on the x / y component rows)."""
+    nx, ny, nz = grid
+    K = G.generator_octant(grid, KAPPA)
+    Mz = 0.8 + 0.1j + 0.05 * np.arange(nz)
+    D = C.chan_olkin_blocks_2level(K, Mz, nx, ny, nz)
+    m = 3 * nz
+    Sx = np.diag(np.where(np.arange(m) < nz, -1.0, 1.0))
+    Sy = np.diag(np.where((np.arange(m) >= nz) & (np.arange(m) < 2 * nz), -1.0, 1.0))
+    scale = np.abs(D).max()
+    for kx in range(nx):
+        for ky in range(ny):
+            assert np.abs(D[(nx - kx) % nx, ky] - Sx @ D[kx, ky] @ Sx).max() < 1e-13 * scale, (kx, ky)
+            assert np.abs(D[kx, (ny - ky) % ny] - Sy @ D[kx, ky] @ Sy).max() < 1e-13 * scale, (kx, ky)
+    assert np.abs(D[1, 1][nz:2 * nz, :nz]).max() > 1e-3 * scale   # the xy coupling is there
