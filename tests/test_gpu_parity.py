@@ -751,6 +751,9 @@ LARGE_BLOCK_CASES = [
     ((6, 24, 8), 'c128', 1e-10),  # m = 576 > 512: the first FP64 panels take the column-slice
                                   # kernels and the row moves come from replaying the pivots
     ((4, 44, 8), 'c64', 1e-4),    # m = 1056 > 1024: the same for FP32, 4-sub-panel macro panels
+    ((7, 12, 8), 'c128', 1e-10),  # m = 288, 480: the per-block solve with 1-2 rows per thread,
+    ((6, 20, 8), 'c128', 1e-10),  # two right-hand sides of a reflected pair in one workgroup
+    ((7, 20, 8), 'c64', 1e-4),
 ]
 
 
