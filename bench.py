@@ -386,7 +386,7 @@ def main():
     plan = workload_plan(cfg, args.config)
 
     def step(record, mode=None, reduce_tol='default', boxes='default', proxy='product', factor=None,
-             keep_zero_rows=False, precond=True, share_tol=0.0):
+             keep_zero_rows=False, precond=True, share_tol=0.0, mirror=True):
         mode = mode or plan['mode']
         bxs = plan['boxes'] if boxes == 'default' else boxes
         rt = plan['reduce_tol'] if reduce_tol == 'default' else reduce_tol
@@ -399,7 +399,7 @@ def main():
         print('bench: operator built', file=sys.stderr, flush=True)
         pc = vie.Preconditioner(op, homog=plan['homog'], boxes=bxs, reduce_tol=rt, factor_prec=fp, proxy=proxy,
                                 keep_zero_rows=keep_zero_rows, levels=plan.get('levels', 1),
-                                share_tol=share_tol) if precond else None
+                                share_tol=share_tol, mirror=mirror) if precond else None
         ev[2].record(stream)
         print('bench: preconditioner set up (%s factors)' % factor, file=sys.stderr, flush=True)
         op.rhs(e_d, b_d, nrhs=R)
@@ -459,9 +459,11 @@ def main():
     if args.no_compare:
         pass
     elif plan['mode'] == 'fp64':
-        # memory-reduced 1-level preconditioner (tolerance 1e-3), both readings of the proxy column;
-        # the 2-level disk against no preconditioner
-        legs = (('reduced_1e-3', dict(reduce_tol=1e-3)),
+        # every mode factorised (no reflection pairing); memory-reduced 1-level preconditioner
+        # (tolerance 1e-3), both readings of the proxy column; the 2-level disk against no
+        # preconditioner
+        legs = (('full_every_mode_factorised', dict(mirror=False)),
+                ('reduced_1e-3', dict(reduce_tol=1e-3)),
                 ('reduced_1e-3_centre_proxy', dict(reduce_tol=1e-3, proxy='centre')),
                 ('reduced_1e-3_shared_runs_0.01', dict(reduce_tol=1e-3, share_tol=0.01)),
                 ('reduced_1e-3_shared_runs_0.05', dict(reduce_tol=1e-3, share_tol=0.05)))

@@ -199,6 +199,12 @@ __global__ void k_to_bf16(const c64 *src, bf16c *dst, long long count) {
     dst[i].v = bf16_bits(v.re) | (bf16_bits(v.im) << 16);
 }
 
+// dst[k] = src[k * stride], k < n (one entry of every mode's table, for a contiguous read-back)
+__global__ void k_gather_strided(const c128 *src, c128 *dst, int n, long long stride) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[k * stride];
+}
+
 __global__ void k_narrow_c128(const c128 *src, c64 *dst, long long count) {
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -1547,8 +1553,12 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         }
         int iy = 0 - yp + by - 1, iz = 0 - zp + bz - 1;
         std::vector<c128> v(n);
-        VIE_HIP(hipMemcpy2DAsync(v.data(), sizeof(c128), Ch.as<c128>() + (long long)iz * ndy + iy,
-                                 sizeof(c128) * 6 * ndy * ndz, sizeof(c128), n, hipMemcpyDeviceToHost, s));
+        DevBuf vd;  // gathered on the device: a strided copy of n 16-byte rows to the host is slow
+        VIE_CHECK(vd.ensure(sizeof(c128) * n));
+        hipLaunchKernelGGL(k_gather_strided, dim3((n + 255) / 256), dim3(256), 0, s,
+                           Ch.as<const c128>() + (long long)iz * ndy + iy, vd.as<c128>(), n, 6LL * ndy * ndz);
+        VIE_HIP(hipGetLastError());
+        VIE_HIP(hipMemcpyAsync(v.data(), vd.p, sizeof(c128) * n, hipMemcpyDeviceToHost, s));
         VIE_HIP(hipStreamSynchronize(s));
         if (yp == 0 && zp == 0)
             for (auto &x : v) x.re -= 1.0;
@@ -1559,6 +1569,13 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
                 double vh = vmax > 0 ? std::sqrt(v[k].re * v[k].re + v[k].im * v[k].im) / vmax : 0.0;
                 keep[k] = vh > o->reduce_tol;
             }
+            // With the reflection pairing (below) the decision of mode k > n/2 is taken at n - k: the
+            // proxy is an xx entry, even in x, so |v_{n-k}| = |v_k| up to the DFT's rounding.  The
+            // kept set is then symmetric and kept modes pair; discarded ones take the central block
+            // unsigned.  (Taken before the central mode is forced in, which its partner is not.)
+            if (!o->no_mirror && !(o->share_tol > 0))
+                for (int k = 1; k < n; ++k)
+                    if (n - k < k) keep[k] = keep[n - k];
             keep[centre] = 1;
         }
         // runs of kept modes whose proxy stays within share_tol of the run's first mode share its block
@@ -1581,7 +1598,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
     // the x-DFT), so D_{n-kx} = S_x D_kx S_x and modes kx > n/2 take the factors of mode n - kx;
     // the 2-level table keeps the y parities through its Chan circulant along y, so y-modes
     // ky > by/2 take those of by - ky (S_y on the y rows).
-    const bool mirror = !o->no_mirror && (pc->levels == 2 || (!o->reduce && !(o->share_tol > 0)));
+    const bool mirror = !o->no_mirror && (pc->levels == 2 || !(o->share_tol > 0));
     pc->mirror_rows = m / 3;
     std::vector<int> mir(nm, 0), canon(nm);
     for (int k = 0; k < nm; ++k) {
@@ -1590,6 +1607,7 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         canon[k] = (fy ? by - ky : ky) * n + (fx ? n - kx : kx);
         mir[k] = (fx ? VIE_MODE_MIRROR_X : 0) | (fy ? VIE_MODE_MIRROR_Y : 0);
     }
+
     // block map: stored blocks ordered (box, mode)
     pc->block_of_mode_host.assign((size_t)nbx * nm, -1);
     std::vector<int> smode, sbox;

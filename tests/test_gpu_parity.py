@@ -234,8 +234,8 @@ def test_precond_apply_matches_oracle(gpu_lib, case):
     pc.apply(rd, zd, nrhs=2)
     err = _rel(zd.cpu().numpy(), z_ref)
     kept = sum(int(p.keep.sum()) for p in ref_pc.parts)
-    # without memory reduction, modes k > n/2 reuse the factors of mode n - k (reflection along x)
-    stored = kept if tol is not None else sum(len(p.keep) // 2 + 1 for p in ref_pc.parts)
+    # kept modes k > n/2 reuse the factors of mode n - k (reflection along x)
+    stored = sum(sum(1 for k in range(len(p.keep)) if p.keep[k] and k <= len(p.keep) - k) for p in ref_pc.parts)
     print('precond', grid, homog, boxes, tol, 'err', err, 'stored', info['stored_blocks'], 'oracle kept', kept)
     assert info['stored_blocks'] == stored
     assert err < 1e-10
@@ -293,6 +293,8 @@ MIRROR_CASES = [
     ((12, 10, 3), 1, 'c128-2'),  # 2-level, m = 9: x, y and xy reflections, 7 columns per wavefront
     ((13, 9, 8), 2, 'c128-2'),   # 2-level, m = 24, odd lengths
     ((8, 6, 22), 1, 'c128-2'),   # 2-level, m = 66: per-block workgroups
+    ((40, 6, 2), 1, 'c128-r'),   # memory-reduced: the kept set symmetric, discarded modes unsigned
+    ((41, 6, 2), 16, 'c128-r'),  # on the matrix cores (the central block's many columns)
 ]
 
 
@@ -303,6 +305,7 @@ def test_precond_mirror_equals_every_mode(gpu_lib, case):
     import torch
     grid, nrhs, prec = case
     levels = 2 if prec.endswith('-2') else 1
+    tol = 0.5 if prec.endswith('-r') else None  # keeps 20 of the 40 or 41 modes
     prec = prec.split('-')[0]
     delta = 50e-9
     K = oracle_generator(grid, delta)
@@ -318,14 +321,17 @@ def test_precond_mirror_equals_every_mode(gpu_lib, case):
     rd = _to_dev(r if prec == 'c128' else r.astype(np.complex64))
     out, stored = {}, {}
     for mirror in (True, False):
-        pc = gpu_lib.Preconditioner(op, factor_prec=fp, mirror=mirror, levels=levels,
+        pc = gpu_lib.Preconditioner(op, factor_prec=fp, mirror=mirror, levels=levels, reduce_tol=tol,
                                     homog='mode' if levels == 2 else 'none')
         zd = torch.empty_like(rd)
         pc.apply(rd, zd, nrhs=nrhs)
         out[mirror] = zd.cpu().numpy().astype(np.complex128)
         stored[mirror] = pc.info()['stored_blocks']
     nx, ny = grid[:2]
-    if levels == 1:
+    if tol is not None:
+        # about half: the kept modes pair, the central block stays, its partner may be discarded
+        assert 1 < stored[True] < stored[False] and abs(2 * stored[True] - stored[False]) <= 2
+    elif levels == 1:
         assert stored[False] == nx and stored[True] == nx // 2 + 1
     else:
         assert stored[False] == nx * ny and stored[True] == (nx // 2 + 1) * (ny // 2 + 1)
