@@ -164,15 +164,18 @@ typedef struct {
                             starts a new run (the central mode of the memory reduction always
                             starts one).  Fewer stored blocks, an approximate solve for the
                             shared modes. */
-    int32_t no_mirror;      /* 0 (default): the 1-level blocks without memory reduction or
-                            sharing use the reflection symmetry of the operator along x: the
+    int32_t no_mirror;      /* 0 (default): the blocks use the reflection symmetry of the
+                            operator along x (1-level without sharing, and 2-level): the
                             components xy and xz of the x-level Toeplitz sequences are odd in the
                             x offset and the others even, so T. Chan's circulant has the same
                             parities and D_{n-k} = S D_k S with S = diag(-1 on the x rows, +1 on
                             the y and z rows) (exact up to the rounding of the x-DFT).  Modes
                             k > n/2 are then solved with the factors of mode n - k (about half
                             the stored blocks; a block's factors serve both modes in one read).
-                            1 = factorise every mode. */
+                            Under the memory reduction the keep decision of mode k > n/2 is taken
+                            at n - k (the proxy is even in x), so kept modes pair.  The 2-level
+                            blocks pair along y as well (xy and yz are odd in the y offset): a
+                            quarter of the blocks.  1 = factorise every mode. */
 } vie_pc_opts;
 
 typedef struct {

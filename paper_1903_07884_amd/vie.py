@@ -228,8 +228,8 @@ class Preconditioner:
         block (0 = off); ``keep_zero_rows``: factorise the full
         cross-section even where the homogenised contrast is zero; ``levels``: 1 or 2 (the
         2-level circulant, one 3*bz block per (x-mode, y-mode) pair); ``mirror``: solve the modes
-        k > n/2 with the factors of mode n - k through the reflection symmetry along x (1-level,
-        no memory reduction or sharing; False factorises every mode)."""
+        k > n/2 with the factors of mode n - k through the reflection symmetry along x (and, for
+        the 2-level blocks, along y; not with ``share_tol``); False factorises every mode."""
         lib = load()
         self.op = op
         bx = None
