@@ -6,13 +6,15 @@
 // and of its upper part (upper entries incl. the diagonal), so each diagonal tile is applied
 // as a product.  work element (rhs, box, row i, mode k) sits at ((rhs*nboxes + box)*m + i)*n + k.
 //
-// Two kernels share the modes:
-//  * narrow: one workgroup per (box, mode, chunk of <= 8 right-hand sides), rows in registers;
-//    for blocks used by few columns (one mode at R = 1);
-//  * wide: one workgroup per (stored block, group of <= 64 columns), where a column is one
-//    (mode, right-hand side) pair whose mode uses the block -- the R right-hand sides of a
-//    mode, and, under the memory reduction, every mode that shares the central block.  The
-//    products run on the matrix cores.
+// A column of a stored block is one (mode, right-hand side) pair whose mode uses the block: the
+// R right-hand sides of its own mode, of the reflected mode (n - k along x, and by - ky for the
+// 2-level blocks: solved as S D^{-1} S, signs on the x / y rows) and, under the memory
+// reduction, of every mode that shares the central block.  Three kernels share the columns:
+//  * narrow: one workgroup per (stored block, chunk of <= 8 columns), rows in registers; for
+//    blocks used by few columns;
+//  * tiny (m <= 64): one wavefront per (stored block, 64/m columns);
+//  * wide: one workgroup per (stored block, group of <= 64 columns), the products on the
+//    matrix cores.
 #include <algorithm>
 #include <cstdio>
 
