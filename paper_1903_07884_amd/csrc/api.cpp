@@ -129,6 +129,12 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
             return fail(VIE_EDEVICE);
     } else if ((st = launch_generator(op, s)) < 0)
         return fail(st);
+    // twiddles of the x-length (the default preconditioner box) computed on the host while the
+    // generator runs, instead of with the device idle at the preconditioner setup
+    if (fft_supported_length(op->nx)) {
+        FftPlan px_box;
+        if ((st = op->fft.get(op->nx, &px_box)) < 0) return fail(st);
+    }
     if ((st = build_kernel_transform(op, s)) < 0) return fail(st);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
