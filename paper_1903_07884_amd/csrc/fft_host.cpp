@@ -174,6 +174,17 @@ extern "C" vie_status vie_device_bytes(uint64_t *current, uint64_t *peak, int32_
     return VIE_OK;
 }
 
+uint64_t pool_cached_bytes() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    return g_pool_bytes;
+}
+
+// Cached blocks back to the driver, each after its own last work (no device-wide wait).
+void pool_trim_cached() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    pool_trim_locked();
+}
+
 extern "C" vie_status vie_trim(void) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     VIE_HIP(hipDeviceSynchronize());

@@ -27,6 +27,10 @@
 
 #include "vie_internal.h"
 
+// buffer cache of fft_host.cpp: bytes of the released blocks kept for reuse, and returning them
+uint64_t pool_cached_bytes();
+void pool_trim_cached();
+
 namespace {
 using Clock = std::chrono::steady_clock;
 
@@ -157,6 +161,9 @@ bool pick(vie_server srv, Batch *b) {
         // a cached entry grows when it serves more right-hand sides than it was sized for
         const uint64_t need = run + (idle ? (resident > idle->bytes ? resident - idle->bytes : 0) : resident);
         if (make_room(srv, need, idle)) {
+            // released buffers cached for reuse hold device memory too: past the budget they go back
+            // to the driver, so the runtime's own allocations at launch (kernel scratch) still fit
+            if (srv->committed + need + pool_cached_bytes() > srv->budget) pool_trim_cached();
             commit(srv, need);
             b->reqs.clear();
             for (size_t k : idx) b->reqs.push_back(srv->queue[k]);
