@@ -5,7 +5,9 @@ A step is one complete solve from inputs resident in HBM: operator build
 preconditioner setup (Chan table, block assembly, batched LU), right-hand
 side b = M e_inc and right-preconditioned GMRES(50) to a 1e-6 relative
 residual.  The workload is the long uniform Si waveguide (2048 x 16 x 8 voxels
-of 25 nm, complex128, 2048 LU blocks of 384 x 384).
+of 25 nm, complex128, one 384 x 384 block per each of the 2048 modes; the blocks
+of modes k > 1024 are S D_{2048-k} S by the reflection symmetry along x, so 1025
+are factorised).
 
 Prints one JSON line.  ``value`` is solves per second (1 / time-to-1e-6).
 Per-kernel durations come from HIP events recorded by the library on the
@@ -557,10 +559,10 @@ def main():
         'vs_baseline': None,
         'dtype': 'c128' if plan['mode'] == 'fp64' else ('c64+bf16+f64' if factor == 'bf16' else 'c64+f64'),
         'data': 'synthetic',
-        'config': {'workload': cfg['name'] + ', %s, %d-level Chan-Olkin %s (%d blocks of %dx%d: the %d rows of the '
-                   '%d-row block with nonzero contrast), GMRES(50) to %g'
-                   % (plan['mode'], plan.get('levels', 1), plan['label'], info['stored_blocks'], info['active_m'],
-                      info['active_m'],
+        'config': {'workload': cfg['name'] + ', %s, %d-level Chan-Olkin %s (%d modes served by %d factorised blocks '
+                   'of %dx%d: the %d rows of the %d-row block with nonzero contrast), GMRES(50) to %g'
+                   % (plan['mode'], plan.get('levels', 1), plan['label'], info['modes'], info['stored_blocks'],
+                      info['active_m'], info['active_m'],
                       info['active_m'], info['block_m'], plan.get('tol', 1e-6)),
                    'grid': list(grid), 'voxel_m': delta, 'nrhs': R, 'precision': plan['mode']},
         'compare': compare or None,
