@@ -234,61 +234,78 @@ struct GState {
     int m;
 };
 
-// Step j for every active right-hand side: one lane per right-hand side.
-__global__ void k_givens(GState S, int j, int R) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+// Step j for every active right-hand side: one wavefront per right-hand side.  Its lanes stage
+// the new column (h1 + h2) and the earlier rotations in LDS; lane 0 then applies the rotations
+// in order (the serial chain reads LDS, not global memory) and forms the new one.
+#define KR_MAX_RESTART 200
+__global__ void __launch_bounds__(64) k_givens(GState S, int j, int R) {
+    __shared__ c128 col[KR_MAX_RESTART + 1];
+    __shared__ double csl[KR_MAX_RESTART];
+    __shared__ c128 snl[KR_MAX_RESTART];
+    const int r = blockIdx.x, lane = threadIdx.x;
     if (r >= R) return;
     const int m = S.m;
     double *st = S.st + 4 * r;
     if (!S.active[r]) {
-        st[0] = 0.0;
-        st[1] = 0.0;
-        st[2] = 1.0;
-        st[3] = 0.0;
+        if (lane == 0) {
+            st[0] = 0.0;
+            st[1] = 0.0;
+            st[2] = 1.0;
+            st[3] = 0.0;
+        }
         return;
     }
     const c128 *h1 = S.h1 + (long long)r * (m + 2), *h2 = S.h2 + (long long)r * (m + 2);
-    c128 *col = S.Rm + ((long long)r * m + j) * (m + 1);
+    c128 *colg = S.Rm + ((long long)r * m + j) * (m + 1);
     double *cs = S.cs + (long long)r * m;
     c128 *sn = S.sn + (long long)r * m;
     c128 *g = S.g + (long long)r * (m + 1);
-    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-    double hn = sqrt(S.nrm2[r].re);
-    double w0 = sqrt(h1[j + 1].re);
-    for (int i = 0; i < j; ++i) {
-        c128 a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = cs[i] * b - conjg(sn[i]) * a;
+    for (int i = lane; i <= j; i += 64) col[i] = h1[i] + h2[i];
+    for (int i = lane; i < j; i += 64) {
+        csl[i] = cs[i];
+        snl[i] = sn[i];
     }
-    c128 a = col[j];
-    double c;
-    c128 s, rr;
-    double aa = sqrt(abs2(a)), bb = hn;
-    if (bb == 0.0) {
-        c = 1.0;
-        s = czero<double>();
-        rr = a;
-    } else if (aa == 0.0) {
-        c = 0.0;
-        s = mk(1.0, 0.0);
-        rr = mk(hn, 0.0);
-    } else {
-        double rho = hypot(aa, bb);
-        c128 ph = mk(a.re / aa, a.im / aa);
-        c = aa / rho;
-        s = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b) / rho, b real
-        rr = mk(ph.re * rho, ph.im * rho);
+    __syncthreads();
+    if (lane == 0) {
+        double hn = sqrt(S.nrm2[r].re);
+        double w0 = sqrt(h1[j + 1].re);
+        for (int i = 0; i < j; ++i) {
+            c128 a = col[i], b = col[i + 1];
+            col[i] = csl[i] * a + snl[i] * b;
+            col[i + 1] = csl[i] * b - conjg(snl[i]) * a;
+        }
+        c128 a = col[j];
+        double c;
+        c128 s, rr;
+        double aa = sqrt(abs2(a)), bb = hn;
+        if (bb == 0.0) {
+            c = 1.0;
+            s = czero<double>();
+            rr = a;
+        } else if (aa == 0.0) {
+            c = 0.0;
+            s = mk(1.0, 0.0);
+            rr = mk(hn, 0.0);
+        } else {
+            double rho = hypot(aa, bb);
+            c128 ph = mk(a.re / aa, a.im / aa);
+            c = aa / rho;
+            s = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b) / rho, b real
+            rr = mk(ph.re * rho, ph.im * rho);
+        }
+        cs[j] = c;
+        sn[j] = s;
+        col[j] = rr;
+        c128 gj = g[j];
+        g[j + 1] = mk(0.0, 0.0) - conjg(s) * gj;
+        g[j] = c * gj;
+        st[0] = sqrt(abs2(g[j + 1]));
+        st[1] = hn;
+        st[2] = (hn <= 1e-14 * w0) ? 1.0 : 0.0;
+        st[3] = w0;
     }
-    cs[j] = c;
-    sn[j] = s;
-    col[j] = rr;
-    c128 gj = g[j];
-    g[j + 1] = mk(0.0, 0.0) - conjg(s) * gj;
-    g[j] = c * gj;
-    st[0] = sqrt(abs2(g[j + 1]));
-    st[1] = hn;
-    st[2] = (hn <= 1e-14 * w0) ? 1.0 : 0.0;
-    st[3] = w0;
+    __syncthreads();
+    for (int i = lane; i <= j; i += 64) colg[i] = col[i];
 }
 
 // y_r = R_r^{-1} g_r over the first jr[r] columns; one lane per right-hand side.
@@ -374,7 +391,7 @@ vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState 
     }
     hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbu, 1, S.nrm2, 1);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_givens, dim3((R + 63) / 64), dim3(64), 0, s, S, j, R);
+    hipLaunchKernelGGL(k_givens, dim3(R), dim3(64), 0, s, S, j, R);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scale<VT>, grid_e, dim3(256), 0, s, (const c128 *)w, vnext, n, (const double *)(S.st + 1), 4,
                        (const int *)S.active);
