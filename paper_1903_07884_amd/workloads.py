@@ -237,3 +237,24 @@ def guide_with_lossy_ends(grid, ramp, loss=0.3):
     w[nx - ramp:] = t
     chi = chi - 1j * loss * w[None, None, :]
     return chi
+
+
+def synthetic_generator(grid, tag, scale=5e-3, self_term=-1.0 / 3.0):
+    """Seeded stand-in for the octant generator table [6, nz, ny, nx] (components xx, yy, zz,
+    xy, xz, yz; offsets d >= 0), for parity checks on grids whose quadrature generator is too
+    slow to evaluate on the CPU.  Entries are complex normal, scaled by scale / (1 + |d|)^3 (the
+    fall-off of a dipole interaction), the three diagonal components hold `self_term` at zero
+    offset, and an off-diagonal component is zero wherever the offset along either of its two
+    axes is zero (its block is odd along them, so it vanishes there).  A test input only: it
+    holds none of the solver's arithmetic."""
+    nx, ny, nz = grid
+    K = random_field((6, nz, ny, nx), tag)
+    dz, dy, dx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing='ij')
+    K *= scale / (1.0 + np.sqrt(dx * dx + dy * dy + dz * dz)) ** 3
+    K[0:3, 0, 0, 0] += self_term
+    for c, axes in ((3, (0, 1)), (4, (0, 2)), (5, (1, 2))):
+        for ax in axes:
+            sl = [c, slice(None), slice(None), slice(None)]
+            sl[3 - ax] = 0                      # table axes are [z, y, x]
+            K[tuple(sl)] = 0.0
+    return K

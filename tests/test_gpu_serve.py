@@ -4,11 +4,16 @@ Each result must not depend on what it is solved beside: a request solved alone 
 worker, no merging) and the same request solved while other devices run on other streams,
 possibly merged with another request of its own device, agree to 1e-12 (FP64) / 1e-6
 (mixed) relative, and every result meets its tolerance.  Merged requests equal the plain
-library solve of each request.
+library solve of each request.  Every served result's residual ||M e - (I - M N) x|| / ||M e||
+is also evaluated by the oracle (its generator quadrature and FFT reference operator) and
+must meet the request's tolerance.
 """
 import numpy as np
 import pytest
 
+from oracle import contrast as OCT
+from oracle import fftref as FR
+from oracle import generator as OG
 from paper_1903_07884_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -44,6 +49,21 @@ def _e(dev, nrhs, seed):
 
 def _tol(dev):
     return 1e-6 if dev.get('mode') == 'mixed' else 1e-12
+
+
+_REF = {}
+
+
+def _oracle_relres(dev, x, e):
+    """Residuals of served solutions x [R, 3N] for incident fields e [R, 3N], by the oracle."""
+    grid, delta = tuple(dev['grid']), dev['voxel_size']
+    key = (grid, delta, dev['chi'].tobytes())
+    if key not in _REF:
+        K = OG.generator_octant(grid, dev['k_background'] * delta)
+        _REF[key] = FR.FftOperator(K, OCT.contrast_from_chi(dev['chi']), grid)
+    ref = _REF[key]
+    b = np.tile(ref.M.reshape(-1), 3)[None] * np.atleast_2d(e)
+    return ref.relres(np.atleast_2d(x), b)
 
 
 def test_result_is_the_same_alone_and_in_the_mix(gpu_lib):
@@ -85,6 +105,9 @@ def test_result_is_the_same_alone_and_in_the_mix(gpu_lib):
         assert d <= _tol(dev)
         assert all(s['status'] == 0 for s in sa + sm)
         assert all(s['relres'] <= (1e-10 if dev.get('mode') != 'mixed' else 1e-6) for s in sm)
+        ores = _oracle_relres(dev, xm, _e(dev, 2, 11))
+        print('  oracle-evaluated residuals', ores)
+        assert np.all(ores <= (1e-10 if dev.get('mode') != 'mixed' else 1e-6) * 1.01)
     assert all(all(s['status'] == 0 for s in st) for _, st, _ in others)
     print('server info', info)
     assert info['completed'] == len(order) and info['queued'] == 0 and info['running'] == 0
@@ -125,6 +148,7 @@ def test_queued_requests_of_one_device_are_merged_and_cached(gpu_lib):
         gpu_lib.solve(op, None, b, xd, tol=1e-10)
         assert _rel(x, xd.cpu().numpy()) <= 1e-12
         assert st[0]['status'] == 0
+        assert _oracle_relres(dev, x, e)[0] <= 1e-10 * 1.01
     assert _rel(x4, res[0][0]) <= 1e-12
 
 
@@ -162,6 +186,10 @@ def test_budget_admission_and_eviction(gpu_lib):
     srv.close()
     print('budget %d bytes, one request %d; info %s' % (budget, need.value, info))
     assert all(st[0]['status'] == 0 for _, st, _ in out)
+    for k, (x, _, _) in enumerate(out):
+        d = dict(g)
+        d['chi'] = g['chi'] * (1.0 + 0.1 * k)
+        assert _oracle_relres(d, x, _e(d, 1, 40 + k))[0] <= 1e-10 * 1.01
     assert info['evictions'] >= 1
     assert info['peak_committed_bytes'] <= budget
 
@@ -217,4 +245,5 @@ def test_continuous_batching_completes_early_and_takes_joiners(gpu_lib):
         ref = gpu_lib.solve(op, None, b, xd, tol=1e-10, restart=10)
         assert st[0]['status'] == 0 and st[0]['iters'] == ref[0]['iters']
         assert _rel(x, xd.cpu().numpy()) <= 1e-12
+        assert _oracle_relres(dev, x, e)[0] <= 1e-10 * 1.01
     assert info['solves'] == 2  # the busy solve and the (a, b) solve, which c joined
