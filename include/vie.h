@@ -110,6 +110,21 @@ vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrhs, void *st
 vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the product of vie_matvec, same
+ * arguments, same kernels and the same result, with no allocation of any kind.  Its scratch
+ * (the x-spectra of every line, plus the y-spectra of the split plane pass) lives in one
+ * fixed device array of VIE_MATVEC_NOALLOC_MAX_BYTES per GPU, which the library holds until
+ * the process ends.  A product needing more (about 16*3*ny*nz*Px*nrhs bytes in FP64, half in
+ * complex64, Px the x period) returns VIE_EARG before any device work; vie_matvec serves any
+ * size.  Every call on one GPU shares that array and leaves its contents behind (nothing in
+ * it needs to start at zero): calls that overlap on one GPU (different streams, or host
+ * threads without ordering) race and must be serialised by the caller.  Asynchronous on
+ * `stream`; argument errors as vie_matvec. */
+#define VIE_MATVEC_NOALLOC_MAX_BYTES (64u << 20)
+vie_status vie_matvec_noalloc(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec,
+                              void *stream);
+
 /* ---- preconditioner ------------------------------------------------------ */
 
 typedef enum {

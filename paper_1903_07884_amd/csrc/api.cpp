@@ -165,13 +165,19 @@ extern "C" vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrh
     return launch_rhs(op, (const c128 *)e_inc, (c128 *)b, nrhs, (hipStream_t)stream);
 }
 
+vie_status matvec_check_args(const char *who, vie_op op, const void *x, const void *y, int32_t nrhs, int prec) {
+    const std::string w(who);
+    if (!op || !x || !y) return arg_error(w + ": NULL argument");
+    if (nrhs < 1) return arg_error(w + ": nrhs must be >= 1");
+    if (prec != VIE_C128 && prec != VIE_C64) return arg_error(w + ": unknown precision");
+    if (prec == VIE_C64 && !op->has_c64) return arg_error(w + ": operator built without complex64 transform");
+    if (x == y) return arg_error(w + ": x and y must not overlap");
+    return VIE_OK;
+}
+
 extern "C" vie_status vie_matvec(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec, void *stream) {
     StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
-    if (!op || !x || !y) return arg_error("vie_matvec: NULL argument");
-    if (nrhs < 1) return arg_error("vie_matvec: nrhs must be >= 1");
-    if (prec != VIE_C128 && prec != VIE_C64) return arg_error("vie_matvec: unknown precision");
-    if (prec == VIE_C64 && !op->has_c64) return arg_error("vie_matvec: operator built without complex64 transform");
-    if (x == y) return arg_error("vie_matvec: x and y must not overlap");
+    VIE_CHECK(matvec_check_args("vie_matvec", op, x, y, nrhs, prec));
     return launch_matvec(op, x, y, nrhs, prec, (hipStream_t)stream);
 }
 

@@ -14,6 +14,8 @@
 #include <cstdio>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "fft_device.h"
 
@@ -498,14 +500,20 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
     (void)lines_per_comp_rhs_N;
 }
 
+// Device bytes a product of nrhs vectors of element size esz works in: the x-spectra of every
+// line (*work) and, for the split plane pass, the y-spectra before and after the coupling (*ysp).
+static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, size_t *ysp) {
+    *work = esz * 3 * (size_t)op->ny * op->nz * nrhs * op->Px;
+    *ysp = op->split_plane ? 2 * esz * (size_t)nrhs * op->Px * 3 * op->nz * op->Py : 0;
+}
+
+// One product through the three passes; work and ysp hold matvec_scratch's bytes.
 template <class R>
 static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
-                             const cpx<R> *M, hipStream_t s) {
+                             const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, hipStream_t s) {
     const int nx = op->nx, ny = op->ny, nz = op->nz, Px = op->Px;
     const int pi = sizeof(R) == 8 ? 0 : 1;
     long long lines = 3LL * ny * nz * nrhs;
-    VIE_CHECK(op->work.ensure(sizeof(cpx<R>) * lines * Px));
-    cpx<R> *work = op->work.as<cpx<R>>();
     size_t ldsx;
     int thx, bpt;
     fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, op->cfg_x_thr[pi]);
@@ -524,9 +532,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
         int lg = (int)std::min<size_t>(8, max_lds() / (2 * sizeof(cpx<R>) * Py));
         lg = std::max(1, std::min(lg, rows));
         const size_t ldsy = 2 * sizeof(cpx<R>) * lg * Py;
-        const size_t yb = sizeof(cpx<R>) * (size_t)nrhs * Px * rows * Py;
-        VIE_CHECK(op->ybuf.ensure(2 * yb));
-        cpx<R> *y1 = op->ybuf.as<cpx<R>>(), *y2 = y1 + (size_t)nrhs * Px * rows * Py;
+        cpx<R> *y1 = ysp, *y2 = y1 + (size_t)nrhs * Px * rows * Py;
         const unsigned gx = (unsigned)(8 * ((Px + 7) / 8) * ((rows + lg - 1) / lg));
         ProfScope ps("matvec_plane", s);
         vie_lds_attr((const void *)k_ysplit_fwd<R>, ldsy);
@@ -573,6 +579,11 @@ template <class R>
 static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
                            const cpx<R> *M, hipStream_t s) {
     const int pi = sizeof(R) == 8 ? 0 : 1;
+    size_t wb, yb;
+    matvec_scratch(op, nrhs, sizeof(cpx<R>), &wb, &yb);
+    VIE_CHECK(op->work.ensure(wb));
+    if (yb) VIE_CHECK(op->ybuf.ensure(yb));
+    cpx<R> *work = op->work.as<cpx<R>>(), *ysp = op->ybuf.as<cpx<R>>();
     if (tune_enabled() && op->tuned_nrhs[pi] != nrhs) {
         char key[160];
         snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d split=%d",
@@ -595,7 +606,7 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
             for (auto &c : cands) {
                 op->cfg_plane_thr[pi] = c[0], op->cfg_x_thr[pi] = c[1];
                 double ms = 0;
-                VIE_CHECK(tune_time(s, 2, [&]() { return matvec_run<R>(op, x, y, nrhs, khat, M, s); }, &ms));
+                VIE_CHECK(tune_time(s, 2, [&]() { return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, s); }, &ms));
                 if (ms < best) {
                     best = ms;
                     choice = c;
@@ -606,7 +617,7 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
         op->cfg_plane_thr[pi] = choice[0], op->cfg_x_thr[pi] = choice[1];
         op->tuned_nrhs[pi] = nrhs;
     }
-    return matvec_run<R>(op, x, y, nrhs, khat, M, s);
+    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, s);
 }
 
 vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s) {
@@ -614,4 +625,61 @@ vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, 
         return matvec_t<double>(op, (const c128 *)x, (c128 *)y, nrhs, op->khat64.as<c128>(),
                                 op->M64.as<c128>(), s);
     return matvec_t<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(), s);
+}
+
+// ---------------------------------------------------------------- allocation-free product
+// The product's scratch (x-spectra, split-pass y-spectra) in a fixed device array instead of
+// the handle's buffers.  Each device holds its own copy of the array; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[VIE_MATVEC_NOALLOC_MAX_BYTES];
+
+#define VIE_NOALLOC_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[VIE_NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static vie_status scratch_address(void **out) {
+    int dev = 0;
+    VIE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= VIE_NOALLOC_MAX_DEVICES) {
+        vie_set_error("vie_matvec_noalloc: device index beyond the library's table");
+        return VIE_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        VIE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            vie_set_error("vie_matvec_noalloc: no device address for the scratch array");
+            return VIE_EDEVICE;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_matvec_noalloc(vie_op op, const void *x, void *y, int32_t nrhs, vie_prec prec,
+                                         void *stream) {
+    NoAllocScope na;  // no profiling events either
+    VIE_CHECK(matvec_check_args("vie_matvec_noalloc", op, x, y, nrhs, prec));
+    const size_t esz = prec == VIE_C128 ? sizeof(c128) : sizeof(c64);
+    size_t wb, yb;
+    matvec_scratch(op, nrhs, esz, &wb, &yb);
+    const size_t wpad = (wb + 255) & ~(size_t)255;
+    if (wpad + yb > (size_t)VIE_MATVEC_NOALLOC_MAX_BYTES) {
+        vie_set_error("vie_matvec_noalloc: this product needs " + std::to_string(wpad + yb) +
+                      " scratch bytes, more than the fixed " + std::to_string((size_t)VIE_MATVEC_NOALLOC_MAX_BYTES) +
+                      " (use vie_matvec, or fewer right-hand sides per call)");
+        return VIE_EARG;
+    }
+    void *base = nullptr;
+    VIE_CHECK(scratch_address(&base));
+    unsigned char *p = static_cast<unsigned char *>(base);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == VIE_C128)
+        return matvec_run<double>(op, (const c128 *)x, (c128 *)y, nrhs, op->khat64.as<c128>(), op->M64.as<c128>(),
+                                  reinterpret_cast<c128 *>(p), reinterpret_cast<c128 *>(p + wpad), s);
+    return matvec_run<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(),
+                             reinterpret_cast<c64 *>(p), reinterpret_cast<c64 *>(p + wpad), s);
 }

@@ -15,8 +15,13 @@ std::vector<Rec> g_recs;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pool;
 }  // namespace
 
+static thread_local int g_noalloc_depth = 0;
+NoAllocScope::NoAllocScope() { ++g_noalloc_depth; }
+NoAllocScope::~NoAllocScope() { --g_noalloc_depth; }
+bool in_noalloc() { return g_noalloc_depth > 0; }
+
 ProfScope::ProfScope(const char *name, hipStream_t stream) : s(stream) {
-    if (tune_active()) return;
+    if (tune_active() || in_noalloc()) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     hipEvent_t a, b;

@@ -266,6 +266,14 @@ struct vie_pc_s {
 };
 
 // ---------------------------------------------------------------- profiling
+// Inside an allocation-free entry point (on this thread): profiling records nothing, since it
+// would create events.
+struct NoAllocScope {
+    NoAllocScope();
+    ~NoAllocScope();
+};
+bool in_noalloc();
+
 // Records a pair of HIP events around a launch on `s` while profiling is on.
 struct ProfScope {
     int slot = -1;
@@ -288,6 +296,8 @@ vie_status launch_generator(vie_op op, hipStream_t s);
 // matvec.hip
 vie_status build_kernel_transform(vie_op op, hipStream_t s);
 vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s);
+// api.cpp: the argument checks of vie_matvec and its allocation-free variant (`who` names the call)
+vie_status matvec_check_args(const char *who, vie_op op, const void *x, const void *y, int32_t nrhs, int prec);
 vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s);
 vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
 vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s);

@@ -21,7 +21,8 @@ STATUS = {0: 'VIE_OK', 1: 'VIE_NOT_CONVERGED', -1: 'VIE_EARG', -2: 'VIE_EOOM', -
 HOMOG = {'none': 0, 'mode': 1, 'mean': 2, 'realmean': 3}
 MODE = {'fp64': 0, 'mixed': 1}
 
-EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'precond_setup',
+EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'vie_matvec_noalloc',
+           'precond_setup',
            'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
            'vie_profile_kernel', 'vie_profile_end', 'vie_last_error', 'vie_footprint', 'vie_autotune',
            'vie_autotune_report', 'vie_device_bytes', 'vie_trim', 'vie_server_create', 'vie_server_submit',
@@ -105,6 +106,7 @@ def load(path=None):
     lib.vie_generator.argtypes = [vp, vp]
     lib.vie_rhs.argtypes = [vp, vp, vp, i32, vp]
     lib.vie_matvec.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.vie_matvec_noalloc.argtypes = [vp, vp, vp, i32, i32, vp]
     lib.precond_setup.argtypes = [vp, ctypes.POINTER(PcOpts), vp, ctypes.POINTER(vp)]
     lib.precond_info.argtypes = [vp, ctypes.POINTER(PcInfo)]
     lib.precond_destroy.argtypes = [vp]
@@ -202,6 +204,11 @@ class Operator:
 
     def matvec(self, x, y, nrhs=1, stream=None):
         _check(_lib.vie_matvec(self.h, _dev(x, x.dtype), _dev(y, x.dtype), nrhs, _prec(x), _stream(stream)))
+
+    def matvec_noalloc(self, x, y, nrhs=1, stream=None):
+        """The product through the allocation-free entry point (fixed per-GPU scratch)."""
+        _check(_lib.vie_matvec_noalloc(self.h, _dev(x, x.dtype), _dev(y, x.dtype), nrhs, _prec(x),
+                                       _stream(stream)))
 
     def close(self):
         if self.h:
