@@ -23,8 +23,13 @@
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = legacy default
  * stream).  vie_matvec, vie_rhs and precond_apply are asynchronous on it;
  * vie_create, precond_setup and vie_solve synchronise it before returning.
- * A handle owns per-handle scratch memory, so calls that use the same handle
- * concurrently from different streams race: serialise them.
+ * Handles are read-only once built: calls on different streams (and host
+ * threads) may use one operator / preconditioner at the same time.  What a
+ * call writes besides its outputs (intermediate spectra, block-solve schedules,
+ * tuned launch parameters) lives in scratch owned by the handle per stream:
+ * created on the stream's first call, grown as needed, kept until the handle is
+ * destroyed.  Calls on one stream from several host threads take turns on that
+ * scratch.  A handle must not be destroyed while calls using it are running.
  *
  * Errors.  Every call returns a vie_status.  Negative values are failures;
  * outputs are then unspecified and *out handles are set to NULL.
@@ -303,6 +308,9 @@ typedef struct {
     int64_t submitted, completed, solves, cache_hits, evictions;
     int32_t cached_entries, queued, running;
     uint64_t committed_bytes, peak_committed_bytes, budget_bytes;
+    int64_t shared_runs;    /* solves admitted onto an entry another solve was running on */
+    int64_t cache_trims;    /* admissions that returned the released blocks cached for reuse to the
+                               driver (committed + request + cached blocks above the budget) */
 } vie_server_info;
 
 vie_status vie_server_create(const vie_server_opts *opts, vie_server *out);

@@ -165,6 +165,16 @@ extern "C" vie_status vie_rhs(vie_op op, const void *e_inc, void *b, int32_t nrh
     return launch_rhs(op, (const c128 *)e_inc, (c128 *)b, nrhs, (hipStream_t)stream);
 }
 
+void op_drop_ws(vie_op op, hipStream_t s) {
+    if (op) op->ws.drop(s);
+}
+
+void pc_drop_ws(vie_pc pc, hipStream_t s) {
+    if (!pc) return;
+    for (vie_pc c : pc->children) pc_drop_ws(c, s);
+    pc->ws.drop(s);
+}
+
 vie_status matvec_check_args(const char *who, vie_op op, const void *x, const void *y, int32_t nrhs, int prec) {
     const std::string w(who);
     if (!op || !x || !y) return arg_error(w + ": NULL argument");
@@ -415,7 +425,8 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
         }
     }
     if (so) {
-        if (so->restart < 1 || so->restart > 200) return arg_error("vie_footprint: restart must be in [1, 200]");
+        if (so->restart < 1 || so->restart > VIE_MAX_RESTART)
+            return arg_error("vie_footprint: restart must be in [1, " + std::to_string(VIE_MAX_RESTART) + "]");
         const uint64_t rs = (uint64_t)so->restart;
         const bool mixed = so->mode == VIE_MODE_MIXED;
         const uint64_t vb = mixed ? 8 : 16;  // basis precision
@@ -440,7 +451,7 @@ extern "C" vie_status vie_footprint(vie_op op, const vie_pc_opts *pco, int32_t n
 }
 
 vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts *pco, int32_t nrhs,
-                             const vie_solve_opts *so, uint64_t *resident, uint64_t *run) {
+                             const vie_solve_opts *so, uint64_t *resident, uint64_t *build, uint64_t *run) {
     uint64_t held, transient, mv, pcb, ap, sb;
     int Px;
     op_bytes_estimate(grid[0], grid[1], grid[2], c64, &held, &transient, &Px);
@@ -449,8 +460,9 @@ vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts 
                        sizeof(c128) * ((size_t)6 * nz * Py + (size_t)6 * Hy * nz) <= max_lds();
     VIE_CHECK(footprint_parts(grid[0], grid[1], grid[2], Px, Py, nz <= 16 && !fused, pco, nrhs, so, &mv, &pcb, &ap,
                               &sb));
-    *resident = held + mv + pcb + ap;           // kept by a cached operator + preconditioner
-    *run = sb + transient + 2 * 16 * 3ULL * grid[0] * grid[1] * grid[2] * nrhs;  // workspace, build, e/b
+    *resident = held + pcb;                     // kept by a cached operator + preconditioner
+    *build = transient;                         // the transformed embedding while the operator is built
+    *run = sb + mv + ap + 2 * 16 * 3ULL * grid[0] * grid[1] * grid[2] * nrhs;  // workspace, scratch, e/b
     return VIE_OK;
 }
 
@@ -497,6 +509,16 @@ extern "C" vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t n
     return pc_apply(pc, r, z, nrhs, prec, (hipStream_t)stream);
 }
 
+vie_status solve_opts_check(const char *who, const vie_solve_opts &o) {
+    const std::string w(who);
+    if (!(o.tol > 0) || !std::isfinite(o.tol)) return arg_error(w + ": tol must be finite and > 0");
+    if (o.restart < 1 || o.restart > VIE_MAX_RESTART)
+        return arg_error(w + ": restart must be in [1, " + std::to_string(VIE_MAX_RESTART) + "]");
+    if (o.maxit < 1) return arg_error(w + ": maxit must be >= 1");
+    if (o.mode != VIE_MODE_FP64 && o.mode != VIE_MODE_MIXED) return arg_error(w + ": unknown mode");
+    return VIE_OK;
+}
+
 extern "C" vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, int32_t nrhs,
                                 const vie_solve_opts *opts, vie_solve_stats *stats, void *stream) {
     StreamScope scope((hipStream_t)stream);  // buffers released in this call wait for its stream
@@ -505,10 +527,7 @@ extern "C" vie_status vie_solve(vie_op op, vie_pc pc, const void *b, void *x, in
     if (pc && pc->op != op) return arg_error("vie_solve: preconditioner built for another operator");
     vie_solve_opts o{1e-6, 50, 5000, VIE_MODE_FP64, 0};
     if (opts) o = *opts;
-    if (!(o.tol > 0) || !std::isfinite(o.tol)) return arg_error("vie_solve: tol must be > 0");
-    if (o.restart < 1 || o.restart > 200) return arg_error("vie_solve: restart must be in [1, 200]");
-    if (o.maxit < 1) return arg_error("vie_solve: maxit must be >= 1");
-    if (o.mode != VIE_MODE_FP64 && o.mode != VIE_MODE_MIXED) return arg_error("vie_solve: unknown mode");
+    VIE_CHECK(solve_opts_check("vie_solve", o));
     hipStream_t s = (hipStream_t)stream;
     vie_status st = solve_gmres(op, pc, (const c128 *)b, (c128 *)x, nrhs, &o, stats, s);
     hipError_t e = hipStreamSynchronize(s);

@@ -880,16 +880,16 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
 
 // Split the stored blocks between the two kernels for `nrhs` right-hand sides and upload the
 // tables (only when nrhs changed since the last apply).
-static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
-    if (pc->sched_nrhs == nrhs) return VIE_OK;
+static vie_status build_schedule(vie_pc pc, PcWs *w, int nrhs, hipStream_t s) {
+    if (w->sched_nrhs == nrhs) return VIE_OK;
     const int n = pc->nm;
     // bfloat16 factors are solved on the matrix cores only (every block goes wide)
     const bool all_wide = pc->prec == VIE_BF16C;
-    const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : pc->cfg_min_rhs;
+    const int min_cols = all_wide ? 1 : WIDE_MIN_COLS, min_rhs = all_wide ? 1 : w->cfg_min_rhs;
     std::vector<int> wide;    // int4 items
     std::vector<int> narrow;  // int4 items of narrow_rc columns (tiny blocks: 64/m columns)
     const bool tiny = pc->m <= TS;
-    const int rc = pc->cfg_rc ? pc->cfg_rc : block_solve_rc(pc->m, block_cols_max(pc, nrhs),
+    const int rc = w->cfg_rc ? w->cfg_rc : block_solve_rc(pc->m, block_cols_max(pc, nrhs),
                                                             pc->prec == VIE_C128 ? sizeof(c128) : sizeof(c64));
     int maxc = 0;
     long long wide_cols = 0;
@@ -897,7 +897,7 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
         const long long cols = (long long)(pc->mode_ptr[sb + 1] - pc->mode_ptr[sb]) * nrhs;
         if (cols >= min_cols && nrhs >= min_rhs) wide_cols += cols;
     }
-    int gmax = pc->cfg_gmax;
+    int gmax = w->cfg_gmax;
     if (gmax == 0) {  // default: the widest group that still gives >= 512 workgroups
         gmax = WIDE_MAX_COLS;
         while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
@@ -919,23 +919,23 @@ static vie_status build_schedule(vie_pc pc, int nrhs, hipStream_t s) {
                 narrow.insert(narrow.end(), {sb, (int)c, (int)std::min<long long>(per, cols - c), pc->block_box[sb]});
         }
     }
-    pc->n_wide = (int)(wide.size() / 4);
-    pc->n_narrow = (int)(narrow.size() / 4);
-    pc->narrow_rc = rc;
-    pc->wide_ct = maxc <= 16 ? 1 : maxc <= 32 ? 2 : 4;
+    w->n_wide = (int)(wide.size() / 4);
+    w->n_narrow = (int)(narrow.size() / 4);
+    w->narrow_rc = rc;
+    w->wide_ct = maxc <= 16 ? 1 : maxc <= 32 ? 2 : 4;
     std::vector<int> tab(wide);
     tab.insert(tab.end(), narrow.begin(), narrow.end());
-    VIE_CHECK(pc->sched.ensure(sizeof(int) * std::max<size_t>(tab.size(), 4)));
-    VIE_HIP(hipMemcpyAsync(pc->sched.p, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s));
+    VIE_CHECK(w->sched.ensure(sizeof(int) * std::max<size_t>(tab.size(), 4)));
+    VIE_HIP(hipMemcpyAsync(w->sched.p, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, s));
     VIE_HIP(hipStreamSynchronize(s));  // the host table is freed on return
-    pc->sched_nrhs = nrhs;
+    w->sched_nrhs = nrhs;
     return VIE_OK;
 }
 
 template <class R, int CT, int NW, class FT>
-static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
+static void launch_wide_nw(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
                            hipStream_t s) {
-    const int per = (pc->n_wide + 7) / 8;
+    const int per = (w->n_wide + 7) / 8;
     // two 64-row tiles + two chunk slots of solved rows (FP: 16 / 8 rows; bfloat16: hi + lo, 16 rows)
     const size_t chunk = sizeof(FT) == 4 ? 2 * 2 * (size_t)CT * 16 * 16 * sizeof(uint32_t)
                                          : 2 * (size_t)(sizeof(R) == 8 ? 8 : 16) * CT * 16 * sizeof(cpx<R>);
@@ -943,75 +943,75 @@ static void launch_wide_nw(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out
     vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_block_solve_wide<R, CT, NW, FT>), dim3(8 * per), dim3(NW * 64), lds, s, work,
-                       pc->factors.as<const FT>(), pc->perm.as<const int>(), pc->sched.as<const int4>(), pc->n_wide,
+                       pc->factors.as<const FT>(), pc->perm.as<const int>(), w->sched.as<const int4>(), w->n_wide,
                        mp, mp + pc->nstored + 1, Y, pc->m, pc->nm, pc->nboxes, nrhs, out_mode, Yadd,
-                       pc->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16, pc->mirror_rows);
+                       w->wide_bf16.as<uint32_t>(), (pc->m + 15) / 16 * 16, pc->mirror_rows);
 }
 
 // wavefronts per workgroup (16 NW rows per super-tile): 8 or 16 for FP32, 4 or 8 for FP64
-static int wide_nw(vie_pc pc, bool fp32) {
-    if (pc->cfg_nw) return pc->cfg_nw;
+static int wide_nw(vie_pc pc, const PcWs *w, bool fp32) {
+    if (w->cfg_nw) return w->cfg_nw;
     if (pc->prec == VIE_BF16C) return 8;  // the bfloat16 double buffers need > 128 VGPRs
     return fp32 ? 16 : 8;
 }
 
 template <class R, int CT, class FT>
-static void launch_wide(vie_pc pc, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
+static void launch_wide(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
                         hipStream_t s) {
-    const int nw = wide_nw(pc, sizeof(R) == 4);
+    const int nw = wide_nw(pc, w, sizeof(R) == 4);
     if (sizeof(R) == 4) {
-        if (nw == 8) launch_wide_nw<R, CT, 8, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
-        else launch_wide_nw<R, CT, 16, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+        if (nw == 8) launch_wide_nw<R, CT, 8, FT>(pc, w, work, Y, nrhs, out_mode, Yadd, s);
+        else launch_wide_nw<R, CT, 16, FT>(pc, w, work, Y, nrhs, out_mode, Yadd, s);
     } else {
-        if (nw == 4) launch_wide_nw<R, CT, 4, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
-        else launch_wide_nw<R, CT, 8, FT>(pc, work, Y, nrhs, out_mode, Yadd, s);
+        if (nw == 4) launch_wide_nw<R, CT, 4, FT>(pc, w, work, Y, nrhs, out_mode, Yadd, s);
+        else launch_wide_nw<R, CT, 8, FT>(pc, w, work, Y, nrhs, out_mode, Yadd, s);
     }
 }
 
 template <int CT>
-static void launch_residual(vie_pc pc, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
+static void launch_residual(vie_pc pc, PcWs *w, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
     constexpr int NW = 16;  // one workgroup per CU (the table fills the LDS): 16 wavefronts hide the latency
-    const int per = (pc->n_wide + 7) / 8;
+    const int per = (w->n_wide + 7) / 8;
     const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
     const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16) + sizeof(int) * pc->m;
     vie_lds_attr((const void *)k_refine_residual<CT, NW>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
-                       pc->sched.as<const int4>(), pc->n_wide, mp, mp + pc->nstored + 1, Y,
+                       w->sched.as<const int4>(), w->n_wide, mp, mp + pc->nstored + 1, Y,
                        pc->rows.as<const int>(), pc->m, pc->nm, pc->nboxes, nrhs, pc->by, pc->bz, pc->mirror_rows);
 }
 
 template <class R, class FT>
-static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
+static vie_status block_solve_run(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hipStream_t s) {
     const int m = pc->m, n = pc->nm;
     const int qr = (m + 255) / 256;
-    VIE_CHECK(build_schedule(pc, nrhs, s));
-    if (pc->n_wide > 0) {
-        const int WC = 16 * pc->wide_ct;
-        const size_t ybytes = sizeof(cpx<R>) * (size_t)pc->n_wide * m * WC;
-        VIE_CHECK(pc->wide_scratch.ensure(ybytes));
-        cpx<R> *Y = pc->wide_scratch.as<cpx<R>>();
+    VIE_CHECK(build_schedule(pc, w, nrhs, s));
+    if (w->n_wide > 0) {
+        const int WC = 16 * w->wide_ct;
+        const size_t ybytes = sizeof(cpx<R>) * (size_t)w->n_wide * m * WC;
+        VIE_CHECK(w->wide_scratch.ensure(ybytes));
+        cpx<R> *Y = w->wide_scratch.as<cpx<R>>();
         if (pc->prec == VIE_BF16C)  // hi + lo bfloat16 copies of the solved rows
-            VIE_CHECK(pc->wide_bf16.ensure(sizeof(uint32_t) * 2 * (size_t)pc->n_wide * WC * ((m + 15) / 16 * 16)));
+            VIE_CHECK(w->wide_bf16.ensure(sizeof(uint32_t) * 2 * (size_t)w->n_wide * WC * ((m + 15) / 16 * 16)));
         const bool refine = pc->refine && sizeof(R) == 4;
         cpx<R> *Y2 = nullptr;
         if (refine) {
-            VIE_CHECK(pc->wide_scratch2.ensure(ybytes));
-            Y2 = pc->wide_scratch2.as<cpx<R>>();
+            VIE_CHECK(w->wide_scratch2.ensure(ybytes));
+            Y2 = w->wide_scratch2.as<cpx<R>>();
         }
 #define WIDE_CASES(CTV)                                                                                  \
     if (!refine) {                                                                                       \
-        launch_wide<R, CTV, FT>(pc, work, Y, nrhs, 0, nullptr, s);                                       \
+        launch_wide<R, CTV, FT>(pc, w, work, Y, nrhs, 0, nullptr, s);                                       \
     } else {                                                                                             \
-        launch_wide<R, CTV, FT>(pc, work, Y, nrhs, 1, nullptr, s);                                       \
+        launch_wide<R, CTV, FT>(pc, w, work, Y, nrhs, 1, nullptr, s);                                       \
         VIE_HIP(hipGetLastError());                                                                      \
         ProfScope pr("refine_residual", s);                                                              \
-        launch_residual<CTV>(pc, (c64 *)work, (const c64 *)Y, nrhs, s);                                  \
+        launch_residual<CTV>(pc, w, (c64 *)work, (const c64 *)Y, nrhs, s);                                  \
         VIE_HIP(hipGetLastError());                                                                      \
-        launch_wide<R, CTV, FT>(pc, work, Y2, nrhs, 2, Y, s);                                            \
+        launch_wide<R, CTV, FT>(pc, w, work, Y2, nrhs, 2, Y, s);                                            \
     }
-        switch (pc->wide_ct) {
+        switch (w->wide_ct) {
             case 1: WIDE_CASES(1) break;
             case 2: WIDE_CASES(2) break;
             default: WIDE_CASES(4) break;
@@ -1019,20 +1019,20 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
 #undef WIDE_CASES
         VIE_HIP(hipGetLastError());
     }
-    if (pc->n_narrow > 0 && m <= TS) {
-        const int4 *items = reinterpret_cast<const int4 *>(pc->sched.as<const int>() + 4 * pc->n_wide);
-        const int nitems = pc->n_narrow;
+    if (w->n_narrow > 0 && m <= TS) {
+        const int4 *items = reinterpret_cast<const int4 *>(w->sched.as<const int>() + 4 * w->n_wide);
+        const int nitems = w->n_narrow;
         const int *mp = pc->modes_dev.as<const int>();
         hipLaunchKernelGGL((k_block_solve_tiny<R, FT>), dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, work,
                            pc->factors.as<const FT>(), pc->perm.as<const int>(), items, mp, mp + pc->nstored + 1, m,
                            n, pc->nboxes, nrhs, nitems, pc->mirror_rows);
         VIE_HIP(hipGetLastError());
-    } else if (pc->n_narrow > 0) {
-        const int rc = pc->narrow_rc;
-        dim3 grid((unsigned)pc->n_narrow);
+    } else if (w->n_narrow > 0) {
+        const int rc = w->narrow_rc;
+        dim3 grid((unsigned)w->n_narrow);
         size_t lds = 5 * (size_t)TS * rc * sizeof(cpx<R>);
         const int *mp = pc->modes_dev.as<const int>();
-        const NarrowArgs a{reinterpret_cast<const int4 *>(pc->sched.as<const int>() + 4 * pc->n_wide), mp,
+        const NarrowArgs a{reinterpret_cast<const int4 *>(w->sched.as<const int>() + 4 * w->n_wide), mp,
                            mp + pc->nstored + 1, m, n, pc->nboxes, nrhs, pc->mirror_rows};
         const FT *F = pc->factors.as<const FT>();
         const int *perm = pc->perm.as<const int>();
@@ -1052,12 +1052,12 @@ static vie_status block_solve_run(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t
 // autotuning on the fastest candidate for this shape (timed on a copy of `work`, since the
 // solves run in place), looked up in or added to the process-wide cache.
 template <class R, class FT>
-static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s) {
+static vie_status block_solve_t(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hipStream_t s) {
     if ((pc->m + 255) / 256 > VIE_MAX_QR) {
         vie_set_error("block size above 1280 is not supported by the block solve");
         return VIE_EARG;
     }
-    if (tune_enabled() && pc->tuned_nrhs != nrhs) {
+    if (tune_enabled() && w->tuned_nrhs != nrhs) {
         const bool bf = pc->prec == VIE_BF16C, fp32 = sizeof(R) == 4;
         char key[160];
         snprintf(key, sizeof key, "block_solve prec=%d m=%d n=%d boxes=%d stored=%d nrhs=%d refine=%d", pc->prec,
@@ -1078,12 +1078,12 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
                 VIE_CHECK(copy.ensure(bytes));
                 double best = 1e300;
                 for (auto &c : cands) {
-                    pc->cfg_gmax = c[0], pc->cfg_nw = c[1], pc->cfg_rc = c[2], pc->cfg_min_rhs = c[3];
-                    pc->sched_nrhs = 0;
+                    w->cfg_gmax = c[0], w->cfg_nw = c[1], w->cfg_rc = c[2], w->cfg_min_rhs = c[3];
+                    w->sched_nrhs = 0;
                     double ms = 0;
                     VIE_CHECK(tune_time(s, 2, [&]() -> vie_status {
                         VIE_HIP(hipMemcpyAsync(copy.p, work, bytes, hipMemcpyDeviceToDevice, s));
-                        return block_solve_run<R, FT>(pc, copy.as<cpx<R>>(), nrhs, s);
+                        return block_solve_run<R, FT>(pc, w, copy.as<cpx<R>>(), nrhs, s);
                     }, &ms));
                     if (ms < best) {
                         best = ms;
@@ -1096,16 +1096,16 @@ static vie_status block_solve_t(vie_pc pc, cpx<R> *work, int nrhs, hipStream_t s
             }
         }
         if (!choice.empty()) {
-            pc->cfg_gmax = choice[0], pc->cfg_nw = choice[1], pc->cfg_rc = choice[2], pc->cfg_min_rhs = choice[3];
-            pc->sched_nrhs = 0;
+            w->cfg_gmax = choice[0], w->cfg_nw = choice[1], w->cfg_rc = choice[2], w->cfg_min_rhs = choice[3];
+            w->sched_nrhs = 0;
         }
-        pc->tuned_nrhs = nrhs;
+        w->tuned_nrhs = nrhs;
     }
-    return block_solve_run<R, FT>(pc, work, nrhs, s);
+    return block_solve_run<R, FT>(pc, w, work, nrhs, s);
 }
 
-vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s) {
-    if (pc->prec == VIE_C128) return block_solve_t<double, c128>(pc, (c128 *)work, nrhs, s);
-    if (pc->prec == VIE_BF16C) return block_solve_t<float, bf16c>(pc, (c64 *)work, nrhs, s);
-    return block_solve_t<float, c64>(pc, (c64 *)work, nrhs, s);
+vie_status launch_block_solve(vie_pc pc, PcWs *w, void *work, int nrhs, hipStream_t s) {
+    if (pc->prec == VIE_C128) return block_solve_t<double, c128>(pc, w, (c128 *)work, nrhs, s);
+    if (pc->prec == VIE_BF16C) return block_solve_t<float, bf16c>(pc, w, (c64 *)work, nrhs, s);
+    return block_solve_t<float, c64>(pc, w, (c64 *)work, nrhs, s);
 }

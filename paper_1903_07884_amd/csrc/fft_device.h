@@ -35,14 +35,14 @@ __device__ __forceinline__ cpx<R> tw_at(const cpx<R> *tw, int q, bool inv) {
 }
 
 template <class R>
-__device__ __forceinline__ void bfly2(cpx<R> *v) {
+__host__ __device__ __forceinline__ void bfly2(cpx<R> *v) {
     cpx<R> a = v[0], b = v[1];
     v[0] = a + b;
     v[1] = a - b;
 }
 
 template <class R>
-__device__ __forceinline__ void bfly4(cpx<R> *v, bool inv) {
+__host__ __device__ __forceinline__ void bfly4(cpx<R> *v, bool inv) {
     cpx<R> s02 = v[0] + v[2], d02 = v[0] - v[2];
     cpx<R> s13 = v[1] + v[3], d13 = v[1] - v[3];
     // forward: -i * d13 ; inverse: +i * d13
@@ -54,7 +54,7 @@ __device__ __forceinline__ void bfly4(cpx<R> *v, bool inv) {
 }
 
 template <class R>
-__device__ __forceinline__ void bfly3(cpx<R> *v, bool inv) {
+__host__ __device__ __forceinline__ void bfly3(cpx<R> *v, bool inv) {
     const R h = R(0.8660254037844386467637231707529362);  // sqrt(3)/2
     cpx<R> s = v[1] + v[2], d = v[1] - v[2];
     cpx<R> t = mk(v[0].re - R(0.5) * s.re, v[0].im - R(0.5) * s.im);
@@ -67,7 +67,7 @@ __device__ __forceinline__ void bfly3(cpx<R> *v, bool inv) {
 }
 
 template <class R>
-__device__ __forceinline__ void bfly5(cpx<R> *v, bool inv) {
+__host__ __device__ __forceinline__ void bfly5(cpx<R> *v, bool inv) {
     const R c1 = R(0.3090169943749474241022934171828191);
     const R c2 = R(-0.8090169943749474241022934171828191);
     const R s1 = R(0.9510565162951535721164393333793821);

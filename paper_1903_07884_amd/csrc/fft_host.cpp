@@ -179,10 +179,25 @@ uint64_t pool_cached_bytes() {
     return g_pool_bytes;
 }
 
-// Cached blocks back to the driver, each after its own last work (no device-wide wait).
+// Cached blocks back to the driver, each after its own last work.  The blocks leave the cache
+// under its lock and are freed after it is released, so other threads' allocations and releases
+// go on meanwhile (hipFree itself may still wait for the device).
 void pool_trim_cached() {
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    pool_trim_locked();
+    std::vector<Block> gone;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (auto &kv : g_pool) gone.push_back(kv.second);
+        g_pool.clear();
+        g_pool_bytes = 0;
+    }
+    for (Block &b : gone) {
+        if (b.ev) {
+            (void)hipEventSynchronize(b.ev);
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            g_events.emplace_back(b.ev, b.stream);
+        }
+        (void)hipFree(b.p);
+    }
 }
 
 extern "C" vie_status vie_trim(void) {

@@ -237,7 +237,7 @@ struct GState {
 // Step j for every active right-hand side: one wavefront per right-hand side.  Its lanes stage
 // the new column (h1 + h2) and the earlier rotations in LDS; lane 0 then applies the rotations
 // in order (the serial chain reads LDS, not global memory) and forms the new one.
-#define KR_MAX_RESTART 200
+#define KR_MAX_RESTART VIE_MAX_RESTART
 __global__ void __launch_bounds__(64) k_givens(GState S, int j, int R) {
     __shared__ c128 col[KR_MAX_RESTART + 1];
     __shared__ double csl[KR_MAX_RESTART];

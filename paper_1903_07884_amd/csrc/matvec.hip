@@ -508,16 +508,16 @@ static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, 
 }
 
 // One product through the three passes; work and ysp hold matvec_scratch's bytes.
+// cfg_plane / cfg_x: threads of the plane pass / the x-line passes (0 = default).
 template <class R>
 static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
-                             const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, hipStream_t s) {
+                             const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, int cfg_plane, int cfg_x, hipStream_t s) {
     const int nx = op->nx, ny = op->ny, nz = op->nz, Px = op->Px;
-    const int pi = sizeof(R) == 8 ? 0 : 1;
     long long lines = 3LL * ny * nz * nrhs;
     size_t ldsx;
     int thx, bpt;
-    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, op->cfg_x_thr[pi]);
-    const int thp = op->cfg_plane_thr[pi] ? op->cfg_plane_thr[pi] : 256;
+    fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, cfg_x);
+    const int thp = cfg_plane ? cfg_plane : 256;
     {
         ProfScope ps("matvec_xfwd", s);
 #define LAUNCH_XFWD(B)                                      \
@@ -579,12 +579,14 @@ template <class R>
 static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
                            const cpx<R> *M, hipStream_t s) {
     const int pi = sizeof(R) == 8 ? 0 : 1;
+    OpWs *w = op->ws.get(s);
+    std::lock_guard<std::mutex> lk(w->mu);
     size_t wb, yb;
     matvec_scratch(op, nrhs, sizeof(cpx<R>), &wb, &yb);
-    VIE_CHECK(op->work.ensure(wb));
-    if (yb) VIE_CHECK(op->ybuf.ensure(yb));
-    cpx<R> *work = op->work.as<cpx<R>>(), *ysp = op->ybuf.as<cpx<R>>();
-    if (tune_enabled() && op->tuned_nrhs[pi] != nrhs) {
+    VIE_CHECK(w->work.ensure(wb));
+    if (yb) VIE_CHECK(w->ybuf.ensure(yb));
+    cpx<R> *work = w->work.as<cpx<R>>(), *ysp = w->ybuf.as<cpx<R>>();
+    if (tune_enabled() && w->tuned_nrhs[pi] != nrhs) {
         char key[160];
         snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d split=%d",
                  (int)sizeof(cpx<R>), op->Px, op->Py, op->Pz, op->nx, op->ny, op->nz, nrhs, (int)op->direct_z,
@@ -604,9 +606,10 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
                 }
             double best = 1e300;
             for (auto &c : cands) {
-                op->cfg_plane_thr[pi] = c[0], op->cfg_x_thr[pi] = c[1];
                 double ms = 0;
-                VIE_CHECK(tune_time(s, 2, [&]() { return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, s); }, &ms));
+                VIE_CHECK(tune_time(s, 2, [&]() {
+                    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, c[0], c[1], s);
+                }, &ms));
                 if (ms < best) {
                     best = ms;
                     choice = c;
@@ -614,10 +617,10 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
             }
             tune_store(key, choice, best, (int)cands.size());
         }
-        op->cfg_plane_thr[pi] = choice[0], op->cfg_x_thr[pi] = choice[1];
-        op->tuned_nrhs[pi] = nrhs;
+        w->cfg_plane_thr[pi] = choice[0], w->cfg_x_thr[pi] = choice[1];
+        w->tuned_nrhs[pi] = nrhs;
     }
-    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, s);
+    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, w->cfg_plane_thr[pi], w->cfg_x_thr[pi], s);
 }
 
 vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s) {
@@ -679,7 +682,7 @@ extern "C" vie_status vie_matvec_noalloc(vie_op op, const void *x, void *y, int3
     hipStream_t s = (hipStream_t)stream;
     if (prec == VIE_C128)
         return matvec_run<double>(op, (const c128 *)x, (c128 *)y, nrhs, op->khat64.as<c128>(), op->M64.as<c128>(),
-                                  reinterpret_cast<c128 *>(p), reinterpret_cast<c128 *>(p + wpad), s);
+                                  reinterpret_cast<c128 *>(p), reinterpret_cast<c128 *>(p + wpad), 0, 0, s);
     return matvec_run<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(),
-                             reinterpret_cast<c64 *>(p), reinterpret_cast<c64 *>(p + wpad), s);
+                             reinterpret_cast<c64 *>(p), reinterpret_cast<c64 *>(p + wpad), 0, 0, s);
 }

@@ -1191,6 +1191,11 @@ __global__ void k_box_yfft(cpx<R> *x1, cpx<R> *x2, int bx, int by, int bz, FftPl
     }
 }
 
+// Clear one flag word (a kernel rather than a memset, so a captured apply replays it).
+__global__ void k_zero_u32(uint32_t *p) {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
 // Identity rows of every D_k (M~ = 0 on the row): z = r on their box lines, and *flag = epoch
 // when any of that input is nonzero (it then couples into the solved rows).
 template <class R>
@@ -1255,12 +1260,12 @@ __global__ void __launch_bounds__(256) k_couple(cpx<R> *work, const cpx<R> *work
 // 2-level apply: x-DFT of every box line, y-DFT to the (x-mode, y-mode) spectra, one block solve
 // per mode pair, inverse y-DFT, inverse x-DFT (Sec. 4: C_B2^{-1}).
 template <class R>
-static vie_status apply2_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
+static vie_status apply2_t(vie_pc pc, PcWs *ws, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
     vie_op op = pc->op;
     const int bx = pc->bx, by = pc->by, bz = pc->bz, m1 = 3 * by * bz;
     const long long lines1 = (long long)nrhs * pc->nboxes * m1;
-    VIE_CHECK(pc->work1.ensure(sizeof(cpx<R>) * lines1 * bx));
-    VIE_CHECK(pc->work.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->nm));
+    VIE_CHECK(ws->work1.ensure(sizeof(cpx<R>) * lines1 * bx));
+    VIE_CHECK(ws->work.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->nm));
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
     const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * pc->nm);
@@ -1268,7 +1273,7 @@ static vie_status apply2_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipS
     int thr, bpt;
     size_t lds;
     fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds, &bpt);
-    cpx<R> *w1 = pc->work1.as<cpx<R>>(), *w2 = pc->work.as<cpx<R>>();
+    cpx<R> *w1 = ws->work1.as<cpx<R>>(), *w2 = ws->work.as<cpx<R>>();
     const unsigned ygrid = (unsigned)((long long)nrhs * pc->nboxes * pc->m * ((bx + YC - 1) / YC));
     const size_t ylds = 2 * sizeof(cpx<R>) * YC * by;
     vie_lds_attr((const void *)k_box_yfft<R>, ylds);
@@ -1286,7 +1291,7 @@ static vie_status apply2_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipS
     }
     {
         ProfScope ps("block_solve", s);
-        VIE_CHECK(launch_block_solve(pc, w2, nrhs, s));
+        VIE_CHECK(launch_block_solve(pc, ws, w2, nrhs, s));
     }
     {
         ProfScope ps("precond_ixfft", s);
@@ -1306,11 +1311,21 @@ static vie_status apply2_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipS
 template <class R>
 static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipStream_t s) {
     vie_op op = pc->op;
-    if (pc->levels == 2) return apply2_t<R>(pc, r, z, nrhs, s);
+    PcWs *ws = pc->ws.get(s);
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if (pc->levels == 2) return apply2_t<R>(pc, ws, r, z, nrhs, s);
     const int m = pc->m, mc = pc->m_full - pc->m, n = pc->bx;
     long long lines = (long long)nrhs * pc->nboxes * m;
-    VIE_CHECK(pc->work.ensure(sizeof(cpx<R>) * lines * n));
-    if (mc > 0) VIE_CHECK(pc->workc.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * mc * n));
+    VIE_CHECK(ws->work.ensure(sizeof(cpx<R>) * lines * n));
+    if (mc > 0) {
+        VIE_CHECK(ws->workc.ensure(sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * mc * n));
+        if (!ws->cflag.p) {  // this stream's first apply: no epoch has matched yet
+            VIE_CHECK(ws->cflag.ensure(sizeof(uint32_t)));
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws->cflag.as<uint32_t>());
+            VIE_HIP(hipGetLastError());
+            ws->epoch = 0;
+        }
+    }
     if (!pc->covers_all)
         VIE_HIP(hipMemcpyAsync(z, r, sizeof(cpx<R>) * 3 * op->N * nrhs, hipMemcpyDeviceToDevice, s));
     const int *dboxes = reinterpret_cast<const int *>(pc->block_of_mode.as<int>() + pc->nboxes * pc->nm);
@@ -1318,17 +1333,18 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     int thr, bpt;
     size_t lds;
     fft_line_shape(pc->pxb, sizeof(cpx<R>), &thr, &lds, &bpt);
-    cpx<R> *work = pc->work.as<cpx<R>>();
-    uint32_t *flag = pc->cflag.as<uint32_t>();
+    cpx<R> *work = ws->work.as<cpx<R>>();
+    uint32_t *flag = ws->cflag.as<uint32_t>();
     if (mc > 0) {
-        if (++pc->epoch == 0) {  // wrapped: no earlier apply may match the new epochs
-            VIE_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
-            pc->epoch = 1;
+        if (++ws->epoch == 0) {  // wrapped: no earlier apply may match the new epochs
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, flag);
+            VIE_HIP(hipGetLastError());
+            ws->epoch = 1;
         }
         ProfScope ps("precond_identity_rows", s);
         hipLaunchKernelGGL(k_identity_rows<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * mc)), dim3(256), 0, s,
                            r, z, dboxes, rows + m, mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, flag,
-                           pc->epoch);
+                           ws->epoch);
         VIE_HIP(hipGetLastError());
     }
     {
@@ -1343,12 +1359,12 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     VIE_HIP(hipGetLastError());
     if (mc > 0) {  // both launches return at once unless the identity rows held input
         ProfScope ps("precond_identity_rows", s);
-        cpx<R> *workc = pc->workc.as<cpx<R>>();
+        cpx<R> *workc = ws->workc.as<cpx<R>>();
         const long long clines = (long long)nrhs * pc->nboxes * mc;
 #define LAUNCH_BOX_FFT_C(B)                                                                                       \
     vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                             \
     hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)clines), dim3(thr), lds, s, r, workc, dboxes, rows + m, \
-                       mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, flag, pc->epoch)
+                       mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, flag, ws->epoch)
         VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT_C);
 #undef LAUNCH_BOX_FFT_C
         VIE_HIP(hipGetLastError());
@@ -1357,12 +1373,12 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
         const size_t clds = (sizeof(cpx<R>) + sizeof(int)) * mc;
         vie_lds_attr((const void *)k_couple<R>, clds);
         hipLaunchKernelGGL(k_couple<R>, dim3((unsigned)((long long)nrhs * pc->nboxes * n)), dim3(256), clds, s, work,
-                           workc, chan, mt, rows, m, mc, n, pc->nboxes, pc->by, pc->bz, flag, pc->epoch);
+                           workc, chan, mt, rows, m, mc, n, pc->nboxes, pc->by, pc->bz, flag, ws->epoch);
         VIE_HIP(hipGetLastError());
     }
     {
         ProfScope ps("block_solve", s);
-        VIE_CHECK(launch_block_solve(pc, work, nrhs, s));
+        VIE_CHECK(launch_block_solve(pc, ws, work, nrhs, s));
     }
     {
         ProfScope ps("precond_ixfft", s);
@@ -1516,9 +1532,6 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
         for (int yz = 0; yz < plane; ++yz) pc->m += 3 * act[yz];
         VIE_CHECK(pc->rows.ensure(sizeof(int) * pc->m_full));
         VIE_HIP(hipMemcpyAsync(pc->rows.p, pc->rows_host.data(), sizeof(int) * pc->m_full, hipMemcpyHostToDevice, s));
-        VIE_CHECK(pc->cflag.ensure(sizeof(uint32_t)));
-        VIE_HIP(hipMemsetAsync(pc->cflag.p, 0, sizeof(uint32_t), s));
-        pc->epoch = 0;
     }
     const int m = pc->m, nm = pc->nm;
     const bool shortcut = pc->m < pc->m_full;
@@ -1644,7 +1657,6 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
                 pc->mode_list[fill[e & ~VIE_MODE_MIRROR]++] = k | (e & VIE_MODE_MIRROR);
             }
     }
-    pc->sched_nrhs = 0;
     VIE_CHECK(pc->modes_dev.ensure(sizeof(int) * (pc->mode_ptr.size() + pc->mode_list.size())));
     VIE_HIP(hipMemcpyAsync(pc->modes_dev.p, pc->mode_ptr.data(), sizeof(int) * pc->mode_ptr.size(),
                            hipMemcpyHostToDevice, s));

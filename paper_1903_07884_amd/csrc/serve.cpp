@@ -1,9 +1,11 @@
 // Request scheduler for many solves on one GPU (the serving part of the C ABI).
 //
 // Submitted requests wait in a FIFO queue.  A worker thread (one HIP stream each) takes the
-// first queued request that can be admitted: its operator and preconditioner are found idle
-// in the resident cache, or the bytes to build them fit the budget after evicting idle cache
-// entries (least recently used first); the solve workspace must fit as well.  Later queued
+// first queued request that can be admitted: its operator and preconditioner are found in the
+// resident cache (shared with any solves running on them: the handles are read-only and each
+// stream has its own scratch), or the bytes to build them fit the budget after evicting idle
+// cache entries (least recently used first); the solve's own bytes must fit as well.  An entry
+// is built once: requests for it wait while another worker builds it.  Later queued
 // requests with the same device, preconditioner options and solver settings join it in one
 // multi-RHS solve.  A request that has been passed over by later ones several times blocks
 // further overtaking until it is admitted.
@@ -73,7 +75,8 @@ struct Entry {
     vie_op op = nullptr;
     vie_pc pc = nullptr;
     uint64_t bytes = 0;  // resident bytes accounted for this entry
-    bool in_use = false;
+    int users = 0;       // solves running on it
+    bool ready = false;  // built (until then the admitting worker is building it)
     uint64_t last = 0;
 };
 
@@ -82,9 +85,11 @@ struct Batch {
     std::vector<Req *> reqs;  // requests of the solve not yet completed (a waiter may free the others)
     std::string key, batch_key;
     int n_total = 0;          // requests that took part, joiners included
-    Entry *entry = nullptr;   // cache entry in use (nullptr: build a new one)
+    Entry *entry = nullptr;   // cache entry it runs on
+    bool build = false;       // this solve builds the entry
+    bool trim = false;        // return the released blocks cached for reuse before running
     int R = 0;
-    uint64_t resident = 0, run = 0;  // bytes committed for the entry (when new) and the run
+    uint64_t build_bytes = 0, run = 0;  // bytes committed for the build (while it runs) and the run
 };
 
 double ms_between(Clock::time_point a, Clock::time_point b) {
@@ -106,7 +111,7 @@ struct vie_server_s {
     bool stop = false;
     int running = 0;
     std::vector<std::thread> threads;
-    int64_t n_submitted = 0, n_completed = 0, n_solves = 0, n_hits = 0, n_evicted = 0;
+    int64_t n_submitted = 0, n_completed = 0, n_solves = 0, n_hits = 0, n_evicted = 0, n_shared = 0, n_trims = 0;
 };
 
 namespace {
@@ -127,7 +132,7 @@ bool make_room(vie_server srv, uint64_t need, const Entry *keep) {
     while (srv->committed + need > srv->budget) {
         Entry *victim = nullptr;
         for (Entry *e : srv->cache)
-            if (!e->in_use && e != keep && (!victim || e->last < victim->last)) victim = e;
+            if (e->users == 0 && e->ready && e != keep && (!victim || e->last < victim->last)) victim = e;
         if (!victim) return false;
         srv->cache.remove(victim);
         srv->committed -= victim->bytes;
@@ -151,19 +156,22 @@ bool pick(vie_server srv, Batch *b) {
                 R += o->nrhs;
             }
         }
-        Entry *idle = nullptr;
+        Entry *ent = nullptr;
         for (Entry *e : srv->cache)
-            if (!e->in_use && e->key == r->key && (!idle || e->last > idle->last)) idle = e;
-        uint64_t resident = 0, run = 0;
+            if (e->key == r->key) ent = e;
+        if (ent && !ent->ready) continue;  // another worker is building it: later requests may go
+        uint64_t resident = 0, build = 0, run = 0;
         const bool mixed = r->so.mode == VIE_MODE_MIXED;
-        if (request_footprint(r->grid, mixed, r->precond ? &r->pco : nullptr, R, &r->so, &resident, &run) != VIE_OK)
-            resident = run = 0;  // arguments were checked on submit
-        // a cached entry grows when it serves more right-hand sides than it was sized for
-        const uint64_t need = run + (idle ? (resident > idle->bytes ? resident - idle->bytes : 0) : resident);
-        if (make_room(srv, need, idle)) {
-            // released buffers cached for reuse hold device memory too: past the budget they go back
-            // to the driver, so the runtime's own allocations at launch (kernel scratch) still fit
-            if (srv->committed + need + pool_cached_bytes() > srv->budget) pool_trim_cached();
+        if (request_footprint(r->grid, mixed, r->precond ? &r->pco : nullptr, R, &r->so, &resident, &build, &run) !=
+            VIE_OK)
+            resident = build = run = 0;  // arguments were checked on submit
+        const uint64_t need = run + (ent ? 0 : resident + build);
+        if (make_room(srv, need, ent)) {
+            // released buffers cached for reuse hold device memory too: past the budget the worker
+            // returns them to the driver (outside this lock), so the runtime's own allocations at
+            // launch (kernel scratch) still fit
+            b->trim = srv->committed + need + pool_cached_bytes() > srv->budget;
+            srv->n_trims += b->trim ? 1 : 0;
             commit(srv, need);
             b->reqs.clear();
             for (size_t k : idx) b->reqs.push_back(srv->queue[k]);
@@ -172,13 +180,18 @@ bool pick(vie_server srv, Batch *b) {
             b->n_total = (int)idx.size();
             for (size_t k = idx.size(); k-- > 0;) srv->queue.erase(srv->queue.begin() + (long)idx[k]);
             for (size_t k = 0; k < qi; ++k) srv->queue[k]->overtaken++;
-            b->entry = idle;
-            if (idle) {
-                idle->in_use = true;
-                idle->bytes = std::max(idle->bytes, resident);
+            b->build = ent == nullptr;
+            if (!ent) {  // listed now, so requests for it wait for this build instead of repeating it
+                ent = new Entry();
+                ent->key = r->key;
+                ent->bytes = resident;
+                srv->cache.push_back(ent);
             }
+            if (ent->users > 0) srv->n_shared++;
+            ent->users++;
+            b->entry = ent;
             b->R = R;
-            b->resident = resident;
+            b->build_bytes = b->build ? build : 0;
             b->run = run;
             return true;
         }
@@ -192,7 +205,7 @@ bool pick(vie_server srv, Batch *b) {
 void complete_locked(vie_server srv, Req *r, Batch *b, vie_status st, const std::string &err) {
     b->reqs.erase(std::remove(b->reqs.begin(), b->reqs.end(), r), b->reqs.end());
     r->t_end = Clock::now();
-    r->cache_hit = (b->entry != nullptr) || r->joined;
+    r->cache_hit = !b->build || r->joined;
     r->merged = b->n_total;
     if (st < 0) {
         r->status = st;
@@ -286,21 +299,55 @@ struct SlotHook : SolveHook {
 // Build (or take from the cache) the operator and preconditioner and solve the merged
 // right-hand sides as slots of one batched GMRES (SlotHook completes the requests and takes
 // joiners).  Runs without the lock.
-vie_status run_batch(vie_server srv, Batch *b, hipStream_t s, vie_op *op_out, vie_pc *pc_out) {
+// Build the entry's operator and preconditioner (the admitting worker, without the lock), then
+// publish them; on failure the entry leaves the cache.
+vie_status build_entry(vie_server srv, Batch *b, hipStream_t s) {
+    Req *r0 = b->reqs[0];
+    vie_op op = nullptr;
+    vie_pc pc = nullptr;
+    vie_create_opts co{};
+    co.build_c64 = r0->so.mode == VIE_MODE_MIXED;
+    vie_status st = vie_create(r0->grid, r0->delta, r0->kb, r0->chi.data(), &co, s, &op);
+    if (st >= 0 && r0->precond) st = precond_setup(op, &r0->pco, s, &pc);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->committed -= b->build_bytes;  // the build's transient bytes are released
+    b->build_bytes = 0;
+    Entry *e = b->entry;
+    if (st < 0) {
+        if (pc) precond_destroy(pc);
+        if (op) vie_destroy(op);
+        srv->cache.remove(e);
+        srv->committed -= e->bytes;
+        delete e;
+        b->entry = nullptr;
+    } else {
+        e->op = op;
+        e->pc = pc;
+        e->ready = true;
+    }
+    srv->cv_work.notify_all();  // requests waiting for this entry
+    return st;
+}
+
+vie_status run_batch(vie_server srv, Batch *b, hipStream_t s) {
     StreamScope scope(s);  // the batch's buffers are reused once this worker's stream is past them
     Req *r0 = b->reqs[0];
     const long long N = (long long)r0->grid[0] * r0->grid[1] * r0->grid[2];
     const long long n3 = 3 * N;
-    vie_op op = b->entry ? b->entry->op : nullptr;
-    vie_pc pc = b->entry ? b->entry->pc : nullptr;
-    if (!op) {
-        vie_create_opts co{};
-        co.build_c64 = r0->so.mode == VIE_MODE_MIXED;
-        VIE_CHECK(vie_create(r0->grid, r0->delta, r0->kb, r0->chi.data(), &co, s, &op));
-        *op_out = op;
-        if (r0->precond) VIE_CHECK(precond_setup(op, &r0->pco, s, &pc));
-        *pc_out = pc;
-    }
+    if (b->build) VIE_CHECK(build_entry(srv, b, s));
+    vie_op op = b->entry->op;
+    vie_pc pc = b->entry->pc;
+    // this stream's scratch of the shared handles goes back to the cache of released blocks when
+    // the solve ends (it is part of the solve's accounted bytes, not the entry's)
+    struct WsDrop {
+        vie_op op;
+        vie_pc pc;
+        hipStream_t s;
+        ~WsDrop() {
+            op_drop_ws(op, s);
+            pc_drop_ws(pc, s);
+        }
+    } ws_drop{op, pc, s};
     DevBuf e, bb, x;
     VIE_CHECK(e.ensure(sizeof(c128) * n3 * b->R));
     VIE_CHECK(bb.ensure(sizeof(c128) * n3 * b->R));
@@ -353,31 +400,24 @@ void worker(vie_server srv) {
         const Clock::time_point t0 = Clock::now();
         for (Req *r : b.reqs) r->t_start = t0;
         const size_t n_admitted = b.reqs.size();  // later joiners are counted when they join
-        vie_op op = nullptr;
-        vie_pc pc = nullptr;
-        vie_status st = have_stream ? run_batch(srv, &b, s, &op, &pc) : VIE_EDEVICE;
+        if (b.trim) pool_trim_cached();
+        vie_status st = have_stream ? run_batch(srv, &b, s) : VIE_EDEVICE;
         if (!have_stream) vie_set_error("vie_server: hipStreamCreate failed");
         const std::string err = st < 0 ? std::string(vie_last_error()) : std::string();
         lk.lock();
         srv->running--;
         srv->committed -= b.run;
         srv->n_solves++;
+        if (b.entry && !b.entry->ready) {  // admitted to build it but never ran (no stream)
+            srv->committed -= b.build_bytes + b.entry->bytes;
+            srv->cache.remove(b.entry);
+            delete b.entry;
+            b.entry = nullptr;
+        }
         if (b.entry) {
-            b.entry->in_use = false;
+            b.entry->users--;
             b.entry->last = ++srv->tick;
-            srv->n_hits += (int64_t)n_admitted;
-        } else if (st >= 0) {
-            Entry *ne = new Entry();
-            ne->key = b.key;
-            ne->op = op;
-            ne->pc = pc;
-            ne->bytes = b.resident;
-            ne->last = ++srv->tick;
-            srv->cache.push_back(ne);
-        } else {
-            srv->committed -= b.resident;
-            if (pc) precond_destroy(pc);
-            if (op) vie_destroy(op);
+            if (!b.build) srv->n_hits += (int64_t)n_admitted;
         }
         const std::vector<Req *> left = b.reqs;  // finished at the last boundary, or the solve failed
         for (Req *r : left) {
@@ -484,16 +524,21 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
     r->so = req->solve;
     r->x_out = x_out;
     r->st_out = stats_out;
-    uint64_t resident = 0, run = 0;
+    const vie_status vs = solve_opts_check("vie_server_submit", r->so);
+    if (vs < 0) {
+        delete r;
+        return vs;
+    }
+    uint64_t resident = 0, build = 0, run = 0;
     const vie_status fs = request_footprint(r->grid, r->so.mode == VIE_MODE_MIXED, r->precond ? &r->pco : nullptr,
-                                            r->nrhs, &r->so, &resident, &run);
+                                            r->nrhs, &r->so, &resident, &build, &run);
     if (fs < 0) {
         delete r;
         return fs;
     }
-    if (resident + run > srv->budget) {
+    if (resident + build + run > srv->budget) {
         delete r;
-        vie_set_error("vie_server_submit: the request needs " + std::to_string(resident + run) +
+        vie_set_error("vie_server_submit: the request needs " + std::to_string(resident + build + run) +
                       " device bytes, above the budget of " + std::to_string(srv->budget));
         return VIE_EBUDGET;
     }
@@ -590,6 +635,8 @@ extern "C" vie_status vie_server_info_get(vie_server srv, vie_server_info *info)
     info->committed_bytes = srv->committed;
     info->peak_committed_bytes = srv->peak;
     info->budget_bytes = srv->budget;
+    info->shared_runs = srv->n_shared;
+    info->cache_trims = srv->n_trims;
     return VIE_OK;
 }
 

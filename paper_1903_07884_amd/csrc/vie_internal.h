@@ -5,7 +5,10 @@
 #include <stdint.h>
 
 #include <functional>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/vie.h"
@@ -173,6 +176,68 @@ bool fft_supported_length(int L);  // every prime factor <= VIE_FFT_MAX_PRIME
 int fft_good_length(int minL);     // smallest 2^a 3^b 5^c >= minL
 
 // ---------------------------------------------------------------- handles
+// A handle is read-only once built, so calls on different streams may share it.  What a call
+// writes (intermediate spectra, schedules, flags, tuned launch parameters) lives in a workspace
+// per (handle, stream): created on the stream's first call, kept until the handle is destroyed.
+// Calls on one stream hold its workspace's lock, so host threads sharing a stream take turns
+// (as the stream itself orders their work).
+template <class W>
+struct WsTable {
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, std::unique_ptr<W>>> v;
+    W *get(hipStream_t s) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &e : v)
+            if (e.first == s) return e.second.get();
+        v.emplace_back(s, std::unique_ptr<W>(new W()));
+        return v.back().second.get();
+    }
+    // Return stream s's scratch (its buffers go back to the cache of released blocks, reusable
+    // once the work queued on s so far is done).  No call may be using it on s.
+    void drop(hipStream_t s) {
+        std::unique_ptr<W> gone;
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i].first == s) {
+                gone = std::move(v[i].second);
+                v.erase(v.begin() + (long)i);
+                break;
+            }
+    }
+};
+
+// Operator product scratch of one stream.
+struct OpWs {
+    std::mutex mu;
+    DevBuf ybuf;             // split plane pass: y-spectra and coupled y-spectra, 2 x nrhs*Px*3nz*Py
+    DevBuf work;             // x-spectra, nrhs*3*ny*nz*Px complex
+    // FFT launch parameters per vector precision (0 = default; autotuned for tuned_nrhs)
+    int cfg_plane_thr[2] = {0, 0}, cfg_x_thr[2] = {0, 0}, tuned_nrhs[2] = {-1, -1};
+};
+
+// Preconditioner apply scratch of one stream.
+struct PcWs {
+    std::mutex mu;
+    DevBuf work;             // apply intermediate: nrhs * nboxes * m * modes complex (vector prec)
+    DevBuf workc;            // x-DFT of the identity rows, nrhs * nboxes * (m_full - m) * bx
+    DevBuf cflag;            // int32: epoch of the last apply whose identity rows held input
+    uint32_t epoch = 0;
+    DevBuf work1;            // 2-level: x-DFT lines of the full cross-section before the y-DFT
+    // block-solve schedule for sched_nrhs right-hand sides
+    int sched_nrhs = 0, n_wide = 0, n_narrow = 0, wide_ct = 1, narrow_rc = 1;
+    DevBuf sched;            // int4 wide items [n_wide], then int4 narrow items of narrow_rc columns
+                             // (m <= 64: of 64/m columns)
+    DevBuf wide_scratch;     // wide-solve tiles: n_wide * m * 16*wide_ct complex
+    DevBuf wide_scratch2;    // second solve of a refined apply
+    DevBuf wide_bf16;        // bfloat16 hi + lo split of the solved rows (BF16 factors)
+    // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)
+    int cfg_gmax = 0;        // widest column group of the wide solve (0: widest giving >= 512 groups)
+    int cfg_nw = 0;          // wavefronts per wide workgroup (0: 16 for FP32, 8 for FP64)
+    int cfg_rc = 0;          // columns per narrow workgroup (0: register-budget rule)
+    int cfg_min_rhs = 8;     // blocks go wide from this many right-hand sides on
+    int tuned_nrhs = -1;
+};
+
 struct vie_op_s {
     int nx, ny, nz;
     long long N;             // nx*ny*nz
@@ -187,12 +252,9 @@ struct vie_op_s {
     bool direct_z = false;   // kernel transform along x, y only; z handled as a direct Toeplitz sum
     bool split_plane = false; // direct z, but the (y, z) plane exceeds one workgroup's LDS: the plane
                              // pass runs as y-FFT, z coupling and inverse y-FFT through ybuf
-    DevBuf ybuf;             // split plane pass: y-spectra and coupled y-spectra, 2 x nrhs*Px*3nz*Py
-    DevBuf work;             // matvec intermediate, nrhs*3*ny*nz*Px complex
-    // FFT launch parameters per vector precision (0 = default; autotuned for tuned_nrhs)
-    int cfg_plane_thr[2] = {0, 0}, cfg_x_thr[2] = {0, 0}, tuned_nrhs[2] = {-1, -1};
     FftCache fft;
     FftPlan px, py, pz;      // plans for the three periods
+    WsTable<OpWs> ws;        // product scratch per stream
 };
 
 // Flags on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is a
@@ -225,18 +287,13 @@ struct vie_pc_s {
     DevBuf factors;          // [nstored][m][m] column-major LU (complex, factor precision)
     DevBuf perm;             // int32 [nstored][m] row permutation: (P r)[i] = r[perm[i]]
     DevBuf info;             // int32 [nstored] 0 or first zero-pivot column + 1
-    DevBuf work;             // apply scratch: nrhs * nboxes * m * bx complex (vector prec)
     // Cross-section rows in solve order: rows[0..m) have M~ != 0 in some box (factorised),
     // rows[m..m_full) are identity rows of every D_k.  Entry = a*by*bz + z*by + y.
     DevBuf rows;             // int32 [m_full]
     std::vector<int> rows_host;
-    DevBuf workc;            // x-DFT of the identity rows, nrhs * nboxes * (m_full - m) * bx
-    DevBuf cflag;            // int32: epoch of the last apply whose identity rows held input
-    uint32_t epoch = 0;
     DevBuf chan64, mt64;     // FP64 C^_k table / M~ for the coupling of an FP64 apply
-    // 2-level: x-DFT lines of the full cross-section [R][box][3*by*bz][bx] before the y-DFT,
-    // and the identity map of those lines
-    DevBuf work1, rows1;
+    // 2-level: the identity map of the x-DFT lines of the full cross-section
+    DevBuf rows1;
     FftPlan pyb2;            // length by (the y-DFT of the 2-level circulant)
     FftPlan pxb;             // length bx
     // block-solve schedule
@@ -244,25 +301,13 @@ struct vie_pc_s {
     int mirror_rows = 0;                   // block rows per component (m/3): x rows first, then y
     std::vector<int> block_box;            // box of stored block s
     DevBuf modes_dev;                      // int32 mode_ptr [nstored+1] then mode_list
-    int sched_nrhs = 0;                    // nrhs the tables below were built for
-    int n_wide = 0, n_narrow = 0, wide_ct = 1, narrow_rc = 1;
-    DevBuf sched;                          // int4 wide items [n_wide], then int4 narrow items of
-                                           // narrow_rc columns (m <= 64: of 64/m columns)
-    DevBuf wide_scratch;                   // wide-solve tiles: n_wide * m * 16*wide_ct complex
-    DevBuf wide_scratch2;                  // second solve of a refined apply
-    DevBuf wide_bf16;                      // bfloat16 hi + lo split of the solved rows (BF16 factors)
     // refinement of VIE_BF16C solves
     int refine = 0;
     DevBuf chan32;                         // complex float C^_k tables [n][6][2bz-1][2by-1] per box length
                                            // (refinement, and the coupling of an FP32 apply)
     DevBuf mt32;                           // complex float M~ [nboxes][bz][by]
     DevBuf smode_dev;                      // int32 [nstored] mode of each stored block
-    // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)
-    int cfg_gmax = 0;        // widest column group of the wide solve (0: widest giving >= 512 groups)
-    int cfg_nw = 0;          // wavefronts per wide workgroup (0: 16 for FP32, 8 for FP64)
-    int cfg_rc = 0;          // columns per narrow workgroup (0: register-budget rule)
-    int cfg_min_rhs = 8;     // blocks go wide from this many right-hand sides on
-    int tuned_nrhs = -1;
+    WsTable<PcWs> ws;                      // apply scratch per stream
 };
 
 // ---------------------------------------------------------------- profiling
@@ -303,13 +348,22 @@ vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
 vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s);
 // precond.hip
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
+// Drop the per-stream scratch of an operator / a preconditioner (and its box groups) for s.
+void op_drop_ws(vie_op op, hipStream_t s);
+void pc_drop_ws(vie_pc pc, hipStream_t s);
 // api.cpp: device bytes of a request before its operator exists: what a cached operator +
-// preconditioner keep (resident) and what one solve of nrhs right-hand sides adds (run)
+// preconditioner keep (resident), what building them needs on top while it runs (build), and
+// what one solve of nrhs right-hand sides adds (run: Krylov workspace, the product's and the
+// apply's per-stream scratch, incident fields and right-hand sides)
 vie_status request_footprint(const int32_t grid[3], bool c64, const vie_pc_opts *pco, int32_t nrhs,
-                             const vie_solve_opts *so, uint64_t *resident, uint64_t *run);
+                             const vie_solve_opts *so, uint64_t *resident, uint64_t *build, uint64_t *run);
+// Largest GMRES restart length (the Givens kernel sizes its LDS by it).
+#define VIE_MAX_RESTART 200
+// Checks of the solver settings shared by vie_solve and the server's submit (`who` names the call).
+vie_status solve_opts_check(const char *who, const vie_solve_opts &o);
 vie_status pc_apply(vie_pc pc, const void *r, void *z, int nrhs, int prec, hipStream_t s);
 // block_solve.hip: the per-mode block solves, in place in the apply work buffer
-vie_status launch_block_solve(vie_pc pc, void *work, int nrhs, hipStream_t s);
+vie_status launch_block_solve(vie_pc pc, PcWs *w, void *work, int nrhs, hipStream_t s);
 // krylov.hip
 // complex partial sums per right-hand side kept by the Arnoldi reductions (vector length n)
 long long arnoldi_partials(long long n, int restart);

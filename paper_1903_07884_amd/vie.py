@@ -77,7 +77,8 @@ class ServerInfo(ctypes.Structure):
     _fields_ = [('submitted', ctypes.c_int64), ('completed', ctypes.c_int64), ('solves', ctypes.c_int64),
                 ('cache_hits', ctypes.c_int64), ('evictions', ctypes.c_int64), ('cached_entries', ctypes.c_int32),
                 ('queued', ctypes.c_int32), ('running', ctypes.c_int32), ('committed_bytes', ctypes.c_uint64),
-                ('peak_committed_bytes', ctypes.c_uint64), ('budget_bytes', ctypes.c_uint64)]
+                ('peak_committed_bytes', ctypes.c_uint64), ('budget_bytes', ctypes.c_uint64),
+                ('shared_runs', ctypes.c_int64), ('cache_trims', ctypes.c_int64)]
 
 
 class SolveStats(ctypes.Structure):
@@ -382,21 +383,38 @@ class Server:
 
     def submit(self, grid, voxel_size, k_background, chi, e_inc, precond=True, homog='none', boxes=None,
                reduce_tol=None, factor_prec=VIE_C128, refine=None, keep_zero_rows=False, tol=1e-6, restart=50,
-               maxit=5000, mode='fp64'):
+               maxit=5000, mode='fp64', levels=1, proxy='product', share_tol=0.0, mirror=True):
         """Queue one request; ``chi`` [nz, ny, nx] and ``e_inc`` [nrhs, 3, nz, ny, nx] are host
-        arrays (copied).  Returns the request id; ``wait(id)`` returns (x, stats, times)."""
+        arrays (copied).  The preconditioner options are those of ``Preconditioner`` (``homog``
+        and ``levels`` may be lists with one entry per box).  Returns the request id;
+        ``wait(id)`` returns (x, stats, times)."""
         nx, ny, nz = (int(v) for v in grid)
         chi = np.ascontiguousarray(np.asarray(chi, dtype=np.complex128).reshape(nz, ny, nx))
         e = np.ascontiguousarray(np.asarray(e_inc, dtype=np.complex128).reshape(-1, 3 * nx * ny * nz))
         nrhs = e.shape[0]
         if refine is None:
             refine = 1 if factor_prec == VIE_BF16C else 0
-        pc = PcOpts(HOMOG[homog], 0, None, 0, 0.0, factor_prec, 0, int(refine), 1 if keep_zero_rows else 0)
+        per_box_h = isinstance(homog, (list, tuple))
+        per_box_l = isinstance(levels, (list, tuple))
+        pc = PcOpts(0 if per_box_h else HOMOG[homog], 0, None, 0, 0.0, factor_prec,
+                    {'product': 0, 'centre': 1}[proxy], int(refine), 1 if keep_zero_rows else 0,
+                    0 if per_box_l else int(levels))
+        pc.share_tol = float(share_tol)
+        pc.no_mirror = 0 if mirror else 1
+        keep = []
         bx = None
         if boxes is not None:
             bx = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
             pc.nboxes = bx.shape[0]
             pc.boxes = bx.ctypes.data
+        if per_box_h:
+            hb = np.ascontiguousarray([HOMOG[h] for h in homog], dtype=np.int32)
+            pc.box_homog = hb.ctypes.data
+            keep.append(hb)
+        if per_box_l:
+            lb = np.ascontiguousarray(levels, dtype=np.int32)
+            pc.box_levels = lb.ctypes.data
+            keep.append(lb)
         if reduce_tol is not None:
             pc.reduce, pc.reduce_tol = 1, float(reduce_tol)
         req = Request((ctypes.c_int32 * 3)(nx, ny, nz), float(voxel_size), float(k_background), chi.ctypes.data,

@@ -247,3 +247,87 @@ def test_continuous_batching_completes_early_and_takes_joiners(gpu_lib):
         assert _rel(x, xd.cpu().numpy()) <= 1e-12
         assert _oracle_relres(dev, x, e)[0] <= 1e-10 * 1.01
     assert info['solves'] == 2  # the busy solve and the (a, b) solve, which c joined
+
+
+def test_concurrent_solves_share_one_cached_entry(gpu_lib):
+    """Requests of one device with different solver settings (so they are neither merged nor
+    joined) run at the same time on several workers: they share one cached operator and
+    preconditioner (built once), each stream with its own scratch, and every result equals the
+    plain library solve of its request and passes the oracle's residual check."""
+    import torch
+    devs = _devices()
+    dev = dict(devs['guide'])
+    dev['grid'] = (96, 8, 4)
+    dev['chi'] = W.waveguide((96, 8, 4))
+    srv = gpu_lib.Server(workers=4, max_batch_rhs=64)
+    tols = [1e-10, 1e-11, 2e-11, 5e-11, 1e-10 * 0.7, 3e-11]
+    es = [_e(dev, 2, 70 + k) for k in range(len(tols))]
+    rids = [srv.submit(e_inc=e, tol=t, **dev) for e, t in zip(es, tols)]
+    out = [srv.wait(r) for r in rids]
+    info = srv.info()
+    srv.close()
+    print('shared entry: %s' % info)
+    assert info['cached_entries'] == 1 and info['evictions'] == 0
+    assert info['shared_runs'] >= 1
+    op = gpu_lib.Operator(dev['grid'], dev['voxel_size'], dev['k_background'], dev['chi'])
+    pc = gpu_lib.Preconditioner(op)
+    for (x, st, _), e, t in zip(out, es, tols):
+        ed = torch.from_numpy(e).cuda()
+        b = torch.empty_like(ed)
+        op.rhs(ed, b, nrhs=2)
+        xd = torch.zeros_like(b)
+        ref = gpu_lib.solve(op, pc, b, xd, nrhs=2, tol=t)
+        assert [q['iters'] for q in st] == [q['iters'] for q in ref]
+        assert _rel(x, xd.cpu().numpy()) <= 1e-12
+        assert np.all(_oracle_relres(dev, x, e) <= t * 1.01)
+
+
+def test_admission_returns_cached_blocks_past_the_budget(gpu_lib):
+    """With a budget just above one request's footprint, admitting the second device evicts the
+    first and, since the blocks the first solve released are still cached for reuse, returns
+    them to the driver before building (regression: the cache once filled the device)."""
+    import ctypes
+    lib = gpu_lib.load()
+    g = _devices()['guide']
+    pc = gpu_lib.PcOpts(0, 0, None, 0, 0.0, 0, 0, 0, 0)
+    so = gpu_lib.SolveOpts(1e-10, 50, 5000, 0, 0)
+    op = gpu_lib.Operator(g['grid'], g['voxel_size'], g['k_background'], g['chi'])
+    need = ctypes.c_uint64()
+    assert lib.vie_footprint(op.h, ctypes.byref(pc), 1, ctypes.byref(so), ctypes.byref(need)) == 0
+    op.close()
+    budget = int(need.value) + (1 << 20)
+    srv = gpu_lib.Server(workers=1, hbm_budget=budget)
+    devs = []
+    for k in range(2):
+        d = dict(g)
+        d['chi'] = g['chi'] * (1.0 + 0.2 * k)
+        devs.append(d)
+    out = []
+    for k, d in enumerate(devs):  # one after the other: the first solve's blocks are cached
+        out.append(srv.wait(srv.submit(e_inc=_e(d, 1, 90 + k), tol=1e-10, **d)))
+    info = srv.info()
+    srv.close()
+    print('budget %d, one request %d: %s' % (budget, need.value, info))
+    assert info['cache_trims'] >= 1 and info['evictions'] >= 1
+    assert info['peak_committed_bytes'] <= budget
+    for k, (d, (x, st, _)) in enumerate(zip(devs, out)):
+        assert st[0]['status'] == 0
+        assert _oracle_relres(d, x, _e(d, 1, 90 + k))[0] <= 1e-10 * 1.01
+
+
+def test_submit_rejects_bad_solver_settings(gpu_lib):
+    """Solver settings are validated on submit, as vie_solve does (unknown mode, tol, maxit)."""
+    g = _devices()['guide']
+    srv = gpu_lib.Server(workers=1)
+    for kw in (dict(tol=0.0), dict(tol=float('nan')), dict(maxit=0), dict(restart=201)):
+        with pytest.raises(gpu_lib.VieError) as ei:
+            srv.submit(e_inc=_e(g, 1, 1), **kw, **g)
+        assert ei.value.status == -1
+    gpu_lib.MODE['bogus'] = 7
+    try:
+        with pytest.raises(gpu_lib.VieError) as ei:
+            srv.submit(e_inc=_e(g, 1, 1), mode='bogus', **{k: v for k, v in g.items() if k != 'mode'})
+        assert ei.value.status == -1
+    finally:
+        del gpu_lib.MODE['bogus']
+    srv.close()
