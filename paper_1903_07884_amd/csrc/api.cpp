@@ -97,9 +97,21 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
         int thr, bpt;
         size_t lds;
         fft_line_shape(op->px, sizeof(c128), &thr, &lds, &bpt);
-        if (lds > max_lds())
-            return fail(arg_error("vie_create: x extent too long for the LDS line transform (padded length " +
-                                  std::to_string(op->Px) + ")"));
+        if (lds > max_lds()) {
+            // four-step: Px = L1 L2 with L2 the largest divisor <= sqrt(Px) that leaves L1 a
+            // multiple of the column tile (16) and both factors within one workgroup's LDS
+            int L2 = 0;
+            for (int d = 1; (long long)d * d <= op->Px; ++d)
+                if (op->Px % d == 0 && (op->Px / d) % 16 == 0) L2 = d;
+            if (L2 < 2 || L2 > 512 || sizeof(c128) * (size_t)L2 * 16 > max_lds())
+                return fail(arg_error("vie_create: no four-step split of the x period " + std::to_string(op->Px)));
+            op->xsplit = L2;
+            if ((st = op->fft.get(op->Px / L2, &op->px1)) < 0) return fail(st);
+            if ((st = op->fft.get(L2, &op->px2)) < 0) return fail(st);
+            fft_line_shape(op->px1, sizeof(c128), &thr, &lds, &bpt);
+            if (lds > max_lds())
+                return fail(arg_error("vie_create: x period " + std::to_string(op->Px) + " too long"));
+        }
     }
     if ((st = op->M64.ensure(sizeof(c128) * N)) < 0) return fail(st);
     if ((st = op->M32.ensure(sizeof(c64) * N)) < 0) return fail(st);

@@ -14,11 +14,11 @@ template <class R>
 struct TwTable;
 template <>
 struct TwTable<double> {
-    static __device__ __forceinline__ const c128 *get(const FftPlan &p) { return p.tw64; }
+    static __host__ __device__ __forceinline__ const c128 *get(const FftPlan &p) { return p.tw64; }
 };
 template <>
 struct TwTable<float> {
-    static __device__ __forceinline__ const c64 *get(const FftPlan &p) { return p.tw32; }
+    static __host__ __device__ __forceinline__ const c64 *get(const FftPlan &p) { return p.tw32; }
 };
 
 // Lines addressed inside LDS: line l starts at (l % nl1) * s1 + (l / nl1) * s2,

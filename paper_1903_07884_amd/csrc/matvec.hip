@@ -18,6 +18,15 @@
 #include <string>
 
 #include "fft_device.h"
+#include "reg_fft.h"
+
+// Position of x-frequency kx in its line of the x-spectra: natural order, or, for lines that
+// take the four-step transform (xsplit = L2 > 1), (kx mod L2) (Px / L2) + kx / L2.
+__host__ __device__ __forceinline__ int xpos(int kx, int Px, int xsplit) {
+    if (xsplit <= 1) return kx;
+    const int k1 = kx / xsplit;
+    return (kx - k1 * xsplit) * (Px / xsplit) + k1;
+}
 
 template <class R>
 __global__ void k_contrast(const c128 *chi, cpx<R> *M, long long N) {
@@ -109,7 +118,7 @@ __global__ void k_fft_lines(cpx<R> *data, long long nl1, long long s1, long long
 
 // Octant extraction: khat[kx][kz][ky][c] = E[c][kz][ky][kx] / (Px Py Pz)
 __global__ void k_extract(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, int Pz, int Hx, int Hy,
-                          int Hz) {
+                          int Hz, int xsplit) {
     long long total = (long long)Hx * Hy * Hz * 6;
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -120,7 +129,7 @@ __global__ void k_extract(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, in
     int kz = (int)(r % Hz);
     int kx = (int)(r / Hz);
     double sc = 1.0 / ((double)Px * Py * Pz);
-    c128 v = E[(long long)c * Px * Py * Pz + ((long long)kz * Py + ky) * Px + kx];
+    c128 v = E[(long long)c * Px * Py * Pz + ((long long)kz * Py + ky) * Px + xpos(kx, Px, xsplit)];
     v = mk(v.re * sc, v.im * sc);
     k64[i] = v;
     if (k32) k32[i] = mk((float)v.re, (float)v.im);
@@ -128,7 +137,8 @@ __global__ void k_extract(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, in
 
 // (x, y)-transformed generator for the direct z sum, octant in (kx, ky), real-space z offsets
 // dz in [0, nz): khat[kx][ky][dz][c] = E[c][dz][ky][kx] / (Px Py)
-__global__ void k_extract_xy(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, int Pz, int Hx, int Hy, int nz) {
+__global__ void k_extract_xy(const c128 *E, c128 *k64, c64 *k32, int Px, int Py, int Pz, int Hx, int Hy, int nz,
+                             int xsplit) {
     long long total = (long long)Hx * Hy * nz * 6;
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -139,10 +149,149 @@ __global__ void k_extract_xy(const c128 *E, c128 *k64, c64 *k32, int Px, int Py,
     int ky = (int)(r % Hy);
     int kx = (int)(r / Hy);
     double sc = 1.0 / ((double)Px * Py);
-    c128 v = E[(long long)c * Px * Py * Pz + ((long long)dz * Py + ky) * Px + kx];
+    c128 v = E[(long long)c * Px * Py * Pz + ((long long)dz * Py + ky) * Px + xpos(kx, Px, xsplit)];
     v = mk(v.re * sc, v.im * sc);
     k64[i] = v;
     if (k32) k32[i] = mk((float)v.re, (float)v.im);
+}
+
+// ---------------------------------------------------------------- lines longer than one workgroup's LDS
+// Four-step transform of length L = L1 L2 (n = n1 + L1 n2, k = k2 + L2 k1), through the line's own
+// storage in device memory:
+//   columns: for every n1, the length-L2 DFT over n2, times W_L^{n1 k2}  -> [k2][n1]
+//   rows:    for every k2, the length-L1 DFT over n1                     -> [k2][k1]
+// so frequency k is left at position (k mod L2) L1 + k / L2 of its line (xpos).  The inverse runs
+// the rows, then the columns with the conjugate twiddle, back to natural order.  A workgroup takes
+// a tile of LT consecutive columns (rows of LT elements are contiguous, so loads and stores move
+// LT-element segments) or one whole row.
+#define LONG_LT 16
+
+// columns forward: src line (zero beyond nx when the source is a vector of x-lines of length nx,
+// src_len = nx; src_len = L for a line of the work buffer), dst = work line.
+template <class R, int BPT>
+__global__ void k_long_cols(const cpx<R> *src, int src_len, cpx<R> *dst, int L, int L1, FftPlan p2,
+                            const cpx<R> *twL, int inv) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    const int L2 = p2.L, ntile = L1 / LONG_LT;
+    const long long line = blockIdx.x / ntile;
+    const int c0 = (blockIdx.x - (int)(line * ntile)) * LONG_LT;
+    const cpx<R> *s = src + line * (long long)src_len;
+    for (int i = threadIdx.x; i < L2 * LONG_LT; i += blockDim.x) {
+        const int n2 = i / LONG_LT, j = i - n2 * LONG_LT;
+        const int n = c0 + j + L1 * n2;
+        a[i] = n < src_len ? s[n] : czero<R>();
+    }
+    __syncthreads();
+    const LdsLines ln = {LONG_LT, 1, 0, LONG_LT, LONG_LT};
+    cpx<R> *res = a;
+    if (BPT > 0) fft_lds_inplace<R, (BPT > 0 ? BPT : 1)>(a, ln, p2, inv != 0);
+    else res = fft_lds<R>(a, a + L2 * LONG_LT, ln, p2, inv != 0);
+    cpx<R> *d = dst + line * (long long)L;
+    for (int i = threadIdx.x; i < L2 * LONG_LT; i += blockDim.x) {
+        const int k2 = i / LONG_LT, j = i - k2 * LONG_LT;
+        const int q = (int)(((long long)(c0 + j) * k2) % L);
+        cpx<R> v = res[i];
+        if (q) v = v * tw_at(twL, q, inv != 0);
+        d[(long long)k2 * L1 + c0 + j] = v;
+    }
+}
+
+// rows, in place on the work buffer: one workgroup per (line, row)
+template <class R, int BPT>
+__global__ void k_long_rows(cpx<R> *work, int L, FftPlan p1, int inv) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    const int L1 = p1.L, L2 = L / L1;
+    const long long line = blockIdx.x / L2;
+    const int k2 = blockIdx.x - (int)(line * L2);
+    cpx<R> *row = work + line * (long long)L + (long long)k2 * L1;
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) a[i] = row[i];
+    __syncthreads();
+    cpx<R> *res = fft_line<R, BPT>(a, p1, inv != 0);
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) row[i] = res[i];
+}
+
+// columns inverse: conjugate twiddle, inverse length-L2 DFT over k2, and the line's first nx
+// entries written as y = x - M (x + (K x)) (cropped product, eq. discrete_form)
+template <class R, int BPT>
+__global__ void k_long_cols_inv(const cpx<R> *work, int L, int L1, FftPlan p2, const cpx<R> *twL, const cpx<R> *x,
+                                const cpx<R> *M, cpx<R> *y, int nx, int nyz) {
+    cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
+    const int L2 = p2.L, ntile = L1 / LONG_LT;
+    const long long line = blockIdx.x / ntile;
+    const int c0 = (blockIdx.x - (int)(line * ntile)) * LONG_LT;
+    const cpx<R> *w = work + line * (long long)L;
+    for (int i = threadIdx.x; i < L2 * LONG_LT; i += blockDim.x) {
+        const int k2 = i / LONG_LT, j = i - k2 * LONG_LT;
+        const int q = (int)(((long long)(c0 + j) * k2) % L);
+        cpx<R> v = w[(long long)k2 * L1 + c0 + j];
+        a[i] = q ? v * tw_at(twL, q, true) : v;
+    }
+    __syncthreads();
+    const LdsLines ln = {LONG_LT, 1, 0, LONG_LT, LONG_LT};
+    cpx<R> *res = a;
+    if (BPT > 0) fft_lds_inplace<R, (BPT > 0 ? BPT : 1)>(a, ln, p2, true);
+    else res = fft_lds<R>(a, a + L2 * LONG_LT, ln, p2, true);
+    const long long yz = line % nyz;
+    const cpx<R> *xl = x + line * (long long)nx;
+    const cpx<R> *ml = M + yz * nx;
+    cpx<R> *yl = y + line * (long long)nx;
+    for (int i = threadIdx.x; i < L2 * LONG_LT; i += blockDim.x) {
+        const int n2 = i / LONG_LT, j = i - n2 * LONG_LT;
+        const int n = c0 + j + L1 * n2;
+        if (n < nx) {
+            const cpx<R> xv = xl[n];
+            yl[n] = xv - ml[n] * (xv + res[i]);
+        }
+    }
+}
+
+// Launch shape of the column kernels: LONG_LT lines of length L2 in LDS, ping-pong when both
+// buffers fit in FFT_PINGPONG_LDS bytes, else in place with up to 4 butterflies per thread
+// (threads enough for the radix-2 stages: (L2 / 2) LONG_LT <= 4 threads).
+static void long_cols_shape(const FftPlan &p2, size_t esz, int *thr, size_t *lds, int *bpt) {
+    *lds = 2 * esz * (size_t)p2.L * LONG_LT;
+    *bpt = *lds > FFT_PINGPONG_LDS && fft_plan_inplace(p2) ? 4 : 0;
+    if (*bpt) *lds /= 2;
+    const int need = (p2.L / 2 * LONG_LT + 3) / 4;
+    *thr = 256;
+    while (*thr < need && *thr < 1024) *thr *= 2;
+}
+
+// Forward four-step transform of `lines` lines of length Px: columns (reading src, lines of
+// src_len entries, zero beyond), then rows in place in dst.  inverse = true runs the rows only
+// (the inverse columns are fused with the product's final combination, k_long_cols_inv).
+template <class R>
+static vie_status long_lines(vie_op op, const cpx<R> *src, int src_len, cpx<R> *dst, long long lines, bool inverse,
+                             hipStream_t s) {
+    const int L = op->Px, L1 = op->px1.L;
+    const int ntile = L1 / LONG_LT;
+    if (!inverse) {
+        size_t lds;
+        int thr, bpt;
+        long_cols_shape(op->px2, sizeof(cpx<R>), &thr, &lds, &bpt);
+#define LAUNCH_COLS(B)                                                                                         \
+    vie_lds_attr((const void *)k_long_cols<R, B>, lds);                                                        \
+    hipLaunchKernelGGL((k_long_cols<R, B>), dim3((unsigned)(lines * ntile)), dim3(thr), lds, s, src, src_len, dst, \
+                       L, L1, op->px2, TwTable<R>::get(op->px), 0)
+        if (bpt) {
+            LAUNCH_COLS(4);
+        } else {
+            LAUNCH_COLS(0);
+        }
+#undef LAUNCH_COLS
+        VIE_HIP(hipGetLastError());
+    }
+    size_t ldsr;
+    int thr, bpt;
+    fft_line_shape(op->px1, sizeof(cpx<R>), &thr, &ldsr, &bpt);
+#define LAUNCH_ROWS(B)                                                                                        \
+    vie_lds_attr((const void *)k_long_rows<R, B>, ldsr);                                                      \
+    hipLaunchKernelGGL((k_long_rows<R, B>), dim3((unsigned)(lines * op->px2.L)), dim3(thr), ldsr, s, dst, L, op->px1, \
+                       inverse ? 1 : 0)
+    VIE_BPT_SWITCH(bpt, LAUNCH_ROWS);
+#undef LAUNCH_ROWS
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
 }
 
 static int block_for(int L) {
@@ -173,6 +322,10 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
         auto &ps = passes[pi];
         if (ps.p->L == 1) continue;
         if (pi == 2 && op->direct_z) continue;  // z offsets stay in real space
+        if (pi == 0 && op->xsplit > 1) {        // x lines longer than the LDS: four-step, in place
+            VIE_CHECK(long_lines<double>(op, E.as<c128>(), Px, E.as<c128>(), ps.nlines, false, s));
+            continue;
+        }
         size_t lds;
         int thr, bpt;
         fft_line_shape(*ps.p, sizeof(c128), &thr, &lds, &bpt);
@@ -190,11 +343,11 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
     if (op->direct_z)
         hipLaunchKernelGGL(k_extract_xy, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
                            op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
-                           op->Hx, op->Hy, op->nz);
+                           op->Hx, op->Hy, op->nz, op->xsplit);
     else
         hipLaunchKernelGGL(k_extract, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, E.as<c128>(),
                            op->khat64.as<c128>(), op->has_c64 ? op->khat32.as<c64>() : nullptr, Px, Py, Pz,
-                           op->Hx, op->Hy, op->Hz);
+                           op->Hx, op->Hy, op->Hz, op->xsplit);
     VIE_HIP(hipGetLastError());
     VIE_HIP(hipStreamSynchronize(s));
     E.release();
@@ -228,7 +381,7 @@ __device__ __forceinline__ int xcd_block(int b, int count) {
 #define PLANE_KB 1
 template <class R>
 __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hx, int Hy, int Hz,
-                        FftPlan py, FftPlan pz) {
+                        FftPlan py, FftPlan pz, int xsplit) {
     const int Py = py.L, Pz = pz.L;
     const int plane = Py * Pz;
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);
@@ -236,7 +389,7 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
     for (int kk = 0; kk < PLANE_KB; ++kk) {
     const int kx = xcd_block(blockIdx.x * PLANE_KB + kk, Px);
     if (kx >= Px) break;
-    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
+    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + xpos(kx, Px, xsplit);
     __syncthreads();
     for (int i = threadIdx.x; i < 6 * plane; i += blockDim.x) a[i] = czero<R>();
     __syncthreads();
@@ -306,7 +459,8 @@ __global__ void k_plane(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px
 // direct sum over the nz z-offsets of the (x, y)-transformed generator (its z-Toeplitz
 // structure kept in real space, parities applied per axis), inverse y-FFT, crop.
 template <class R>
-__global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hy, FftPlan py) {
+__global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int Px, int Hy, FftPlan py,
+                           int xsplit) {
     const int Py = py.L;
     const int rows = 3 * nz;
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem);  // [3][nz][Py] lines
@@ -316,7 +470,7 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
     if (kx >= Px) return;
     const int kxo = kx <= Px - kx ? kx : Px - kx;
     const bool fx = kx > Px - kx;
-    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + kx;
+    cpx<R> *base = work + (long long)blockIdx.y * 3 * ny * nz * Px + xpos(kx, Px, xsplit);
     const cpx<R> *kh = khat + (long long)kxo * Hy * nz * 6;
     const FastDiv f6nz(6 * nz), fpy(Py), fny(ny);
     for (int i = threadIdx.x; i < Hy * nz * 6; i += blockDim.x) {
@@ -371,18 +525,155 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
     }
 }
 
+// pass 2 for thin cross-sections (direct z sum) with the y period and the layer count fixed at
+// compile time: one workgroup per (x-frequency, group of right-hand sides), the group's planes
+// processed one after another with the x-frequency's transformed generator staged in LDS once.
+// The y-FFT of period PY = P1 P2 runs on registers in two steps with one LDS exchange:
+// y = n2 + P2 n1, ky = k1 + P1 k2; step 1 transforms over n1 (zero-padded rows, loaded straight
+// from the x-spectra), multiplies by W_PY^{n2 k1} and leaves [k1][n2] in LDS; step 2 transforms
+// over n2 into natural order.  The z coupling reads every (component, layer) of a y-frequency from
+// LDS; the inverse runs the two steps in reverse and stores the cropped rows.
+template <class R, int PY, int P1, int P2, int NZ>
+__global__ void __launch_bounds__(64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64))
+k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cpx<R> *__restrict__ twtab, int ny,
+            int Px, int Hy, int nrhs, int rb, int xsplit) {
+    static_assert(P1 * P2 == PY, "PY = P1 P2");
+    constexpr int L = 3 * NZ;                 // lines: (component, layer)
+    constexpr int NT = 64 * ((L * (P1 > P2 ? P1 : P2) + 63) / 64);
+    // line stride: room for the padded exchange layouts [k1][P2 + 1] and [n2][P1 + 1] (odd strides,
+    // so the transposed reads spread over the LDS banks) as well as the natural order [PY]
+    constexpr int SP = PY + (P1 > P2 ? P1 : P2);
+    cpx<R> *S = reinterpret_cast<cpx<R> *>(vie_smem);  // [L][SP] plane
+    cpx<R> *G = S + L * SP;                             // [NZ][6][Hy] transformed generator
+    cpx<R> *W = G + NZ * 6 * Hy;                        // [PY] twiddles W_PY^q
+    const int kx = xcd_block(blockIdx.x, Px);
+    if (kx >= Px) return;
+    const int kxo = kx <= Px - kx ? kx : Px - kx;
+    const R sx = kx > Px - kx ? R(-1) : R(1);
+    const int t = threadIdx.x;
+    {
+        const cpx<R> *kh = khat + (long long)kxo * Hy * NZ * 6;
+        for (int i = t; i < Hy * NZ * 6; i += NT) {
+            const int kyo = i / (6 * NZ), e = i - kyo * 6 * NZ;  // source layout [Hy][NZ][6]
+            G[e * Hy + kyo] = kh[i];                              // e = dz * 6 + c
+        }
+        for (int i = t; i < PY; i += NT) W[i] = twtab[i];
+    }
+    const int r0 = blockIdx.y * rb, r1 = min(nrhs, r0 + rb);
+    for (int rhs = r0; rhs < r1; ++rhs) {
+        cpx<R> *base = work + (long long)rhs * L * ny * Px + xpos(kx, Px, xsplit);
+        __syncthreads();  // G, W staged; the previous plane's last reads of S are done
+        // forward step 1: item (line, n2) transforms its zero-padded column over n1
+        if (t < L * P2) {
+            const int line = t / P2, n2 = t - line * P2;
+            cpx<R> v[P1];
+            rfft::sfor<P1>([&](auto ic) {
+                constexpr int n1 = decltype(ic)::value;
+                const int y = n2 + P2 * n1;
+                v[n1] = y < ny ? base[((long long)line * ny + y) * Px] : czero<R>();
+            });
+            rfft::Dft<R, P1, false>::run(v);
+            rfft::sfor<P1>([&](auto ic) {
+                constexpr int k1 = decltype(ic)::value;
+                S[line * SP + k1 * (P2 + 1) + n2] = k1 == 0 ? v[k1] : v[k1] * W[n2 * k1];
+            });
+        }
+        __syncthreads();
+        // forward step 2: item (line, k1) transforms over n2 -> ky = k1 + P1 k2
+        {
+            cpx<R> u[P2];
+            const int line = t / P1, k1 = t - line * P1;
+            const bool act = t < L * P1;
+            if (act)
+                rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 * (P2 + 1) + decltype(ic)::value]; });
+            __syncthreads();
+            if (act) {
+                rfft::Dft<R, P2, false>::run(u);
+                rfft::sfor<P2>([&](auto ic) { S[line * SP + k1 + P1 * decltype(ic)::value] = u[decltype(ic)::value]; });
+            }
+        }
+        __syncthreads();
+        // z coupling: item (c, ky) forms component c of its y-frequency at every layer z, the sum
+        // over z' and c' of the (c, c') block of the transformed generator at offset z - z' with the
+        // parity signs (xy odd in x and y, xz in x and z, yz in y and z).  The source components are
+        // taken one at a time (NZ spectra in registers); every item reads before any writes back.
+        {
+            static_assert(3 * PY <= NT, "one coupling item per thread");
+            const bool act = t < 3 * PY;
+            const int c = t / PY, ky = t - c * PY;
+            cpx<R> acc[NZ];
+            rfft::sfor<NZ>([&](auto iz) { acc[decltype(iz)::value] = czero<R>(); });
+            if (act) {
+                const int kyo = ky <= PY - ky ? ky : PY - ky;
+                const R sy = ky > PY - ky ? R(-1) : R(1);
+#pragma unroll 1
+                for (int cp = 0; cp < 3; ++cp) {
+                    cpx<R> uc[NZ];
+                    rfft::sfor<NZ>([&](auto iz) { uc[decltype(iz)::value] = S[(cp * NZ + decltype(iz)::value) * SP + ky]; });
+                    const bool off = c != cp;
+                    const int e = off ? c + cp + 2 : c;  // block index (xx yy zz xy xz yz)
+                    const R pxy = (off && (c == 0 || cp == 0) ? sx : R(1)) * (off && (c == 1 || cp == 1) ? sy : R(1));
+                    const bool zodd = off && (c == 2 || cp == 2);
+                    const cpx<R> *ge = G + e * Hy + kyo;
+                    rfft::sfor<2 * NZ - 1>([&](auto id) {
+                        constexpr int dz = decltype(id)::value - (NZ - 1);
+                        constexpr int adz = dz < 0 ? -dz : dz;
+                        const cpx<R> g = ((zodd && dz < 0) ? -pxy : pxy) * ge[adz * 6 * Hy];
+                        rfft::sfor<NZ>([&](auto iz) {
+                            constexpr int z = decltype(iz)::value, zp = z - dz;
+                            if constexpr (zp >= 0 && zp < NZ) acc[z] = acc[z] + g * uc[zp];
+                        });
+                    });
+                }
+            }
+            __syncthreads();
+            if (act) rfft::sfor<NZ>([&](auto iz) { S[(c * NZ + decltype(iz)::value) * SP + ky] = acc[decltype(iz)::value]; });
+        }
+        __syncthreads();
+        // inverse step A: item (line, k1) transforms over k2, multiplies by conj W_PY^{n2 k1}
+        {
+            cpx<R> u[P2];
+            const int line = t / P1, k1 = t - line * P1;
+            const bool act = t < L * P1;
+            if (act) rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 + P1 * decltype(ic)::value]; });
+            __syncthreads();
+            if (act) {
+                rfft::Dft<R, P2, true>::run(u);
+                rfft::sfor<P2>([&](auto ic) {
+                    constexpr int n2 = decltype(ic)::value;
+                    S[line * SP + n2 * (P1 + 1) + k1] = n2 == 0 ? u[n2] : u[n2] * conjg(W[n2 * k1]);
+                });
+            }
+        }
+        __syncthreads();
+        // inverse step B: item (line, n2) transforms over k1 -> y = n2 + P2 n1; cropped store
+        if (t < L * P2) {
+            const int line = t / P2, n2 = t - line * P2;
+            cpx<R> v[P1];
+            rfft::sfor<P1>([&](auto ic) { v[decltype(ic)::value] = S[line * SP + n2 * (P1 + 1) + decltype(ic)::value]; });
+            rfft::Dft<R, P1, true>::run(v);
+            rfft::sfor<P1>([&](auto ic) {
+                constexpr int n1 = decltype(ic)::value;
+                const int y = n2 + P2 * n1;
+                if (y < ny) base[((long long)line * ny + y) * Px] = v[n1];
+            });
+        }
+    }
+}
+
 // pass 2 split in three, for cross-sections whose (y, z) plane does not fit one workgroup's LDS
 // (few z layers, direct z sum).  yb[rhs][kx][row][ky], row = c*nz + z, holds y-spectra.
 // (a) forward y-FFT of `lg` zero-padded rows per workgroup (rows of one (rhs, x-frequency)).
 template <class R>
-__global__ void k_ysplit_fwd(const cpx<R> *work, cpx<R> *yb, int ny, int nz, int Px, int lg, FftPlan py) {
+__global__ void k_ysplit_fwd(const cpx<R> *work, cpx<R> *yb, int ny, int nz, int Px, int lg, FftPlan py,
+                             int xsplit) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem), *b = a + lg * py.L;
     const int Py = py.L, rows = 3 * nz, ngr = (rows + lg - 1) / lg;
     const int g = blockIdx.x % ngr;
     const int kx = xcd_block(blockIdx.x / ngr, Px);
     if (kx >= Px) return;
     const long long rhs = blockIdx.y;
-    const cpx<R> *base = work + rhs * 3LL * ny * nz * Px + kx;
+    const cpx<R> *base = work + rhs * 3LL * ny * nz * Px + xpos(kx, Px, xsplit);
     const int r0 = g * lg, nr = min(lg, rows - r0);
     for (int i = threadIdx.x; i < lg * Py; i += blockDim.x) {
         const int l = i / Py, y = i - l * Py;
@@ -459,7 +750,8 @@ __global__ void __launch_bounds__(256) k_ysplit_couple(const cpx<R> *__restrict_
 
 // (c) inverse y-FFT of `lg` coupled rows per workgroup, cropped back into the x-spectra.
 template <class R>
-__global__ void k_ysplit_inv(cpx<R> *work, const cpx<R> *yc, int ny, int nz, int Px, int lg, FftPlan py) {
+__global__ void k_ysplit_inv(cpx<R> *work, const cpx<R> *yc, int ny, int nz, int Px, int lg, FftPlan py,
+                             int xsplit) {
     cpx<R> *a = reinterpret_cast<cpx<R> *>(vie_smem), *b = a + lg * py.L;
     const int Py = py.L, rows = 3 * nz, ngr = (rows + lg - 1) / lg;
     const int g = blockIdx.x % ngr;
@@ -472,7 +764,7 @@ __global__ void k_ysplit_inv(cpx<R> *work, const cpx<R> *yc, int ny, int nz, int
     __syncthreads();
     const LdsLines ln = {lg, Py, 0, 1, lg};
     cpx<R> *res = Py > 1 ? fft_lds<R>(a, b, ln, py, true) : a;
-    cpx<R> *base = work + rhs * 3LL * ny * nz * Px + kx;
+    cpx<R> *base = work + rhs * 3LL * ny * nz * Px + xpos(kx, Px, xsplit);
     for (int i = threadIdx.x; i < nr * ny; i += blockDim.x) {
         const int l = i / ny, y = i - l * ny;
         base[((long long)(r0 + l) * ny + y) * Px] = res[l * Py + y];
@@ -500,6 +792,42 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
     (void)lines_per_comp_rhs_N;
 }
 
+// The register-FFT plane pass for the (y period, layer count) pairs it is instantiated for;
+// false for any other shape (the generic LDS plane pass runs then).  Right-hand sides are grouped
+// so that about 8192 workgroups remain (c.f. 256 CUs), each group sharing one staging of the
+// x-frequency's transformed generator.
+template <class R, int PY, int P1, int P2, int NZ>
+static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, hipStream_t s) {
+    constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
+    constexpr int NT = 64 * ((L * PM + 63) / 64), SP = PY + PM;
+    const size_t lds = sizeof(cpx<R>) * ((size_t)L * SP + (size_t)NZ * 6 * op->Hy + PY);
+    const long long planes = (long long)op->Px * nrhs;
+    const int rb = (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
+    const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
+    vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ>, lds);
+    hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s, work, khat,
+                       TwTable<R>::get(op->py), op->ny, op->Px, op->Hy, nrhs, rb, op->xsplit);
+}
+
+template <class R>
+static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, hipStream_t s) {
+    const int Py = op->Py, nz = op->nz;
+#define VIE_PLANE_REG(PY, P1, P2, NZ)                                    \
+    if (Py == PY && nz == NZ) {                                          \
+        plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, s);    \
+        return true;                                                     \
+    }
+    VIE_PLANE_REG(96, 12, 8, 8)
+    VIE_PLANE_REG(64, 8, 8, 8)
+    VIE_PLANE_REG(48, 8, 6, 8)
+    VIE_PLANE_REG(32, 8, 4, 8)
+    VIE_PLANE_REG(15, 5, 3, 8)
+    VIE_PLANE_REG(32, 8, 4, 4)
+    VIE_PLANE_REG(15, 5, 3, 4)
+#undef VIE_PLANE_REG
+    return false;
+}
+
 // Device bytes a product of nrhs vectors of element size esz works in: the x-spectra of every
 // line (*work) and, for the split plane pass, the y-spectra before and after the coupling (*ysp).
 static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, size_t *ysp) {
@@ -518,7 +846,10 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
     int thx, bpt;
     fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, cfg_x);
     const int thp = cfg_plane ? cfg_plane : 256;
-    {
+    if (op->xsplit > 1) {
+        ProfScope ps("matvec_xfwd", s);
+        VIE_CHECK(long_lines<R>(op, x, nx, work, lines, false, s));
+    } else {
         ProfScope ps("matvec_xfwd", s);
 #define LAUNCH_XFWD(B)                                      \
     vie_lds_attr((const void *)k_xfwd<R, B>, ldsx);         \
@@ -537,7 +868,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
         ProfScope ps("matvec_plane", s);
         vie_lds_attr((const void *)k_ysplit_fwd<R>, ldsy);
         hipLaunchKernelGGL(k_ysplit_fwd<R>, dim3(gx, nrhs), dim3(256), ldsy, s, (const cpx<R> *)work, y1, ny, nz, Px,
-                           lg, op->py);
+                           lg, op->py, op->xsplit);
         const int kb = 256 / nz;
         const size_t ldsc = sizeof(cpx<R>) * ((size_t)3 * nz * kb + (size_t)kb * (6 * nz + 1));
         vie_lds_attr((const void *)k_ysplit_couple<R>, ldsc);
@@ -545,22 +876,41 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
                            (const cpx<R> *)y1, y2, khat, nz, Px, Py, op->Hy);
         vie_lds_attr((const void *)k_ysplit_inv<R>, ldsy);
         hipLaunchKernelGGL(k_ysplit_inv<R>, dim3(gx, nrhs), dim3(256), ldsy, s, work, (const cpx<R> *)y2, ny, nz, Px,
-                           lg, op->py);
+                           lg, op->py, op->xsplit);
     } else if (op->direct_z) {
-        size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
-        vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
         ProfScope ps("matvec_plane", s);
-        hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz, Px,
-                           op->Hy, op->py);
+        if (!plane_reg<R>(op, work, khat, nrhs, s)) {
+            size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
+            vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
+            hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz,
+                               Px, op->Hy, op->py, op->xsplit);
+        }
     } else {
         size_t ldsp = 6 * sizeof(cpx<R>) * op->Py * op->Pz;
         vie_lds_attr((const void *)k_plane<R>, ldsp);
         ProfScope ps("matvec_plane", s);
         hipLaunchKernelGGL(k_plane<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz, Px,
-                           op->Hx, op->Hy, op->Hz, op->py, op->pz);
+                           op->Hx, op->Hy, op->Hz, op->py, op->pz, op->xsplit);
     }
     VIE_HIP(hipGetLastError());
-    {
+    if (op->xsplit > 1) {
+        ProfScope ps("matvec_xinv", s);
+        VIE_CHECK(long_lines<R>(op, work, Px, work, lines, true, s));
+        const int ntile = op->px1.L / LONG_LT;
+        size_t lds;
+        int cthr, cb;
+        long_cols_shape(op->px2, sizeof(cpx<R>), &cthr, &lds, &cb);
+#define LAUNCH_COLS_INV(B)                                                                                         \
+    vie_lds_attr((const void *)k_long_cols_inv<R, B>, lds);                                                        \
+    hipLaunchKernelGGL((k_long_cols_inv<R, B>), dim3((unsigned)(lines * ntile)), dim3(cthr), lds, s, work, Px,      \
+                       op->px1.L, op->px2, TwTable<R>::get(op->px), x, M, y, nx, ny * nz)
+        if (cb) {
+            LAUNCH_COLS_INV(4);
+        } else {
+            LAUNCH_COLS_INV(0);
+        }
+#undef LAUNCH_COLS_INV
+    } else {
         ProfScope ps("matvec_xinv", s);
 #define LAUNCH_XINV(B)                                                                               \
     vie_lds_attr((const void *)k_xinv<R, B>, ldsx);                                                  \

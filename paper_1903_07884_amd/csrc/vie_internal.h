@@ -254,6 +254,10 @@ struct vie_op_s {
                              // pass runs as y-FFT, z coupling and inverse y-FFT through ybuf
     FftCache fft;
     FftPlan px, py, pz;      // plans for the three periods
+    // x lines too long for one workgroup's LDS: four-step transform Px = L1 * L2 (xsplit = L2,
+    // plans of L1 = px1.L and L2 = px2.L); x-frequency kx then sits at (kx mod L2) L1 + kx / L2
+    int xsplit = 1;
+    FftPlan px1, px2;
     WsTable<OpWs> ws;        // product scratch per stream
 };
 
