@@ -82,7 +82,8 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
     its plane pass alone: the x-spectra of the cross-section rows in and out, and the transform."""
     nx, ny, nz = cfg['grid']
     N = nx * ny * nz
-    v = 16 if mode == 'fp64' else 8      # vector bytes per complex
+    v = 16 if mode in ('fp64', 'mixed_pc') else 8   # product vector bytes per complex
+    vp = 16 if mode == 'fp64' else 8                # preconditioner vector bytes
     f = {'c128': 16, 'c64': 8, 'bf16': 4}[factor]
     m = info['active_m']     # order of the solved blocks (identity rows of every D_k left out)
     modes = info['modes']
@@ -92,17 +93,26 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
     if R >= 8:
         bs = ('mfma', 8.0 * m * m * modes * R * (3 if refine else 1), 'flops')
     else:
-        bs = ('hbm', stored * m * m * f + R * modes * (2 * m * v + 4 * m), 'bytes')
+        bs = ('hbm', stored * m * m * f + R * modes * (2 * m * vp + 4 * m), 'bytes')
     models = {'block_solve': bs, 'matvec': ('hbm', R * (3 * N + 3 * N + N) * v + khat, 'bytes')}
     # plane pass of one product: the 3 ny nz rows of every x-frequency's spectra read and
     # written once, and the kernel transform ((x, y) octant with nz real offsets when nz <= 16)
     Px = good_length(2 * nx - 1)
     kplane = 6 * Hx * Hy * nz * v if nz <= 16 else khat
     models['matvec_plane'] = ('hbm', R * 2 * 3 * ny * nz * Px * v + kplane, 'bytes')
+    if nz <= 16:
+        # the plane pass with the direct z sum is bound by its arithmetic (counters: VALU issue):
+        # per (x-frequency, right-hand side) the z coupling, 9 nz^2 complex multiply-adds per
+        # y-frequency (8 real flops each), and the forward + inverse y-FFTs of the 3 nz rows
+        # (5 Py log2 Py real flops each)
+        Py = good_length(2 * ny - 1)
+        fl = 9 * nz * nz * Py * 8 + 2 * 3 * nz * 5 * Py * np.log2(Py)
+        models['matvec_plane'] = ('alu', R * Px * fl, 'flops')
+        models['_plane_bytes'] = R * 2 * 3 * ny * nz * Px * v + kplane
     if iters:
         # CGS2 per Arnoldi step j (index within its cycle): each of the two dot passes reads the
         # j+1 basis vectors and w once; each update pass also writes w.  Average per launch.
-        pv = 16 if mode == 'fp64' else 8
+        pv = 8 if mode == 'mixed' else 16
         js = [it % restart for it in range(iters)]
         n3 = 3 * N
         models['arnoldi_dots'] = ('hbm', sum(((j + 1) * pv + 16) * n3 * R for j in js) / len(js), 'bytes')
@@ -149,34 +159,40 @@ def counter_traffic(kernel, workload_tag):
         return None
 
 
-def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, pool=4):
-    """The request scheduler on a seeded stream of catalogue devices (waveguides, Bragg gratings,
-    couplers; lengths 256-1024; cross-sections 16x8-32x8; 1-16 right-hand sides; mixed precision,
-    complex64 factors, 1-level preconditioner).  Each device is visited once to fill the resident
-    cache; a closed burst of n_burst requests measures the capacity; then open-loop Poisson streams
-    at the given fractions of it.  Latency = scheduled arrival -> result on the host."""
+def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, pool=4, small=False):
+    """The request scheduler on a seeded stream of catalogue devices (waveguides, Bragg gratings
+    and couplers of 256-8192 voxels along x with cross-sections 16x8-48x8, and the 2 um disk on
+    160x160x8; 1-16 right-hand sides; mixed precision with complex64 factors; memory-reduced
+    preconditioners from 2048 voxels on, the 2-level one for the disk).  Each device is visited
+    once to fill the resident cache; a closed burst of n_burst requests measures the capacity;
+    then open-loop Poisson streams at the given fractions of it.  Latency = scheduled arrival ->
+    result on the host."""
     import queue as _queue
     import threading
 
     from paper_1903_07884_amd import workloads as W
-    devs = W.serving_devices()
+    devs = W.serving_devices(small=small)
     kb = W.k_background()
     chis = [W.device_chi(d) for d in devs]
     srcs = [W.device_sources(d, pool, 1000 + i).reshape(pool, -1) for i, d in enumerate(devs)]
+    solver = [W.device_solver(d) for d in devs]
 
     def submit(srv, i, nrhs, k):
         d = devs[i]
         e = srcs[i][[(k + j) % pool for j in range(nrhs)]]
-        return srv.submit(d['grid'], d['delta'], kb, chis[i], e, precond=True,
-                          homog='realmean' if d['geometry'] == 'bragg' else 'none', factor_prec=vie.VIE_C64,
-                          mode='mixed', tol=1e-6, restart=50)
+        return srv.submit(d['grid'], d['delta'], kb, chis[i], e, precond=True, factor_prec=vie.VIE_C64,
+                          mode='mixed', restart=50, **solver[i])
 
-    def run(srv, stream):
+    def run(srv, stream, label):
         q = _queue.Queue()
         rec = [None] * len(stream)
 
         def collect():
-            for _ in range(len(stream)):
+            every = max(10, len(stream) // 10)
+            for c in range(len(stream)):
+                if c and c % every == 0:
+                    print('bench: serving %s: %d of %d requests collected' % (label, c, len(stream)),
+                          file=sys.stderr, flush=True)
                 k, rid, late_ms, nrhs = q.get()
                 try:
                     _, st, tm = srv.wait(rid)
@@ -215,16 +231,18 @@ def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, po
     vie.autotune(False)
     vie.trim()
     srv = vie.Server(workers=workers, max_batch_rhs=64)
-    warm = run(srv, [(0.0, i, 1) for i in range(len(devs))])
+    warm = run(srv, [(0.0, i, 1) for i in range(len(devs))], 'cache fill')
     print('bench: serving cache filled (%d devices, %.2f s)' % (len(devs), warm['seconds']), file=sys.stderr,
           flush=True)
     g = np.random.default_rng(seed)
-    burst = run(srv, [(0.0, int(g.integers(0, len(devs))), int(g.integers(1, 17))) for _ in range(n_burst)])
+    burst = run(srv, [(0.0, int(g.integers(0, len(devs))), int(g.integers(1, 17))) for _ in range(n_burst)],
+                'burst')
     cap = burst['requests_per_s']
     print('bench: serving capacity %.1f requests/s' % cap, file=sys.stderr, flush=True)
     out = dict(workers=workers, devices=len(devs), capacity_requests_per_s=cap, burst=burst, streams=[])
     for frac, n in streams:
-        st = run(srv, W.serving_stream(n, frac * cap, seed + int(100 * frac)))
+        st = run(srv, W.serving_stream(n, frac * cap, seed + int(100 * frac), ndev=len(devs)),
+                 'stream at %.1fx capacity' % frac)
         st['offered_fraction_of_capacity'] = frac
         st['offered_requests_per_s'] = frac * cap
         out['streams'].append(st)
@@ -232,9 +250,15 @@ def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, po
               file=sys.stderr, flush=True)
     out['server'] = srv.info()
     srv.close()
-    out['mix'] = ('catalogue of %d devices (waveguide / Bragg / coupler; n_x 256-1024; cross-sections 16x8-32x8; '
-                  '25 nm), 1-16 RHS per request, mixed precision with complex64 factors, GMRES(50) to 1e-6'
-                  % len(devs))
+    out['mix'] = ('catalogue of %d devices (waveguide / Bragg / coupler; n_x %d-%d; cross-sections %dx%d-%dx%d; '
+                  '25 nm%s), 1-16 RHS per request, mixed precision with complex64 factors, GMRES(50) to 1e-6 '
+                  '(memory-reduced preconditioner from n_x %d on%s)'
+                  % (len(devs), min(d['grid'][0] for d in devs if d['geometry'] != 'disk'),
+                     max(d['grid'][0] for d in devs if d['geometry'] != 'disk'),
+                     min(d['grid'][1] for d in devs if d['geometry'] != 'disk'), devs[0]['grid'][2],
+                     max(d['grid'][1] for d in devs if d['geometry'] != 'disk'), devs[0]['grid'][2],
+                     '' if small else '; plus the 2 um Si disk on 160x160x8', W.SERVE_REDUCE_FROM_NX,
+                     '' if small else '; the disk: 2-level over the modal-average contrast, to 1e-4'))
     return out
 
 
@@ -381,6 +405,8 @@ def roofline_of(kern, models, mode, dev, copy=True):
         achieved = amount / avg_s / 1e12
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit='TFLOP/s', frac=achieved / peak,
                     traffic=counter_traffic(dom, models.get('_tag')), per_launch_flops=amount)
+        if dom == 'matvec_plane' and '_plane_bytes' in models:
+            roof['hbm_gbps_algorithmic'] = models['_plane_bytes'] / avg_s / 1e9
     else:
         achieved = amount / avg_s / 1e9
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=HBM_PEAK_GBS, unit='GB/s',
@@ -425,7 +451,7 @@ class Workload:
         mode = mode or plan['mode']
         bxs = plan['boxes'] if boxes == 'default' else boxes
         rt = plan['reduce_tol'] if reduce_tol == 'default' else reduce_tol
-        factor = factor or (plan.get('factor', 'c64') if mode == 'mixed' else 'c128')
+        factor = factor or (plan.get('factor', 'c64') if mode in ('mixed', 'mixed_pc') else 'c128')
         fp = {'c128': vie.VIE_C128, 'c64': vie.VIE_C64, 'bf16': vie.VIE_BF16C}[factor]
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(self.stream)
@@ -462,9 +488,15 @@ class Workload:
         mdl = algorithmic_models(self.cfg, rec['info'], self.R, mode, factor,
                                  refine=1 if factor == 'bf16' else 0, iters=rec['iters'])
         out = {'_tag': self.tag}
-        for k, (bound, amount, unit) in mdl.items():
+        for k, val in mdl.items():
+            if k.startswith('_'):
+                out[k] = val
+                continue
+            bound, amount, unit = val
             peak = HBM_PEAK_GBS
-            if unit == 'flops':
+            if bound == 'alu':   # vector units of the product's precision
+                peak = FP32_PEAK_TFLOPS if mode == 'mixed' else FP64_PEAK_TFLOPS
+            elif unit == 'flops':
                 # matrix-core block solves: FP64 operands in FP64 mode; complex64 factors on the FP32
                 # units; bfloat16 factors: the off-diagonal products on the BF16 units, while the
                 # diagonal tiles and the refinement residual run in FP32 -- priced at the FP32 peak
@@ -517,14 +549,18 @@ def leg_plan(tag, main_mode):
     if tag == 4:
         legs = [('fp64', dict(mode='fp64')), ('mixed_bf16_refined', dict(mode='mixed', factor='bf16')),
                 ('mixed_c64_factors', dict(mode='mixed', factor='c64')),
+                ('mixed_pc_c64_factors', dict(mode='mixed_pc', factor='c64')),
                 ('mixed_bf16_reduced_1e-3_centre_proxy', dict(mode='mixed', factor='bf16', reduce_tol=1e-3,
                                                                proxy='centre'))]
     elif tag == 3:
         legs = [('fp64', dict(mode='fp64')), ('mixed_c64_factors', dict(mode='mixed', factor='c64')),
+                ('mixed_pc_c64_factors', dict(mode='mixed_pc', factor='c64')),
                 ('fp64_single_box', dict(mode='fp64', boxes=None)),
-                ('mixed_single_box', dict(mode='mixed', factor='c64', boxes=None))]
+                ('mixed_single_box', dict(mode='mixed', factor='c64', boxes=None)),
+                ('mixed_pc_single_box', dict(mode='mixed_pc', factor='c64', boxes=None))]
     elif tag == 2:
         legs = [('fp64', dict(mode='fp64')), ('mixed_c64_factors', dict(mode='mixed', factor='c64')),
+                ('mixed_pc_c64_factors', dict(mode='mixed_pc', factor='c64')),
                 ('fp64_reduced_1e-3', dict(mode='fp64', reduce_tol=1e-3)),
                 ('fp64_reduced_1e-3_centre_proxy', dict(mode='fp64', reduce_tol=1e-3, proxy='centre'))]
     elif tag == 5:
@@ -541,7 +577,7 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--config', type=int, default=4,
                     help='workload of the timed steps (4: the 1024x48x8 coupler with 64 right-hand sides)')
-    ap.add_argument('--precision', choices=('fp64', 'mixed'), default='fp64',
+    ap.add_argument('--precision', choices=('fp64', 'mixed', 'mixed_pc'), default='fp64',
                     help='precision of the timed steps (the other one is a comparison leg)')
     ap.add_argument('--legs', default='4,3,2',
                     help='workloads whose FP64 / mixed comparison legs the line carries ("" = none)')
@@ -593,7 +629,7 @@ def main():
 
     wl = Workload(vie, args.config, dev)
     main_kw = dict(mode=args.precision)
-    if args.precision == 'mixed':
+    if args.precision != 'fp64':
         main_kw['factor'] = wl.plan.get('factor', 'c64')
     vie.autotune(not args.no_autotune)
     for _ in range(max(args.warmup, 0 if args.no_autotune else 1)):
@@ -655,7 +691,8 @@ def main():
         for label in list(res):
             if not label.startswith('mixed'):
                 continue
-            twin = 'fp64_' + label[len('mixed_'):]   # the FP64 leg of the same preconditioner, if any
+            rest = label[len('mixed_pc_'):] if label.startswith('mixed_pc_') else label[len('mixed_'):]
+            twin = 'fp64_' + rest   # the FP64 leg of the same preconditioner, if any
             ref_ms = res[twin]['ms'] if twin in res else t64
             if ref_ms:
                 ratios['c%d %s' % (tag, label)] = ref_ms / res[label]['ms']
@@ -663,7 +700,8 @@ def main():
         if w is not wl:
             del w
             torch.cuda.empty_cache()
-    dtype = {'fp64': 'c128', 'mixed': 'c64+bf16+f64' if last['factor'] == 'bf16' else 'c64+f64'}[last['mode']]
+    dtype = {'fp64': 'c128', 'mixed': 'c64+bf16+f64' if last['factor'] == 'bf16' else 'c64+f64',
+             'mixed_pc': 'c128+bf16' if last['factor'] == 'bf16' else 'c128+c64'}[last['mode']]
     cfg = wl.cfg
     out = {
         'metric': METRIC,

@@ -228,9 +228,14 @@ vie_status precond_apply(vie_pc pc, const void *r, void *z, int32_t nrhs, vie_pr
 /* ---- solver ---------------------------------------------------------------- */
 
 typedef enum {
-    VIE_MODE_FP64 = 0,  /* GMRES, everything in complex128 */
-    VIE_MODE_MIXED = 1  /* flexible GMRES: complex64 matvec and preconditioner,
-                           FP64 Arnoldi/Givens and FP64 true residual */
+    VIE_MODE_FP64 = 0,      /* GMRES, everything in complex128 */
+    VIE_MODE_MIXED = 1,     /* flexible GMRES: complex64 matvec and preconditioner,
+                               complex64 basis, FP64 Arnoldi/Givens and FP64 true residual */
+    VIE_MODE_MIXED_PC = 2   /* flexible GMRES with only the preconditioner in reduced precision
+                               (complex64 or bfloat16 factors, complex64 Z): complex128 operator
+                               product and basis, FP64 Arnoldi/Givens.  The inner products then
+                               carry no complex64 operator error, which bounds what one restart
+                               cycle of VIE_MODE_MIXED can gain on ill-conditioned problems. */
 } vie_mode;
 
 typedef struct {
@@ -373,14 +378,23 @@ vie_status vie_trim(void);
  * right-hand-side count times every candidate launch configuration of the block solves
  * (column-group width and workgroup height of the matrix-core solve, right-hand sides per
  * workgroup of the per-mode solve, and the right-hand-side count from which blocks use the
- * matrix-core solve) on a copy of the data, and the first vie_matvec for a new shape times
- * the thread counts of its FFT passes; the fastest is kept for the rest of the process,
- * keyed by the shape.  Results never depend on the choice beyond rounding order.
+ * matrix-core solve) on a copy of the data; the first vie_matvec for a new shape and
+ * right-hand-side count times the right-hand sides per workgroup of the register plane pass
+ * (or the threads of the LDS plane pass) and the threads of the LDS x-line passes; and
+ * precond_setup times the sub-panels per macro panel (1, 2, 4, 8) of the batched LU on a
+ * copy of the first min(blocks, 256) blocks.  The fastest is kept for the rest of the
+ * process, keyed by the shape.  Results never depend on the choice beyond rounding order.
  * vie_autotune_report writes the cache as text ("key -> choice (ms, candidates)" lines)
  * into buf (truncated to size - 1 characters, NUL-terminated); *needed receives the full
- * length + 1.  Both calls are process-wide and thread-safe. */
+ * length + 1.  vie_autotune_set stores the n values `choice` under `key` (a key as the
+ * report prints it; n = 0 removes the entry), so that tuned parameters can be restored in
+ * a later process or a candidate forced: with autotuning on, a call whose shape has that
+ * key uses the stored values without timing, and fails with VIE_EARG (nothing launched) if
+ * they are not one of that shape's candidates.  VIE_EARG for a null key, n outside 0..16 or
+ * a null choice with n > 0.  All three calls are process-wide and thread-safe. */
 vie_status vie_autotune(int32_t enable);
 vie_status vie_autotune_report(char *buf, int64_t size, int64_t *needed);
+vie_status vie_autotune_set(const char *key, const int32_t *choice, int32_t n);
 
 /* Thread-local description of the last failure ("" if none). */
 const char *vie_last_error(void);

@@ -440,10 +440,14 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
         if (so->restart < 1 || so->restart > VIE_MAX_RESTART)
             return arg_error("vie_footprint: restart must be in [1, " + std::to_string(VIE_MAX_RESTART) + "]");
         const uint64_t rs = (uint64_t)so->restart;
-        const bool mixed = so->mode == VIE_MODE_MIXED;
-        const uint64_t vb = mixed ? 8 : 16;  // basis precision
-        *solve_bytes = vb * R * n3 * (rs + 1) + vb * R * n3 * rs + 2 * 16 * R * n3 + 16 * R * (uint64_t)arnoldi_partials((long long)n3, (int)rs) +
-                       (mixed ? 8 * R * n3 : 0) + 16 * R * (rs + 2) * (rs + 4);
+        const bool mixed = so->mode == VIE_MODE_MIXED, mixed_pc = so->mode == VIE_MODE_MIXED_PC;
+        const uint64_t vb = mixed ? 8 : 16;              // basis precision
+        const uint64_t zb = mixed || mixed_pc ? 8 : 16;  // preconditioned vectors
+        // complex64 product output (mixed); complex64 copy of v_j + widened z_j (mixed_pc)
+        const uint64_t extra = mixed ? 8 : mixed_pc ? 8 + 16 : 0;
+        *solve_bytes = vb * R * n3 * (rs + 1) + zb * R * n3 * rs + 2 * 16 * R * n3 +
+                       16 * R * (uint64_t)arnoldi_partials((long long)n3, (int)rs) + extra * R * n3 +
+                       16 * R * (rs + 2) * (rs + 4);
     }
     return VIE_OK;
 }
@@ -527,7 +531,8 @@ vie_status solve_opts_check(const char *who, const vie_solve_opts &o) {
     if (o.restart < 1 || o.restart > VIE_MAX_RESTART)
         return arg_error(w + ": restart must be in [1, " + std::to_string(VIE_MAX_RESTART) + "]");
     if (o.maxit < 1) return arg_error(w + ": maxit must be >= 1");
-    if (o.mode != VIE_MODE_FP64 && o.mode != VIE_MODE_MIXED) return arg_error(w + ": unknown mode");
+    if (o.mode != VIE_MODE_FP64 && o.mode != VIE_MODE_MIXED && o.mode != VIE_MODE_MIXED_PC)
+        return arg_error(w + ": unknown mode");
     return VIE_OK;
 }
 

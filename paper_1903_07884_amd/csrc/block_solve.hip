@@ -1062,16 +1062,18 @@ static vie_status block_solve_t(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hipS
         char key[160];
         snprintf(key, sizeof key, "block_solve prec=%d m=%d n=%d boxes=%d stored=%d nrhs=%d refine=%d", pc->prec,
                  pc->m, pc->nm, pc->nboxes, pc->nstored, nrhs, pc->refine);
+        std::vector<std::vector<int>> cands;  // {gmax, nw, rc, min_rhs}
+        const int rcmax = block_solve_rc(pc->m, block_cols_max(pc, nrhs), sizeof(cpx<R>));
+        const int nws[2] = {fp32 ? 8 : 4, fp32 ? 16 : 8};
+        if (bf || nrhs >= WIDE_MIN_RHS)
+            for (int g = 16; g <= WIDE_MAX_COLS; g *= 2)
+                for (int nw : nws) cands.push_back({g, nw, 0, bf ? 1 : WIDE_MIN_RHS});
+        if (!bf && nrhs < 32)
+            for (int rc = 1; rc <= rcmax; rc *= 2) cands.push_back({0, 0, rc, 1 << 30});
         std::vector<int> choice;
-        if (!tune_lookup(key, &choice)) {
-            std::vector<std::vector<int>> cands;  // {gmax, nw, rc, min_rhs}
-            const int rcmax = block_solve_rc(pc->m, block_cols_max(pc, nrhs), sizeof(cpx<R>));
-            const int nws[2] = {fp32 ? 8 : 4, fp32 ? 16 : 8};
-            if (bf || nrhs >= WIDE_MIN_RHS)
-                for (int g = 16; g <= WIDE_MAX_COLS; g *= 2)
-                    for (int nw : nws) cands.push_back({g, nw, 0, bf ? 1 : WIDE_MIN_RHS});
-            if (!bf && nrhs < 32)
-                for (int rc = 1; rc <= rcmax; rc *= 2) cands.push_back({0, 0, rc, 1 << 30});
+        if (tune_lookup(key, &choice)) {
+            VIE_CHECK(tune_check_choice(key, choice, cands));
+        } else {
             if (cands.size() > 1) {
                 const size_t bytes = sizeof(cpx<R>) * (size_t)nrhs * pc->nboxes * pc->m * pc->nm;
                 DevBuf copy;
@@ -1093,6 +1095,7 @@ static vie_status block_solve_t(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hipS
                 tune_store(key, choice, best, (int)cands.size());
             } else if (cands.size() == 1) {
                 choice = cands[0];
+                tune_store(key, choice, 0.0, 1);
             }
         }
         if (!choice.empty()) {

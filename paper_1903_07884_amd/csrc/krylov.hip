@@ -16,7 +16,10 @@
 // complex64 for the preconditioner (complex64 factors) and the complex64 operator
 // product, whose result is widened back for the FP64 Arnoldi step; Z is kept in
 // complex64; the true residual of every cycle uses the complex128 product, so the
-// outer loop is an FP64 iterative refinement around the FP32 inner solve.
+// outer loop is an FP64 iterative refinement around the FP32 inner solve; the basis V is
+// stored in complex64.  Mixed-preconditioner mode: only the preconditioner runs in complex64
+// (or bfloat16 factors), on a complex64 copy of v_j; Z is kept in complex64, each z_j is
+// widened for the complex128 product, and V stays complex128.
 #include <cmath>
 
 #include "vie_internal.h"
@@ -417,12 +420,14 @@ long long arnoldi_partials(long long n, int restart) {
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, const vie_solve_opts *o,
                        vie_solve_stats *stats, hipStream_t s, SolveHook *hook) {
     const bool mixed = o->mode == VIE_MODE_MIXED;
+    const bool mixed_pc = o->mode == VIE_MODE_MIXED_PC;  // reduced-precision preconditioner only
+    const bool lowpc = mixed || mixed_pc;
     if (mixed && !op->has_c64) {
         vie_set_error("mixed-precision solve needs an operator built with build_c64");
         return VIE_EARG;
     }
-    if (pc && (mixed ? (pc->prec != VIE_C64 && pc->prec != VIE_BF16C) : pc->prec != VIE_C128)) {
-        vie_set_error(mixed ? "mixed-precision solve needs complex64 or bfloat16 preconditioner factors"
+    if (pc && (lowpc ? (pc->prec != VIE_C64 && pc->prec != VIE_BF16C) : pc->prec != VIE_C128)) {
+        vie_set_error(lowpc ? "mixed-precision solve needs complex64 or bfloat16 preconditioner factors"
                             : "FP64 solve needs complex128 preconditioner factors");
         return VIE_EARG;
     }
@@ -430,11 +435,19 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     const long long n = 3LL * op->N;
     const long long Rn = (long long)R * n;
     Ctx C{op, s, n, R, kr_parts(n, KR_EPT_DOTS), kr_parts(n, KR_EPT_UPD), nullptr, nullptr};
-    // mixed mode: basis V and flexible basis Z in complex64, FP64 sums and w
-    const size_t zsz = mixed ? sizeof(c64) : sizeof(c128);
-    DevBuf Vb, Zb, wb, rb, part, small, w32;
-    VIE_CHECK(Vb.ensure(zsz * Rn * (m + 1)));
+    // mixed: basis V and flexible basis Z in complex64, FP64 sums and w.  mixed_pc: V in
+    // complex128 with a complex64 copy of its newest vector (vlo) for the preconditioner, Z in
+    // complex64, each z_j widened (zw) for the complex128 product.
+    const bool v32 = mixed;
+    const size_t vsz = v32 ? sizeof(c64) : sizeof(c128);
+    const size_t zsz = lowpc ? sizeof(c64) : sizeof(c128);
+    DevBuf Vb, Zb, wb, rb, part, small, w32, vlo, zw;
+    VIE_CHECK(Vb.ensure(vsz * Rn * (m + 1)));
     VIE_CHECK(Zb.ensure(zsz * Rn * m));
+    if (mixed_pc) {
+        VIE_CHECK(vlo.ensure(sizeof(c64) * Rn));
+        VIE_CHECK(zw.ensure(sizeof(c128) * Rn));
+    }
     VIE_CHECK(wb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
@@ -564,11 +577,14 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         }
         VIE_HIP(hipMemcpyAsync(beta_dev, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
         VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
-        if (mixed)
+        if (v32)
             hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(), n,
                                (const double *)beta_dev, 1, (const int *)S.active);
         else
             hipLaunchKernelGGL(k_scale<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(), n,
+                               (const double *)beta_dev, 1, (const int *)S.active);
+        if (mixed_pc)
+            hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, vlo.as<c64>(), n,
                                (const double *)beta_dev, 1, (const int *)S.active);
         VIE_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_setg, dim3((unsigned)(((m + 1) * R + 63) / 64)), dim3(64), 0, s, S.g, m + 1,
@@ -576,28 +592,40 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         VIE_HIP(hipGetLastError());
         int j = 0;
         while (j < m && nact > 0) {
-            void *vj = (char *)Vb.p + zsz * Rn * j;
+            void *vj = (char *)Vb.p + vsz * Rn * j;
             void *zj = (char *)Zb.p + zsz * Rn * j;
-            if (!mixed) {
+            if (!lowpc) {
                 if (pc)
                     VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
                 else
                     VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
                 VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
             } else {
+                const void *vin = mixed_pc ? vlo.p : vj;
                 if (pc)
-                    VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C64, s));
+                    VIE_CHECK(pc_apply(pc, vin, zj, R, VIE_C64, s));
                 else
-                    VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
-                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
-                hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
-                VIE_HIP(hipGetLastError());
+                    VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
+                if (mixed) {
+                    VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
+                    hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
+                    VIE_HIP(hipGetLastError());
+                } else {
+                    hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, (const c64 *)zj, zw.as<c128>(), Rn);
+                    VIE_HIP(hipGetLastError());
+                    VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s));
+                }
             }
-            if (mixed)
+            if (v32)
                 VIE_CHECK(cgs2_step<c64>(C, Vb.as<const c64>(), ldj, j, w, S, m, grid_e, Vb.as<c64>() + (j + 1) * ldj));
             else
                 VIE_CHECK(cgs2_step<c128>(C, Vb.as<const c128>(), ldj, j, w, S, m, grid_e,
                                           Vb.as<c128>() + (j + 1) * ldj));
+            if (mixed_pc) {  // the complex64 copy of v_{j+1} = w / h_{j+1,j}
+                hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)w, vlo.as<c64>(), n,
+                                   (const double *)(S.st + 1), 4, (const int *)S.active);
+                VIE_HIP(hipGetLastError());
+            }
             VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
             ++j;
             bool changed = false;
@@ -626,7 +654,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         VIE_HIP(hipMemcpyAsync(jr_dev, hjr, sizeof(int) * R, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_lsq, dim3((R + 63) / 64), dim3(64), 0, s, S, (const int *)jr_dev, R);
         VIE_HIP(hipGetLastError());
-        if (mixed)
+        if (lowpc)
             hipLaunchKernelGGL(k_combine<float>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c64>(), ldj,
                                (const int *)jr_dev, (const c128 *)S.y, m, x, n);
         else

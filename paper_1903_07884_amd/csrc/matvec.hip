@@ -354,6 +354,30 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
     return VIE_OK;
 }
 
+// MODE 0: forward, x-line (nx entries, zero beyond) -> x-spectra line; MODE 1: inverse,
+// x-spectra line -> y = x - M (x + line) on the first nx entries.
+template <class R, int R1, int R2, int R3, int R4, int MODE>
+__global__ void __launch_bounds__((rfft::Radices<R1, R2, R3, R4>::T))
+k_xline_reg(const cpx<R> *__restrict__ in, cpx<R> *__restrict__ out, const cpx<R> *__restrict__ x,
+            const cpx<R> *__restrict__ M, int nx, int nyz, const cpx<R> *__restrict__ tw) {
+    constexpr int L = rfft::Radices<R1, R2, R3, R4>::L;
+    const long long line = blockIdx.x;
+    const cpx<R> *src = MODE == 0 ? in + line * nx : in + line * L;
+    const cpx<R> *xl = x + line * nx;
+    const cpx<R> *ml = M + (line % nyz) * nx;
+    cpx<R> *dl = MODE == 0 ? out + line * L : out + line * nx;
+    rfft::reg_line<R, R1, R2, R3, R4, MODE == 1>(
+        tw, [&](int i) -> cpx<R> { return MODE == 0 ? (i < nx ? src[i] : czero<R>()) : src[i]; },
+        [&](int i, cpx<R> v) {
+            if (MODE == 0) {
+                dl[i] = v;
+            } else if (i < nx) {
+                const cpx<R> xv = xl[i];
+                dl[i] = xv - ml[i] * (xv + v);
+            }
+        });
+}
+
 // ---------------------------------------------------------------- product
 // pass 1: one workgroup per x-line (rhs, a, z, y): zero-pad to Px, forward FFT.
 template <class R, int BPT>
@@ -560,25 +584,43 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         for (int i = t; i < PY; i += NT) W[i] = twtab[i];
     }
     const int r0 = blockIdx.y * rb, r1 = min(nrhs, r0 + rb);
+    const long long xo = xpos(kx, Px, xsplit), rstride = (long long)L * ny * Px;
+    // the zero-padded column of item (line, n2) of the forward step 1; the next plane's column
+    // is loaded while the current plane is processed (every barrier below orders LDS only)
+    // ny <= (PY + 1) / 2, so only the first NNZ entries of a column (y = n2 + P2 n1) can be
+    // nonzero: the others are compile-time zeros in the step-1 DFT
+    constexpr int NNZ = ((PY + 1) / 2 + P2 - 1) / P2;
+    const int line1 = t / P2, n21 = t - line1 * P2;
+    cpx<R> vn[NNZ];
+    auto load_col = [&](int rhs) {
+        const cpx<R> *src = work + rhs * rstride + xo;
+        rfft::sfor<NNZ>([&](auto ic) {
+            constexpr int n1 = decltype(ic)::value;
+            const int y = n21 + P2 * n1;
+            vn[n1] = (t < L * P2 && y < ny) ? src[((long long)line1 * ny + y) * Px] : czero<R>();
+        });
+    };
+    if (r0 < r1) load_col(r0);
     for (int rhs = r0; rhs < r1; ++rhs) {
-        cpx<R> *base = work + (long long)rhs * L * ny * Px + xpos(kx, Px, xsplit);
-        __syncthreads();  // G, W staged; the previous plane's last reads of S are done
+        cpx<R> *base = work + rhs * rstride + xo;
+        rfft::lds_barrier();  // G, W staged; the previous plane's last reads of S are done
         // forward step 1: item (line, n2) transforms its zero-padded column over n1
         if (t < L * P2) {
-            const int line = t / P2, n2 = t - line * P2;
+            const int line = line1, n2 = n21;
             cpx<R> v[P1];
             rfft::sfor<P1>([&](auto ic) {
                 constexpr int n1 = decltype(ic)::value;
-                const int y = n2 + P2 * n1;
-                v[n1] = y < ny ? base[((long long)line * ny + y) * Px] : czero<R>();
+                if constexpr (n1 < NNZ) v[n1] = vn[n1];
+                else v[n1] = czero<R>();
             });
+            if (rhs + 1 < r1) load_col(rhs + 1);
             rfft::Dft<R, P1, false>::run(v);
             rfft::sfor<P1>([&](auto ic) {
                 constexpr int k1 = decltype(ic)::value;
                 S[line * SP + k1 * (P2 + 1) + n2] = k1 == 0 ? v[k1] : v[k1] * W[n2 * k1];
             });
         }
-        __syncthreads();
+        rfft::lds_barrier();
         // forward step 2: item (line, k1) transforms over n2 -> ky = k1 + P1 k2
         {
             cpx<R> u[P2];
@@ -586,13 +628,13 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
             const bool act = t < L * P1;
             if (act)
                 rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 * (P2 + 1) + decltype(ic)::value]; });
-            __syncthreads();
+            rfft::lds_barrier();
             if (act) {
                 rfft::Dft<R, P2, false>::run(u);
                 rfft::sfor<P2>([&](auto ic) { S[line * SP + k1 + P1 * decltype(ic)::value] = u[decltype(ic)::value]; });
             }
         }
-        __syncthreads();
+        rfft::lds_barrier();
         // z coupling: item (c, ky) forms component c of its y-frequency at every layer z, the sum
         // over z' and c' of the (c, c') block of the transformed generator at offset z - z' with the
         // parity signs (xy odd in x and y, xz in x and z, yz in y and z).  The source components are
@@ -626,17 +668,17 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                     });
                 }
             }
-            __syncthreads();
+            rfft::lds_barrier();
             if (act) rfft::sfor<NZ>([&](auto iz) { S[(c * NZ + decltype(iz)::value) * SP + ky] = acc[decltype(iz)::value]; });
         }
-        __syncthreads();
+        rfft::lds_barrier();
         // inverse step A: item (line, k1) transforms over k2, multiplies by conj W_PY^{n2 k1}
         {
             cpx<R> u[P2];
             const int line = t / P1, k1 = t - line * P1;
             const bool act = t < L * P1;
             if (act) rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 + P1 * decltype(ic)::value]; });
-            __syncthreads();
+            rfft::lds_barrier();
             if (act) {
                 rfft::Dft<R, P2, true>::run(u);
                 rfft::sfor<P2>([&](auto ic) {
@@ -645,7 +687,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                 });
             }
         }
-        __syncthreads();
+        rfft::lds_barrier();
         // inverse step B: item (line, n2) transforms over k1 -> y = n2 + P2 n1; cropped store
         if (t < L * P2) {
             const int line = t / P2, n2 = t - line * P2;
@@ -797,25 +839,29 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
 // so that about 8192 workgroups remain (c.f. 256 CUs), each group sharing one staging of the
 // x-frequency's transformed generator.
 template <class R, int PY, int P1, int P2, int NZ>
-static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, hipStream_t s) {
+static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb_req, hipStream_t s) {
     constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
     constexpr int NT = 64 * ((L * PM + 63) / 64), SP = PY + PM;
     const size_t lds = sizeof(cpx<R>) * ((size_t)L * SP + (size_t)NZ * 6 * op->Hy + PY);
     const long long planes = (long long)op->Px * nrhs;
-    const int rb = (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
+    const int rb = rb_req > 0 ? std::min(rb_req, nrhs)
+                              : (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
     const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
     vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ>, lds);
     hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s, work, khat,
                        TwTable<R>::get(op->py), op->ny, op->Px, op->Hy, nrhs, rb, op->xsplit);
 }
 
+// rb > 0: right-hand sides per workgroup (autotuned), 0: the default grouping.  work = nullptr
+// only asks whether the shape is instantiated.
 template <class R>
-static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, hipStream_t s) {
+static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
     const int Py = op->Py, nz = op->nz;
-#define VIE_PLANE_REG(PY, P1, P2, NZ)                                    \
-    if (Py == PY && nz == NZ) {                                          \
-        plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, s);    \
-        return true;                                                     \
+    if (!op->direct_z || op->split_plane) return false;
+#define VIE_PLANE_REG(PY, P1, P2, NZ)                                              \
+    if (Py == PY && nz == NZ) {                                                    \
+        if (work) plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, rb, s); \
+        return true;                                                               \
     }
     VIE_PLANE_REG(96, 12, 8, 8)
     VIE_PLANE_REG(64, 8, 8, 8)
@@ -828,6 +874,49 @@ static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, hip
     return false;
 }
 
+// The register x-line transform for the x periods it is instantiated for (false otherwise:
+// the LDS Stockham kernels run).  mode 0: forward pass, 1: inverse pass with the final
+// combination.
+template <class R, int R1, int R2, int R3, int R4>
+static void xline_launch(int mode, long long lines, const cpx<R> *in, cpx<R> *out, const cpx<R> *x, const cpx<R> *M,
+                         int nx, int nyz, const cpx<R> *tw, hipStream_t s) {
+    typedef rfft::Radices<R1, R2, R3, R4> RD;
+    const size_t lds = sizeof(cpx<R>) * RD::L;
+    if (mode == 0) {
+        vie_lds_attr((const void *)k_xline_reg<R, R1, R2, R3, R4, 0>, lds);
+        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 0>), dim3((unsigned)lines), dim3(RD::T), lds, s, in, out, x,
+                           M, nx, nyz, tw);
+    } else {
+        vie_lds_attr((const void *)k_xline_reg<R, R1, R2, R3, R4, 1>, lds);
+        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 1>), dim3((unsigned)lines), dim3(RD::T), lds, s, in, out, x,
+                           M, nx, nyz, tw);
+    }
+}
+
+// mode -1 only asks whether the length is instantiated.
+template <class R>
+static bool xline_reg(vie_op op, int mode, long long lines, const cpx<R> *in, cpx<R> *out, const cpx<R> *x,
+                      const cpx<R> *M, hipStream_t s) {
+    if (op->xsplit > 1) return false;
+    if (mode < 0) return op->Px == 1024 || op->Px == 2048 || op->Px == 4096 || op->Px == 8192 ||
+                         (op->Px == 16384 && sizeof(R) == 4);
+    const cpx<R> *tw = TwTable<R>::get(op->px);
+    const int nyz = op->ny * op->nz;
+    switch (op->Px) {
+        case 1024: xline_launch<R, 16, 8, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
+        case 2048: xline_launch<R, 16, 16, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
+        case 4096: xline_launch<R, 16, 16, 16, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
+        case 8192: xline_launch<R, 16, 16, 16, 2>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
+        case 16384:  // complex64 only (a complex128 line of this length takes the four-step path)
+            if constexpr (sizeof(R) == 4) {
+                xline_launch<R, 16, 16, 16, 4>(mode, lines, in, out, x, M, op->nx, nyz, tw, s);
+                return true;
+            }
+            return false;
+        default: return false;
+    }
+}
+
 // Device bytes a product of nrhs vectors of element size esz works in: the x-spectra of every
 // line (*work) and, for the split plane pass, the y-spectra before and after the coupling (*ysp).
 static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, size_t *ysp) {
@@ -836,7 +925,8 @@ static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, 
 }
 
 // One product through the three passes; work and ysp hold matvec_scratch's bytes.
-// cfg_plane / cfg_x: threads of the plane pass / the x-line passes (0 = default).
+// cfg_plane: right-hand sides per workgroup of the register plane pass, or the threads of the
+// LDS plane pass; cfg_x: threads of the LDS x-line passes (0 = defaults).
 template <class R>
 static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
                              const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, int cfg_plane, int cfg_x, hipStream_t s) {
@@ -846,16 +936,17 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
     int thx, bpt;
     fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, cfg_x);
     const int thp = cfg_plane ? cfg_plane : 256;
-    if (op->xsplit > 1) {
+    {
         ProfScope ps("matvec_xfwd", s);
-        VIE_CHECK(long_lines<R>(op, x, nx, work, lines, false, s));
-    } else {
-        ProfScope ps("matvec_xfwd", s);
+        if (op->xsplit > 1) {
+            VIE_CHECK(long_lines<R>(op, x, nx, work, lines, false, s));
+        } else if (!xline_reg<R>(op, 0, lines, x, work, nullptr, nullptr, s)) {
 #define LAUNCH_XFWD(B)                                      \
     vie_lds_attr((const void *)k_xfwd<R, B>, ldsx);         \
     hipLaunchKernelGGL((k_xfwd<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, x, work, nx, op->px)
-        VIE_BPT_SWITCH(bpt, LAUNCH_XFWD);
+            VIE_BPT_SWITCH(bpt, LAUNCH_XFWD);
 #undef LAUNCH_XFWD
+        }
     }
     VIE_HIP(hipGetLastError());
     if (op->split_plane) {
@@ -879,7 +970,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
                            lg, op->py, op->xsplit);
     } else if (op->direct_z) {
         ProfScope ps("matvec_plane", s);
-        if (!plane_reg<R>(op, work, khat, nrhs, s)) {
+        if (!plane_reg<R>(op, work, khat, nrhs, cfg_plane, s)) {
             size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
             vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
             hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz,
@@ -912,12 +1003,14 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
 #undef LAUNCH_COLS_INV
     } else {
         ProfScope ps("matvec_xinv", s);
+        if (!xline_reg<R>(op, 1, lines, work, y, x, M, s)) {
 #define LAUNCH_XINV(B)                                                                               \
     vie_lds_attr((const void *)k_xinv<R, B>, ldsx);                                                  \
     hipLaunchKernelGGL((k_xinv<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, work, x, M, y, nx, \
                        0LL, ny * nz, op->px)
-        VIE_BPT_SWITCH(bpt, LAUNCH_XINV);
+            VIE_BPT_SWITCH(bpt, LAUNCH_XINV);
 #undef LAUNCH_XINV
+        }
     }
     VIE_HIP(hipGetLastError());
     return VIE_OK;
@@ -941,19 +1034,38 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
         snprintf(key, sizeof key, "matvec esz=%d P=%dx%dx%d grid=%dx%dx%d nrhs=%d direct_z=%d split=%d",
                  (int)sizeof(cpx<R>), op->Px, op->Py, op->Pz, op->nx, op->ny, op->nz, nrhs, (int)op->direct_z,
                  (int)op->split_plane);
-        std::vector<int> choice;
-        if (!tune_lookup(key, &choice)) {
-            int t0, b0;
-            size_t l0;
-            fft_line_shape(op->px, sizeof(cpx<R>), &t0, &l0, &b0);
-            std::vector<std::vector<int>> cands;
-            for (int tp : {128, 256, 512})
+        int t0, b0;
+        size_t l0;
+        fft_line_shape(op->px, sizeof(cpx<R>), &t0, &l0, &b0);
+        std::vector<std::vector<int>> cands;
+        {
+            // plane pass: right-hand sides per workgroup (register pass) or threads (LDS pass);
+            // x passes: threads of the LDS kernels (the register and four-step kernels have none)
+            std::vector<int> pcand, xcand;
+            if (plane_reg<R>(op, nullptr, khat, nrhs, 0, s)) {
+                pcand.push_back(0);
+                for (int rb = 1; rb <= nrhs && rb <= 64; rb *= 2) pcand.push_back(rb);
+            } else {
+                pcand = {128, 256, 512};
+            }
+            const bool xfixed = op->xsplit > 1 || xline_reg<R>(op, -1, 0, nullptr, nullptr, nullptr, nullptr, s);
+            if (xfixed) {
+                xcand.push_back(0);
+            } else {
                 for (int tx : {t0 / 2, t0, 2 * t0}) {
                     int t, b;
                     size_t l;
                     if (tx < 64 || tx > 1024 || !fft_line_shape(op->px, sizeof(cpx<R>), &t, &l, &b, tx)) continue;
-                    cands.push_back({tp, tx});
+                    xcand.push_back(tx);
                 }
+            }
+            for (int tp : pcand)
+                for (int tx : xcand) cands.push_back({tp, tx});
+        }
+        std::vector<int> choice;
+        if (tune_lookup(key, &choice)) {
+            VIE_CHECK(tune_check_choice(key, choice, cands));
+        } else {
             double best = 1e300;
             for (auto &c : cands) {
                 double ms = 0;

@@ -27,6 +27,7 @@
 #include <utility>
 
 #include "fft_device.h"
+#include "reg_fft.h"
 
 #define LU_NB 32
 #define LU_TILE 64
@@ -965,19 +966,16 @@ __global__ void __launch_bounds__(256) k_invert_diag(cpx<R> *F, int m) {
     }
 }
 
-// LU of the batch [b0, b0 + nb) of stored blocks, all launches on stream `s`.
 template <class R>
 static cpx<R> *A_of(vie_pc pc) { return pc->factors.as<cpx<R>>(); }
 
+// LU with partial pivoting of nb column-major m x m blocks A (in place), all launches on
+// stream `s`; ns = sub-panels of LU_NB columns per macro panel.  ipiv (nb x m), linv
+// (nb x LU_NB^2) and moves (nb x LU_MOVES) are scratch; info[b] is set nonzero for a
+// singular block.
 template <class R>
-static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<R> *linv_all, int *moves_all,
-                                  hipStream_t s) {
-    const int m = pc->m;
-    cpx<R> *A = pc->factors.as<cpx<R>>() + (size_t)b0 * m * m;
-    int *ipiv = ipiv_all + (size_t)b0 * m;
-    int *moves = moves_all + (size_t)b0 * LU_MOVES;
-    int *info = pc->info.as<int>() + b0;
-    cpx<R> *linv = linv_all + (size_t)b0 * LU_NB * LU_NB;
+static vie_status lu_factor_blocks(int m, int nb, cpx<R> *A, int *ipiv, cpx<R> *linv, int *moves, int *info,
+                                   int ns, hipStream_t s) {
     auto panel = [&](int j0, int w) -> vie_status {
         ProfScope ps("lu_panel", s);
         const int mrem = m - j0;
@@ -1054,10 +1052,7 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
     // sub-panel first takes the updates of the earlier sub-panels of its macro panel (its
     // columns from row jr down), is factored, has its interchanges applied everywhere, and its
     // rows right of it take the same updates before the U12 solve; the trailing matrix is
-    // updated once per macro panel, with K = the macro panel's width.  Measured: FP32 gains
-    // from wider macro panels (fewer passes over the trailing matrix; 4 sub-panels: -13% update
-    // time at 1024 blocks of 768), FP64 does not (2: the matrix-core time dominates).
-    const int ns = sizeof(R) == 8 ? 2 : 4;
+    // updated once per macro panel, with K = the macro panel's width.
     for (int J0 = 0; J0 < m; J0 += ns * LU_NB) {
         int jend = J0;
         for (int i = 0; i < ns && J0 + i * LU_NB < m; ++i) {
@@ -1079,6 +1074,49 @@ static vie_status lu_factor_range(vie_pc pc, int b0, int nb, int *ipiv_all, cpx<
     return VIE_OK;
 }
 
+// Sub-panels per macro panel of the batched LU: the default, or with autotuning the fastest of
+// 1, 2, 4, 8 timed on a copy of the first min(nb, 256) blocks (one block per compute unit,
+// the LU's own launch shape), cached per (precision, m, block count).  Measured default: FP32
+// gains from wider macro panels (fewer passes over the trailing matrix; 4 sub-panels: -13%
+// update time at 1024 blocks of 768), FP64 does not (2: the matrix-core time dominates).
+template <class R>
+static vie_status lu_macro_panels(vie_pc pc, int *ipiv, cpx<R> *linv, int *moves, hipStream_t s, int *ns_out) {
+    const int m = pc->m, nb = pc->nstored;
+    int ns = sizeof(R) == 8 ? 2 : 4;
+    if (tune_enabled() && m > LU_NB) {
+        char key[128];
+        snprintf(key, sizeof key, "lu_factor real=%d m=%d blocks=%d", (int)sizeof(R) * 8, m, nb);
+        std::vector<std::vector<int>> cands;
+        for (int c : {1, 2, 4, 8})
+            if ((c - 1) * LU_NB < m) cands.push_back({c});
+        std::vector<int> choice;
+        if (tune_lookup(key, &choice)) {
+            VIE_CHECK(tune_check_choice(key, choice, cands));
+            ns = choice[0];
+        } else {
+            const int sample = std::min(nb, 256);
+            const size_t bytes = sizeof(cpx<R>) * (size_t)sample * m * m;
+            DevBuf copy, info;
+            VIE_CHECK(copy.ensure(bytes));
+            VIE_CHECK(info.ensure(sizeof(int) * (size_t)sample));
+            double best = 1e300;
+            for (auto &cv : cands) {
+                const int c = cv[0];
+                double ms = 0;
+                VIE_CHECK(tune_time(s, 1, [&]() -> vie_status {
+                    VIE_HIP(hipMemcpyAsync(copy.p, pc->factors.p, bytes, hipMemcpyDeviceToDevice, s));
+                    VIE_HIP(hipMemsetAsync(info.p, 0, sizeof(int) * (size_t)sample, s));
+                    return lu_factor_blocks<R>(m, sample, copy.as<cpx<R>>(), ipiv, linv, moves, info.as<int>(), c, s);
+                }, &ms));
+                if (ms < best) best = ms, ns = c;
+            }
+            tune_store(key, {ns}, best, (int)cands.size());
+        }
+    }
+    *ns_out = ns;
+    return VIE_OK;
+}
+
 // Batched LU of every stored block.
 template <class R>
 static vie_status lu_factor(vie_pc pc, hipStream_t s) {
@@ -1087,8 +1125,11 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
     VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
     VIE_CHECK(moves.ensure(sizeof(int) * (size_t)nb * LU_MOVES));
+    int ns = 0;
+    VIE_CHECK(lu_macro_panels<R>(pc, ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(), s, &ns));
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
-    VIE_CHECK(lu_factor_range<R>(pc, 0, nb, ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(), s));
+    VIE_CHECK(lu_factor_blocks<R>(m, nb, A_of<R>(pc), ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(),
+                                  pc->info.as<int>(), ns, s));
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());
@@ -1148,6 +1189,78 @@ __global__ void k_box_ifft(const cpx<R> *work, cpx<R> *zv, const int *boxes, con
     cpx<R> *dst = zv + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
     R sc = R(1) / R(n);
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = sc * res[i];
+}
+
+// The box line transforms above on registers for the box lengths they are instantiated for:
+// the same lines, maps and scaling, one line per workgroup of L / 16 threads.
+template <class R, int R1, int R2, int R3, int R4>
+__global__ void __launch_bounds__((rfft::Radices<R1, R2, R3, R4>::T))
+k_box_fft_reg(const cpx<R> *r, cpx<R> *work, const int *boxes, const int *rows, int mr, int nx, int ny, int nz, int by,
+              int bz, int nboxes, const cpx<R> *tw, const uint32_t *gate, uint32_t epoch) {
+    if (gate && *gate != epoch) return;
+    constexpr int n = rfft::Radices<R1, R2, R3, R4>::L;
+    const long long line = blockIdx.x;  // ((rhs * nboxes + box) * mr + i)
+    const int row = rows[(int)(line % mr)];
+    const int box = (int)((line / mr) % nboxes);
+    const long long rhs = line / ((long long)mr * nboxes);
+    const int comp = row / (by * bz), y = row % by, z = (row / by) % bz;
+    const int *bx = boxes + 6 * box;
+    const cpx<R> *src = r + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
+    cpx<R> *dst = work + line * n;
+    rfft::reg_line<R, R1, R2, R3, R4, false>(tw, [&](int i) { return src[i]; }, [&](int i, cpx<R> v) { dst[i] = v; });
+}
+
+template <class R, int R1, int R2, int R3, int R4>
+__global__ void __launch_bounds__((rfft::Radices<R1, R2, R3, R4>::T))
+k_box_ifft_reg(const cpx<R> *work, cpx<R> *zv, const int *boxes, const int *rows, int mr, int nx, int ny, int nz,
+               int by, int bz, int nboxes, const cpx<R> *tw) {
+    constexpr int n = rfft::Radices<R1, R2, R3, R4>::L;
+    const long long line = blockIdx.x;
+    const int row = rows[(int)(line % mr)];
+    const int box = (int)((line / mr) % nboxes);
+    const long long rhs = line / ((long long)mr * nboxes);
+    const int comp = row / (by * bz), y = row % by, z = (row / by) % bz;
+    const int *bx = boxes + 6 * box;
+    const cpx<R> *src = work + line * n;
+    cpx<R> *dst = zv + rhs * 3LL * nx * ny * nz + (((long long)comp * nz + bx[2] + z) * ny + bx[1] + y) * nx + bx[0];
+    const R sc = R(1) / R(n);
+    rfft::reg_line<R, R1, R2, R3, R4, true>(tw, [&](int i) { return src[i]; },
+                                            [&](int i, cpx<R> v) { dst[i] = sc * v; });
+}
+
+// Launch the register box transform for lengths 1024 .. 8192 (16384 in complex64); false for
+// any other length (the LDS Stockham kernels run).  inverse: k_box_ifft_reg (gate unused).
+template <class R>
+static bool box_fft_reg(bool inverse, const FftPlan &p, long long lines, const cpx<R> *in, cpx<R> *out,
+                        const int *boxes, const int *rows, int mr, int nx, int ny, int nz, int by, int bz, int nboxes,
+                        const uint32_t *gate, uint32_t epoch, hipStream_t s) {
+    const cpx<R> *tw = TwTable<R>::get(p);
+#define VIE_BOX_REG(R1, R2, R3, R4)                                                                                    \
+    {                                                                                                                  \
+        typedef rfft::Radices<R1, R2, R3, R4> RD;                                                                      \
+        const size_t lds = sizeof(cpx<R>) * RD::L;                                                                     \
+        if (inverse) {                                                                                                 \
+            vie_lds_attr((const void *)k_box_ifft_reg<R, R1, R2, R3, R4>, lds);                                        \
+            hipLaunchKernelGGL((k_box_ifft_reg<R, R1, R2, R3, R4>), dim3((unsigned)lines), dim3(RD::T), lds, s, in,    \
+                               out, boxes, rows, mr, nx, ny, nz, by, bz, nboxes, tw);                                  \
+        } else {                                                                                                       \
+            vie_lds_attr((const void *)k_box_fft_reg<R, R1, R2, R3, R4>, lds);                                         \
+            hipLaunchKernelGGL((k_box_fft_reg<R, R1, R2, R3, R4>), dim3((unsigned)lines), dim3(RD::T), lds, s, in,     \
+                               out, boxes, rows, mr, nx, ny, nz, by, bz, nboxes, tw, gate, epoch);                     \
+        }                                                                                                              \
+        return true;                                                                                                   \
+    }
+    switch (p.L) {
+        case 1024: VIE_BOX_REG(16, 8, 8, 1)
+        case 2048: VIE_BOX_REG(16, 16, 8, 1)
+        case 4096: VIE_BOX_REG(16, 16, 16, 1)
+        case 8192: VIE_BOX_REG(16, 16, 16, 2)
+        case 16384:
+            if constexpr (sizeof(R) == 4) VIE_BOX_REG(16, 16, 16, 4)
+            return false;
+        default: return false;
+    }
+#undef VIE_BOX_REG
 }
 
 // 2-level apply, y stage.  Forward: from the x-DFT lines x1[rb][(a, y, z)][kx] (rb = rhs*nboxes
@@ -1283,7 +1396,9 @@ static vie_status apply2_t(vie_pc pc, PcWs *ws, const cpx<R> *r, cpx<R> *z, int 
     vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                            \
     hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines1), dim3(thr), lds, s, r, w1, dboxes, rows1, m1, op->nx, \
                        op->ny, op->nz, by, bz, pc->nboxes, pc->pxb, nullptr, 0u)
-        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
+        if (!box_fft_reg<R>(false, pc->pxb, lines1, r, w1, dboxes, rows1, m1, op->nx, op->ny, op->nz, by, bz,
+                            pc->nboxes, nullptr, 0u, s))
+            VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
 #undef LAUNCH_BOX_FFT
         VIE_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_box_yfft<R>, dim3(ygrid), dim3(256), ylds, s, w1, w2, bx, by, bz, pc->pyb2, 0);
@@ -1301,7 +1416,9 @@ static vie_status apply2_t(vie_pc pc, PcWs *ws, const cpx<R> *r, cpx<R> *z, int 
     vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                           \
     hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines1), dim3(thr), lds, s, w1, z, dboxes, rows1, m1,     \
                        op->nx, op->ny, op->nz, by, bz, pc->nboxes, pc->pxb)
-        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
+        if (!box_fft_reg<R>(true, pc->pxb, lines1, w1, z, dboxes, rows1, m1, op->nx, op->ny, op->nz, by, bz,
+                            pc->nboxes, nullptr, 0u, s))
+            VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
 #undef LAUNCH_BOX_IFFT
     }
     VIE_HIP(hipGetLastError());
@@ -1353,7 +1470,9 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                       \
     hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, r, work, dboxes, rows, m, \
                        op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, nullptr, 0u)
-        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
+        if (!box_fft_reg<R>(false, pc->pxb, lines, r, work, dboxes, rows, m, op->nx, op->ny, op->nz, pc->by, pc->bz,
+                            pc->nboxes, nullptr, 0u, s))
+            VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT);
 #undef LAUNCH_BOX_FFT
     }
     VIE_HIP(hipGetLastError());
@@ -1365,7 +1484,9 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     vie_lds_attr((const void *)k_box_fft<R, B>, lds);                                                             \
     hipLaunchKernelGGL((k_box_fft<R, B>), dim3((unsigned)clines), dim3(thr), lds, s, r, workc, dboxes, rows + m, \
                        mc, op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb, flag, ws->epoch)
-        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT_C);
+        if (!box_fft_reg<R>(false, pc->pxb, clines, r, workc, dboxes, rows + m, mc, op->nx, op->ny, op->nz, pc->by,
+                            pc->bz, pc->nboxes, flag, ws->epoch, s))
+            VIE_BPT_SWITCH(bpt, LAUNCH_BOX_FFT_C);
 #undef LAUNCH_BOX_FFT_C
         VIE_HIP(hipGetLastError());
         const cpx<R> *chan = sizeof(R) == 8 ? (const cpx<R> *)pc->chan64.p : (const cpx<R> *)pc->chan32.p;
@@ -1386,7 +1507,9 @@ static vie_status apply_t(vie_pc pc, const cpx<R> *r, cpx<R> *z, int nrhs, hipSt
     vie_lds_attr((const void *)k_box_ifft<R, B>, lds);                                                      \
     hipLaunchKernelGGL((k_box_ifft<R, B>), dim3((unsigned)lines), dim3(thr), lds, s, work, z, dboxes, rows, m, \
                        op->nx, op->ny, op->nz, pc->by, pc->bz, pc->nboxes, pc->pxb)
-        VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
+        if (!box_fft_reg<R>(true, pc->pxb, lines, work, z, dboxes, rows, m, op->nx, op->ny, op->nz, pc->by, pc->bz,
+                            pc->nboxes, nullptr, 0u, s))
+            VIE_BPT_SWITCH(bpt, LAUNCH_BOX_IFFT);
 #undef LAUNCH_BOX_IFFT
     }
     VIE_HIP(hipGetLastError());

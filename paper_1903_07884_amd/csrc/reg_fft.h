@@ -28,6 +28,14 @@ __host__ __device__ __forceinline__ void sfor(F &&f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores issued before it
+// stay in flight (for kernels whose workgroups exchange nothing through global memory).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- constexpr cos / sin
 constexpr double kQuarterPi = 0.78539816339744830961566084581987572;
 
@@ -164,5 +172,83 @@ struct Dft {
         });
     }
 };
+
+// ---------------------------------------------------------------- line transforms
+// Register Stockham transform of one line per workgroup, length L = R1 R2 R3 R4 fixed at
+// compile time (radices <= 16, trailing 1s unused), on T = L / max radix threads.  Step s
+// (radix Rs, Ns = R1..R(s-1)) takes butterfly j in [0, L/Rs): inputs j + r L/Rs, times
+// W_L^{r k L/(Ns Rs)} with k = j mod Ns (table tw of W_L^q), a length-Rs DFT on registers,
+// outputs (j / Ns) Ns Rs + k + r Ns.  The first step reads the line through ld(i), the last
+// writes it through st(i, v), both in natural order and coalesced (consecutive threads take
+// consecutive i); the steps between exchange through one LDS line of L entries (every thread
+// reads its inputs, barrier, writes its outputs).
+template <int R1, int R2, int R3, int R4>
+struct Radices {
+    static constexpr int L = R1 * R2 * R3 * R4;
+    static constexpr int RMAX = R1 > R2 ? (R1 > R3 ? (R1 > R4 ? R1 : R4) : (R3 > R4 ? R3 : R4))
+                                        : (R2 > R3 ? (R2 > R4 ? R2 : R4) : (R3 > R4 ? R3 : R4));
+    static constexpr int T = L / RMAX;  // threads
+    static constexpr int NSTEP = 1 + (R2 > 1) + (R3 > 1) + (R4 > 1);
+};
+
+// One step: SRC / DST 0 = LDS line, 1 = device memory (through the ld / st callbacks).
+template <class R, int L, int RS, int NS, int T, bool INV, class Ld, class St>
+__device__ __forceinline__ void xstep(const cpx<R> *__restrict__ tw, Ld ld, St st, bool sync_between) {
+    constexpr int NB = L / RS, BPT = NB / T;
+    static_assert(NB % T == 0, "whole butterflies per thread");
+    cpx<R> v[BPT][RS];
+    const int t = threadIdx.x;
+    sfor<BPT>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int j = t + b * T;
+        sfor<RS>([&](auto rc) { v[b][decltype(rc)::value] = ld(j + decltype(rc)::value * NB); });
+        if constexpr (NS > 1) {
+            const int k = j % NS;
+            sfor<RS - 1>([&](auto rc) {
+                constexpr int r = decltype(rc)::value + 1;
+                const cpx<R> w = tw[r * k * (L / (NS * RS))];
+                v[b][r] = v[b][r] * (INV ? conjg(w) : w);
+            });
+        }
+        Dft<R, RS, INV>::run(v[b]);
+    });
+    if (sync_between) lds_barrier();
+    sfor<BPT>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int j = t + b * T, k = j % NS, base = (j / NS) * NS * RS + k;
+        sfor<RS>([&](auto rc) { st(base + decltype(rc)::value * NS, v[b][decltype(rc)::value]); });
+    });
+}
+
+
+// The whole transform of one line (see above); vie_smem holds the LDS line.
+template <class R, int R1, int R2, int R3, int R4, bool INV, class Ld, class St>
+__device__ __forceinline__ void reg_line(const cpx<R> *__restrict__ tw, Ld ld_first, St st_last) {
+    typedef Radices<R1, R2, R3, R4> RD;
+    constexpr int L = RD::L, T = RD::T;
+    cpx<R> *S = reinterpret_cast<cpx<R> *>(vie_smem);
+    auto ld_lds = [&](int i) -> cpx<R> { return S[i]; };
+    auto st_lds = [&](int i, cpx<R> v) { S[i] = v; };
+    constexpr int N2 = R1, N3 = R1 * R2, N4 = R1 * R2 * R3;
+    if constexpr (RD::NSTEP == 2) {
+        xstep<R, L, R1, 1, T, INV>(tw, ld_first, st_lds, false);
+        lds_barrier();
+        xstep<R, L, R2, N2, T, INV>(tw, ld_lds, st_last, false);
+    } else if constexpr (RD::NSTEP == 3) {
+        xstep<R, L, R1, 1, T, INV>(tw, ld_first, st_lds, false);
+        lds_barrier();
+        xstep<R, L, R2, N2, T, INV>(tw, ld_lds, st_lds, true);
+        lds_barrier();
+        xstep<R, L, R3, N3, T, INV>(tw, ld_lds, st_last, false);
+    } else {
+        xstep<R, L, R1, 1, T, INV>(tw, ld_first, st_lds, false);
+        lds_barrier();
+        xstep<R, L, R2, N2, T, INV>(tw, ld_lds, st_lds, true);
+        lds_barrier();
+        xstep<R, L, R3, N3, T, INV>(tw, ld_lds, st_lds, true);
+        lds_barrier();
+        xstep<R, L, R4, N4, T, INV>(tw, ld_lds, st_last, false);
+    }
+}
 
 }  // namespace rfft

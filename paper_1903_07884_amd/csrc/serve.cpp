@@ -142,6 +142,11 @@ bool make_room(vie_server srv, uint64_t need, const Entry *keep) {
     return true;
 }
 
+// The operator keeps a complex64 copy: complex64 products (mixed mode) or bfloat16 factors.
+bool op_c64(const Req *r) {
+    return r->so.mode == VIE_MODE_MIXED || (r->precond && r->pco.factor_prec == VIE_BF16C);
+}
+
 // Admit the first admissible queued request (with the requests merged into it).  Lock held.
 bool pick(vie_server srv, Batch *b) {
     for (size_t qi = 0; qi < srv->queue.size(); ++qi) {
@@ -160,12 +165,23 @@ bool pick(vie_server srv, Batch *b) {
         for (Entry *e : srv->cache)
             if (e->key == r->key) ent = e;
         if (ent && !ent->ready) continue;  // another worker is building it: later requests may go
-        uint64_t resident = 0, build = 0, run = 0;
-        const bool mixed = r->so.mode == VIE_MODE_MIXED;
-        if (request_footprint(r->grid, mixed, r->precond ? &r->pco : nullptr, R, &r->so, &resident, &build, &run) !=
-            VIE_OK)
-            resident = build = run = 0;  // arguments were checked on submit
-        const uint64_t need = run + (ent ? 0 : resident + build);
+        // Merged requests are dropped from the end while the batch could not fit even with every
+        // idle entry evicted: the head alone always fits an empty server (checked on submit), so
+        // a merge never holds it back for good.
+        uint64_t evictable = 0;
+        for (Entry *e : srv->cache)
+            if (e->users == 0 && e->ready && e != ent) evictable += e->bytes;
+        const uint64_t avail = srv->budget + evictable > srv->committed ? srv->budget + evictable - srv->committed : 0;
+        uint64_t resident = 0, build = 0, run = 0, need = 0;
+        for (;;) {
+            if (request_footprint(r->grid, op_c64(r), r->precond ? &r->pco : nullptr, R, &r->so, &resident, &build,
+                                  &run) != VIE_OK)
+                resident = build = run = 0;  // arguments were checked on submit
+            need = run + (ent ? 0 : resident + build);
+            if (need <= avail || idx.size() == 1) break;
+            R -= srv->queue[idx.back()]->nrhs;
+            idx.pop_back();
+        }
         if (make_room(srv, need, ent)) {
             // released buffers cached for reuse hold device memory too: past the budget the worker
             // returns them to the driver (outside this lock), so the runtime's own allocations at
@@ -306,7 +322,7 @@ vie_status build_entry(vie_server srv, Batch *b, hipStream_t s) {
     vie_op op = nullptr;
     vie_pc pc = nullptr;
     vie_create_opts co{};
-    co.build_c64 = r0->so.mode == VIE_MODE_MIXED;
+    co.build_c64 = op_c64(r0);
     vie_status st = vie_create(r0->grid, r0->delta, r0->kb, r0->chi.data(), &co, s, &op);
     if (st >= 0 && r0->precond) st = precond_setup(op, &r0->pco, s, &pc);
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -530,8 +546,8 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
         return vs;
     }
     uint64_t resident = 0, build = 0, run = 0;
-    const vie_status fs = request_footprint(r->grid, r->so.mode == VIE_MODE_MIXED, r->precond ? &r->pco : nullptr,
-                                            r->nrhs, &r->so, &resident, &build, &run);
+    const vie_status fs = request_footprint(r->grid, op_c64(r), r->precond ? &r->pco : nullptr, r->nrhs, &r->so,
+                                            &resident, &build, &run);
     if (fs < 0) {
         delete r;
         return fs;
@@ -545,7 +561,7 @@ extern "C" vie_status vie_server_submit(vie_server srv, const vie_request *req, 
     char buf[256];
     const uint64_t hchi = fnv1a(r->chi.data(), sizeof(double) * r->chi.size());
     snprintf(buf, sizeof buf, "%dx%dx%d|%a|%a|%016llx|%d|%d", r->grid[0], r->grid[1], r->grid[2], r->delta, r->kb,
-             (unsigned long long)hchi, r->precond, r->so.mode == VIE_MODE_MIXED);
+             (unsigned long long)hchi, r->precond, (int)op_c64(r));
     r->key = buf;
     if (r->precond) {
         const vie_pc_opts &p = r->pco;

@@ -40,6 +40,14 @@ void tune_store(const std::string &key, const std::vector<int> &choice, double m
     g_cache[key] = Entry{choice, ms, candidates};
 }
 
+vie_status tune_check_choice(const std::string &key, const std::vector<int> &choice,
+                             const std::vector<std::vector<int>> &cands) {
+    for (auto &c : cands)
+        if (c == choice) return VIE_OK;
+    vie_set_error("autotune entry '" + key + "' holds a choice that is not one of this shape's candidates");
+    return VIE_EARG;
+}
+
 vie_status tune_time(hipStream_t s, int reps, const std::function<vie_status()> &run, double *ms) {
     ++g_active;
     struct Guard {
@@ -70,6 +78,19 @@ vie_status tune_time(hipStream_t s, int reps, const std::function<vie_status()> 
 extern "C" vie_status vie_autotune(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_on = enable != 0;
+    return VIE_OK;
+}
+
+extern "C" vie_status vie_autotune_set(const char *key, const int32_t *choice, int32_t n) {
+    if (!key || n < 0 || n > 16 || (n > 0 && !choice)) {
+        vie_set_error("vie_autotune_set: needs a key and 0..16 values");
+        return VIE_EARG;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (n == 0)
+        g_cache.erase(key);
+    else
+        g_cache[key] = Entry{std::vector<int>(choice, choice + n), 0.0, 0};
     return VIE_OK;
 }
 

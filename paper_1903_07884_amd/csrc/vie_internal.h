@@ -337,6 +337,9 @@ bool tune_active();  // candidates are running: profiling records nothing
 bool tune_lookup(const std::string &key, std::vector<int> *choice);
 void tune_store(const std::string &key, const std::vector<int> &choice, double ms, int candidates);
 // one warm-up run, then `reps` runs bracketed by events on `s`; *ms = time per run
+// VIE_EARG unless `choice` (from the cache, possibly set by vie_autotune_set) is one of `cands`.
+vie_status tune_check_choice(const std::string &key, const std::vector<int> &choice,
+                             const std::vector<std::vector<int>> &cands);
 vie_status tune_time(hipStream_t s, int reps, const std::function<vie_status()> &run, double *ms);
 
 // ---------------------------------------------------------------- launchers

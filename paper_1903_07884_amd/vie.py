@@ -19,13 +19,13 @@ VIE_OK, VIE_NOT_CONVERGED = 0, 1
 STATUS = {0: 'VIE_OK', 1: 'VIE_NOT_CONVERGED', -1: 'VIE_EARG', -2: 'VIE_EOOM', -3: 'VIE_EDEVICE',
           -4: 'VIE_ESINGULAR', -5: 'VIE_ENONFINITE', -6: 'VIE_EBUDGET'}
 HOMOG = {'none': 0, 'mode': 1, 'mean': 2, 'realmean': 3}
-MODE = {'fp64': 0, 'mixed': 1}
+MODE = {'fp64': 0, 'mixed': 1, 'mixed_pc': 2}
 
 EXPORTS = ('vie_create', 'vie_destroy', 'vie_generator', 'vie_rhs', 'vie_matvec', 'vie_matvec_noalloc',
            'precond_setup',
            'precond_info', 'precond_destroy', 'precond_apply', 'vie_solve', 'vie_profile_begin',
            'vie_profile_kernel', 'vie_profile_end', 'vie_last_error', 'vie_footprint', 'vie_autotune',
-           'vie_autotune_report', 'vie_device_bytes', 'vie_trim', 'vie_server_create', 'vie_server_submit',
+           'vie_autotune_report', 'vie_autotune_set', 'vie_device_bytes', 'vie_trim', 'vie_server_create', 'vie_server_submit',
            'vie_server_wait', 'vie_server_query', 'vie_server_info_get', 'vie_server_destroy')
 
 
@@ -122,6 +122,7 @@ def load(path=None):
     lib.vie_footprint.argtypes = [vp, ctypes.POINTER(PcOpts), i32, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(ctypes.c_uint64)]
     lib.vie_autotune_report.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.vie_autotune_set.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32), i32]
     lib.vie_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     lib.vie_server_submit.argtypes = [vp, ctypes.POINTER(Request), vp, ctypes.POINTER(SolveStats),
                                       ctypes.POINTER(ctypes.c_int64)]
@@ -291,7 +292,9 @@ class Preconditioner:
 
 
 def solve(op, pc, b, x, nrhs=1, tol=1e-6, restart=50, maxit=5000, mode='fp64', x0_given=False, stream=None):
-    """vie_solve; returns a list of per-RHS stats dicts (status VIE_NOT_CONVERGED does not raise)."""
+    """vie_solve; returns a list of per-RHS stats dicts (status VIE_NOT_CONVERGED does not raise).
+    ``mode``: 'fp64', 'mixed' (complex64 products and preconditioner) or 'mixed_pc' (complex64
+    preconditioner only)."""
     import torch
     lib = load()
     o = SolveOpts(float(tol), int(restart), int(maxit), MODE[mode], 1 if x0_given else 0)
@@ -351,6 +354,24 @@ def autotune_report():
     buf = ctypes.create_string_buffer(max(int(need.value), 1))
     _check(lib.vie_autotune_report(buf, len(buf), ctypes.byref(need)))
     return buf.value.decode()
+
+
+def autotune_set(key, choice):
+    """Store `choice` (a sequence of ints; empty removes the entry) under an autotuner key as
+    autotune_report prints it (vie_autotune_set)."""
+    vals = (ctypes.c_int32 * max(len(choice), 1))(*choice)
+    _check(load().vie_autotune_set(key.encode(), vals, len(choice)))
+
+
+def autotune_entries():
+    """The autotuner cache as {key: [values]}."""
+    out = {}
+    for line in autotune_report().splitlines():
+        if ' -> ' not in line:
+            continue
+        key, rest = line.split(' -> ', 1)
+        out[key] = [int(v) for v in rest.split('  (', 1)[0].split()]
+    return out
 
 
 def profile_begin():

@@ -153,14 +153,37 @@ def random_field(shape, tag):
 
 # ---------------------------------------------------------------- serving stream
 SERVE_TYPES = ('waveguide', 'bragg', 'coupler')
-SERVE_NX = (256, 512, 1024)
-SERVE_CROSS = ((16, 8), (24, 8), (32, 8))
+SERVE_NX = (256, 512, 1024, 2048, 4096, 8192)
+SERVE_CROSS = ((16, 8), (24, 8), (32, 8), (48, 8))
+SERVE_DISK = dict(geometry='disk', grid=(160, 160, 8), radius=2e-6)
+SERVE_REDUCE_FROM_NX = 2048   # longer devices are served with the memory-reduced preconditioner
 
 
-def serving_devices(delta=25e-9):
-    """Device catalogue of the serving stream: geometry x length x cross-section."""
-    return [dict(geometry=t, grid=(nx, ny, nz), delta=delta)
-            for t in SERVE_TYPES for nx in SERVE_NX for (ny, nz) in SERVE_CROSS]
+def serving_devices(delta=25e-9, small=False):
+    """Device catalogue of the serving stream: geometry x length x cross-section (lengths
+    256-8192 voxels, cross-sections 16x8 to 48x8 at 25 nm), plus the 2 um Si disk on a
+    160x160x8 grid.  small=True keeps lengths up to 1024 and cross-sections up to 32x8 (no
+    disk), a catalogue whose every device fits the cache at once."""
+    nxs = SERVE_NX[:3] if small else SERVE_NX
+    cross = SERVE_CROSS[:3] if small else SERVE_CROSS
+    out = [dict(geometry=t, grid=(nx, ny, nz), delta=delta) for t in SERVE_TYPES for nx in nxs for (ny, nz) in cross]
+    if not small:
+        out.append(dict(SERVE_DISK, delta=delta))
+    return out
+
+
+def device_solver(dev):
+    """Solver settings of a catalogue device (mixed precision, complex64 factors, GMRES(50)):
+    real-mean homogenisation for gratings; the memory-reduced preconditioner (tolerance 1e-3,
+    centre reading of the proxy column) from SERVE_REDUCE_FROM_NX voxels on; the disk with the
+    2-level circulant over its modal-average contrast, solved to 1e-4 as the paper reports its
+    disks.  Returns keyword settings by name (no arithmetic)."""
+    if dev['geometry'] == 'disk':
+        return dict(homog='mode', levels=2, tol=1e-4)
+    kw = dict(homog='realmean' if dev['geometry'] == 'bragg' else 'none', tol=1e-6)
+    if dev['grid'][0] >= SERVE_REDUCE_FROM_NX:
+        kw.update(reduce_tol=1e-3, proxy='centre')
+    return kw
 
 
 def coupler_cores(ny):
@@ -176,6 +199,8 @@ def device_chi(dev):
         return waveguide(grid)
     if dev['geometry'] == 'bragg':
         return bragg(grid, delta)
+    if dev['geometry'] == 'disk':
+        return disk(grid, delta, dev['radius'])
     return coupler(grid, cores=coupler_cores(grid[1]))
 
 
@@ -201,11 +226,12 @@ def device_sources(dev, count, tag):
     return out
 
 
-def serving_stream(n, rate, tag, max_rhs=16):
+def serving_stream(n, rate, tag, max_rhs=16, ndev=None):
     """Seeded request stream: Poisson arrivals at `rate` per second, a uniform catalogue device
-    and U{1..max_rhs} right-hand sides per request.  Returns [(t_arrival_s, device_index, nrhs)]."""
+    (of `ndev`, default the full catalogue) and U{1..max_rhs} right-hand sides per request.
+    Returns [(t_arrival_s, device_index, nrhs)]."""
     g = rng(tag)
-    ndev = len(serving_devices())
+    ndev = ndev or len(serving_devices())
     t = 0.0
     out = []
     for _ in range(n):

@@ -142,10 +142,12 @@ def test_batched_fp64_solve_matches_oracle_per_column(gpu_lib):
         assert abs(st[q]['iters'] - info['iters']) <= max(1, info['iters'] // 50)
 
 
-def test_batched_mixed_solve_matches_oracle_per_column(gpu_lib):
+@pytest.mark.parametrize("mode", ['mixed', 'mixed_pc'])
+def test_batched_mixed_solve_matches_oracle_per_column(gpu_lib, mode):
     """48x8x2 Bragg-like grating, two x-boxes with real-mean contrast, complex64 factors,
-    8 right-hand sides in one lockstep mixed-precision solve to 1e-6: every column's FP64
-    residual evaluated by the oracle, and its error against the dense direct solution."""
+    8 right-hand sides in one lockstep mixed-precision solve to 1e-6 (complex64 products and
+    preconditioner, or the preconditioner alone in complex64): every column's FP64 residual
+    evaluated by the oracle, and its error against the dense direct solution."""
     import torch
     grid, delta = (48, 8, 2), 50e-9
     nx, ny, nz = grid
@@ -163,13 +165,13 @@ def test_batched_mixed_solve_matches_oracle_per_column(gpu_lib):
     pc = gpu_lib.Preconditioner(op, homog='realmean', boxes=boxes, factor_prec=gpu_lib.VIE_C64)
     Bd = _to_dev(B)
     Xd = torch.zeros_like(Bd)
-    st = gpu_lib.solve(op, pc, Bd, Xd, nrhs=R, tol=1e-6, mode='mixed')
+    st = gpu_lib.solve(op, pc, Bd, Xd, nrhs=R, tol=1e-6, mode=mode)
     X = Xd.cpu().numpy()
     for q in range(R):
         res = np.linalg.norm(B[q] - A @ X[q]) / np.linalg.norm(B[q])
         err = _rel(X[q], X_ref[q])
-        print('batched mixed column %d: iters %d, oracle-evaluated FP64 residual %.2e, error vs the FP64 '
-              'oracle solution %.2e' % (q, st[q]['iters'], res, err))
+        print('batched %s column %d: iters %d, oracle-evaluated FP64 residual %.2e, error vs the FP64 '
+              'oracle solution %.2e' % (mode, q, st[q]['iters'], res, err))
         assert st[q]['status'] == 0 and res <= 1e-6 and err < 1e-4
 
 

@@ -315,6 +315,59 @@ def test_admission_returns_cached_blocks_past_the_budget(gpu_lib):
         assert _oracle_relres(d, x, _e(d, 1, 90 + k))[0] <= 1e-10 * 1.01
 
 
+def test_merge_past_the_budget_does_not_hold_the_queue(gpu_lib):
+    """Regression: two queued 2-RHS requests of one device whose merged 4-RHS batch exceeds the
+    budget (each alone fits), with eight small requests behind the first.  The scheduler once
+    kept trying the merged batch at the head of the queue after the head had been overtaken its
+    maximum number of times, and nothing was admitted again.  Now merged requests that cannot
+    fit are left queued: every request completes, the two 2-RHS requests are never admitted as
+    one batch, committed bytes stay within the budget, and every result passes the oracle's
+    residual check."""
+    import ctypes
+    lib = gpu_lib.load()
+    devs = _devices()
+    g, blk = devs['guide'], devs['block']
+    nx, ny, nz = g['grid']
+    n3 = 3 * nx * ny * nz
+    pc = gpu_lib.PcOpts(0, 0, None, 0, 0.0, 0, 0, 0, 0)
+    so = gpu_lib.SolveOpts(1e-10, 50, 5000, 0, 0)
+    op = gpu_lib.Operator(g['grid'], g['voxel_size'], g['k_background'], g['chi'])
+    fp = {}
+    for R in (2, 3):
+        need = ctypes.c_uint64()
+        assert lib.vie_footprint(op.h, ctypes.byref(pc), R, ctypes.byref(so), ctypes.byref(need)) == 0
+        fp[R] = int(need.value)
+    op.close()
+    # the server adds the incident fields and right-hand sides (2 x 16 bytes per entry) to the
+    # footprint: 2 right-hand sides fit, 4 do not
+    budget = fp[2] + 2 * 32 * n3 + (fp[3] - fp[2])
+    srv = gpu_lib.Server(workers=1, max_batch_rhs=64, hbm_budget=budget)
+    # a first request (another guide: its build and solve) keeps the one worker busy while the
+    # queue forms
+    blocker = dict(g)
+    blocker['chi'] = g['chi'] * 1.3
+    subs = [(blocker, 1, 1e-12, 200)]
+    subs.append((g, 2, 1e-10, 201))
+    for k in range(8):  # eight different small devices (contrast scaled): no merging among them
+        d = dict(blk)
+        d['chi'] = blk['chi'] * (1.0 + 0.05 * k)
+        subs.append((d, 1, 1e-10, 210 + k))
+    subs.append((g, 2, 1e-10, 202))
+    rids = [srv.submit(e_inc=_e(d, R, seed), tol=tol, **d) for d, R, tol, seed in subs]
+    out = [srv.wait(r) for r in rids]
+    info = srv.info()
+    srv.close()
+    print('budget %d (2 RHS: %d + %d): %s' % (budget, fp[2], 2 * 32 * n3, info))
+    assert info['completed'] == len(subs)
+    assert info['peak_committed_bytes'] <= budget
+    for (d, R, tol, seed), (x, st, tm) in zip(subs, out):
+        assert all(q['status'] == 0 for q in st)
+        assert np.all(_oracle_relres(d, x, _e(d, R, seed)) <= tol * 1.01)
+    # the second 2-RHS request either ran on its own or joined the first one's slots once those
+    # had ended (a join takes freed slots, no new memory); it was never admitted merged with it
+    assert out[-1][2]['joined'] == 1 or (out[1][2]['merged'] == 1 and out[-1][2]['merged'] == 1)
+
+
 def test_submit_rejects_bad_solver_settings(gpu_lib):
     """Solver settings are validated on submit, as vie_solve does (unknown mode, tol, maxit)."""
     g = _devices()['guide']
