@@ -141,9 +141,15 @@ def copy_gbps(dev, nbytes=1 << 30, reps=5):
     return 2 * nbytes / best / 1e9
 
 
-def counter_traffic(kernel, workload_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the sources."""
-    path = os.path.join(ROOT, 'profiles', '%s_c%d_counters.txt' % (kernel, workload_tag))
+WORKLOAD_FILES = {2: 'guide_2048x16x8', 3: 'grating_4096x24x8', 4: 'coupler_1024x48x8', 5: 'disk_160x160x8'}
+
+
+def counter_traffic(kernel, workload_tag, factor='c128'):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel, workload
+    and factor precision, if it matches the sources."""
+    prec = {'c128': 'fp64', 'c64': 'c64', 'bf16': 'bf16'}.get(factor, factor)
+    path = os.path.join(ROOT, 'profiles', '%s_%s_%s_counters.txt' % (kernel, WORKLOAD_FILES.get(workload_tag, '?'),
+                                                                     prec))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -404,13 +410,13 @@ def roofline_of(kern, models, mode, dev, copy=True):
     elif unit == 'flops':
         achieved = amount / avg_s / 1e12
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=peak, unit='TFLOP/s', frac=achieved / peak,
-                    traffic=counter_traffic(dom, models.get('_tag')), per_launch_flops=amount)
+                    traffic=counter_traffic(dom, models.get('_tag'), models.get('_factor')), per_launch_flops=amount)
         if dom == 'matvec_plane' and '_plane_bytes' in models:
             roof['hbm_gbps_algorithmic'] = models['_plane_bytes'] / avg_s / 1e9
     else:
         achieved = amount / avg_s / 1e9
         roof = dict(kernel=dom, bound=bound, achieved=achieved, peak=HBM_PEAK_GBS, unit='GB/s',
-                    frac=achieved / HBM_PEAK_GBS, traffic=counter_traffic(dom, models.get('_tag')),
+                    frac=achieved / HBM_PEAK_GBS, traffic=counter_traffic(dom, models.get('_tag'), models.get('_factor')),
                     per_launch_bytes=amount)
         if copy:   # context: what a plain device copy reaches on this HBM
             cp = copy_gbps(dev)
@@ -487,7 +493,7 @@ class Workload:
         mode, factor = rec['mode'], rec['factor']
         mdl = algorithmic_models(self.cfg, rec['info'], self.R, mode, factor,
                                  refine=1 if factor == 'bf16' else 0, iters=rec['iters'])
-        out = {'_tag': self.tag}
+        out = {'_tag': self.tag, '_factor': factor}
         for k, val in mdl.items():
             if k.startswith('_'):
                 out[k] = val
