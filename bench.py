@@ -110,13 +110,16 @@ def algorithmic_models(cfg, info, R, mode, factor='c128', refine=0, iters=0, res
         models['matvec_plane'] = ('alu', R * Px * fl, 'flops')
         models['_plane_bytes'] = R * 2 * 3 * ny * nz * Px * v + kplane
     if iters:
-        # CGS2 per Arnoldi step j (index within its cycle): each of the two dot passes reads the
-        # j+1 basis vectors and w once; each update pass also writes w.  Average per launch.
+        # Arnoldi step j (index within its cycle), one reduction and one update pass: the
+        # reduction reads q_0..q_{j-1}, u_j (j + 1 basis vectors) and w; the update reads the same
+        # and writes q_j and u_{j+1} (plus u_{j+1}'s complex64 copy when only the preconditioner
+        # runs in complex64).  Average per launch.
         pv = 8 if mode == 'mixed' else 16
         js = [it % restart for it in range(iters)]
         n3 = 3 * N
+        extra = 8 if mode == 'mixed_pc' else 0
         models['arnoldi_dots'] = ('hbm', sum(((j + 1) * pv + 16) * n3 * R for j in js) / len(js), 'bytes')
-        models['arnoldi_update'] = ('hbm', sum(((j + 1) * pv + 32) * n3 * R for j in js) / len(js), 'bytes')
+        models['arnoldi_update'] = ('hbm', sum(((j + 3) * pv + 16 + extra) * n3 * R for j in js) / len(js), 'bytes')
     return models
 
 
@@ -165,7 +168,7 @@ def counter_traffic(kernel, workload_tag, factor='c128'):
         return None
 
 
-def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, pool=4, small=False):
+def serving_bench(vie, n_burst=24, streams=((0.5, 40),), seed=11, workers=4, pool=4, small=False):
     """The request scheduler on a seeded stream of catalogue devices (waveguides, Bragg gratings
     and couplers of 256-8192 voxels along x with cross-sections 16x8-48x8, and the 2 um disk on
     160x160x8; 1-16 right-hand sides; mixed precision with complex64 factors; memory-reduced
@@ -194,11 +197,12 @@ def serving_bench(vie, n_burst=40, streams=((0.8, 120),), seed=11, workers=4, po
         rec = [None] * len(stream)
 
         def collect():
-            every = max(10, len(stream) // 10)
             for c in range(len(stream)):
-                if c and c % every == 0:
-                    print('bench: serving %s: %d of %d requests collected' % (label, c, len(stream)),
-                          file=sys.stderr, flush=True)
+                if c:
+                    r = rec[k]
+                    print('bench: serving %s: %d of %d collected (request %d, %d RHS, %s)'
+                          % (label, c, len(stream), k, r['nrhs'],
+                             '%.0f ms' % r['lat'] if r['lat'] is not None else 'failed'), file=sys.stderr, flush=True)
                 k, rid, late_ms, nrhs = q.get()
                 try:
                     _, st, tm = srv.wait(rid)
@@ -597,7 +601,7 @@ def main():
     ap.add_argument('--no-serving', action='store_true', help='skip the short serving-stream measurement')
     ap.add_argument('--serve', action='store_true',
                     help='only the serving stream: Poisson arrivals at 0.5, 0.8 and 1.0 of the measured '
-                         'capacity, 1000 requests each (one JSON line)')
+                         'capacity, 150 requests each (one JSON line)')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py runs on one GPU only (--gpus %d requested); sharding over several GPUs is '
@@ -613,7 +617,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.serve:
         t0 = time.perf_counter()
-        sv = serving_bench(vie, n_burst=60, streams=((0.5, 1000), (0.8, 1000), (1.0, 1000)))
+        sv = serving_bench(vie, n_burst=40, streams=((0.5, 150), (0.8, 150), (1.0, 150)))
         t1 = time.perf_counter()
         s08 = [x for x in sv['streams'] if x['offered_fraction_of_capacity'] == 0.8][0]
         print(json.dumps({

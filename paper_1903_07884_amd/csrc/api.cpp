@@ -447,7 +447,7 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
         const uint64_t extra = mixed ? 8 : mixed_pc ? 8 + 16 : 0;
         *solve_bytes = vb * R * n3 * (rs + 1) + zb * R * n3 * rs + 2 * 16 * R * n3 +
                        16 * R * (uint64_t)arnoldi_partials((long long)n3, (int)rs) + extra * R * n3 +
-                       16 * R * (rs + 2) * (rs + 4);
+                       2 * 16 * R * (rs + 2) * (rs + 4);
     }
     return VIE_OK;
 }

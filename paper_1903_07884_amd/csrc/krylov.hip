@@ -2,29 +2,43 @@
 // sides in lockstep (Sec. 1: the discrete JVIE is solved by GMRES; restart, side and
 // orthogonalisation are this library's choices).
 //
-// Per Arnoldi step j, for every right-hand side r of the batch at once:
-//   z_j = P^{-1} v_j (kept, so x += Z y at the end of a cycle: flexible GMRES),
+// Arnoldi by classical Gram-Schmidt applied twice, with the second pass of each vector
+// delayed to the next step, so that a step makes one reduction pass and one update pass over
+// the basis instead of two of each.  Slot j of the basis first holds u_j: orthogonalised once
+// against q_0..q_{j-1}, not normalised (u_0 = r).  Step j, for every right-hand side at once:
+//   z_j = P^{-1} u_j (kept, so x += Z y at the end of a cycle: flexible GMRES),
 //   w = A z_j (one batched operator product),
-//   classical Gram-Schmidt applied twice with wavefront reductions (per-workgroup
-//   partials, then one reduction kernel), FP64 throughout,
-//   a single-lane kernel per right-hand side applies the previous complex Givens rotations
-//   to the new Hessenberg column, forms the next rotation and updates |g_{j+1}|;
-//   these estimates (one per right-hand side) are the only values read back per step.
-// Each cycle ends with x += Z y and the FP64 true residual r = b - A x.
+//   reduction pass:  s = Q^H u_j, a = |u_j|^2, c = Q^H w, d = u_j^H w, e = |w|^2,
+//   alpha = sqrt(a - |s|^2), so q_j = (u_j - Q s) / alpha is u_j's second pass, normalised,
+//   h = q_j^H w = (d - s^H c) / alpha,
+//   update pass:  q_j over u_j in slot j, and in slot j + 1
+//                 u_{j+1} = (w - Q c - q_j h) / sigma = (w - Q (c - s h / alpha) - u_j h / alpha) / sigma,
+//                 sigma = |w|, so that no stored vector grows or shrinks from step to step
+//                 (u_0 = r / |r| likewise).
+// As u_{j+1} = Q' s' + alpha' q_{j+1} (Q' = [Q, q_j]; s', alpha' from the next reduction),
+// A z_j = Q' ([c; h] + sigma s') + sigma alpha' q_{j+1}: column j of the Hessenberg matrix is
+// [c; h] + sigma s' with subdiagonal sigma alpha'.  So step j completes column j - 1 and forms its complex Givens
+// rotation, and a cycle's last column is completed by one more reduction pass.  Convergence
+// and breakdown are judged at step j on the provisional column [c; h] with subdiagonal
+// sigma |u_{j+1}|, which differs from the completed one only by the second-pass terms.  Z holds the
+// preconditioned u_j, for which A Z = Q H holds, so x += Z y is the flexible GMRES update; with
+// a fixed preconditioner span{P^{-1} u_i} = P^{-1} span{q_i}, and the iterates are GMRES's.
+// All sums are FP64; one residual estimate and breakdown flag per right-hand side are read
+// back per step.  Each cycle ends with x += Z y and the FP64 true residual r = b - A x.
 //
-// FP64 mode: v, z, products and factors complex128.  Mixed mode: v_j is rounded to
-// complex64 for the preconditioner (complex64 factors) and the complex64 operator
-// product, whose result is widened back for the FP64 Arnoldi step; Z is kept in
-// complex64; the true residual of every cycle uses the complex128 product, so the
-// outer loop is an FP64 iterative refinement around the FP32 inner solve; the basis V is
-// stored in complex64.  Mixed-preconditioner mode: only the preconditioner runs in complex64
-// (or bfloat16 factors), on a complex64 copy of v_j; Z is kept in complex64, each z_j is
-// widened for the complex128 product, and V stays complex128.
+// FP64 mode: basis, z, products and factors complex128.  Mixed mode: the basis (u_j, then q_j)
+// is stored in complex64 and u_j feeds the complex64 preconditioner and operator product, whose
+// result is widened back for the FP64 reduction and update; Z is kept in complex64; the true
+// residual of every cycle uses the complex128 product, so the outer loop is an FP64 iterative
+// refinement around the FP32 inner solve.  Mixed-preconditioner mode: only the preconditioner
+// runs in complex64 (or bfloat16 factors), on a complex64 copy of u_j; Z is kept in complex64,
+// each z_j is widened for the complex128 product, and the basis stays complex128.
 #include <cmath>
 
 #include "vie_internal.h"
 
 #define KR_THREADS 256
+#define KR_MAX_RESTART VIE_MAX_RESTART
 // The Arnoldi kernels split every vector into parts, one workgroup each: about KR_EPT_DOTS
 // elements per thread for the dot products (their 16 loads in flight per element already
 // cover the latency; fewer parts mean fewer partial reductions), KR_EPT_UPD for the updates,
@@ -145,38 +159,164 @@ __global__ void __launch_bounds__(KR_THREADS) k_reduce(const c128 *partial, int 
     if (threadIdx.x == 0) out[(long long)r * ostride + i] = s;
 }
 
-// w_r -= sum_i V_i,r h_r[i]; optional partial |w_r|^2 into partial[r * gridDim.x + blk].
+// Reduction pass of an Arnoldi step, per right-hand side r (skipped when inactive, or when
+// nq_r gives it no basis vectors): with nq basis vectors q_i in slots 0..nq-1 (nq = nq_r[r] if
+// nq_r is given), u in slot nq and w (optional),
+//   partial[(r * gridDim.x + blk) * stride + k] = the part's share of
+//     k < nq: conj(q_k) . u;  with w: nq + k: conj(q_k) . w, then 2nq: |u|^2, 2nq+1: conj(u) . w,
+//     2nq+2: |w|^2;  without w: nq: |u|^2.
+// The outputs are formed KR_DG2 basis vectors at a time (u and w read once per group); inside a
+// group the loads of an element are unconditional (a short last group clamps its index and
+// drops the extra products), so they are in flight together.
+#define KR_DG2 8
 template <class VT>
-__global__ void __launch_bounds__(KR_THREADS) k_update(const VT *V, long long ldj, int nv, const c128 *h, int hstride,
-                                                       c128 *w, long long n, c128 *partial) {
-    __shared__ c128 hs[256];
+__global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj, int nq, const int *nq_r,
+                                                      const c128 *w, long long n, const int *active, int stride,
+                                                      c128 *partial) {
+    __shared__ c128 sh[2 * KR_DG2 + 3][KR_THREADS / 64];
+    const int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int nqr = nq_r ? nq_r[r] : nq;
+    if (nq_r && nqr == 0) return;
+    const VT *Vr = V + r * n;
+    const VT *ur = Vr + nqr * ldj;
+    const c128 *wr = w ? w + r * n : nullptr;
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int ngroups = nqr > 0 ? (nqr + KR_DG2 - 1) / KR_DG2 : 1;
+    const int self0 = wr ? 2 * nqr : nqr;  // index of |u|^2
+    const int last = max(nqr - 1, 0);
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const int i0 = gi * KR_DG2, cnt = max(0, min(KR_DG2, nqr - i0));
+        const bool self = gi == 0;
+        c128 as[KR_DG2], ac[KR_DG2], sd = czero<double>();
+        double sa = 0.0, se = 0.0;
+#pragma unroll
+        for (int u = 0; u < KR_DG2; ++u) as[u] = ac[u] = czero<double>();
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+            const c128 ue = wide(ur[e]);
+            const c128 we = wr ? wr[e] : czero<double>();
+            c128 v[KR_DG2];
+#pragma unroll
+            for (int u = 0; u < KR_DG2; ++u) v[u] = wide(Vr[min(i0 + u, last) * ldj + e]);
+#pragma unroll
+            for (int u = 0; u < KR_DG2; ++u)
+                if (u < cnt) {
+                    as[u] = as[u] + cmulc(v[u], ue);
+                    if (wr) ac[u] = ac[u] + cmulc(v[u], we);
+                }
+            if (self) {
+                sa += abs2(ue);
+                if (wr) {
+                    sd = sd + cmulc(ue, we);
+                    se += abs2(we);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KR_DG2; ++u) {
+            if (u >= cnt) break;
+            const c128 t1 = wave_sum(as[u]);
+            if (lane == 0) sh[u][wid] = t1;
+            if (wr) {
+                const c128 t2 = wave_sum(ac[u]);
+                if (lane == 0) sh[KR_DG2 + u][wid] = t2;
+            }
+        }
+        if (self) {
+            const c128 t0 = wave_sum(mk(sa, 0.0));
+            if (lane == 0) sh[2 * KR_DG2][wid] = t0;
+            if (wr) {
+                const c128 t1 = wave_sum(sd), t2 = wave_sum(mk(se, 0.0));
+                if (lane == 0) {
+                    sh[2 * KR_DG2 + 1][wid] = t1;
+                    sh[2 * KR_DG2 + 2][wid] = t2;
+                }
+            }
+        }
+        __syncthreads();
+        // thread t < 2 KR_DG2 + 3 writes one output of the group
+        const int t = threadIdx.x;
+        int slot = -1, dst = 0;
+        if (t < cnt) slot = t, dst = i0 + t;
+        else if (wr && t >= KR_DG2 && t < KR_DG2 + cnt) slot = t, dst = nqr + i0 + (t - KR_DG2);
+        else if (self && t == 2 * KR_DG2) slot = t, dst = self0;
+        else if (self && wr && t > 2 * KR_DG2 && t < 2 * KR_DG2 + 3) slot = t, dst = self0 + (t - 2 * KR_DG2);
+        if (slot >= 0) {
+            c128 acc = czero<double>();
+            for (int q = 0; q < KR_THREADS / 64; ++q) acc = acc + sh[slot][q];
+            out[dst] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Update pass of an Arnoldi step, per active right-hand side r, with co = coef + r * cstride =
+// [s_i (nq) | c_i - s_i h/alpha (nq) | 1/alpha | h/alpha | 1/sigma]:
+//   slot nq:      q_j = (u_j - sum_i q_i s_i) / alpha                                  (over u_j)
+//   slot nq + 1:  u_{j+1} = (w - sum_i q_i (c_i - s_i h/alpha) - u_j h/alpha) / sigma   (and a complex64 copy in vlo)
+//   partial[r * gridDim.x + blk] = the part's share of |u_{j+1}|^2 (FP64 values).
+// An inactive right-hand side stopped at an earlier step (or never started this cycle), so slot
+// nq + 1 lies past its last u: it is zeroed (with its complex64 copy), so that the products and
+// preconditioner applies of the batch never read stale values for it.
+template <class VT>
+__global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, int nq, const c128 *coef, int cstride,
+                                                        const c128 *w, long long n, const int *active, c64 *vlo,
+                                                        c128 *partial) {
+    typedef decltype(V->re) T;
+    __shared__ c128 cs[2 * KR_MAX_RESTART + 3];
     __shared__ c128 sh[KR_THREADS / 64];
     const int r = blockIdx.y;
-    for (int i = threadIdx.x; i < nv; i += KR_THREADS) hs[i] = h[(long long)r * hstride + i];
+    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    if (!active[r]) {
+        VT *un = V + r * n + (nq + 1) * ldj;
+        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+            un[e] = mk((T)0, (T)0);
+            if (vlo) vlo[r * n + e] = mk(0.0f, 0.0f);
+        }
+        return;
+    }
+    const c128 *co = coef + (long long)r * cstride;
+    for (int i = threadIdx.x; i < 2 * nq + 3; i += KR_THREADS) cs[i] = co[i];
     __syncthreads();
-    c128 *wr = w + r * n;
-    long long chunk = (n + gridDim.x - 1) / gridDim.x;
-    long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    c128 nrm = czero<double>();
-    const VT *Vr = V + r * n;
+    const double ia = cs[2 * nq].re, isg = cs[2 * nq + 2].re;
+    const c128 hu = cs[2 * nq + 1];
+    VT *Vr = V + r * n;
+    VT *ur = Vr + nq * ldj, *un = Vr + (nq + 1) * ldj;
+    const c128 *wr = w + r * n;
+    c64 *lr = vlo ? vlo + r * n : nullptr;
+    double nrm = 0.0;
     for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
-        c128 acc = wr[e];
+        const c128 u = wide(ur[e]);
+        c128 aq = u, aw = wr[e];
         int i = 0;
-        for (; i + 8 <= nv; i += 8) {  // eight loads in flight, products in order of i
+        for (; i + 8 <= nq; i += 8) {  // eight loads in flight, products in order of i
             c128 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = wide(Vr[(i + u) * ldj + e]);
+            for (int k = 0; k < 8; ++k) v[k] = wide(Vr[(i + k) * ldj + e]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc = cfms(acc, v[u], hs[i + u]);
+            for (int k = 0; k < 8; ++k) {
+                aq = cfms(aq, v[k], cs[i + k]);
+                aw = cfms(aw, v[k], cs[nq + i + k]);
+            }
         }
-        for (; i < nv; ++i) acc = cfms(acc, wide(Vr[i * ldj + e]), hs[i]);
-        wr[e] = acc;
-        nrm.re += abs2(acc);
+        for (; i < nq; ++i) {
+            const c128 v = wide(Vr[i * ldj + e]);
+            aq = cfms(aq, v, cs[i]);
+            aw = cfms(aw, v, cs[nq + i]);
+        }
+        aw = cfms(aw, u, hu);
+        aw = mk(aw.re * isg, aw.im * isg);
+        ur[e] = mk((T)(aq.re * ia), (T)(aq.im * ia));
+        un[e] = mk((T)aw.re, (T)aw.im);
+        if (lr) lr[e] = mk((float)aw.re, (float)aw.im);
+        nrm += abs2(aw);
     }
-    if (partial) {
-        c128 s = block_sum_kr(nrm, sh);
-        if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = s;
-    }
+    const c128 t = block_sum_kr(mk(nrm, 0.0), sh);
+    if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = t;
 }
 
 // x_r += sum_{i < jr[r]} Z_i,r y_r[i]   (Z in complex128 or complex64)
@@ -199,17 +339,17 @@ __global__ void __launch_bounds__(KR_THREADS) k_combine(const cpx<R> *Z, long lo
     }
 }
 
-// v_r = w_r / scal[r * sstride]  (zero for an inactive right-hand side or a zero scale),
-// stored in the basis precision
+// First basis slot of a cycle: u_0 = r / beta (zero for an inactive right-hand side or a zero
+// beta), stored in the basis precision, with an optional complex64 copy.
 template <class VT>
-__global__ void k_scale(const c128 *w, VT *v, long long n, const double *scal, int sstride, const int *active) {
+__global__ void k_store(const c128 *src, VT *v, c64 *vlo, long long n, const double *beta, const int *active) {
     typedef decltype(v->re) T;
     const int r = blockIdx.y;
-    double s = scal[(long long)r * sstride];
-    double f = (active[r] && s != 0.0) ? 1.0 / s : 0.0;
+    const double f = (active[r] && beta[r] > 0.0) ? 1.0 / beta[r] : 0.0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        c128 a = w[r * n + e];
-        v[r * n + e] = mk((T)(a.re * f), (T)(a.im * f));
+        const c128 a = f * src[r * n + e];
+        v[r * n + e] = mk((T)a.re, (T)a.im);
+        if (vlo) vlo[r * n + e] = mk((float)a.re, (float)a.im);
     }
 }
 
@@ -225,90 +365,191 @@ __global__ void k_widen(const c64 *a, c128 *b, long long n) {
 
 // Per right-hand side Arnoldi bookkeeping arrays (device), each with R slices.
 struct GState {
-    c128 *h1, *h2;  // [R][m+2]: two CGS passes; h1[nv] = |w0|^2 (self entry)
-    c128 *nrm2;     // [R]: |w|^2 after orthogonalisation
-    c128 *Rm;       // [R][m][m+1] column-major rotated Hessenberg
-    double *cs;     // [R][m]
-    c128 *sn;       // [R][m]
-    c128 *g;        // [R][m+1]
-    c128 *y;        // [R][m]
-    double *st;     // [R][4]: |g_{j+1}|, h_{j+1,j}, breakdown, |w0|
-    int *active;    // [R]
-    int m;
+    c128 *h1;    // [R][hstride]: the step's reduction outputs (hstride >= 2m + 3)
+    c128 *coef;  // [R][cstride]: the update pass's coefficients (cstride >= 2m + 3)
+    c128 *nrm2;  // [R]: |u_{j+1}|^2
+    c128 *P;     // [R][m][m+1] column-major: [c; h] of each step (before the second-pass terms)
+    c128 *Rm;    // [R][m][m+1] column-major: completed columns after their rotations
+    double *cs;  // [R][m]
+    c128 *sn;    // [R][m]
+    c128 *g;     // [R][m+1]
+    c128 *y;     // [R][m]
+    double *st;  // [R][4]: provisional |g_{j+1}|, sigma |u_{j+1}|, breakdown, |w|
+    double *sig; // [R][m]: sigma_j = |w| of step j (the scale of u_{j+1})
+    double *beta; // [R]: |r| of the cycle (the scale of u_0)
+    int *active; // [R]
+    int m, hstride, cstride;
 };
 
-// Step j for every active right-hand side: one wavefront per right-hand side.  Its lanes stage
-// the new column (h1 + h2) and the earlier rotations in LDS; lane 0 then applies the rotations
-// in order (the serial chain reads LDS, not global memory) and forms the new one.
-#define KR_MAX_RESTART VIE_MAX_RESTART
-__global__ void __launch_bounds__(64) k_givens(GState S, int j, int R) {
-    __shared__ c128 col[KR_MAX_RESTART + 1];
-    __shared__ double csl[KR_MAX_RESTART];
-    __shared__ c128 snl[KR_MAX_RESTART];
-    const int r = blockIdx.x, lane = threadIdx.x;
-    if (r >= R) return;
-    const int m = S.m;
-    double *st = S.st + 4 * r;
-    if (!S.active[r]) {
-        if (lane == 0) {
-            st[0] = 0.0;
-            st[1] = 0.0;
-            st[2] = 1.0;
-            st[3] = 0.0;
-        }
-        return;
-    }
-    const c128 *h1 = S.h1 + (long long)r * (m + 2), *h2 = S.h2 + (long long)r * (m + 2);
-    c128 *colg = S.Rm + ((long long)r * m + j) * (m + 1);
+// Complete column jc of right-hand side r: col = P[jc][0..jc] + sigma_jc s[0..jc] with
+// subdiagonal sigma_jc alpha; apply rotations 0..jc-1, form rotation jc (c real, s complex), update g and store the
+// rotated column.  One wavefront; col / csl / snl are LDS arrays of the caller.
+__device__ void finish_column(GState &S, int r, int jc, const c128 *s, double alpha, c128 *col, double *csl,
+                              c128 *snl) {
+    const int m = S.m, lane = threadIdx.x;
+    const c128 *pc = S.P + ((long long)r * m + jc) * (m + 1);
     double *cs = S.cs + (long long)r * m;
     c128 *sn = S.sn + (long long)r * m;
     c128 *g = S.g + (long long)r * (m + 1);
-    for (int i = lane; i <= j; i += 64) col[i] = h1[i] + h2[i];
-    for (int i = lane; i < j; i += 64) {
+    const double sg = S.sig[(long long)r * m + jc];
+    for (int i = lane; i <= jc; i += 64) col[i] = pc[i] + sg * s[i];
+    for (int i = lane; i < jc; i += 64) {
         csl[i] = cs[i];
         snl[i] = sn[i];
     }
     __syncthreads();
     if (lane == 0) {
-        double hn = sqrt(S.nrm2[r].re);
-        double w0 = sqrt(h1[j + 1].re);
-        for (int i = 0; i < j; ++i) {
-            c128 a = col[i], b = col[i + 1];
+        for (int i = 0; i < jc; ++i) {
+            const c128 a = col[i], b = col[i + 1];
             col[i] = csl[i] * a + snl[i] * b;
             col[i + 1] = csl[i] * b - conjg(snl[i]) * a;
         }
-        c128 a = col[j];
+        const c128 a = col[jc];
+        const double aa = sqrt(abs2(a)), bb = sg * alpha;
         double c;
-        c128 s, rr;
-        double aa = sqrt(abs2(a)), bb = hn;
+        c128 sr, rr;
         if (bb == 0.0) {
             c = 1.0;
-            s = czero<double>();
+            sr = czero<double>();
             rr = a;
         } else if (aa == 0.0) {
             c = 0.0;
-            s = mk(1.0, 0.0);
-            rr = mk(hn, 0.0);
+            sr = mk(1.0, 0.0);
+            rr = mk(bb, 0.0);
         } else {
-            double rho = hypot(aa, bb);
-            c128 ph = mk(a.re / aa, a.im / aa);
+            const double rho = hypot(aa, bb);
+            const c128 ph = mk(a.re / aa, a.im / aa);
             c = aa / rho;
-            s = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b) / rho, b real
+            sr = mk(ph.re * bb / rho, ph.im * bb / rho);  // phase * conj(b) / rho, b real
             rr = mk(ph.re * rho, ph.im * rho);
         }
-        cs[j] = c;
-        sn[j] = s;
-        col[j] = rr;
-        c128 gj = g[j];
-        g[j + 1] = mk(0.0, 0.0) - conjg(s) * gj;
-        g[j] = c * gj;
-        st[0] = sqrt(abs2(g[j + 1]));
-        st[1] = hn;
-        st[2] = (hn <= 1e-14 * w0) ? 1.0 : 0.0;
-        st[3] = w0;
+        cs[jc] = c;
+        sn[jc] = sr;
+        col[jc] = rr;
+        const c128 gj = g[jc];
+        g[jc + 1] = czero<double>() - conjg(sr) * gj;
+        g[jc] = c * gj;
     }
     __syncthreads();
-    for (int i = lane; i <= j; i += 64) colg[i] = col[i];
+    c128 *rc = S.Rm + ((long long)r * m + jc) * (m + 1);
+    for (int i = lane; i <= jc; i += 64) rc[i] = col[i];
+}
+
+// After the reduction of step j, per active right-hand side (one wavefront): alpha, h, sigma,
+// the update coefficients, the step's column [c; h], and column j - 1 completed (for j = 0:
+// g = (beta alpha, 0, ...), r = beta u_0 = beta alpha q_0).
+__global__ void __launch_bounds__(64) k_arnoldi_coef(GState S, int j, int R) {
+    __shared__ c128 col[KR_MAX_RESTART + 1];
+    __shared__ double csl[KR_MAX_RESTART];
+    __shared__ c128 snl[KR_MAX_RESTART];
+    __shared__ double sal;
+    __shared__ c128 shu;
+    const int r = blockIdx.x, lane = threadIdx.x;
+    if (r >= R || !S.active[r]) return;
+    const int m = S.m;
+    const c128 *h = S.h1 + (long long)r * S.hstride;  // [s (j) | c (j) | a | d | e]
+    double ss = 0.0;
+    c128 sc = czero<double>();
+    for (int i = lane; i < j; i += 64) {
+        ss += abs2(h[i]);
+        sc = sc + cmulc(h[i], h[j + i]);
+    }
+    const c128 ssum = wave_sum(mk(ss, 0.0)), csum = wave_sum(sc);
+    c128 *pcol = S.P + ((long long)r * m + j) * (m + 1);
+    if (lane == 0) {
+        const double a2 = h[2 * j].re - ssum.re;
+        const double al = a2 > 0.0 ? sqrt(a2) : 0.0;
+        const c128 d = h[2 * j + 1] - csum;
+        const c128 hh = al > 0.0 ? mk(d.re / al, d.im / al) : czero<double>();
+        sal = al;
+        shu = al > 0.0 ? mk(hh.re / al, hh.im / al) : czero<double>();
+        pcol[j] = hh;
+        const double sg = sqrt(h[2 * j + 2].re);
+        S.sig[(long long)r * m + j] = sg;
+        c128 *co = S.coef + (long long)r * S.cstride;
+        co[2 * j + 2] = mk(sg > 0.0 ? 1.0 / sg : 0.0, 0.0);
+    }
+    __syncthreads();
+    const double al = sal;
+    const c128 hu = shu;
+    c128 *co = S.coef + (long long)r * S.cstride;  // [s (j) | c - s h/alpha (j) | 1/alpha | h/alpha | 1/sigma]
+    for (int i = lane; i < j; i += 64) {
+        co[i] = h[i];
+        co[j + i] = h[j + i] - h[i] * hu;
+        pcol[i] = h[j + i];
+    }
+    if (lane == 0) {
+        co[2 * j] = mk(al > 0.0 ? 1.0 / al : 0.0, 0.0);
+        co[2 * j + 1] = hu;
+    }
+    if (j == 0) {
+        c128 *g = S.g + (long long)r * (m + 1);
+        for (int i = lane; i <= m; i += 64) g[i] = mk(i == 0 ? S.beta[r] * al : 0.0, 0.0);
+    } else {
+        finish_column(S, r, j - 1, h, al, col, csl, snl);
+    }
+}
+
+// After the update pass of step j, per active right-hand side (one wavefront): the provisional
+// residual estimate |g_{j+1}| of column [c; h] with subdiagonal sigma |u_{j+1}| under the
+// completed rotations 0..j-1, and the breakdown flag (sigma |u_{j+1}| <= 1e-14 |w|, sigma = |w|).
+__global__ void __launch_bounds__(64) k_arnoldi_est(GState S, int j, int R) {
+    __shared__ c128 col[KR_MAX_RESTART + 1];
+    __shared__ double csl[KR_MAX_RESTART];
+    __shared__ c128 snl[KR_MAX_RESTART];
+    const int r = blockIdx.x, lane = threadIdx.x;
+    if (r >= R) return;
+    double *st = S.st + 4 * r;
+    if (!S.active[r]) {
+        if (lane == 0) st[0] = 0.0, st[1] = 0.0, st[2] = 1.0, st[3] = 0.0;
+        return;
+    }
+    const int m = S.m;
+    const c128 *pc = S.P + ((long long)r * m + j) * (m + 1);
+    for (int i = lane; i <= j; i += 64) col[i] = pc[i];
+    for (int i = lane; i < j; i += 64) {
+        csl[i] = S.cs[(long long)r * m + i];
+        snl[i] = S.sn[(long long)r * m + i];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        for (int i = 0; i < j; ++i) {
+            const c128 a = col[i], b = col[i + 1];
+            col[i] = csl[i] * a + snl[i] * b;
+            col[i + 1] = csl[i] * b - conjg(snl[i]) * a;
+        }
+        const double w0 = S.sig[(long long)r * m + j];
+        const double aa = sqrt(abs2(col[j])), bb = w0 * sqrt(S.nrm2[r].re);
+        const double rho = hypot(aa, bb);
+        const double gj = sqrt(abs2(S.g[(long long)r * (m + 1) + j]));
+        st[0] = rho > 0.0 ? gj * bb / rho : 0.0;
+        st[1] = bb;
+        st[2] = (bb <= 1e-14 * w0) ? 1.0 : 0.0;
+        st[3] = w0;
+    }
+}
+
+// End of a cycle, per right-hand side with jr[r] > 0 steps: complete its last column jr - 1 from
+// the finishing reduction [s (jr) | a] of u_{jr} against q_0..q_{jr-1}.
+__global__ void __launch_bounds__(64) k_arnoldi_final(GState S, const int *jr, int R) {
+    __shared__ c128 col[KR_MAX_RESTART + 1];
+    __shared__ double csl[KR_MAX_RESTART];
+    __shared__ c128 snl[KR_MAX_RESTART];
+    __shared__ double sal;
+    const int r = blockIdx.x, lane = threadIdx.x;
+    if (r >= R) return;
+    const int k = jr[r];
+    if (k == 0) return;
+    const c128 *h = S.h1 + (long long)r * S.hstride;
+    double ss = 0.0;
+    for (int i = lane; i < k; i += 64) ss += abs2(h[i]);
+    const c128 ssum = wave_sum(mk(ss, 0.0));
+    if (lane == 0) {
+        const double a2 = h[k].re - ssum.re;
+        sal = a2 > 0.0 ? sqrt(a2) : 0.0;
+    }
+    __syncthreads();
+    finish_column(S, r, k - 1, h, sal, col, csl, snl);
 }
 
 // y_r = R_r^{-1} g_r over the first jr[r] columns; one lane per right-hand side.
@@ -324,14 +565,6 @@ __global__ void k_lsq(GState S, const int *jr, int R) {
         for (int c = i + 1; c < k; ++c) acc = cfms(acc, Rm[(long long)c * (m + 1) + i], y[c]);
         y[i] = cdiv(acc, Rm[(long long)i * (m + 1) + i]);
     }
-}
-
-// g_r = (beta_r, 0, ...)
-__global__ void k_setg(c128 *g, int m1, const double *beta, int R) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m1 * R) return;
-    int r = i / m1, k = i % m1;
-    g[i] = mk(k == 0 ? beta[r] : 0.0, 0.0);
 }
 
 namespace {
@@ -355,49 +588,52 @@ vie_status norms(Ctx &C, const c128 *w, c128 *out) {
     return VIE_OK;
 }
 
-// Classical Gram-Schmidt twice against v_0..v_j, the Givens update of column j and
-// v_{j+1} = w / h_{j+1,j} (Sec. 1: GMRES; the orthogonalisation is this library's choice).
+// Arnoldi step j (Sec. 1: GMRES; the orthogonalisation is this library's choice): with
+// z_j = P^{-1} u_j and w = A z_j formed, one reduction pass, the coefficients (completing
+// column j - 1), one update pass (q_j over u_j, u_{j+1} into slot j + 1, and its complex64
+// copy when vlo is given), |u_{j+1}|^2 and the provisional residual estimate.
 template <class VT>
-vie_status cgs2_step(Ctx &C, const VT *V, long long ldj, int j, c128 *w, GState &S, int m, dim3 grid_e,
-                     VT *vnext) {
+vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int j, const c128 *w, GState &S, c64 *vlo) {
     hipStream_t s = C.s;
     const long long n = C.n;
-    const int R = C.R;
-    const dim3 grid_d(C.nbd, R), grid_u(C.nbu, R);
+    const int R = C.R, cnt = 2 * j + 3;
     {
         ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots<VT>, grid_d, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 1, C.partial);
+        hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, j,
+                           (const int *)nullptr, w, n, (const int *)S.active, cnt, C.partial);
         VIE_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_reduce, dim3(j + 2, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, j + 2,
-                       S.h1, m + 2);
+    hipLaunchKernelGGL(k_reduce, dim3(cnt, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
+                       S.hstride);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_arnoldi_coef, dim3(R), dim3(64), 0, s, S, j, R);
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update<VT>, grid_u, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h1, m + 2, w, n,
-                           (c128 *)nullptr);
-        VIE_HIP(hipGetLastError());
-    }
-    {
-        ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots<VT>, grid_d, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)w, n, 0, C.partial);
-        VIE_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_reduce, dim3(j + 1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, j + 1,
-                       S.h2, m + 2);
-    VIE_HIP(hipGetLastError());
-    {
-        ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update<VT>, grid_u, dim3(KR_THREADS), 0, s, V, ldj, j + 1, (const c128 *)S.h2, m + 2, w, n,
-                           C.partial);
+        hipLaunchKernelGGL(k_update2<VT>, dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, j, (const c128 *)S.coef,
+                           S.cstride, w, n, (const int *)S.active, vlo, C.partial);
         VIE_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbu, 1, S.nrm2, 1);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_givens, dim3(R), dim3(64), 0, s, S, j, R);
+    hipLaunchKernelGGL(k_arnoldi_est, dim3(R), dim3(64), 0, s, S, j, R);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scale<VT>, grid_e, dim3(256), 0, s, (const c128 *)w, vnext, n, (const double *)(S.st + 1), 4,
-                       (const int *)S.active);
+    return VIE_OK;
+}
+
+// End of a cycle: the reduction of u_{jr} against q_0..q_{jr-1} for every right-hand side that
+// took jr[r] > 0 steps (max_jr the largest), and its last column completed.
+template <class VT>
+vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, const int *jr_dev, int max_jr, GState &S) {
+    hipStream_t s = C.s;
+    const int cnt = max_jr + 1;
+    hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, 0, jr_dev, (const c128 *)nullptr,
+                       C.n, (const int *)nullptr, cnt, C.partial);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(cnt, C.R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
+                       S.hstride);
+    VIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_arnoldi_final, dim3(C.R), dim3(64), 0, s, S, jr_dev, C.R);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
@@ -414,7 +650,7 @@ static int kr_parts(long long n, int ept) {
 }
 
 long long arnoldi_partials(long long n, int restart) {
-    return std::max((long long)kr_parts(n, KR_EPT_DOTS) * (restart + 2), (long long)kr_parts(n, KR_EPT_UPD));
+    return std::max((long long)kr_parts(n, KR_EPT_DOTS) * (2 * restart + 3), (long long)kr_parts(n, KR_EPT_UPD));
 }
 
 vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, const vie_solve_opts *o,
@@ -452,18 +688,22 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
     if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
-    size_t nc = (size_t)R * ((size_t)(m + 2) * 2 + 1 + (size_t)m * (m + 1) + m + (m + 1) + m);
-    size_t nd = (size_t)R * (m + 4 + 1);
-    VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * 2 * R));
-    c128 *cp = small.as<c128>();
     GState S;
     S.m = m;
+    S.hstride = 2 * m + 3;
+    S.cstride = 2 * m + 3;
+    size_t nc = (size_t)R * ((size_t)S.hstride + S.cstride + 1 + 2 * (size_t)m * (m + 1) + m + (m + 1) + m);
+    size_t nd = (size_t)R * (2 * m + 4 + 1);
+    VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * 2 * R));
+    c128 *cp = small.as<c128>();
     S.h1 = cp;
-    cp += (size_t)R * (m + 2);
-    S.h2 = cp;
-    cp += (size_t)R * (m + 2);
+    cp += (size_t)R * S.hstride;
+    S.coef = cp;
+    cp += (size_t)R * S.cstride;
     S.nrm2 = cp;
     cp += R;
+    S.P = cp;
+    cp += (size_t)R * m * (m + 1);
     S.Rm = cp;
     cp += (size_t)R * m * (m + 1);
     S.sn = cp;
@@ -477,7 +717,9 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     dp += (size_t)R * m;
     S.st = dp;
     dp += (size_t)R * 4;
-    double *beta_dev = dp;
+    S.sig = dp;
+    dp += (size_t)R * m;
+    S.beta = dp;
     dp += R;
     S.active = reinterpret_cast<int *>(dp);
     int *jr_dev = S.active + R;
@@ -570,25 +812,21 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
             }
         }
         if (nact == 0) break;
-        // v0 = r / beta (zero for finished right-hand sides), g = (beta, 0, ...)
+        // u_0 = r / beta (zero for finished right-hand sides); g is set by the first step
         for (int q = 0; q < R; ++q) {
             host[q] = beta[q];
             hact[q] = act[q];
         }
-        VIE_HIP(hipMemcpyAsync(beta_dev, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
+        VIE_HIP(hipMemcpyAsync(S.beta, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
         VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
         if (v32)
-            hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(), n,
-                               (const double *)beta_dev, 1, (const int *)S.active);
+            hipLaunchKernelGGL(k_store<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(),
+                               mixed_pc ? vlo.as<c64>() : (c64 *)nullptr, n, (const double *)S.beta,
+                               (const int *)S.active);
         else
-            hipLaunchKernelGGL(k_scale<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(), n,
-                               (const double *)beta_dev, 1, (const int *)S.active);
-        if (mixed_pc)
-            hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, vlo.as<c64>(), n,
-                               (const double *)beta_dev, 1, (const int *)S.active);
-        VIE_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_setg, dim3((unsigned)(((m + 1) * R + 63) / 64)), dim3(64), 0, s, S.g, m + 1,
-                           (const double *)beta_dev, R);
+            hipLaunchKernelGGL(k_store<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(),
+                               mixed_pc ? vlo.as<c64>() : (c64 *)nullptr, n, (const double *)S.beta,
+                               (const int *)S.active);
         VIE_HIP(hipGetLastError());
         int j = 0;
         while (j < m && nact > 0) {
@@ -616,16 +854,11 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                     VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s));
                 }
             }
+            c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
             if (v32)
-                VIE_CHECK(cgs2_step<c64>(C, Vb.as<const c64>(), ldj, j, w, S, m, grid_e, Vb.as<c64>() + (j + 1) * ldj));
+                VIE_CHECK(arnoldi_step<c64>(C, Vb.as<c64>(), ldj, j, w, S, vl));
             else
-                VIE_CHECK(cgs2_step<c128>(C, Vb.as<const c128>(), ldj, j, w, S, m, grid_e,
-                                          Vb.as<c128>() + (j + 1) * ldj));
-            if (mixed_pc) {  // the complex64 copy of v_{j+1} = w / h_{j+1,j}
-                hipLaunchKernelGGL(k_scale<c64>, grid_e, dim3(256), 0, s, (const c128 *)w, vlo.as<c64>(), n,
-                                   (const double *)(S.st + 1), 4, (const int *)S.active);
-                VIE_HIP(hipGetLastError());
-            }
+                VIE_CHECK(arnoldi_step<c128>(C, Vb.as<c128>(), ldj, j, w, S, vl));
             VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
             ++j;
             bool changed = false;
@@ -649,9 +882,19 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
             }
         }
-        // x += Z y
-        for (int q = 0; q < R; ++q) hjr[q] = jr[q];
+        // last columns completed, then x += Z y
+        int max_jr = 0;
+        for (int q = 0; q < R; ++q) {
+            hjr[q] = jr[q];
+            max_jr = std::max(max_jr, jr[q]);
+        }
         VIE_HIP(hipMemcpyAsync(jr_dev, hjr, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        if (max_jr > 0) {
+            if (v32)
+                VIE_CHECK(arnoldi_finish<c64>(C, Vb.as<const c64>(), ldj, jr_dev, max_jr, S));
+            else
+                VIE_CHECK(arnoldi_finish<c128>(C, Vb.as<const c128>(), ldj, jr_dev, max_jr, S));
+        }
         hipLaunchKernelGGL(k_lsq, dim3((R + 63) / 64), dim3(64), 0, s, S, (const int *)jr_dev, R);
         VIE_HIP(hipGetLastError());
         if (lowpc)

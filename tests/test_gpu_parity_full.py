@@ -217,3 +217,43 @@ def test_full_size_solve_against_fft_reference(gpu_lib, case):
         assert st[q]['status'] == 0 and info['converged']
         assert res[q] <= tol * 1.01
         assert err < (1e-9 if mode == 'fp64' else 1e-4)
+
+
+# ---------------------------------------------------------------- scale invariance
+@pytest.mark.parametrize("mode", ['fp64', 'mixed'])
+def test_solve_is_scale_invariant(gpu_lib, mode):
+    """Regression for the Arnoldi vectors' range: the same 64x8x4 guide system with b scaled by
+    1e-20, 1 and 1e20 takes the same iterations and gives x scaled alike (the basis vectors are
+    stored at unit size whatever |b|, also in complex64); the unscaled solution meets the
+    oracle-evaluated residual."""
+    import torch
+    cfg = W.CONFIGS[1]
+    grid, delta = cfg['grid'], cfg['delta']
+    K = OG.generator_octant(grid, KB * delta)
+    chi = W.make_chi(cfg)
+    M = OCT.contrast_from_chi(chi)
+    A = OM.operator_matrix(K, M, grid)
+    R = 2
+    B = np.tile(M.reshape(-1), 3)[None] * _sources(grid, delta, 'waveguide', R, 64)
+    mixed = mode == 'mixed'
+    op = gpu_lib.Operator(grid, delta, KB, chi, build_c64=mixed)
+    pc = gpu_lib.Preconditioner(op, factor_prec=gpu_lib.VIE_C64 if mixed else gpu_lib.VIE_C128)
+    tol = 1e-6 if mixed else 1e-11
+    out = {}
+    for sc in (1e-20, 1.0, 1e20):
+        Bd = _to_dev(B * sc)
+        Xd = torch.zeros_like(Bd)
+        st = gpu_lib.solve(op, pc, Bd, Xd, nrhs=R, tol=tol, mode=mode)
+        out[sc] = ([q['iters'] for q in st], Xd.cpu().numpy() / sc, [q['status'] for q in st])
+    pc.close()
+    op.close()
+    for sc in (1e-20, 1e20):
+        print('%s scale %g: iterations %s (unscaled %s), x difference %.2e'
+              % (mode, sc, out[sc][0], out[1.0][0], _rel(out[sc][1], out[1.0][1])))
+        assert out[sc][2] == [0] * R
+        assert all(abs(a - b) <= 1 for a, b in zip(out[sc][0], out[1.0][0]))
+        assert _rel(out[sc][1], out[1.0][1]) < (1e-5 if mixed else 1e-10)
+    X = out[1.0][1]
+    for q in range(R):
+        res = np.linalg.norm(B[q] - A @ X[q]) / np.linalg.norm(B[q])
+        assert res <= tol * 1.01
