@@ -381,8 +381,8 @@ vie_status vie_trim(void);
  * matrix-core solve) on a copy of the data; the first vie_matvec for a new shape and
  * right-hand-side count times the right-hand sides per workgroup of the register plane pass
  * (or the threads of the LDS plane pass) and the threads of the LDS x-line passes; and
- * precond_setup times the sub-panels per macro panel (1, 2, 4, 8) of the batched LU on a
- * copy of the first min(blocks, 256) blocks.  The fastest is kept for the rest of the
+ * precond_setup times the sub-panels per macro panel (1, 2, 4, 8) and the sub-panel width
+ * (32, 16 columns) of the batched LU on a copy of the first min(blocks, 256) blocks.  The fastest is kept for the rest of the
  * process, keyed by the shape.  Results never depend on the choice beyond rounding order.
  * vie_autotune_report writes the cache as text ("key -> choice (ms, candidates)" lines)
  * into buf (truncated to size - 1 characters, NUL-terminated); *needed receives the full

@@ -563,6 +563,7 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     cpx<R> *Yi = Y + (long long)it * m * WC;
     const cpx<R> *Ya = Yadd ? Yadd + (long long)it * m * WC : nullptr;
     constexpr bool kBf16 = sizeof(FT) == 4;
+    static_assert(!kBf16 || sizeof(R) == 4, "bfloat16 factors are solved in FP32");
     uint32_t *Yh = kBf16 ? Yb + (long long)it * 2 * WC * mp : nullptr;
     uint32_t *Yl = kBf16 ? Yh + (long long)WC * mp : nullptr;
     if (kBf16)  // zero padding rows m..mp-1 of the split copy (read by the last ragged K-step)
@@ -632,23 +633,23 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                     return (row >= w || kc >= w || kc < row) ? czero<R>() : v;
                 });
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
+            for (int ct = 0; ct < CT; ++ct) {
+                uint32_t hv[4], lv[4];  // hi + lo bfloat16 split of the solved rows (bfloat16 factors)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = wrow + Mfma<R>::acc_row(q, v);
                     const cpx<R> x = mk(cr[ct][v], ci[ct][v]);
                     ys_c[row * WC + ct * 16 + r] = x;
+                    if constexpr (kBf16) {
+                        const uint32_t hr = bf16_bits((float)x.re), hi_ = bf16_bits((float)x.im);
+                        const float lr = (float)x.re - __uint_as_float(hr << 16);
+                        const float li = (float)x.im - __uint_as_float(hi_ << 16);
+                        hv[v] = hr | (hi_ << 16);
+                        lv[v] = bf16_bits(lr) | (bf16_bits(li) << 16);
+                    }
                     if (row < w) {
                         const long long yo = (long long)(t0 + row) * WC + ct * 16 + r;
                         Yi[yo] = x;
-                        if (kBf16) {  // hi + lo bfloat16 split of the solved row
-                            const uint32_t hr = bf16_bits((float)x.re), hi_ = bf16_bits((float)x.im);
-                            const float lr = (float)x.re - __uint_as_float(hr << 16);
-                            const float li = (float)x.im - __uint_as_float(hi_ << 16);
-                            const long long bo = (long long)(ct * 16 + r) * mp + t0 + row;
-                            Yh[bo] = hr | (hi_ << 16);
-                            Yl[bo] = bf16_bits(lr) | (bf16_bits(li) << 16);
-                        }
                         if (!lower && off[ct] >= 0 && out_mode != 1) {
                             const cpx<R> o = out_mode == 2 ? x + Ya[yo] : x;
                             work[off[ct] + (long long)(t0 + row) * n] =
@@ -656,6 +657,25 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                         }
                     }
                 }
+                if constexpr (kBf16) {
+                    // FP32 accumulators: register v holds row wrow + 4q + v, so a lane's four rows are
+                    // consecutive in the column-major split copy: one 16-byte store each (rows
+                    // t0 + wrow + 4q.. are 16-byte aligned: t0, wrow and mp are multiples of 16)
+                    const int row0 = wrow + 4 * q;
+                    const long long bo = (long long)(ct * 16 + r) * mp + t0 + row0;
+                    if (row0 + 3 < w) {
+                        *reinterpret_cast<uint4 *>(Yh + bo) = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+                        *reinterpret_cast<uint4 *>(Yl + bo) = make_uint4(lv[0], lv[1], lv[2], lv[3]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (row0 + v < w) {
+                                Yh[bo + v] = hv[v];
+                                Yl[bo + v] = lv[v];
+                            }
+                    }
+                }
+            }
         }
         __syncthreads();
         // the other tiles of the super-tile that still need this one

@@ -435,8 +435,8 @@ __global__ void __launch_bounds__(32 * G) k_lu_panel_reg(cpx<R> *A, int *ipiv, i
 // wavefront max-reduction of the ROCm device library (every lane receives the maximum)
 extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
 
-template <class R, int RPT, int MAXT, int jj>
-__device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][LU_NB], int (&pos)[RPT], const int j0, const int w,
+template <class R, int RPT, int MAXT, int NBW, int jj>
+__device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][NBW], int (&pos)[RPT], const int j0, const int w,
                                                   const int mrem, const int t, const int T, const int lane,
                                                   const int wid, const int nw, cpx<R> *rowp, unsigned long long *wkey,
                                                   int *piv, int *info) {
@@ -473,7 +473,7 @@ __device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][LU_NB], int (
             const R rd = R(1) / cabs2(pv);
             rowp[jj] = mk(pv.re * rd, -pv.im * rd);
 #pragma unroll
-            for (int c = jj + 1; c < LU_NB; ++c) rowp[c] = v[sidx][c];
+            for (int c = jj + 1; c < NBW; ++c) rowp[c] = v[sidx][c];
             pos[sidx] = jj;
         } else if (pos[sidx] == jj) {
             pos[sidx] = pp;
@@ -489,9 +489,9 @@ __device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][LU_NB], int (
             // four pivot-row entries at a time, so that the LDS reads are not all hoisted
             // into registers ahead of the products; columns >= w hold zeros and stay zero
 #pragma unroll
-            for (int c0 = jj + 1; c0 < LU_NB; c0 += 4) {
+            for (int c0 = jj + 1; c0 < NBW; c0 += 4) {
 #pragma unroll
-                for (int c = c0; c < c0 + 4 && c < LU_NB; ++c) v[sidx][c] = cfms(v[sidx][c], l, rowp[c]);
+                for (int c = c0; c < c0 + 4 && c < NBW; ++c) v[sidx][c] = cfms(v[sidx][c], l, rowp[c]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -499,27 +499,29 @@ __device__ __forceinline__ void panel_rows_column(cpx<R> (&v)[RPT][LU_NB], int (
     if (t == 0) piv[jj] = j0 + pp;
 }
 
-template <class R, int RPT, int MAXT, int... J>
-__device__ __forceinline__ void panel_rows_all(std::integer_sequence<int, J...>, cpx<R> (&v)[RPT][LU_NB],
+template <class R, int RPT, int MAXT, int NBW, int... J>
+__device__ __forceinline__ void panel_rows_all(std::integer_sequence<int, J...>, cpx<R> (&v)[RPT][NBW],
                                                int (&pos)[RPT], int j0, int w, int mrem, int t, int T, int lane,
                                                int wid, int nw, cpx<R> *rowp, unsigned long long *wkey, int *piv,
                                                int *info) {
-    ((J < w ? panel_rows_column<R, RPT, MAXT, J>(v, pos, j0, w, mrem, t, T, lane, wid, nw, rowp, wkey, piv, info)
+    ((J < w ? panel_rows_column<R, RPT, MAXT, NBW, J>(v, pos, j0, w, mrem, t, T, lane, wid, nw, rowp, wkey, piv, info)
             : void()),
      ...);
 }
 
-template <class R, int RPT, int MAXT>
+// NBW: the panel's largest width (w <= NBW columns; NBW < LU_NB for narrower sub-panels whose
+// rows would not fit the registers at full width).
+template <class R, int RPT, int MAXT, int NBW = LU_NB>
 __global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, int *info, int m, int j0, int w,
                                                         int *moves) {
-    __shared__ cpx<R> rowp[LU_NB];
+    __shared__ cpx<R> rowp[NBW];
     __shared__ unsigned long long wkey[MAXT / 64];
     __shared__ int nmove;
     const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = T >> 6;
     const int mrem = m - j0;
     cpx<R> *a = A + (long long)blockIdx.x * m * m + (long long)j0 * m + j0;
     int *piv = ipiv + (long long)blockIdx.x * m + j0;
-    cpx<R> v[RPT][LU_NB];
+    cpx<R> v[RPT][NBW];
     int pos[RPT];
     // column bases are uniform, row offsets 32-bit: scalar-base addressing, no per-lane 64-bit
     // addresses kept live
@@ -528,23 +530,23 @@ __global__ void __launch_bounds__(MAXT) k_lu_panel_rows(cpx<R> *A, int *ipiv, in
         const int row = t + sidx * T;
         pos[sidx] = row;
 #pragma unroll
-        for (int c = 0; c < LU_NB; ++c) {
+        for (int c = 0; c < NBW; ++c) {
             const cpx<R> *col = a + c * m;
             v[sidx][c] = (c < w && row < mrem) ? col[row] : czero<R>();
         }
     }
     if (t == 0) nmove = 0;
-    panel_rows_all<R, RPT, MAXT>(std::make_integer_sequence<int, LU_NB>{}, v, pos, j0, w, mrem, t, T, lane, wid, nw,
-                                 rowp, wkey, piv, info);
+    panel_rows_all<R, RPT, MAXT, NBW>(std::make_integer_sequence<int, NBW>{}, v, pos, j0, w, mrem, t, T, lane, wid,
+                                      nw, rowp, wkey, piv, info);
     // the panel's row moves for the other columns: (destination, source) of every row that
-    // changed position, at most 2 LU_NB of them
+    // changed position, at most 2 NBW of them
     int *mv = moves + (long long)blockIdx.x * LU_MOVES;
 #pragma unroll
     for (int sidx = 0; sidx < RPT; ++sidx) {
         const int row = t + sidx * T;
         if (row < mrem) {
 #pragma unroll
-            for (int c = 0; c < LU_NB; ++c) {
+            for (int c = 0; c < NBW; ++c) {
                 cpx<R> *col = a + c * m;
                 if (c < w) col[pos[sidx]] = v[sidx][c];
             }
@@ -969,18 +971,33 @@ __global__ void __launch_bounds__(256) k_invert_diag(cpx<R> *F, int m) {
 template <class R>
 static cpx<R> *A_of(vie_pc pc) { return pc->factors.as<cpx<R>>(); }
 
+// Width of the LU sub-panel starting with mrem rows: `pref` (LU_NB or LU_NB / 2; autotuned),
+// and LU_NB / 2 for FP64 panels of 513-768 rows, which one thread per row holds in registers
+// only at half width (768 threads leave 170 VGPRs each: 32 complex doubles per row spilled,
+// 16 fit).
+template <class R>
+static int lu_sub_width(int mrem, int pref) {
+    return (sizeof(R) == 8 && mrem > 512 && mrem <= 768) ? LU_NB / 2 : pref;
+}
+
 // LU with partial pivoting of nb column-major m x m blocks A (in place), all launches on
 // stream `s`; ns = sub-panels of LU_NB columns per macro panel.  ipiv (nb x m), linv
 // (nb x LU_NB^2) and moves (nb x LU_MOVES) are scratch; info[b] is set nonzero for a
 // singular block.
 template <class R>
 static vie_status lu_factor_blocks(int m, int nb, cpx<R> *A, int *ipiv, cpx<R> *linv, int *moves, int *info,
-                                   int ns, hipStream_t s) {
+                                   int ns, int wsub, hipStream_t s) {
     auto panel = [&](int j0, int w) -> vie_status {
         ProfScope ps("lu_panel", s);
         const int mrem = m - j0;
         // row-resident panel while the rows fit the registers of one workgroup
         if constexpr (sizeof(R) == 8) {
+            if (mrem <= 768 && w <= LU_NB / 2) {  // half-width sub-panels (lu_sub_width)
+                hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 768, LU_NB / 2>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s,
+                                   A, ipiv, info, m, j0, w, moves);
+                VIE_HIP(hipGetLastError());
+                return VIE_OK;
+            }
             if (mrem <= 512) {
                 hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 512>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
                                    info, m, j0, w, moves);
@@ -988,6 +1005,12 @@ static vie_status lu_factor_blocks(int m, int nb, cpx<R> *A, int *ipiv, cpx<R> *
                 return VIE_OK;
             }
         } else {
+            if (mrem <= 1024 && w <= LU_NB / 2) {
+                hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 1024, LU_NB / 2>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0,
+                                   s, A, ipiv, info, m, j0, w, moves);
+                VIE_HIP(hipGetLastError());
+                return VIE_OK;
+            }
             if (mrem <= 1024) {
                 hipLaunchKernelGGL((k_lu_panel_rows<R, 1, 1024>), dim3(nb), dim3((mrem + 63) / 64 * 64), 0, s, A, ipiv,
                                    info, m, j0, w, moves);
@@ -1048,17 +1071,17 @@ static vie_status lu_factor_blocks(int m, int nb, cpx<R> *A, int *ipiv, cpx<R> *
         VIE_HIP(hipGetLastError());
         return VIE_OK;
     };
-    // Two-level right-looking LU: macro panels of ns sub-panels of LU_NB columns.  Each
+    // Two-level right-looking LU: macro panels of ns LU_NB columns, factored as sub-panels of
+    // lu_sub_width columns (LU_NB, or half that for large FP64 panels).  Each
     // sub-panel first takes the updates of the earlier sub-panels of its macro panel (its
     // columns from row jr down), is factored, has its interchanges applied everywhere, and its
     // rows right of it take the same updates before the U12 solve; the trailing matrix is
     // updated once per macro panel, with K = the macro panel's width.
-    for (int J0 = 0; J0 < m; J0 += ns * LU_NB) {
-        int jend = J0;
-        for (int i = 0; i < ns && J0 + i * LU_NB < m; ++i) {
-            const int jr = J0 + i * LU_NB, w = std::min(LU_NB, m - jr);
-            jend = jr + w;
-            if (i == 0) {
+    for (int J0 = 0; J0 < m;) {
+        const int jend = std::min(m, J0 + ns * LU_NB);
+        for (int jr = J0, w = 0; jr < jend; jr += w) {
+            w = std::min(lu_sub_width<R>(m - jr, wsub), jend - jr);
+            if (jr == J0) {
                 VIE_CHECK(panel(jr, w));
                 VIE_CHECK(swap_trsm(jr, w, 1, 1));
             } else {
@@ -1070,29 +1093,34 @@ static vie_status lu_factor_blocks(int m, int nb, cpx<R> *A, int *ipiv, cpx<R> *
             }
         }
         VIE_CHECK(update(jend, m, jend, m, J0, jend - J0));             // trailing matrix
+        J0 = jend;
     }
     return VIE_OK;
 }
 
-// Sub-panels per macro panel of the batched LU: the default, or with autotuning the fastest of
-// 1, 2, 4, 8 timed on a copy of the first min(nb, 256) blocks (one block per compute unit,
-// the LU's own launch shape), cached per (precision, m, block count).  Measured default: FP32
-// gains from wider macro panels (fewer passes over the trailing matrix; 4 sub-panels: -13%
-// update time at 1024 blocks of 768), FP64 does not (2: the matrix-core time dominates).
+// Macro-panel and sub-panel shape of the batched LU: the default, or with autotuning the
+// fastest of {1, 2, 4, 8} sub-panels per macro panel x sub-panel width {LU_NB, LU_NB / 2},
+// timed on a copy of the first min(nb, 256) blocks (one block per compute unit, the LU's own
+// launch shape), cached per (precision, m, block count).  Measured default: FP32 gains from
+// wider macro panels (fewer passes over the trailing matrix; 4 sub-panels: -13% update time
+// at 1024 blocks of 768), FP64 does not (2: the matrix-core time dominates).
 template <class R>
-static vie_status lu_macro_panels(vie_pc pc, int *ipiv, cpx<R> *linv, int *moves, hipStream_t s, int *ns_out) {
+static vie_status lu_macro_panels(vie_pc pc, int *ipiv, cpx<R> *linv, int *moves, hipStream_t s, int *ns_out,
+                                  int *w_out) {
     const int m = pc->m, nb = pc->nstored;
-    int ns = sizeof(R) == 8 ? 2 : 4;
+    int ns = sizeof(R) == 8 ? 2 : 4, wsub = LU_NB;
     if (tune_enabled() && m > LU_NB) {
         char key[128];
         snprintf(key, sizeof key, "lu_factor real=%d m=%d blocks=%d", (int)sizeof(R) * 8, m, nb);
         std::vector<std::vector<int>> cands;
         for (int c : {1, 2, 4, 8})
-            if ((c - 1) * LU_NB < m) cands.push_back({c});
+            if ((c - 1) * LU_NB < m)
+                for (int wc : {LU_NB, LU_NB / 2}) cands.push_back({c, wc});
         std::vector<int> choice;
         if (tune_lookup(key, &choice)) {
             VIE_CHECK(tune_check_choice(key, choice, cands));
             ns = choice[0];
+            wsub = choice[1];
         } else {
             const int sample = std::min(nb, 256);
             const size_t bytes = sizeof(cpx<R>) * (size_t)sample * m * m;
@@ -1101,19 +1129,20 @@ static vie_status lu_macro_panels(vie_pc pc, int *ipiv, cpx<R> *linv, int *moves
             VIE_CHECK(info.ensure(sizeof(int) * (size_t)sample));
             double best = 1e300;
             for (auto &cv : cands) {
-                const int c = cv[0];
                 double ms = 0;
                 VIE_CHECK(tune_time(s, 1, [&]() -> vie_status {
                     VIE_HIP(hipMemcpyAsync(copy.p, pc->factors.p, bytes, hipMemcpyDeviceToDevice, s));
                     VIE_HIP(hipMemsetAsync(info.p, 0, sizeof(int) * (size_t)sample, s));
-                    return lu_factor_blocks<R>(m, sample, copy.as<cpx<R>>(), ipiv, linv, moves, info.as<int>(), c, s);
+                    return lu_factor_blocks<R>(m, sample, copy.as<cpx<R>>(), ipiv, linv, moves, info.as<int>(), cv[0],
+                                               cv[1], s);
                 }, &ms));
-                if (ms < best) best = ms, ns = c;
+                if (ms < best) best = ms, ns = cv[0], wsub = cv[1];
             }
-            tune_store(key, {ns}, best, (int)cands.size());
+            tune_store(key, {ns, wsub}, best, (int)cands.size());
         }
     }
     *ns_out = ns;
+    *w_out = wsub;
     return VIE_OK;
 }
 
@@ -1125,11 +1154,11 @@ static vie_status lu_factor(vie_pc pc, hipStream_t s) {
     VIE_CHECK(ipiv.ensure(sizeof(int) * (size_t)nb * m));
     VIE_CHECK(linv.ensure(sizeof(cpx<R>) * (size_t)nb * LU_NB * LU_NB));
     VIE_CHECK(moves.ensure(sizeof(int) * (size_t)nb * LU_MOVES));
-    int ns = 0;
-    VIE_CHECK(lu_macro_panels<R>(pc, ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(), s, &ns));
+    int ns = 0, wsub = 0;
+    VIE_CHECK(lu_macro_panels<R>(pc, ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(), s, &ns, &wsub));
     VIE_HIP(hipMemsetAsync(pc->info.p, 0, sizeof(int) * nb, s));
     VIE_CHECK(lu_factor_blocks<R>(m, nb, A_of<R>(pc), ipiv.as<int>(), linv.as<cpx<R>>(), moves.as<int>(),
-                                  pc->info.as<int>(), ns, s));
+                                  pc->info.as<int>(), ns, wsub, s));
     hipLaunchKernelGGL(k_lu_perm, dim3((nb + 63) / 64), dim3(64), 0, s, ipiv.as<int>(), pc->perm.as<int>(), m,
                        nb);
     VIE_HIP(hipGetLastError());

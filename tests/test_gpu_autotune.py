@@ -6,8 +6,8 @@ results are compared with the oracle, not only with the default launch:
 * operator products (right-hand sides per workgroup of the register plane pass x threads of
   the LDS x-line passes) on a 64x8x4 grid (LDS x lines) and a 512x16x8 grid (register x lines),
   FP64 and complex64, entry by entry against the oracle's FFT reference operator;
-* the batched LU's sub-panels per macro panel (1, 2, 4, 8) on 384 x 384 blocks, FP64 and
-  complex64 factors, and the block solves' per-mode and matrix-core candidates, each as the
+* the batched LU's sub-panels per macro panel (1, 2, 4, 8) x sub-panel width (32, 16) on
+  384 x 384 blocks, FP64 and complex64 factors, and the block solves' per-mode and matrix-core candidates, each as the
   preconditioner's apply against the oracle's blocked preconditioner;
 * a lockstep solve with every family tuned by timing, each column against the dense solution.
 
@@ -161,11 +161,12 @@ def test_every_lu_and_block_solve_candidate_matches_oracle(gpu_lib):
                 nbs = _ncand(gpu_lib, bs[0])
                 tried = 0
                 for ns in (1, 2, 4, 8):
-                    z = _forced(gpu_lib, lu[0], [ns], apply)
-                    assert z is not None  # m = 384: all four are candidates
-                    err = _rel(z, z_ref)
-                    print('%s -> %d: apply error %.2e' % (lu[0], ns, err))
-                    assert err < bar
+                    for wsub in (32, 16):
+                        z = _forced(gpu_lib, lu[0], [ns, wsub], apply)
+                        assert z is not None  # m = 384: all eight are candidates
+                        err = _rel(z, z_ref)
+                        print('%s -> %d %d: apply error %.2e' % (lu[0], ns, wsub, err))
+                        assert err < bar
                 cands = [[0, 0, rc, 1 << 30] for rc in (1, 2, 4, 8, 16, 32, 64)]
                 fp32 = fprec != gpu_lib.VIE_C128
                 cands += [[g, nw, 0, 8] for g in (16, 32, 64) for nw in ((8, 16) if fp32 else (4, 8))]
