@@ -1026,9 +1026,11 @@ static vie_status block_solve_run(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hi
     } else {                                                                                             \
         launch_wide<R, CTV, FT>(pc, w, work, Y, nrhs, 1, nullptr, s);                                       \
         VIE_HIP(hipGetLastError());                                                                      \
-        ProfScope pr("refine_residual", s);                                                              \
-        launch_residual<CTV>(pc, w, (c64 *)work, (const c64 *)Y, nrhs, s);                                  \
-        VIE_HIP(hipGetLastError());                                                                      \
+        {                                                                                                \
+            ProfScope pr("refine_residual", s);                                                          \
+            launch_residual<CTV>(pc, w, (c64 *)work, (const c64 *)Y, nrhs, s);                              \
+            VIE_HIP(hipGetLastError());                                                                  \
+        }                                                                                                \
         launch_wide<R, CTV, FT>(pc, w, work, Y2, nrhs, 2, Y, s);                                            \
     }
         switch (w->wide_ct) {

@@ -25,6 +25,9 @@
 // a fixed preconditioner span{P^{-1} u_i} = P^{-1} span{q_i}, and the iterates are GMRES's.
 // All sums are FP64; one residual estimate and breakdown flag per right-hand side are read
 // back per step.  Each cycle ends with x += Z y and the FP64 true residual r = b - A x.
+// Every right-hand side runs its own restart cycles in a ring of basis slots (ring_slot), so
+// a column can end a cycle, restart or enter (a queued request taking a free slot) at any step
+// while the others go on; a column's arithmetic never depends on the others'.
 //
 // FP64 mode: basis, z, products and factors complex128.  Mixed mode: the basis (u_j, then q_j)
 // is stored in complex64 and u_j feeds the complex64 preconditioner and operator product, whose
@@ -159,27 +162,37 @@ __global__ void __launch_bounds__(KR_THREADS) k_reduce(const c128 *partial, int 
     if (threadIdx.x == 0) out[(long long)r * ostride + i] = s;
 }
 
-// Reduction pass of an Arnoldi step, per right-hand side r (skipped when inactive, or when
-// nq_r gives it no basis vectors): with nq basis vectors q_i in slots 0..nq-1 (nq = nq_r[r] if
-// nq_r is given), u in slot nq and w (optional),
+// Basis slots form a ring of m + 1 per right-hand side: basis vector i of column r's current
+// cycle lives in slot (s0_r + i) mod (m + 1), s0_r being the slot its cycle started in.  Columns
+// that started together share the slot of every step; a column that (re)starts later keeps its
+// own offset, and at any step the vector every active column needs next sits in one common
+// slot (the step index mod m + 1), so the batched preconditioner and product read one slot.
+__device__ __forceinline__ long long ring_slot(int s0, int i, int m1) {
+    const int k = s0 + i;
+    return k >= m1 ? k - m1 : k;
+}
+
+// Reduction pass of an Arnoldi step, per right-hand side r with mask[r] set (no mask: all), and
+// with nq = nq_r[r] basis vectors q_i, u in the ring slot after them, and w (optional):
 //   partial[(r * gridDim.x + blk) * stride + k] = the part's share of
 //     k < nq: conj(q_k) . u;  with w: nq + k: conj(q_k) . w, then 2nq: |u|^2, 2nq+1: conj(u) . w,
 //     2nq+2: |w|^2;  without w: nq: |u|^2.
-// The outputs are formed KR_DG2 basis vectors at a time (u and w read once per group); inside a
-// group the loads of an element are unconditional (a short last group clamps its index and
-// drops the extra products), so they are in flight together.
+// need_nq skips columns with nq = 0 (the finishing reduction of a cycle).  The outputs are
+// formed KR_DG2 basis vectors at a time (u and w read once per group); inside a group the
+// loads of an element are unconditional (a short last group clamps its index and drops the
+// extra products), so they are in flight together.
 #define KR_DG2 8
 template <class VT>
-__global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj, int nq, const int *nq_r,
-                                                      const c128 *w, long long n, const int *active, int stride,
-                                                      c128 *partial) {
+__global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj, int m1, const int *nq_r,
+                                                      const int *s0_r, const c128 *w, long long n, const int *mask,
+                                                      int need_nq, int stride, c128 *partial) {
     __shared__ c128 sh[2 * KR_DG2 + 3][KR_THREADS / 64];
     const int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const int nqr = nq_r ? nq_r[r] : nq;
-    if (nq_r && nqr == 0) return;
+    if (mask && !mask[r]) return;
+    const int nqr = nq_r[r], s0 = s0_r[r];
+    if (need_nq && nqr == 0) return;
     const VT *Vr = V + r * n;
-    const VT *ur = Vr + nqr * ldj;
+    const VT *ur = Vr + ring_slot(s0, nqr, m1) * ldj;
     const c128 *wr = w ? w + r * n : nullptr;
     const long long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
@@ -191,6 +204,9 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
     for (int gi = 0; gi < ngroups; ++gi) {
         const int i0 = gi * KR_DG2, cnt = max(0, min(KR_DG2, nqr - i0));
         const bool self = gi == 0;
+        const VT *vp[KR_DG2];
+#pragma unroll
+        for (int u = 0; u < KR_DG2; ++u) vp[u] = Vr + ring_slot(s0, min(i0 + u, last), m1) * ldj;
         c128 as[KR_DG2], ac[KR_DG2], sd = czero<double>();
         double sa = 0.0, se = 0.0;
 #pragma unroll
@@ -200,7 +216,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
             const c128 we = wr ? wr[e] : czero<double>();
             c128 v[KR_DG2];
 #pragma unroll
-            for (int u = 0; u < KR_DG2; ++u) v[u] = wide(Vr[min(i0 + u, last) * ldj + e]);
+            for (int u = 0; u < KR_DG2; ++u) v[u] = wide(vp[u][e]);
 #pragma unroll
             for (int u = 0; u < KR_DG2; ++u)
                 if (u < cnt) {
@@ -253,16 +269,19 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
     }
 }
 
-// Update pass of an Arnoldi step, per active right-hand side r, with co = coef + r * cstride =
-// [s_i (nq) | c_i - s_i h/alpha (nq) | 1/alpha | h/alpha | 1/sigma]:
-//   slot nq:      q_j = (u_j - sum_i q_i s_i) / alpha                                  (over u_j)
-//   slot nq + 1:  u_{j+1} = (w - sum_i q_i (c_i - s_i h/alpha) - u_j h/alpha) / sigma   (and a complex64 copy in vlo)
+// Update pass of an Arnoldi step, per active right-hand side r with nq = nq_r[r] basis vectors
+// in its ring (above) and co = coef + r * cstride = [s_i (nq) | c_i - s_i h/alpha (nq) | 1/alpha |
+// h/alpha | 1/sigma]:
+//   slot of u_j:  q_j = (u_j - sum_i q_i s_i) / alpha                                  (over u_j)
+//   next slot:    u_{j+1} = (w - sum_i q_i (c_i - s_i h/alpha) - u_j h/alpha) / sigma   (and a complex64 copy in vlo)
 //   partial[r * gridDim.x + blk] = the part's share of |u_{j+1}|^2 (FP64 values).
-// An inactive right-hand side stopped at an earlier step (or never started this cycle), so slot
-// nq + 1 lies past its last u: it is zeroed (with its complex64 copy), so that the products and
-// preconditioner applies of the batch never read stale values for it.
+// The next slot is next_slot for every active column.  An inactive column's slot next_slot
+// lies past its last basis vector (its cycle ended before this step; within one cycle of at
+// most m steps the ring does not come back to it), so it is zeroed, with its complex64 copy:
+// the batch's preconditioner applies and products then never read stale values for it.
 template <class VT>
-__global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, int nq, const c128 *coef, int cstride,
+__global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, int m1, const int *nq_r,
+                                                        const int *s0_r, int next_slot, const c128 *coef, int cstride,
                                                         const c128 *w, long long n, const int *active, c64 *vlo,
                                                         c128 *partial) {
     typedef decltype(V->re) T;
@@ -271,21 +290,22 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
     const int r = blockIdx.y;
     const long long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    VT *Vr = V + r * n;
+    VT *un = Vr + next_slot * ldj;
     if (!active[r]) {
-        VT *un = V + r * n + (nq + 1) * ldj;
         for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
             un[e] = mk((T)0, (T)0);
             if (vlo) vlo[r * n + e] = mk(0.0f, 0.0f);
         }
         return;
     }
+    const int nq = nq_r[r], s0 = s0_r[r];
     const c128 *co = coef + (long long)r * cstride;
     for (int i = threadIdx.x; i < 2 * nq + 3; i += KR_THREADS) cs[i] = co[i];
     __syncthreads();
     const double ia = cs[2 * nq].re, isg = cs[2 * nq + 2].re;
     const c128 hu = cs[2 * nq + 1];
-    VT *Vr = V + r * n;
-    VT *ur = Vr + nq * ldj, *un = Vr + (nq + 1) * ldj;
+    VT *ur = Vr + ring_slot(s0, nq, m1) * ldj;
     const c128 *wr = w + r * n;
     c64 *lr = vlo ? vlo + r * n : nullptr;
     double nrm = 0.0;
@@ -296,7 +316,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
         for (; i + 8 <= nq; i += 8) {  // eight loads in flight, products in order of i
             c128 v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = wide(Vr[(i + k) * ldj + e]);
+            for (int k = 0; k < 8; ++k) v[k] = wide(Vr[ring_slot(s0, i + k, m1) * ldj + e]);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 aq = cfms(aq, v[k], cs[i + k]);
@@ -304,7 +324,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
             }
         }
         for (; i < nq; ++i) {
-            const c128 v = wide(Vr[i * ldj + e]);
+            const c128 v = wide(Vr[ring_slot(s0, i, m1) * ldj + e]);
             aq = cfms(aq, v, cs[i]);
             aw = cfms(aw, v, cs[nq + i]);
         }
@@ -319,36 +339,46 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
     if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = t;
 }
 
-// x_r += sum_{i < jr[r]} Z_i,r y_r[i]   (Z in complex128 or complex64)
+// x_r += sum_{i < jr[r]} z_i,r y_r[i], z_i of column r in the slot (z0_r + i) mod m of the ring
+// of m preconditioned vectors (Z in complex128 or complex64).
 template <class R>
-__global__ void __launch_bounds__(KR_THREADS) k_combine(const cpx<R> *Z, long long ldj, const int *jr, const c128 *y,
-                                                        int ystride, c128 *x, long long n) {
+__global__ void __launch_bounds__(KR_THREADS) k_combine(const cpx<R> *Z, long long ldj, int m, const int *jr,
+                                                        const int *z0_r, const c128 *y, int ystride, c128 *x,
+                                                        long long n) {
     __shared__ c128 ys[256];
+    __shared__ int zs[256];
     const int r = blockIdx.y;
-    const int nv = jr[r];
-    for (int i = threadIdx.x; i < nv; i += KR_THREADS) ys[i] = y[(long long)r * ystride + i];
+    const int nv = jr[r], z0 = z0_r[r];
+    for (int i = threadIdx.x; i < nv; i += KR_THREADS) {
+        ys[i] = y[(long long)r * ystride + i];
+        zs[i] = z0 + i >= m ? z0 + i - m : z0 + i;
+    }
     __syncthreads();
     if (nv == 0) return;
     for (long long e = blockIdx.x * (long long)KR_THREADS + threadIdx.x; e < n; e += (long long)gridDim.x * KR_THREADS) {
         c128 acc = x[r * n + e];
         for (int i = 0; i < nv; ++i) {
-            cpx<R> z = Z[i * ldj + r * n + e];
+            cpx<R> z = Z[zs[i] * ldj + r * n + e];
             acc = acc + mk((double)z.re, (double)z.im) * ys[i];
         }
         x[r * n + e] = acc;
     }
 }
 
-// First basis slot of a cycle: u_0 = r / beta (zero for an inactive right-hand side or a zero
-// beta), stored in the basis precision, with an optional complex64 copy.
+// First basis vector of a new cycle for the right-hand sides with mask[r] set: u_0 = r / beta
+// (zero for a zero beta) into ring slot `slot`, with an optional complex64 copy; the other
+// columns are left as they are.
 template <class VT>
-__global__ void k_store(const c128 *src, VT *v, c64 *vlo, long long n, const double *beta, const int *active) {
-    typedef decltype(v->re) T;
+__global__ void k_store(const c128 *src, VT *V, long long ldj, int slot, c64 *vlo, long long n, const double *beta,
+                        const int *mask) {
+    typedef decltype(V->re) T;
     const int r = blockIdx.y;
-    const double f = (active[r] && beta[r] > 0.0) ? 1.0 / beta[r] : 0.0;
+    if (!mask[r]) return;
+    const double f = beta[r] > 0.0 ? 1.0 / beta[r] : 0.0;
+    VT *v = V + slot * ldj + r * n;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
         const c128 a = f * src[r * n + e];
-        v[r * n + e] = mk((T)a.re, (T)a.im);
+        v[e] = mk((T)a.re, (T)a.im);
         if (vlo) vlo[r * n + e] = mk((float)a.re, (float)a.im);
     }
 }
@@ -435,10 +465,11 @@ __device__ void finish_column(GState &S, int r, int jc, const c128 *s, double al
     for (int i = lane; i <= jc; i += 64) rc[i] = col[i];
 }
 
-// After the reduction of step j, per active right-hand side (one wavefront): alpha, h, sigma,
+// After the reduction of a step, per active right-hand side r at its step j = jcol[r] of its
+// cycle (one wavefront): alpha, h, sigma,
 // the update coefficients, the step's column [c; h], and column j - 1 completed (for j = 0:
 // g = (beta alpha, 0, ...), r = beta u_0 = beta alpha q_0).
-__global__ void __launch_bounds__(64) k_arnoldi_coef(GState S, int j, int R) {
+__global__ void __launch_bounds__(64) k_arnoldi_coef(GState S, const int *jcol, int R) {
     __shared__ c128 col[KR_MAX_RESTART + 1];
     __shared__ double csl[KR_MAX_RESTART];
     __shared__ c128 snl[KR_MAX_RESTART];
@@ -446,7 +477,7 @@ __global__ void __launch_bounds__(64) k_arnoldi_coef(GState S, int j, int R) {
     __shared__ c128 shu;
     const int r = blockIdx.x, lane = threadIdx.x;
     if (r >= R || !S.active[r]) return;
-    const int m = S.m;
+    const int m = S.m, j = jcol[r];
     const c128 *h = S.h1 + (long long)r * S.hstride;  // [s (j) | c (j) | a | d | e]
     double ss = 0.0;
     c128 sc = czero<double>();
@@ -490,10 +521,11 @@ __global__ void __launch_bounds__(64) k_arnoldi_coef(GState S, int j, int R) {
     }
 }
 
-// After the update pass of step j, per active right-hand side (one wavefront): the provisional
+// After the update pass of a step, per active right-hand side r at its step j = jcol[r] (one
+// wavefront): the provisional
 // residual estimate |g_{j+1}| of column [c; h] with subdiagonal sigma |u_{j+1}| under the
 // completed rotations 0..j-1, and the breakdown flag (sigma |u_{j+1}| <= 1e-14 |w|, sigma = |w|).
-__global__ void __launch_bounds__(64) k_arnoldi_est(GState S, int j, int R) {
+__global__ void __launch_bounds__(64) k_arnoldi_est(GState S, const int *jcol, int R) {
     __shared__ c128 col[KR_MAX_RESTART + 1];
     __shared__ double csl[KR_MAX_RESTART];
     __shared__ c128 snl[KR_MAX_RESTART];
@@ -504,7 +536,7 @@ __global__ void __launch_bounds__(64) k_arnoldi_est(GState S, int j, int R) {
         if (lane == 0) st[0] = 0.0, st[1] = 0.0, st[2] = 1.0, st[3] = 0.0;
         return;
     }
-    const int m = S.m;
+    const int m = S.m, j = jcol[r];
     const c128 *pc = S.P + ((long long)r * m + j) * (m + 1);
     for (int i = lane; i <= j; i += 64) col[i] = pc[i];
     for (int i = lane; i < j; i += 64) {
@@ -588,47 +620,51 @@ vie_status norms(Ctx &C, const c128 *w, c128 *out) {
     return VIE_OK;
 }
 
-// Arnoldi step j (Sec. 1: GMRES; the orthogonalisation is this library's choice): with
-// z_j = P^{-1} u_j and w = A z_j formed, one reduction pass, the coefficients (completing
-// column j - 1), one update pass (q_j over u_j, u_{j+1} into slot j + 1, and its complex64
-// copy when vlo is given), |u_{j+1}|^2 and the provisional residual estimate.
+// One Arnoldi step of every active right-hand side (Sec. 1: GMRES; the orthogonalisation is this
+// library's choice), column r at its own step jcol[r] with its ring starting in slot s0[r]:
+// with z = P^{-1} u and w = A z formed, one reduction pass, the coefficients (completing each
+// column's previous Hessenberg column), one update pass (q over u, the next u into next_slot and
+// its complex64 copy when vlo is given), |u_next|^2 and the provisional residual estimates.
+// max_j bounds jcol over the active columns.
 template <class VT>
-vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int j, const c128 *w, GState &S, c64 *vlo) {
+vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int m1, const int *jcol, const int *s0, int max_j,
+                        int next_slot, const c128 *w, GState &S, c64 *vlo) {
     hipStream_t s = C.s;
     const long long n = C.n;
-    const int R = C.R, cnt = 2 * j + 3;
+    const int R = C.R, cnt = 2 * max_j + 3;
     {
         ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, j,
-                           (const int *)nullptr, w, n, (const int *)S.active, cnt, C.partial);
+        hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, m1, jcol, s0, w, n,
+                           (const int *)S.active, 0, cnt, C.partial);
         VIE_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce, dim3(cnt, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
                        S.hstride);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_arnoldi_coef, dim3(R), dim3(64), 0, s, S, j, R);
+    hipLaunchKernelGGL(k_arnoldi_coef, dim3(R), dim3(64), 0, s, S, jcol, R);
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update2<VT>, dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, j, (const c128 *)S.coef,
-                           S.cstride, w, n, (const int *)S.active, vlo, C.partial);
+        hipLaunchKernelGGL(k_update2<VT>, dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, m1, jcol, s0, next_slot,
+                           (const c128 *)S.coef, S.cstride, w, n, (const int *)S.active, vlo, C.partial);
         VIE_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbu, 1, S.nrm2, 1);
     VIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_arnoldi_est, dim3(R), dim3(64), 0, s, S, j, R);
+    hipLaunchKernelGGL(k_arnoldi_est, dim3(R), dim3(64), 0, s, S, jcol, R);
     VIE_HIP(hipGetLastError());
     return VIE_OK;
 }
 
-// End of a cycle: the reduction of u_{jr} against q_0..q_{jr-1} for every right-hand side that
-// took jr[r] > 0 steps (max_jr the largest), and its last column completed.
+// End of the cycles of the right-hand sides with jr[r] > 0 (max_jr the largest): the reduction of
+// u_{jr} against q_0..q_{jr-1} in each one's ring, and its last column completed.
 template <class VT>
-vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, const int *jr_dev, int max_jr, GState &S) {
+vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, int m1, const int *jr_dev, const int *s0,
+                          int max_jr, GState &S) {
     hipStream_t s = C.s;
     const int cnt = max_jr + 1;
-    hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, 0, jr_dev, (const c128 *)nullptr,
-                       C.n, (const int *)nullptr, cnt, C.partial);
+    hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, m1, jr_dev, s0,
+                       (const c128 *)nullptr, C.n, (const int *)nullptr, 1, cnt, C.partial);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(cnt, C.R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
                        S.hstride);
@@ -667,18 +703,19 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                             : "FP64 solve needs complex128 preconditioner factors");
         return VIE_EARG;
     }
-    const int m = o->restart;
+    const int m = o->restart, m1 = m + 1;
     const long long n = 3LL * op->N;
     const long long Rn = (long long)R * n;
     Ctx C{op, s, n, R, kr_parts(n, KR_EPT_DOTS), kr_parts(n, KR_EPT_UPD), nullptr, nullptr};
     // mixed: basis V and flexible basis Z in complex64, FP64 sums and w.  mixed_pc: V in
     // complex128 with a complex64 copy of its newest vector (vlo) for the preconditioner, Z in
-    // complex64, each z_j widened (zw) for the complex128 product.
+    // complex64, each z_j widened (zw) for the complex128 product.  V is a ring of m + 1 slots
+    // and Z one of m slots per right-hand side (see ring_slot).
     const bool v32 = mixed;
     const size_t vsz = v32 ? sizeof(c64) : sizeof(c128);
     const size_t zsz = lowpc ? sizeof(c64) : sizeof(c128);
     DevBuf Vb, Zb, wb, rb, part, small, w32, vlo, zw;
-    VIE_CHECK(Vb.ensure(vsz * Rn * (m + 1)));
+    VIE_CHECK(Vb.ensure(vsz * Rn * m1));
     VIE_CHECK(Zb.ensure(zsz * Rn * m));
     if (mixed_pc) {
         VIE_CHECK(vlo.ensure(sizeof(c64) * Rn));
@@ -692,9 +729,10 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     S.m = m;
     S.hstride = 2 * m + 3;
     S.cstride = 2 * m + 3;
+    constexpr int NI = 6;  // device int arrays of R: active, jcol, s0, z0, jend, mask
     size_t nc = (size_t)R * ((size_t)S.hstride + S.cstride + 1 + 2 * (size_t)m * (m + 1) + m + (m + 1) + m);
     size_t nd = (size_t)R * (2 * m + 4 + 1);
-    VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * 2 * R));
+    VIE_CHECK(small.ensure(sizeof(c128) * nc + sizeof(double) * nd + sizeof(int) * NI * R));
     c128 *cp = small.as<c128>();
     S.h1 = cp;
     cp += (size_t)R * S.hstride;
@@ -722,11 +760,12 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     S.beta = dp;
     dp += R;
     S.active = reinterpret_cast<int *>(dp);
-    int *jr_dev = S.active + R;
+    int *jcol_dev = S.active + R, *s0_dev = jcol_dev + R, *z0_dev = s0_dev + R, *jend_dev = z0_dev + R,
+        *mask_dev = jend_dev + R;
     C.partial = part.as<c128>();
     double *host = nullptr;
-    // pinned layout: doubles [0, 4R) | ints active [R] | ints jr [R]
-    VIE_HIP(hipHostMalloc((void **)&host, sizeof(double) * 4 * (size_t)R + sizeof(int) * 2 * R + 64,
+    // pinned layout: doubles [0, 4R) | ints active, jcol, s0, z0, jend, mask [R each]
+    VIE_HIP(hipHostMalloc((void **)&host, sizeof(double) * 4 * (size_t)R + sizeof(int) * NI * R + 64,
                           hipHostMallocDefault));
     struct HostFree {
         double *p;
@@ -734,13 +773,20 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     } hf{host};
     C.host = host;
     int *hact = reinterpret_cast<int *>(host + 4 * (size_t)R);
-    int *hjr = hact + R;
+    int *hjcol = hact + R, *hs0 = hjcol + R, *hz0 = hs0 + R, *hjend = hz0 + R, *hmask = hjend + R;
     c128 *w = wb.as<c128>(), *r = rb.as<c128>();
-    const long long ldj = Rn;  // stride between Arnoldi vectors
+    const long long ldj = Rn;  // stride between ring slots
     dim3 grid_e(1024, R);
 
+    // Columns run their own restart cycles.  Without a hook (vie_solve) every column starts at
+    // the first step, so all reach the end of a full cycle at the same step, and a column whose
+    // estimate converges earlier waits for that common end: one batched true residual per cycle.
+    // With a hook (the server) a column ends its cycle at the step its estimate converges, so
+    // its request can complete there, and a freed slot takes a queued right-hand side at any step.
+    const bool immediate = hook != nullptr;
     std::vector<double> nb(R), beta(R);
-    std::vector<int> done(R, 0), act(R, 0), jr(R, 0), told(R, 0);
+    std::vector<int> done(R, 0), act(R, 0), jr(R, 0), t0(R, 0), told(R, 0), pend(R, 0);
+    vie_status result = VIE_OK;
     for (int q = 0; q < R; ++q) stats[q] = vie_solve_stats{0, 0, 0.0, VIE_OK};
     VIE_CHECK(norms(C, b, S.nrm2));
     VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
@@ -761,158 +807,245 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     VIE_CHECK(norms(C, r, S.nrm2));
     VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
     for (int q = 0; q < R; ++q) beta[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
-    vie_status result = VIE_OK;
-    for (;;) {
-        int nact = 0;
-        for (int q = 0; q < R; ++q) {
-            if (!std::isfinite(beta[q])) {
-                vie_set_error("non-finite residual for right-hand side " + std::to_string(q));
+
+    // the true residual decides: converged, out of iterations, or another cycle
+    auto judge = [&](int q) -> vie_status {
+        if (!std::isfinite(beta[q])) {
+            vie_set_error("non-finite residual for right-hand side " + std::to_string(q));
+            return VIE_ENONFINITE;
+        }
+        const double rel = nb[q] > 0 ? beta[q] / nb[q] : 0.0;
+        stats[q].relres = rel;
+        if (nb[q] == 0.0 || rel <= o->tol) {
+            done[q] = 1;
+        } else if (stats[q].iters >= o->maxit) {
+            done[q] = 1;
+            stats[q].status = VIE_NOT_CONVERGED;
+            result = VIE_NOT_CONVERGED;
+        }
+        return VIE_OK;
+    };
+    // hand out ended columns, take new right-hand sides into their slots (they join `starting`)
+    auto run_hook = [&](std::vector<int> *starting) -> vie_status {
+        std::vector<int> ended, refill;
+        for (int q = 0; q < R; ++q)
+            if (done[q] && !told[q]) {
+                told[q] = 1;
+                ended.push_back(q);
+            }
+        VIE_CHECK(hook->boundary(ended, stats, x, const_cast<c128 *>(b), s, &refill));
+        if (refill.empty()) return VIE_OK;
+        for (int q : refill) {
+            VIE_HIP(hipMemsetAsync(x + (long long)q * n, 0, sizeof(c128) * n, s));
+            VIE_HIP(hipMemcpyAsync(r + (long long)q * n, b + (long long)q * n, sizeof(c128) * n,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        VIE_CHECK(norms(C, b, S.nrm2));
+        VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
+        for (int q : refill) {
+            nb[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+            if (!std::isfinite(nb[q])) {
+                vie_set_error("non-finite right-hand side in slot " + std::to_string(q));
                 return VIE_ENONFINITE;
             }
-            double rel = nb[q] > 0 ? beta[q] / nb[q] : 0.0;
-            stats[q].relres = rel;
-            if (!done[q] && (nb[q] == 0.0 || rel <= o->tol)) done[q] = 1;
-            if (!done[q] && stats[q].iters >= o->maxit) {
+            beta[q] = nb[q];
+            stats[q] = vie_solve_stats{0, 0, nb[q] > 0 ? 1.0 : 0.0, VIE_OK};
+            done[q] = told[q] = 0;
+            if (nb[q] == 0.0)
                 done[q] = 1;
-                stats[q].status = VIE_NOT_CONVERGED;
-                result = VIE_NOT_CONVERGED;
-            }
-            act[q] = !done[q];
-            jr[q] = 0;
-            nact += act[q];
+            else
+                starting->push_back(q);
         }
-        if (hook) {  // hand out ended columns, take new right-hand sides into their slots
-            std::vector<int> ended, refill;
-            for (int q = 0; q < R; ++q)
-                if (done[q] && !told[q]) {
-                    told[q] = 1;
-                    ended.push_back(q);
-                }
-            VIE_CHECK(hook->boundary(ended, stats, x, const_cast<c128 *>(b), s, &refill));
-            if (!refill.empty()) {
-                for (int q : refill) {
-                    VIE_HIP(hipMemsetAsync(x + (long long)q * n, 0, sizeof(c128) * n, s));
-                    VIE_HIP(hipMemcpyAsync(r + (long long)q * n, b + (long long)q * n, sizeof(c128) * n,
-                                           hipMemcpyDeviceToDevice, s));
-                }
-                VIE_CHECK(norms(C, b, S.nrm2));
-                VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
-                for (int q : refill) {
-                    nb[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
-                    if (!std::isfinite(nb[q])) {
-                        vie_set_error("non-finite right-hand side in slot " + std::to_string(q));
-                        return VIE_ENONFINITE;
-                    }
-                    beta[q] = nb[q];
-                    stats[q] = vie_solve_stats{0, 0, nb[q] > 0 ? 1.0 : 0.0, VIE_OK};
-                    done[q] = told[q] = 0;
-                    act[q] = 1;
-                    ++nact;
-                }
-            }
-        }
-        if (nact == 0) break;
-        // u_0 = r / beta (zero for finished right-hand sides); g is set by the first step
+        return VIE_OK;
+    };
+    long long t = 0;  // global step: the ring slot of the step's input is t mod (m + 1)
+    bool dirty = true;  // active / s0 changed since the last upload
+    // u_0 = r / beta of each starting column into the slot of step t
+    auto start_cycles = [&](const std::vector<int> &cols) -> vie_status {
+        if (cols.empty()) return VIE_OK;
+        const int slot = (int)(t % m1);
         for (int q = 0; q < R; ++q) {
+            hmask[q] = 0;
             host[q] = beta[q];
-            hact[q] = act[q];
+        }
+        for (int q : cols) {
+            hmask[q] = 1;
+            act[q] = 1;
+            jr[q] = 0;
+            t0[q] = (int)(t % ((long long)m * m1));  // s0 = t0 mod (m + 1), z0 = t0 mod m
+            pend[q] = 0;
         }
         VIE_HIP(hipMemcpyAsync(S.beta, host, sizeof(double) * R, hipMemcpyHostToDevice, s));
-        VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        VIE_HIP(hipMemcpyAsync(mask_dev, hmask, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
         if (v32)
-            hipLaunchKernelGGL(k_store<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(),
-                               mixed_pc ? vlo.as<c64>() : (c64 *)nullptr, n, (const double *)S.beta,
-                               (const int *)S.active);
+            hipLaunchKernelGGL(k_store<c64>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c64>(), ldj, slot, vl, n,
+                               (const double *)S.beta, (const int *)mask_dev);
         else
-            hipLaunchKernelGGL(k_store<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(),
-                               mixed_pc ? vlo.as<c64>() : (c64 *)nullptr, n, (const double *)S.beta,
-                               (const int *)S.active);
+            hipLaunchKernelGGL(k_store<c128>, grid_e, dim3(256), 0, s, (const c128 *)r, Vb.as<c128>(), ldj, slot, vl, n,
+                               (const double *)S.beta, (const int *)mask_dev);
         VIE_HIP(hipGetLastError());
-        int j = 0;
-        while (j < m && nact > 0) {
-            void *vj = (char *)Vb.p + vsz * Rn * j;
-            void *zj = (char *)Zb.p + zsz * Rn * j;
-            if (!lowpc) {
-                if (pc)
-                    VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
-                else
-                    VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
-                VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
-            } else {
-                const void *vin = mixed_pc ? vlo.p : vj;
-                if (pc)
-                    VIE_CHECK(pc_apply(pc, vin, zj, R, VIE_C64, s));
-                else
-                    VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
-                if (mixed) {
-                    VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
-                    hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
-                    VIE_HIP(hipGetLastError());
-                } else {
-                    hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, (const c64 *)zj, zw.as<c128>(), Rn);
-                    VIE_HIP(hipGetLastError());
-                    VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s));
-                }
-            }
-            c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
-            if (v32)
-                VIE_CHECK(arnoldi_step<c64>(C, Vb.as<c64>(), ldj, j, w, S, vl));
-            else
-                VIE_CHECK(arnoldi_step<c128>(C, Vb.as<c128>(), ldj, j, w, S, vl));
-            VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
-            ++j;
-            bool changed = false;
-            for (int q = 0; q < R; ++q) {
-                if (!act[q]) continue;
-                double est = host[4 * q] / nb[q];
-                if (!std::isfinite(est)) {
-                    vie_set_error("non-finite Arnoldi step for right-hand side " + std::to_string(q));
-                    return VIE_ENONFINITE;
-                }
-                ++stats[q].iters;
-                jr[q] = j;
-                if (est <= o->tol || host[4 * q + 2] != 0.0 || stats[q].iters >= o->maxit) {
-                    act[q] = 0;
-                    --nact;
-                    changed = true;
-                }
-            }
-            if (changed && nact > 0 && j < m) {
-                for (int q = 0; q < R; ++q) hact[q] = act[q];
-                VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
-            }
-        }
-        // last columns completed, then x += Z y
+        // the pinned arrays are reused only after the next read-back has synchronised the stream
+        VIE_HIP(hipStreamSynchronize(s));
+        dirty = true;
+        return VIE_OK;
+    };
+    // end the cycles of `cols`: last columns completed, x += Z y, the FP64 true residual, judged
+    auto end_cycles = [&](const std::vector<int> &cols, std::vector<int> *restart) -> vie_status {
         int max_jr = 0;
         for (int q = 0; q < R; ++q) {
-            hjr[q] = jr[q];
+            hjend[q] = 0;
+            hz0[q] = t0[q] % m;
+        }
+        for (int q : cols) {
+            hjend[q] = jr[q];
             max_jr = std::max(max_jr, jr[q]);
         }
-        VIE_HIP(hipMemcpyAsync(jr_dev, hjr, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        VIE_HIP(hipMemcpyAsync(jend_dev, hjend, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        VIE_HIP(hipMemcpyAsync(z0_dev, hz0, sizeof(int) * R, hipMemcpyHostToDevice, s));
         if (max_jr > 0) {
             if (v32)
-                VIE_CHECK(arnoldi_finish<c64>(C, Vb.as<const c64>(), ldj, jr_dev, max_jr, S));
+                VIE_CHECK(arnoldi_finish<c64>(C, Vb.as<const c64>(), ldj, m1, jend_dev, s0_dev, max_jr, S));
             else
-                VIE_CHECK(arnoldi_finish<c128>(C, Vb.as<const c128>(), ldj, jr_dev, max_jr, S));
+                VIE_CHECK(arnoldi_finish<c128>(C, Vb.as<const c128>(), ldj, m1, jend_dev, s0_dev, max_jr, S));
+            hipLaunchKernelGGL(k_lsq, dim3((R + 63) / 64), dim3(64), 0, s, S, (const int *)jend_dev, R);
+            VIE_HIP(hipGetLastError());
+            if (lowpc)
+                hipLaunchKernelGGL(k_combine<float>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c64>(), ldj, m,
+                                   (const int *)jend_dev, (const int *)z0_dev, (const c128 *)S.y, m, x, n);
+            else
+                hipLaunchKernelGGL(k_combine<double>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c128>(), ldj, m,
+                                   (const int *)jend_dev, (const int *)z0_dev, (const c128 *)S.y, m, x, n);
+            VIE_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_lsq, dim3((R + 63) / 64), dim3(64), 0, s, S, (const int *)jr_dev, R);
-        VIE_HIP(hipGetLastError());
-        if (lowpc)
-            hipLaunchKernelGGL(k_combine<float>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c64>(), ldj,
-                               (const int *)jr_dev, (const c128 *)S.y, m, x, n);
-        else
-            hipLaunchKernelGGL(k_combine<double>, grid_e, dim3(KR_THREADS), 0, s, Zb.as<const c128>(), ldj,
-                               (const int *)jr_dev, (const c128 *)S.y, m, x, n);
-        VIE_HIP(hipGetLastError());
-        for (int q = 0; q < R; ++q)
+        for (int q : cols) {
             if (jr[q] > 0) ++stats[q].restarts;
-        // FP64 true residual
-        VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
-        hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
-        VIE_HIP(hipGetLastError());
+            act[q] = 0;
+            pend[q] = 0;
+        }
+        dirty = true;
+        // FP64 true residual r = b - A x of the ended columns (the whole batch when they are at
+        // least half of it: the other columns' r is not needed before their own cycles end)
+        if (2 * cols.size() >= (size_t)R) {
+            VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
+            hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
+            VIE_HIP(hipGetLastError());
+        } else {
+            for (int q : cols) {
+                VIE_CHECK(launch_matvec(op, x + (long long)q * n, r + (long long)q * n, 1, VIE_C128, s));
+                hipLaunchKernelGGL(k_residual, dim3(256), dim3(256), 0, s, b + (long long)q * n, r + (long long)q * n,
+                                   n);
+                VIE_HIP(hipGetLastError());
+            }
+        }
         VIE_CHECK(norms(C, r, S.nrm2));
         VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
-        for (int q = 0; q < R; ++q) beta[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+        for (int q : cols) beta[q] = sqrt(reinterpret_cast<c128 *>(host)[q].re);
+        for (int q : cols) {
+            VIE_CHECK(judge(q));
+            if (!done[q]) restart->push_back(q);
+        }
+        return VIE_OK;
+    };
+
+    std::vector<int> starting;
+    for (int q = 0; q < R; ++q) {
+        VIE_CHECK(judge(q));
+        if (!done[q]) starting.push_back(q);
+    }
+    if (hook) VIE_CHECK(run_hook(&starting));
+    VIE_CHECK(start_cycles(starting));
+    for (;;) {
+        int max_j = 0, nact = 0;
+        for (int q = 0; q < R; ++q)
+            if (act[q]) {
+                ++nact;
+                max_j = std::max(max_j, jr[q]);
+            }
+        if (nact == 0) break;
+        for (int q = 0; q < R; ++q) hjcol[q] = jr[q];
+        VIE_HIP(hipMemcpyAsync(jcol_dev, hjcol, sizeof(int) * R, hipMemcpyHostToDevice, s));
+        if (dirty) {
+            for (int q = 0; q < R; ++q) {
+                hact[q] = act[q];
+                hs0[q] = t0[q] % m1;
+            }
+            VIE_HIP(hipMemcpyAsync(S.active, hact, sizeof(int) * R, hipMemcpyHostToDevice, s));
+            VIE_HIP(hipMemcpyAsync(s0_dev, hs0, sizeof(int) * R, hipMemcpyHostToDevice, s));
+            dirty = false;
+        }
+        void *vj = (char *)Vb.p + vsz * Rn * (t % m1);
+        void *zj = (char *)Zb.p + zsz * Rn * (t % m);
+        if (!lowpc) {
+            if (pc)
+                VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
+            else
+                VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
+            VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
+        } else {
+            const void *vin = mixed_pc ? vlo.p : vj;
+            if (pc)
+                VIE_CHECK(pc_apply(pc, vin, zj, R, VIE_C64, s));
+            else
+                VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
+            if (mixed) {
+                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
+                hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
+                VIE_HIP(hipGetLastError());
+            } else {
+                hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, (const c64 *)zj, zw.as<c128>(), Rn);
+                VIE_HIP(hipGetLastError());
+                VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s));
+            }
+        }
+        c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
+        const int next_slot = (int)((t + 1) % m1);
+        if (v32)
+            VIE_CHECK(arnoldi_step<c64>(C, Vb.as<c64>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot, w, S, vl));
+        else
+            VIE_CHECK(arnoldi_step<c128>(C, Vb.as<c128>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot, w, S, vl));
+        VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
+        ++t;
+        std::vector<int> ending;
+        bool full = false;
+        for (int q = 0; q < R; ++q) {
+            if (!act[q]) continue;
+            const double est = host[4 * q] / nb[q];
+            if (!std::isfinite(est)) {
+                vie_set_error("non-finite Arnoldi step for right-hand side " + std::to_string(q));
+                return VIE_ENONFINITE;
+            }
+            ++stats[q].iters;
+            ++jr[q];
+            const bool stop = est <= o->tol || host[4 * q + 2] != 0.0 || stats[q].iters >= o->maxit;
+            if (jr[q] == m) {
+                ending.push_back(q);
+                full = true;
+            } else if (stop) {
+                if (immediate) {
+                    ending.push_back(q);
+                } else {  // waits for the batch's common cycle end
+                    pend[q] = 1;
+                    act[q] = 0;
+                    dirty = true;
+                }
+            }
+        }
+        if (!immediate) {
+            int going = 0;
+            for (int q = 0; q < R; ++q) going += act[q] && jr[q] < m;
+            if (full || going == 0)
+                for (int q = 0; q < R; ++q)
+                    if (pend[q]) ending.push_back(q);
+        }
+        starting.clear();
+        if (!ending.empty()) VIE_CHECK(end_cycles(ending, &starting));
+        if (hook) {
+            bool call = !ending.empty();
+            for (int q = 0; q < R && !call; ++q) call = done[q] != 0;  // a free slot may take a joiner
+            if (call) VIE_CHECK(run_hook(&starting));
+        }
+        VIE_CHECK(start_cycles(starting));
     }
     return result;
 }

@@ -374,11 +374,12 @@ vie_status launch_block_solve(vie_pc pc, PcWs *w, void *work, int nrhs, hipStrea
 // krylov.hip
 // complex partial sums per right-hand side kept by the Arnoldi reductions (vector length n)
 long long arnoldi_partials(long long n, int restart);
-// Called by the batched GMRES at every restart-cycle boundary, before the next cycle: `ended`
-// lists the columns (slots) whose solve ended since the previous call; their stats are final
-// and so is their column of x once the work queued on s is done.  The hook may put a new
-// right-hand side into ended slots (writing b on s) and returns those slots in `refill`: the
-// solver restarts them from x = 0 with fresh statistics.
+// Called by the batched GMRES before the first step and then after every step at which a
+// column ended a restart cycle or a slot is free (columns run their own cycles when a hook is
+// given): `ended` lists the columns (slots) whose solve ended since the previous call; their
+// stats are final and so is their column of x once the work queued on s is done.  The hook may
+// put a new right-hand side into free slots (writing b on s) and returns those slots in
+// `refill`: the solver starts them from x = 0 with fresh statistics at the next step.
 struct SolveHook {
     virtual ~SolveHook() = default;
     virtual vie_status boundary(const std::vector<int> &ended, const vie_solve_stats *stats, const c128 *x,
