@@ -249,6 +249,56 @@ def test_continuous_batching_completes_early_and_takes_joiners(gpu_lib):
     assert info['solves'] == 2  # the busy solve and the (a, b) solve, which c joined
 
 
+def test_request_joins_a_running_cycle_at_the_next_step(gpu_lib):
+    """Joins at Arnoldi-step granularity: a zero-field request merged with b frees its slot at
+    once; with one long restart cycle (GMRES(200), unpreconditioned to 1e-10) a request
+    submitted while b is being solved takes that slot after the next step, not at b's cycle
+    end, so its wait is a small part of b's run.  Both results equal the plain library solve
+    (same iterations) and pass the oracle's residual check."""
+    import time
+    import torch
+    devs = _devices()
+    busy = devs['block']
+    dev = dict(devs['guide'])
+    dev['grid'] = (128, 8, 4)
+    dev['chi'] = W.waveguide((128, 8, 4))
+    dev['precond'] = False
+    kw = dict(tol=1e-10, restart=200)
+    srv = gpu_lib.Server(workers=1, max_batch_rhs=64)
+    r_busy = srv.submit(e_inc=_e(busy, 1, 3), tol=1e-10, **busy)
+    e_b, e_c = _e(dev, 1, 81), _e(dev, 1, 82)
+    r_a = srv.submit(e_inc=np.zeros_like(e_b), **kw, **dev)  # merged with b behind the busy solve
+    r_b = srv.submit(e_inc=e_b, **kw, **dev)
+    t0 = time.time()
+    while True:  # until the (a, b) solve is admitted
+        info = srv.info()
+        if info['queued'] == 0 and info['running'] == 1 and srv.done(r_busy):
+            break
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    time.sleep(0.01)  # b is stepping
+    r_c = srv.submit(e_inc=e_c, **kw, **dev)
+    srv.wait(r_a)
+    xc, sc, tc = srv.wait(r_c)
+    xb, sb, tb = srv.wait(r_b)
+    srv.wait(r_busy)
+    srv.close()
+    print('b: %s (iters %d); c: %s (iters %d)' % (tb, sb[0]['iters'], tc, sc[0]['iters']))
+    assert tc['joined'] == 1
+    assert tc['queue_ms'] < 0.5 * tb['run_ms']
+    op = gpu_lib.Operator(dev['grid'], dev['voxel_size'], dev['k_background'], dev['chi'])
+    for x, st, e in ((xb, sb, e_b), (xc, sc, e_c)):
+        ed = torch.from_numpy(e).cuda()
+        b = torch.empty_like(ed)
+        op.rhs(ed, b, nrhs=1)
+        xd = torch.zeros_like(b)
+        ref = gpu_lib.solve(op, None, b, xd, **kw)
+        assert st[0]['status'] == 0 and st[0]['iters'] == ref[0]['iters']
+        assert _rel(x, xd.cpu().numpy()) <= 1e-12
+        assert _oracle_relres(dev, x, e)[0] <= 1e-10 * 1.01
+    op.close()
+
+
 def test_concurrent_solves_share_one_cached_entry(gpu_lib):
     """Requests of one device with different solver settings (so they are neither merged nor
     joined) run at the same time on several workers: they share one cached operator and
