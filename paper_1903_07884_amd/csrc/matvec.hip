@@ -557,55 +557,74 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
 // from the x-spectra), multiplies by W_PY^{n2 k1} and leaves [k1][n2] in LDS; step 2 transforms
 // over n2 into natural order.  The z coupling reads every (component, layer) of a y-frequency from
 // LDS; the inverse runs the two steps in reverse and stores the cropped rows.
-template <class R, int PY, int P1, int P2, int NZ>
-__global__ void __launch_bounds__(64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64))
+// PL planes (consecutive right-hand sides of the group) run side by side, each on its own
+// threads and LDS plane, sharing the staged generator: with PL = 2 a workgroup holds 2 x 4.5
+// wavefronts of items, which the four SIMDs share more evenly than one plane's 4.5.
+template <class R, int PY, int P1, int P2, int NZ, int PL>
+__global__ void __launch_bounds__(PL * 64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64))
 k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cpx<R> *__restrict__ twtab, int ny,
-            int Px, int Hy, int nrhs, int rb, int xsplit) {
+            int Px, int nrhs, int rb, int xsplit) {
     static_assert(P1 * P2 == PY, "PY = P1 P2");
+    constexpr int Hy = PY / 2 + 1;            // stored y-frequencies 0 .. PY/2 (octant)
     constexpr int L = 3 * NZ;                 // lines: (component, layer)
-    constexpr int NT = 64 * ((L * (P1 > P2 ? P1 : P2) + 63) / 64);
+    constexpr int NTP = 64 * ((L * (P1 > P2 ? P1 : P2) + 63) / 64);  // threads per plane
+    constexpr int NT = PL * NTP;
     // line stride: room for the padded exchange layouts [k1][P2 + 1] and [n2][P1 + 1] (odd strides,
     // so the transposed reads spread over the LDS banks) as well as the natural order [PY]
     constexpr int SP = PY + (P1 > P2 ? P1 : P2);
-    cpx<R> *S = reinterpret_cast<cpx<R> *>(vie_smem);  // [L][SP] plane
-    cpx<R> *G = S + L * SP;                             // [NZ][6][Hy] transformed generator
-    cpx<R> *W = G + NZ * 6 * Hy;                        // [PY] twiddles W_PY^q
+    const int h = PL > 1 ? (int)threadIdx.x / NTP : 0;                // plane of this thread
+    const int t = (int)threadIdx.x - h * NTP;                        // thread within the plane
+    cpx<R> *S = reinterpret_cast<cpx<R> *>(vie_smem) + h * L * SP;    // [L][SP] plane h
+    cpx<R> *G = reinterpret_cast<cpx<R> *>(vie_smem) + PL * L * SP;   // [NZ][6][Hy] transformed generator
+    cpx<R> *W = G + NZ * 6 * Hy;                                     // [PY] twiddles W_PY^q
     const int kx = xcd_block(blockIdx.x, Px);
     if (kx >= Px) return;
     const int kxo = kx <= Px - kx ? kx : Px - kx;
     const R sx = kx > Px - kx ? R(-1) : R(1);
-    const int t = threadIdx.x;
     {
         const cpx<R> *kh = khat + (long long)kxo * Hy * NZ * 6;
-        for (int i = t; i < Hy * NZ * 6; i += NT) {
+        for (int i = threadIdx.x; i < Hy * NZ * 6; i += NT) {
             const int kyo = i / (6 * NZ), e = i - kyo * 6 * NZ;  // source layout [Hy][NZ][6]
             G[e * Hy + kyo] = kh[i];                              // e = dz * 6 + c
         }
-        for (int i = t; i < PY; i += NT) W[i] = twtab[i];
+        for (int i = threadIdx.x; i < PY; i += NT) W[i] = twtab[i];
     }
     const int r0 = blockIdx.y * rb, r1 = min(nrhs, r0 + rb);
     const long long xo = xpos(kx, Px, xsplit), rstride = (long long)L * ny * Px;
     // the zero-padded column of item (line, n2) of the forward step 1; the next plane's column
     // is loaded while the current plane is processed (every barrier below orders LDS only)
     // ny <= (PY + 1) / 2, so only the first NNZ entries of a column (y = n2 + P2 n1) can be
-    // nonzero: the others are compile-time zeros in the step-1 DFT
+    // nonzero: the others are compile-time zeros in the step-1 DFT.  Offsets within a plane's
+    // slab are 32-bit (the host keeps the slab below 2^31 entries) from a uniform base.
     constexpr int NNZ = ((PY + 1) / 2 + P2 - 1) / P2;
     const int line1 = t / P2, n21 = t - line1 * P2;
+    const unsigned ystep = (unsigned)(P2 * Px);
+    const unsigned off1 = (unsigned)((line1 * ny + n21) * Px);
     cpx<R> vn[NNZ];
+    rfft::sfor<NNZ>([&](auto ic) { vn[decltype(ic)::value] = czero<R>(); });
     auto load_col = [&](int rhs) {
         const cpx<R> *src = work + rhs * rstride + xo;
         rfft::sfor<NNZ>([&](auto ic) {
             constexpr int n1 = decltype(ic)::value;
             const int y = n21 + P2 * n1;
-            vn[n1] = (t < L * P2 && y < ny) ? src[((long long)line1 * ny + y) * Px] : czero<R>();
+            vn[n1] = (t < L * P2 && y < ny) ? src[off1 + n1 * ystep] : czero<R>();
         });
     };
-    if (r0 < r1) load_col(r0);
-    for (int rhs = r0; rhs < r1; ++rhs) {
-        cpx<R> *base = work + rhs * rstride + xo;
+    if (r0 + h < r1) load_col(r0 + h);
+    // every thread runs the same iterations (barriers); a plane past the group's end computes on
+    // whatever its registers hold and stores nothing
+    for (int rr = r0; rr < r1; rr += PL) {
+        // the thread index passes through an empty asm statement once per plane, so the indices
+        // and LDS addresses derived from it are recomputed in each phase instead of being kept
+        // live across the whole loop (fewer registers held)
+        int tq = t;
+        asm volatile("" : "+v"(tq));
+        const int rhs = rr + h;
+        const bool live = rhs < r1;
+        cpx<R> *base = work + (live ? rhs : r0) * rstride + xo;
         rfft::lds_barrier();  // G, W staged; the previous plane's last reads of S are done
         // forward step 1: item (line, n2) transforms its zero-padded column over n1
-        if (t < L * P2) {
+        if (tq < L * P2) {
             const int line = line1, n2 = n21;
             cpx<R> v[P1];
             rfft::sfor<P1>([&](auto ic) {
@@ -613,7 +632,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                 if constexpr (n1 < NNZ) v[n1] = vn[n1];
                 else v[n1] = czero<R>();
             });
-            if (rhs + 1 < r1) load_col(rhs + 1);
+            if (rhs + PL < r1) load_col(rhs + PL);
             rfft::Dft<R, P1, false>::run(v);
             rfft::sfor<P1>([&](auto ic) {
                 constexpr int k1 = decltype(ic)::value;
@@ -624,8 +643,8 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         // forward step 2: item (line, k1) transforms over n2 -> ky = k1 + P1 k2
         {
             cpx<R> u[P2];
-            const int line = t / P1, k1 = t - line * P1;
-            const bool act = t < L * P1;
+            const int line = tq / P1, k1 = tq - line * P1;
+            const bool act = tq < L * P1;
             if (act)
                 rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 * (P2 + 1) + decltype(ic)::value]; });
             rfft::lds_barrier();
@@ -640,9 +659,9 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         // parity signs (xy odd in x and y, xz in x and z, yz in y and z).  The source components are
         // taken one at a time (NZ spectra in registers); every item reads before any writes back.
         {
-            static_assert(3 * PY <= NT, "one coupling item per thread");
-            const bool act = t < 3 * PY;
-            const int c = t / PY, ky = t - c * PY;
+            static_assert(3 * PY <= NTP, "one coupling item per thread");
+            const bool act = tq < 3 * PY;
+            const int c = tq / PY, ky = tq - c * PY;
             cpx<R> acc[NZ];
             rfft::sfor<NZ>([&](auto iz) { acc[decltype(iz)::value] = czero<R>(); });
             if (act) {
@@ -663,7 +682,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                         const cpx<R> g = ((zodd && dz < 0) ? -pxy : pxy) * ge[adz * 6 * Hy];
                         rfft::sfor<NZ>([&](auto iz) {
                             constexpr int z = decltype(iz)::value, zp = z - dz;
-                            if constexpr (zp >= 0 && zp < NZ) acc[z] = acc[z] + g * uc[zp];
+                            if constexpr (zp >= 0 && zp < NZ) acc[z] = cfma(acc[z], g, uc[zp]);
                         });
                     });
                 }
@@ -675,8 +694,8 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         // inverse step A: item (line, k1) transforms over k2, multiplies by conj W_PY^{n2 k1}
         {
             cpx<R> u[P2];
-            const int line = t / P1, k1 = t - line * P1;
-            const bool act = t < L * P1;
+            const int line = tq / P1, k1 = tq - line * P1;
+            const bool act = tq < L * P1;
             if (act) rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 + P1 * decltype(ic)::value]; });
             rfft::lds_barrier();
             if (act) {
@@ -689,15 +708,16 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         }
         rfft::lds_barrier();
         // inverse step B: item (line, n2) transforms over k1 -> y = n2 + P2 n1; cropped store
-        if (t < L * P2) {
-            const int line = t / P2, n2 = t - line * P2;
+        if (tq < L * P2) {
+            const int line = tq / P2, n2 = tq - line * P2;
             cpx<R> v[P1];
             rfft::sfor<P1>([&](auto ic) { v[decltype(ic)::value] = S[line * SP + n2 * (P1 + 1) + decltype(ic)::value]; });
             rfft::Dft<R, P1, true>::run(v);
+            const unsigned off = (unsigned)((line * ny + n2) * Px);
             rfft::sfor<P1>([&](auto ic) {
                 constexpr int n1 = decltype(ic)::value;
                 const int y = n2 + P2 * n1;
-                if (y < ny) base[((long long)line * ny + y) * Px] = v[n1];
+                if (live && y < ny) base[off + n1 * ystep] = v[n1];
             });
         }
     }
@@ -834,22 +854,38 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
     (void)lines_per_comp_rhs_N;
 }
 
+// One launch of the register-FFT plane pass: rb right-hand sides per workgroup, PL planes at a time.
+template <class R, int PY, int P1, int P2, int NZ, int PL>
+static void plane_reg_launch_pl(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
+    constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
+    constexpr int NT = PL * 64 * ((L * PM + 63) / 64), SP = PY + PM;
+    const size_t lds = sizeof(cpx<R>) * ((size_t)PL * L * SP + (size_t)NZ * 6 * op->Hy + PY);
+    const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
+    vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ, PL>, lds);
+    hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ, PL>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s, work,
+                       khat, TwTable<R>::get(op->py), op->ny, op->Px, nrhs, rb, op->xsplit);
+}
+
 // The register-FFT plane pass for the (y period, layer count) pairs it is instantiated for;
 // false for any other shape (the generic LDS plane pass runs then).  Right-hand sides are grouped
 // so that about 8192 workgroups remain (c.f. 256 CUs), each group sharing one staging of the
-// x-frequency's transformed generator.
+// x-frequency's transformed generator; groups of two or more run two planes side by side (single
+// precision, or double where the pair's wavefronts fit the register file without spilling).
 template <class R, int PY, int P1, int P2, int NZ>
 static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb_req, hipStream_t s) {
-    constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
-    constexpr int NT = 64 * ((L * PM + 63) / 64), SP = PY + PM;
-    const size_t lds = sizeof(cpx<R>) * ((size_t)L * SP + (size_t)NZ * 6 * op->Hy + PY);
     const long long planes = (long long)op->Px * nrhs;
     const int rb = rb_req > 0 ? std::min(rb_req, nrhs)
                               : (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
-    const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
-    vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ>, lds);
-    hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s, work, khat,
-                       TwTable<R>::get(op->py), op->ny, op->Px, op->Hy, nrhs, rb, op->xsplit);
+    // two planes side by side where their wavefronts still fit the register file without spills
+    constexpr int NTP = 64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64);
+    constexpr bool kPair = sizeof(R) == 4 || 2 * NTP <= 512;
+    if constexpr (kPair) {
+        if (rb >= 2) {
+            plane_reg_launch_pl<R, PY, P1, P2, NZ, 2>(op, work, khat, nrhs, rb, s);
+            return;
+        }
+    }
+    plane_reg_launch_pl<R, PY, P1, P2, NZ, 1>(op, work, khat, nrhs, rb, s);
 }
 
 // rb > 0: right-hand sides per workgroup (autotuned), 0: the default grouping.  work = nullptr
@@ -858,6 +894,7 @@ template <class R>
 static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
     const int Py = op->Py, nz = op->nz;
     if (!op->direct_z || op->split_plane) return false;
+    if ((long long)3 * nz * op->ny * op->Px >= (1LL << 31)) return false;  // 32-bit offsets in a slab
 #define VIE_PLANE_REG(PY, P1, P2, NZ)                                              \
     if (Py == PY && nz == NZ) {                                                    \
         if (work) plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, rb, s); \

@@ -47,6 +47,14 @@ __host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
 }
 template <class R>
 __host__ __device__ __forceinline__ R abs2(cpx<R> a) { return a.re * a.re + a.im * a.im; }
+// a + b*c as four fused multiply-adds (the sum of a product into an accumulator without the
+// separate rounding of the product)
+__host__ __device__ __forceinline__ float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double rfma(double a, double b, double c) { return fma(a, b, c); }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cfma(cpx<R> a, cpx<R> b, cpx<R> c) {
+    return mk<R>(rfma(-b.im, c.im, rfma(b.re, c.re, a.re)), rfma(b.im, c.re, rfma(b.re, c.im, a.im)));
+}
 // a - b*c
 template <class R>
 __host__ __device__ __forceinline__ cpx<R> cfms(cpx<R> a, cpx<R> b, cpx<R> c) {

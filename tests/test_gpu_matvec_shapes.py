@@ -58,6 +58,38 @@ def test_register_plane_pass_matches_explicit_sum(gpu_lib, grid):
     assert e64 < 1e-10 and e32 < 1e-5
 
 
+@pytest.mark.parametrize("grid", [(6, 48, 8), (5, 32, 8), (7, 24, 8), (12, 16, 4)])
+def test_register_plane_pass_in_pairs_matches_explicit_sum(gpu_lib, grid):
+    """Three right-hand sides forced two to a workgroup (the plane pass then runs two planes side
+    by side where the pair fits the register file): a full pair and a lone last plane."""
+    delta = 25e-9
+    K = OG.generator_octant(grid, KB * delta)
+    rng = np.random.default_rng(sum(grid) + 1)
+    nx, ny, nz = grid
+    chi = 3.0 + rng.standard_normal((nz, ny, nx)) + 0.2j * rng.standard_normal((nz, ny, nx))
+    M = OCT.contrast_from_chi(chi)
+    x = W.random_field((3, 3 * nx * ny * nz), 35)
+    ref = OM.matvec(K, M, grid, x)
+    keys = []
+    try:
+        gpu_lib.autotune(True)
+        op = gpu_lib.Operator(grid, delta, KB, chi, generator=K, build_c64=True)
+        _products(gpu_lib, op, x, 3)  # tunes both precisions
+        keys = [k for k in gpu_lib.autotune_entries() if k.startswith('matvec ') and 'grid=%dx%dx%d nrhs=3 ' % grid in k]
+        assert len(keys) == 2, gpu_lib.autotune_entries()
+        for key in keys:
+            gpu_lib.autotune_set(key, [2, 0])
+        y64, y32 = _products(gpu_lib, op, x, 3)
+        op.close()
+    finally:
+        for key in keys:
+            gpu_lib.autotune_set(key, [])
+        gpu_lib.autotune(False)
+    e64, e32 = _entrywise(y64, ref), _entrywise(y32, ref)
+    print('plane pass in pairs', grid, 'fp64 %.2e c64 %.2e (entry-wise)' % (e64, e32))
+    assert e64 < 1e-10 and e32 < 1e-5
+
+
 def test_register_plane_pass_grouped_rhs_against_fft_reference(gpu_lib):
     """1024x48x8 (the coupler grid) with 13 right-hand sides: several per plane-pass workgroup
     and a ragged last group; a seeded synthetic generator is injected so the oracle holds the
