@@ -560,15 +560,30 @@ __global__ void k_plane_dz(cpx<R> *work, const cpx<R> *khat, int ny, int nz, int
 // PL planes (consecutive right-hand sides of the group) run side by side, each on its own
 // threads and LDS plane, sharing the staged generator: with PL = 2 a workgroup holds 2 x 4.5
 // wavefronts of items, which the four SIMDs share more evenly than one plane's 4.5.
-template <class R, int PY, int P1, int P2, int NZ, int PL>
-__global__ void __launch_bounds__(PL * 64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64))
+// TAIL: a plane takes four wavefronts (256 threads) although the 96-point phases have 288 items
+// (24 lines x 12, or 3 components x 96 y-frequencies): the last 32 items of such a phase are
+// split by output over all 256 threads (one DFT output, or one layer of the z sum, each), so the
+// four SIMDs get equal work and two workgroups fit a compute unit.
+template <int PY, int P1, int P2, int NZ, bool TAIL>
+struct PlaneThreads {
+    static constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
+    static constexpr int value = TAIL ? 256 : 64 * ((L * PM + 63) / 64);
+};
+template <class R, int PY, int P1, int P2, int NZ, int PL, bool TAIL>
+__global__ void __launch_bounds__((PL * PlaneThreads<PY, P1, P2, NZ, TAIL>::value))
 k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cpx<R> *__restrict__ twtab, int ny,
             int Px, int nrhs, int rb, int xsplit) {
     static_assert(P1 * P2 == PY, "PY = P1 P2");
     constexpr int Hy = PY / 2 + 1;            // stored y-frequencies 0 .. PY/2 (octant)
     constexpr int L = 3 * NZ;                 // lines: (component, layer)
-    constexpr int NTP = 64 * ((L * (P1 > P2 ? P1 : P2) + 63) / 64);  // threads per plane
+    constexpr int NTP = PlaneThreads<PY, P1, P2, NZ, TAIL>::value;  // threads per plane
     constexpr int NT = PL * NTP;
+    // items past NTP in the (line, k1) and (component, y-frequency) phases, split by output
+    constexpr int NTK = L * P1 > NTP ? L * P1 - NTP : 0;
+    constexpr int NTC = 3 * PY > NTP ? 3 * PY - NTP : 0;
+    static_assert(L * P2 <= NTP, "one (line, n2) item per thread");
+    static_assert(NTK * P2 <= NTP && NTC * NZ <= NTP, "tail outputs fit the threads");
+    static_assert(TAIL || (NTK == 0 && NTC == 0), "tails only in the four-wavefront form");
     // line stride: room for the padded exchange layouts [k1][P2 + 1] and [n2][P1 + 1] (odd strides,
     // so the transposed reads spread over the LDS banks) as well as the natural order [PY]
     constexpr int SP = PY + (P1 > P2 ? P1 : P2);
@@ -647,11 +662,27 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
             const bool act = tq < L * P1;
             if (act)
                 rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 * (P2 + 1) + decltype(ic)::value]; });
+            // tail item NTP + ti: thread (ti, k2) forms output k2 by the definition of the DFT
+            cpx<R> tv = czero<R>();
+            int tdst = -1;
+            if constexpr (NTK > 0) {
+                const int ti = tq / P2, k2 = tq - ti * P2;
+                if (ti < NTK) {
+                    const int it = NTP + ti, tl = it / P1, tk = it - tl * P1;
+                    const cpx<R> *col = S + tl * SP + tk * (P2 + 1);
+                    rfft::sfor<P2>([&](auto ic) {
+                        constexpr int n2 = decltype(ic)::value;
+                        tv = cfma(tv, col[n2], W[((n2 * k2) % P2) * (PY / P2)]);
+                    });
+                    tdst = tl * SP + tk + P1 * k2;
+                }
+            }
             rfft::lds_barrier();
             if (act) {
                 rfft::Dft<R, P2, false>::run(u);
                 rfft::sfor<P2>([&](auto ic) { S[line * SP + k1 + P1 * decltype(ic)::value] = u[decltype(ic)::value]; });
             }
+            if (NTK > 0 && tdst >= 0) S[tdst] = tv;
         }
         rfft::lds_barrier();
         // z coupling: item (c, ky) forms component c of its y-frequency at every layer z, the sum
@@ -659,7 +690,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         // parity signs (xy odd in x and y, xz in x and z, yz in y and z).  The source components are
         // taken one at a time (NZ spectra in registers); every item reads before any writes back.
         {
-            static_assert(3 * PY <= NTP, "one coupling item per thread");
+            static_assert(3 * PY <= NTP + NTC, "coupling items: one per thread plus the tail");
             const bool act = tq < 3 * PY;
             const int c = tq / PY, ky = tq - c * PY;
             cpx<R> acc[NZ];
@@ -687,8 +718,35 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                     });
                 }
             }
+            // tail item NTP + ti = (component tc, y-frequency tk): thread (ti, z) forms its layer z
+            cpx<R> tv = czero<R>();
+            int tdst = -1;
+            if constexpr (NTC > 0) {
+                const int ti = tq / NZ, z = tq - ti * NZ;
+                if (ti < NTC) {
+                    const int it = NTP + ti, tc = it / PY, tk = it - tc * PY;
+                    const int kyo = tk <= PY - tk ? tk : PY - tk;
+                    const R sy = tk > PY - tk ? R(-1) : R(1);
+#pragma unroll 1
+                    for (int cp = 0; cp < 3; ++cp) {
+                        const bool off = tc != cp;
+                        const int e = off ? tc + cp + 2 : tc;
+                        const R pxy = (off && (tc == 0 || cp == 0) ? sx : R(1)) * (off && (tc == 1 || cp == 1) ? sy : R(1));
+                        const bool zodd = off && (tc == 2 || cp == 2);
+                        const cpx<R> *ge = G + e * Hy + kyo;
+                        rfft::sfor<NZ>([&](auto izp) {
+                            constexpr int zp = decltype(izp)::value;
+                            const int dz = z - zp, adz = dz < 0 ? -dz : dz;
+                            const cpx<R> g = ((zodd && dz < 0) ? -pxy : pxy) * ge[adz * 6 * Hy];
+                            tv = cfma(tv, g, S[(cp * NZ + zp) * SP + tk]);
+                        });
+                    }
+                    tdst = (tc * NZ + z) * SP + tk;
+                }
+            }
             rfft::lds_barrier();
             if (act) rfft::sfor<NZ>([&](auto iz) { S[(c * NZ + decltype(iz)::value) * SP + ky] = acc[decltype(iz)::value]; });
+            if (NTC > 0 && tdst >= 0) S[tdst] = tv;
         }
         rfft::lds_barrier();
         // inverse step A: item (line, k1) transforms over k2, multiplies by conj W_PY^{n2 k1}
@@ -697,6 +755,22 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
             const int line = tq / P1, k1 = tq - line * P1;
             const bool act = tq < L * P1;
             if (act) rfft::sfor<P2>([&](auto ic) { u[decltype(ic)::value] = S[line * SP + k1 + P1 * decltype(ic)::value]; });
+            // tail item NTP + ti: thread (ti, n2) forms output n2 by the definition of the inverse DFT
+            cpx<R> tv = czero<R>();
+            int tdst = -1;
+            if constexpr (NTK > 0) {
+                const int ti = tq / P2, n2 = tq - ti * P2;
+                if (ti < NTK) {
+                    const int it = NTP + ti, tl = it / P1, tk = it - tl * P1;
+                    const cpx<R> *row = S + tl * SP + tk;
+                    rfft::sfor<P2>([&](auto ic) {
+                        constexpr int k2 = decltype(ic)::value;
+                        tv = cfma(tv, row[P1 * k2], conjg(W[((n2 * k2) % P2) * (PY / P2)]));
+                    });
+                    if (n2 > 0) tv = tv * conjg(W[n2 * tk]);
+                    tdst = tl * SP + n2 * (P1 + 1) + tk;
+                }
+            }
             rfft::lds_barrier();
             if (act) {
                 rfft::Dft<R, P2, true>::run(u);
@@ -705,6 +779,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
                     S[line * SP + n2 * (P1 + 1) + k1] = n2 == 0 ? u[n2] : u[n2] * conjg(W[n2 * k1]);
                 });
             }
+            if (NTK > 0 && tdst >= 0) S[tdst] = tv;
         }
         rfft::lds_barrier();
         // inverse step B: item (line, n2) transforms over k1 -> y = n2 + P2 n1; cropped store
@@ -855,15 +930,15 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
 }
 
 // One launch of the register-FFT plane pass: rb right-hand sides per workgroup, PL planes at a time.
-template <class R, int PY, int P1, int P2, int NZ, int PL>
+template <class R, int PY, int P1, int P2, int NZ, int PL, bool TAIL>
 static void plane_reg_launch_pl(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
     constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
-    constexpr int NT = PL * 64 * ((L * PM + 63) / 64), SP = PY + PM;
+    constexpr int NT = PL * PlaneThreads<PY, P1, P2, NZ, TAIL>::value, SP = PY + PM;
     const size_t lds = sizeof(cpx<R>) * ((size_t)PL * L * SP + (size_t)NZ * 6 * op->Hy + PY);
     const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
-    vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ, PL>, lds);
-    hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ, PL>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s, work,
-                       khat, TwTable<R>::get(op->py), op->ny, op->Px, nrhs, rb, op->xsplit);
+    vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ, PL, TAIL>, lds);
+    hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ, PL, TAIL>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s,
+                       work, khat, TwTable<R>::get(op->py), op->ny, op->Px, nrhs, rb, op->xsplit);
 }
 
 // The register-FFT plane pass for the (y period, layer count) pairs it is instantiated for;
@@ -876,16 +951,21 @@ static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nr
     const long long planes = (long long)op->Px * nrhs;
     const int rb = rb_req > 0 ? std::min(rb_req, nrhs)
                               : (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
-    // two planes side by side where their wavefronts still fit the register file without spills
-    constexpr int NTP = 64 * ((3 * NZ * (P1 > P2 ? P1 : P2) + 63) / 64);
-    constexpr bool kPair = sizeof(R) == 4 || 2 * NTP <= 512;
-    if constexpr (kPair) {
-        if (rb >= 2) {
-            plane_reg_launch_pl<R, PY, P1, P2, NZ, 2>(op, work, khat, nrhs, rb, s);
-            return;
+    // more than four wavefronts of items per plane: the four-wavefront form with split tails;
+    // otherwise two planes side by side where their wavefronts still fit the register file
+    constexpr int NTP = PlaneThreads<PY, P1, P2, NZ, false>::value;
+    if constexpr (NTP > 256) {
+        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, true>(op, work, khat, nrhs, rb, s);
+    } else {
+        constexpr bool kPair = sizeof(R) == 4 || 2 * NTP <= 512;
+        if constexpr (kPair) {
+            if (rb >= 2) {
+                plane_reg_launch_pl<R, PY, P1, P2, NZ, 2, false>(op, work, khat, nrhs, rb, s);
+                return;
+            }
         }
+        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, false>(op, work, khat, nrhs, rb, s);
     }
-    plane_reg_launch_pl<R, PY, P1, P2, NZ, 1>(op, work, khat, nrhs, rb, s);
 }
 
 // rb > 0: right-hand sides per workgroup (autotuned), 0: the default grouping.  work = nullptr
