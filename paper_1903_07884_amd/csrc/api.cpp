@@ -136,6 +136,31 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
         if ((st = launch_contrast(op, chid.as<c128>(), s)) < 0) return fail(st);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(VIE_EDEVICE);
     }
+    {
+        // lines of the vectors with contrast somewhere along x, then the others (identity rows of
+        // the operator); the solver restricts its basis passes to the former
+        const int nyz = op->ny * op->nz;
+        DevBuf fl;
+        if ((st = fl.ensure(sizeof(int) * nyz)) < 0) return fail(st);
+        if ((st = launch_line_flags(op, fl.as<int>(), s)) < 0) return fail(st);
+        std::vector<int> hf(nyz);
+        if (hipMemcpyAsync(hf.data(), fl.p, sizeof(int) * nyz, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(VIE_EDEVICE);
+        std::vector<int> act, zero;
+        for (int c = 0; c < 3; ++c)
+            for (int yz = 0; yz < nyz; ++yz) (hf[yz] ? act : zero).push_back(c * nyz + yz);
+        if (!zero.empty()) {
+            act.insert(act.end(), zero.begin(), zero.end());
+            if ((st = op->lines.ensure(sizeof(int) * act.size())) < 0) return fail(st);
+            if (hipMemcpyAsync(op->lines.p, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(VIE_EDEVICE);
+            op->n_line_zero = (int)zero.size();
+            op->n_line_act = (int)act.size() - op->n_line_zero;
+        }
+    }
     if (o.generator) {
         if (hipMemcpyAsync(op->gen.p, o.generator, sizeof(c128) * 6 * N, hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(VIE_EDEVICE);

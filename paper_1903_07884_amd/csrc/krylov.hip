@@ -172,6 +172,40 @@ __device__ __forceinline__ long long ring_slot(int s0, int i, int m1) {
     return k >= m1 ? k - m1 : k;
 }
 
+// The elements of a vector one part of the Arnoldi passes covers.  Without a line list: a
+// contiguous chunk of [0, n).  With one (the x-lines of the grid where the contrast is not zero
+// everywhere; every basis vector is zero on the others, see solve_gmres): the part's share of the
+// listed lines, element i of the share at lines[l0 + i / nx] * nx + i mod nx.
+struct ActiveLines {
+    const int *lines = nullptr;  // nullptr: every element
+    int nlines = 0, nx = 0;
+};
+struct PartRange {
+    long long lo, hi;  // local indices [lo, hi) of this part
+    int l0, nx;
+    const int *lines;
+    __device__ __forceinline__ PartRange(const ActiveLines &A, long long n, int part, int parts) : nx(A.nx), lines(A.lines) {
+        if (lines) {
+            const int per = (A.nlines + parts - 1) / parts;
+            l0 = min(A.nlines, part * per);
+            const int l1 = min(A.nlines, l0 + per);
+            lo = 0;
+            hi = (long long)(l1 - l0) * nx;
+        } else {
+            const long long chunk = (n + parts - 1) / parts;
+            lo = part * chunk;
+            hi = min(n, lo + chunk);
+            l0 = 0;
+        }
+    }
+    // vector index of local index i (i < hi; (l1 - l0) nx is far below 2^24, so FastDiv is exact)
+    __device__ __forceinline__ long long at(long long i, const FastDiv &fnx) const {
+        if (!lines) return i;
+        const int li = fnx.div((int)i);
+        return (long long)lines[l0 + li] * nx + (i - (long long)li * nx);
+    }
+};
+
 // Reduction pass of an Arnoldi step, per right-hand side r with mask[r] set (no mask: all), and
 // with nq = nq_r[r] basis vectors q_i, u in the ring slot after them, and w (optional):
 //   partial[(r * gridDim.x + blk) * stride + k] = the part's share of
@@ -185,7 +219,7 @@ __device__ __forceinline__ long long ring_slot(int s0, int i, int m1) {
 template <class VT>
 __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj, int m1, const int *nq_r,
                                                       const int *s0_r, const c128 *w, long long n, const int *mask,
-                                                      int need_nq, int stride, c128 *partial) {
+                                                      int need_nq, int stride, c128 *partial, ActiveLines act) {
     __shared__ c128 sh[2 * KR_DG2 + 3][KR_THREADS / 64];
     const int r = blockIdx.y;
     if (mask && !mask[r]) return;
@@ -194,8 +228,8 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
     const VT *Vr = V + r * n;
     const VT *ur = Vr + ring_slot(s0, nqr, m1) * ldj;
     const c128 *wr = w ? w + r * n : nullptr;
-    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-    const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const PartRange pr(act, n, blockIdx.x, gridDim.x);
+    const FastDiv fnx(act.lines ? act.nx : 1);
     c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int ngroups = nqr > 0 ? (nqr + KR_DG2 - 1) / KR_DG2 : 1;
@@ -211,7 +245,8 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
         double sa = 0.0, se = 0.0;
 #pragma unroll
         for (int u = 0; u < KR_DG2; ++u) as[u] = ac[u] = czero<double>();
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+        for (long long i = pr.lo + threadIdx.x; i < pr.hi; i += KR_THREADS) {
+            const long long e = pr.at(i, fnx);
             const c128 ue = wide(ur[e]);
             const c128 we = wr ? wr[e] : czero<double>();
             c128 v[KR_DG2];
@@ -283,17 +318,18 @@ template <class VT>
 __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, int m1, const int *nq_r,
                                                         const int *s0_r, int next_slot, const c128 *coef, int cstride,
                                                         const c128 *w, long long n, const int *active, c64 *vlo,
-                                                        c128 *partial) {
+                                                        c128 *partial, ActiveLines act) {
     typedef decltype(V->re) T;
     __shared__ c128 cs[2 * KR_MAX_RESTART + 3];
     __shared__ c128 sh[KR_THREADS / 64];
     const int r = blockIdx.y;
-    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-    const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    const PartRange pr(act, n, blockIdx.x, gridDim.x);
+    const FastDiv fnx(act.lines ? act.nx : 1);
     VT *Vr = V + r * n;
     VT *un = Vr + next_slot * ldj;
     if (!active[r]) {
-        for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+        for (long long i = pr.lo + threadIdx.x; i < pr.hi; i += KR_THREADS) {
+            const long long e = pr.at(i, fnx);
             un[e] = mk((T)0, (T)0);
             if (vlo) vlo[r * n + e] = mk(0.0f, 0.0f);
         }
@@ -309,7 +345,8 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
     const c128 *wr = w + r * n;
     c64 *lr = vlo ? vlo + r * n : nullptr;
     double nrm = 0.0;
-    for (long long e = lo + threadIdx.x; e < hi; e += KR_THREADS) {
+    for (long long li = pr.lo + threadIdx.x; li < pr.hi; li += KR_THREADS) {
+        const long long e = pr.at(li, fnx);
         const c128 u = wide(ur[e]);
         c128 aq = u, aw = wr[e];
         int i = 0;
@@ -337,6 +374,42 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
     }
     const c128 t = block_sum_kr(mk(nrm, 0.0), sh);
     if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = t;
+}
+
+// Zero the listed x-lines (nx elements each) of `count` vectors of n elements, vector v at
+// base + v * n (grid.y = vectors).
+template <class T>
+__global__ void __launch_bounds__(KR_THREADS) k_zero_lines(T *base, long long n, const int *lines, int nlines, int nx) {
+    T *v = base + (long long)blockIdx.y * n;
+    const long long total = (long long)nlines * nx;
+    const FastDiv fnx(nx);
+    for (long long i = (long long)blockIdx.x * KR_THREADS + threadIdx.x; i < total; i += (long long)gridDim.x * KR_THREADS) {
+        const int li = fnx.div((int)i);
+        T z;
+        z.re = 0;
+        z.im = 0;
+        v[(long long)lines[li] * nx + (i - (long long)li * nx)] = z;
+    }
+}
+
+// On the listed lines (where the operator is the identity, so x = b there exactly) of the right-
+// hand sides col0 + blockIdx.y: x = b and r = 0; *nonzero is set where b has an entry there.
+__global__ void __launch_bounds__(KR_THREADS) k_identity_lines(c128 *x, const c128 *b, c128 *r, long long n,
+                                                               int col0, const int *lines, int nlines, int nx,
+                                                               int *nonzero) {
+    const long long off = (long long)(col0 + blockIdx.y) * n;
+    const long long total = (long long)nlines * nx;
+    const FastDiv fnx(nx);
+    int nz = 0;
+    for (long long i = (long long)blockIdx.x * KR_THREADS + threadIdx.x; i < total; i += (long long)gridDim.x * KR_THREADS) {
+        const int li = fnx.div((int)i);
+        const long long e = off + (long long)lines[li] * nx + (i - (long long)li * nx);
+        const c128 bv = b[e];
+        x[e] = bv;
+        r[e] = czero<double>();
+        nz |= bv.re != 0.0 || bv.im != 0.0;
+    }
+    if (nz) atomicOr(nonzero, 1);
 }
 
 // x_r += sum_{i < jr[r]} z_i,r y_r[i], z_i of column r in the slot (z0_r + i) mod m of the ring
@@ -608,6 +681,7 @@ struct Ctx {
     int nbd, nbu;  // parts per vector of the dot products and of the updates
     c128 *partial;
     double *host;  // pinned scratch
+    ActiveLines act;  // lines the basis passes cover (all when act.lines is null)
 };
 
 // batched norms: out[r].re = |w_r|^2
@@ -635,7 +709,7 @@ vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int m1, const int *jcol, c
     {
         ProfScope ps("arnoldi_dots", s);
         hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, m1, jcol, s0, w, n,
-                           (const int *)S.active, 0, cnt, C.partial);
+                           (const int *)S.active, 0, cnt, C.partial, C.act);
         VIE_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce, dim3(cnt, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
@@ -646,7 +720,7 @@ vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int m1, const int *jcol, c
     {
         ProfScope ps("arnoldi_update", s);
         hipLaunchKernelGGL(k_update2<VT>, dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, m1, jcol, s0, next_slot,
-                           (const c128 *)S.coef, S.cstride, w, n, (const int *)S.active, vlo, C.partial);
+                           (const c128 *)S.coef, S.cstride, w, n, (const int *)S.active, vlo, C.partial, C.act);
         VIE_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce, dim3(1, R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbu, 1, S.nrm2, 1);
@@ -664,7 +738,7 @@ vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, int m1, const int 
     hipStream_t s = C.s;
     const int cnt = max_jr + 1;
     hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, m1, jr_dev, s0,
-                       (const c128 *)nullptr, C.n, (const int *)nullptr, 1, cnt, C.partial);
+                       (const c128 *)nullptr, C.n, (const int *)nullptr, 1, cnt, C.partial, C.act);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(cnt, C.R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
                        S.hstride);
@@ -706,7 +780,29 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     const int m = o->restart, m1 = m + 1;
     const long long n = 3LL * op->N;
     const long long Rn = (long long)R * n;
-    Ctx C{op, s, n, R, kr_parts(n, KR_EPT_DOTS), kr_parts(n, KR_EPT_UPD), nullptr, nullptr};
+    Ctx C{op, s, n, R, kr_parts(n, KR_EPT_DOTS), kr_parts(n, KR_EPT_UPD), nullptr, nullptr, ActiveLines{}};
+    // Lines whose contrast vanishes along all of x: there the operator is the identity and the
+    // solution equals b.  With x = b and r = 0 there from the start and every preconditioned
+    // vector projected to zero there, every basis vector and every product is zero on those
+    // lines (A z = z on them), so the basis passes skip them.
+    const bool skip = op->n_line_zero > 0;
+    const int *zero_lines = skip ? op->lines.as<const int>() + op->n_line_act : nullptr;
+    if (skip) C.act = ActiveLines{op->lines.as<const int>(), op->n_line_act, op->nx};
+    const unsigned gzl = (unsigned)std::min<long long>(1024, ((long long)op->n_line_zero * op->nx + KR_THREADS - 1) / KR_THREADS);
+    // zero the skipped lines of `count` vectors of n elements from base (complex64 or complex128)
+    auto zero_skipped = [&](void *base, bool c64v, long long count) -> vie_status {
+        for (long long v0 = 0; v0 < count; v0 += 65535) {
+            const unsigned gy = (unsigned)std::min<long long>(65535, count - v0);
+            if (c64v)
+                hipLaunchKernelGGL(k_zero_lines<c64>, dim3(gzl, gy), dim3(KR_THREADS), 0, s, (c64 *)base + v0 * n, n,
+                                   zero_lines, op->n_line_zero, op->nx);
+            else
+                hipLaunchKernelGGL(k_zero_lines<c128>, dim3(gzl, gy), dim3(KR_THREADS), 0, s, (c128 *)base + v0 * n, n,
+                                   zero_lines, op->n_line_zero, op->nx);
+            VIE_HIP(hipGetLastError());
+        }
+        return VIE_OK;
+    };
     // mixed: basis V and flexible basis Z in complex64, FP64 sums and w.  mixed_pc: V in
     // complex128 with a complex64 copy of its newest vector (vlo) for the preconditioner, Z in
     // complex64, each z_j widened (zw) for the complex128 product.  V is a ring of m + 1 slots
@@ -725,6 +821,13 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
     if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
+    DevBuf nzflag;
+    if (skip) {
+        // the ring slots are written on the covered lines only from here on
+        VIE_CHECK(zero_skipped(Vb.p, v32, (long long)R * m1));
+        if (mixed_pc) VIE_CHECK(zero_skipped(vlo.p, true, R));
+        VIE_CHECK(nzflag.ensure(sizeof(int)));
+    }
     GState S;
     S.m = m;
     S.hstride = 2 * m + 3;
@@ -796,13 +899,33 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
             vie_set_error("non-finite right-hand side " + std::to_string(q));
             return VIE_ENONFINITE;
         }
+    // x = b on the skipped lines of columns [c0, c0 + cnt), r = 0 there; true when b has an entry
+    // there (then r on the other lines needs the product with x)
+    auto identity_lines = [&](int c0, int cnt, bool *nonzero) -> vie_status {
+        VIE_HIP(hipMemsetAsync(nzflag.p, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_identity_lines, dim3(gzl, cnt), dim3(KR_THREADS), 0, s, x, b, r, n, c0, zero_lines,
+                           op->n_line_zero, op->nx, nzflag.as<int>());
+        VIE_HIP(hipGetLastError());
+        VIE_CHECK(read_host(C, nzflag.p, sizeof(int)));
+        *nonzero = *reinterpret_cast<int *>(host) != 0;
+        return VIE_OK;
+    };
     if (o->x0_given) {
+        bool nz = false;  // the product below forms r everywhere anyway
+        if (skip) VIE_CHECK(identity_lines(0, R, &nz));
         VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
         hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
         VIE_HIP(hipGetLastError());
     } else {
         VIE_HIP(hipMemsetAsync(x, 0, sizeof(c128) * Rn, s));
         VIE_HIP(hipMemcpyAsync(r, b, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
+        bool nz = false;
+        if (skip) VIE_CHECK(identity_lines(0, R, &nz));
+        if (nz) {
+            VIE_CHECK(launch_matvec(op, x, r, R, VIE_C128, s));
+            hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, s, b, r, Rn);
+            VIE_HIP(hipGetLastError());
+        }
     }
     VIE_CHECK(norms(C, r, S.nrm2));
     VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
@@ -839,6 +962,13 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
             VIE_HIP(hipMemsetAsync(x + (long long)q * n, 0, sizeof(c128) * n, s));
             VIE_HIP(hipMemcpyAsync(r + (long long)q * n, b + (long long)q * n, sizeof(c128) * n,
                                    hipMemcpyDeviceToDevice, s));
+            bool nz = false;
+            if (skip) VIE_CHECK(identity_lines(q, 1, &nz));
+            if (nz) {
+                VIE_CHECK(launch_matvec(op, x + (long long)q * n, r + (long long)q * n, 1, VIE_C128, s));
+                hipLaunchKernelGGL(k_residual, dim3(256), dim3(256), 0, s, b + (long long)q * n, r + (long long)q * n, n);
+                VIE_HIP(hipGetLastError());
+            }
         }
         VIE_CHECK(norms(C, b, S.nrm2));
         VIE_CHECK(read_host(C, S.nrm2, sizeof(c128) * R));
@@ -976,11 +1106,14 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         }
         void *vj = (char *)Vb.p + vsz * Rn * (t % m1);
         void *zj = (char *)Zb.p + zsz * Rn * (t % m);
+        // a preconditioner that does not keep the skipped lines at zero (one homogenising over y,
+        // say) is projected: FGMRES takes any z, and A z then stays zero there
         if (!lowpc) {
             if (pc)
                 VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
             else
                 VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
+            if (skip && pc) VIE_CHECK(zero_skipped(zj, false, R));
             VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
         } else {
             const void *vin = mixed_pc ? vlo.p : vj;
@@ -988,6 +1121,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_CHECK(pc_apply(pc, vin, zj, R, VIE_C64, s));
             else
                 VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
+            if (skip && pc) VIE_CHECK(zero_skipped(zj, true, R));
             if (mixed) {
                 VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
                 hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);

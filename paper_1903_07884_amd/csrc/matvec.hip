@@ -50,6 +50,24 @@ vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t 
     return VIE_OK;
 }
 
+// one thread per cross-section position (z, y): does the contrast vanish along the whole x-line?
+__global__ void k_line_flags(const c128 *M, int nx, int nyz, int *flags) {
+    const int yz = blockIdx.x * blockDim.x + threadIdx.x;
+    if (yz >= nyz) return;
+    const c128 *m = M + (long long)yz * nx;
+    int any = 0;
+    for (int i = 0; i < nx && !any; ++i) any = m[i].re != 0.0 || m[i].im != 0.0;
+    flags[yz] = any;
+}
+
+vie_status launch_line_flags(vie_op op, int *flags, hipStream_t s) {
+    const int nyz = op->ny * op->nz;
+    hipLaunchKernelGGL(k_line_flags, dim3((nyz + 255) / 256), dim3(256), 0, s, op->M64.as<const c128>(), op->nx, nyz,
+                       flags);
+    VIE_HIP(hipGetLastError());
+    return VIE_OK;
+}
+
 vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s) {
     long long N = op->N;
     unsigned g = (unsigned)((N + 255) / 256);

@@ -267,6 +267,11 @@ struct vie_op_s {
     int xsplit = 1;
     FftPlan px1, px2;
     WsTable<OpWs> ws;        // product scratch per stream
+    // x-lines (component, z, y) of the vectors (layout [c][z][y][x]): on a line whose contrast is
+    // zero at every x the operator is the identity.  lines = the other lines (n_line_act), then
+    // these (n_line_zero); both counts 0 when every line has contrast somewhere.
+    DevBuf lines;
+    int n_line_act = 0, n_line_zero = 0;
 };
 
 // Flags on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is a
@@ -361,6 +366,8 @@ vie_status matvec_check_args(const char *who, vie_op op, const void *x, const vo
 vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s);
 vie_status launch_contrast(vie_op op, const c128 *chi_dev, hipStream_t s);
 vie_status launch_check_chi(const c128 *chi, long long N, int *bad, hipStream_t s);
+// flags[yz] = 1 where the contrast of cross-section position yz = z ny + y is nonzero at some x
+vie_status launch_line_flags(vie_op op, int *flags, hipStream_t s);
 // precond.hip
 vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s);
 // Drop the per-stream scratch of an operator / a preconditioner (and its box groups) for s.
