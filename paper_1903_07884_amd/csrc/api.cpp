@@ -140,7 +140,7 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
         // lines of the vectors with contrast somewhere along x, then the others (identity rows of
         // the operator); the solver restricts its basis passes to the former
         const int nyz = op->ny * op->nz;
-        DevBuf fl;
+        DevBuf &fl = op->yzflag;
         if ((st = fl.ensure(sizeof(int) * nyz)) < 0) return fail(st);
         if ((st = launch_line_flags(op, fl.as<int>(), s)) < 0) return fail(st);
         std::vector<int> hf(nyz);
@@ -159,6 +159,8 @@ extern "C" vie_status vie_create(const int32_t grid[3], double voxel_size, doubl
                 return fail(VIE_EDEVICE);
             op->n_line_zero = (int)zero.size();
             op->n_line_act = (int)act.size() - op->n_line_zero;
+        } else {
+            fl.release();
         }
     }
     if (o.generator) {

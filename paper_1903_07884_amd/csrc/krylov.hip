@@ -826,6 +826,9 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         // the ring slots are written on the covered lines only from here on
         VIE_CHECK(zero_skipped(Vb.p, v32, (long long)R * m1));
         if (mixed_pc) VIE_CHECK(zero_skipped(vlo.p, true, R));
+        // the step products leave their outputs' skipped lines as they are
+        VIE_CHECK(zero_skipped(wb.p, false, R));
+        if (mixed) VIE_CHECK(zero_skipped(w32.p, true, R));
         VIE_CHECK(nzflag.ensure(sizeof(int)));
     }
     GState S;
@@ -1114,7 +1117,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
             else
                 VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
             if (skip && pc) VIE_CHECK(zero_skipped(zj, false, R));
-            VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s));
+            VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s, skip));
         } else {
             const void *vin = mixed_pc ? vlo.p : vj;
             if (pc)
@@ -1123,13 +1126,13 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
             if (skip && pc) VIE_CHECK(zero_skipped(zj, true, R));
             if (mixed) {
-                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s));
+                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s, skip));
                 hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
                 VIE_HIP(hipGetLastError());
             } else {
                 hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, (const c64 *)zj, zw.as<c128>(), Rn);
                 VIE_HIP(hipGetLastError());
-                VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s));
+                VIE_CHECK(launch_matvec(op, zw.p, w, R, VIE_C128, s, skip));
             }
         }
         c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;

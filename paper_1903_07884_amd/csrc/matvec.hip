@@ -373,13 +373,19 @@ vie_status build_kernel_transform(vie_op op, hipStream_t s) {
 }
 
 // MODE 0: forward, x-line (nx entries, zero beyond) -> x-spectra line; MODE 1: inverse,
-// x-spectra line -> y = x - M (x + line) on the first nx entries.
+// x-spectra line -> y = x - M (x + line) on the first nx entries.  With a line map, workgroup b
+// takes line lmap[b mod nmap] of right-hand side b / nmap (3 nyz lines each).
 template <class R, int R1, int R2, int R3, int R4, int MODE>
 __global__ void __launch_bounds__((rfft::Radices<R1, R2, R3, R4>::T))
 k_xline_reg(const cpx<R> *__restrict__ in, cpx<R> *__restrict__ out, const cpx<R> *__restrict__ x,
-            const cpx<R> *__restrict__ M, int nx, int nyz, const cpx<R> *__restrict__ tw) {
+            const cpx<R> *__restrict__ M, int nx, int nyz, const cpx<R> *__restrict__ tw, const int *__restrict__ lmap,
+            int nmap) {
     constexpr int L = rfft::Radices<R1, R2, R3, R4>::L;
-    const long long line = blockIdx.x;
+    long long line = blockIdx.x;
+    if (lmap) {
+        const int rh = (int)(blockIdx.x / (unsigned)nmap);
+        line = (long long)rh * 3 * nyz + lmap[blockIdx.x - (unsigned)rh * nmap];
+    }
     const cpx<R> *src = MODE == 0 ? in + line * nx : in + line * L;
     const cpx<R> *xl = x + line * nx;
     const cpx<R> *ml = M + (line % nyz) * nx;
@@ -394,6 +400,21 @@ k_xline_reg(const cpx<R> *__restrict__ in, cpx<R> *__restrict__ out, const cpx<R
                 dl[i] = xv - ml[i] * (xv + v);
             }
         });
+}
+
+// y = x on the listed lines (nx entries each) of right-hand side blockIdx.y (3 nyz lines each):
+// the product on a line whose contrast is zero along all of x.
+template <class R>
+__global__ void k_copy_lines(const cpx<R> *__restrict__ x, cpx<R> *__restrict__ y, const int *__restrict__ lines,
+                             int nlines, int nx, int nyz) {
+    const long long base = (long long)blockIdx.y * 3 * nyz * nx;
+    const long long total = (long long)nlines * nx;
+    const FastDiv fnx(nx);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        const int li = fnx.div((int)i);
+        const long long e = base + (long long)lines[li] * nx + (i - (long long)li * nx);
+        y[e] = x[e];
+    }
 }
 
 // ---------------------------------------------------------------- product
@@ -590,7 +611,7 @@ struct PlaneThreads {
 template <class R, int PY, int P1, int P2, int NZ, int PL, bool TAIL>
 __global__ void __launch_bounds__((PL * PlaneThreads<PY, P1, P2, NZ, TAIL>::value))
 k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cpx<R> *__restrict__ twtab, int ny,
-            int Px, int nrhs, int rb, int xsplit) {
+            int Px, int nrhs, int rb, int xsplit, const int *__restrict__ yzf, int zero_in) {
     static_assert(P1 * P2 == PY, "PY = P1 P2");
     constexpr int Hy = PY / 2 + 1;            // stored y-frequencies 0 .. PY/2 (octant)
     constexpr int L = 3 * NZ;                 // lines: (component, layer)
@@ -633,6 +654,15 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
     const int line1 = t / P2, n21 = t - line1 * P2;
     const unsigned ystep = (unsigned)(P2 * Px);
     const unsigned off1 = (unsigned)((line1 * ny + n21) * Px);
+    // bit n1: the entry y = n2 + P2 n1 of this thread's column lies on a line with contrast (with
+    // yzf given, lines without contrast are not stored and, with zero_in, not loaded)
+    unsigned keep = 0;
+    rfft::sfor<P1>([&](auto ic) {
+        constexpr int n1 = decltype(ic)::value;
+        const int y = n21 + P2 * n1;
+        if (t < L * P2 && y < ny && (!yzf || yzf[(line1 % NZ) * ny + y])) keep |= 1u << n1;
+    });
+    const unsigned keep_in = zero_in ? keep : ~0u;
     cpx<R> vn[NNZ];
     rfft::sfor<NNZ>([&](auto ic) { vn[decltype(ic)::value] = czero<R>(); });
     auto load_col = [&](int rhs) {
@@ -640,7 +670,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
         rfft::sfor<NNZ>([&](auto ic) {
             constexpr int n1 = decltype(ic)::value;
             const int y = n21 + P2 * n1;
-            vn[n1] = (t < L * P2 && y < ny) ? src[off1 + n1 * ystep] : czero<R>();
+            vn[n1] = (t < L * P2 && y < ny && ((keep_in >> n1) & 1u)) ? src[off1 + n1 * ystep] : czero<R>();
         });
     };
     if (r0 + h < r1) load_col(r0 + h);
@@ -810,7 +840,7 @@ k_plane_reg(cpx<R> *__restrict__ work, const cpx<R> *__restrict__ khat, const cp
             rfft::sfor<P1>([&](auto ic) {
                 constexpr int n1 = decltype(ic)::value;
                 const int y = n2 + P2 * n1;
-                if (live && y < ny) base[off + n1 * ystep] = v[n1];
+                if (live && y < ny && ((keep >> n1) & 1u)) base[off + n1 * ystep] = v[n1];
             });
         }
     }
@@ -949,14 +979,15 @@ __global__ void k_xinv(const cpx<R> *work, const cpx<R> *x, const cpx<R> *M, cpx
 
 // One launch of the register-FFT plane pass: rb right-hand sides per workgroup, PL planes at a time.
 template <class R, int PY, int P1, int P2, int NZ, int PL, bool TAIL>
-static void plane_reg_launch_pl(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
+static void plane_reg_launch_pl(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, const int *yzf,
+                                int zero_in, hipStream_t s) {
     constexpr int L = 3 * NZ, PM = P1 > P2 ? P1 : P2;
     constexpr int NT = PL * PlaneThreads<PY, P1, P2, NZ, TAIL>::value, SP = PY + PM;
     const size_t lds = sizeof(cpx<R>) * ((size_t)PL * L * SP + (size_t)NZ * 6 * op->Hy + PY);
     const unsigned gy = (unsigned)((nrhs + rb - 1) / rb);
     vie_lds_attr((const void *)k_plane_reg<R, PY, P1, P2, NZ, PL, TAIL>, lds);
     hipLaunchKernelGGL((k_plane_reg<R, PY, P1, P2, NZ, PL, TAIL>), dim3(8 * ((op->Px + 7) / 8), gy), dim3(NT), lds, s,
-                       work, khat, TwTable<R>::get(op->py), op->ny, op->Px, nrhs, rb, op->xsplit);
+                       work, khat, TwTable<R>::get(op->py), op->ny, op->Px, nrhs, rb, op->xsplit, yzf, zero_in);
 }
 
 // The register-FFT plane pass for the (y period, layer count) pairs it is instantiated for;
@@ -965,7 +996,8 @@ static void plane_reg_launch_pl(vie_op op, cpx<R> *work, const cpx<R> *khat, int
 // x-frequency's transformed generator; groups of two or more run two planes side by side (single
 // precision, or double where the pair's wavefronts fit the register file without spilling).
 template <class R, int PY, int P1, int P2, int NZ>
-static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb_req, hipStream_t s) {
+static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb_req, const int *yzf,
+                             int zero_in, hipStream_t s) {
     const long long planes = (long long)op->Px * nrhs;
     const int rb = rb_req > 0 ? std::min(rb_req, nrhs)
                               : (int)std::max<long long>(1, std::min<long long>(nrhs, planes / 8192));
@@ -973,29 +1005,31 @@ static void plane_reg_launch(vie_op op, cpx<R> *work, const cpx<R> *khat, int nr
     // otherwise two planes side by side where their wavefronts still fit the register file
     constexpr int NTP = PlaneThreads<PY, P1, P2, NZ, false>::value;
     if constexpr (NTP > 256) {
-        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, true>(op, work, khat, nrhs, rb, s);
+        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, true>(op, work, khat, nrhs, rb, yzf, zero_in, s);
     } else {
         constexpr bool kPair = sizeof(R) == 4 || 2 * NTP <= 512;
         if constexpr (kPair) {
             if (rb >= 2) {
-                plane_reg_launch_pl<R, PY, P1, P2, NZ, 2, false>(op, work, khat, nrhs, rb, s);
+                plane_reg_launch_pl<R, PY, P1, P2, NZ, 2, false>(op, work, khat, nrhs, rb, yzf, zero_in, s);
                 return;
             }
         }
-        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, false>(op, work, khat, nrhs, rb, s);
+        plane_reg_launch_pl<R, PY, P1, P2, NZ, 1, false>(op, work, khat, nrhs, rb, yzf, zero_in, s);
     }
 }
 
 // rb > 0: right-hand sides per workgroup (autotuned), 0: the default grouping.  work = nullptr
-// only asks whether the shape is instantiated.
+// only asks whether the shape is instantiated.  yzf: store only the lines with contrast (and with
+// zero_in load only those, the others being zero).
 template <class R>
-static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s) {
+static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int rb, hipStream_t s,
+                      const int *yzf = nullptr, int zero_in = 0) {
     const int Py = op->Py, nz = op->nz;
     if (!op->direct_z || op->split_plane) return false;
     if ((long long)3 * nz * op->ny * op->Px >= (1LL << 31)) return false;  // 32-bit offsets in a slab
 #define VIE_PLANE_REG(PY, P1, P2, NZ)                                              \
     if (Py == PY && nz == NZ) {                                                    \
-        if (work) plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, rb, s); \
+        if (work) plane_reg_launch<R, PY, P1, P2, NZ>(op, work, khat, nrhs, rb, yzf, zero_in, s); \
         return true;                                                               \
     }
     VIE_PLANE_REG(96, 12, 8, 8)
@@ -1014,37 +1048,40 @@ static bool plane_reg(vie_op op, cpx<R> *work, const cpx<R> *khat, int nrhs, int
 // combination.
 template <class R, int R1, int R2, int R3, int R4>
 static void xline_launch(int mode, long long lines, const cpx<R> *in, cpx<R> *out, const cpx<R> *x, const cpx<R> *M,
-                         int nx, int nyz, const cpx<R> *tw, hipStream_t s) {
+                         int nx, int nyz, const cpx<R> *tw, const int *lmap, int nmap, hipStream_t s) {
     typedef rfft::Radices<R1, R2, R3, R4> RD;
     const size_t lds = sizeof(cpx<R>) * RD::L;
+    const unsigned g = (unsigned)(lmap ? lines / (3LL * nyz) * nmap : lines);
+    if (g == 0) return;
     if (mode == 0) {
         vie_lds_attr((const void *)k_xline_reg<R, R1, R2, R3, R4, 0>, lds);
-        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 0>), dim3((unsigned)lines), dim3(RD::T), lds, s, in, out, x,
-                           M, nx, nyz, tw);
+        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 0>), dim3(g), dim3(RD::T), lds, s, in, out, x, M, nx, nyz,
+                           tw, lmap, nmap);
     } else {
         vie_lds_attr((const void *)k_xline_reg<R, R1, R2, R3, R4, 1>, lds);
-        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 1>), dim3((unsigned)lines), dim3(RD::T), lds, s, in, out, x,
-                           M, nx, nyz, tw);
+        hipLaunchKernelGGL((k_xline_reg<R, R1, R2, R3, R4, 1>), dim3(g), dim3(RD::T), lds, s, in, out, x, M, nx, nyz,
+                           tw, lmap, nmap);
     }
 }
 
-// mode -1 only asks whether the length is instantiated.
+// mode -1 only asks whether the length is instantiated.  lmap (nmap lines of each right-hand
+// side's 3 ny nz): transform only those lines.
 template <class R>
 static bool xline_reg(vie_op op, int mode, long long lines, const cpx<R> *in, cpx<R> *out, const cpx<R> *x,
-                      const cpx<R> *M, hipStream_t s) {
+                      const cpx<R> *M, hipStream_t s, const int *lmap = nullptr, int nmap = 0) {
     if (op->xsplit > 1) return false;
     if (mode < 0) return op->Px == 1024 || op->Px == 2048 || op->Px == 4096 || op->Px == 8192 ||
                          (op->Px == 16384 && sizeof(R) == 4);
     const cpx<R> *tw = TwTable<R>::get(op->px);
     const int nyz = op->ny * op->nz;
     switch (op->Px) {
-        case 1024: xline_launch<R, 16, 8, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
-        case 2048: xline_launch<R, 16, 16, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
-        case 4096: xline_launch<R, 16, 16, 16, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
-        case 8192: xline_launch<R, 16, 16, 16, 2>(mode, lines, in, out, x, M, op->nx, nyz, tw, s); return true;
+        case 1024: xline_launch<R, 16, 8, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, lmap, nmap, s); return true;
+        case 2048: xline_launch<R, 16, 16, 8, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, lmap, nmap, s); return true;
+        case 4096: xline_launch<R, 16, 16, 16, 1>(mode, lines, in, out, x, M, op->nx, nyz, tw, lmap, nmap, s); return true;
+        case 8192: xline_launch<R, 16, 16, 16, 2>(mode, lines, in, out, x, M, op->nx, nyz, tw, lmap, nmap, s); return true;
         case 16384:  // complex64 only (a complex128 line of this length takes the four-step path)
             if constexpr (sizeof(R) == 4) {
-                xline_launch<R, 16, 16, 16, 4>(mode, lines, in, out, x, M, op->nx, nyz, tw, s);
+                xline_launch<R, 16, 16, 16, 4>(mode, lines, in, out, x, M, op->nx, nyz, tw, lmap, nmap, s);
                 return true;
             }
             return false;
@@ -1062,20 +1099,31 @@ static void matvec_scratch(const vie_op op, int nrhs, size_t esz, size_t *work, 
 // One product through the three passes; work and ysp hold matvec_scratch's bytes.
 // cfg_plane: right-hand sides per workgroup of the register plane pass, or the threads of the
 // LDS plane pass; cfg_x: threads of the LDS x-line passes (0 = defaults).
+// Lines whose contrast vanishes along all of x (op->lines, when the register x-line and plane
+// passes serve the shape): their product is y = x, so the inverse pass transforms only the other
+// lines and copies x on these, and the plane pass does not store them.  zero_in (x zero on them,
+// y not needed there): the forward pass and the plane pass skip them too and y is left as it is.
 template <class R>
 static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
-                             const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, int cfg_plane, int cfg_x, hipStream_t s) {
+                             const cpx<R> *M, cpx<R> *work, cpx<R> *ysp, int cfg_plane, int cfg_x, hipStream_t s,
+                             bool zero_in = false) {
     const int nx = op->nx, ny = op->ny, nz = op->nz, Px = op->Px;
     long long lines = 3LL * ny * nz * nrhs;
     size_t ldsx;
     int thx, bpt;
     fft_line_shape(op->px, sizeof(cpx<R>), &thx, &ldsx, &bpt, cfg_x);
     const int thp = cfg_plane ? cfg_plane : 256;
+    const bool lskip = op->n_line_zero > 0 && op->direct_z && !op->split_plane &&
+                       xline_reg<R>(op, -1, 0, nullptr, nullptr, nullptr, nullptr, s) &&
+                       plane_reg<R>(op, nullptr, khat, nrhs, 0, s);
+    const int *lact = lskip ? op->lines.as<const int>() : nullptr;
+    const int *yzf = lskip ? op->yzflag.as<const int>() : nullptr;
+    const int zin = lskip && zero_in ? 1 : 0;
     {
         ProfScope ps("matvec_xfwd", s);
         if (op->xsplit > 1) {
             VIE_CHECK(long_lines<R>(op, x, nx, work, lines, false, s));
-        } else if (!xline_reg<R>(op, 0, lines, x, work, nullptr, nullptr, s)) {
+        } else if (!xline_reg<R>(op, 0, lines, x, work, nullptr, nullptr, s, zin ? lact : nullptr, op->n_line_act)) {
 #define LAUNCH_XFWD(B)                                      \
     vie_lds_attr((const void *)k_xfwd<R, B>, ldsx);         \
     hipLaunchKernelGGL((k_xfwd<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, x, work, nx, op->px)
@@ -1105,7 +1153,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
                            lg, op->py, op->xsplit);
     } else if (op->direct_z) {
         ProfScope ps("matvec_plane", s);
-        if (!plane_reg<R>(op, work, khat, nrhs, cfg_plane, s)) {
+        if (!plane_reg<R>(op, work, khat, nrhs, cfg_plane, s, yzf, zin)) {
             size_t ldsp = sizeof(cpx<R>) * ((size_t)6 * nz * op->Py + (size_t)6 * op->Hy * nz);
             vie_lds_attr((const void *)k_plane_dz<R>, ldsp);
             hipLaunchKernelGGL(k_plane_dz<R>, dim3(8 * ((Px + 7) / 8), nrhs), dim3(thp), ldsp, s, work, khat, ny, nz,
@@ -1138,7 +1186,15 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
 #undef LAUNCH_COLS_INV
     } else {
         ProfScope ps("matvec_xinv", s);
-        if (!xline_reg<R>(op, 1, lines, work, y, x, M, s)) {
+        if (lskip) {
+            xline_reg<R>(op, 1, lines, work, y, x, M, s, lact, op->n_line_act);
+            if (!zin) {
+                const long long per = (long long)op->n_line_zero * nx;
+                hipLaunchKernelGGL(k_copy_lines<R>, dim3((unsigned)std::min<long long>(1024, (per + 255) / 256), nrhs),
+                                   dim3(256), 0, s, x, y, op->lines.as<const int>() + op->n_line_act, op->n_line_zero,
+                                   nx, ny * nz);
+            }
+        } else if (!xline_reg<R>(op, 1, lines, work, y, x, M, s)) {
 #define LAUNCH_XINV(B)                                                                               \
     vie_lds_attr((const void *)k_xinv<R, B>, ldsx);                                                  \
     hipLaunchKernelGGL((k_xinv<R, B>), dim3((unsigned)lines), dim3(thx), ldsx, s, work, x, M, y, nx, \
@@ -1155,7 +1211,7 @@ static vie_status matvec_run(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, co
 // fastest (plane-pass threads x x-line threads) for this shape, cached per process.
 template <class R>
 static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, const cpx<R> *khat,
-                           const cpx<R> *M, hipStream_t s) {
+                           const cpx<R> *M, hipStream_t s, bool zero_in) {
     const int pi = sizeof(R) == 8 ? 0 : 1;
     OpWs *w = op->ws.get(s);
     std::lock_guard<std::mutex> lk(w->mu);
@@ -1217,14 +1273,15 @@ static vie_status matvec_t(vie_op op, const cpx<R> *x, cpx<R> *y, int nrhs, cons
         w->cfg_plane_thr[pi] = choice[0], w->cfg_x_thr[pi] = choice[1];
         w->tuned_nrhs[pi] = nrhs;
     }
-    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, w->cfg_plane_thr[pi], w->cfg_x_thr[pi], s);
+    return matvec_run<R>(op, x, y, nrhs, khat, M, work, ysp, w->cfg_plane_thr[pi], w->cfg_x_thr[pi], s, zero_in);
 }
 
-vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s) {
+vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s, bool zero_skipped_in) {
     if (prec == VIE_C128)
         return matvec_t<double>(op, (const c128 *)x, (c128 *)y, nrhs, op->khat64.as<c128>(),
-                                op->M64.as<c128>(), s);
-    return matvec_t<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(), s);
+                                op->M64.as<c128>(), s, zero_skipped_in);
+    return matvec_t<float>(op, (const c64 *)x, (c64 *)y, nrhs, op->khat32.as<c64>(), op->M32.as<c64>(), s,
+                           zero_skipped_in);
 }
 
 // ---------------------------------------------------------------- allocation-free product

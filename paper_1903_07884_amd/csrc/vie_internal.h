@@ -272,6 +272,7 @@ struct vie_op_s {
     // these (n_line_zero); both counts 0 when every line has contrast somewhere.
     DevBuf lines;
     int n_line_act = 0, n_line_zero = 0;
+    DevBuf yzflag;           // int32 [nz][ny]: 1 where the line has contrast (with the lists only)
 };
 
 // Flags on a stored-block index (block_of_mode) or a mode entry (mode_list): the mode is a
@@ -360,7 +361,10 @@ vie_status tune_time(hipStream_t s, int reps, const std::function<vie_status()> 
 vie_status launch_generator(vie_op op, hipStream_t s);
 // matvec.hip
 vie_status build_kernel_transform(vie_op op, hipStream_t s);
-vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s);
+// zero_skipped_in: x is zero on the lines of zero contrast (op->lines) and y is not needed there
+// (left as it is); the passes then skip those lines.  Otherwise y = x there, which is exact.
+vie_status launch_matvec(vie_op op, const void *x, void *y, int nrhs, int prec, hipStream_t s,
+                         bool zero_skipped_in = false);
 // api.cpp: the argument checks of vie_matvec and its allocation-free variant (`who` names the call)
 vie_status matvec_check_args(const char *who, vie_op op, const void *x, const void *y, int32_t nrhs, int prec);
 vie_status launch_rhs(vie_op op, const c128 *e, c128 *b, int nrhs, hipStream_t s);

@@ -120,3 +120,78 @@ def test_skipped_lines_equal_full_lines_solve(gpu_lib):
     diff = np.linalg.norm(out[0][1] - out[1][1]) / np.linalg.norm(out[1][1])
     print('skipped lines: iters %d / %d, difference %.2e' % (out[0][0], out[1][0], diff))
     assert out[0][0] == out[1][0] and diff < 1e-9
+
+
+def _register_grid_problem():
+    """512x16x8 (x period 1024, y period 32: the register x-line and plane passes) with two
+    cores in y; a seeded synthetic generator injected so the oracle's FFT operator is exact."""
+    grid = (512, 16, 8)
+    K = W.synthetic_generator(grid, 81, scale=0.2)
+    chi = W.coupler(grid, cores=((2, 6), (9, 13)))
+    M = OCT.contrast_from_chi(chi)
+    nx, ny, nz = grid
+    zero_yz = ~np.any(M != 0, axis=2)
+    skipped = np.broadcast_to(zero_yz[None, :, :, None], (3, nz, ny, nx)).reshape(-1)
+    return grid, K, chi, M, skipped
+
+
+def test_products_with_skipped_lines_match_oracle(gpu_lib):
+    """Products of inputs with entries everywhere (y = x on the lines without contrast, the other
+    lines by the transforms): entry by entry against the oracle's FFT operator, FP64 and complex64."""
+    import torch
+    grid, K, chi, M, skipped = _register_grid_problem()
+    from oracle import fftref as FR
+    R = 5
+    x = W.random_field((R, 3 * int(np.prod(grid))), 82)
+    ref = FR.FftOperator(K, M, grid).matvec(x)
+    op = gpu_lib.Operator(grid, 25e-9, KB, chi, generator=K, build_c64=True)
+    xd = _dev(x)
+    y64 = torch.empty_like(xd)
+    op.matvec(xd, y64, nrhs=R)
+    x32 = xd.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    op.matvec(x32, y32, nrhs=R)
+    op.close()
+    y64, y32 = y64.cpu().numpy(), y32.cpu().numpy().astype(np.complex128)
+    for q in range(R):
+        e64 = np.abs(y64[q] - ref[q]).max() / np.abs(ref[q]).max()
+        e32 = np.abs(y32[q] - ref[q]).max() / np.abs(ref[q]).max()
+        print('rhs %d: fp64 %.2e c64 %.2e (entry-wise)' % (q, e64, e32))
+        assert e64 < 1e-10 and e32 < 1e-5
+        assert np.array_equal(y64[q][skipped], x[q][skipped])
+
+
+@pytest.mark.parametrize("mode", ['fp64', 'mixed'])
+def test_register_grid_solve_with_skipped_lines(gpu_lib, mode):
+    """The step products skip the lines without contrast (input zero there): the solution's
+    oracle-evaluated residual, x = b on those lines, and the same iterations and solution as the
+    solve where those lines carry a contrast of 1e-30 (nothing skipped)."""
+    import torch
+    grid, K, chi, M, skipped = _register_grid_problem()
+    from oracle import fftref as FR
+    n = 3 * int(np.prod(grid))
+    e = W.random_field((2, n), 83)
+    B = np.stack([np.tile(M.reshape(-1), 3) * e[0], e[1]])
+    tol = 1e-8 if mode == 'fp64' else 1e-6
+    out = []
+    for c in (chi, np.where(chi == 0, 1e-30, chi)):
+        op = gpu_lib.Operator(grid, 25e-9, KB, c, generator=K, build_c64=(mode == 'mixed'))
+        pc = gpu_lib.Preconditioner(op, factor_prec=gpu_lib.VIE_C128 if mode == 'fp64' else gpu_lib.VIE_C64)
+        Xd = torch.zeros_like(_dev(B))
+        st = gpu_lib.solve(op, pc, _dev(B), Xd, nrhs=2, tol=tol, mode=mode)
+        out.append((st, Xd.cpu().numpy()))
+        pc.close()
+        op.close()
+    (st, X), (st_full, X_full) = out
+    A = FR.FftOperator(K, M, grid)
+    for q in range(2):
+        res = np.linalg.norm(B[q] - A.matvec(X[q])) / np.linalg.norm(B[q])
+        diff = np.linalg.norm(X[q] - X_full[q]) / np.linalg.norm(X_full[q])
+        print('%s rhs %d: iters %d (nothing skipped: %d), oracle residual %.2e, difference %.2e'
+              % (mode, q, st[q]['iters'], st_full[q]['iters'], res, diff))
+        assert st[q]['status'] == 0 and res <= 2 * tol
+        assert np.array_equal(X[q][skipped], B[q][skipped])
+        if q == 0 and mode == 'fp64':  # M e: the same Krylov space in both solves
+            assert st[q]['iters'] == st_full[q]['iters'] and diff < 1e-9
+        elif q == 0:  # complex64 products: rounding differs between the two, within its bar
+            assert abs(st[q]['iters'] - st_full[q]['iters']) <= 2 and diff < 1e-4
