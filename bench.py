@@ -327,6 +327,18 @@ def cpu_baseline(cfg, iters, restarts, R, factor_blocks):
     kappa = W.k_background() * cfg['delta']
     rng = np.random.default_rng(5)
     parts = {}
+
+    def per_call(fn, reps):
+        # seconds per call of a small sampled step: one untimed call (library threads and caches
+        # warm), then the fastest of `reps` timed calls, since the step is scaled up many times
+        fn()
+        best = float('inf')
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
     # generator: all 6 components on sampled octant offsets
     offs = [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))) for _ in range(100)]
     offs += [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 1, 0)]
@@ -351,35 +363,26 @@ def cpu_baseline(cfg, iters, restarts, R, factor_blocks):
     # Chan table: Chan weights + explicit DFT of sampled x-sequences (6 (2ny-1)(2nz-1) in all)
     nseq = 6 * (2 * ny - 1) * (2 * nz - 1)
     F = OC.dft_matrix(nx)
-    t = time.perf_counter()
-    for _ in range(20):
-        seq = rng.standard_normal(2 * nx - 1) + 0j
-        F @ OC.chan(seq)
-    parts['chan_table'] = (time.perf_counter() - t) / 20 * nseq
+    seq = rng.standard_normal(2 * nx - 1) + 0j
+    parts['chan_table'] = per_call(lambda: F @ OC.chan(seq), 20) * nseq
     # LU of sampled blocks (the oracle factorises every mode's block)
     D = np.eye(m) + 0.1 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
-    t = time.perf_counter()
-    for _ in range(2):
-        lu = scipy.linalg.lu_factor(D)
-    parts['lu'] = (time.perf_counter() - t) / 2 * factor_blocks
+    lu = scipy.linalg.lu_factor(D)
+    parts['lu'] = per_call(lambda: scipy.linalg.lu_factor(D), 2) * factor_blocks
     # preconditioner apply: explicit DFT of sampled lines + block solves of R columns
     r = rng.standard_normal((8, nx)) + 0j
-    t = time.perf_counter()
-    r @ F.T
-    t_dft = (time.perf_counter() - t) / 8 * m * R * 2
+    t_dft = per_call(lambda: r @ F.T, 5) / 8 * m * R * 2
     rhs = rng.standard_normal((m, R)) + 0j
-    t = time.perf_counter()
-    for _ in range(4):
-        scipy.linalg.lu_solve(lu, rhs)
-    t_sol = (time.perf_counter() - t) / 4 * nx
+    t_sol = per_call(lambda: scipy.linalg.lu_solve(lu, rhs), 4) * nx
     # modified Gram-Schmidt against an average of 25.5 basis vectors, per right-hand side
     V = rng.standard_normal((4, n3)) + 0j
-    w = rng.standard_normal(n3) + 0j
-    t = time.perf_counter()
-    for i in range(4):
-        h = np.vdot(V[i], w)
-        w = w - h * V[i]
-    t_mgs = (time.perf_counter() - t) / 4 * 25.5 * R
+    w0 = rng.standard_normal(n3) + 0j
+
+    def mgs4():
+        w = w0
+        for i in range(4):
+            w = w - np.vdot(V[i], w) * V[i]
+    t_mgs = per_call(mgs4, 3) / 4 * 25.5 * R
     per_iter = R * t_mv + t_dft + t_sol + t_mgs
     setup = sum(parts.values())
     total = setup + iters * per_iter + restarts * R * t_mv

@@ -331,7 +331,7 @@ __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, type
                                                   const FT *arow, const FT *abase, long long m, bool rv,
                                                   const cpx<R> *Y, int kb, int ke, int rot, cpx<R> *buf) {
     constexpr int WC = CT * 16;
-    constexpr int YC = sizeof(R) == 8 ? 8 : 16;       // rows per chunk
+    constexpr int YC = 16;                            // rows per chunk (FP64: the two slots and two tiles fill 160 KB)
     constexpr int SPT = (YC * WC + NTH - 1) / NTH;    // staged complex per thread
     constexpr int KS = YC / 2;                        // K-steps per chunk
     const int lane = threadIdx.x & 63;
@@ -956,9 +956,9 @@ template <class R, int CT, int NW, class FT>
 static void launch_wide_nw(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
                            hipStream_t s) {
     const int per = (w->n_wide + 7) / 8;
-    // two 64-row tiles + two chunk slots of solved rows (FP: 16 / 8 rows; bfloat16: hi + lo, 16 rows)
+    // two 64-row tiles + two chunk slots of 16 solved rows (bfloat16: hi + lo)
     const size_t chunk = sizeof(FT) == 4 ? 2 * 2 * (size_t)CT * 16 * 16 * sizeof(uint32_t)
-                                         : 2 * (size_t)(sizeof(R) == 8 ? 8 : 16) * CT * 16 * sizeof(cpx<R>);
+                                         : 2 * (size_t)16 * CT * 16 * sizeof(cpx<R>);
     const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16 + chunk;
     vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
     const int *mp = pc->modes_dev.as<const int>();
