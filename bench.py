@@ -458,7 +458,7 @@ class Workload:
         self.stream = torch.cuda.current_stream()
 
     def step(self, record, mode=None, reduce_tol='default', boxes='default', proxy='product', factor=None,
-             keep_zero_rows=False, precond=True, share_tol=0.0, mirror=True):
+             keep_zero_rows=False, precond=True, share_tol=0.0, mirror=True, refine=None):
         import torch
         vie, plan, R = self.vie, self.plan, self.R
         mode = mode or plan['mode']
@@ -472,7 +472,7 @@ class Workload:
         ev[1].record(self.stream)
         pc = vie.Preconditioner(op, homog=plan['homog'], boxes=bxs, reduce_tol=rt, factor_prec=fp, proxy=proxy,
                                 keep_zero_rows=keep_zero_rows, levels=plan.get('levels', 1),
-                                share_tol=share_tol, mirror=mirror) if precond else None
+                                share_tol=share_tol, mirror=mirror, refine=refine) if precond else None
         ev[2].record(self.stream)
         op.rhs(self.e_d, self.b_d, nrhs=R)
         st = vie.solve(op, pc, self.b_d, self.x_d, nrhs=R, tol=plan.get('tol', 1e-6), restart=50, mode=mode,
@@ -491,15 +491,16 @@ class Workload:
                                solve_ms=ev[2].elapsed_time(ev[3]),
                                iters=max(q['iters'] for q in st), restarts=max(q['restarts'] for q in st),
                                relres=max(q['relres'] for q in st),
-                               status=max(q['status'] for q in st), info=info, mode=mode, factor=factor))
+                               status=max(q['status'] for q in st), info=info, mode=mode, factor=factor,
+                               refine=(1 if factor == 'bf16' else 0) if refine is None else refine))
         return st
 
     def models(self, rec):
         """Algorithmic work of the dominant kernels of a recorded step: name -> (bound, amount,
         unit, peak), the peak that of the kernel's own arithmetic type."""
         mode, factor = rec['mode'], rec['factor']
-        mdl = algorithmic_models(self.cfg, rec['info'], self.R, mode, factor,
-                                 refine=1 if factor == 'bf16' else 0, iters=rec['iters'])
+        mdl = algorithmic_models(self.cfg, rec['info'], self.R, mode, factor, refine=rec['refine'],
+                                 iters=rec['iters'])
         out = {'_tag': self.tag, '_factor': factor}
         for k, val in mdl.items():
             if k.startswith('_'):
@@ -517,8 +518,9 @@ class Workload:
                 peak = FP64_PEAK_TFLOPS if mode == 'fp64' else FP32_PEAK_TFLOPS
             if unit == 'flops' and factor == 'bf16' and k == 'block_solve':
                 # two solves (off-diagonal products on the BF16 units) + the FP32 residual: the time
-                # each third of the flops takes at its own peak, summed
-                peak = 1.0 / ((2.0 / 3.0) / BF16_PEAK_TFLOPS + (1.0 / 3.0) / FP32_PEAK_TFLOPS)
+                # each third of the flops takes at its own peak, summed; one solve alone: the BF16 peak
+                peak = (1.0 / ((2.0 / 3.0) / BF16_PEAK_TFLOPS + (1.0 / 3.0) / FP32_PEAK_TFLOPS) if rec['refine']
+                        else BF16_PEAK_TFLOPS)
             out[k] = (bound, amount, unit, peak)
         info = rec['info']
         if info.get('stored_blocks'):
@@ -561,6 +563,7 @@ def leg_plan(tag, main_mode):
     """Comparison legs of the default run per workload: (label, kwargs)."""
     if tag == 4:
         legs = [('fp64', dict(mode='fp64')), ('mixed_bf16_refined', dict(mode='mixed', factor='bf16')),
+                ('mixed_bf16_unrefined', dict(mode='mixed', factor='bf16', refine=0)),
                 ('mixed_c64_factors', dict(mode='mixed', factor='c64')),
                 ('mixed_pc_c64_factors', dict(mode='mixed_pc', factor='c64')),
                 ('mixed_bf16_reduced_1e-3_centre_proxy', dict(mode='mixed', factor='bf16', reduce_tol=1e-3,
