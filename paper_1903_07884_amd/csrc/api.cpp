@@ -456,10 +456,11 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
             if (!o.keep_zero_rows && o.factor_prec == VIE_C128) pcb += table * 16 + nb * by * bz * 16;
             pcb += 3 * by * bz * 4 + 64;  // row orders, coupling flag
             *pc_held += pcb;
-            // apply: x-DFT lines plus the matrix-core solve scratch (once more when refining)
+            // apply: x-DFT lines plus the matrix-core solve scratch (once more for the bfloat16
+            // hi + lo copy of the solved rows, which a refined apply's two solves share)
             const uint64_t cols = modes * R;
             const uint64_t wide = (cols + 64 * modes) * m * vesz;
-            *apply_scratch += R * nb * m * (modes / nb) * vesz + wide * (o.refine_steps ? 2 : 1);
+            *apply_scratch += R * nb * m * (modes / nb) * vesz + wide * (o.factor_prec == VIE_BF16C ? 2 : 1);
             if (two) *apply_scratch += R * nb * 3 * by * bz * bx * vesz;  // x-stage lines
         }
     }

@@ -323,23 +323,39 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 // once per workgroup, in chunks, double-buffered: the next chunk's rows and factor entries are
 // loaded while the current chunk is multiplied, one barrier per chunk.  Every wavefront of the
 // workgroup must call these (active = false: it only helps stage).  Chunks run in rotated order
-// (rot) so that workgroups sharing one factor read different parts of it at a time.
+// (rot): the workgroups of one stored block take the same rotation and, dispatched together on
+// one XCD, read each factor chunk at about the same time (the later reads hit L2), while
+// different blocks start at different chunks.
 
-// FP32 / FP64 solved rows, row-major [m][CT*16] complex; YC rows per chunk.
+// FP32 / FP64 solved rows, row-major [m][CT*16] complex; YC rows per chunk.  The complex
+// product takes three real matrix-core products per K-step of four complex rows (Gauss):
+// with a = L[row][k] and y = Y[k][col], P1 = Re a Re y, P2 = Im a Im y and
+// P3 = (Re a + Im a)(Re y + Im y) give Re(a y) = P1 - P2 and Im(a y) = P3 - P1 - P2, so the
+// accumulators are g1 = Re acc - sum P1, g2 = sum P2 and g3 = Re acc + Im acc - sum P3, folded
+// back at the end.  Lane (r, q) of the 16x16x4 instruction supplies factor row r and solved
+// column r of complex row k0 + q (four distinct complex rows per instruction, where the
+// (Re, Im)-interleaved form needs two instructions for two rows).
 template <class R, int CT, int NTH, class FT>
 __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, bool active,
                                                   const FT *arow, const FT *abase, long long m, bool rv,
                                                   const cpx<R> *Y, int kb, int ke, int rot, cpx<R> *buf) {
+    typedef typename Mfma<R>::v4 v4;
     constexpr int WC = CT * 16;
     constexpr int YC = 16;                            // rows per chunk (FP64: the two slots and two tiles fill 160 KB)
     constexpr int SPT = (YC * WC + NTH - 1) / NTH;    // staged complex per thread
-    constexpr int KS = YC / 2;                        // K-steps per chunk
+    constexpr int KS = YC / 4;                        // K-steps per chunk
     const int lane = threadIdx.x & 63;
-    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    const int r = lane & 15, q = lane >> 4;
     const FT *ap = rv ? arow + r : abase;
     const int nch = (ke - kb + YC - 1) / YC;
     rot = rot % nch;
     cpx<R> st[SPT], a0[KS], a1[KS];
+    v4 g2[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        g2[ct] = v4{0, 0, 0, 0};
+        ci[ct] += cr[ct];  // g3; cr is g1
+    }
     auto row0 = [&](int c) { int cc = c + rot; if (cc >= nch) cc -= nch; return kb + YC * cc; };
     auto load = [&](int c, cpx<R> *a) {
         const int k0 = row0(c);
@@ -350,7 +366,7 @@ __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, type
         }
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
-            const int kc = k0 + 2 * u + kh;
+            const int kc = k0 + 4 * u + q;
             a[u] = ldf(ap + (long long)(kc < ke ? kc : kb) * m);  // past ke: multiplied by zero rows
         }
     };
@@ -363,17 +379,17 @@ __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, type
         }
     };
     auto compute = [&](int slot, const cpx<R> *a) {
-        const R *xs = reinterpret_cast<const R *>(buf + slot * YC * WC) + p;
+        const cpx<R> *ys = buf + slot * YC * WC + r;
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
-            const R ar = p ? a[u].im : -a[u].re;   // negated (Re a, -Im a)
-            const R ai = p ? -a[u].re : -a[u].im;  // negated (Im a, Re a)
-            const R *xr = xs + (2 * u + kh) * WC * 2;
+            const R n1 = -a[u].re, p2 = a[u].im, n3 = -(a[u].re + a[u].im);
+            const cpx<R> *yr = ys + (4 * u + q) * WC;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const R bv = xr[(ct * 16 + r) * 2];
-                cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
-                ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
+                const cpx<R> y = yr[ct * 16];
+                cr[ct] = Mfma<R>::fma(n1, y.re, cr[ct]);
+                g2[ct] = Mfma<R>::fma(p2, y.im, g2[ct]);
+                ci[ct] = Mfma<R>::fma(n3, y.re + y.im, ci[ct]);
             }
         }
     };
@@ -389,6 +405,11 @@ __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, type
         __syncthreads();
         if (active) compute(1, a1);
         if (c + 2 < nch) stage(0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        ci[ct] = ci[ct] - cr[ct] + g2[ct];
+        cr[ct] += g2[ct];
     }
 }
 
@@ -522,7 +543,9 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
 
 // Item = (stored block s, first column c0, column count, box).  Column g of block s is the
 // pair (mode modes[mode_ptr[s] + g / nrhs], right-hand side g % nrhs).  Y is a per-item
-// scratch, row-major [m][CT*16], holding y = L^{-1} P b and then x = U^{-1} y.
+// scratch, row-major [m][CT*16], holding y = L^{-1} P b and then x = U^{-1} y.  With bfloat16
+// factors the split copy Yb alone holds y and the solved x rows, and Y receives x only when it
+// is kept (out_mode 1), so a solve writes its solved rows once, not twice.
 //
 // NW wavefronts own 16 rows each of a super-tile of 16*NW rows (NW/4 tiles of 64 rows).
 // Forward, per super-tile S:
@@ -649,7 +672,7 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                     }
                     if (row < w) {
                         const long long yo = (long long)(t0 + row) * WC + ct * 16 + r;
-                        Yi[yo] = x;
+                        if (!kBf16 || (!lower && out_mode == 1)) Yi[yo] = x;
                         if (!lower && off[ct] >= 0 && out_mode != 1) {
                             const cpx<R> o = out_mode == 2 ? x + Ya[yo] : x;
                             work[off[ct] + (long long)(t0 + row) * n] =
@@ -710,9 +733,9 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
             const FT *ar = A + min(myt0 + wrow, m - 1);
             if constexpr (kBf16)
                 wide_gemm_chunked_bf16<CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yh, Yl, mp, 0, s0,
-                                                    5 * it, reinterpret_cast<uint32_t *>(yb_c));
+                                                    5 * sblk, reinterpret_cast<uint32_t *>(yb_c));
             else
-                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, 0, s0, 5 * it, yb_c);
+                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, 0, s0, 5 * sblk, yb_c);
         }
         __syncthreads();
         for (int tt = 0; tt < NW / 4; ++tt) {
@@ -727,23 +750,44 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
         const int s0 = S * ST;
         const int se = min(m, s0 + ST);
         const int myt0 = s0 + TS * sub;
+        if constexpr (kBf16) {
+            // y from its hi + lo split (about 17 significant bits, far below the error of the
+            // bfloat16 factors): the lane's rows rb..rb+3 are consecutive in the column-major copy
+            const int rb = myt0 + wrow + 4 * q;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+            for (int ct = 0; ct < CT; ++ct) {
+                uint4 h = make_uint4(0, 0, 0, 0), l = h;
+                if (rb < mp) {  // mp and rb are multiples of 16 and 4: rows rb..rb+3 exist (past m: zero)
+                    const long long bo = (long long)(ct * 16 + r) * mp + rb;
+                    h = *reinterpret_cast<const uint4 *>(Yh + bo);
+                    l = *reinterpret_cast<const uint4 *>(Yl + bo);
+                }
+                const uint32_t hv[4] = {h.x, h.y, h.z, h.w}, lv[4] = {l.x, l.y, l.z, l.w};
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
-                cpx<R> y = row < m ? Yi[(long long)row * WC + ct * 16 + r] : czero<R>();
-                cr[ct][v] = y.re;
-                ci[ct][v] = y.im;
+                for (int v = 0; v < 4; ++v) {
+                    cr[ct][v] = __uint_as_float(hv[v] << 16) + __uint_as_float(lv[v] << 16);
+                    ci[ct][v] = __uint_as_float(hv[v] & 0xffff0000u) + __uint_as_float(lv[v] & 0xffff0000u);
+                }
             }
+        } else {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = myt0 + wrow + Mfma<R>::acc_row(q, v);
+                    cpx<R> y = row < m ? Yi[(long long)row * WC + ct * 16 + r] : czero<R>();
+                    cr[ct][v] = y.re;
+                    ci[ct][v] = y.im;
+                }
+        }
         if (se < m) {
             const bool act = myt0 < m;
             const FT *ar = A + min(myt0 + wrow, m - 1);
             if constexpr (kBf16)
                 wide_gemm_chunked_bf16<CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yh, Yl, mp, se, m,
-                                                    5 * it, reinterpret_cast<uint32_t *>(yb_c));
+                                                    5 * sblk, reinterpret_cast<uint32_t *>(yb_c));
             else
-                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, se, m, 5 * it, yb_c);
+                wide_gemm_chunked<R, CT, NW * 64>(cr, ci, act, ar, A, m, myt0 + wrow + r < m, Yi, se, m, 5 * sblk, yb_c);
         }
         __syncthreads();
         for (int tt = NW / 4 - 1; tt >= 0; --tt) {
@@ -765,8 +809,9 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
 // are left out; their input enters the right-hand side before the first solve),
 // the Chan/x-DFT table of the block (complex float, [6][2bz-1][2by-1] per mode, staged in
 // LDS), c(a,b) the index of the unique component (xx, yy, zz, xy, xz, yz).  The product is
-// a matrix-core GEMM whose left operand is generated from the table.  NW wavefronts take
-// 16-row strips in turn.
+// a matrix-core GEMM whose left operand is generated from the table, in three real products
+// per K-step of four complex columns (Gauss, as in the chunked solve products: lane (r, q)
+// looks up entry (row r, column k0 + q)).  NW wavefronts take 16-row strips in turn.
 template <int CT, int NW>
 __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c64 *chan, const c64 *mt,
                                                               const int *smode, const int4 *items, int nitems,
@@ -787,17 +832,18 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
     const int tabn = 6 * ndz * ndy;
     c64 *tab = reinterpret_cast<c64 *>(vie_smem);
     c64 *buf = tab + ((tabn + 1) & ~1);             // two chunk slots of z0 rows
-    int *pk = reinterpret_cast<int *>(buf + 2 * YC * WC);  // (b, z', y') of solve row j, packed
+    // solve row j = (b, y', z'): b and the table offset z' (2by-1) + y' it subtracts, packed
+    int *pk = reinterpret_cast<int *>(buf + 2 * YC * WC);
     const c64 *src = chan + (long long)smode[sblk] * tabn;
     for (int i = threadIdx.x; i < tabn; i += blockDim.x) tab[i] = src[i];
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
         const int pr = rows[j], b = pr / plane, yz = pr - b * plane;
-        pk[j] = (b << 20) | ((yz / by) << 10) | (yz % by);
+        pk[j] = (b << 20) | ((yz / by) * ndy + yz % by);
     }
     const c64 *Yi = Y + (long long)it * m * WC;
     const long long rstride = (long long)nboxes * m * n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    const int r = lane & 15, q = lane >> 4;
     long long off[CT];
     int fl[CT];  // reflected mode: the residual of S D_k S, i.e. rows of r - D_k z0 where S = -1 change sign
 #pragma unroll
@@ -834,29 +880,37 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
         const bool active = row0 < m;
         const int arow = rows[min(row0 + r, m - 1)];  // this lane's operand row (a, y, z)
         const int a = arow / plane, yz = arow - a * plane, z = yz / by, y = yz - z * by;
-        v4 cr[CT], ci[CT];
+        // table index of (row, column (b, y', z')) = base[b] - (z' (2by-1) + y'), base[b] holding
+        // the component c(a, b) and the row's own offsets
+        const int rbase = (z + bz - 1) * ndy + (y + by - 1);
+        const int base0 = (a == 0 ? 0 : a + 2) * ndz * ndy + rbase;   // c(a, 0): xx, xy, xz
+        const int base1 = (a == 1 ? 1 : a + 3) * ndz * ndy + rbase;   // c(a, 1): xy, yy, yz
+        const int base2 = (a == 2 ? 2 : a + 4) * ndz * ndy + rbase;   // c(a, 2): xz, yz, zz
+        const int d01 = base1 - base0, d12 = base2 - base1;  // base[b] by masks (no indexed array)
+        v4 g1[CT], g2[CT], g3[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            cr[ct] = v4{0, 0, 0, 0};
-            ci[ct] = v4{0, 0, 0, 0};
+            g1[ct] = v4{0, 0, 0, 0};
+            g2[ct] = v4{0, 0, 0, 0};
+            g3[ct] = v4{0, 0, 0, 0};
         }
         auto compute = [&](int slot, int c) {
-            const float *xs = reinterpret_cast<const float *>(buf + slot * YC * WC) + p;
-#pragma unroll 2
-            for (int u = 0; u < YC / 2; ++u) {
-                const int kc = c * YC + 2 * u + kh;
-                const int pc = pk[min(kc, m - 1)];  // column (b, y', z')
-                const int b = pc >> 20, zp = (pc >> 10) & 1023, yp = pc & 1023;
-                const int cc = a == b ? a : a + b + 2;  // xy -> 3, xz -> 4, yz -> 5
-                const c64 t = kc < m ? tab[(cc * ndz + (z - zp + bz - 1)) * ndy + (y - yp + by - 1)] : czero<float>();
-                const float ar = p ? -t.im : t.re;
-                const float ai = p ? t.re : t.im;
-                const float *xr = xs + (2 * u + kh) * WC * 2;
+            const c64 *ys = buf + slot * YC * WC + r;
+#pragma unroll
+            for (int u = 0; u < YC / 4; ++u) {
+                const int kc = c * YC + 4 * u + q;
+                const int pc = pk[min(kc, m - 1)];
+                const int b = pc >> 20;
+                const int ti = base0 + (d01 & -(b >= 1)) + (d12 & -(b >= 2)) - (pc & 0xfffff);
+                const c64 t = kc < m ? tab[ti] : czero<float>();
+                const float t3 = t.re + t.im;
+                const c64 *yr = ys + (4 * u + q) * WC;
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
-                    const float bv = xr[(ct * 16 + r) * 2];
-                    cr[ct] = Mfma<float>::fma(ar, bv, cr[ct]);
-                    ci[ct] = Mfma<float>::fma(ai, bv, ci[ct]);
+                    const c64 v = yr[ct * 16];
+                    g1[ct] = Mfma<float>::fma(t.re, v.re, g1[ct]);
+                    g2[ct] = Mfma<float>::fma(t.im, v.im, g2[ct]);
+                    g3[ct] = Mfma<float>::fma(t3, v.re + v.im, g3[ct]);
                 }
             }
         };
@@ -881,11 +935,10 @@ __global__ void __launch_bounds__(NW * 64) k_refine_residual(c64 *work, const c6
                 for (int v = 0; v < 4; ++v) {
                     const int row = row0 + Mfma<float>::acc_row(q, v);
                     if (row < m && off[ct] >= 0) {
-                        const int ryz = ((pk[row] >> 10) & 1023) * by + (pk[row] & 1023);  // M~ index (z, y)
-                        const c64 mv = mt[(long long)box * plane + ryz];
+                        const c64 mv = mt[(long long)box * plane + rows[row] % plane];  // M~ at (z, y)
                         const c64 z0 = Yi[(long long)row * WC + ct * 16 + r];
                         const long long wo = off[ct] + (long long)row * n;
-                        const c64 t = mv * mk(cr[ct][v], ci[ct][v]);
+                        const c64 t = mv * mk(g1[ct][v] - g2[ct][v], g3[ct][v] - g1[ct][v] - g2[ct][v]);
                         work[wo] = mirror_flip(fl[ct], row, mx) ? work[wo] + z0 - t : work[wo] - z0 + t;
                     }
                 }
@@ -918,8 +971,13 @@ static vie_status build_schedule(vie_pc pc, PcWs *w, int nrhs, hipStream_t s) {
         if (cols >= min_cols && nrhs >= min_rhs) wide_cols += cols;
     }
     int gmax = w->cfg_gmax;
-    if (gmax == 0) {  // default: the widest group that still gives >= 512 workgroups
+    if (gmax == 0) {
+        // default: FP64 the narrowest group (16 columns in 4-wavefront workgroups: several
+        // workgroups per CU hide the latency of the factor stream better than wider column
+        // tiles, whose registers only allow one or two); otherwise the widest group that still
+        // gives >= 512 workgroups
         gmax = WIDE_MAX_COLS;
+        if (pc->prec == VIE_C128) gmax = WIDE_MIN_COLS;
         while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
     }
     for (int sb = 0; sb < pc->nstored; ++sb) {
@@ -972,7 +1030,7 @@ static void launch_wide_nw(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs
 static int wide_nw(vie_pc pc, const PcWs *w, bool fp32) {
     if (w->cfg_nw) return w->cfg_nw;
     if (pc->prec == VIE_BF16C) return 8;  // the bfloat16 double buffers need > 128 VGPRs
-    return fp32 ? 16 : 8;
+    return fp32 ? 16 : 4;
 }
 
 template <class R, int CT, class FT>
@@ -1014,12 +1072,11 @@ static vie_status block_solve_run(vie_pc pc, PcWs *w, cpx<R> *work, int nrhs, hi
         cpx<R> *Y = w->wide_scratch.as<cpx<R>>();
         if (pc->prec == VIE_BF16C)  // hi + lo bfloat16 copies of the solved rows
             VIE_CHECK(w->wide_bf16.ensure(sizeof(uint32_t) * 2 * (size_t)w->n_wide * WC * ((m + 15) / 16 * 16)));
-        const bool refine = pc->refine && sizeof(R) == 4;
-        cpx<R> *Y2 = nullptr;
-        if (refine) {
-            VIE_CHECK(w->wide_scratch2.ensure(ybytes));
-            Y2 = w->wide_scratch2.as<cpx<R>>();
-        }
+        // refinement comes with bfloat16 factors only; the correcting solve (out_mode 2) then
+        // neither reads nor writes its Y (its solved rows live in the split copy), so it is handed
+        // the first solve's Y, which it reads as Yadd
+        const bool refine = pc->refine && pc->prec == VIE_BF16C;
+        cpx<R> *Y2 = Y;
 #define WIDE_CASES(CTV)                                                                                  \
     if (!refine) {                                                                                       \
         launch_wide<R, CTV, FT>(pc, w, work, Y, nrhs, 0, nullptr, s);                                       \

@@ -236,7 +236,6 @@ struct PcWs {
     DevBuf sched;            // int4 wide items [n_wide], then int4 narrow items of narrow_rc columns
                              // (m <= 64: of 64/m columns)
     DevBuf wide_scratch;     // wide-solve tiles: n_wide * m * 16*wide_ct complex
-    DevBuf wide_scratch2;    // second solve of a refined apply
     DevBuf wide_bf16;        // bfloat16 hi + lo split of the solved rows (BF16 factors)
     // block-solve launch parameters (defaults or autotuned for tuned_nrhs right-hand sides)
     int cfg_gmax = 0;        // widest column group of the wide solve (0: widest giving >= 512 groups)
