@@ -491,21 +491,31 @@ __device__ __forceinline__ void wide_gemm_chunked_bf16(Mfma<float>::v4 *cr, Mfma
     }
 }
 
-// acc (16 rows x CT*16 columns) += T(16 x w) * Xs(w x CT*16) over K-steps [kbeg, kend): T
-// entries loaded from `t_ptr(row, kc)` (always a valid address) and passed through
-// `t_val(row, kc, loaded)`; Xs is an LDS tile, row-major [64][CT*16] complex.
+// acc (16 rows x CT*16 columns) += T(16 x w) * Xs(w x CT*16) over K-steps [kbeg, kend) of four
+// complex rows each: T entries loaded from `t_ptr(row, kc)` (always a valid address) and passed
+// through `t_val(row, kc, loaded)`; Xs is an LDS tile, row-major [64][CT*16] complex.  Three real
+// products per K-step as in the chunked products (here acc += T Xs: g1 = Re acc + sum P1,
+// g2 = -sum P2, g3 = Re acc + Im acc + sum P3).
 template <class R, int CT, class TPtr, class TVal>
-__device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, const R *xs,
+__device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename Mfma<R>::v4 *ci, const cpx<R> *xs,
                                               int kbeg, int kend, TPtr t_ptr, TVal t_val) {
+    typedef typename Mfma<R>::v4 v4;
     const int lane = threadIdx.x & 63;
-    const int r = lane & 15, q = lane >> 4, kh = q >> 1, p = q & 1;
+    const int r = lane & 15, q = lane >> 4;
     constexpr int WC = CT * 16;
     constexpr int KC = 2;
+    if (kbeg >= kend) return;
+    v4 g2[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        g2[ct] = v4{0, 0, 0, 0};
+        ci[ct] += cr[ct];  // g3; cr is g1
+    }
     cpx<R> a0[KC], a1[KC];
     auto load = [&](int ks0, cpx<R> *a) {
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
-            const int kc = 2 * (ks0 + u) + kh;
+            const int kc = 4 * (ks0 + u) + q;
             a[u] = ldf(t_ptr(r, kc < 64 ? kc : 63));
         }
     };
@@ -513,20 +523,19 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
             const int ks = ks0 + u;
-            const int kc = 2 * ks + kh;
+            const int kc = 4 * ks + q;
             const cpx<R> t = (ks < kend) ? t_val(r, kc, a[u]) : czero<R>();
-            const R ar = p ? -t.im : t.re;
-            const R ai = p ? t.re : t.im;
-            const R *xrow = xs + (size_t)(kc < 64 ? kc : 63) * WC * 2 + p;
+            const R p1 = t.re, n2 = -t.im, p3 = t.re + t.im;
+            const cpx<R> *xrow = xs + (kc < 64 ? kc : 63) * WC + r;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const R bv = xrow[(ct * 16 + r) * 2];
-                cr[ct] = Mfma<R>::fma(ar, bv, cr[ct]);
-                ci[ct] = Mfma<R>::fma(ai, bv, ci[ct]);
+                const cpx<R> y = xrow[ct * 16];
+                cr[ct] = Mfma<R>::fma(p1, y.re, cr[ct]);
+                g2[ct] = Mfma<R>::fma(n2, y.im, g2[ct]);
+                ci[ct] = Mfma<R>::fma(p3, y.re + y.im, ci[ct]);
             }
         }
     };
-    if (kbeg >= kend) return;
     load(kbeg, a0);
     for (int ks0 = kbeg; ks0 < kend; ks0 += 2 * KC) {
         load(ks0 + KC, a1);
@@ -538,6 +547,11 @@ __device__ __forceinline__ void wide_gemm_lds(typename Mfma<R>::v4 *cr, typename
         __builtin_amdgcn_sched_barrier(0);
         compute(ks0 + KC, a1);
         __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        ci[ct] = ci[ct] - cr[ct] + g2[ct];
+        cr[ct] += g2[ct];
     }
 }
 
@@ -579,8 +593,6 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
     cpx<R> *xs_c = reinterpret_cast<cpx<R> *>(vie_smem);  // [64][WC]: tile accumulators
     cpx<R> *ys_c = xs_c + TS * WC;                         // [64][WC]: solved tile
     cpx<R> *yb_c = ys_c + TS * WC;                         // staged chunks of solved rows (2 slots)
-    const R *xs = reinterpret_cast<const R *>(xs_c);
-    const R *ys = reinterpret_cast<const R *>(ys_c);
     const FT *A = F + (long long)sblk * m * m;
     const int *pm = perm + (long long)sblk * m;
     cpx<R> *Yi = Y + (long long)it * m * WC;
@@ -644,14 +656,14 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
                 return (row < w && kc < w) ? Aii + (long long)kc * m + row : Aii;
             };
             if (lower)
-                wide_gemm_lds<R, CT>(cr, ci, xs, 0, min((w + 1) / 2, 8 * (wl + 1)), tptr,
+                wide_gemm_lds<R, CT>(cr, ci, xs_c, 0, min((w + 3) / 4, 4 * (wl + 1)), tptr,
                                      [&](int rr, int kc, cpx<R> v) -> cpx<R> {
                                          const int row = wrow + rr;
                                          if (row >= w || kc >= w || kc > row) return czero<R>();
                                          return kc == row ? mk(R(1), R(0)) : v;
                                      });
             else
-                wide_gemm_lds<R, CT>(cr, ci, xs, 8 * wl, (w + 1) / 2, tptr, [&](int rr, int kc, cpx<R> v) -> cpx<R> {
+                wide_gemm_lds<R, CT>(cr, ci, xs_c, 4 * wl, (w + 3) / 4, tptr, [&](int rr, int kc, cpx<R> v) -> cpx<R> {
                     const int row = wrow + rr;
                     return (row >= w || kc >= w || kc < row) ? czero<R>() : v;
                 });
@@ -708,7 +720,7 @@ __global__ void __launch_bounds__(NW * 64) k_block_solve_wide(cpx<R> *work, cons
             const FT *Ab = A + (long long)t0 * m + myt0 + wrow;
             const bool rv = myt0 + wrow + r < m;
             wide_gemm_lds<R, CT>(
-                cr, ci, ys, 0, (w + 1) / 2,
+                cr, ci, ys_c, 0, (w + 3) / 4,
                 [&](int rr, int kc) -> const FT * { return (rv && kc < w) ? Ab + (long long)kc * m + rr : A; },
                 [&](int rr, int kc, cpx<R> v) -> cpx<R> { return (!rv || kc >= w) ? czero<R>() : mk(-v.re, -v.im); });
         }
@@ -972,10 +984,9 @@ static vie_status build_schedule(vie_pc pc, PcWs *w, int nrhs, hipStream_t s) {
     }
     int gmax = w->cfg_gmax;
     if (gmax == 0) {
-        // default: FP64 the narrowest group (16 columns in 4-wavefront workgroups: several
-        // workgroups per CU hide the latency of the factor stream better than wider column
-        // tiles, whose registers only allow one or two); otherwise the widest group that still
-        // gives >= 512 workgroups
+        // default: FP64 the narrowest group (16 columns: several workgroups per CU hide the
+        // latency of the factor stream better than wider column tiles, whose registers allow
+        // only one); otherwise the widest group that still gives >= 512 workgroups
         gmax = WIDE_MAX_COLS;
         if (pc->prec == VIE_C128) gmax = WIDE_MIN_COLS;
         while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
@@ -1030,7 +1041,7 @@ static void launch_wide_nw(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs
 static int wide_nw(vie_pc pc, const PcWs *w, bool fp32) {
     if (w->cfg_nw) return w->cfg_nw;
     if (pc->prec == VIE_BF16C) return 8;  // the bfloat16 double buffers need > 128 VGPRs
-    return fp32 ? 16 : 4;
+    return fp32 ? 16 : 8;
 }
 
 template <class R, int CT, class FT>
