@@ -986,9 +986,9 @@ static vie_status build_schedule(vie_pc pc, PcWs *w, int nrhs, hipStream_t s) {
     if (gmax == 0) {
         // default: FP64 the narrowest group (16 columns: several workgroups per CU hide the
         // latency of the factor stream better than wider column tiles, whose registers allow
-        // only one); otherwise the widest group that still gives >= 512 workgroups
-        gmax = WIDE_MAX_COLS;
-        if (pc->prec == VIE_C128) gmax = WIDE_MIN_COLS;
+        // only one); bfloat16 32 columns; complex64 the widest group; each halved while it
+        // gives fewer than 512 workgroups
+        gmax = pc->prec == VIE_C128 ? WIDE_MIN_COLS : pc->prec == VIE_BF16C ? 32 : WIDE_MAX_COLS;
         while (gmax > WIDE_MIN_COLS && wide_cols / gmax < 512) gmax /= 2;
     }
     for (int sb = 0; sb < pc->nstored; ++sb) {
