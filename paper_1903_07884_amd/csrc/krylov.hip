@@ -748,6 +748,43 @@ vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, int m1, const int 
     return VIE_OK;
 }
 
+// Pinned host scratch of the solves (read-backs of norms and column states), kept for reuse per
+// device: freeing pinned memory waits for the whole device, which would make every finishing
+// solve wait for the work that concurrent solves have queued on other streams.
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<std::pair<int, std::pair<size_t, void *>>> idle;  // (device, (bytes, pointer))
+};
+static PinnedPool &pinned_pool() {
+    static PinnedPool *p = new PinnedPool();  // never destroyed: the buffers live until exit
+    return *p;
+}
+static vie_status pinned_get(size_t bytes, void **out, size_t *got) {
+    int dev = 0;
+    VIE_HIP(hipGetDevice(&dev));
+    {
+        PinnedPool &pp = pinned_pool();
+        std::lock_guard<std::mutex> lk(pp.mu);
+        for (size_t i = 0; i < pp.idle.size(); ++i)
+            if (pp.idle[i].first == dev && pp.idle[i].second.first >= bytes) {
+                *out = pp.idle[i].second.second;
+                *got = pp.idle[i].second.first;
+                pp.idle.erase(pp.idle.begin() + i);
+                return VIE_OK;
+            }
+    }
+    VIE_HIP(hipHostMalloc(out, bytes, hipHostMallocDefault));
+    *got = bytes;
+    return VIE_OK;
+}
+static void pinned_put(size_t bytes, void *p) {
+    int dev = 0;
+    if (!p || hipGetDevice(&dev) != hipSuccess) return;
+    PinnedPool &pp = pinned_pool();
+    std::lock_guard<std::mutex> lk(pp.mu);
+    pp.idle.push_back({dev, {bytes, p}});
+}
+
 vie_status read_host(Ctx &C, const void *dev, size_t bytes) {
     VIE_HIP(hipMemcpyAsync(C.host, dev, bytes, hipMemcpyDeviceToHost, C.s));
     VIE_HIP(hipStreamSynchronize(C.s));
@@ -870,13 +907,18 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         *mask_dev = jend_dev + R;
     C.partial = part.as<c128>();
     double *host = nullptr;
+    size_t host_bytes = 0;
     // pinned layout: doubles [0, 4R) | ints active, jcol, s0, z0, jend, mask [R each]
-    VIE_HIP(hipHostMalloc((void **)&host, sizeof(double) * 4 * (size_t)R + sizeof(int) * NI * R + 64,
-                          hipHostMallocDefault));
-    struct HostFree {
-        double *p;
-        ~HostFree() { (void)hipHostFree(p); }
-    } hf{host};
+    VIE_CHECK(pinned_get(sizeof(double) * 4 * (size_t)R + sizeof(int) * NI * R + 64, (void **)&host, &host_bytes));
+    struct HostPut {  // back to the pool once this solve's stream is done with it (a no-op wait
+        double *p;    // on the normal path; an error return may leave a copy in flight)
+        size_t n;
+        hipStream_t st;
+        ~HostPut() {
+            (void)hipStreamSynchronize(st);
+            pinned_put(n, p);
+        }
+    } hp{host, host_bytes, s};
     C.host = host;
     int *hact = reinterpret_cast<int *>(host + 4 * (size_t)R);
     int *hjcol = hact + R, *hs0 = hjcol + R, *hz0 = hs0 + R, *hjend = hz0 + R, *hmask = hjend + R;
