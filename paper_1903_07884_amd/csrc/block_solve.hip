@@ -414,40 +414,50 @@ __device__ __forceinline__ void wide_gemm_chunked(typename Mfma<R>::v4 *cr, type
 }
 
 // bfloat16 factors: solved rows split into bfloat16 hi + lo, [col][mp] per item (rows past m
-// zero); one chunk = one 16-complex K-step on v_mfma_f32_16x16x32_bf16, whose lane l supplies
-// row l%16 and reals 8 (l/16) .. +7: the four complex entries 4 (l/16) .. +3 as (re, im) pairs,
+// zero); a K-step is 16 complex rows on v_mfma_f32_16x16x32_bf16, whose lane l supplies row
+// l%16 and reals 8 (l/16) .. +7: the four complex entries 4 (l/16) .. +3 as (re, im) pairs,
 // i.e. exactly four packed factor words.  -(Re a, -Im a) is the word with the low sign bit
 // flipped, -(Im a, Re a) the word with its halves swapped and both sign bits flipped.  The
-// accumulator layout is that of the FP32 16x16x4 instruction.  kb is a multiple of 16; columns
-// past ke meet zero rows of Y (ke < m is a multiple of 16; at ke = m the padding rows are zero).
+// accumulator layout is that of the FP32 16x16x4 instruction.  A chunk is BF_KSTEPS K-steps:
+// the products of one K-step are too short to cover the latency of the next chunk's loads, so
+// a chunk carries several.  kb is a multiple of 16; rows from ke on are staged as zeros (in the
+// forward pass the rows past ke are not solved yet), and rows m..mp-1 of Y are zero.
+#define BF_KSTEPS 2
 template <int CT, int NTH>
 __device__ __forceinline__ void wide_gemm_chunked_bf16(Mfma<float>::v4 *cr, Mfma<float>::v4 *ci, bool active,
                                                        const bf16c *arow, const bf16c *abase, long long m, bool rv,
                                                        const uint32_t *Yh, const uint32_t *Yl, int mp, int kb, int ke,
                                                        int rot, uint32_t *buf) {
     constexpr int WC = CT * 16;
-    constexpr int NV = 2 * WC * 4;                   // uint4 loads per chunk (hi and lo, 4 per column)
+    constexpr int KB = BF_KSTEPS;
+    constexpr int NV1 = 2 * WC * 4;                  // uint4 loads per K-step (hi and lo, 4 per column)
+    constexpr int NV = NV1 * KB;
     constexpr int SPT = (NV + NTH - 1) / NTH;
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     const uint32_t *ap = reinterpret_cast<const uint32_t *>(rv ? arow + r : abase);
-    const int nch = (ke - kb + 15) / 16;
+    const int nch = (ke - kb + 16 * KB - 1) / (16 * KB);
     rot = rot % nch;
-    u4v st[SPT], a0, a1;
-    auto row0 = [&](int c) { int cc = c + rot; if (cc >= nch) cc -= nch; return kb + 16 * cc; };
-    auto load = [&](int c, u4v &a) {
+    u4v st[SPT], a0[KB], a1[KB];
+    auto row0 = [&](int c) { int cc = c + rot; if (cc >= nch) cc -= nch; return kb + 16 * KB * cc; };
+    auto load = [&](int c, u4v *a) {
         const int k0 = row0(c);
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
-            const int e = threadIdx.x + u * NTH;      // e = (half * WC + col) * 4 + quad
+            const int e = threadIdx.x + u * NTH;      // e = ((ks * 2 + half) * WC + col) * 4 + quad
             if (e < NV) {
-                const int quad = e & 3, hc = e >> 2, half = hc / WC, col = hc % WC;
-                st[u] = *reinterpret_cast<const u4v *>((half ? Yl : Yh) + (long long)col * mp + k0 + 4 * quad);
+                const int quad = e & 3, hc = e >> 2, col = hc % WC, hk = hc / WC, half = hk & 1;
+                const int row = k0 + 16 * (hk >> 1) + 4 * quad;
+                st[u] = row < ke ? *reinterpret_cast<const u4v *>((half ? Yl : Yh) + (long long)col * mp + row)
+                                 : u4v{0, 0, 0, 0};
             }
         }
-        const int kc0 = k0 + 4 * q;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = ap[(long long)min(kc0 + t, (int)m - 1) * m];
+        for (int ks = 0; ks < KB; ++ks) {
+            const int kc0 = k0 + 16 * ks + 4 * q;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[ks][t] = ap[(long long)min(kc0 + t, (int)m - 1) * m];
+        }
     };
     auto stage = [&](int slot) {
         u4v *b = reinterpret_cast<u4v *>(buf) + slot * NV;
@@ -457,23 +467,26 @@ __device__ __forceinline__ void wide_gemm_chunked_bf16(Mfma<float>::v4 *cr, Mfma
             if (e < NV) b[e] = st[u];
         }
     };
-    auto compute = [&](int slot, const u4v &a) {
-        const u4v *b = reinterpret_cast<const u4v *>(buf) + slot * NV;
-        u4v nre, nim;
+    auto compute = [&](int slot, const u4v *a) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            nre[t] = a[t] ^ 0x00008000u;                           // -(Re a, -Im a)
-            nim[t] = ((a[t] >> 16) | (a[t] << 16)) ^ 0x80008000u;  // -(Im a, Re a)
-        }
-        const v8bf vre = __builtin_bit_cast(v8bf, nre), vim = __builtin_bit_cast(v8bf, nim);
+        for (int ks = 0; ks < KB; ++ks) {
+            const u4v *b = reinterpret_cast<const u4v *>(buf) + slot * NV + ks * NV1;
+            u4v nre, nim;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            const int col = ct * 16 + r;
-            const v8bf h = __builtin_bit_cast(v8bf, b[col * 4 + q]), l = __builtin_bit_cast(v8bf, b[(WC + col) * 4 + q]);
-            cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, h, cr[ct], 0, 0, 0);
-            ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, h, ci[ct], 0, 0, 0);
-            cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, l, cr[ct], 0, 0, 0);
-            ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, l, ci[ct], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) {
+                nre[t] = a[ks][t] ^ 0x00008000u;                               // -(Re a, -Im a)
+                nim[t] = ((a[ks][t] >> 16) | (a[ks][t] << 16)) ^ 0x80008000u;  // -(Im a, Re a)
+            }
+            const v8bf vre = __builtin_bit_cast(v8bf, nre), vim = __builtin_bit_cast(v8bf, nim);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int col = ct * 16 + r;
+                const v8bf h = __builtin_bit_cast(v8bf, b[col * 4 + q]), l = __builtin_bit_cast(v8bf, b[(WC + col) * 4 + q]);
+                cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, h, cr[ct], 0, 0, 0);
+                ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, h, ci[ct], 0, 0, 0);
+                cr[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vre, l, cr[ct], 0, 0, 0);
+                ci[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vim, l, ci[ct], 0, 0, 0);
+            }
         }
     };
     load(0, a0);
@@ -1025,8 +1038,8 @@ template <class R, int CT, int NW, class FT>
 static void launch_wide_nw(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs, int out_mode, const cpx<R> *Yadd,
                            hipStream_t s) {
     const int per = (w->n_wide + 7) / 8;
-    // two 64-row tiles + two chunk slots of 16 solved rows (bfloat16: hi + lo)
-    const size_t chunk = sizeof(FT) == 4 ? 2 * 2 * (size_t)CT * 16 * 16 * sizeof(uint32_t)
+    // two 64-row tiles + two chunk slots of 16 solved rows (bfloat16: hi + lo of 16 BF_KSTEPS rows)
+    const size_t chunk = sizeof(FT) == 4 ? 2 * 2 * (size_t)CT * 16 * 16 * BF_KSTEPS * sizeof(uint32_t)
                                          : 2 * (size_t)16 * CT * 16 * sizeof(cpx<R>);
     const size_t lds = 2 * sizeof(cpx<R>) * TS * CT * 16 + chunk;
     vie_lds_attr((const void *)k_block_solve_wide<R, CT, NW, FT>, lds);
