@@ -471,9 +471,10 @@ static vie_status footprint_parts(int nx, int ny, int nz, int Px, int Py, bool s
         const bool mixed = so->mode == VIE_MODE_MIXED, mixed_pc = so->mode == VIE_MODE_MIXED_PC;
         const uint64_t vb = mixed ? 8 : 16;              // basis precision
         const uint64_t zb = mixed || mixed_pc ? 8 : 16;  // preconditioned vectors
-        // complex64 product output (mixed); complex64 copy of v_j + widened z_j (mixed_pc)
+        // complex64 product output (mixed, which has no complex128 one); complex64 copy of v_j +
+        // widened z_j (mixed_pc)
         const uint64_t extra = mixed ? 8 : mixed_pc ? 8 + 16 : 0;
-        *solve_bytes = vb * R * n3 * (rs + 1) + zb * R * n3 * rs + 2 * 16 * R * n3 +
+        *solve_bytes = vb * R * n3 * (rs + 1) + zb * R * n3 * rs + (mixed ? 1 : 2) * 16 * R * n3 +
                        16 * R * (uint64_t)arnoldi_partials((long long)n3, (int)rs) + extra * R * n3 +
                        2 * 16 * R * (rs + 2) * (rs + 4);
     }

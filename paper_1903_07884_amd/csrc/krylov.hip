@@ -31,9 +31,9 @@
 //
 // FP64 mode: basis, z, products and factors complex128.  Mixed mode: the basis (u_j, then q_j)
 // is stored in complex64 and u_j feeds the complex64 preconditioner and operator product, whose
-// result is widened back for the FP64 reduction and update; Z is kept in complex64; the true
-// residual of every cycle uses the complex128 product, so the outer loop is an FP64 iterative
-// refinement around the FP32 inner solve.  Mixed-preconditioner mode: only the preconditioner
+// result the reduction and update passes read as is and widen on load (their sums are FP64); Z is
+// kept in complex64; the true residual of every cycle uses the complex128 product, so the outer
+// loop is an FP64 iterative refinement around the FP32 inner solve.  Mixed-preconditioner mode: only the preconditioner
 // runs in complex64 (or bfloat16 factors), on a complex64 copy of u_j; Z is kept in complex64,
 // each z_j is widened for the complex128 product, and the basis stays complex128.
 #include <cmath>
@@ -214,11 +214,12 @@ struct PartRange {
 // need_nq skips columns with nq = 0 (the finishing reduction of a cycle).  The outputs are
 // formed KR_DG2 basis vectors at a time (u and w read once per group); inside a group the
 // loads of an element are unconditional (a short last group clamps its index and drops the
-// extra products), so they are in flight together.
+// extra products), so they are in flight together.  w is complex128 or, in mixed mode, the
+// complex64 product itself (widened on load: the sums stay FP64).
 #define KR_DG2 8
-template <class VT>
+template <class VT, class WT>
 __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj, int m1, const int *nq_r,
-                                                      const int *s0_r, const c128 *w, long long n, const int *mask,
+                                                      const int *s0_r, const WT *w, long long n, const int *mask,
                                                       int need_nq, int stride, c128 *partial, ActiveLines act) {
     __shared__ c128 sh[2 * KR_DG2 + 3][KR_THREADS / 64];
     const int r = blockIdx.y;
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
     if (need_nq && nqr == 0) return;
     const VT *Vr = V + r * n;
     const VT *ur = Vr + ring_slot(s0, nqr, m1) * ldj;
-    const c128 *wr = w ? w + r * n : nullptr;
+    const WT *wr = w ? w + r * n : nullptr;
     const PartRange pr(act, n, blockIdx.x, gridDim.x);
     const FastDiv fnx(act.lines ? act.nx : 1);
     c128 *out = partial + ((long long)r * gridDim.x + blockIdx.x) * stride;
@@ -248,7 +249,7 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
         for (long long i = pr.lo + threadIdx.x; i < pr.hi; i += KR_THREADS) {
             const long long e = pr.at(i, fnx);
             const c128 ue = wide(ur[e]);
-            const c128 we = wr ? wr[e] : czero<double>();
+            const c128 we = wr ? wide(wr[e]) : czero<double>();
             c128 v[KR_DG2];
 #pragma unroll
             for (int u = 0; u < KR_DG2; ++u) v[u] = wide(vp[u][e]);
@@ -314,10 +315,10 @@ __global__ void __launch_bounds__(KR_THREADS) k_dots2(const VT *V, long long ldj
 // lies past its last basis vector (its cycle ended before this step; within one cycle of at
 // most m steps the ring does not come back to it), so it is zeroed, with its complex64 copy:
 // the batch's preconditioner applies and products then never read stale values for it.
-template <class VT>
+template <class VT, class WT>
 __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, int m1, const int *nq_r,
                                                         const int *s0_r, int next_slot, const c128 *coef, int cstride,
-                                                        const c128 *w, long long n, const int *active, c64 *vlo,
+                                                        const WT *w, long long n, const int *active, c64 *vlo,
                                                         c128 *partial, ActiveLines act) {
     typedef decltype(V->re) T;
     __shared__ c128 cs[2 * KR_MAX_RESTART + 3];
@@ -342,13 +343,13 @@ __global__ void __launch_bounds__(KR_THREADS) k_update2(VT *V, long long ldj, in
     const double ia = cs[2 * nq].re, isg = cs[2 * nq + 2].re;
     const c128 hu = cs[2 * nq + 1];
     VT *ur = Vr + ring_slot(s0, nq, m1) * ldj;
-    const c128 *wr = w + r * n;
+    const WT *wr = w + r * n;
     c64 *lr = vlo ? vlo + r * n : nullptr;
     double nrm = 0.0;
     for (long long li = pr.lo + threadIdx.x; li < pr.hi; li += KR_THREADS) {
         const long long e = pr.at(li, fnx);
         const c128 u = wide(ur[e]);
-        c128 aq = u, aw = wr[e];
+        c128 aq = u, aw = wide(wr[e]);
         int i = 0;
         for (; i + 8 <= nq; i += 8) {  // eight loads in flight, products in order of i
             c128 v[8];
@@ -700,15 +701,15 @@ vie_status norms(Ctx &C, const c128 *w, c128 *out) {
 // column's previous Hessenberg column), one update pass (q over u, the next u into next_slot and
 // its complex64 copy when vlo is given), |u_next|^2 and the provisional residual estimates.
 // max_j bounds jcol over the active columns.
-template <class VT>
+template <class VT, class WT>
 vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int m1, const int *jcol, const int *s0, int max_j,
-                        int next_slot, const c128 *w, GState &S, c64 *vlo) {
+                        int next_slot, const WT *w, GState &S, c64 *vlo) {
     hipStream_t s = C.s;
     const long long n = C.n;
     const int R = C.R, cnt = 2 * max_j + 3;
     {
         ProfScope ps("arnoldi_dots", s);
-        hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, m1, jcol, s0, w, n,
+        hipLaunchKernelGGL((k_dots2<VT, WT>), dim3(C.nbd, R), dim3(KR_THREADS), 0, s, (const VT *)V, ldj, m1, jcol, s0, w, n,
                            (const int *)S.active, 0, cnt, C.partial, C.act);
         VIE_HIP(hipGetLastError());
     }
@@ -719,7 +720,7 @@ vie_status arnoldi_step(Ctx &C, VT *V, long long ldj, int m1, const int *jcol, c
     VIE_HIP(hipGetLastError());
     {
         ProfScope ps("arnoldi_update", s);
-        hipLaunchKernelGGL(k_update2<VT>, dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, m1, jcol, s0, next_slot,
+        hipLaunchKernelGGL((k_update2<VT, WT>), dim3(C.nbu, R), dim3(KR_THREADS), 0, s, V, ldj, m1, jcol, s0, next_slot,
                            (const c128 *)S.coef, S.cstride, w, n, (const int *)S.active, vlo, C.partial, C.act);
         VIE_HIP(hipGetLastError());
     }
@@ -737,7 +738,7 @@ vie_status arnoldi_finish(Ctx &C, const VT *V, long long ldj, int m1, const int 
                           int max_jr, GState &S) {
     hipStream_t s = C.s;
     const int cnt = max_jr + 1;
-    hipLaunchKernelGGL(k_dots2<VT>, dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, m1, jr_dev, s0,
+    hipLaunchKernelGGL((k_dots2<VT, c128>), dim3(C.nbd, C.R), dim3(KR_THREADS), 0, s, V, ldj, m1, jr_dev, s0,
                        (const c128 *)nullptr, C.n, (const int *)nullptr, 1, cnt, C.partial, C.act);
     VIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(cnt, C.R), dim3(KR_THREADS), 0, s, (const c128 *)C.partial, C.nbd, cnt, S.h1,
@@ -854,7 +855,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         VIE_CHECK(vlo.ensure(sizeof(c64) * Rn));
         VIE_CHECK(zw.ensure(sizeof(c128) * Rn));
     }
-    VIE_CHECK(wb.ensure(sizeof(c128) * Rn));
+    if (!mixed) VIE_CHECK(wb.ensure(sizeof(c128) * Rn));  // mixed: the Arnoldi passes read w32
     VIE_CHECK(rb.ensure(sizeof(c128) * Rn));
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
     if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
@@ -864,8 +865,10 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         VIE_CHECK(zero_skipped(Vb.p, v32, (long long)R * m1));
         if (mixed_pc) VIE_CHECK(zero_skipped(vlo.p, true, R));
         // the step products leave their outputs' skipped lines as they are
-        VIE_CHECK(zero_skipped(wb.p, false, R));
-        if (mixed) VIE_CHECK(zero_skipped(w32.p, true, R));
+        if (mixed)
+            VIE_CHECK(zero_skipped(w32.p, true, R));
+        else
+            VIE_CHECK(zero_skipped(wb.p, false, R));
         VIE_CHECK(nzflag.ensure(sizeof(int)));
     }
     GState S;
@@ -1168,9 +1171,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
             if (skip && pc) VIE_CHECK(zero_skipped(zj, true, R));
             if (mixed) {
-                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s, skip));
-                hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, w32.as<const c64>(), w, Rn);
-                VIE_HIP(hipGetLastError());
+                VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s, skip));  // read as is by the Arnoldi step
             } else {
                 hipLaunchKernelGGL(k_widen, dim3(1024), dim3(256), 0, s, (const c64 *)zj, zw.as<c128>(), Rn);
                 VIE_HIP(hipGetLastError());
@@ -1180,9 +1181,11 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
         const int next_slot = (int)((t + 1) % m1);
         if (v32)
-            VIE_CHECK(arnoldi_step<c64>(C, Vb.as<c64>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot, w, S, vl));
+            VIE_CHECK((arnoldi_step<c64, c64>(C, Vb.as<c64>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot,
+                                              w32.as<const c64>(), S, vl)));
         else
-            VIE_CHECK(arnoldi_step<c128>(C, Vb.as<c128>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot, w, S, vl));
+            VIE_CHECK((arnoldi_step<c128, c128>(C, Vb.as<c128>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot, w, S,
+                                                vl)));
         VIE_CHECK(read_host(C, S.st, sizeof(double) * 4 * R));
         ++t;
         std::vector<int> ending;
