@@ -860,9 +860,17 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
     VIE_CHECK(part.ensure(sizeof(c128) * (size_t)R * arnoldi_partials(n, m)));
     if (mixed) VIE_CHECK(w32.ensure(sizeof(c64) * Rn));
     DevBuf nzflag;
+    // ring slots whose skipped lines are zero: a slot is zeroed there before its first use (slot
+    // 0 now, every other one before the update pass that writes the next u into it), since the
+    // passes write the covered lines only and the preconditioner reads whole vectors
+    std::vector<char> vzero(m1, 0);
+    auto zero_slot = [&](int slot) -> vie_status {
+        if (!skip || vzero[slot]) return VIE_OK;
+        vzero[slot] = 1;
+        return zero_skipped((char *)Vb.p + vsz * Rn * slot, v32, R);
+    };
     if (skip) {
-        // the ring slots are written on the covered lines only from here on
-        VIE_CHECK(zero_skipped(Vb.p, v32, (long long)R * m1));
+        VIE_CHECK(zero_slot(0));
         if (mixed_pc) VIE_CHECK(zero_skipped(vlo.p, true, R));
         // the step products leave their outputs' skipped lines as they are
         if (mixed)
@@ -1155,13 +1163,15 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         void *vj = (char *)Vb.p + vsz * Rn * (t % m1);
         void *zj = (char *)Zb.p + zsz * Rn * (t % m);
         // a preconditioner that does not keep the skipped lines at zero (one homogenising over y,
-        // say) is projected: FGMRES takes any z, and A z then stays zero there
+        // say) is projected: FGMRES takes any z, and A z then stays zero there.  One whose
+        // identity rows include those lines copies the zeros of u_j there and is not.
+        const bool project = skip && pc && !pc->zero_lines_kept;
         if (!lowpc) {
             if (pc)
                 VIE_CHECK(pc_apply(pc, vj, zj, R, VIE_C128, s));
             else
                 VIE_HIP(hipMemcpyAsync(zj, vj, sizeof(c128) * Rn, hipMemcpyDeviceToDevice, s));
-            if (skip && pc) VIE_CHECK(zero_skipped(zj, false, R));
+            if (project) VIE_CHECK(zero_skipped(zj, false, R));
             VIE_CHECK(launch_matvec(op, zj, w, R, VIE_C128, s, skip));
         } else {
             const void *vin = mixed_pc ? vlo.p : vj;
@@ -1169,7 +1179,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
                 VIE_CHECK(pc_apply(pc, vin, zj, R, VIE_C64, s));
             else
                 VIE_HIP(hipMemcpyAsync(zj, vin, sizeof(c64) * Rn, hipMemcpyDeviceToDevice, s));
-            if (skip && pc) VIE_CHECK(zero_skipped(zj, true, R));
+            if (project) VIE_CHECK(zero_skipped(zj, true, R));
             if (mixed) {
                 VIE_CHECK(launch_matvec(op, zj, w32.p, R, VIE_C64, s, skip));  // read as is by the Arnoldi step
             } else {
@@ -1180,6 +1190,7 @@ vie_status solve_gmres(vie_op op, vie_pc pc, const c128 *b, c128 *x, int R, cons
         }
         c64 *vl = mixed_pc ? vlo.as<c64>() : nullptr;
         const int next_slot = (int)((t + 1) % m1);
+        VIE_CHECK(zero_slot(next_slot));
         if (v32)
             VIE_CHECK((arnoldi_step<c64, c64>(C, Vb.as<c64>(), ldj, m1, jcol_dev, s0_dev, max_j, next_slot,
                                               w32.as<const c64>(), S, vl)));

@@ -1682,6 +1682,17 @@ vie_status pc_build(vie_pc pc, const vie_pc_opts *o, hipStream_t s) {
                     if (act[yz] == pass) pc->rows_host.push_back(a * plane + yz);
         pc->m = 0;
         for (int yz = 0; yz < plane; ++yz) pc->m += 3 * act[yz];
+        // the operator's lines without contrast: identity rows here too when the boxes span the
+        // cross-section (position z*by + y in both), so the apply copies its input there
+        pc->zero_lines_kept = false;
+        if (op->n_line_zero > 0 && by == op->ny && bz == op->nz) {
+            std::vector<int> hf(plane);
+            VIE_HIP(hipMemcpyAsync(hf.data(), op->yzflag.p, sizeof(int) * plane, hipMemcpyDeviceToHost, s));
+            VIE_HIP(hipStreamSynchronize(s));
+            bool all = true;
+            for (int yz = 0; yz < plane; ++yz) all &= hf[yz] != 0 || !act[yz];
+            pc->zero_lines_kept = all;
+        }
         VIE_CHECK(pc->rows.ensure(sizeof(int) * pc->m_full));
         VIE_HIP(hipMemcpyAsync(pc->rows.p, pc->rows_host.data(), sizeof(int) * pc->m_full, hipMemcpyHostToDevice, s));
     }

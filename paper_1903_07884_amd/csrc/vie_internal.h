@@ -308,6 +308,9 @@ struct vie_pc_s {
     // rows[m..m_full) are identity rows of every D_k.  Entry = a*by*bz + z*by + y.
     DevBuf rows;             // int32 [m_full]
     std::vector<int> rows_host;
+    // every line of the operator without contrast is an identity row of every box: the apply
+    // copies its input there (zero in, zero out exactly), so the solver need not project z
+    bool zero_lines_kept = false;
     DevBuf chan64, mt64;     // FP64 C^_k table / M~ for the coupling of an FP64 apply
     // 2-level: the identity map of the x-DFT lines of the full cross-section
     DevBuf rows1;
