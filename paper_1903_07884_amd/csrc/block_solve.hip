@@ -1070,18 +1070,32 @@ static void launch_wide(vie_pc pc, PcWs *w, cpx<R> *work, cpx<R> *Y, int nrhs, i
     }
 }
 
-template <int CT>
-static void launch_residual(vie_pc pc, PcWs *w, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
-    constexpr int NW = 16;  // one workgroup per CU (the table fills the LDS): 16 wavefronts hide the latency
+template <int CT, int NW>
+static void launch_residual_nw(vie_pc pc, PcWs *w, c64 *work, const c64 *Y, int nrhs, size_t lds, hipStream_t s) {
     const int per = (w->n_wide + 7) / 8;
-    const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
-    const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16) + sizeof(int) * pc->m;
     vie_lds_attr((const void *)k_refine_residual<CT, NW>, lds);
     const int *mp = pc->modes_dev.as<const int>();
     hipLaunchKernelGGL((k_refine_residual<CT, NW>), dim3(8 * per), dim3(NW * 64), lds, s, work,
                        pc->chan32.as<const c64>(), pc->mt32.as<const c64>(), pc->smode_dev.as<const int>(),
                        w->sched.as<const int4>(), w->n_wide, mp, mp + pc->nstored + 1, Y,
                        pc->rows.as<const int>(), pc->m, pc->nm, pc->nboxes, nrhs, pc->by, pc->bz, pc->mirror_rows);
+}
+
+// 16 wavefronts in one workgroup per CU (the table fills most of the LDS), or, for 32-column
+// groups whose workgroup fits in half the LDS, 8 wavefronts in two workgroups per CU, whose
+// barriers then overlap (coupler, 32 columns: 3.29 -> 2.84 ms; 16 and 64 columns measured
+// slower with 8: the former barely, the latter's registers allow only one such workgroup)
+template <int CT>
+static void launch_residual(vie_pc pc, PcWs *w, c64 *work, const c64 *Y, int nrhs, hipStream_t s) {
+    const size_t tabn = 6 * (size_t)(2 * pc->bz - 1) * (2 * pc->by - 1);
+    const size_t lds = sizeof(c64) * (((tabn + 1) & ~(size_t)1) + 2 * 16 * CT * 16) + sizeof(int) * pc->m;
+    if constexpr (CT == 2) {
+        if (lds <= 80 * 1024) {
+            launch_residual_nw<CT, 8>(pc, w, work, Y, nrhs, lds, s);
+            return;
+        }
+    }
+    launch_residual_nw<CT, 16>(pc, w, work, Y, nrhs, lds, s);
 }
 
 template <class R, class FT>
